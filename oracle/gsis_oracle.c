@@ -1,0 +1,1071 @@
+/*
+ * gsis_oracle.c -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT PATH.
+ *
+ * A plain, slow, FP64 CPU implementation of one GSIS iteration of the
+ * discrete velocity method of arXiv 2310.18916 ("Efficient parallel solver
+ * for rarefied gas flow using GSIS").  It exists only so that the GPU path
+ * can be checked against something written straight from the equations.
+ * Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may
+ * load it.  It shares no code, header, table or constant with the HIP
+ * library: everything below is written out again from the paper.
+ *
+ * Units (dimensionless): x in L, molecular velocity xi in v_m = sqrt(2 R T0),
+ * rho in rho0, T in T0, time in L / v_m.  In these units R T -> T / 2, the
+ * Maxwellian is rho (pi T)^{-3/2} exp(-|c|^2 / T), the collision rate is
+ * 1/tau = delta rho T_t^{1-omega} with delta = sqrt(pi) / (2 Kn) (Sec. 2.1,
+ * definition of Kn and the power-law viscosity), sigma is in p0 and q in
+ * p0 v_m.
+ *
+ * What each function follows:
+ *   moments            Eq. (getmoment), two-pass central sums, Neumaier.
+ *   reference dists    Sec. 2.2, reference distributions g_0t, g_0r, g_1t,
+ *                      g_1r and the q0/q1 mixing matrix; the Rykov mixture
+ *                      g = (1 - 1/Z_r) g_t + g_r / Z_r of Sec. 3.2.
+ *   conservative fix   not in the paper (it cites a conservative DVM): the
+ *                      reference distribution is corrected by M (lambda.phi),
+ *                      phi = (1, xi, |xi|^2), so that its discrete moments
+ *                      equal their continuous values exactly.
+ *   sweep              Sec. 3.2, backward-Euler kinetic update in delta form
+ *                      with first-order upwind fluxes on both sides, solved
+ *                      exactly by visiting cells in upwind order.
+ *   boundary           diffuse wall (discrete half-range zero mass flux, wall
+ *                      density lagged to f^n) and Maxwellian inflow.
+ *   gsis_correct       Sec. 3.3, GSIS-II macroscopic equations with the
+ *                      high-order terms of Eq. (full_constitutive), Rusanov
+ *                      convective flux, the diagonal of Eq. (res_macro) in a
+ *                      point-Jacobi iteration, then Eq. (updatef).
+ *   residual           Eq. (convergence_critertion), Sec. 4.
+ */
+#define _GNU_SOURCE
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <stdio.h>
+
+#define ORC_NBC 7
+#define ORC_WALL 0
+#define ORC_INFLOW 1
+
+typedef struct {
+    int nx, ny, nz;
+    double lx, ly, lz;
+    int nv[3];
+    double vmin[3], vmax[3];
+    int species;            /* 0 monatomic Shakhov, 1 diatomic Rykov (two VDFs) */
+    double Kn, omega;
+    double dr, Zr, A[4];    /* diatomic only: internal DOF, collision number, A_tt A_tr A_rt A_rr */
+    double inv_dt;          /* 1/Delta t of the kinetic update; 0 = source iteration */
+    int conservative;       /* 1: moment-matched reference distribution */
+    double macro_cfl;
+    int bc_kind[ORC_NBC];   /* faces -x,+x,-y,+y,-z,+z of the box, then the solid surface */
+    double bc_u[ORC_NBC][3];
+    double bc_T[ORC_NBC];
+    double bc_rho[ORC_NBC];
+} orc_cfg;
+
+typedef struct {
+    orc_cfg c;
+    int ncell, nv;
+    double h[3];
+    double delta;
+    unsigned char *solid;
+    double *xi[3], *w1[3];
+    double *f0, *f1;
+    double *prev;           /* residual snapshot: rho, ux, uy, uz, Tt per cell */
+    int status;
+} orc_state;
+
+/* ---------------------------------------------------------------- sums -- */
+typedef struct { double s, c; } nsum;
+static void nadd(nsum *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+static double nval(const nsum *a) { return a->s + a->c; }
+
+/* --------------------------------------------------------------- setup -- */
+static int cell_index(const orc_state *s, int i, int j, int k)
+{
+    return i + s->c.nx * (j + s->c.ny * k);
+}
+
+static void node_xi(const orc_state *s, int v, double xi[3], double *w)
+{
+    int kx = v % s->c.nv[0];
+    int ky = (v / s->c.nv[0]) % s->c.nv[1];
+    int kz = v / (s->c.nv[0] * s->c.nv[1]);
+    xi[0] = s->xi[0][kx];
+    xi[1] = s->xi[1][ky];
+    xi[2] = s->xi[2][kz];
+    *w = s->w1[0][kx] * s->w1[1][ky] * s->w1[2][kz];
+}
+
+void orc_free(orc_state *s)
+{
+    if (!s) return;
+    free(s->solid);
+    for (int a = 0; a < 3; ++a) { free(s->xi[a]); free(s->w1[a]); }
+    free(s->f0); free(s->f1); free(s->prev);
+    free(s);
+}
+
+orc_state *orc_create(const orc_cfg *cfg, const unsigned char *solid)
+{
+    if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return NULL;
+    for (int a = 0; a < 3; ++a)
+        if (cfg->nv[a] < 2 || !(cfg->vmax[a] > cfg->vmin[a])) return NULL;
+    orc_state *s = calloc(1, sizeof(*s));
+    s->c = *cfg;
+    s->ncell = cfg->nx * cfg->ny * cfg->nz;
+    s->nv = cfg->nv[0] * cfg->nv[1] * cfg->nv[2];
+    s->h[0] = cfg->lx / cfg->nx;
+    s->h[1] = cfg->ly / cfg->ny;
+    s->h[2] = cfg->lz / cfg->nz;
+    s->delta = sqrt(M_PI) / (2.0 * cfg->Kn);
+    s->solid = calloc((size_t)s->ncell, 1);
+    if (solid) memcpy(s->solid, solid, (size_t)s->ncell);
+    for (int a = 0; a < 3; ++a) {
+        int n = cfg->nv[a];
+        double d = (cfg->vmax[a] - cfg->vmin[a]) / (n - 1);
+        s->xi[a] = malloc(sizeof(double) * n);
+        s->w1[a] = malloc(sizeof(double) * n);
+        for (int k = 0; k < n; ++k) {
+            s->xi[a][k] = cfg->vmin[a] + k * d;
+            s->w1[a][k] = (k == 0 || k == n - 1) ? 0.5 * d : d;   /* trapezoid */
+        }
+    }
+    size_t np = (size_t)s->ncell * s->nv;
+    s->f0 = calloc(np, sizeof(double));
+    if (cfg->species == 1) s->f1 = calloc(np, sizeof(double));
+    s->prev = calloc((size_t)s->ncell * 5, sizeof(double));
+    if (!s->f0 || (cfg->species == 1 && !s->f1)) { orc_free(s); return NULL; }
+    return s;
+}
+
+int orc_ncell(const orc_state *s) { return s->ncell; }
+int orc_nv(const orc_state *s) { return s->nv; }
+int orc_status(const orc_state *s) { return s->status; }
+
+/* Maxwellian rho (pi T)^{-3/2} exp(-|xi-u|^2/T) in the units above. */
+static double maxwellian(double rho, const double u[3], double T, const double xi[3])
+{
+    double c2 = 0;
+    for (int a = 0; a < 3; ++a) c2 += (xi[a] - u[a]) * (xi[a] - u[a]);
+    return rho * pow(M_PI * T, -1.5) * exp(-c2 / T);
+}
+
+/* ------------------------------------------------------------- moments -- */
+typedef struct {
+    double rho, u[3], Tt, sig[6], q[3];   /* sigma order xx yy zz xy xz yz */
+    double Tr, qr[3], T;
+} moms;
+
+/* Eq. (getmoment), written in the units above:
+ *   rho = sum w f0,  rho u = sum w xi f0,  (3/2) rho Tt = sum w |c|^2 f0,
+ *   sigma = 2 sum w (c c - |c|^2 I / 3) f0,  q = sum w c |c|^2 f0,
+ *   (dr/2) rho Tr = sum w f1,  qr = sum w c f1,  T = (3 Tt + dr Tr)/(3 + dr). */
+static void cell_moments(const orc_state *s, int cell, moms *m)
+{
+    const double *f0 = s->f0 + (size_t)cell * s->nv;
+    const double *f1 = s->f1 ? s->f1 + (size_t)cell * s->nv : NULL;
+    nsum r = {0, 0}, mu[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int v = 0; v < s->nv; ++v) {
+        double xi[3], w;
+        node_xi(s, v, xi, &w);
+        nadd(&r, w * f0[v]);
+        for (int a = 0; a < 3; ++a) nadd(&mu[a], w * xi[a] * f0[v]);
+    }
+    m->rho = nval(&r);
+    for (int a = 0; a < 3; ++a) m->u[a] = nval(&mu[a]) / m->rho;
+    nsum cc[6] = {{0, 0}}, c3[3] = {{0, 0}}, e1 = {0, 0}, q1[3] = {{0, 0}};
+    memset(cc, 0, sizeof cc); memset(c3, 0, sizeof c3); memset(q1, 0, sizeof q1);
+    for (int v = 0; v < s->nv; ++v) {
+        double xi[3], w, c[3];
+        node_xi(s, v, xi, &w);
+        for (int a = 0; a < 3; ++a) c[a] = xi[a] - m->u[a];
+        double c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+        double wf = w * f0[v];
+        nadd(&cc[0], wf * c[0] * c[0]);
+        nadd(&cc[1], wf * c[1] * c[1]);
+        nadd(&cc[2], wf * c[2] * c[2]);
+        nadd(&cc[3], wf * c[0] * c[1]);
+        nadd(&cc[4], wf * c[0] * c[2]);
+        nadd(&cc[5], wf * c[1] * c[2]);
+        for (int a = 0; a < 3; ++a) nadd(&c3[a], wf * c[a] * c2);
+        if (f1) {
+            nadd(&e1, w * f1[v]);
+            for (int a = 0; a < 3; ++a) nadd(&q1[a], w * c[a] * f1[v]);
+        }
+    }
+    double S[6];
+    for (int k = 0; k < 6; ++k) S[k] = nval(&cc[k]);
+    double tr = S[0] + S[1] + S[2];
+    m->Tt = (2.0 / 3.0) * tr / m->rho;
+    for (int k = 0; k < 6; ++k) m->sig[k] = 2.0 * (S[k] - (k < 3 ? tr / 3.0 : 0.0));
+    for (int a = 0; a < 3; ++a) m->q[a] = nval(&c3[a]);
+    if (f1) {
+        double dr = s->c.dr;
+        m->Tr = 2.0 * nval(&e1) / (dr * m->rho);
+        for (int a = 0; a < 3; ++a) m->qr[a] = nval(&q1[a]);
+        m->T = (3.0 * m->Tt + dr * m->Tr) / (3.0 + dr);
+    } else {
+        m->Tr = m->Tt;
+        m->qr[0] = m->qr[1] = m->qr[2] = 0.0;
+        m->T = m->Tt;
+    }
+}
+
+/* ---------------------------------------------- reference distribution -- */
+/* Shakhov form of Sec. 2.2 (the bracket with 2/15 fixes Pr = 2/3):
+ *   S = M(rho,u,T) [1 + (4/15) (q.c) / (rho T^2) (|c|^2/T - 5/2)]. */
+static double shakhov(double rho, const double u[3], double T, const double q[3], const double xi[3])
+{
+    double c[3], c2 = 0, qc = 0;
+    for (int a = 0; a < 3; ++a) { c[a] = xi[a] - u[a]; c2 += c[a] * c[a]; qc += q[a] * c[a]; }
+    double M = rho * pow(M_PI * T, -1.5) * exp(-c2 / T);
+    return M * (1.0 + (4.0 / 15.0) * qc / (rho * T * T) * (c2 / T - 2.5));
+}
+
+/* Extra term of g_1t / g_1r: 2 (pi T)^{-3/2} (qr.c / T) exp(-|c|^2/T). */
+static double rot_flux_term(const double u[3], double T, const double qr[3], const double xi[3])
+{
+    double c2 = 0, qc = 0;
+    for (int a = 0; a < 3; ++a) { double c = xi[a] - u[a]; c2 += c * c; qc += qr[a] * c; }
+    return 2.0 * pow(M_PI * T, -1.5) * (qc / T) * exp(-c2 / T);
+}
+
+typedef struct {
+    moms m;
+    double q0[3], q1[3];
+    double lam_t[5], lam_r[5], nu_t, nu_r;
+    double invtau;
+} cellpar;
+
+/* The four uncorrected reference components of Sec. 2.2 at one node. */
+static void ref_components(const orc_cfg *c, const cellpar *p, const double xi[3], double out[4])
+{
+    const moms *m = &p->m;
+    double S0t = shakhov(m->rho, m->u, m->Tt, m->q, xi);
+    out[0] = S0t;
+    if (c->species == 0) { out[1] = out[2] = out[3] = 0.0; return; }
+    double S0r = shakhov(m->rho, m->u, m->T, p->q0, xi);
+    out[1] = S0r;
+    out[2] = 0.5 * c->dr * m->Tr * S0t + rot_flux_term(m->u, m->Tt, m->qr, xi);
+    out[3] = 0.5 * c->dr * m->T * S0r + rot_flux_term(m->u, m->T, p->q1, xi);
+}
+
+static void phi5(const double xi[3], double phi[5])
+{
+    phi[0] = 1.0; phi[1] = xi[0]; phi[2] = xi[1]; phi[3] = xi[2];
+    phi[4] = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+}
+
+/* Dense solve with partial pivoting; n <= 5. */
+static int solve_dense(int n, double *A, double *b)
+{
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < n; ++i) if (fabs(A[i * n + k]) > fabs(A[piv * n + k])) piv = i;
+        if (A[piv * n + k] == 0.0) return -1;
+        if (piv != k) {
+            for (int j = 0; j < n; ++j) { double t = A[k * n + j]; A[k * n + j] = A[piv * n + j]; A[piv * n + j] = t; }
+            double t = b[k]; b[k] = b[piv]; b[piv] = t;
+        }
+        for (int i = k + 1; i < n; ++i) {
+            double f = A[i * n + k] / A[k * n + k];
+            for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+            b[i] -= f * b[k];
+        }
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        double t = b[k];
+        for (int j = k + 1; j < n; ++j) t -= A[k * n + j] * b[j];
+        b[k] = t / A[k * n + k];
+    }
+    return 0;
+}
+
+/* Per-cell parameters: moments, collision rate, q0/q1 mixing and the
+ * conservative correction.  The correction of a component X with
+ * Maxwellian shape M_X solves  [sum w phi phi^T M_X] lambda = target - sum w phi S_X,
+ * target = (rho, rho u, rho |u|^2 + (3/2) rho T_X), brute force over every node. */
+static void cell_params(const orc_state *s, int cell, cellpar *p)
+{
+    const orc_cfg *c = &s->c;
+    memset(p, 0, sizeof(*p));
+    cell_moments(s, cell, &p->m);
+    const moms *m = &p->m;
+    p->invtau = s->delta * m->rho * pow(m->Tt, 1.0 - c->omega);
+    if (c->species == 1) {
+        double Z = c->Zr;
+        double Att = c->A[0], Atr = c->A[1], Art = c->A[2], Arr = c->A[3];
+        for (int a = 0; a < 3; ++a) {
+            p->q0[a] = ((2.0 - 3.0 * Att) * Z + 1.0) * m->q[a] + (-3.0 * Atr * Z) * m->qr[a];
+            p->q1[a] = (-Art * Z) * m->q[a] + (-Arr * Z + 1.0) * m->qr[a];
+        }
+    }
+    if (!c->conservative) return;
+    int ncomp = c->species == 1 ? 2 : 1;
+    for (int X = 0; X < ncomp; ++X) {
+        double TX = X == 0 ? m->Tt : m->T;
+        double G[25] = {0}, b[5] = {0};
+        nsum Gs[25], bs[5];
+        memset(Gs, 0, sizeof Gs); memset(bs, 0, sizeof bs);
+        for (int v = 0; v < s->nv; ++v) {
+            double xi[3], w, ph[5], comp[4];
+            node_xi(s, v, xi, &w);
+            phi5(xi, ph);
+            double MX = maxwellian(m->rho, m->u, TX, xi);
+            ref_components(c, p, xi, comp);
+            double SX = comp[X];
+            for (int i = 0; i < 5; ++i) {
+                nadd(&bs[i], w * ph[i] * SX);
+                for (int j = 0; j < 5; ++j) nadd(&Gs[i * 5 + j], w * ph[i] * ph[j] * MX);
+            }
+        }
+        double u2 = m->u[0] * m->u[0] + m->u[1] * m->u[1] + m->u[2] * m->u[2];
+        double target[5] = {m->rho, m->rho * m->u[0], m->rho * m->u[1], m->rho * m->u[2],
+                            m->rho * u2 + 1.5 * m->rho * TX};
+        for (int i = 0; i < 5; ++i) {
+            b[i] = target[i] - nval(&bs[i]);
+            for (int j = 0; j < 5; ++j) G[i * 5 + j] = nval(&Gs[i * 5 + j]);
+        }
+        solve_dense(5, G, b);
+        memcpy(X == 0 ? p->lam_t : p->lam_r, b, sizeof b);
+    }
+    if (c->species == 1) {
+        /* g_1t and g_1r: one constraint each, sum w g_1X = (dr/2) rho T_X'. */
+        nsum s1t = {0, 0}, s1r = {0, 0}, mt = {0, 0}, mr = {0, 0};
+        for (int v = 0; v < s->nv; ++v) {
+            double xi[3], w, comp[4];
+            node_xi(s, v, xi, &w);
+            ref_components(c, p, xi, comp);
+            nadd(&s1t, w * comp[2]);
+            nadd(&s1r, w * comp[3]);
+            nadd(&mt, w * maxwellian(m->rho, m->u, m->Tt, xi));
+            nadd(&mr, w * maxwellian(m->rho, m->u, m->T, xi));
+        }
+        p->nu_t = (0.5 * c->dr * m->rho * m->Tr - nval(&s1t)) / nval(&mt);
+        p->nu_r = (0.5 * c->dr * m->rho * m->T - nval(&s1r)) / nval(&mr);
+    }
+}
+
+/* The relaxation targets g0, g1 at one node (corrected components mixed
+ * as g = (1 - 1/Z) g_t + g_r / Z; monatomic: g0 = corrected S). */
+static void ref_dist(const orc_cfg *c, const cellpar *p, const double xi[3], double *g0, double *g1)
+{
+    const moms *m = &p->m;
+    double comp[4], ph[5];
+    ref_components(c, p, xi, comp);
+    phi5(xi, ph);
+    double Mt = maxwellian(m->rho, m->u, m->Tt, xi);
+    double lt = 0;
+    for (int i = 0; i < 5; ++i) lt += p->lam_t[i] * ph[i];
+    double g0t = comp[0] + Mt * lt;
+    if (c->species == 0) { *g0 = g0t; *g1 = 0.0; return; }
+    double Mr = maxwellian(m->rho, m->u, m->T, xi);
+    double lr = 0;
+    for (int i = 0; i < 5; ++i) lr += p->lam_r[i] * ph[i];
+    double g0r = comp[1] + Mr * lr;
+    double g1t = comp[2] + p->nu_t * Mt;
+    double g1r = comp[3] + p->nu_r * Mr;
+    double iz = 1.0 / c->Zr;
+    *g0 = (1.0 - iz) * g0t + iz * g0r;
+    *g1 = (1.0 - iz) * g1t + iz * g1r;
+}
+
+/* ------------------------------------------------------------ boundary -- */
+/* Neighbour of a fluid cell across face d (0:-x 1:+x 2:-y 3:+y 4:-z 5:+z):
+ * returns the fluid cell index, or -1 - bc (bc = d for the box faces, 6 for
+ * the solid surface). */
+static int neighbour(const orc_state *s, int cell, int d)
+{
+    int nx = s->c.nx, ny = s->c.ny, nz = s->c.nz;
+    int i = cell % nx, j = (cell / nx) % ny, k = cell / (nx * ny);
+    int a = d / 2, sg = (d & 1) ? 1 : -1;
+    int ii = i + (a == 0 ? sg : 0), jj = j + (a == 1 ? sg : 0), kk = k + (a == 2 ? sg : 0);
+    if (ii < 0 || ii >= nx || jj < 0 || jj >= ny || kk < 0 || kk >= nz) return -1 - d;
+    int nb = cell_index(s, ii, jj, kk);
+    if (s->solid[nb]) return -1 - 6;
+    return nb;
+}
+
+/* Density scale of the incoming half of a boundary face.  Diffuse wall:
+ * rho_w = sum_{xi.n>0} w xi.n f0 / sum_{xi.n<0} w |xi.n| M(1,u_w,T_w), so the
+ * discrete mass flux through the wall is zero; inflow: the fixed density. */
+static double face_scale(const orc_state *s, int cell, int d, int bc)
+{
+    const orc_cfg *c = &s->c;
+    if (c->bc_kind[bc] == ORC_INFLOW) return c->bc_rho[bc];
+    int a = d / 2;
+    double sg = (d & 1) ? 1.0 : -1.0;
+    const double *f0 = s->f0 + (size_t)cell * s->nv;
+    nsum out = {0, 0}, in = {0, 0};
+    for (int v = 0; v < s->nv; ++v) {
+        double xi[3], w;
+        node_xi(s, v, xi, &w);
+        double xn = sg * xi[a];
+        if (xn > 0) nadd(&out, w * xn * f0[v]);
+        else if (xn < 0) nadd(&in, w * (-xn) * maxwellian(1.0, c->bc_u[bc], c->bc_T[bc], xi));
+    }
+    return nval(&out) / nval(&in);
+}
+
+/* Incoming boundary values f0_b, f1_b (f1 = (dr/2) T_b f0 for the equilibrium). */
+static void boundary_value(const orc_cfg *c, int bc, double scale, const double xi[3], double *b0, double *b1)
+{
+    *b0 = scale * maxwellian(1.0, c->bc_u[bc], c->bc_T[bc], xi);
+    *b1 = 0.5 * c->dr * c->bc_T[bc] * (*b0);
+}
+
+/* --------------------------------------------------------------- sweep -- */
+/* One kinetic pass: Sec. 3.2, backward Euler in pseudo time with first-order
+ * upwind fluxes.  For node xi and fluid cell i, with a_a = |xi_a| / h_a:
+ *   f_i^{n+1/2} = [f_i^n / dt + g_i / tau_i + sum_a a_a F_a] / (1/dt + 1/tau_i + sum_a a_a),
+ * F_a = f^{n+1/2} of the upwind cell, or the boundary value of the shared face.
+ * Cells are visited in the upwind lexicographic order of the node's octant,
+ * which solves the lower-triangular system exactly.  In place. */
+static int one_pass(orc_state *s)
+{
+    const orc_cfg *c = &s->c;
+    int ncell = s->ncell, nv = s->nv, dia = c->species == 1;
+    cellpar *P = malloc(sizeof(cellpar) * (size_t)ncell);
+    double *scale = malloc(sizeof(double) * (size_t)ncell * 6);
+    int *nb = malloc(sizeof(int) * (size_t)ncell * 6);
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int cell = 0; cell < ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        cell_params(s, cell, &P[cell]);
+        for (int d = 0; d < 6; ++d) {
+            int n = neighbour(s, cell, d);
+            nb[cell * 6 + d] = n;
+            scale[cell * 6 + d] = n >= 0 ? 0.0 : face_scale(s, cell, d, -1 - n);
+        }
+    }
+    for (int cell = 0; cell < ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        if (!isfinite(P[cell].invtau) || !(P[cell].m.rho > 0) || !(P[cell].m.Tt > 0)) s->status = -5;
+    }
+    int nx = c->nx, ny = c->ny, nz = c->nz;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int v = 0; v < nv; ++v) {
+        double xi[3], w;
+        node_xi(s, v, xi, &w);
+        int sg[3];
+        double aa[3];
+        for (int a = 0; a < 3; ++a) { sg[a] = xi[a] >= 0 ? 1 : -1; aa[a] = fabs(xi[a]) / s->h[a]; }
+        for (int kk = 0; kk < nz; ++kk) {
+            int k = sg[2] > 0 ? kk : nz - 1 - kk;
+            for (int jj = 0; jj < ny; ++jj) {
+                int j = sg[1] > 0 ? jj : ny - 1 - jj;
+                for (int ii = 0; ii < nx; ++ii) {
+                    int i = sg[0] > 0 ? ii : nx - 1 - ii;
+                    int cell = cell_index(s, i, j, k);
+                    if (s->solid[cell]) continue;
+                    size_t at = (size_t)cell * nv + v;
+                    double g0, g1;
+                    ref_dist(c, &P[cell], xi, &g0, &g1);
+                    double it = P[cell].invtau;
+                    double num0 = c->inv_dt * s->f0[at] + it * g0;
+                    double num1 = dia ? c->inv_dt * s->f1[at] + it * g1 : 0.0;
+                    double den = c->inv_dt + it;
+                    for (int a = 0; a < 3; ++a) {
+                        if (aa[a] == 0.0) continue;
+                        int d = 2 * a + (sg[a] > 0 ? 0 : 1);   /* upwind face */
+                        int n = nb[cell * 6 + d];
+                        double F0, F1;
+                        if (n >= 0) {
+                            F0 = s->f0[(size_t)n * nv + v];
+                            F1 = dia ? s->f1[(size_t)n * nv + v] : 0.0;
+                        } else {
+                            boundary_value(c, -1 - n, scale[cell * 6 + d], xi, &F0, &F1);
+                        }
+                        num0 += aa[a] * F0;
+                        num1 += aa[a] * F1;
+                        den += aa[a];
+                    }
+                    s->f0[at] = num0 / den;
+                    if (dia) s->f1[at] = num1 / den;
+                }
+            }
+        }
+    }
+    free(P); free(scale); free(nb);
+    return s->status;
+}
+
+int orc_step(orc_state *s, int npasses)
+{
+    for (int n = 0; n < npasses; ++n) one_pass(s);
+    return s->status;
+}
+
+/* -------------------------------------------------------- state access -- */
+static void snapshot(orc_state *s)
+{
+    for (int cell = 0; cell < s->ncell; ++cell) {
+        double *pv = s->prev + (size_t)cell * 5;
+        if (s->solid[cell]) { memset(pv, 0, 5 * sizeof(double)); continue; }
+        moms m;
+        cell_moments(s, cell, &m);
+        pv[0] = m.rho; pv[1] = m.u[0]; pv[2] = m.u[1]; pv[3] = m.u[2]; pv[4] = m.Tt;
+    }
+}
+
+void orc_init_maxwellian(orc_state *s, double rho, const double u[3], double T, double Tr)
+{
+    for (int cell = 0; cell < s->ncell; ++cell) {
+        for (int v = 0; v < s->nv; ++v) {
+            size_t at = (size_t)cell * s->nv + v;
+            if (s->solid[cell]) { s->f0[at] = 0; if (s->f1) s->f1[at] = 0; continue; }
+            double xi[3], w;
+            node_xi(s, v, xi, &w);
+            s->f0[at] = maxwellian(rho, u, T, xi);
+            if (s->f1) s->f1[at] = 0.5 * s->c.dr * Tr * s->f0[at];
+        }
+    }
+    s->status = 0;
+    snapshot(s);
+}
+
+void orc_set_vdf(orc_state *s, const double *f0, const double *f1)
+{
+    size_t np = (size_t)s->ncell * s->nv;
+    memcpy(s->f0, f0, np * sizeof(double));
+    if (s->f1 && f1) memcpy(s->f1, f1, np * sizeof(double));
+    s->status = 0;
+    snapshot(s);
+}
+
+void orc_get_vdf(const orc_state *s, double *f0, double *f1)
+{
+    size_t np = (size_t)s->ncell * s->nv;
+    memcpy(f0, s->f0, np * sizeof(double));
+    if (s->f1 && f1) memcpy(f1, s->f1, np * sizeof(double));
+}
+
+/* out[ncell][14 or 18]: rho, ux, uy, uz, Tt, sxx, syy, szz, sxy, sxz, syz,
+ * qx, qy, qz, [Tr, qrx, qry, qrz]; NaN in solid cells. */
+void orc_moments(const orc_state *s, double *out)
+{
+    int nm = s->c.species == 1 ? 18 : 14;
+    #pragma omp parallel for schedule(static)
+    for (int cell = 0; cell < s->ncell; ++cell) {
+        double *o = out + (size_t)cell * nm;
+        if (s->solid[cell]) { for (int k = 0; k < nm; ++k) o[k] = NAN; continue; }
+        moms m;
+        cell_moments(s, cell, &m);
+        o[0] = m.rho; o[1] = m.u[0]; o[2] = m.u[1]; o[3] = m.u[2]; o[4] = m.Tt;
+        for (int k = 0; k < 6; ++k) o[5 + k] = m.sig[k];
+        for (int a = 0; a < 3; ++a) o[11 + a] = m.q[a];
+        if (nm == 18) { o[14] = m.Tr; for (int a = 0; a < 3; ++a) o[15 + a] = m.qr[a]; }
+    }
+}
+
+/* Eq. (convergence_critertion) with uniform cell volumes; u is a vector,
+ * a zero denominator reports the absolute value.  Compares with the last
+ * snapshot and takes a new one. */
+void orc_residual(orc_state *s, double eps[3])
+{
+    nsum num[3], den[3];
+    memset(num, 0, sizeof num); memset(den, 0, sizeof den);
+    for (int cell = 0; cell < s->ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        moms m;
+        cell_moments(s, cell, &m);
+        const double *pv = s->prev + (size_t)cell * 5;
+        double dr = m.rho - pv[0], dT = m.Tt - pv[4];
+        nadd(&num[0], dr * dr); nadd(&den[0], pv[0] * pv[0]);
+        for (int a = 0; a < 3; ++a) { double du = m.u[a] - pv[1 + a]; nadd(&num[1], du * du); nadd(&den[1], pv[1 + a] * pv[1 + a]); }
+        nadd(&num[2], dT * dT); nadd(&den[2], pv[4] * pv[4]);
+    }
+    for (int k = 0; k < 3; ++k) {
+        double n = nval(&num[k]), d = nval(&den[k]);
+        eps[k] = d > 0 ? sqrt(n / d) : sqrt(n);
+    }
+    snapshot(s);
+}
+
+/* ---------------------------------------------------- pin/debug access -- */
+/* Corrected relaxation targets g0, g1 of one cell at every node. */
+void orc_ref_dist(const orc_state *s, int cell, double *g0, double *g1)
+{
+    cellpar p;
+    cell_params(s, cell, &p);
+    for (int v = 0; v < s->nv; ++v) {
+        double xi[3], w, a, b;
+        node_xi(s, v, xi, &w);
+        ref_dist(&s->c, &p, xi, &a, &b);
+        g0[v] = a;
+        if (g1) g1[v] = b;
+    }
+}
+
+/* Collision rate 1/tau of one cell from the current VDF. */
+double orc_invtau(const orc_state *s, int cell)
+{
+    cellpar p;
+    cell_params(s, cell, &p);
+    return p.invtau;
+}
+
+/* Boundary values of face (cell, d) at every node (zero at nodes that leave
+ * the cell through that face); returns the face's bc index, or -1 if the face
+ * is interior. */
+int orc_boundary_values(const orc_state *s, int cell, int d, double *b0, double *b1)
+{
+    int n = neighbour(s, cell, d);
+    if (n >= 0) return -1;
+    int bc = -1 - n;
+    double sc = face_scale(s, cell, d, bc);
+    int a = d / 2;
+    double sg = (d & 1) ? 1.0 : -1.0;
+    for (int v = 0; v < s->nv; ++v) {
+        double xi[3], w, x0, x1;
+        node_xi(s, v, xi, &w);
+        boundary_value(&s->c, bc, sc, xi, &x0, &x1);
+        int incoming = sg * xi[a] < 0;
+        b0[v] = incoming ? x0 : 0.0;
+        if (b1) b1[v] = incoming ? x1 : 0.0;
+    }
+    return bc;
+}
+
+/* The four uncorrected reference components (g0t, g0r, g1t, g1r) at n
+ * arbitrary points, from given moments; for pins of Sec. 2.2. */
+void orc_ref_components(const orc_cfg *c, double rho, const double u[3], double Tt, double Tr,
+                        const double qt[3], const double qr[3], int n, const double *xi, double *out)
+{
+    cellpar p;
+    memset(&p, 0, sizeof p);
+    p.m.rho = rho;
+    for (int a = 0; a < 3; ++a) { p.m.u[a] = u[a]; p.m.q[a] = qt[a]; p.m.qr[a] = qr ? qr[a] : 0.0; }
+    p.m.Tt = Tt;
+    p.m.Tr = c->species == 1 ? Tr : Tt;
+    p.m.T = c->species == 1 ? (3.0 * Tt + c->dr * Tr) / (3.0 + c->dr) : Tt;
+    if (c->species == 1) {
+        double Z = c->Zr;
+        for (int a = 0; a < 3; ++a) {
+            p.q0[a] = ((2.0 - 3.0 * c->A[0]) * Z + 1.0) * p.m.q[a] + (-3.0 * c->A[1] * Z) * p.m.qr[a];
+            p.q1[a] = (-c->A[2] * Z) * p.m.q[a] + (-c->A[3] * Z + 1.0) * p.m.qr[a];
+        }
+    }
+    for (int i = 0; i < n; ++i) ref_components(c, &p, xi + 3 * i, out + 4 * i);
+}
+
+/* ------------------------------------------------------- gsis_correct -- */
+/* GSIS-II (Sec. 3.3).  Unknowns per fluid cell, in the units of the moments:
+ *   W = (rho, rho u, E, Er),  E = sum w |xi|^2 f0 + sum w f1 = rho|u|^2 + 1.5 rho Tt + Er,
+ *   Er = sum w f1 = (dr/2) rho Tr   (monatomic: 5 unknowns, Er = 0).
+ * These are the moments 1, xi, |xi|^2 (and 1 on f1) of the kinetic equation,
+ * so the face fluxes are
+ *   mass rho u_n;  momentum rho u u_n + (p n + sigma.n)/2;
+ *   energy (E + p) u_n + (sigma.n).u + q.n + qr.n;  Er: Er u_n + qr.n,  p = rho Tt.
+ * Constitutive relations of Eq. (full_constitutive): sigma = sigma_NSF(W) +
+ * HoT_sigma, q = q_NSF(W) + HoT_q, with the high-order terms evaluated once at
+ * each face from the kinetic moments of f^{n+1/2}:
+ *   HoT = (K_i + K_j)/2 - NSF_face(W^{n+1/2}).
+ * NSF laws of Eq. (NSF_constitutive), Eq. (mu_kappa) in these units:
+ *   sigma_NSF = -(Tt^omega/delta) (grad u + grad u^T - (2/3) div u I),
+ *   q_NSF = -(k_t Tt^omega/delta) grad Tt,  qr_NSF = -(k_r Tt^omega/delta) grad Tr,
+ *   monatomic k_t = 15/8 (Pr = 2/3); diatomic [k_t; k_r] = A^{-1} [5; dr] / 4.
+ * Face gradients: normal derivative (X_j - X_i)/h, tangential derivatives the
+ * mean of the two cells' central (one-sided at walls) gradients.
+ * Convective flux: Rusanov with s = max(|u_n| + c_s), c_s = sqrt(gamma Tt / 2).
+ * Boundary faces: the kinetic boundary flux of f^{n+1/2} keeps its
+ * non-equilibrium part while its equilibrium part follows the iterate, in the
+ * spirit of Eq. (updatef):  F_b(W^m) = F_kin + F_eq(W^m) - F_eq(W^{n+1/2}),
+ * where F_eq(W) is the same face flux for the Maxwellian M(W) of the cell
+ * (outgoing half of M(W), incoming wall Maxwellian with zero mass flux, or the
+ * fixed inflow).  A frozen F_kin alone leaves momentum and energy fluxes that
+ * need not balance, and the closed-box problem then has no steady state.
+ * Iteration: point-Jacobi on the diagonal D of Eq. (res_macro),
+ *   D_i = 1/dtau_i + (1/2) sum_faces Gamma / h,  Gamma = s + C_d Tt^omega / (delta rho h),
+ *   1/dtau_i = (|u| + c_s + C_d Tt^omega/(delta rho h_min)) / (CFL h_min),
+ * C_d = 2 max(diffusivities) (momentum 1/2, heat k_t/1.5, rotational heat
+ * k_r/(dr/2)).  Every cell takes the same pseudo-time step, D* = max_i D_i of
+ * the current iterate, so that sum_i dW_i = sum_i R_i / D* = 0 and the
+ * iteration conserves mass, momentum and energy exactly between walls of zero
+ * flux (a local step would move total mass along the neutral direction of a
+ * closed box).  The rotational relaxation -dQ/dEr = 1/(Z tau) is added to the
+ * Er row of each cell.  Finally Eq. (updatef): f0 += M(W^{n+1}) - M(W^{n+1/2}),
+ * f1 += (dr/2)[Tr' M(W^{n+1}) - Tr M(W^{n+1/2})], M with the translational
+ * temperature (the zero-order solution of the Chapman-Enskog expansion). */
+typedef struct { double rho, u[3], Tt, Tr, p, cs, E, Er; } prim_t;
+
+typedef struct {
+    int dia, nw;
+    double dr, Z, delta, omega, gam, kt, kr, Cd, cfl;
+} macpar;
+
+static void macro_params(const orc_state *s, macpar *mp)
+{
+    const orc_cfg *c = &s->c;
+    mp->dia = c->species == 1;
+    mp->nw = mp->dia ? 6 : 5;
+    mp->dr = c->dr;
+    mp->Z = c->Zr;
+    mp->delta = s->delta;
+    mp->omega = c->omega;
+    mp->cfl = c->macro_cfl;
+    if (mp->dia) {
+        double det = c->A[0] * c->A[3] - c->A[1] * c->A[2];
+        double at = (c->A[3] * 5.0 - c->A[1] * c->dr) / det;
+        double ar = (-c->A[2] * 5.0 + c->A[0] * c->dr) / det;
+        mp->kt = at / 4.0;
+        mp->kr = ar / 4.0;
+        mp->gam = (5.0 + c->dr) / (3.0 + c->dr);
+    } else {
+        mp->kt = 15.0 / 8.0;
+        mp->kr = 0.0;
+        mp->gam = 5.0 / 3.0;
+    }
+    double nu = 0.5;
+    if (mp->kt / 1.5 > nu) nu = mp->kt / 1.5;
+    if (mp->dia && mp->kr / (0.5 * mp->dr) > nu) nu = mp->kr / (0.5 * mp->dr);
+    mp->Cd = 2.0 * nu;
+}
+
+static void prim_of(const macpar *mp, const double *W, prim_t *P)
+{
+    P->rho = W[0];
+    for (int a = 0; a < 3; ++a) P->u[a] = W[1 + a] / W[0];
+    P->E = W[4];
+    P->Er = mp->dia ? W[5] : 0.0;
+    double u2 = P->u[0] * P->u[0] + P->u[1] * P->u[1] + P->u[2] * P->u[2];
+    P->Tt = (2.0 / 3.0) * (P->E - P->Er - P->rho * u2) / P->rho;
+    P->Tr = mp->dia ? 2.0 * P->Er / (mp->dr * P->rho) : P->Tt;
+    P->p = P->rho * P->Tt;
+    P->cs = sqrt(mp->gam * P->Tt / 2.0);
+}
+
+/* Central (one-sided next to non-fluid neighbours) gradient G[b*3+c] = d u_b / d x_c. */
+static void cell_grad(const orc_state *s, const prim_t *P, int cell, double G[9])
+{
+    for (int c = 0; c < 3; ++c) {
+        int nm = neighbour(s, cell, 2 * c), np = neighbour(s, cell, 2 * c + 1);
+        double h = s->h[c];
+        for (int b = 0; b < 3; ++b) {
+            double g;
+            if (nm >= 0 && np >= 0) g = (P[np].u[b] - P[nm].u[b]) / (2.0 * h);
+            else if (np >= 0) g = (P[np].u[b] - P[cell].u[b]) / h;
+            else if (nm >= 0) g = (P[cell].u[b] - P[nm].u[b]) / h;
+            else g = 0.0;
+            G[b * 3 + c] = g;
+        }
+    }
+}
+
+/* NSF stress column sigma_{b a} (b = x,y,z), q_a, qr_a at the face between L and
+ * R = L + e_a. */
+static void nsf_face(const macpar *mp, const prim_t *L, const prim_t *R, const double *gL,
+                     const double *gR, int a, double h, double sigN[3], double *qN, double *qrN)
+{
+    double TF = 0.5 * (L->Tt + R->Tt);
+    double mu = pow(TF, mp->omega) / mp->delta;
+    double G[9];
+    for (int b = 0; b < 3; ++b)
+        for (int c = 0; c < 3; ++c)
+            G[b * 3 + c] = (c == a) ? (R->u[b] - L->u[b]) / h : 0.5 * (gL[b * 3 + c] + gR[b * 3 + c]);
+    double div = G[0] + G[4] + G[8];
+    for (int b = 0; b < 3; ++b)
+        sigN[b] = -mu * (G[b * 3 + a] + G[a * 3 + b] - (b == a ? (2.0 / 3.0) * div : 0.0));
+    *qN = -mp->kt * mu * (R->Tt - L->Tt) / h;
+    *qrN = mp->dia ? -mp->kr * mu * (R->Tr - L->Tr) / h : 0.0;
+}
+
+/* Flux from L to R across the face normal to axis a; hot = (sigma col, q, qr). */
+static void face_flux(const macpar *mp, const prim_t *L, const prim_t *R, const double *gL,
+                      const double *gR, int a, double h, const double hot[5], double F[6], double *Gam)
+{
+    double sigN[3], qN, qrN;
+    nsf_face(mp, L, R, gL, gR, a, h, sigN, &qN, &qrN);
+    const prim_t *S[2] = {L, R};
+    double Phi[2][6], Wv[2][6];
+    for (int k = 0; k < 2; ++k) {
+        const prim_t *P = S[k];
+        double un = P->u[a];
+        Phi[k][0] = P->rho * un;
+        for (int b = 0; b < 3; ++b) Phi[k][1 + b] = P->rho * P->u[b] * un + (b == a ? 0.5 * P->p : 0.0);
+        Phi[k][4] = (P->E + P->p) * un;
+        Phi[k][5] = P->Er * un;
+        Wv[k][0] = P->rho;
+        for (int b = 0; b < 3; ++b) Wv[k][1 + b] = P->rho * P->u[b];
+        Wv[k][4] = P->E;
+        Wv[k][5] = P->Er;
+    }
+    double sL = fabs(L->u[a]) + L->cs, sR = fabs(R->u[a]) + R->cs;
+    double smax = sL > sR ? sL : sR;
+    for (int k = 0; k < 6; ++k) F[k] = 0.5 * (Phi[0][k] + Phi[1][k]) - 0.5 * smax * (Wv[1][k] - Wv[0][k]);
+    double sn[3], uF[3];
+    for (int b = 0; b < 3; ++b) { sn[b] = sigN[b] + hot[b]; uF[b] = 0.5 * (L->u[b] + R->u[b]); }
+    double qn = qN + hot[3], qrn = mp->dia ? qrN + hot[4] : 0.0;
+    for (int b = 0; b < 3; ++b) F[1 + b] += 0.5 * sn[b];
+    F[4] += sn[0] * uF[0] + sn[1] * uF[1] + sn[2] * uF[2] + qn + qrn;
+    F[5] += qrn;
+    double TF = 0.5 * (L->Tt + R->Tt), rF = 0.5 * (L->rho + R->rho);
+    *Gam = smax + mp->Cd * pow(TF, mp->omega) / (mp->delta * rF * h);
+}
+
+/* Kinetic boundary flux of face (cell, d) out of the cell (O6 in the text above):
+ * sum w (xi.n) psi f_face, psi = (1, xi, |xi|^2 f0 + f1, f1); f_face = f of the
+ * cell for outgoing nodes and the boundary value (with rho_w recomputed from
+ * this f, so the wall mass flux is exactly zero) for incoming nodes. */
+static void kinetic_face_flux(const orc_state *s, int cell, int d, int bc, double F[6])
+{
+    const orc_cfg *c = &s->c;
+    int a = d / 2;
+    double sg = (d & 1) ? 1.0 : -1.0;
+    double sc = face_scale(s, cell, d, bc);
+    const double *f0 = s->f0 + (size_t)cell * s->nv;
+    const double *f1 = s->f1 ? s->f1 + (size_t)cell * s->nv : NULL;
+    nsum acc[6];
+    memset(acc, 0, sizeof acc);
+    for (int v = 0; v < s->nv; ++v) {
+        double xi[3], w;
+        node_xi(s, v, xi, &w);
+        double xn = sg * xi[a];
+        if (xn == 0.0) continue;
+        double a0, a1;
+        if (xn > 0) { a0 = f0[v]; a1 = f1 ? f1[v] : 0.0; }
+        else boundary_value(c, bc, sc, xi, &a0, &a1);
+        if (!f1) a1 = 0.0;
+        double x2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+        double ww = w * xn;
+        nadd(&acc[0], ww * a0);
+        for (int b = 0; b < 3; ++b) nadd(&acc[1 + b], ww * xi[b] * a0);
+        nadd(&acc[4], ww * (x2 * a0 + a1));
+        nadd(&acc[5], ww * a1);
+    }
+    for (int k = 0; k < 6; ++k) F[k] = nval(&acc[k]);
+}
+
+/* F_eq of a boundary face: the flux of the face when the cell holds the
+ * Maxwellian of W (f1 = (dr/2) Tr M), with the same boundary rule. */
+static void equilibrium_face_flux(const orc_state *s, const prim_t *P, int d, int bc, double F[6])
+{
+    const orc_cfg *c = &s->c;
+    int a = d / 2;
+    double sg = (d & 1) ? 1.0 : -1.0;
+    int dia = c->species == 1;
+    double sc = c->bc_rho[bc];
+    if (c->bc_kind[bc] == ORC_WALL) {
+        nsum out = {0, 0}, in = {0, 0};
+        for (int v = 0; v < s->nv; ++v) {
+            double xi[3], w;
+            node_xi(s, v, xi, &w);
+            double xn = sg * xi[a];
+            if (xn > 0) nadd(&out, w * xn * maxwellian(P->rho, P->u, P->Tt, xi));
+            else if (xn < 0) nadd(&in, w * (-xn) * maxwellian(1.0, c->bc_u[bc], c->bc_T[bc], xi));
+        }
+        sc = nval(&out) / nval(&in);
+    }
+    nsum acc[6];
+    memset(acc, 0, sizeof acc);
+    for (int v = 0; v < s->nv; ++v) {
+        double xi[3], w;
+        node_xi(s, v, xi, &w);
+        double xn = sg * xi[a];
+        if (xn == 0.0) continue;
+        double a0, a1;
+        if (xn > 0) {
+            a0 = maxwellian(P->rho, P->u, P->Tt, xi);
+            a1 = dia ? 0.5 * c->dr * P->Tr * a0 : 0.0;
+        } else {
+            boundary_value(c, bc, sc, xi, &a0, &a1);
+            if (!dia) a1 = 0.0;
+        }
+        double x2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+        double ww = w * xn;
+        nadd(&acc[0], ww * a0);
+        for (int b = 0; b < 3; ++b) nadd(&acc[1 + b], ww * xi[b] * a0);
+        nadd(&acc[4], ww * (x2 * a0 + a1));
+        nadd(&acc[5], ww * a1);
+    }
+    for (int k = 0; k < 6; ++k) F[k] = nval(&acc[k]);
+}
+
+int orc_gsis_correct(orc_state *s, int iters)
+{
+    const orc_cfg *c = &s->c;
+    macpar mp;
+    macro_params(s, &mp);
+    int ncell = s->ncell, nw = mp.nw;
+    double hmin = s->h[0];
+    if (s->h[1] < hmin) hmin = s->h[1];
+    if (s->h[2] < hmin) hmin = s->h[2];
+    moms *K = calloc((size_t)ncell, sizeof(moms));
+    double *W = calloc((size_t)ncell * 6, sizeof(double));
+    double *Fb = calloc((size_t)ncell * 36, sizeof(double));
+    double *hot = calloc((size_t)ncell * 15, sizeof(double));
+    double *grad = calloc((size_t)ncell * 9, sizeof(double));
+    prim_t *P = calloc((size_t)ncell, sizeof(prim_t));
+    double *R = calloc((size_t)ncell * 6, sizeof(double));
+    double *Dc = calloc((size_t)ncell, sizeof(double));
+    double *Src = calloc((size_t)ncell, sizeof(double));
+
+    /* kinetic moments of f^{n+1/2}, the starting W and the fixed boundary fluxes */
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int cell = 0; cell < ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        cell_moments(s, cell, &K[cell]);
+        const moms *m = &K[cell];
+        double u2 = m->u[0] * m->u[0] + m->u[1] * m->u[1] + m->u[2] * m->u[2];
+        double *w = W + (size_t)cell * 6;
+        w[0] = m->rho;
+        for (int a = 0; a < 3; ++a) w[1 + a] = m->rho * m->u[a];
+        double Er = mp.dia ? 0.5 * c->dr * m->rho * m->Tr : 0.0;
+        w[4] = m->rho * u2 + 1.5 * m->rho * m->Tt + Er;
+        w[5] = Er;
+        for (int d = 0; d < 6; ++d) {
+            int n = neighbour(s, cell, d);
+            if (n < 0) kinetic_face_flux(s, cell, d, -1 - n, Fb + (size_t)cell * 36 + d * 6);
+        }
+    }
+    /* HoT at interior faces (cell, cell + e_a), from W^{n+1/2} */
+    for (int cell = 0; cell < ncell; ++cell)
+        if (!s->solid[cell]) prim_of(&mp, W + (size_t)cell * 6, &P[cell]);
+    /* fixed part of the boundary fluxes: F_kin - F_eq(W^{n+1/2}) */
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int cell = 0; cell < ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        for (int d = 0; d < 6; ++d) {
+            int n = neighbour(s, cell, d);
+            if (n >= 0) continue;
+            double Fe[6];
+            equilibrium_face_flux(s, &P[cell], d, -1 - n, Fe);
+            for (int k = 0; k < 6; ++k) Fb[(size_t)cell * 36 + d * 6 + k] -= Fe[k];
+        }
+    }
+    for (int cell = 0; cell < ncell; ++cell)
+        if (!s->solid[cell]) cell_grad(s, P, cell, grad + (size_t)cell * 9);
+    for (int cell = 0; cell < ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        for (int a = 0; a < 3; ++a) {
+            int nb = neighbour(s, cell, 2 * a + 1);
+            if (nb < 0) continue;
+            double sigN[3], qN, qrN;
+            nsf_face(&mp, &P[cell], &P[nb], grad + (size_t)cell * 9, grad + (size_t)nb * 9, a, s->h[a], sigN, &qN, &qrN);
+            /* sigma column a of the kinetic stress, order xx yy zz xy xz yz */
+            static const int col[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+            double *ho = hot + (size_t)cell * 15 + a * 5;
+            for (int b = 0; b < 3; ++b)
+                ho[b] = 0.5 * (K[cell].sig[col[a][b]] + K[nb].sig[col[a][b]]) - sigN[b];
+            ho[3] = 0.5 * (K[cell].q[a] + K[nb].q[a]) - qN;
+            ho[4] = mp.dia ? 0.5 * (K[cell].qr[a] + K[nb].qr[a]) - qrN : 0.0;
+        }
+    }
+    /* point-Jacobi iterations */
+    for (int it = 0; it < iters; ++it) {
+        for (int cell = 0; cell < ncell; ++cell)
+            if (!s->solid[cell]) prim_of(&mp, W + (size_t)cell * 6, &P[cell]);
+        for (int cell = 0; cell < ncell; ++cell)
+            if (!s->solid[cell]) cell_grad(s, P, cell, grad + (size_t)cell * 9);
+        #pragma omp parallel for schedule(static)
+        for (int cell = 0; cell < ncell; ++cell) {
+            if (s->solid[cell]) continue;
+            const prim_t *Pi = &P[cell];
+            double res[6] = {0, 0, 0, 0, 0, 0}, sumG = 0;
+            for (int d = 0; d < 6; ++d) {
+                int a = d / 2;
+                double h = s->h[a];
+                int n = neighbour(s, cell, d);
+                double F[6], out[6], Gam;
+                if (n >= 0) {
+                    int L = (d & 1) ? cell : n, Rr = (d & 1) ? n : cell;
+                    face_flux(&mp, &P[L], &P[Rr], grad + (size_t)L * 9, grad + (size_t)Rr * 9, a, h,
+                              hot + (size_t)L * 15 + a * 5, F, &Gam);
+                    for (int k = 0; k < 6; ++k) out[k] = (d & 1) ? F[k] : -F[k];
+                } else {
+                    double Fe[6];
+                    equilibrium_face_flux(s, Pi, d, -1 - n, Fe);
+                    for (int k = 0; k < 6; ++k) out[k] = Fb[(size_t)cell * 36 + d * 6 + k] + Fe[k];
+                    Gam = fabs(Pi->u[a]) + Pi->cs + mp.Cd * pow(Pi->Tt, mp.omega) / (mp.delta * Pi->rho * h);
+                }
+                for (int k = 0; k < nw; ++k) res[k] -= out[k] / h;
+                sumG += Gam / h;
+            }
+            double invtau = mp.delta * Pi->rho * pow(Pi->Tt, 1.0 - mp.omega);
+            if (mp.dia) {
+                double T = (3.0 * Pi->Tt + mp.dr * Pi->Tr) / (3.0 + mp.dr);
+                res[5] += 0.5 * mp.dr * Pi->rho * (T - Pi->Tr) * invtau / mp.Z;
+            }
+            double umag = sqrt(Pi->u[0] * Pi->u[0] + Pi->u[1] * Pi->u[1] + Pi->u[2] * Pi->u[2]);
+            double idt = (umag + Pi->cs + mp.Cd * pow(Pi->Tt, mp.omega) / (mp.delta * Pi->rho * hmin)) / (mp.cfl * hmin);
+            double *r = R + (size_t)cell * 6;
+            for (int k = 0; k < 6; ++k) r[k] = res[k];
+            Dc[cell] = idt + 0.5 * sumG;
+            Src[cell] = mp.dia ? invtau / mp.Z : 0.0;
+        }
+        double Dmax = 0.0;
+        for (int cell = 0; cell < ncell; ++cell)
+            if (!s->solid[cell] && Dc[cell] > Dmax) Dmax = Dc[cell];
+        for (int cell = 0; cell < ncell; ++cell) {
+            if (s->solid[cell]) continue;
+            double *w = W + (size_t)cell * 6;
+            const double *r = R + (size_t)cell * 6;
+            for (int k = 0; k < 5; ++k) w[k] += r[k] / Dmax;
+            if (mp.dia) w[5] += r[5] / (Dmax + Src[cell]);
+        }
+    }
+    /* Eq. (updatef) */
+    int bad = 0;
+    for (int cell = 0; cell < ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        prim_of(&mp, W + (size_t)cell * 6, &P[cell]);
+        if (!(P[cell].rho > 0) || !(P[cell].Tt > 0) || !isfinite(P[cell].E)) bad = 1;
+    }
+    if (bad) s->status = -5;
+    #pragma omp parallel for schedule(static)
+    for (int cell = 0; cell < ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        const moms *m = &K[cell];
+        const prim_t *Pn = &P[cell];
+        for (int v = 0; v < s->nv; ++v) {
+            double xi[3], w;
+            node_xi(s, v, xi, &w);
+            double Mn = maxwellian(Pn->rho, Pn->u, Pn->Tt, xi);
+            double Mo = maxwellian(m->rho, m->u, m->Tt, xi);
+            size_t at = (size_t)cell * s->nv + v;
+            s->f0[at] += Mn - Mo;
+            if (mp.dia) s->f1[at] += 0.5 * c->dr * (Pn->Tr * Mn - m->Tr * Mo);
+        }
+    }
+    free(K); free(W); free(Fb); free(hot); free(grad); free(P); free(R); free(Dc); free(Src);
+    return s->status;
+}
+
+/* Total mass sum rho V of the current VDF (closed-cavity drift diagnostic). */
+double orc_total_mass(const orc_state *s)
+{
+    nsum m = {0, 0};
+    for (int cell = 0; cell < s->ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        const double *f0 = s->f0 + (size_t)cell * s->nv;
+        nsum r = {0, 0};
+        for (int v = 0; v < s->nv; ++v) {
+            double xi[3], w;
+            node_xi(s, v, xi, &w);
+            nadd(&r, w * f0[v]);
+        }
+        nadd(&m, nval(&r));
+    }
+    return nval(&m) * s->h[0] * s->h[1] * s->h[2];
+}
+
+/* Heat-conduction coefficients k_t, k_r of the macroscopic solve, with
+ * q = -(k Tt^omega / delta) grad T in the units above (Eq. (mu_kappa)). */
+void orc_conductivities(const orc_cfg *c, double out[2])
+{
+    orc_state s;
+    memset(&s, 0, sizeof s);
+    s.c = *c;
+    s.delta = 1.0;
+    macpar mp;
+    macro_params(&s, &mp);
+    out[0] = mp.kt;
+    out[1] = mp.kr;
+}

@@ -1,0 +1,220 @@
+"""ctypes loader for the FP64 CPU oracle (gsis_oracle.c).
+
+TEST INFRASTRUCTURE: only tests/, __graft_entry__.smoke() and bench.py's
+cpu_baseline leg may import this module.  The product path never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "gsis_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (plain -O2, OpenMP over independent nodes/cells)."""
+    if force or not os.path.exists(LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-fopenmp", "-fPIC", "-shared", SRC, "-o", LIB, "-lm"]
+        subprocess.run(cmd, check=True)
+    return LIB
+
+
+class _Cfg(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
+        ("nv", C.c_int * 3), ("vmin", C.c_double * 3), ("vmax", C.c_double * 3),
+        ("species", C.c_int), ("Kn", C.c_double), ("omega", C.c_double),
+        ("dr", C.c_double), ("Zr", C.c_double), ("A", C.c_double * 4),
+        ("inv_dt", C.c_double), ("conservative", C.c_int), ("macro_cfl", C.c_double),
+        ("bc_kind", C.c_int * 7), ("bc_u", (C.c_double * 3) * 7), ("bc_T", C.c_double * 7),
+        ("bc_rho", C.c_double * 7),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        P = C.c_void_p
+        D = C.POINTER(C.c_double)
+        L.orc_create.restype = P
+        L.orc_create.argtypes = [C.POINTER(_Cfg), C.c_void_p]
+        L.orc_free.argtypes = [P]
+        L.orc_ncell.argtypes = [P]
+        L.orc_nv.argtypes = [P]
+        L.orc_status.argtypes = [P]
+        L.orc_step.argtypes = [P, C.c_int]
+        L.orc_init_maxwellian.argtypes = [P, C.c_double, D, C.c_double, C.c_double]
+        L.orc_set_vdf.argtypes = [P, D, D]
+        L.orc_get_vdf.argtypes = [P, D, D]
+        L.orc_moments.argtypes = [P, D]
+        L.orc_residual.argtypes = [P, D]
+        L.orc_gsis_correct.argtypes = [P, C.c_int]
+        L.orc_ref_dist.argtypes = [P, C.c_int, D, D]
+        L.orc_invtau.argtypes = [P, C.c_int]
+        L.orc_invtau.restype = C.c_double
+        L.orc_boundary_values.argtypes = [P, C.c_int, C.c_int, D, D]
+        L.orc_total_mass.argtypes = [P]
+        L.orc_total_mass.restype = C.c_double
+        L.orc_ref_components.argtypes = [C.POINTER(_Cfg), C.c_double, D, C.c_double, C.c_double, D, D,
+                                         C.c_int, D, D]
+        L.orc_conductivities.argtypes = [C.POINTER(_Cfg), D]
+        _lib = L
+    return _lib
+
+
+def _dp(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_cfg(case) -> _Cfg:
+    c = _Cfg()
+    c.nx, c.ny, c.nz = case.nx, case.ny, case.nz
+    c.lx, c.ly, c.lz = case.lx, case.ly, case.lz
+    for a in range(3):
+        c.nv[a] = case.nv[a]
+        c.vmin[a] = case.vmin[a]
+        c.vmax[a] = case.vmax[a]
+    c.species = case.species
+    c.Kn, c.omega = case.Kn, case.omega
+    c.dr, c.Zr = case.dr, case.Zr
+    for k in range(4):
+        c.A[k] = case.A[k]
+    c.inv_dt = case.inv_dt
+    c.conservative = case.conservative
+    c.macro_cfl = case.macro_cfl
+    for b, bc in enumerate(case.bcs):
+        c.bc_kind[b] = bc.kind
+        for a in range(3):
+            c.bc_u[b][a] = bc.u[a]
+        c.bc_T[b] = bc.T
+        c.bc_rho[b] = bc.rho
+    return c
+
+
+class Oracle:
+    """One problem state held by the C oracle (canonical [cell][node] FP64 VDFs)."""
+
+    def __init__(self, case):
+        self.case = case
+        self._cfg = make_cfg(case)
+        self._mask = case.solid_mask()
+        self.h = lib().orc_create(C.byref(self._cfg), self._mask.ctypes.data_as(C.c_void_p))
+        if not self.h:
+            raise ValueError("oracle rejected the configuration")
+        self.ncell = case.ncell
+        self.nv = case.nvel
+        self.nmom = 18 if case.species == 1 else 14
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_free(self.h)
+            self.h = None
+
+    def init_maxwellian(self, rho=None, u=None, T=None, Tr=None):
+        r0, u0, T0, Tr0 = self.case.init
+        rho = r0 if rho is None else rho
+        u = np.array(u0 if u is None else u, dtype=np.float64)
+        T = T0 if T is None else T
+        Tr = Tr0 if Tr is None else Tr
+        lib().orc_init_maxwellian(self.h, rho, _dp(u), T, Tr)
+
+    def step(self, n: int = 1) -> int:
+        return lib().orc_step(self.h, n)
+
+    def gsis_correct(self, iters: int) -> int:
+        return lib().orc_gsis_correct(self.h, iters)
+
+    def status(self) -> int:
+        return lib().orc_status(self.h)
+
+    def moments(self) -> np.ndarray:
+        out = np.empty((self.ncell, self.nmom), dtype=np.float64)
+        lib().orc_moments(self.h, _dp(out))
+        return out
+
+    def residual(self) -> np.ndarray:
+        e = np.empty(3, dtype=np.float64)
+        lib().orc_residual(self.h, _dp(e))
+        return e
+
+    def get_vdf(self):
+        f0 = np.empty((self.ncell, self.nv), dtype=np.float64)
+        f1 = np.empty_like(f0) if self.case.species == 1 else None
+        lib().orc_get_vdf(self.h, _dp(f0), _dp(f1))
+        return f0, f1
+
+    def set_vdf(self, f0: np.ndarray, f1: Optional[np.ndarray] = None):
+        f0 = np.ascontiguousarray(f0, dtype=np.float64)
+        f1 = None if f1 is None else np.ascontiguousarray(f1, dtype=np.float64)
+        lib().orc_set_vdf(self.h, _dp(f0), _dp(f1))
+
+    def ref_dist(self, cell: int):
+        g0 = np.empty(self.nv)
+        g1 = np.empty(self.nv)
+        lib().orc_ref_dist(self.h, cell, _dp(g0), _dp(g1))
+        return g0, (g1 if self.case.species == 1 else None)
+
+    def invtau(self, cell: int) -> float:
+        return lib().orc_invtau(self.h, cell)
+
+    def boundary_values(self, cell: int, d: int):
+        b0 = np.empty(self.nv)
+        b1 = np.empty(self.nv)
+        bc = lib().orc_boundary_values(self.h, cell, d, _dp(b0), _dp(b1))
+        return bc, b0, b1
+
+    def total_mass(self) -> float:
+        return lib().orc_total_mass(self.h)
+
+
+def ref_components(case, rho, u, Tt, Tr, qt, qr, xi: np.ndarray) -> np.ndarray:
+    """Uncorrected (g0t, g0r, g1t, g1r) at points xi[n,3] from given moments."""
+    cfg = make_cfg(case)
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    n = xi.shape[0]
+    out = np.empty((n, 4))
+    u = np.asarray(u, dtype=np.float64)
+    qt = np.asarray(qt, dtype=np.float64)
+    qr = np.asarray(qr, dtype=np.float64)
+    lib().orc_ref_components(C.byref(cfg), rho, _dp(u), Tt, Tr, _dp(qt), _dp(qr), n, _dp(xi), _dp(out))
+    return out
+
+
+def conductivities(case) -> np.ndarray:
+    """(k_t, k_r) of the oracle's macroscopic heat fluxes."""
+    cfg = make_cfg(case)
+    out = np.empty(2)
+    lib().orc_conductivities(C.byref(cfg), _dp(out))
+    return out
+
+
+def node_grid(case):
+    """Nodes (n,3) and trapezoid weights (n,) in canonical order (x fastest)."""
+    axes, wts = [], []
+    for a in range(3):
+        x = np.linspace(case.vmin[a], case.vmax[a], case.nv[a])
+        d = (case.vmax[a] - case.vmin[a]) / (case.nv[a] - 1)
+        w = np.full(case.nv[a], d)
+        w[0] *= 0.5
+        w[-1] *= 0.5
+        axes.append(x)
+        wts.append(w)
+    Z, Y, X = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    WZ, WY, WX = np.meshgrid(wts[2], wts[1], wts[0], indexing="ij")
+    xi = np.stack([X.reshape(-1), Y.reshape(-1), Z.reshape(-1)], axis=1)
+    return xi, (WX * WY * WZ).reshape(-1)

@@ -1,0 +1,213 @@
+"""Seeded synthetic workloads and inputs, shared by the tests, the bench and the oracle.
+
+This module holds configuration data only -- grid sizes, velocity grids, gas
+constants and boundary conditions -- plus seeded random inputs.  It contains
+none of the method's arithmetic, so both the GPU binding and the CPU oracle can
+read the same case description without sharing any computation.
+
+The workloads stand in for the paper's test problems, whose meshes and
+reference data are not published: a 3-D lid-driven cavity for the 2-D cavity
+of Sec. 4.1, and a cube in a Ma = 5 stream for the Apollo reentry capsule of
+Sec. 4.2.  Velocities are in units of the most probable speed sqrt(2 R T0),
+lengths in the cavity side (or the block side).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+WALL = 0
+INFLOW = 1
+
+MONATOMIC = 0
+DIATOMIC = 1
+
+# Nitrogen (Sec. 4): internal degrees of freedom, rotational collision number,
+# viscosity index and the heat-flux relaxation rates A_tt, A_tr, A_rt, A_rr.
+N2_DR = 2.0
+N2_ZR = 3.5
+N2_OMEGA = 0.74
+N2_A = (0.786, -0.201, -0.059, 0.842)
+
+
+@dataclasses.dataclass
+class Boundary:
+    kind: int = WALL
+    u: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    T: float = 1.0
+    rho: float = 1.0
+
+
+@dataclasses.dataclass
+class Case:
+    """One problem: uniform hex cells, tensor velocity grid, gas, boundaries.
+
+    ``bcs`` has 7 entries: the box faces -x, +x, -y, +y, -z, +z and the surface
+    of solid cells.  ``solid`` is a uint8 array of nx*ny*nz (x fastest) or None.
+    """
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    lx: float
+    ly: float
+    lz: float
+    nv: Tuple[int, int, int]
+    vmin: Tuple[float, float, float]
+    vmax: Tuple[float, float, float]
+    Kn: float
+    omega: float = 0.75
+    species: int = MONATOMIC
+    dr: float = 0.0
+    Zr: float = 1.0
+    A: Tuple[float, float, float, float] = (0.0, 0.0, 0.0, 0.0)
+    inv_dt: float = 0.0
+    conservative: int = 1
+    macro_cfl: float = 10.0
+    bcs: List[Boundary] = dataclasses.field(default_factory=lambda: [Boundary() for _ in range(7)])
+    solid: Optional[np.ndarray] = None
+    init: Tuple[float, Tuple[float, float, float], float, float] = (1.0, (0.0, 0.0, 0.0), 1.0, 1.0)
+    # iteration plan of the workload
+    passes: int = 10
+    gsis: bool = False
+    macro_iters: int = 300
+    tol: float = 1e-6
+    max_iters: int = 100
+
+    @property
+    def ncell(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def nvel(self) -> int:
+        return self.nv[0] * self.nv[1] * self.nv[2]
+
+    @property
+    def nfluid(self) -> int:
+        return self.ncell - (0 if self.solid is None else int(self.solid.sum()))
+
+    def solid_mask(self) -> np.ndarray:
+        if self.solid is None:
+            return np.zeros(self.ncell, dtype=np.uint8)
+        return np.ascontiguousarray(self.solid, dtype=np.uint8)
+
+
+def cavity(n: int, m: int, Kn: float, lid: float = 0.1, vmax: float = 4.0, omega: float = 0.75,
+           name: str = "cavity", lid_axis: int = 0, **kw) -> Case:
+    """Lid-driven cubic cavity: n^3 cells on the unit cube, m^3 nodes on [-vmax, vmax]^3,
+    diffuse walls at T = 1, the z = 1 face moving with speed ``lid`` along ``lid_axis``."""
+    bcs = [Boundary(WALL, (0.0, 0.0, 0.0), 1.0) for _ in range(7)]
+    u = [0.0, 0.0, 0.0]
+    u[lid_axis] = lid
+    bcs[5] = Boundary(WALL, tuple(u), 1.0)
+    return Case(name=name, nx=n, ny=n, nz=n, lx=1.0, ly=1.0, lz=1.0, nv=(m, m, m),
+                vmin=(-vmax,) * 3, vmax=(vmax,) * 3, Kn=Kn, omega=omega, bcs=bcs, **kw)
+
+
+def free_stream_speed(Ma: float, gamma: float) -> float:
+    """Speed of a Mach-Ma stream at T = 1 in units of sqrt(2 R T0): Ma sqrt(gamma/2)."""
+    return Ma * math.sqrt(gamma / 2.0)
+
+
+def block_flow(nx: int, ny: int, nz: int, block: Tuple[Tuple[int, int], Tuple[int, int], Tuple[int, int]],
+               m: int, vmax: float, Kn: float, Ma: float = 5.0, species: int = MONATOMIC,
+               omega: float = 0.75, name: str = "block", **kw) -> Case:
+    """A solid block of masked cells in a uniform stream along +x.
+
+    The block side is the length scale (h = 1 / block cells along x; 1/16 for an
+    empty block), every box face lets in the free-stream Maxwellian, the block
+    surface is a diffuse wall at T_w = 1."""
+    bx = block[0][1] - block[0][0]
+    h = 1.0 / (bx if bx > 0 else 16)
+    solid = np.zeros((nz, ny, nx), dtype=np.uint8)
+    solid[block[2][0]:block[2][1], block[1][0]:block[1][1], block[0][0]:block[0][1]] = 1
+    gamma = 5.0 / 3.0 if species == MONATOMIC else (5.0 + N2_DR) / (3.0 + N2_DR)
+    U = free_stream_speed(Ma, gamma)
+    bcs = [Boundary(INFLOW, (U, 0.0, 0.0), 1.0, 1.0) for _ in range(6)]
+    bcs.append(Boundary(WALL, (0.0, 0.0, 0.0), 1.0))
+    extra = {}
+    if species == DIATOMIC:
+        extra = dict(dr=N2_DR, Zr=N2_ZR, A=N2_A)
+        omega = N2_OMEGA
+    return Case(name=name, nx=nx, ny=ny, nz=nz, lx=nx * h, ly=ny * h, lz=nz * h, nv=(m, m, m),
+                vmin=(-vmax,) * 3, vmax=(vmax,) * 3, Kn=Kn, omega=omega, species=species,
+                bcs=bcs, solid=solid.reshape(-1), init=(1.0, (U, 0.0, 0.0), 1.0, 1.0), **extra, **kw)
+
+
+# ----------------------------------------------------------------- workloads
+def c1() -> Case:
+    """16^3 cavity, 16^3 nodes on [-4,4]^3, Kn = 0.1, lid 0.1, 10 source iterations, FP64."""
+    return cavity(16, 16, 0.1, name="c1_cavity16_v16", passes=10)
+
+
+def c2() -> Case:
+    """48^3 cavity, 32^3 nodes, Kn = 0.01, GSIS until the relative change of rho and T < 1e-6."""
+    return cavity(48, 32, 0.01, name="c2_cavity48_v32_gsis", gsis=True, passes=1, max_iters=200)
+
+
+def c3() -> Case:
+    """Ma = 5 past a 16^3 block in 96x64x64 cells, 40^3 nodes on [-12,12]^3, Kn = 0.05, 20 passes."""
+    return block_flow(96, 64, 64, ((40, 56), (24, 40), (24, 40)), 40, 12.0, 0.05,
+                      name="c3_block96x64x64_v40", passes=20)
+
+
+def c4() -> Case:
+    """Diatomic N2 (Rykov, Z = 3.5), Ma = 5 past a 16^3 block in 64x48x48 cells, 32^3 nodes, GSIS."""
+    return block_flow(64, 48, 48, ((24, 40), (16, 32), (16, 32)), 32, 12.0, 0.05, species=DIATOMIC,
+                      name="c4_n2_block64x48x48_v32_gsis", gsis=True, passes=1)
+
+
+def c5(seed: int = 2310_18916, ncases: int = 64) -> List[Case]:
+    """64 cavities: n ~ U{8..32} cells/side, m ~ U{12..24} nodes/side, Kn = 10^U(-3,0),
+    lid ~ U(0.05, 0.3); draws in case order as (n, m, log10 Kn, lid)."""
+    rng = np.random.default_rng(seed)
+    cases = []
+    for i in range(ncases):
+        n = int(rng.integers(8, 33))
+        m = int(rng.integers(12, 25))
+        kn = float(10.0 ** rng.uniform(-3.0, 0.0))
+        lid = float(rng.uniform(0.05, 0.3))
+        cases.append(cavity(n, m, kn, lid=lid, name=f"c5_case{i}", gsis=True, max_iters=50))
+    return cases
+
+
+def small(case: Case, n: Optional[int] = None, m: Optional[int] = None) -> Case:
+    """A reduced copy of a workload with the same physics (for full-field parity)."""
+    c = dataclasses.replace(case)
+    if case.solid is not None:
+        raise ValueError("use small_block for masked cases")
+    if n is not None:
+        c.nx = c.ny = c.nz = n
+    if m is not None:
+        c.nv = (m, m, m)
+    return c
+
+
+def small_block(species: int = MONATOMIC, n: Tuple[int, int, int] = (12, 9, 10), blk=((4, 7), (3, 6), (4, 6)),
+                m: int = 10, vmax: float = 12.0, Kn: float = 0.05, name: str = "block_small", **kw) -> Case:
+    """Reduced block flow: same physics as c3/c4 on a coarse grid with a ragged block."""
+    c = block_flow(n[0], n[1], n[2], blk, m, vmax, Kn, species=species, name=name, **kw)
+    return c
+
+
+# -------------------------------------------------------------- random data
+def random_vdf(case: Case, seed: int, dtype=np.float64) -> Tuple[np.ndarray, Optional[np.ndarray]]:
+    """Positive random VDFs in the canonical [cell][node] layout (node x fastest):
+    a Maxwellian-like envelope in node index times U(0.5, 1.5) noise."""
+    rng = np.random.default_rng(seed)
+    shape = (case.ncell, case.nvel)
+    axes = [np.linspace(case.vmin[a], case.vmax[a], case.nv[a]) for a in range(3)]
+    xz, xy, xx = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    env = np.exp(-(xx ** 2 + xy ** 2 + xz ** 2) / (1.0 + 0.25 * max(case.vmax) ** 2 / 16.0)).reshape(-1)
+    f0 = (env[None, :] * rng.uniform(0.5, 1.5, size=shape)).astype(dtype)
+    f1 = None
+    if case.species == DIATOMIC:
+        f1 = (env[None, :] * rng.uniform(0.5, 1.5, size=shape)).astype(dtype)
+    if case.solid is not None:
+        f0[case.solid.astype(bool)] = 0
+        if f1 is not None:
+            f1[case.solid.astype(bool)] = 0
+    return f0, f1
