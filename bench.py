@@ -1,0 +1,155 @@
+"""Throughput of the GSIS kinetic hot path on one MI355X.
+
+A step is one GSIS iteration of the whole hot path on one batch of synthetic
+input: a kinetic pass (parameter build, boundary densities, implicit upwind
+sweep, moment reduction), the GSIS-II macroscopic correction (300 inner
+iterations) and the residual.  The workload is the 48^3-cell, 32^3-node
+lid-driven cavity at Kn = 0.01 in FP64 (full GSIS).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    p.add_argument("--dtype", default=None, choices=["fp64", "fp32"])
+    p.add_argument("--macro-iters", type=int, default=None)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-fp32", action="store_true")
+    p.add_argument("--tile", default=None, help="tx,ty,tz,block")
+    return p.parse_args()
+
+
+def workload(name):
+    from paper_2310_18916_amd import inputs as I
+    return {"c1": I.c1, "c2": I.c2, "c3": I.c3}[name]()
+
+
+def run_gpu(case, dtype, steps, warmup, macro_iters, tile):
+    import torch
+    from paper_2310_18916_amd.gsis import Solver
+    s = Solver(case, dtype, tile=tile)
+    s.init_maxwellian()
+
+    def step():
+        s.kinetic_step(1)
+        if case.gsis:
+            s.gsis_correct(macro_iters)
+        return s.residual()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    s.profile_read(reset=True)
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eps = None
+    for _ in range(steps):
+        eps = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.profile(False)
+    prof = s.profile_read(reset=True)
+    return {"seconds": t1 - t0, "prof": prof, "eps": [float(x) for x in eps], "solver": s}
+
+
+def cpu_baseline(case):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload: the same
+    velocity grid and gas on a 10^3-cell corner of the cavity, one kinetic pass."""
+    from oracle.oracle import Oracle, build
+    from paper_2310_18916_amd import inputs as I
+    if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
+        build()
+    n = 10
+    sample = I.cavity(n, case.nv[0], case.Kn, lid=case.bcs[5].u[0], vmax=case.vmax[0], omega=case.omega)
+    o = Oracle(sample)
+    o.init_maxwellian()
+    t0 = time.perf_counter()
+    o.step(1)
+    dt = time.perf_counter() - t0
+    pts = sample.ncell * sample.nvel
+    cores = len(os.sched_getaffinity(0))
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    return {"value": pts / dt, "unit": "cell-updates/s", "cores": min(cores, threads), "kind": "oracle",
+            "sample": f"one FP64 kinetic pass of the oracle on {n}^3 cells x {sample.nv[0]}^3 nodes "
+                      f"(same velocity grid and Kn), {dt:.2f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the path is single-GPU by design",
+              file=sys.stderr)
+        sys.exit(2)
+    case = workload(a.workload)
+    dtype = a.dtype or ("fp32" if a.workload == "c3" else "fp64")
+    macro = a.macro_iters if a.macro_iters is not None else case.macro_iters
+    tile = tuple(int(x) for x in a.tile.split(",")) if a.tile else None
+    r = run_gpu(case, dtype, a.steps, a.warmup, macro, tile)
+    pts = case.nfluid * case.nvel
+    steps = a.steps
+    value = pts * steps / r["seconds"]
+    prof = r["prof"]
+    esz = 8 if dtype == "fp64" else 4
+    sweep_ms, sweep_n = prof["sweep"]
+    mom_ms, mom_n = prof["moments"]
+    sweep_bytes = pts * esz * (2 if case.inv_dt != 0 else 1)   # write f^{n+1/2} (+ read f^n if 1/dt != 0)
+    mom_bytes = pts * esz                                       # read f^{n+1/2}
+    sweep_gbs = sweep_bytes / (sweep_ms / sweep_n * 1e-3) / 1e9
+    mom_gbs = mom_bytes / (mom_ms / mom_n * 1e-3) / 1e9
+    dominant = "sweep" if sweep_ms >= mom_ms else "moments"
+    ach = sweep_gbs if dominant == "sweep" else mom_gbs
+    out = {
+        "metric": "phase-space cell-updates/s (cells x velocities); FP32 vs FP64 at equal accuracy",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": a.warmup,
+        "ms_per_step": r["seconds"] / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if dtype == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": case.name, "cells": case.ncell, "fluid_cells": case.nfluid, "nodes": case.nvel,
+                   "Kn": case.Kn, "gsis": case.gsis, "macro_iters": macro if case.gsis else 0,
+                   "step": "kinetic pass + gsis_correct + residual" if case.gsis else "kinetic pass + residual"},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": dominant},
+        "phases_ms_per_step": {k: v[0] / steps for k, v in prof.items()},
+        "kinetic_only_updates_per_s": pts * steps / ((prof["prep"][0] + sweep_ms + mom_ms) * 1e-3),
+        "sweep_gbs": sweep_gbs,
+        "moments_gbs": mom_gbs,
+        "final_eps": r["eps"],
+    }
+    del r
+    if not a.no_fp32 and dtype == "fp64":
+        r32 = run_gpu(case, "fp32", steps, a.warmup, macro, None)
+        v32 = pts * steps / r32["seconds"]
+        out["fp32"] = {"value": v32, "speedup_vs_fp64": v32 / value,
+                       "phases_ms_per_step": {k: v[0] / steps for k, v in r32["prof"].items()}}
+        del r32
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * gsis.h -- C-ABI of libgsis.so, the MI355X (gfx950) kinetic hot path of the
+ * general synthetic iterative scheme (GSIS) of arXiv 2310.18916, "Efficient
+ * parallel solver for rarefied gas flow using GSIS".
+ *
+ * One kinetic pass (gsis_kinetic_step) builds, for every fluid cell and
+ * velocity node, the Shakhov (monatomic) or Rykov two-VDF (diatomic)
+ * reference distribution of Sec. 2.2, solves the implicit first-order upwind
+ * transport system of Sec. 3.2 (Eq. delta_equations with first-order fluxes
+ * on both sides) exactly by upwind sweeps, and reduces the distribution to
+ * the moments of Eq. (getmoment).  gsis_gsis_correct runs the GSIS-II
+ * macroscopic synthetic solve of Sec. 3.3 and schedules the VDF update of
+ * Eq. (updatef); gsis_residual evaluates the convergence criterion of Sec. 4.
+ * The calls mirror the Require/Ensure lists of Algorithms 1-3: the kinetic
+ * solver takes f and returns W, the high-order terms and the boundary flux;
+ * the macroscopic solver takes those and returns W.
+ *
+ * Units are dimensionless: lengths in L, molecular velocity in the most
+ * probable speed sqrt(2 R T0), density in rho0, temperature in T0.
+ *
+ * Conventions for every call:
+ *  - Every call returns gsis_status; nothing throws or aborts across the ABI.
+ *    On an error the message is available from gsis_last_error(ctx).
+ *  - All argument checks run on the host before any device work.
+ *  - The library owns host metadata only.  Device memory is caller owned:
+ *    query gsis_workspace_size, allocate that many bytes on the GPU (256-byte
+ *    aligned) and pass them to gsis_bind_workspace.  The library never calls
+ *    hipMalloc.
+ *  - Device work is asynchronous on the bound stream (gsis_set_stream) except
+ *    where a call says it synchronises.
+ *  - One context per host thread; calls on one context must not overlap.
+ *  - Canonical external layouts: cells x fastest, c = i + nx (j + ny k);
+ *    velocity nodes x fastest, v = kx + nvx (ky + nvy kz); a VDF is
+ *    [cell][node].  The internal octant-grouped VDF layout is not exposed.
+ */
+#ifndef GSIS_H
+#define GSIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gsis_ctx gsis_ctx;
+
+typedef enum {
+    GSIS_OK = 0,
+    GSIS_EINVAL = -1,      /* bad argument or configuration */
+    GSIS_ESTATE = -2,      /* call out of order (e.g. step before init) */
+    GSIS_ENOMEM = -3,      /* workspace too small, or host allocation failed */
+    GSIS_EDEVICE = -4,     /* HIP runtime error */
+    GSIS_ENOTFINITE = -5,  /* a non-positive or non-finite density/temperature appeared */
+    GSIS_EDIVERGED = -6    /* residual grew beyond the divergence factor */
+} gsis_status;
+
+enum { GSIS_MONATOMIC = 0, GSIS_DIATOMIC = 1 };
+enum { GSIS_FP64 = 0, GSIS_FP32 = 1 };
+enum { GSIS_DIFFUSE_WALL = 0, GSIS_MAXWELL_INFLOW = 1 };
+/* boundary slots for gsis_set_boundary: box faces, then the solid surface */
+enum { GSIS_FACE_XM = 0, GSIS_FACE_XP = 1, GSIS_FACE_YM = 2, GSIS_FACE_YP = 3,
+       GSIS_FACE_ZM = 4, GSIS_FACE_ZP = 5, GSIS_FACE_SOLID = 6 };
+
+/* Number of FP64 values per cell returned by gsis_moments:
+ * rho, ux, uy, uz, Tt, sxx, syy, szz, sxy, sxz, syz, qx, qy, qz
+ * and, diatomic only, Tr, qrx, qry, qrz (Eq. getmoment; sigma in p0, q in p0 v_m). */
+#define GSIS_NMOM_MONATOMIC 14
+#define GSIS_NMOM_DIATOMIC 18
+
+typedef struct {
+    int nx, ny, nz;            /* uniform hex cells; h = l / n per axis */
+    double lx, ly, lz;
+    int nvx, nvy, nvz;         /* tensor velocity grid, >= 2 nodes per axis */
+    double vmin[3], vmax[3];   /* node k at vmin + k (vmax - vmin)/(n - 1), trapezoid weights */
+    int species;               /* GSIS_MONATOMIC (Shakhov, Pr = 2/3) or GSIS_DIATOMIC (Rykov) */
+    double Kn;                 /* Knudsen number of Sec. 2.1; delta = sqrt(pi) / (2 Kn) */
+    double omega;              /* viscosity index, mu ~ Tt^omega */
+    double dr, Zr, A[4];       /* diatomic: internal DOF, rotational collision number,
+                                  heat-flux relaxation rates A_tt, A_tr, A_rt, A_rr */
+    double inv_dt;             /* 1/Delta t of the kinetic update; 0 = source iteration */
+    int vdf_dtype;             /* GSIS_FP64 or GSIS_FP32 storage and sweep arithmetic */
+    int conservative;          /* 1: reference distribution corrected to conserve the
+                                  discrete mass, momentum and energy exactly */
+    double macro_cfl;          /* pseudo-time CFL of the macroscopic iteration (e.g. 10) */
+} gsis_config;
+
+/* Create a context for cfg.  Validates sizes (n >= 1, nv >= 2, vmax > vmin,
+ * Kn > 0, lengths > 0; diatomic: dr > 0, Zr >= 1, A invertible).  All
+ * boundaries default to a diffuse wall at rest with T = 1.  *out is NULL on
+ * error. */
+gsis_status gsis_create(gsis_ctx **out, const gsis_config *cfg);
+
+/* Free the context (host memory only; the caller frees the workspace). */
+gsis_status gsis_destroy(gsis_ctx *ctx);
+
+/* Host array of n = nx*ny*nz bytes, 1 = solid cell, 0 = fluid.  Must precede
+ * gsis_workspace_size.  Solid cells carry no VDF update and report NaN. */
+gsis_status gsis_set_solid_mask(gsis_ctx *ctx, const uint8_t *mask, size_t n);
+
+/* Boundary condition of slot face (GSIS_FACE_*): kind GSIS_DIFFUSE_WALL with
+ * wall velocity u and temperature T (rho ignored; the wall density is set so
+ * the discrete mass flux is zero), or GSIS_MAXWELL_INFLOW with the Maxwellian
+ * (rho, u, T) entering through the face (Tr = T for the diatomic VDF).  Must
+ * precede gsis_bind_workspace. */
+gsis_status gsis_set_boundary(gsis_ctx *ctx, int face, int kind, const double u[3], double T, double rho);
+
+/* Bytes of device workspace the context needs (after the mask is set). */
+gsis_status gsis_workspace_size(const gsis_ctx *ctx, size_t *bytes);
+
+/* Bind caller-owned device memory (>= gsis_workspace_size bytes, 256-byte
+ * aligned) and upload the geometry and boundary tables.  Synchronises. */
+gsis_status gsis_bind_workspace(gsis_ctx *ctx, void *device_ptr, size_t bytes);
+
+/* HIP stream (hipStream_t) for all later device work; NULL = null stream. */
+gsis_status gsis_set_stream(gsis_ctx *ctx, void *hip_stream);
+
+/* f0 = M(rho, u, T), f1 = (dr/2) Tr M in every fluid cell; resets the
+ * residual snapshot and the pass counter.  Asynchronous. */
+gsis_status gsis_init_maxwellian(gsis_ctx *ctx, double rho, const double u[3], double T, double Tr);
+
+/* npasses kinetic passes (Algorithm 3 with one exact upwind solve per pass):
+ * reference distribution, boundary values from f^n, implicit upwind sweep in
+ * place, moment reduction.  Asynchronous. */
+gsis_status gsis_kinetic_step(gsis_ctx *ctx, int npasses);
+
+/* Cell moments of the current state, [ncell][GSIS_NMOM_*] FP64 (NaN in solid
+ * cells), to host memory (synchronises) or device memory (asynchronous). */
+gsis_status gsis_moments(gsis_ctx *ctx, double *out, int out_is_device);
+
+/* GSIS-II macroscopic correction (Algorithm 2, Sec. 3.3): inner_iters >= 0
+ * point-Jacobi iterations of the synthetic equations with the high-order
+ * terms of Eq. (full_constitutive), then the update of Eq. (updatef), whose
+ * moments are applied at once and whose pointwise part is deferred until the
+ * VDF is next read.  Needs a kinetic step since init.  Asynchronous. */
+gsis_status gsis_gsis_correct(gsis_ctx *ctx, int inner_iters);
+
+/* Convergence criterion of Sec. 4 (volume-weighted relative L2 change of rho,
+ * |u| as a vector, Tt since the previous call or init; a zero denominator
+ * gives the absolute change).  Synchronises.  Returns GSIS_ENOTFINITE if a
+ * kernel met a non-positive/non-finite density or temperature, and
+ * GSIS_EDIVERGED if any component exceeds 1e6 times its first value. */
+gsis_status gsis_residual(gsis_ctx *ctx, double eps[3]);
+
+/* Copy the VDF(s) out / in, canonical [cell][node] FP64 in device memory
+ * (f1 may be NULL for monatomic).  set_vdf resets the residual snapshot.
+ * Asynchronous. */
+gsis_status gsis_get_vdf(gsis_ctx *ctx, double *f0_device, double *f1_device);
+gsis_status gsis_set_vdf(gsis_ctx *ctx, const double *f0_device, const double *f1_device);
+
+/* Checkpoint: the complete iteration state (VDF, moments, pending correction,
+ * residual snapshot, pass counter) as an opaque blob in device memory.
+ * Restoring it and continuing is bitwise identical to never stopping.
+ * Synchronises. */
+gsis_status gsis_state_size(const gsis_ctx *ctx, size_t *bytes);
+gsis_status gsis_get_state(gsis_ctx *ctx, void *dst_device);
+gsis_status gsis_set_state(gsis_ctx *ctx, const void *src_device);
+
+/* Sweep tile (cells per tile along x, y, z in the octant's upwind frame) and
+ * threads per block; 0 picks the built-in default for the VDF precision.
+ * Only compiled shapes are accepted (see gsis_tile_shapes). */
+gsis_status gsis_set_tile(gsis_ctx *ctx, int tx, int ty, int tz, int block);
+
+/* Compiled sweep tile shapes: writes up to max triples (tx, ty, precision in
+ * bits: 32 or 64) to out and their number to *count. */
+gsis_status gsis_tile_shapes(int *out, int max, int *count);
+
+/* Copy the VDF at nnodes canonical node indices (host array) for every cell,
+ * out_device[k][cell] FP64 (f1 of the diatomic gas is not included).  Applies
+ * a pending GSIS update first.  Asynchronous. */
+gsis_status gsis_get_vdf_nodes(gsis_ctx *ctx, const int *nodes, int nnodes, double *out_device);
+
+/* Phase timing with HIP events on the bound stream.  Phases: */
+enum { GSIS_PHASE_PREP = 0,      /* per-cell parameters and boundary densities */
+       GSIS_PHASE_SWEEP = 1,     /* implicit upwind sweep (all tile-plane launches of a pass) */
+       GSIS_PHASE_MOMENTS = 2,   /* moment reduction and central moments */
+       GSIS_PHASE_MACRO = 3,     /* gsis_correct: macroscopic solve and moment update */
+       GSIS_PHASE_RESIDUAL = 4,  /* gsis_residual */
+       GSIS_NPHASE = 5 };
+/* enable != 0 starts recording (events are created on first use and kept by the
+ * context); 0 stops. */
+gsis_status gsis_profile_enable(gsis_ctx *ctx, int enable);
+/* Synchronises, then returns the accumulated milliseconds and call counts per
+ * phase (arrays of GSIS_NPHASE); reset != 0 clears them. */
+gsis_status gsis_profile_read(gsis_ctx *ctx, double *ms, long long *calls, int reset);
+
+/* Number of kinetic passes since init/set_vdf. */
+gsis_status gsis_pass_count(const gsis_ctx *ctx, long long *passes);
+
+/* NUL-terminated message of the last error on ctx (static string if ctx is NULL). */
+const char *gsis_last_error(const gsis_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSIS_H */

@@ -1,0 +1,113 @@
+// Internal definitions shared by the libgsis kernels and the host runtime.
+// Not part of the public ABI (see include/gsis.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsis {
+
+constexpr int NRS = 17;    // raw moments stored per (cell, octant):
+                           // 1, x, y, z, xx, yy, zz, xy, xz, yz, x|xi|^2, y|xi|^2, z|xi|^2 on f0,
+                           // then 1, x, y, z on f1 (diatomic)
+constexpr int NMOM = 18;   // central moments per cell (public order, diatomic tail)
+constexpr int NPAR = 36;   // sweep parameters per cell
+constexpr int NBC = 7;     // 6 box faces + solid surface
+constexpr int NCORR = 12;  // pending GSIS correction per cell: new (rho,u,Tt,Tr), old (rho,u,Tt,Tr)
+constexpr int NSNAP = 5;   // residual snapshot per cell: rho, u, Tt
+constexpr double PI = 3.14159265358979323846;
+
+// Geometry, velocity grid and gas constants, passed to kernels by value.
+//
+// Velocity octant o = sx + 2 sy + 4 sz with s_a = 1 when xi_a < 0 (a node with
+// xi_a = 0 belongs to the positive half).  Along axis a the negative half is
+// nodes [0, k0[a]) and the positive half [k0[a], n1[a]).  Inside an octant the
+// nodes are ordered x fastest; the VDF of a cell is the 8 octants back to back.
+struct Geo {
+    int nx, ny, nz, ncell;
+    double h[3], invh[3];
+    int n1[3], k0[3];
+    int nv;
+    int on[8][3];
+    int osize[8];
+    int obase[8];
+    int species;
+    double delta, omega, dr, Zr, A[4];
+    double inv_dt;
+    int conservative;
+    double macro_cfl;
+    int nface, nfluid;
+    double kt, kr, gam, Cd;   // macroscopic transport constants
+    double hmin;
+};
+
+struct BcInfo {
+    int kind[NBC];
+    double u[NBC][3], T[NBC], rho[NBC];
+};
+
+// Device buffers, carved out of the caller's workspace.
+struct Dev {
+    void *f0, *f1;
+    double *mom8;      // [ncell][8][NRS]
+    double *cm;        // [ncell][NMOM]
+    double *par;       // [ncell][NPAR]
+    float *parf;       // [ncell][NPAR]
+    int *cflag;        // [ncell] 1 = fluid
+    int *nbr;          // [ncell][6]: neighbour cell, or -(face + 1)
+    int *face_cell, *face_dir, *face_bc;   // [nface]
+    double *fscale;    // [nface] density scale of the incoming half
+    float *fscalef;
+    double *xi64[3];   // per-axis nodes
+    float *xi32[3];
+    double *w64[3];    // per-axis trapezoid weights
+    double *xtab;      // [n1x][4]: w, w xi, w xi^2, w xi^3 along x
+    double *ytab;      // [n1y][2]: w, xi
+    double *ztab;      // [n1z][2]
+    double *mb64, *mb1_64;   // [NBC][nv] boundary Maxwellian M(1,u_b,T_b), and (dr/2) T_b times it
+    float *mb32, *mb1_32;
+    double *inpsi;     // [NBC][6][6] incoming half-range psi-moments of M(1,u_b,T_b)
+    int *perm;         // [nv] internal node -> canonical node
+    int *tiles;        // sweep tile list grouped by plane
+    double *corr;      // [ncell][NCORR]
+    double *snap;      // [ncell][NSNAP]
+    double *W, *P, *grad, *K, *hot, *R, *Dc, *Src, *fbfix;   // macroscopic solve
+    double *red;       // reduction scratch
+    unsigned long long *dmax;   // two slots, bit pattern of a positive double
+    int *errflag;
+};
+
+// ------------------------------------------------------------ device helpers
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Maxwellian rho (pi T)^{-3/2} exp(-|xi - u|^2 / T) in units of sqrt(2 R T0).
+__device__ __forceinline__ double maxwell64(double rho, const double *u, double T, double x, double y, double z)
+{
+    double cx = x - u[0], cy = y - u[1], cz = z - u[2];
+    return rho * pow(PI * T, -1.5) * exp(-(cx * cx + cy * cy + cz * cz) / T);
+}
+
+__device__ __forceinline__ void node_of(const Geo &g, int o, int l, int &kx, int &ky, int &kz)
+{
+    int nox = g.on[o][0], noy = g.on[o][1];
+    int lx = l % nox, r = l / nox;
+    int ly = r % noy, lz = r / noy;
+    kx = ((o & 1) ? 0 : g.k0[0]) + lx;
+    ky = ((o & 2) ? 0 : g.k0[1]) + ly;
+    kz = ((o & 4) ? 0 : g.k0[2]) + lz;
+}
+
+// internal node index l in [0, nv) -> (octant, local index)
+__device__ __forceinline__ int octant_of(const Geo &g, int node, int &l)
+{
+    int o = 0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) if (node >= g.obase[k]) o = k;
+    l = node - g.obase[o];
+    return o;
+}
+
+}  // namespace gsis

@@ -1,0 +1,827 @@
+// libgsis host runtime: argument checks, geometry metadata, workspace
+// carving and the kernel sequence behind every C-ABI entry point.
+#include "gsis.h"
+#include "gsis_common.h"
+#include "gsis_launch.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace gsis;
+
+struct gsis_ctx {
+    gsis_config cfg;
+    Geo g;
+    BcInfo bc;
+    bool fp32 = false;
+    std::vector<uint8_t> mask;
+    bool meta_ready = false;
+    std::vector<int> cflag, nbr, face_cell, face_dir, face_bc, perm;
+    std::vector<double> xi[3], w[3];
+    int tx = 0, ty = 0, tz = 0, bs = 0;
+    std::vector<int> tiles, plane_off, plane_cnt;
+    int vw = 1;
+    Dev d;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool bound = false, inited = false, pending = false, stepped = false;
+    long long passes = 0;
+    hipStream_t stream = nullptr;
+    bool have_first = false;
+    double first_eps[3] = {0, 0, 0};
+    std::string err;
+    // phase timing
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_open;
+    double prof_ms[GSIS_NPHASE] = {0};
+    long long prof_calls[GSIS_NPHASE] = {0};
+    ~gsis_ctx()
+    {
+        for (auto &e : ev_open) { hipEventDestroy(e.second.first); hipEventDestroy(e.second.second); }
+        for (auto e : ev_pool) hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+gsis_status fail(gsis_ctx *c, gsis_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                              \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) return fail(ctx, GSIS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool finite3(const double *u) { return u && std::isfinite(u[0]) && std::isfinite(u[1]) && std::isfinite(u[2]); }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <class P> void carve(size_t &off, P *&ptr, size_t count, char *base)
+{
+    off = align256(off);
+    ptr = base ? (P *)(base + off) : nullptr;
+    off += count * sizeof(P);
+}
+
+void default_tile(gsis_ctx *c)
+{
+    if (c->fp32) { c->tx = 8; c->ty = 8; c->tz = 8; c->bs = 128; }
+    else { c->tx = 4; c->ty = 4; c->tz = 4; c->bs = 128; }
+}
+
+size_t sweep_lds(const gsis_ctx *c, int tx, int ty, int bs)
+{
+    return (size_t)tx * ty * bs * (c->fp32 ? 4 : 8) * (c->g.species == 1 ? 2 : 1);
+}
+
+void build_tiles(gsis_ctx *c)
+{
+    const Geo &g = c->g;
+    int ntx = (g.nx + c->tx - 1) / c->tx, nty = (g.ny + c->ty - 1) / c->ty, ntz = (g.nz + c->tz - 1) / c->tz;
+    int nplane = ntx + nty + ntz - 2;
+    c->tiles.clear();
+    c->plane_off.assign(nplane, 0);
+    c->plane_cnt.assign(nplane, 0);
+    for (int s = 0; s < nplane; ++s) {
+        c->plane_off[s] = (int)c->tiles.size();
+        for (int z = 0; z < ntz; ++z)
+            for (int y = 0; y < nty; ++y) {
+                int x = s - y - z;
+                if (x < 0 || x >= ntx) continue;
+                c->tiles.push_back(x | (y << 10) | (z << 20));
+            }
+        c->plane_cnt[s] = (int)c->tiles.size() - c->plane_off[s];
+    }
+}
+
+// neighbour table, boundary faces, node permutation, moment vector width
+void build_meta(gsis_ctx *c)
+{
+    Geo &g = c->g;
+    int nx = g.nx, ny = g.ny, nz = g.nz, n = g.ncell;
+    if (c->mask.empty()) c->mask.assign(n, 0);
+    c->cflag.assign(n, 0);
+    c->nbr.assign((size_t)n * 6, 0);
+    c->face_cell.clear(); c->face_dir.clear(); c->face_bc.clear();
+    for (int cell = 0; cell < n; ++cell) c->cflag[cell] = c->mask[cell] ? 0 : 1;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                int cell = i + nx * (j + ny * k);
+                for (int dir = 0; dir < 6; ++dir) {
+                    if (!c->cflag[cell]) { c->nbr[(size_t)cell * 6 + dir] = -1; continue; }
+                    int a = dir / 2, sg = (dir & 1) ? 1 : -1;
+                    int ii = i + (a == 0 ? sg : 0), jj = j + (a == 1 ? sg : 0), kk = k + (a == 2 ? sg : 0);
+                    int bc = -1, nb = -1;
+                    if (ii < 0 || ii >= nx || jj < 0 || jj >= ny || kk < 0 || kk >= nz) bc = dir;
+                    else {
+                        nb = ii + nx * (jj + ny * kk);
+                        if (!c->cflag[nb]) bc = 6;
+                    }
+                    if (bc >= 0) {
+                        int f = (int)c->face_cell.size();
+                        c->face_cell.push_back(cell);
+                        c->face_dir.push_back(dir);
+                        c->face_bc.push_back(bc);
+                        c->nbr[(size_t)cell * 6 + dir] = -(f + 1);
+                    } else {
+                        c->nbr[(size_t)cell * 6 + dir] = nb;
+                    }
+                }
+            }
+    g.nface = (int)c->face_cell.size();
+    g.nfluid = 0;
+    for (int cell = 0; cell < n; ++cell) g.nfluid += c->cflag[cell];
+    c->perm.assign(g.nv, 0);
+    for (int o = 0; o < 8; ++o)
+        for (int l = 0; l < g.osize[o]; ++l) {
+            int nox = g.on[o][0], noy = g.on[o][1];
+            int lx = l % nox, r = l / nox, ly = r % noy, lz = r / noy;
+            int kx = ((o & 1) ? 0 : g.k0[0]) + lx;
+            int ky = ((o & 2) ? 0 : g.k0[1]) + ly;
+            int kz = ((o & 4) ? 0 : g.k0[2]) + lz;
+            c->perm[g.obase[o] + l] = kx + g.n1[0] * (ky + g.n1[1] * kz);
+        }
+    int vw = c->fp32 ? 4 : 2;
+    while (vw > 1) {
+        bool ok = true;
+        for (int o = 0; o < 8; ++o)
+            if (g.osize[o] > 0 && g.on[o][0] % vw) ok = false;
+        if (ok) break;
+        vw >>= 1;
+    }
+    c->vw = vw;
+    build_tiles(c);
+    c->meta_ready = true;
+}
+
+// Layout of the workspace; with base == nullptr only the size is computed.
+size_t layout(gsis_ctx *c, char *base)
+{
+    const Geo &g = c->g;
+    Dev &d = c->d;
+    size_t off = 0, n = g.ncell, nv = g.nv, esz = c->fp32 ? 4 : 8;
+    size_t nf = std::max(g.nface, 1);
+    char *f0 = nullptr, *f1 = nullptr;
+    carve(off, f0, n * nv * esz, base);
+    if (g.species == 1) carve(off, f1, n * nv * esz, base);
+    d.f0 = f0;
+    d.f1 = f1;
+    carve(off, d.mom8, n * 8 * NRS, base);
+    carve(off, d.cm, n * NMOM, base);
+    carve(off, d.par, n * NPAR, base);
+    carve(off, d.parf, n * NPAR, base);
+    carve(off, d.cflag, n, base);
+    carve(off, d.nbr, n * 6, base);
+    carve(off, d.face_cell, nf, base);
+    carve(off, d.face_dir, nf, base);
+    carve(off, d.face_bc, nf, base);
+    carve(off, d.fscale, nf, base);
+    carve(off, d.fscalef, nf, base);
+    for (int a = 0; a < 3; ++a) {
+        carve(off, d.xi64[a], (size_t)g.n1[a], base);
+        carve(off, d.xi32[a], (size_t)g.n1[a], base);
+        carve(off, d.w64[a], (size_t)g.n1[a], base);
+    }
+    carve(off, d.xtab, (size_t)g.n1[0] * 4, base);
+    carve(off, d.ytab, (size_t)g.n1[1] * 2, base);
+    carve(off, d.ztab, (size_t)g.n1[2] * 2, base);
+    carve(off, d.mb64, (size_t)NBC * nv, base);
+    carve(off, d.mb1_64, (size_t)NBC * nv, base);
+    carve(off, d.mb32, (size_t)NBC * nv, base);
+    carve(off, d.mb1_32, (size_t)NBC * nv, base);
+    carve(off, d.inpsi, (size_t)NBC * 36, base);
+    carve(off, d.perm, nv, base);
+    carve(off, d.tiles, n, base);
+    carve(off, d.corr, n * NCORR, base);
+    carve(off, d.snap, n * NSNAP, base);
+    carve(off, d.W, n * 6, base);
+    carve(off, d.P, n * 8, base);
+    carve(off, d.grad, n * 9, base);
+    carve(off, d.K, n * 12, base);
+    carve(off, d.hot, n * 15, base);
+    carve(off, d.R, n * 6, base);
+    carve(off, d.Dc, n, base);
+    carve(off, d.Src, n, base);
+    carve(off, d.fbfix, nf * 6, base);
+    carve(off, d.red, (size_t)(resid_blocks(g) + 1) * 6, base);
+    carve(off, d.dmax, 2, base);
+    carve(off, d.errflag, 4, base);
+    return align256(off);
+}
+
+gsis_status reset_flags(gsis_ctx *c)
+{
+    HIPCHK(c, launch_zero_int(c->d.errflag, 4, c->stream));
+    return GSIS_OK;
+}
+
+// moments of the stored VDF (octant sums, then central moments)
+gsis_status reduce_vdf(gsis_ctx *c)
+{
+    HIPCHK(c, launch_moments(c->g, c->d, c->fp32, c->vw, c->stream));
+    HIPCHK(c, launch_derive(c->g, c->d, c->stream));
+    return GSIS_OK;
+}
+
+gsis_status materialize(gsis_ctx *c)
+{
+    if (!c->pending) return GSIS_OK;
+    HIPCHK(c, launch_apply_correction(c->g, c->d, c->fp32, c->stream));
+    c->pending = false;
+    return GSIS_OK;
+}
+
+// Records an event pair around a phase when profiling is on.
+struct PhaseTimer {
+    gsis_ctx *c;
+    int phase;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t take(hipEvent_t &e)
+    {
+        if (!c->ev_pool.empty()) { e = c->ev_pool.back(); c->ev_pool.pop_back(); return hipSuccess; }
+        return hipEventCreate(&e);
+    }
+    hipError_t start(gsis_ctx *ctx, int ph)
+    {
+        c = ctx;
+        phase = ph;
+        if (!c->prof) return hipSuccess;
+        hipError_t e = take(a);
+        if (e == hipSuccess) e = take(b);
+        if (e == hipSuccess) e = hipEventRecord(a, c->stream);
+        return e;
+    }
+    hipError_t stop()
+    {
+        if (!c->prof || !a) return hipSuccess;
+        hipError_t e = hipEventRecord(b, c->stream);
+        c->ev_open.push_back({phase, {a, b}});
+        return e;
+    }
+};
+
+struct StateHeader {
+    char magic[8];
+    int version, ncell, nv, fp32, species, pending, stepped, have_first;
+    long long passes;
+    double first_eps[3];
+    char pad[128 - 8 - 9 * 4 - 8 - 24];
+};
+static_assert(sizeof(StateHeader) == 128, "state header size");
+
+struct StatePart { void *ptr; size_t bytes; };
+
+void state_parts(const gsis_ctx *c, std::vector<StatePart> &parts)
+{
+    const Geo &g = c->g;
+    size_t n = g.ncell, esz = c->fp32 ? 4 : 8;
+    parts.clear();
+    parts.push_back({c->d.f0, n * g.nv * esz});
+    if (g.species == 1) parts.push_back({c->d.f1, n * g.nv * esz});
+    parts.push_back({c->d.mom8, n * 8 * NRS * sizeof(double)});
+    parts.push_back({c->d.cm, n * NMOM * sizeof(double)});
+    parts.push_back({c->d.corr, n * NCORR * sizeof(double)});
+    parts.push_back({c->d.snap, n * NSNAP * sizeof(double)});
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gsis_last_error(const gsis_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : "no context";
+}
+
+gsis_status gsis_create(gsis_ctx **out, const gsis_config *cfg)
+{
+    if (!out) return GSIS_EINVAL;
+    *out = nullptr;
+    if (!cfg) return GSIS_EINVAL;
+    const gsis_config &c = *cfg;
+    if (c.nx < 1 || c.ny < 1 || c.nz < 1 || c.nx > 4096 || c.ny > 4096 || c.nz > 4096) return GSIS_EINVAL;
+    if (!(c.lx > 0) || !(c.ly > 0) || !(c.lz > 0) || !std::isfinite(c.lx) || !std::isfinite(c.ly) || !std::isfinite(c.lz))
+        return GSIS_EINVAL;
+    int nvv[3] = {c.nvx, c.nvy, c.nvz};
+    for (int a = 0; a < 3; ++a) {
+        if (nvv[a] < 2 || nvv[a] > 4096) return GSIS_EINVAL;
+        if (!std::isfinite(c.vmin[a]) || !std::isfinite(c.vmax[a]) || !(c.vmax[a] > c.vmin[a])) return GSIS_EINVAL;
+    }
+    long long nv = (long long)c.nvx * c.nvy * c.nvz;
+    long long ncell = (long long)c.nx * c.ny * c.nz;
+    if (nv > (1ll << 30) || ncell > (1ll << 30)) return GSIS_EINVAL;
+    if (c.species != GSIS_MONATOMIC && c.species != GSIS_DIATOMIC) return GSIS_EINVAL;
+    if (!(c.Kn > 0) || !std::isfinite(c.Kn) || !std::isfinite(c.omega)) return GSIS_EINVAL;
+    if (c.species == GSIS_DIATOMIC) {
+        double det = c.A[0] * c.A[3] - c.A[1] * c.A[2];
+        if (!(c.dr > 0) || !(c.Zr >= 1.0) || !std::isfinite(det) || det == 0.0) return GSIS_EINVAL;
+    }
+    if (!(c.inv_dt >= 0) || !std::isfinite(c.inv_dt)) return GSIS_EINVAL;
+    if (c.vdf_dtype != GSIS_FP64 && c.vdf_dtype != GSIS_FP32) return GSIS_EINVAL;
+    if (c.conservative != 0 && c.conservative != 1) return GSIS_EINVAL;
+    if (!(c.macro_cfl > 0) || !std::isfinite(c.macro_cfl)) return GSIS_EINVAL;
+
+    gsis_ctx *x = new (std::nothrow) gsis_ctx();
+    if (!x) return GSIS_ENOMEM;
+    x->cfg = c;
+    x->fp32 = c.vdf_dtype == GSIS_FP32;
+    Geo &g = x->g;
+    std::memset(&g, 0, sizeof g);
+    g.nx = c.nx; g.ny = c.ny; g.nz = c.nz;
+    g.ncell = (int)ncell;
+    g.h[0] = c.lx / c.nx; g.h[1] = c.ly / c.ny; g.h[2] = c.lz / c.nz;
+    g.hmin = std::min(g.h[0], std::min(g.h[1], g.h[2]));
+    for (int a = 0; a < 3; ++a) {
+        g.invh[a] = 1.0 / g.h[a];
+        int n = nvv[a];
+        g.n1[a] = n;
+        double dv = (c.vmax[a] - c.vmin[a]) / (n - 1);
+        x->xi[a].resize(n);
+        x->w[a].resize(n);
+        int k0 = n;
+        for (int k = 0; k < n; ++k) {
+            x->xi[a][k] = c.vmin[a] + k * dv;
+            x->w[a][k] = (k == 0 || k == n - 1) ? 0.5 * dv : dv;
+            if (k0 == n && x->xi[a][k] >= 0.0) k0 = k;
+        }
+        g.k0[a] = k0;
+    }
+    g.nv = (int)nv;
+    int base = 0;
+    for (int o = 0; o < 8; ++o) {
+        int sz = 1;
+        for (int a = 0; a < 3; ++a) {
+            g.on[o][a] = ((o >> a) & 1) ? g.k0[a] : g.n1[a] - g.k0[a];
+            sz *= g.on[o][a];
+        }
+        g.osize[o] = sz;
+        g.obase[o] = base;
+        base += sz;
+    }
+    g.species = c.species;
+    g.delta = std::sqrt(PI) / (2.0 * c.Kn);
+    g.omega = c.omega;
+    g.dr = c.species == GSIS_DIATOMIC ? c.dr : 0.0;
+    g.Zr = c.species == GSIS_DIATOMIC ? c.Zr : 1.0;
+    for (int k = 0; k < 4; ++k) g.A[k] = c.A[k];
+    g.inv_dt = c.inv_dt;
+    g.conservative = c.conservative;
+    g.macro_cfl = c.macro_cfl;
+    if (c.species == GSIS_DIATOMIC) {
+        double det = c.A[0] * c.A[3] - c.A[1] * c.A[2];
+        double at = (c.A[3] * 5.0 - c.A[1] * c.dr) / det;
+        double ar = (-c.A[2] * 5.0 + c.A[0] * c.dr) / det;
+        g.kt = at / 4.0;
+        g.kr = ar / 4.0;
+        g.gam = (5.0 + c.dr) / (3.0 + c.dr);
+    } else {
+        g.kt = 15.0 / 8.0;
+        g.kr = 0.0;
+        g.gam = 5.0 / 3.0;
+    }
+    double nu = 0.5;
+    if (g.kt / 1.5 > nu) nu = g.kt / 1.5;
+    if (c.species == GSIS_DIATOMIC && g.kr / (0.5 * c.dr) > nu) nu = g.kr / (0.5 * c.dr);
+    g.Cd = 2.0 * nu;
+    for (int b = 0; b < NBC; ++b) {
+        x->bc.kind[b] = GSIS_DIFFUSE_WALL;
+        x->bc.u[b][0] = x->bc.u[b][1] = x->bc.u[b][2] = 0.0;
+        x->bc.T[b] = 1.0;
+        x->bc.rho[b] = 1.0;
+    }
+    default_tile(x);
+    *out = x;
+    return GSIS_OK;
+}
+
+gsis_status gsis_destroy(gsis_ctx *ctx)
+{
+    if (!ctx) return GSIS_EINVAL;
+    delete ctx;
+    return GSIS_OK;
+}
+
+gsis_status gsis_set_solid_mask(gsis_ctx *ctx, const uint8_t *mask, size_t n)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (ctx->bound || ctx->meta_ready) return fail(ctx, GSIS_ESTATE, "set_solid_mask must precede workspace_size/bind");
+    if (!mask) return fail(ctx, GSIS_EINVAL, "mask is NULL");
+    if (n != (size_t)ctx->g.ncell) return fail(ctx, GSIS_EINVAL, "mask size must be nx*ny*nz");
+    size_t fluid = 0;
+    for (size_t i = 0; i < n; ++i) {
+        if (mask[i] > 1) return fail(ctx, GSIS_EINVAL, "mask entries must be 0 or 1");
+        fluid += mask[i] == 0;
+    }
+    if (fluid == 0) return fail(ctx, GSIS_EINVAL, "all cells are solid");
+    ctx->mask.assign(mask, mask + n);
+    return GSIS_OK;
+}
+
+gsis_status gsis_set_boundary(gsis_ctx *ctx, int face, int kind, const double u[3], double T, double rho)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (ctx->bound) return fail(ctx, GSIS_ESTATE, "set_boundary must precede bind_workspace");
+    if (face < 0 || face >= NBC) return fail(ctx, GSIS_EINVAL, "face must be 0..6");
+    if (kind != GSIS_DIFFUSE_WALL && kind != GSIS_MAXWELL_INFLOW) return fail(ctx, GSIS_EINVAL, "unknown boundary kind");
+    if (!finite3(u)) return fail(ctx, GSIS_EINVAL, "boundary velocity must be finite");
+    if (!(T > 0) || !std::isfinite(T)) return fail(ctx, GSIS_EINVAL, "boundary temperature must be positive");
+    if (kind == GSIS_MAXWELL_INFLOW && (!(rho >= 0) || !std::isfinite(rho)))
+        return fail(ctx, GSIS_EINVAL, "inflow density must be >= 0");
+    ctx->bc.kind[face] = kind;
+    for (int a = 0; a < 3; ++a) ctx->bc.u[face][a] = u[a];
+    ctx->bc.T[face] = T;
+    ctx->bc.rho[face] = kind == GSIS_MAXWELL_INFLOW ? rho : 1.0;
+    return GSIS_OK;
+}
+
+gsis_status gsis_workspace_size(const gsis_ctx *cctx, size_t *bytes)
+{
+    gsis_ctx *ctx = const_cast<gsis_ctx *>(cctx);
+    if (!ctx || !bytes) return GSIS_EINVAL;
+    if (!ctx->meta_ready) build_meta(ctx);
+    Dev save = ctx->d;
+    *bytes = layout(ctx, nullptr);
+    ctx->d = save;
+    return GSIS_OK;
+}
+
+gsis_status gsis_bind_workspace(gsis_ctx *ctx, void *device_ptr, size_t bytes)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (ctx->bound) return fail(ctx, GSIS_ESTATE, "workspace already bound");
+    if (!device_ptr) return fail(ctx, GSIS_EINVAL, "workspace pointer is NULL");
+    if ((uintptr_t)device_ptr % 256) return fail(ctx, GSIS_EINVAL, "workspace must be 256-byte aligned");
+    if (!ctx->meta_ready) build_meta(ctx);
+    size_t need = layout(ctx, nullptr);
+    if (bytes < need) return fail(ctx, GSIS_ENOMEM, "workspace smaller than gsis_workspace_size");
+    ctx->ws = (char *)device_ptr;
+    ctx->ws_bytes = bytes;
+    layout(ctx, ctx->ws);
+    const Geo &g = ctx->g;
+    Dev &d = ctx->d;
+    auto up = [&](void *dst, const void *src, size_t nbytes) { return hipMemcpy(dst, src, nbytes, hipMemcpyHostToDevice); };
+    HIPCHK(ctx, up(d.cflag, ctx->cflag.data(), ctx->cflag.size() * sizeof(int)));
+    HIPCHK(ctx, up(d.nbr, ctx->nbr.data(), ctx->nbr.size() * sizeof(int)));
+    if (g.nface > 0) {
+        HIPCHK(ctx, up(d.face_cell, ctx->face_cell.data(), g.nface * sizeof(int)));
+        HIPCHK(ctx, up(d.face_dir, ctx->face_dir.data(), g.nface * sizeof(int)));
+        HIPCHK(ctx, up(d.face_bc, ctx->face_bc.data(), g.nface * sizeof(int)));
+    }
+    std::vector<double> xt((size_t)g.n1[0] * 4), yt((size_t)g.n1[1] * 2), zt((size_t)g.n1[2] * 2);
+    for (int a = 0; a < 3; ++a) {
+        std::vector<float> x32(ctx->xi[a].begin(), ctx->xi[a].end());
+        HIPCHK(ctx, up(d.xi64[a], ctx->xi[a].data(), g.n1[a] * sizeof(double)));
+        HIPCHK(ctx, up(d.xi32[a], x32.data(), g.n1[a] * sizeof(float)));
+        HIPCHK(ctx, up(d.w64[a], ctx->w[a].data(), g.n1[a] * sizeof(double)));
+    }
+    for (int k = 0; k < g.n1[0]; ++k) {
+        double x = ctx->xi[0][k], w = ctx->w[0][k];
+        xt[4 * k] = w; xt[4 * k + 1] = w * x; xt[4 * k + 2] = w * x * x; xt[4 * k + 3] = w * x * x * x;
+    }
+    for (int k = 0; k < g.n1[1]; ++k) { yt[2 * k] = ctx->w[1][k]; yt[2 * k + 1] = ctx->xi[1][k]; }
+    for (int k = 0; k < g.n1[2]; ++k) { zt[2 * k] = ctx->w[2][k]; zt[2 * k + 1] = ctx->xi[2][k]; }
+    HIPCHK(ctx, up(d.xtab, xt.data(), xt.size() * sizeof(double)));
+    HIPCHK(ctx, up(d.ytab, yt.data(), yt.size() * sizeof(double)));
+    HIPCHK(ctx, up(d.ztab, zt.data(), zt.size() * sizeof(double)));
+    HIPCHK(ctx, up(d.perm, ctx->perm.data(), ctx->perm.size() * sizeof(int)));
+    HIPCHK(ctx, up(d.tiles, ctx->tiles.data(), ctx->tiles.size() * sizeof(int)));
+    HIPCHK(ctx, hipMemset(d.errflag, 0, 4 * sizeof(int)));
+    HIPCHK(ctx, hipMemset(d.dmax, 0, 2 * sizeof(unsigned long long)));
+    HIPCHK(ctx, launch_setup_tables(g, ctx->bc, d, nullptr));
+    HIPCHK(ctx, hipDeviceSynchronize());
+    ctx->bound = true;
+    return GSIS_OK;
+}
+
+gsis_status gsis_set_stream(gsis_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return GSIS_EINVAL;
+    ctx->stream = (hipStream_t)hip_stream;
+    return GSIS_OK;
+}
+
+gsis_status gsis_init_maxwellian(gsis_ctx *ctx, double rho, const double u[3], double T, double Tr)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (!ctx->bound) return fail(ctx, GSIS_ESTATE, "bind_workspace first");
+    if (!(rho > 0) || !std::isfinite(rho) || !(T > 0) || !std::isfinite(T) || !finite3(u))
+        return fail(ctx, GSIS_EINVAL, "init needs rho > 0, T > 0, finite u");
+    if (ctx->g.species == GSIS_DIATOMIC && (!(Tr > 0) || !std::isfinite(Tr)))
+        return fail(ctx, GSIS_EINVAL, "init needs Tr > 0");
+    gsis_status st = reset_flags(ctx);
+    if (st) return st;
+    HIPCHK(ctx, launch_init_maxwellian(ctx->g, ctx->d, ctx->fp32, rho, u, T, Tr, ctx->stream));
+    if ((st = reduce_vdf(ctx))) return st;
+    HIPCHK(ctx, launch_snapshot(ctx->g, ctx->d, ctx->stream));
+    ctx->pending = false;
+    ctx->inited = true;
+    ctx->stepped = false;
+    ctx->passes = 0;
+    ctx->have_first = false;
+    return GSIS_OK;
+}
+
+gsis_status gsis_kinetic_step(gsis_ctx *ctx, int npasses)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (!ctx->inited) return fail(ctx, GSIS_ESTATE, "initialise the VDF first");
+    if (npasses < 0) return fail(ctx, GSIS_EINVAL, "npasses must be >= 0");
+    const Geo &g = ctx->g;
+    for (int n = 0; n < npasses; ++n) {
+        if (g.inv_dt != 0.0) {
+            gsis_status st = materialize(ctx);
+            if (st) return st;
+        }
+        PhaseTimer t0, t1, t2;
+        HIPCHK(ctx, t0.start(ctx, GSIS_PHASE_PREP));
+        HIPCHK(ctx, launch_params(g, ctx->d, ctx->stream));
+        HIPCHK(ctx, launch_face_scale(g, ctx->bc, ctx->d, ctx->stream));
+        HIPCHK(ctx, t0.stop());
+        HIPCHK(ctx, t1.start(ctx, GSIS_PHASE_SWEEP));
+        HIPCHK(ctx, launch_sweep(g, ctx->d, ctx->fp32, ctx->tx, ctx->ty, ctx->tz, ctx->bs, ctx->plane_off.data(),
+                                 ctx->plane_cnt.data(), (int)ctx->plane_off.size(), ctx->stream));
+        HIPCHK(ctx, t1.stop());
+        ctx->pending = false;   // every fluid point was rewritten
+        HIPCHK(ctx, t2.start(ctx, GSIS_PHASE_MOMENTS));
+        gsis_status st = reduce_vdf(ctx);
+        if (st) return st;
+        HIPCHK(ctx, t2.stop());
+        ctx->passes++;
+        ctx->stepped = true;
+    }
+    return GSIS_OK;
+}
+
+gsis_status gsis_moments(gsis_ctx *ctx, double *out, int out_is_device)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (!ctx->inited) return fail(ctx, GSIS_ESTATE, "initialise the VDF first");
+    if (!out) return fail(ctx, GSIS_EINVAL, "out is NULL");
+    size_t nm = ctx->g.species == GSIS_DIATOMIC ? GSIS_NMOM_DIATOMIC : GSIS_NMOM_MONATOMIC;
+    HIPCHK(ctx, hipMemcpy2DAsync(out, nm * sizeof(double), ctx->d.cm, NMOM * sizeof(double), nm * sizeof(double),
+                                 ctx->g.ncell, out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                 ctx->stream));
+    if (!out_is_device) HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return GSIS_OK;
+}
+
+gsis_status gsis_gsis_correct(gsis_ctx *ctx, int inner_iters)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (!ctx->inited || !ctx->stepped) return fail(ctx, GSIS_ESTATE, "gsis_correct needs a kinetic step since init");
+    if (inner_iters < 0) return fail(ctx, GSIS_EINVAL, "inner_iters must be >= 0");
+    gsis_status st = materialize(ctx);
+    if (st) return st;
+    PhaseTimer t;
+    HIPCHK(ctx, t.start(ctx, GSIS_PHASE_MACRO));
+    HIPCHK(ctx, launch_gsis_macro(ctx->g, ctx->bc, ctx->d, inner_iters, ctx->stream));
+    HIPCHK(ctx, launch_commit_correction(ctx->g, ctx->d, ctx->stream));
+    HIPCHK(ctx, launch_derive(ctx->g, ctx->d, ctx->stream));
+    HIPCHK(ctx, t.stop());
+    ctx->pending = true;
+    return GSIS_OK;
+}
+
+gsis_status gsis_residual(gsis_ctx *ctx, double eps[3])
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (!ctx->inited) return fail(ctx, GSIS_ESTATE, "initialise the VDF first");
+    if (!eps) return fail(ctx, GSIS_EINVAL, "eps is NULL");
+    const Geo &g = ctx->g;
+    PhaseTimer t;
+    HIPCHK(ctx, t.start(ctx, GSIS_PHASE_RESIDUAL));
+    HIPCHK(ctx, launch_residual(g, ctx->d, ctx->stream));
+    double sums[6];
+    int flag[4];
+    HIPCHK(ctx, hipMemcpyAsync(sums, ctx->d.red + (size_t)resid_blocks(g) * 6, sizeof sums, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(flag, ctx->d.errflag, sizeof flag, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, launch_snapshot(g, ctx->d, ctx->stream));
+    HIPCHK(ctx, t.stop());
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < 3; ++k) eps[k] = sums[3 + k] > 0 ? std::sqrt(sums[k] / sums[3 + k]) : std::sqrt(sums[k]);
+    if (flag[0] || !std::isfinite(eps[0]) || !std::isfinite(eps[1]) || !std::isfinite(eps[2]))
+        return fail(ctx, GSIS_ENOTFINITE, "non-positive or non-finite density/temperature (flag " +
+                                              std::to_string(flag[0]) + ")");
+    if (!ctx->have_first) {
+        for (int k = 0; k < 3; ++k) ctx->first_eps[k] = eps[k];
+        ctx->have_first = true;
+    } else {
+        for (int k = 0; k < 3; ++k)
+            if (ctx->first_eps[k] > 0 && eps[k] > 1e6 * ctx->first_eps[k])
+                return fail(ctx, GSIS_EDIVERGED, "residual grew beyond 1e6 times its first value");
+    }
+    return GSIS_OK;
+}
+
+gsis_status gsis_get_vdf(gsis_ctx *ctx, double *f0_device, double *f1_device)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (!ctx->inited) return fail(ctx, GSIS_ESTATE, "initialise the VDF first");
+    if (!f0_device || (ctx->g.species == GSIS_DIATOMIC && !f1_device)) return fail(ctx, GSIS_EINVAL, "NULL output");
+    gsis_status st = materialize(ctx);
+    if (st) return st;
+    HIPCHK(ctx, launch_to_canonical(ctx->g, ctx->d, ctx->fp32, ctx->d.f0, f0_device, ctx->stream));
+    if (ctx->g.species == GSIS_DIATOMIC)
+        HIPCHK(ctx, launch_to_canonical(ctx->g, ctx->d, ctx->fp32, ctx->d.f1, f1_device, ctx->stream));
+    return GSIS_OK;
+}
+
+gsis_status gsis_set_vdf(gsis_ctx *ctx, const double *f0_device, const double *f1_device)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (!ctx->bound) return fail(ctx, GSIS_ESTATE, "bind_workspace first");
+    if (!f0_device || (ctx->g.species == GSIS_DIATOMIC && !f1_device)) return fail(ctx, GSIS_EINVAL, "NULL input");
+    gsis_status st = reset_flags(ctx);
+    if (st) return st;
+    HIPCHK(ctx, launch_from_canonical(ctx->g, ctx->d, ctx->fp32, f0_device, ctx->d.f0, ctx->stream));
+    if (ctx->g.species == GSIS_DIATOMIC)
+        HIPCHK(ctx, launch_from_canonical(ctx->g, ctx->d, ctx->fp32, f1_device, ctx->d.f1, ctx->stream));
+    if ((st = reduce_vdf(ctx))) return st;
+    HIPCHK(ctx, launch_snapshot(ctx->g, ctx->d, ctx->stream));
+    ctx->pending = false;
+    ctx->inited = true;
+    ctx->stepped = false;
+    ctx->passes = 0;
+    ctx->have_first = false;
+    return GSIS_OK;
+}
+
+gsis_status gsis_state_size(const gsis_ctx *ctx, size_t *bytes)
+{
+    if (!ctx || !bytes) return GSIS_EINVAL;
+    if (!ctx->bound) return fail(const_cast<gsis_ctx *>(ctx), GSIS_ESTATE, "bind_workspace first");
+    std::vector<StatePart> parts;
+    state_parts(ctx, parts);
+    size_t off = align256(sizeof(StateHeader));
+    for (auto &p : parts) off = align256(off + p.bytes);
+    *bytes = off;
+    return GSIS_OK;
+}
+
+gsis_status gsis_get_state(gsis_ctx *ctx, void *dst_device)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (!ctx->inited) return fail(ctx, GSIS_ESTATE, "initialise the VDF first");
+    if (!dst_device) return fail(ctx, GSIS_EINVAL, "NULL destination");
+    StateHeader h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, "GSISSTA", 8);
+    h.version = 1;
+    h.ncell = ctx->g.ncell;
+    h.nv = ctx->g.nv;
+    h.fp32 = ctx->fp32;
+    h.species = ctx->g.species;
+    h.pending = ctx->pending;
+    h.stepped = ctx->stepped;
+    h.have_first = ctx->have_first;
+    h.passes = ctx->passes;
+    for (int k = 0; k < 3; ++k) h.first_eps[k] = ctx->first_eps[k];
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(dst_device, &h, sizeof h, hipMemcpyHostToDevice));
+    std::vector<StatePart> parts;
+    state_parts(ctx, parts);
+    size_t off = align256(sizeof(StateHeader));
+    for (auto &p : parts) {
+        HIPCHK(ctx, hipMemcpyAsync((char *)dst_device + off, p.ptr, p.bytes, hipMemcpyDeviceToDevice, ctx->stream));
+        off = align256(off + p.bytes);
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return GSIS_OK;
+}
+
+gsis_status gsis_set_state(gsis_ctx *ctx, const void *src_device)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (!ctx->bound) return fail(ctx, GSIS_ESTATE, "bind_workspace first");
+    if (!src_device) return fail(ctx, GSIS_EINVAL, "NULL source");
+    StateHeader h;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(&h, src_device, sizeof h, hipMemcpyDeviceToHost));
+    if (std::memcmp(h.magic, "GSISSTA", 8) != 0 || h.version != 1 || h.ncell != ctx->g.ncell || h.nv != ctx->g.nv ||
+        h.fp32 != (int)ctx->fp32 || h.species != ctx->g.species)
+        return fail(ctx, GSIS_EINVAL, "state blob does not match this context");
+    std::vector<StatePart> parts;
+    state_parts(ctx, parts);
+    size_t off = align256(sizeof(StateHeader));
+    for (auto &p : parts) {
+        HIPCHK(ctx, hipMemcpyAsync(p.ptr, (const char *)src_device + off, p.bytes, hipMemcpyDeviceToDevice, ctx->stream));
+        off = align256(off + p.bytes);
+    }
+    gsis_status st = reset_flags(ctx);
+    if (st) return st;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->pending = h.pending != 0;
+    ctx->stepped = h.stepped != 0;
+    ctx->have_first = h.have_first != 0;
+    ctx->passes = h.passes;
+    for (int k = 0; k < 3; ++k) ctx->first_eps[k] = h.first_eps[k];
+    ctx->inited = true;
+    return GSIS_OK;
+}
+
+gsis_status gsis_set_tile(gsis_ctx *ctx, int tx, int ty, int tz, int block)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (tx == 0 && ty == 0 && tz == 0 && block == 0) {
+        default_tile(ctx);
+    } else {
+        if (!sweep_shape_supported(ctx->fp32, tx, ty)) return fail(ctx, GSIS_EINVAL, "tile (tx, ty) not compiled");
+        if (tz < 1 || tz > 1024) return fail(ctx, GSIS_EINVAL, "tz must be 1..1024");
+        if (block < 64 || block > 256 || block % 64) return fail(ctx, GSIS_EINVAL, "block must be 64, 128, 192 or 256");
+        if (sweep_lds(ctx, tx, ty, block) > 65536) return fail(ctx, GSIS_EINVAL, "tile plane exceeds 64 KiB of LDS");
+        int ntx = (ctx->g.nx + tx - 1) / tx, nty = (ctx->g.ny + ty - 1) / ty, ntz = (ctx->g.nz + tz - 1) / tz;
+        if (ntx > 1023 || nty > 1023 || ntz > 1023) return fail(ctx, GSIS_EINVAL, "too many tiles per axis");
+        ctx->tx = tx; ctx->ty = ty; ctx->tz = tz; ctx->bs = block;
+    }
+    if (ctx->meta_ready) build_tiles(ctx);
+    if (ctx->bound) {
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        HIPCHK(ctx, hipMemcpy(ctx->d.tiles, ctx->tiles.data(), ctx->tiles.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    return GSIS_OK;
+}
+
+gsis_status gsis_tile_shapes(int *out, int max, int *count)
+{
+    if (!out || !count || max < 0) return GSIS_EINVAL;
+    int buf[64];
+    int n32 = sweep_shapes(true, buf, 16);
+    int n64 = sweep_shapes(false, buf + 2 * n32, 16);
+    int n = 0;
+    for (int k = 0; k < n32 + n64 && n < max; ++k) {
+        out[3 * n] = buf[2 * k];
+        out[3 * n + 1] = buf[2 * k + 1];
+        out[3 * n + 2] = k < n32 ? 32 : 64;
+        ++n;
+    }
+    *count = n;
+    return GSIS_OK;
+}
+
+gsis_status gsis_get_vdf_nodes(gsis_ctx *ctx, const int *nodes, int nnodes, double *out_device)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (!ctx->inited) return fail(ctx, GSIS_ESTATE, "initialise the VDF first");
+    if (!nodes || nnodes < 1 || nnodes > 4096 || !out_device) return fail(ctx, GSIS_EINVAL, "bad node list");
+    std::vector<int> inv(ctx->g.nv);
+    for (int k = 0; k < ctx->g.nv; ++k) inv[ctx->perm[k]] = k;
+    std::vector<int> internal(nnodes);
+    for (int k = 0; k < nnodes; ++k) {
+        if (nodes[k] < 0 || nodes[k] >= ctx->g.nv) return fail(ctx, GSIS_EINVAL, "node index out of range");
+        internal[k] = inv[nodes[k]];
+    }
+    gsis_status st = materialize(ctx);
+    if (st) return st;
+    for (int k = 0; k < nnodes; ++k)
+        HIPCHK(ctx, launch_vdf_node(ctx->g, ctx->d, ctx->fp32, internal[k], out_device + (size_t)k * ctx->g.ncell,
+                                    ctx->stream));
+    return GSIS_OK;
+}
+
+gsis_status gsis_profile_enable(gsis_ctx *ctx, int enable)
+{
+    if (!ctx) return GSIS_EINVAL;
+    ctx->prof = enable != 0;
+    return GSIS_OK;
+}
+
+gsis_status gsis_profile_read(gsis_ctx *ctx, double *ms, long long *calls, int reset)
+{
+    if (!ctx || !ms || !calls) return GSIS_EINVAL;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto &e : ctx->ev_open) {
+        float t = 0.0f;
+        HIPCHK(ctx, hipEventElapsedTime(&t, e.second.first, e.second.second));
+        ctx->prof_ms[e.first] += t;
+        ctx->prof_calls[e.first] += 1;
+        ctx->ev_pool.push_back(e.second.first);
+        ctx->ev_pool.push_back(e.second.second);
+    }
+    ctx->ev_open.clear();
+    for (int k = 0; k < GSIS_NPHASE; ++k) {
+        ms[k] = ctx->prof_ms[k];
+        calls[k] = ctx->prof_calls[k];
+        if (reset) { ctx->prof_ms[k] = 0.0; ctx->prof_calls[k] = 0; }
+    }
+    return GSIS_OK;
+}
+
+gsis_status gsis_pass_count(const gsis_ctx *ctx, long long *passes)
+{
+    if (!ctx || !passes) return GSIS_EINVAL;
+    *passes = ctx->passes;
+    return GSIS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,336 @@
+// GSIS-II macroscopic synthetic solve (Sec. 3.3), plain point-Jacobi
+// iteration on the GPU.  Not an optimisation target: per-cell kernels.
+//
+// Unknowns per fluid cell W = (rho, rho u, E, Er) with E = rho |u|^2 + 1.5 rho Tt + Er,
+// Er = (dr/2) rho Tr (monatomic: Er = 0) -- the moments 1, xi, |xi|^2 (+ 1 on
+// f1) of the kinetic equation, so the face fluxes are mass rho u_n; momentum
+// rho u u_n + (p n + sigma.n)/2; energy (E + p) u_n + (sigma.n).u + q.n + qr.n;
+// Er u_n + qr.n, p = rho Tt.
+// Stress and heat flux follow Eq. (full_constitutive): the NSF laws of
+// Eq. (NSF_constitutive) at the iterate plus the high-order terms frozen at
+// each face, HoT = (K_i + K_j)/2 - NSF_face(W^{n+1/2}).  In these units
+// sigma_NSF = -(Tt^omega/delta)(grad u + grad u^T - (2/3) div u I),
+// q_NSF = -(k_t Tt^omega/delta) grad Tt, qr_NSF = -(k_r Tt^omega/delta) grad Tr,
+// [k_t; k_r] = A^{-1}[5; dr]/4 (Eq. mu_kappa), k_t = 15/8 for Pr = 2/3.
+// Face gradients: normal difference, tangential = mean of the cells' central
+// (one-sided at non-fluid neighbours) gradients.  Convective flux: Rusanov.
+// Boundary faces: F_kin + F_eq(W^m) - F_eq(W^{n+1/2}) -- the kinetic flux of
+// f^{n+1/2} keeps its non-equilibrium part while the equilibrium part
+// follows the iterate.  Pseudo time: the diagonal of Eq. (res_macro),
+// D_i = 1/dtau_i + (1/2) sum_faces Gamma / h, Gamma = s + C_d Tt^omega/(delta rho h),
+// with one global step D* = max_i D_i per iteration so the update is exactly
+// conservative, and the rotational relaxation 1/(Z tau) on the Er row.
+#include "gsis_common.h"
+#include "gsis_launch.h"
+
+namespace gsis {
+
+constexpr int NP = 8;   // prims per cell: rho, ux, uy, uz, Tt, Tr, E, Er
+
+__device__ __forceinline__ void prim_from_W(const Geo &g, const double *W, double *P)
+{
+    double rho = W[0];
+    double u0 = W[1] / rho, u1 = W[2] / rho, u2 = W[3] / rho;
+    double E = W[4];
+    double Er = g.species == 1 ? W[5] : 0.0;
+    double uu = u0 * u0 + u1 * u1 + u2 * u2;
+    double Tt = (2.0 / 3.0) * (E - Er - rho * uu) / rho;
+    double Tr = g.species == 1 ? 2.0 * Er / (g.dr * rho) : Tt;
+    P[0] = rho; P[1] = u0; P[2] = u1; P[3] = u2; P[4] = Tt; P[5] = Tr; P[6] = E; P[7] = Er;
+}
+
+__device__ __forceinline__ double sound(const Geo &g, const double *P) { return sqrt(g.gam * P[4] / 2.0); }
+
+__device__ void nsf_face(const Geo &g, const double *L, const double *R, const double *gL, const double *gR, int a,
+                         double h, double sigN[3], double *qN, double *qrN)
+{
+    double TF = 0.5 * (L[4] + R[4]);
+    double mu = pow(TF, g.omega) / g.delta;
+    double G[9];
+    for (int b = 0; b < 3; ++b)
+        for (int c = 0; c < 3; ++c)
+            G[b * 3 + c] = (c == a) ? (R[1 + b] - L[1 + b]) / h : 0.5 * (gL[b * 3 + c] + gR[b * 3 + c]);
+    double div = G[0] + G[4] + G[8];
+    for (int b = 0; b < 3; ++b)
+        sigN[b] = -mu * (G[b * 3 + a] + G[a * 3 + b] - (b == a ? (2.0 / 3.0) * div : 0.0));
+    *qN = -g.kt * mu * (R[4] - L[4]) / h;
+    *qrN = g.species == 1 ? -g.kr * mu * (R[5] - L[5]) / h : 0.0;
+}
+
+__device__ void face_flux(const Geo &g, const double *L, const double *R, const double *gL, const double *gR, int a,
+                          double h, const double *hot, double F[6], double *Gam)
+{
+    double sigN[3], qN, qrN;
+    nsf_face(g, L, R, gL, gR, a, h, sigN, &qN, &qrN);
+    const double *S[2] = {L, R};
+    double Phi[2][6], Wv[2][6];
+    for (int k = 0; k < 2; ++k) {
+        const double *P = S[k];
+        double rho = P[0], un = P[1 + a], p = P[0] * P[4];
+        Phi[k][0] = rho * un;
+        for (int b = 0; b < 3; ++b) Phi[k][1 + b] = rho * P[1 + b] * un + (b == a ? 0.5 * p : 0.0);
+        Phi[k][4] = (P[6] + p) * un;
+        Phi[k][5] = P[7] * un;
+        Wv[k][0] = rho;
+        for (int b = 0; b < 3; ++b) Wv[k][1 + b] = rho * P[1 + b];
+        Wv[k][4] = P[6];
+        Wv[k][5] = P[7];
+    }
+    double sL = fabs(L[1 + a]) + sound(g, L), sR = fabs(R[1 + a]) + sound(g, R);
+    double smax = sL > sR ? sL : sR;
+    for (int k = 0; k < 6; ++k) F[k] = 0.5 * (Phi[0][k] + Phi[1][k]) - 0.5 * smax * (Wv[1][k] - Wv[0][k]);
+    double sn[3], uF[3];
+    for (int b = 0; b < 3; ++b) { sn[b] = sigN[b] + hot[b]; uF[b] = 0.5 * (L[1 + b] + R[1 + b]); }
+    double qn = qN + hot[3];
+    double qrn = g.species == 1 ? qrN + hot[4] : 0.0;
+    for (int b = 0; b < 3; ++b) F[1 + b] += 0.5 * sn[b];
+    F[4] += sn[0] * uF[0] + sn[1] * uF[1] + sn[2] * uF[2] + qn + qrn;
+    F[5] += qrn;
+    double TF = 0.5 * (L[4] + R[4]), rF = 0.5 * (L[0] + R[0]);
+    *Gam = smax + g.Cd * pow(TF, g.omega) / (g.delta * rF * h);
+}
+
+// Outgoing half-range psi-moments of M(rho, u, Tt) through face dir (sum over
+// nodes with xi.n > 0 of w (xi.n) psi M), separable on the tensor grid, and
+// the face flux of the equilibrium state with the face's boundary rule.
+__device__ void equilibrium_face_flux(const Geo &g, const BcInfo &bc, const Dev &d, const double *P, int dir, int b,
+                                      double F[6])
+{
+    int a = dir / 2;
+    double sg = (dir & 1) ? 1.0 : -1.0;
+    double T = P[4];
+    double H[4] = {0, 0, 0, 0};   // half sums along a, powers 0..3
+    double Fo[3][3];              // full sums along the other axes, powers 0..2
+    for (int ax = 0; ax < 3; ++ax) {
+        const double *xi = d.xi64[ax], *w = d.w64[ax];
+        double u = P[1 + ax];
+        if (ax == a) {
+            for (int k = 0; k < g.n1[ax]; ++k) {
+                double x = xi[k];
+                if (!(sg * x > 0.0)) continue;
+                double c = x - u;
+                double e = w[k] * exp(-c * c / T);
+                H[1] += e * x;
+                H[2] += e * x * x;
+                H[3] += e * x * x * x;
+            }
+        } else {
+            double s0 = 0, s1 = 0, s2 = 0;
+            for (int k = 0; k < g.n1[ax]; ++k) {
+                double x = xi[k], c = x - u;
+                double e = w[k] * exp(-c * c / T);
+                s0 += e;
+                s1 += e * x;
+                s2 += e * x * x;
+            }
+            Fo[ax][0] = s0; Fo[ax][1] = s1; Fo[ax][2] = s2;
+        }
+    }
+    int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+    double K = P[0] * pow(PI * T, -1.5) * sg;
+    double out[6];
+    out[0] = K * H[1] * Fo[b1][0] * Fo[b2][0];
+    out[1 + a] = K * H[2] * Fo[b1][0] * Fo[b2][0];
+    out[1 + b1] = K * H[1] * Fo[b1][1] * Fo[b2][0];
+    out[1 + b2] = K * H[1] * Fo[b1][0] * Fo[b2][1];
+    double h1 = g.species == 1 ? 0.5 * g.dr * P[5] : 0.0;
+    out[4] = K * (H[3] * Fo[b1][0] * Fo[b2][0] + H[1] * Fo[b1][2] * Fo[b2][0] + H[1] * Fo[b1][0] * Fo[b2][2])
+             + h1 * out[0];
+    out[5] = h1 * out[0];
+    const double *in = d.inpsi + (b * 6 + dir) * 6;
+    double sc = bc.kind[b] == 1 ? bc.rho[b] : out[0] / (-in[0]);
+    for (int k = 0; k < 6; ++k) F[k] = out[k] + sc * in[k];
+}
+
+// W^{n+1/2}, kinetic stress/heat flux, the old half of the correction record.
+__global__ void k_mac_init(Geo g, Dev d)
+{
+    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell || !d.cflag[cell]) return;
+    const double *m = d.cm + (size_t)cell * NMOM;
+    double rho = m[0], Tt = m[4];
+    double uu = m[1] * m[1] + m[2] * m[2] + m[3] * m[3];
+    double Er = g.species == 1 ? 0.5 * g.dr * rho * m[14] : 0.0;
+    double *W = d.W + (size_t)cell * 6;
+    W[0] = rho;
+    W[1] = rho * m[1]; W[2] = rho * m[2]; W[3] = rho * m[3];
+    W[4] = rho * uu + 1.5 * rho * Tt + Er;
+    W[5] = Er;
+    double *K = d.K + (size_t)cell * 12;
+    for (int k = 0; k < 6; ++k) K[k] = m[5 + k];
+    for (int k = 0; k < 3; ++k) K[6 + k] = m[11 + k];
+    for (int k = 0; k < 3; ++k) K[9 + k] = g.species == 1 ? m[15 + k] : 0.0;
+    double *c = d.corr + (size_t)cell * NCORR;
+    c[6] = rho; c[7] = m[1]; c[8] = m[2]; c[9] = m[3]; c[10] = Tt;
+    c[11] = g.species == 1 ? m[14] : Tt;
+    prim_from_W(g, W, d.P + (size_t)cell * NP);
+}
+
+__global__ void k_mac_grad(Geo g, Dev d)
+{
+    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell || !d.cflag[cell]) return;
+    const int *nb = d.nbr + (size_t)cell * 6;
+    const double *Pc = d.P + (size_t)cell * NP;
+    double *G = d.grad + (size_t)cell * 9;
+    for (int c = 0; c < 3; ++c) {
+        int nm = nb[2 * c], np = nb[2 * c + 1];
+        double h = g.h[c];
+        for (int b = 0; b < 3; ++b) {
+            double v;
+            if (nm >= 0 && np >= 0) v = (d.P[(size_t)np * NP + 1 + b] - d.P[(size_t)nm * NP + 1 + b]) / (2.0 * h);
+            else if (np >= 0) v = (d.P[(size_t)np * NP + 1 + b] - Pc[1 + b]) / h;
+            else if (nm >= 0) v = (Pc[1 + b] - d.P[(size_t)nm * NP + 1 + b]) / h;
+            else v = 0.0;
+            G[b * 3 + c] = v;
+        }
+    }
+}
+
+// HoT at the faces (cell, cell + e_a) from W^{n+1/2}.
+__global__ void k_mac_hot(Geo g, Dev d)
+{
+    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell || !d.cflag[cell]) return;
+    const int col[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    for (int a = 0; a < 3; ++a) {
+        int nb = d.nbr[(size_t)cell * 6 + 2 * a + 1];
+        double *ho = d.hot + (size_t)cell * 15 + a * 5;
+        if (nb < 0) {
+            for (int k = 0; k < 5; ++k) ho[k] = 0.0;
+            continue;
+        }
+        double sigN[3], qN, qrN;
+        nsf_face(g, d.P + (size_t)cell * NP, d.P + (size_t)nb * NP, d.grad + (size_t)cell * 9,
+                 d.grad + (size_t)nb * 9, a, g.h[a], sigN, &qN, &qrN);
+        const double *Ki = d.K + (size_t)cell * 12, *Kj = d.K + (size_t)nb * 12;
+        for (int b = 0; b < 3; ++b) ho[b] = 0.5 * (Ki[col[a][b]] + Kj[col[a][b]]) - sigN[b];
+        ho[3] = 0.5 * (Ki[6 + a] + Kj[6 + a]) - qN;
+        ho[4] = g.species == 1 ? 0.5 * (Ki[9 + a] + Kj[9 + a]) - qrN : 0.0;
+    }
+}
+
+// Fixed part of each boundary face flux: F_kin(f^{n+1/2}) - F_eq(W^{n+1/2}).
+__global__ void k_mac_fbfix(Geo g, BcInfo bc, Dev d)
+{
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= g.nface) return;
+    int cell = d.face_cell[f], dir = d.face_dir[f], b = d.face_bc[f];
+    int a = dir / 2;
+    int neg = (dir & 1) ? 0 : 1;
+    double sg = neg ? -1.0 : 1.0;
+    double out[6] = {0, 0, 0, 0, 0, 0};
+    for (int o = 0; o < 8; ++o) {
+        if (((o >> a) & 1) != neg) continue;
+        const double *m = d.mom8 + ((size_t)cell * 8 + o) * NRS;
+        const int m2row[3][3] = {{4, 7, 8}, {7, 5, 9}, {8, 9, 6}};
+        out[0] += m[1 + a];
+        for (int c = 0; c < 3; ++c) out[1 + c] += m[m2row[a][c]];
+        out[4] += m[10 + a] + m[14 + a];
+        out[5] += m[14 + a];
+    }
+    for (int k = 0; k < 6; ++k) out[k] *= sg;
+    const double *in = d.inpsi + (b * 6 + dir) * 6;
+    double sc = bc.kind[b] == 1 ? bc.rho[b] : out[0] / (-in[0]);
+    double Fe[6];
+    equilibrium_face_flux(g, bc, d, d.P + (size_t)d.face_cell[f] * NP, dir, b, Fe);
+    for (int k = 0; k < 6; ++k) d.fbfix[(size_t)f * 6 + k] = out[k] + sc * in[k] - Fe[k];
+}
+
+// Residual and diagonal of every cell; D* = max D_i by an atomic max on the
+// bit pattern (positive doubles order like their bits), so it is exact and
+// order independent.
+__global__ void k_mac_res(Geo g, BcInfo bc, Dev d, int slot)
+{
+    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell || !d.cflag[cell]) return;
+    const double *Pi = d.P + (size_t)cell * NP;
+    const int *nb = d.nbr + (size_t)cell * 6;
+    double res[6] = {0, 0, 0, 0, 0, 0}, sumG = 0.0;
+    double csi = sound(g, Pi);
+    for (int dir = 0; dir < 6; ++dir) {
+        int a = dir / 2;
+        double h = g.h[a];
+        int n = nb[dir];
+        double F[6], out[6], Gam;
+        if (n >= 0) {
+            int L = (dir & 1) ? cell : n, R = (dir & 1) ? n : cell;
+            face_flux(g, d.P + (size_t)L * NP, d.P + (size_t)R * NP, d.grad + (size_t)L * 9, d.grad + (size_t)R * 9, a,
+                      h, d.hot + (size_t)L * 15 + a * 5, F, &Gam);
+            for (int k = 0; k < 6; ++k) out[k] = (dir & 1) ? F[k] : -F[k];
+        } else {
+            int f = -n - 1;
+            double Fe[6];
+            equilibrium_face_flux(g, bc, d, Pi, dir, d.face_bc[f], Fe);
+            for (int k = 0; k < 6; ++k) out[k] = d.fbfix[(size_t)f * 6 + k] + Fe[k];
+            Gam = fabs(Pi[1 + a]) + csi + g.Cd * pow(Pi[4], g.omega) / (g.delta * Pi[0] * h);
+        }
+        int nw = g.species == 1 ? 6 : 5;
+        for (int k = 0; k < nw; ++k) res[k] -= out[k] / h;
+        sumG += Gam / h;
+    }
+    double invtau = g.delta * Pi[0] * pow(Pi[4], 1.0 - g.omega);
+    if (g.species == 1) {
+        double T = (3.0 * Pi[4] + g.dr * Pi[5]) / (3.0 + g.dr);
+        res[5] += 0.5 * g.dr * Pi[0] * (T - Pi[5]) * invtau / g.Zr;
+    }
+    double umag = sqrt(Pi[1] * Pi[1] + Pi[2] * Pi[2] + Pi[3] * Pi[3]);
+    double idt = (umag + csi + g.Cd * pow(Pi[4], g.omega) / (g.delta * Pi[0] * g.hmin)) / (g.macro_cfl * g.hmin);
+    double D = idt + 0.5 * sumG;
+    double *r = d.R + (size_t)cell * 6;
+    for (int k = 0; k < 6; ++k) r[k] = res[k];
+    d.Dc[cell] = D;
+    d.Src[cell] = g.species == 1 ? invtau / g.Zr : 0.0;
+    if (D > 0.0 && isfinite(D)) atomicMax(&d.dmax[slot], (unsigned long long)__double_as_longlong(D));
+    else atomicOr(d.errflag, 2);
+}
+
+__global__ void k_mac_update(Geo g, Dev d, int slot)
+{
+    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell == 0) d.dmax[slot ^ 1] = 0ull;   // the other slot was last used by the previous iteration
+    if (cell >= g.ncell || !d.cflag[cell]) return;
+    double Dm = __longlong_as_double((long long)d.dmax[slot]);
+    double *W = d.W + (size_t)cell * 6;
+    const double *r = d.R + (size_t)cell * 6;
+    for (int k = 0; k < 5; ++k) W[k] += r[k] / Dm;
+    if (g.species == 1) W[5] += r[5] / (Dm + d.Src[cell]);
+    prim_from_W(g, W, d.P + (size_t)cell * NP);
+}
+
+__global__ void k_mac_reset(Dev d)
+{
+    if (threadIdx.x < 2) d.dmax[threadIdx.x] = 0ull;
+}
+
+// New half of the correction record; flags non-physical states.
+__global__ void k_mac_final(Geo g, Dev d)
+{
+    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell || !d.cflag[cell]) return;
+    const double *P = d.P + (size_t)cell * NP;
+    double *c = d.corr + (size_t)cell * NCORR;
+    c[0] = P[0]; c[1] = P[1]; c[2] = P[2]; c[3] = P[3]; c[4] = P[4];
+    c[5] = g.species == 1 ? P[5] : P[4];
+    if (!(P[0] > 0.0) || !(P[4] > 0.0) || !isfinite(P[6]) || (g.species == 1 && !(P[5] > 0.0))) atomicOr(d.errflag, 4);
+}
+
+hipError_t launch_gsis_macro(const Geo &g, const BcInfo &bc, const Dev &d, int iters, hipStream_t s)
+{
+    dim3 blk(128), grd((g.ncell + 127) / 128);
+    hipLaunchKernelGGL(k_mac_reset, dim3(1), dim3(64), 0, s, d);
+    hipLaunchKernelGGL(k_mac_init, grd, blk, 0, s, g, d);
+    hipLaunchKernelGGL(k_mac_grad, grd, blk, 0, s, g, d);
+    hipLaunchKernelGGL(k_mac_hot, grd, blk, 0, s, g, d);
+    if (g.nface > 0) hipLaunchKernelGGL(k_mac_fbfix, dim3((g.nface + 127) / 128), blk, 0, s, g, bc, d);
+    for (int it = 0; it < iters; ++it) {
+        int slot = it & 1;
+        if (it > 0) hipLaunchKernelGGL(k_mac_grad, grd, blk, 0, s, g, d);
+        hipLaunchKernelGGL(k_mac_res, grd, blk, 0, s, g, bc, d, slot);
+        hipLaunchKernelGGL(k_mac_update, grd, blk, 0, s, g, d, slot);
+    }
+    hipLaunchKernelGGL(k_mac_final, grd, blk, 0, s, g, d);
+    return hipGetLastError();
+}
+
+}  // namespace gsis

@@ -1,0 +1,278 @@
+// Moment reduction of Eq. (getmoment).
+//
+// k_moments: raw moments of every (cell, velocity octant) about the origin,
+// accumulated in FP64 whatever the VDF precision.  The tensor grid makes the
+// contraction separable: each lane walks rows of x-nodes (contiguous in the
+// octant-grouped layout), forms the four row sums sum_x w_x xi_x^p f
+// (p = 0..3), and folds them with the row's y/z weights into the 13 (+4 for
+// f1) monomials.  One block per cell, one wave per octant, so per-octant
+// sums -- from which every half-range wall flux follows -- need only a wave
+// reduction.  The x-weights are wave-uniform (scalar loads).
+//
+// k_derive: central moments (rho, u, Tt, sigma, q, Tr, qr) of every cell from
+// the octant sums.
+//
+// k_commit_correction: adds to the octant sums the discrete raw moments of
+// M(W') - M(W) of Eq. (updatef), which factor into 1-D sums on the tensor grid,
+// so the corrected state's moments are exact without touching the VDF.
+#include "gsis_common.h"
+#include "gsis_launch.h"
+
+namespace gsis {
+
+template <typename T, int VW> struct VecLoad;
+template <> struct VecLoad<float, 1> { static __device__ void ld(const float *p, double *o) { o[0] = p[0]; } };
+template <> struct VecLoad<float, 2> {
+    static __device__ void ld(const float *p, double *o) { float2 v = *(const float2 *)p; o[0] = v.x; o[1] = v.y; }
+};
+template <> struct VecLoad<float, 4> {
+    static __device__ void ld(const float *p, double *o)
+    {
+        float4 v = *(const float4 *)p;
+        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+    }
+};
+template <> struct VecLoad<double, 1> { static __device__ void ld(const double *p, double *o) { o[0] = p[0]; } };
+template <> struct VecLoad<double, 2> {
+    static __device__ void ld(const double *p, double *o) { double2 v = *(const double2 *)p; o[0] = v.x; o[1] = v.y; }
+};
+
+template <typename T, int VW, bool DIA>
+__global__ __launch_bounds__(512) void k_moments(Geo g, const T *__restrict__ f0, const T *__restrict__ f1,
+                                                 const int *__restrict__ cflag, const double *__restrict__ xtab,
+                                                 const double *__restrict__ ytab, const double *__restrict__ ztab,
+                                                 double *__restrict__ mom8)
+{
+    const int cell = blockIdx.x;
+    const int o = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    double *out = mom8 + ((size_t)cell * 8 + o) * NRS;
+    if (!cflag[cell]) {
+        if (lane < NRS) out[lane] = 0.0;
+        return;
+    }
+    const int nox = g.on[o][0], noy = g.on[o][1], noz = g.on[o][2];
+    const int x0 = (o & 1) ? 0 : g.k0[0];
+    const int y0 = (o & 2) ? 0 : g.k0[1];
+    const int z0 = (o & 4) ? 0 : g.k0[2];
+    const size_t base = (size_t)cell * g.nv + g.obase[o];
+    const int nrow = noy * noz;
+    double acc[13];
+#pragma unroll
+    for (int k = 0; k < 13; ++k) acc[k] = 0.0;
+    double acc1[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = lane; r < nrow; r += 64) {
+        const int ly = r % noy, lz = r / noy;
+        const T *row0 = f0 + base + (size_t)r * nox;
+        const T *row1 = DIA ? f1 + base + (size_t)r * nox : nullptr;
+        double s0 = 0, s1 = 0, s2 = 0, s3 = 0, t0 = 0, t1 = 0;
+        for (int lx = 0; lx < nox; lx += VW) {
+            double v[VW], v1[VW];
+            VecLoad<T, VW>::ld(row0 + lx, v);
+            if (DIA) VecLoad<T, VW>::ld(row1 + lx, v1);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                const double *xt = xtab + (size_t)(x0 + lx + e) * 4;
+                s0 += xt[0] * v[e];
+                s1 += xt[1] * v[e];
+                s2 += xt[2] * v[e];
+                s3 += xt[3] * v[e];
+                if (DIA) {
+                    t0 += xt[0] * v1[e];
+                    t1 += xt[1] * v1[e];
+                }
+            }
+        }
+        const double wy = ytab[2 * (y0 + ly)], y = ytab[2 * (y0 + ly) + 1];
+        const double wz = ztab[2 * (z0 + lz)], z = ztab[2 * (z0 + lz) + 1];
+        const double W0 = wy * wz;
+        const double Y1 = W0 * y, Z1 = W0 * z;
+        const double Y2 = Y1 * y, Z2 = Z1 * z, YZ = Y1 * z;
+        const double Y3 = Y2 * y, Z3 = Z2 * z, YZ2 = YZ * z, Y2Z = Y2 * z;
+        acc[0] += W0 * s0;
+        acc[1] += W0 * s1;
+        acc[2] += Y1 * s0;
+        acc[3] += Z1 * s0;
+        acc[4] += W0 * s2;
+        acc[5] += Y2 * s0;
+        acc[6] += Z2 * s0;
+        acc[7] += Y1 * s1;
+        acc[8] += Z1 * s1;
+        acc[9] += YZ * s0;
+        acc[10] += W0 * s3 + (Y2 + Z2) * s1;   // x |xi|^2 = x^3 + x y^2 + x z^2
+        acc[11] += Y1 * s2 + (Y3 + YZ2) * s0;  // y |xi|^2 = x^2 y + y^3 + y z^2
+        acc[12] += Z1 * s2 + (Y2Z + Z3) * s0;  // z |xi|^2 = x^2 z + y^2 z + z^3
+        if (DIA) {
+            acc1[0] += W0 * t0;
+            acc1[1] += W0 * t1;
+            acc1[2] += Y1 * t0;
+            acc1[3] += Z1 * t0;
+        }
+    }
+    double res[NRS];
+#pragma unroll
+    for (int k = 0; k < 13; ++k) res[k] = wave_sum(acc[k]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) res[13 + k] = DIA ? wave_sum(acc1[k]) : 0.0;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NRS; ++k) out[k] = res[k];
+    }
+}
+
+// Central moments from the octant sums (octants added in a fixed order).
+__global__ void k_derive(Geo g, Dev d)
+{
+    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell) return;
+    double *out = d.cm + (size_t)cell * NMOM;
+    if (!d.cflag[cell]) {
+        for (int k = 0; k < NMOM; ++k) out[k] = __builtin_nan("");
+        return;
+    }
+    double m[NRS];
+    for (int k = 0; k < NRS; ++k) m[k] = 0.0;
+    for (int o = 0; o < 8; ++o) {
+        const double *mo = d.mom8 + ((size_t)cell * 8 + o) * NRS;
+        for (int k = 0; k < NRS; ++k) m[k] += mo[k];
+    }
+    double rho = m[0];
+    double u[3] = {m[1] / rho, m[2] / rho, m[3] / rho};
+    // second raw moments as a matrix
+    double M2[3][3] = {{m[4], m[7], m[8]}, {m[7], m[5], m[9]}, {m[8], m[9], m[6]}};
+    double S[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) S[a][b] = M2[a][b] - rho * u[a] * u[b];
+    double tr = S[0][0] + S[1][1] + S[2][2];
+    double Tt = (2.0 / 3.0) * tr / rho;
+    double tr2 = M2[0][0] + M2[1][1] + M2[2][2];
+    double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    out[0] = rho;
+    out[1] = u[0];
+    out[2] = u[1];
+    out[3] = u[2];
+    out[4] = Tt;
+    out[5] = 2.0 * (S[0][0] - tr / 3.0);
+    out[6] = 2.0 * (S[1][1] - tr / 3.0);
+    out[7] = 2.0 * (S[2][2] - tr / 3.0);
+    out[8] = 2.0 * S[0][1];
+    out[9] = 2.0 * S[0][2];
+    out[10] = 2.0 * S[1][2];
+    // q_a = sum c_a |c|^2 f = m3_a - 2 (M2 u)_a - u_a tr(M2) + 2 rho u_a |u|^2
+    for (int a = 0; a < 3; ++a) {
+        double m2u = M2[a][0] * u[0] + M2[a][1] * u[1] + M2[a][2] * u[2];
+        out[11 + a] = m[10 + a] - 2.0 * m2u - u[a] * tr2 + 2.0 * rho * u[a] * u2;
+    }
+    if (g.species == 1) {
+        double e1 = m[13];
+        out[14] = 2.0 * e1 / (g.dr * rho);
+        for (int a = 0; a < 3; ++a) out[15 + a] = m[14 + a] - u[a] * e1;
+    } else {
+        out[14] = out[15] = out[16] = out[17] = 0.0;
+    }
+    if (!(rho > 0.0) || !(Tt > 0.0)) atomicOr(d.errflag, 1);
+}
+
+// 1-D sums over the negative (h = 0) and positive (h = 1) halves of one axis:
+// R[h][p] = sum_k w_k xi_k^p exp(-(xi_k - u)^2 / T), p = 0..3.
+__device__ void half_sums(const double *xi, const double *w, int n, int k0, double u, double T, double R[2][4])
+{
+    for (int h = 0; h < 2; ++h)
+        for (int p = 0; p < 4; ++p) R[h][p] = 0.0;
+    for (int k = 0; k < n; ++k) {
+        double x = xi[k], c = x - u;
+        double e = w[k] * exp(-c * c / T);
+        int h = k >= k0;
+        R[h][0] += e;
+        R[h][1] += e * x;
+        R[h][2] += e * x * x;
+        R[h][3] += e * x * x * x;
+    }
+}
+
+// Raw octant moments (13 on f0, 4 on f1) of K * prod_a exp(-(xi_a-u_a)^2/T) given the
+// half sums of each axis; f1 gets the factor h1.
+__device__ void octant_monomials(const double X[4], const double Y[4], const double Z[4], double K, double h1,
+                                 double *m)
+{
+    m[0] = K * X[0] * Y[0] * Z[0];
+    m[1] = K * X[1] * Y[0] * Z[0];
+    m[2] = K * X[0] * Y[1] * Z[0];
+    m[3] = K * X[0] * Y[0] * Z[1];
+    m[4] = K * X[2] * Y[0] * Z[0];
+    m[5] = K * X[0] * Y[2] * Z[0];
+    m[6] = K * X[0] * Y[0] * Z[2];
+    m[7] = K * X[1] * Y[1] * Z[0];
+    m[8] = K * X[1] * Y[0] * Z[1];
+    m[9] = K * X[0] * Y[1] * Z[1];
+    m[10] = K * (X[3] * Y[0] * Z[0] + X[1] * Y[2] * Z[0] + X[1] * Y[0] * Z[2]);
+    m[11] = K * (X[2] * Y[1] * Z[0] + X[0] * Y[3] * Z[0] + X[0] * Y[1] * Z[2]);
+    m[12] = K * (X[2] * Y[0] * Z[1] + X[0] * Y[2] * Z[1] + X[0] * Y[0] * Z[3]);
+    m[13] = h1 * m[0];
+    m[14] = h1 * m[1];
+    m[15] = h1 * m[2];
+    m[16] = h1 * m[3];
+}
+
+// Octant sums += moments of M(W') - M(W) (and (dr/2)[Tr' M(W') - Tr M(W)] on f1).
+__global__ void k_commit_correction(Geo g, Dev d)
+{
+    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell || !d.cflag[cell]) return;
+    const double *c = d.corr + (size_t)cell * NCORR;
+    double Rn[3][2][4], Ro[3][2][4];
+    for (int a = 0; a < 3; ++a) {
+        half_sums(d.xi64[a], d.w64[a], g.n1[a], g.k0[a], c[1 + a], c[4], Rn[a]);
+        half_sums(d.xi64[a], d.w64[a], g.n1[a], g.k0[a], c[7 + a], c[10], Ro[a]);
+    }
+    double Kn = c[0] * pow(PI * c[4], -1.5), Ko = c[6] * pow(PI * c[10], -1.5);
+    double hn = g.species == 1 ? 0.5 * g.dr * c[5] : 0.0;
+    double ho = g.species == 1 ? 0.5 * g.dr * c[11] : 0.0;
+    for (int o = 0; o < 8; ++o) {
+        int hx = (o & 1) ? 0 : 1, hy = (o & 2) ? 0 : 1, hz = (o & 4) ? 0 : 1;
+        double mn[NRS], mo[NRS];
+        octant_monomials(Rn[0][hx], Rn[1][hy], Rn[2][hz], Kn, hn, mn);
+        octant_monomials(Ro[0][hx], Ro[1][hy], Ro[2][hz], Ko, ho, mo);
+        double *dst = d.mom8 + ((size_t)cell * 8 + o) * NRS;
+        for (int k = 0; k < NRS; ++k) dst[k] += mn[k] - mo[k];
+    }
+}
+
+// ------------------------------------------------------------------ launches
+template <typename T, int VW>
+static void moments_vw(const Geo &g, const Dev &d, hipStream_t s)
+{
+    if (g.species == 1)
+        hipLaunchKernelGGL((k_moments<T, VW, true>), dim3(g.ncell), dim3(512), 0, s, g, (const T *)d.f0,
+                           (const T *)d.f1, d.cflag, d.xtab, d.ytab, d.ztab, d.mom8);
+    else
+        hipLaunchKernelGGL((k_moments<T, VW, false>), dim3(g.ncell), dim3(512), 0, s, g, (const T *)d.f0,
+                           (const T *)nullptr, d.cflag, d.xtab, d.ytab, d.ztab, d.mom8);
+}
+
+hipError_t launch_moments(const Geo &g, const Dev &d, bool fp32, int vw, hipStream_t s)
+{
+    if (fp32) {
+        if (vw == 4) moments_vw<float, 4>(g, d, s);
+        else if (vw == 2) moments_vw<float, 2>(g, d, s);
+        else moments_vw<float, 1>(g, d, s);
+    } else {
+        if (vw >= 2) moments_vw<double, 2>(g, d, s);
+        else moments_vw<double, 1>(g, d, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_derive(const Geo &g, const Dev &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_derive, dim3((g.ncell + 255) / 256), dim3(256), 0, s, g, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_commit_correction(const Geo &g, const Dev &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_commit_correction, dim3((g.ncell + 127) / 128), dim3(128), 0, s, g, d);
+    return hipGetLastError();
+}
+
+}  // namespace gsis

@@ -1,0 +1,94 @@
+// Convergence criterion of Sec. 4: volume-weighted relative L2 change of
+// rho, u (as a vector) and Tt between two states; uniform cells, so the
+// weights cancel.  Two-stage fixed-order reduction (deterministic).
+#include "gsis_common.h"
+#include "gsis_launch.h"
+
+namespace gsis {
+
+__global__ __launch_bounds__(256) void k_resid_partial(Geo g, Dev d)
+{
+    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[6] = {0, 0, 0, 0, 0, 0};   // num rho, u, T; den rho, u, T
+    if (cell < g.ncell && d.cflag[cell]) {
+        const double *m = d.cm + (size_t)cell * NMOM;
+        const double *p = d.snap + (size_t)cell * NSNAP;
+        double dr = m[0] - p[0], dT = m[4] - p[4];
+        v[0] = dr * dr;
+        v[3] = p[0] * p[0];
+        for (int a = 0; a < 3; ++a) {
+            double du = m[1 + a] - p[1 + a];
+            v[1] += du * du;
+            v[4] += p[1 + a] * p[1 + a];
+        }
+        v[2] = dT * dT;
+        v[5] = p[4] * p[4];
+    }
+    __shared__ double sh[6][256];
+    for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 6; ++k) d.red[(size_t)blockIdx.x * 6 + k] = sh[k][0];
+}
+
+__global__ __launch_bounds__(256) void k_resid_final(Dev d, int nblk)
+{
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+        for (int k = 0; k < 6; ++k) v[k] += d.red[(size_t)b * 6 + k];
+    __shared__ double sh[6][256];
+    for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 6; ++k) d.red[(size_t)nblk * 6 + k] = sh[k][0];
+}
+
+__global__ void k_snapshot(Geo g, Dev d)
+{
+    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell) return;
+    const double *m = d.cm + (size_t)cell * NMOM;
+    double *p = d.snap + (size_t)cell * NSNAP;
+    bool fl = d.cflag[cell] != 0;
+    for (int k = 0; k < NSNAP; ++k) p[k] = fl ? m[k] : 0.0;
+}
+
+__global__ void k_zero_int(int *p, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+hipError_t launch_zero_int(int *p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_int, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+int resid_blocks(const Geo &g) { return (g.ncell + 255) / 256; }
+
+hipError_t launch_residual(const Geo &g, const Dev &d, hipStream_t s)
+{
+    int nb = resid_blocks(g);
+    hipLaunchKernelGGL(k_resid_partial, dim3(nb), dim3(256), 0, s, g, d);
+    hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, s, d, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_snapshot(const Geo &g, const Dev &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_snapshot, dim3((g.ncell + 255) / 256), dim3(256), 0, s, g, d);
+    return hipGetLastError();
+}
+
+}  // namespace gsis

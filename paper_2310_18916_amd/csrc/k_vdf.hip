@@ -1,0 +1,204 @@
+// VDF set-up kernels: boundary Maxwellian tables, initial Maxwellian,
+// canonical <-> internal layout, and the pointwise GSIS update (Eq. updatef).
+#include "gsis_common.h"
+#include "gsis_launch.h"
+
+namespace gsis {
+
+// M(1, u_b, T_b) at every node, per boundary slot, in the internal node order;
+// mb1 = (dr/2) T_b M is the equilibrium of the rotational VDF.
+__global__ void k_boundary_tables(Geo g, BcInfo bc, Dev d)
+{
+    int node = blockIdx.y * blockDim.x + threadIdx.x;
+    int b = blockIdx.x;
+    if (node >= g.nv) return;
+    int l, kx, ky, kz;
+    int o = octant_of(g, node, l);
+    node_of(g, o, l, kx, ky, kz);
+    double m = maxwell64(1.0, bc.u[b], bc.T[b], d.xi64[0][kx], d.xi64[1][ky], d.xi64[2][kz]);
+    double m1 = 0.5 * g.dr * bc.T[b] * m;
+    size_t at = (size_t)b * g.nv + node;
+    d.mb64[at] = m;
+    d.mb32[at] = (float)m;
+    d.mb1_64[at] = m1;
+    d.mb1_32[at] = (float)m1;
+}
+
+// Incoming half-range moments of the boundary Maxwellian for slot b and
+// face direction dir (outward normal n):  sum_{xi.n<0} w (xi.n) psi M(1,u_b,T_b),
+// psi = (1, xi_x, xi_y, xi_z, |xi|^2 + (dr/2) T_b, (dr/2) T_b).
+// One block per (b, dir); fixed-order tree reduction.
+__global__ __launch_bounds__(256) void k_incoming_moments(Geo g, BcInfo bc, Dev d)
+{
+    int b = blockIdx.x / 6, dir = blockIdx.x % 6;
+    int a = dir / 2;
+    double sg = (dir & 1) ? 1.0 : -1.0;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    double h1 = 0.5 * g.dr * bc.T[b];
+    for (int node = threadIdx.x; node < g.nv; node += blockDim.x) {
+        int l, kx, ky, kz;
+        int o = octant_of(g, node, l);
+        node_of(g, o, l, kx, ky, kz);
+        double x = d.xi64[0][kx], y = d.xi64[1][ky], z = d.xi64[2][kz];
+        double xa = a == 0 ? x : (a == 1 ? y : z);
+        double xn = sg * xa;
+        if (!(xn < 0.0)) continue;
+        double w = d.w64[0][kx] * d.w64[1][ky] * d.w64[2][kz];
+        double m = d.mb64[(size_t)b * g.nv + node];
+        double ww = w * xn * m;
+        acc[0] += ww;
+        acc[1] += ww * x;
+        acc[2] += ww * y;
+        acc[3] += ww * z;
+        acc[4] += ww * (x * x + y * y + z * z + h1);
+        acc[5] += ww * h1;
+    }
+    __shared__ double sh[6][256];
+    for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 6; ++k) d.inpsi[(b * 6 + dir) * 6 + k] = sh[k][0];
+}
+
+template <typename T>
+__global__ void k_init_maxwellian(Geo g, Dev d, double rho, double ux, double uy, double uz, double Tt, double Tr)
+{
+    int node = blockIdx.y * blockDim.x + threadIdx.x;
+    int cell = blockIdx.x;
+    if (node >= g.nv) return;
+    T *f0 = (T *)d.f0;
+    T *f1 = (T *)d.f1;
+    size_t at = (size_t)cell * g.nv + node;
+    if (!d.cflag[cell]) {
+        f0[at] = T(0);
+        if (g.species == 1) f1[at] = T(0);
+        return;
+    }
+    int l, kx, ky, kz;
+    int o = octant_of(g, node, l);
+    node_of(g, o, l, kx, ky, kz);
+    double u[3] = {ux, uy, uz};
+    double m = maxwell64(rho, u, Tt, d.xi64[0][kx], d.xi64[1][ky], d.xi64[2][kz]);
+    f0[at] = (T)m;
+    if (g.species == 1) f1[at] = (T)(0.5 * g.dr * Tr * m);
+}
+
+template <typename T>
+__global__ void k_to_canonical(Geo g, Dev d, const T *src, double *dst)
+{
+    int node = blockIdx.y * blockDim.x + threadIdx.x;
+    int cell = blockIdx.x;
+    if (node >= g.nv) return;
+    size_t row = (size_t)cell * g.nv;
+    dst[row + d.perm[node]] = (double)src[row + node];
+}
+
+template <typename T>
+__global__ void k_from_canonical(Geo g, Dev d, const double *src, T *dst)
+{
+    int node = blockIdx.y * blockDim.x + threadIdx.x;
+    int cell = blockIdx.x;
+    if (node >= g.nv) return;
+    size_t row = (size_t)cell * g.nv;
+    dst[row + node] = d.cflag[cell] ? (T)src[row + d.perm[node]] : T(0);
+}
+
+// one internal node of every cell -> out[cell] (FP64)
+template <typename T>
+__global__ void k_vdf_node(Geo g, Dev d, int node, double *out)
+{
+    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell) return;
+    out[cell] = (double)((const T *)d.f0)[(size_t)cell * g.nv + node];
+}
+
+// Eq. (updatef) pointwise: f0 += M(W') - M(W), f1 += (dr/2)[Tr' M(W') - Tr M(W)],
+// both Maxwellians with the translational temperature.
+template <typename T>
+__global__ void k_apply_correction(Geo g, Dev d)
+{
+    int node = blockIdx.y * blockDim.x + threadIdx.x;
+    int cell = blockIdx.x;
+    if (node >= g.nv || !d.cflag[cell]) return;
+    const double *c = d.corr + (size_t)cell * NCORR;
+    int l, kx, ky, kz;
+    int o = octant_of(g, node, l);
+    node_of(g, o, l, kx, ky, kz);
+    double x = d.xi64[0][kx], y = d.xi64[1][ky], z = d.xi64[2][kz];
+    double mn = maxwell64(c[0], c + 1, c[4], x, y, z);
+    double mo = maxwell64(c[6], c + 7, c[10], x, y, z);
+    size_t at = (size_t)cell * g.nv + node;
+    T *f0 = (T *)d.f0;
+    f0[at] = (T)((double)f0[at] + (mn - mo));
+    if (g.species == 1) {
+        T *f1 = (T *)d.f1;
+        f1[at] = (T)((double)f1[at] + 0.5 * g.dr * (c[5] * mn - c[11] * mo));
+    }
+}
+
+// ------------------------------------------------------------------ launches
+// blockIdx.x = row (cell or boundary slot), blockIdx.y * 256 + tid = node
+static dim3 node_grid(const Geo &g, int rows) { return dim3(rows, (g.nv + 255) / 256); }
+
+hipError_t launch_setup_tables(const Geo &g, const BcInfo &bc, const Dev &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_boundary_tables, node_grid(g, NBC), dim3(256), 0, s, g, bc, d);
+    hipLaunchKernelGGL(k_incoming_moments, dim3(NBC * 6), dim3(256), 0, s, g, bc, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_maxwellian(const Geo &g, const Dev &d, bool fp32, double rho, const double *u, double Tt,
+                                  double Tr, hipStream_t s)
+{
+    if (fp32)
+        hipLaunchKernelGGL(k_init_maxwellian<float>, node_grid(g, g.ncell), dim3(256), 0, s, g, d, rho, u[0], u[1],
+                           u[2], Tt, Tr);
+    else
+        hipLaunchKernelGGL(k_init_maxwellian<double>, node_grid(g, g.ncell), dim3(256), 0, s, g, d, rho, u[0], u[1],
+                           u[2], Tt, Tr);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_canonical(const Geo &g, const Dev &d, bool fp32, const void *src, double *dst, hipStream_t s)
+{
+    if (fp32)
+        hipLaunchKernelGGL(k_to_canonical<float>, node_grid(g, g.ncell), dim3(256), 0, s, g, d, (const float *)src, dst);
+    else
+        hipLaunchKernelGGL(k_to_canonical<double>, node_grid(g, g.ncell), dim3(256), 0, s, g, d, (const double *)src,
+                           dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_from_canonical(const Geo &g, const Dev &d, bool fp32, const double *src, void *dst, hipStream_t s)
+{
+    if (fp32)
+        hipLaunchKernelGGL(k_from_canonical<float>, node_grid(g, g.ncell), dim3(256), 0, s, g, d, src, (float *)dst);
+    else
+        hipLaunchKernelGGL(k_from_canonical<double>, node_grid(g, g.ncell), dim3(256), 0, s, g, d, src,
+                           (double *)dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_vdf_node(const Geo &g, const Dev &d, bool fp32, int node, double *out, hipStream_t s)
+{
+    dim3 grd((g.ncell + 255) / 256);
+    if (fp32) hipLaunchKernelGGL(k_vdf_node<float>, grd, dim3(256), 0, s, g, d, node, out);
+    else hipLaunchKernelGGL(k_vdf_node<double>, grd, dim3(256), 0, s, g, d, node, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_correction(const Geo &g, const Dev &d, bool fp32, hipStream_t s)
+{
+    if (fp32)
+        hipLaunchKernelGGL(k_apply_correction<float>, node_grid(g, g.ncell), dim3(256), 0, s, g, d);
+    else
+        hipLaunchKernelGGL(k_apply_correction<double>, node_grid(g, g.ncell), dim3(256), 0, s, g, d);
+    return hipGetLastError();
+}
+
+}  // namespace gsis

@@ -1,0 +1,201 @@
+"""Python face of libgsis: the same calls as include/gsis.h, argument marshalling only.
+
+Device memory and streams come from PyTorch (ROCm): the workspace is a torch
+uint8 tensor on the GPU and device work goes to torch's current stream.  Every
+step of the kinetic path runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Tuple
+
+import numpy as np
+
+from . import _lib
+from .inputs import Case, DIATOMIC
+
+
+class GsisError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        self.status = status
+        super().__init__(f"{where}: {_lib.STATUS.get(status, status)}: {message}")
+
+
+def make_config(case: Case, dtype: str = "fp64") -> _lib.Config:
+    c = _lib.Config()
+    c.nx, c.ny, c.nz = case.nx, case.ny, case.nz
+    c.lx, c.ly, c.lz = case.lx, case.ly, case.lz
+    c.nvx, c.nvy, c.nvz = case.nv
+    for a in range(3):
+        c.vmin[a] = case.vmin[a]
+        c.vmax[a] = case.vmax[a]
+    c.species = case.species
+    c.Kn, c.omega = case.Kn, case.omega
+    c.dr, c.Zr = case.dr, case.Zr
+    for k in range(4):
+        c.A[k] = case.A[k]
+    c.inv_dt = case.inv_dt
+    c.vdf_dtype = {"fp64": 0, "fp32": 1}[dtype]
+    c.conservative = case.conservative
+    c.macro_cfl = case.macro_cfl
+    return c
+
+
+def tile_shapes():
+    """Compiled sweep tiles as (tx, ty, precision bits)."""
+    buf = (C.c_int * 96)()
+    n = C.c_int()
+    st = _lib.lib().gsis_tile_shapes(buf, 32, C.byref(n))
+    if st:
+        raise GsisError(st, "gsis_tile_shapes", "")
+    return [(buf[3 * k], buf[3 * k + 1], buf[3 * k + 2]) for k in range(n.value)]
+
+
+class Context:
+    """A gsis_ctx without device memory: creation, mask, boundaries, workspace size.
+    Touches no GPU (usable on a CPU-only host)."""
+
+    def __init__(self, case: Case, dtype: str = "fp64"):
+        self.case = case
+        self.dtype = dtype
+        self.L = _lib.lib()
+        self._cfg = make_config(case, dtype)
+        h = C.c_void_p()
+        st = self.L.gsis_create(C.byref(h), C.byref(self._cfg))
+        if st:
+            raise GsisError(st, "gsis_create", "invalid configuration")
+        self.h = h
+        if case.solid is not None:
+            mask = case.solid_mask()
+            self._check(self.L.gsis_set_solid_mask(self.h, mask.ctypes.data_as(C.c_void_p), mask.size),
+                        "gsis_set_solid_mask")
+        for face, bc in enumerate(case.bcs):
+            u = (C.c_double * 3)(*bc.u)
+            self._check(self.L.gsis_set_boundary(self.h, face, bc.kind, u, bc.T, bc.rho), "gsis_set_boundary")
+
+    def _check(self, st: int, where: str):
+        if st:
+            msg = self.L.gsis_last_error(self.h)
+            raise GsisError(st, where, msg.decode() if msg else "")
+
+    def workspace_size(self) -> int:
+        n = C.c_size_t()
+        self._check(self.L.gsis_workspace_size(self.h, C.byref(n)), "gsis_workspace_size")
+        return n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.gsis_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver(Context):
+    """A bound context on the current GPU (torch workspace, torch stream)."""
+
+    def __init__(self, case: Case, dtype: str = "fp64", tile: Optional[Tuple[int, int, int, int]] = None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libgsis needs a GPU; none is visible")
+        super().__init__(case, dtype)
+        self.torch = torch
+        if tile is not None:
+            self.set_tile(*tile)
+        nbytes = self.workspace_size()
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self._check(self.L.gsis_bind_workspace(self.h, C.c_void_p(self.ws.data_ptr()), nbytes), "gsis_bind_workspace")
+        self._check(self.L.gsis_set_stream(self.h, C.c_void_p(torch.cuda.current_stream().cuda_stream)),
+                    "gsis_set_stream")
+        self.nmom = _lib.NMOM[case.species]
+
+    def set_tile(self, tx: int, ty: int, tz: int, block: int):
+        self._check(self.L.gsis_set_tile(self.h, tx, ty, tz, block), "gsis_set_tile")
+
+    def init_maxwellian(self, rho=None, u=None, T=None, Tr=None):
+        r0, u0, T0, Tr0 = self.case.init
+        rho = r0 if rho is None else rho
+        u = (C.c_double * 3)(*(u0 if u is None else u))
+        T = T0 if T is None else T
+        Tr = Tr0 if Tr is None else Tr
+        self._check(self.L.gsis_init_maxwellian(self.h, rho, u, T, Tr), "gsis_init_maxwellian")
+
+    def kinetic_step(self, npasses: int = 1):
+        self._check(self.L.gsis_kinetic_step(self.h, npasses), "gsis_kinetic_step")
+
+    def gsis_correct(self, inner_iters: int):
+        self._check(self.L.gsis_gsis_correct(self.h, inner_iters), "gsis_gsis_correct")
+
+    def moments(self) -> np.ndarray:
+        out = np.empty((self.case.ncell, self.nmom), dtype=np.float64)
+        self._check(self.L.gsis_moments(self.h, out.ctypes.data_as(C.c_void_p), 0), "gsis_moments")
+        return out
+
+    def moments_device(self):
+        out = self.torch.empty((self.case.ncell, self.nmom), dtype=self.torch.float64, device="cuda")
+        self._check(self.L.gsis_moments(self.h, C.c_void_p(out.data_ptr()), 1), "gsis_moments")
+        return out
+
+    def residual(self) -> np.ndarray:
+        eps = (C.c_double * 3)()
+        self._check(self.L.gsis_residual(self.h, eps), "gsis_residual")
+        return np.array(eps[:])
+
+    def get_vdf(self):
+        t = self.torch
+        shape = (self.case.ncell, self.case.nvel)
+        f0 = t.empty(shape, dtype=t.float64, device="cuda")
+        f1 = t.empty(shape, dtype=t.float64, device="cuda") if self.case.species == DIATOMIC else None
+        self._check(self.L.gsis_get_vdf(self.h, C.c_void_p(f0.data_ptr()),
+                                        C.c_void_p(f1.data_ptr()) if f1 is not None else None), "gsis_get_vdf")
+        return f0, f1
+
+    def set_vdf(self, f0, f1=None):
+        t = self.torch
+        f0 = t.as_tensor(f0, dtype=t.float64).to("cuda").contiguous()
+        f1 = None if f1 is None else t.as_tensor(f1, dtype=t.float64).to("cuda").contiguous()
+        self._check(self.L.gsis_set_vdf(self.h, C.c_void_p(f0.data_ptr()),
+                                        C.c_void_p(f1.data_ptr()) if f1 is not None else None), "gsis_set_vdf")
+        t.cuda.current_stream().synchronize()
+
+    def state_size(self) -> int:
+        n = C.c_size_t()
+        self._check(self.L.gsis_state_size(self.h, C.byref(n)), "gsis_state_size")
+        return n.value
+
+    def get_state(self):
+        blob = self.torch.empty(self.state_size(), dtype=self.torch.uint8, device="cuda")
+        self._check(self.L.gsis_get_state(self.h, C.c_void_p(blob.data_ptr())), "gsis_get_state")
+        return blob
+
+    def set_state(self, blob):
+        self._check(self.L.gsis_set_state(self.h, C.c_void_p(blob.data_ptr())), "gsis_set_state")
+
+    def get_vdf_nodes(self, nodes):
+        nodes = np.ascontiguousarray(nodes, dtype=np.int32)
+        out = self.torch.empty((nodes.size, self.case.ncell), dtype=self.torch.float64, device="cuda")
+        self._check(self.L.gsis_get_vdf_nodes(self.h, nodes.ctypes.data_as(C.POINTER(C.c_int)), nodes.size,
+                                              C.c_void_p(out.data_ptr())), "gsis_get_vdf_nodes")
+        return out
+
+    def profile(self, enable: bool = True):
+        self._check(self.L.gsis_profile_enable(self.h, int(enable)), "gsis_profile_enable")
+
+    def profile_read(self, reset: bool = True):
+        """{phase: (milliseconds, calls)} measured with HIP events on the bound stream."""
+        ms = (C.c_double * 5)()
+        calls = (C.c_longlong * 5)()
+        self._check(self.L.gsis_profile_read(self.h, ms, calls, int(reset)), "gsis_profile_read")
+        return {name: (ms[k], calls[k]) for k, name in enumerate(_lib.PHASES)}
+
+    def pass_count(self) -> int:
+        n = C.c_longlong()
+        self._check(self.L.gsis_pass_count(self.h, C.byref(n)), "gsis_pass_count")
+        return n.value
+
+    def synchronize(self):
+        self.torch.cuda.current_stream().synchronize()

@@ -1,0 +1,126 @@
+"""Host-side checks of the C-ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments and out-of-order calls before any
+device work (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2310_18916_amd import _lib
+from paper_2310_18916_amd import gsis as G
+from paper_2310_18916_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+pytestmark = pytest.mark.skipif(not os.path.exists(_lib.LIB_PATH), reason="libgsis.so not built")
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "gsis.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gsis_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    names = header_symbols()
+    assert len(names) >= 20
+    L = _lib.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(_lib.SIGNATURES) == names
+
+
+def _cfg(**kw):
+    c = G.make_config(I.cavity(4, 6, 0.1))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def _create(cfg):
+    h = C.c_void_p()
+    st = _lib.lib().gsis_create(C.byref(h), C.byref(cfg))
+    return st, h
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 0), ("nvy", 1), ("Kn", 0.0), ("Kn", -1.0), ("lx", 0.0), ("species", 2), ("vdf_dtype", 3),
+    ("conservative", 2), ("inv_dt", -1.0), ("macro_cfl", 0.0), ("nz", 5000),
+])
+def test_create_rejects_bad_config(field, value):
+    st, h = _create(_cfg(**{field: value}))
+    assert st == -1 and not h.value
+
+
+def test_create_rejects_inverted_velocity_range_and_singular_A():
+    c = _cfg()
+    c.vmin[0], c.vmax[0] = 1.0, -1.0
+    assert _create(c)[0] == -1
+    c = _cfg(species=1, dr=2.0, Zr=3.5)
+    for k, v in enumerate([1.0, 2.0, 0.5, 1.0]):   # det = 0
+        c.A[k] = v
+    assert _create(c)[0] == -1
+
+
+def test_mask_boundary_and_order_checks():
+    L = _lib.lib()
+    st, h = _create(_cfg())
+    assert st == 0
+    try:
+        bad = np.zeros(10, dtype=np.uint8)
+        assert L.gsis_set_solid_mask(h, bad.ctypes.data_as(C.c_void_p), bad.size) == -1
+        allsolid = np.ones(64, dtype=np.uint8)
+        assert L.gsis_set_solid_mask(h, allsolid.ctypes.data_as(C.c_void_p), 64) == -1
+        assert b"solid" in L.gsis_last_error(h)
+        u = (C.c_double * 3)(0, 0, 0)
+        assert L.gsis_set_boundary(h, 7, 0, u, 1.0, 1.0) == -1
+        assert L.gsis_set_boundary(h, 0, 5, u, 1.0, 1.0) == -1
+        assert L.gsis_set_boundary(h, 0, 0, u, 0.0, 1.0) == -1
+        assert L.gsis_set_boundary(h, 0, 1, u, 1.0, -1.0) == -1
+        assert L.gsis_set_boundary(h, 0, 1, u, 1.0, 1.0) == 0
+        # device calls before a workspace is bound
+        assert L.gsis_init_maxwellian(h, 1.0, u, 1.0, 1.0) == -2
+        assert L.gsis_kinetic_step(h, 1) == -2
+        assert L.gsis_gsis_correct(h, 1) == -2
+        eps = (C.c_double * 3)()
+        assert L.gsis_residual(h, eps) == -2
+        out = np.empty(64 * 14)
+        assert L.gsis_moments(h, out.ctypes.data_as(C.c_void_p), 0) == -2
+        n = C.c_size_t()
+        assert L.gsis_workspace_size(h, C.byref(n)) == 0
+        vdf = 64 * 216 * 8
+        assert n.value > vdf
+        # the mask is frozen once the workspace is sized
+        ok = np.zeros(64, dtype=np.uint8)
+        assert L.gsis_set_solid_mask(h, ok.ctypes.data_as(C.c_void_p), 64) == -2
+        assert L.gsis_bind_workspace(h, C.c_void_p(255), n.value) == -1         # misaligned
+        assert L.gsis_bind_workspace(h, C.c_void_p(256), n.value - 1) == -3     # too small
+        assert L.gsis_bind_workspace(h, None, n.value) == -1
+    finally:
+        L.gsis_destroy(h)
+
+
+def test_workspace_grows_with_precision_and_species():
+    sizes = {}
+    for dt in ("fp32", "fp64"):
+        sizes[dt] = G.Context(I.cavity(6, 8, 0.1), dt).workspace_size()
+    assert sizes["fp64"] - sizes["fp32"] >= 6 ** 3 * 8 ** 3 * 4
+    mono = G.Context(I.small_block(), "fp32").workspace_size()
+    dia = G.Context(I.small_block(species=I.DIATOMIC), "fp32").workspace_size()
+    case = I.small_block()
+    assert dia - mono >= case.ncell * case.nvel * 4
+
+
+def test_tile_shapes_and_set_tile_validation():
+    shapes = G.tile_shapes()
+    assert (8, 8, 32) in shapes and (4, 4, 64) in shapes
+    ctx = G.Context(I.cavity(6, 8, 0.1), "fp32")
+    L = ctx.L
+    assert L.gsis_set_tile(ctx.h, 8, 8, 4, 128) == 0
+    assert L.gsis_set_tile(ctx.h, 5, 5, 4, 128) == -1     # not compiled
+    assert L.gsis_set_tile(ctx.h, 8, 8, 0, 128) == -1
+    assert L.gsis_set_tile(ctx.h, 8, 8, 4, 100) == -1     # not a multiple of 64
+    assert L.gsis_set_tile(ctx.h, 16, 8, 4, 256) == -1    # 16*8*256*4 B = 128 KiB of LDS
+    assert L.gsis_set_tile(ctx.h, 16, 8, 4, 128) == 0
