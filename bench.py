@@ -45,6 +45,9 @@ def run_gpu(case, dtype, steps, warmup, macro_iters, tile):
     from paper_2310_18916_amd.gsis import Solver
     s = Solver(case, dtype, tile=tile)
     s.init_maxwellian()
+    tune = None
+    if tile is None and case.inv_dt == 0.0:
+        tune = sorted(s.autotune(reps=2), key=lambda r: r[1])   # untimed set-up: one pass
 
     def step():
         s.kinetic_step(1)
@@ -66,7 +69,8 @@ def run_gpu(case, dtype, steps, warmup, macro_iters, tile):
     t1 = time.perf_counter()
     s.profile(False)
     prof = s.profile_read(reset=True)
-    return {"seconds": t1 - t0, "prof": prof, "eps": [float(x) for x in eps], "solver": s}
+    return {"seconds": t1 - t0, "prof": prof, "eps": [float(x) for x in eps], "solver": s, "tune": tune,
+            "tile": s.get_tile()}
 
 
 def cpu_baseline(case):
@@ -138,13 +142,16 @@ def main():
         "sweep_gbs": sweep_gbs,
         "moments_gbs": mom_gbs,
         "final_eps": r["eps"],
+        "sweep_tile": r["tile"],
+        "autotune_top": [[list(c), round(ms, 4)] for c, ms in (r["tune"] or [])[:6]],
     }
     del r
     if not a.no_fp32 and dtype == "fp64":
         r32 = run_gpu(case, "fp32", steps, a.warmup, macro, None)
         v32 = pts * steps / r32["seconds"]
-        out["fp32"] = {"value": v32, "speedup_vs_fp64": v32 / value,
-                       "phases_ms_per_step": {k: v[0] / steps for k, v in r32["prof"].items()}}
+        out["fp32"] = {"value": v32, "speedup_vs_fp64": v32 / value, "sweep_tile": r32["tile"],
+                       "phases_ms_per_step": {k: v[0] / steps for k, v in r32["prof"].items()},
+                       "autotune_top": [[list(c), round(ms, 4)] for c, ms in (r32["tune"] or [])[:6]]}
         del r32
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)

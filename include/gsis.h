@@ -161,6 +161,20 @@ gsis_status gsis_set_state(gsis_ctx *ctx, const void *src_device);
  * Only compiled shapes are accepted (see gsis_tile_shapes). */
 gsis_status gsis_set_tile(gsis_ctx *ctx, int tx, int ty, int tz, int block);
 
+/* Current sweep configuration (tx, ty, tz, block) into tile[4]. */
+gsis_status gsis_get_tile(const gsis_ctx *ctx, int *tile);
+
+/* Autotuner: performs the next kinetic pass, running its sweep reps >= 1 times
+ * under every compiled (tx, ty) tile shape, tile depths tz in {tx/2, tx, 2 tx}
+ * and blocks of 64, 128 and 256 threads, timed with HIP events; selects the
+ * fastest configuration for the context.  Valid because every configuration
+ * gives a bitwise-identical sweep; requires source iteration (inv_dt = 0),
+ * where the sweep does not read f^n.  Writes up to max entries of
+ * (tx, ty, tz, block) to cfg_out[4*k] and their mean sweep time in ms to
+ * ms_out[k], and the number of entries to *count (any output may be NULL).
+ * Synchronises. */
+gsis_status gsis_autotune(gsis_ctx *ctx, int reps, int *cfg_out, double *ms_out, int max, int *count);
+
 /* Compiled sweep tile shapes: writes up to max triples (tx, ty, precision in
  * bits: 32 or 64) to out and their number to *count. */
 gsis_status gsis_tile_shapes(int *out, int max, int *count);

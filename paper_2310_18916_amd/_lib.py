@@ -49,6 +49,8 @@ SIGNATURES = {
     "gsis_get_state": (_I, [_P, _P]),
     "gsis_set_state": (_I, [_P, _P]),
     "gsis_set_tile": (_I, [_P, _I, _I, _I, _I]),
+    "gsis_get_tile": (_I, [_P, C.POINTER(C.c_int)]),
+    "gsis_autotune": (_I, [_P, _I, C.POINTER(C.c_int), _DP, _I, C.POINTER(C.c_int)]),
     "gsis_tile_shapes": (_I, [C.POINTER(C.c_int), _I, C.POINTER(C.c_int)]),
     "gsis_get_vdf_nodes": (_I, [_P, C.POINTER(C.c_int), _I, _P]),
     "gsis_profile_enable": (_I, [_P, _I]),

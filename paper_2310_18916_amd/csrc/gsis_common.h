@@ -70,7 +70,7 @@ struct Dev {
     int *tiles;        // sweep tile list grouped by plane
     double *corr;      // [ncell][NCORR]
     double *snap;      // [ncell][NSNAP]
-    double *W, *P, *grad, *K, *hot, *R, *Dc, *Src, *fbfix;   // macroscopic solve
+    double *W, *P, *grad, *K, *hot, *R, *Dc, *Src, *fbfix, *Fb, *Gb;   // macroscopic solve
     double *red;       // reduction scratch
     unsigned long long *dmax;   // two slots, bit pattern of a positive double
     int *errflag;

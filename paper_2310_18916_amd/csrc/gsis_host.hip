@@ -74,13 +74,9 @@ template <class P> void carve(size_t &off, P *&ptr, size_t count, char *base)
 
 void default_tile(gsis_ctx *c)
 {
-    if (c->fp32) { c->tx = 8; c->ty = 8; c->tz = 8; c->bs = 128; }
+    bool dia = c->g.species == GSIS_DIATOMIC;
+    if (c->fp32) { c->tx = 8; c->ty = dia ? 4 : 8; c->tz = 8; c->bs = 128; }
     else { c->tx = 4; c->ty = 4; c->tz = 4; c->bs = 128; }
-}
-
-size_t sweep_lds(const gsis_ctx *c, int tx, int ty, int bs)
-{
-    return (size_t)tx * ty * bs * (c->fp32 ? 4 : 8) * (c->g.species == 1 ? 2 : 1);
 }
 
 void build_tiles(gsis_ctx *c)
@@ -205,7 +201,7 @@ size_t layout(gsis_ctx *c, char *base)
     carve(off, d.corr, n * NCORR, base);
     carve(off, d.snap, n * NSNAP, base);
     carve(off, d.W, n * 6, base);
-    carve(off, d.P, n * 8, base);
+    carve(off, d.P, n * 12, base);
     carve(off, d.grad, n * 9, base);
     carve(off, d.K, n * 12, base);
     carve(off, d.hot, n * 15, base);
@@ -213,6 +209,8 @@ size_t layout(gsis_ctx *c, char *base)
     carve(off, d.Dc, n, base);
     carve(off, d.Src, n, base);
     carve(off, d.fbfix, nf * 6, base);
+    carve(off, d.Fb, nf * 6, base);
+    carve(off, d.Gb, nf, base);
     carve(off, d.red, (size_t)(resid_blocks(g) + 1) * 6, base);
     carve(off, d.dmax, 2, base);
     carve(off, d.errflag, 4, base);
@@ -736,10 +734,10 @@ gsis_status gsis_set_tile(gsis_ctx *ctx, int tx, int ty, int tz, int block)
     if (tx == 0 && ty == 0 && tz == 0 && block == 0) {
         default_tile(ctx);
     } else {
-        if (!sweep_shape_supported(ctx->fp32, tx, ty)) return fail(ctx, GSIS_EINVAL, "tile (tx, ty) not compiled");
+        if (!sweep_shape_supported(ctx->fp32, ctx->g.species == GSIS_DIATOMIC, tx, ty))
+            return fail(ctx, GSIS_EINVAL, "tile (tx, ty) not compiled for this precision and gas");
         if (tz < 1 || tz > 1024) return fail(ctx, GSIS_EINVAL, "tz must be 1..1024");
         if (block < 64 || block > 256 || block % 64) return fail(ctx, GSIS_EINVAL, "block must be 64, 128, 192 or 256");
-        if (sweep_lds(ctx, tx, ty, block) > 65536) return fail(ctx, GSIS_EINVAL, "tile plane exceeds 64 KiB of LDS");
         int ntx = (ctx->g.nx + tx - 1) / tx, nty = (ctx->g.ny + ty - 1) / ty, ntz = (ctx->g.nz + tz - 1) / tz;
         if (ntx > 1023 || nty > 1023 || ntz > 1023) return fail(ctx, GSIS_EINVAL, "too many tiles per axis");
         ctx->tx = tx; ctx->ty = ty; ctx->tz = tz; ctx->bs = block;
@@ -749,6 +747,89 @@ gsis_status gsis_set_tile(gsis_ctx *ctx, int tx, int ty, int tz, int block)
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
         HIPCHK(ctx, hipMemcpy(ctx->d.tiles, ctx->tiles.data(), ctx->tiles.size() * sizeof(int), hipMemcpyHostToDevice));
     }
+    return GSIS_OK;
+}
+
+gsis_status gsis_autotune(gsis_ctx *ctx, int reps, int *cfg_out, double *ms_out, int max, int *count)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (!ctx->inited) return fail(ctx, GSIS_ESTATE, "initialise the VDF first");
+    if (reps < 1 || max < 0) return fail(ctx, GSIS_EINVAL, "reps must be >= 1");
+    if (ctx->g.inv_dt != 0.0) return fail(ctx, GSIS_EINVAL, "autotune needs source iteration (inv_dt = 0)");
+    const Geo &g = ctx->g;
+    bool dia = g.species == GSIS_DIATOMIC;
+    int shapes[32];
+    int nsh = sweep_shapes(ctx->fp32, shapes, 16);
+    struct Cand { int tx, ty, tz, bs; double ms; };
+    std::vector<Cand> cands;
+    for (int k = 0; k < nsh; ++k) {
+        int tx = shapes[2 * k], ty = shapes[2 * k + 1];
+        if (!sweep_shape_supported(ctx->fp32, dia, tx, ty)) continue;
+        for (int tz : {tx / 2, tx, 2 * tx})
+            for (int bs : {64, 128, 256}) cands.push_back({tx, ty, std::max(tz, 1), bs, 0.0});
+    }
+    int save[4] = {ctx->tx, ctx->ty, ctx->tz, ctx->bs};
+    HIPCHK(ctx, launch_params(g, ctx->d, ctx->stream));
+    HIPCHK(ctx, launch_face_scale(g, ctx->bc, ctx->d, ctx->stream));
+    hipEvent_t e0, e1;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    gsis_status st = GSIS_OK;
+    for (auto &c : cands) {
+        ctx->tx = c.tx; ctx->ty = c.ty; ctx->tz = c.tz; ctx->bs = c.bs;
+        build_tiles(ctx);
+        hipError_t e = hipMemcpy(ctx->d.tiles, ctx->tiles.data(), ctx->tiles.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess)   // warm-up launch of this configuration
+            e = launch_sweep(g, ctx->d, ctx->fp32, c.tx, c.ty, c.tz, c.bs, ctx->plane_off.data(), ctx->plane_cnt.data(),
+                             (int)ctx->plane_off.size(), ctx->stream);
+        if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            e = launch_sweep(g, ctx->d, ctx->fp32, c.tx, c.ty, c.tz, c.bs, ctx->plane_off.data(), ctx->plane_cnt.data(),
+                             (int)ctx->plane_off.size(), ctx->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { st = fail(ctx, GSIS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e)); break; }
+        c.ms = ms / reps;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) {
+        ctx->tx = save[0]; ctx->ty = save[1]; ctx->tz = save[2]; ctx->bs = save[3];
+        build_tiles(ctx);
+        hipMemcpy(ctx->d.tiles, ctx->tiles.data(), ctx->tiles.size() * sizeof(int), hipMemcpyHostToDevice);
+        return st;
+    }
+    size_t best = 0;
+    for (size_t k = 1; k < cands.size(); ++k)
+        if (cands[k].ms < cands[best].ms) best = k;
+    ctx->tx = cands[best].tx; ctx->ty = cands[best].ty; ctx->tz = cands[best].tz; ctx->bs = cands[best].bs;
+    build_tiles(ctx);
+    HIPCHK(ctx, hipMemcpy(ctx->d.tiles, ctx->tiles.data(), ctx->tiles.size() * sizeof(int), hipMemcpyHostToDevice));
+    // the VDF now holds this pass's sweep result (identical under every configuration)
+    ctx->pending = false;
+    st = reduce_vdf(ctx);
+    if (st) return st;
+    ctx->passes++;
+    ctx->stepped = true;
+    int n = 0;
+    for (size_t k = 0; k < cands.size() && n < max; ++k, ++n) {
+        if (cfg_out) {
+            cfg_out[4 * n] = cands[k].tx; cfg_out[4 * n + 1] = cands[k].ty;
+            cfg_out[4 * n + 2] = cands[k].tz; cfg_out[4 * n + 3] = cands[k].bs;
+        }
+        if (ms_out) ms_out[n] = cands[k].ms;
+    }
+    if (count) *count = n;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return GSIS_OK;
+}
+
+gsis_status gsis_get_tile(const gsis_ctx *ctx, int *tile)
+{
+    if (!ctx || !tile) return GSIS_EINVAL;
+    tile[0] = ctx->tx; tile[1] = ctx->ty; tile[2] = ctx->tz; tile[3] = ctx->bs;
     return GSIS_OK;
 }
 

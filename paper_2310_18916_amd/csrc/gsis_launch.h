@@ -19,7 +19,7 @@ hipError_t launch_commit_correction(const Geo &g, const Dev &d, hipStream_t s);
 hipError_t launch_params(const Geo &g, const Dev &d, hipStream_t s);
 hipError_t launch_face_scale(const Geo &g, const BcInfo &bc, const Dev &d, hipStream_t s);
 
-bool sweep_shape_supported(bool fp32, int tx, int ty);
+bool sweep_shape_supported(bool fp32, bool dia, int tx, int ty);
 int sweep_shapes(bool fp32, int *out, int max);
 hipError_t launch_sweep(const Geo &g, const Dev &d, bool fp32, int tx, int ty, int tz, int bs, const int *plane_off,
                         const int *plane_cnt, int nplane, hipStream_t s);

@@ -25,7 +25,10 @@
 
 namespace gsis {
 
-constexpr int NP = 8;   // prims per cell: rho, ux, uy, uz, Tt, Tr, E, Er
+// prims per cell: rho, ux, uy, uz, Tt, Tr, E, Er, c_s, Tt^omega / delta, 1/tau, (unused)
+constexpr int NP = 12;
+
+__device__ __forceinline__ double sound(const Geo &g, const double *P) { return sqrt(g.gam * P[4] / 2.0); }
 
 __device__ __forceinline__ void prim_from_W(const Geo &g, const double *W, double *P)
 {
@@ -37,9 +40,11 @@ __device__ __forceinline__ void prim_from_W(const Geo &g, const double *W, doubl
     double Tt = (2.0 / 3.0) * (E - Er - rho * uu) / rho;
     double Tr = g.species == 1 ? 2.0 * Er / (g.dr * rho) : Tt;
     P[0] = rho; P[1] = u0; P[2] = u1; P[3] = u2; P[4] = Tt; P[5] = Tr; P[6] = E; P[7] = Er;
+    P[8] = sqrt(g.gam * Tt / 2.0);
+    P[9] = pow(Tt, g.omega) / g.delta;
+    P[10] = g.delta * rho * pow(Tt, 1.0 - g.omega);
+    P[11] = 0.0;
 }
-
-__device__ __forceinline__ double sound(const Geo &g, const double *P) { return sqrt(g.gam * P[4] / 2.0); }
 
 __device__ void nsf_face(const Geo &g, const double *L, const double *R, const double *gL, const double *gR, int a,
                          double h, double sigN[3], double *qN, double *qrN)
@@ -57,32 +62,41 @@ __device__ void nsf_face(const Geo &g, const double *L, const double *R, const d
     *qrN = g.species == 1 ? -g.kr * mu * (R[5] - L[5]) / h : 0.0;
 }
 
-__device__ void face_flux(const Geo &g, const double *L, const double *R, const double *gL, const double *gR, int a,
-                          double h, const double *hot, double F[6], double *Gam)
+// convective flux vector Phi(W).n and the state vector of one side
+__device__ __forceinline__ void side(const double *P, int a, double Phi[6], double Wv[6])
+{
+    double rho = P[0], un = P[1 + a], p = P[0] * P[4];
+    Phi[0] = rho * un;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Phi[1 + b] = rho * P[1 + b] * un + (b == a ? 0.5 * p : 0.0);
+    Phi[4] = (P[6] + p) * un;
+    Phi[5] = P[7] * un;
+    Wv[0] = rho;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Wv[1 + b] = rho * P[1 + b];
+    Wv[4] = P[6];
+    Wv[5] = P[7];
+}
+
+__device__ __forceinline__ void face_flux(const Geo &g, const double *L, const double *R, const double *gL,
+                                          const double *gR, int a, double h, const double *hot, double F[6],
+                                          double *Gam)
 {
     double sigN[3], qN, qrN;
     nsf_face(g, L, R, gL, gR, a, h, sigN, &qN, &qrN);
-    const double *S[2] = {L, R};
-    double Phi[2][6], Wv[2][6];
-    for (int k = 0; k < 2; ++k) {
-        const double *P = S[k];
-        double rho = P[0], un = P[1 + a], p = P[0] * P[4];
-        Phi[k][0] = rho * un;
-        for (int b = 0; b < 3; ++b) Phi[k][1 + b] = rho * P[1 + b] * un + (b == a ? 0.5 * p : 0.0);
-        Phi[k][4] = (P[6] + p) * un;
-        Phi[k][5] = P[7] * un;
-        Wv[k][0] = rho;
-        for (int b = 0; b < 3; ++b) Wv[k][1 + b] = rho * P[1 + b];
-        Wv[k][4] = P[6];
-        Wv[k][5] = P[7];
-    }
-    double sL = fabs(L[1 + a]) + sound(g, L), sR = fabs(R[1 + a]) + sound(g, R);
+    double PhiL[6], WL[6], PhiR[6], WR[6];
+    side(L, a, PhiL, WL);
+    side(R, a, PhiR, WR);
+    double sL = fabs(L[1 + a]) + L[8], sR = fabs(R[1 + a]) + R[8];
     double smax = sL > sR ? sL : sR;
-    for (int k = 0; k < 6; ++k) F[k] = 0.5 * (Phi[0][k] + Phi[1][k]) - 0.5 * smax * (Wv[1][k] - Wv[0][k]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) F[k] = 0.5 * (PhiL[k] + PhiR[k]) - 0.5 * smax * (WR[k] - WL[k]);
     double sn[3], uF[3];
+#pragma unroll
     for (int b = 0; b < 3; ++b) { sn[b] = sigN[b] + hot[b]; uF[b] = 0.5 * (L[1 + b] + R[1 + b]); }
     double qn = qN + hot[3];
     double qrn = g.species == 1 ? qrN + hot[4] : 0.0;
+#pragma unroll
     for (int b = 0; b < 3; ++b) F[1 + b] += 0.5 * sn[b];
     F[4] += sn[0] * uF[0] + sn[1] * uF[1] + sn[2] * uF[2] + qn + qrn;
     F[5] += qrn;
@@ -210,7 +224,8 @@ __global__ void k_mac_hot(Geo g, Dev d)
     }
 }
 
-// Fixed part of each boundary face flux: F_kin(f^{n+1/2}) - F_eq(W^{n+1/2}).
+// Fixed part of each boundary face flux, F_kin(f^{n+1/2}) - F_eq(W^{n+1/2}), and
+// the face flux of the first inner iteration, fixed part + F_eq(W^{n+1/2}).
 __global__ void k_mac_fbfix(Geo g, BcInfo bc, Dev d)
 {
     int f = blockIdx.x * blockDim.x + threadIdx.x;
@@ -220,10 +235,10 @@ __global__ void k_mac_fbfix(Geo g, BcInfo bc, Dev d)
     int neg = (dir & 1) ? 0 : 1;
     double sg = neg ? -1.0 : 1.0;
     double out[6] = {0, 0, 0, 0, 0, 0};
+    const int m2row[3][3] = {{4, 7, 8}, {7, 5, 9}, {8, 9, 6}};
     for (int o = 0; o < 8; ++o) {
         if (((o >> a) & 1) != neg) continue;
         const double *m = d.mom8 + ((size_t)cell * 8 + o) * NRS;
-        const int m2row[3][3] = {{4, 7, 8}, {7, 5, 9}, {8, 9, 6}};
         out[0] += m[1 + a];
         for (int c = 0; c < 3; ++c) out[1 + c] += m[m2row[a][c]];
         out[4] += m[10 + a] + m[14 + a];
@@ -232,60 +247,71 @@ __global__ void k_mac_fbfix(Geo g, BcInfo bc, Dev d)
     for (int k = 0; k < 6; ++k) out[k] *= sg;
     const double *in = d.inpsi + (b * 6 + dir) * 6;
     double sc = bc.kind[b] == 1 ? bc.rho[b] : out[0] / (-in[0]);
+    const double *P = d.P + (size_t)cell * NP;
     double Fe[6];
-    equilibrium_face_flux(g, bc, d, d.P + (size_t)d.face_cell[f] * NP, dir, b, Fe);
-    for (int k = 0; k < 6; ++k) d.fbfix[(size_t)f * 6 + k] = out[k] + sc * in[k] - Fe[k];
+    equilibrium_face_flux(g, bc, d, P, dir, b, Fe);
+    for (int k = 0; k < 6; ++k) {
+        double fix = out[k] + sc * in[k] - Fe[k];
+        d.fbfix[(size_t)f * 6 + k] = fix;
+        d.Fb[(size_t)f * 6 + k] = fix + Fe[k];
+    }
+    d.Gb[f] = fabs(P[1 + a]) + P[8] + g.Cd * pow(P[4], g.omega) / (g.delta * P[0] * g.h[a]);
 }
 
 // Residual and diagonal of every cell; D* = max D_i by an atomic max on the
 // bit pattern (positive doubles order like their bits), so it is exact and
 // order independent.
-__global__ void k_mac_res(Geo g, BcInfo bc, Dev d, int slot)
+template <bool DIA>
+__global__ __launch_bounds__(128) void k_mac_res(Geo g, Dev d, int slot)
 {
     int cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= g.ncell || !d.cflag[cell]) return;
     const double *Pi = d.P + (size_t)cell * NP;
     const int *nb = d.nbr + (size_t)cell * 6;
+    constexpr int NW = DIA ? 6 : 5;
     double res[6] = {0, 0, 0, 0, 0, 0}, sumG = 0.0;
-    double csi = sound(g, Pi);
+#pragma unroll
     for (int dir = 0; dir < 6; ++dir) {
-        int a = dir / 2;
-        double h = g.h[a];
-        int n = nb[dir];
-        double F[6], out[6], Gam;
+        const int a = dir / 2;
+        const double h = g.h[a];
+        const int n = nb[dir];
+        double out[6], Gam;
         if (n >= 0) {
-            int L = (dir & 1) ? cell : n, R = (dir & 1) ? n : cell;
-            face_flux(g, d.P + (size_t)L * NP, d.P + (size_t)R * NP, d.grad + (size_t)L * 9, d.grad + (size_t)R * 9, a,
-                      h, d.hot + (size_t)L * 15 + a * 5, F, &Gam);
+            const int L = (dir & 1) ? cell : n, R = (dir & 1) ? n : cell;
+            double F[6];
+            face_flux(g, d.P + (size_t)L * NP, d.P + (size_t)R * NP, d.grad + (size_t)L * 9, d.grad + (size_t)R * 9,
+                      a, h, d.hot + (size_t)L * 15 + a * 5, F, &Gam);
+#pragma unroll
             for (int k = 0; k < 6; ++k) out[k] = (dir & 1) ? F[k] : -F[k];
         } else {
-            int f = -n - 1;
-            double Fe[6];
-            equilibrium_face_flux(g, bc, d, Pi, dir, d.face_bc[f], Fe);
-            for (int k = 0; k < 6; ++k) out[k] = d.fbfix[(size_t)f * 6 + k] + Fe[k];
-            Gam = fabs(Pi[1 + a]) + csi + g.Cd * pow(Pi[4], g.omega) / (g.delta * Pi[0] * h);
+            const int f = -n - 1;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) out[k] = d.Fb[(size_t)f * 6 + k];
+            Gam = d.Gb[f];
         }
-        int nw = g.species == 1 ? 6 : 5;
-        for (int k = 0; k < nw; ++k) res[k] -= out[k] / h;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) res[k] -= out[k] / h;
         sumG += Gam / h;
     }
     double invtau = g.delta * Pi[0] * pow(Pi[4], 1.0 - g.omega);
-    if (g.species == 1) {
+    if (DIA) {
         double T = (3.0 * Pi[4] + g.dr * Pi[5]) / (3.0 + g.dr);
         res[5] += 0.5 * g.dr * Pi[0] * (T - Pi[5]) * invtau / g.Zr;
     }
     double umag = sqrt(Pi[1] * Pi[1] + Pi[2] * Pi[2] + Pi[3] * Pi[3]);
-    double idt = (umag + csi + g.Cd * pow(Pi[4], g.omega) / (g.delta * Pi[0] * g.hmin)) / (g.macro_cfl * g.hmin);
+    double idt = (umag + Pi[8] + g.Cd * pow(Pi[4], g.omega) / (g.delta * Pi[0] * g.hmin)) / (g.macro_cfl * g.hmin);
     double D = idt + 0.5 * sumG;
     double *r = d.R + (size_t)cell * 6;
+#pragma unroll
     for (int k = 0; k < 6; ++k) r[k] = res[k];
-    d.Dc[cell] = D;
-    d.Src[cell] = g.species == 1 ? invtau / g.Zr : 0.0;
+    d.Src[cell] = DIA ? invtau / g.Zr : 0.0;
     if (D > 0.0 && isfinite(D)) atomicMax(&d.dmax[slot], (unsigned long long)__double_as_longlong(D));
     else atomicOr(d.errflag, 2);
 }
 
-__global__ void k_mac_update(Geo g, Dev d, int slot)
+// W += R / D*, new prims, and the flux of the cell's boundary faces at the new
+// state (fixed part + F_eq(W^{m+1})) for the next iteration.
+__global__ __launch_bounds__(128) void k_mac_update(Geo g, BcInfo bc, Dev d, int slot)
 {
     int cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell == 0) d.dmax[slot ^ 1] = 0ull;   // the other slot was last used by the previous iteration
@@ -295,7 +321,19 @@ __global__ void k_mac_update(Geo g, Dev d, int slot)
     const double *r = d.R + (size_t)cell * 6;
     for (int k = 0; k < 5; ++k) W[k] += r[k] / Dm;
     if (g.species == 1) W[5] += r[5] / (Dm + d.Src[cell]);
-    prim_from_W(g, W, d.P + (size_t)cell * NP);
+    double *P = d.P + (size_t)cell * NP;
+    prim_from_W(g, W, P);
+    const int *nb = d.nbr + (size_t)cell * 6;
+    for (int dir = 0; dir < 6; ++dir) {
+        int n = nb[dir];
+        if (n >= 0) continue;
+        int f = -n - 1;
+        double Fe[6];
+        equilibrium_face_flux(g, bc, d, P, dir, d.face_bc[f], Fe);
+        for (int k = 0; k < 6; ++k) d.Fb[(size_t)f * 6 + k] = d.fbfix[(size_t)f * 6 + k] + Fe[k];
+        int a = dir / 2;
+        d.Gb[f] = fabs(P[1 + a]) + P[8] + g.Cd * pow(P[4], g.omega) / (g.delta * P[0] * g.h[a]);
+    }
 }
 
 __global__ void k_mac_reset(Dev d)
@@ -326,8 +364,9 @@ hipError_t launch_gsis_macro(const Geo &g, const BcInfo &bc, const Dev &d, int i
     for (int it = 0; it < iters; ++it) {
         int slot = it & 1;
         if (it > 0) hipLaunchKernelGGL(k_mac_grad, grd, blk, 0, s, g, d);
-        hipLaunchKernelGGL(k_mac_res, grd, blk, 0, s, g, bc, d, slot);
-        hipLaunchKernelGGL(k_mac_update, grd, blk, 0, s, g, d, slot);
+        if (g.species == 1) hipLaunchKernelGGL(k_mac_res<true>, grd, blk, 0, s, g, d, slot);
+        else hipLaunchKernelGGL(k_mac_res<false>, grd, blk, 0, s, g, d, slot);
+        hipLaunchKernelGGL(k_mac_update, grd, blk, 0, s, g, bc, d, slot);
     }
     hipLaunchKernelGGL(k_mac_final, grd, blk, 0, s, g, d);
     return hipGetLastError();

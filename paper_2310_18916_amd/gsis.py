@@ -116,6 +116,20 @@ class Solver(Context):
     def set_tile(self, tx: int, ty: int, tz: int, block: int):
         self._check(self.L.gsis_set_tile(self.h, tx, ty, tz, block), "gsis_set_tile")
 
+    def get_tile(self):
+        t = (C.c_int * 4)()
+        self._check(self.L.gsis_get_tile(self.h, t), "gsis_get_tile")
+        return tuple(t)
+
+    def autotune(self, reps: int = 2):
+        """Time the next pass's sweep under every compiled configuration and keep the
+        fastest; returns [((tx, ty, tz, block), ms), ...]."""
+        cfg = (C.c_int * 512)()
+        ms = (C.c_double * 128)()
+        n = C.c_int()
+        self._check(self.L.gsis_autotune(self.h, reps, cfg, ms, 128, C.byref(n)), "gsis_autotune")
+        return [((cfg[4 * k], cfg[4 * k + 1], cfg[4 * k + 2], cfg[4 * k + 3]), ms[k]) for k in range(n.value)]
+
     def init_maxwellian(self, rho=None, u=None, T=None, Tr=None):
         r0, u0, T0, Tr0 = self.case.init
         rho = r0 if rho is None else rho

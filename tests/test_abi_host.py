@@ -122,5 +122,14 @@ def test_tile_shapes_and_set_tile_validation():
     assert L.gsis_set_tile(ctx.h, 5, 5, 4, 128) == -1     # not compiled
     assert L.gsis_set_tile(ctx.h, 8, 8, 0, 128) == -1
     assert L.gsis_set_tile(ctx.h, 8, 8, 4, 100) == -1     # not a multiple of 64
-    assert L.gsis_set_tile(ctx.h, 16, 8, 4, 256) == -1    # 16*8*256*4 B = 128 KiB of LDS
-    assert L.gsis_set_tile(ctx.h, 16, 8, 4, 128) == 0
+    assert L.gsis_set_tile(ctx.h, 16, 8, 4, 128) == -1    # not compiled
+    assert L.gsis_set_tile(ctx.h, 8, 4, 16, 256) == 0
+    tile = (C.c_int * 4)()
+    assert L.gsis_get_tile(ctx.h, tile) == 0 and tuple(tile) == (8, 4, 16, 256)
+    # the diatomic gas keeps two register planes: the 8x8 slab is not compiled for it
+    dia = G.Context(I.small_block(species=I.DIATOMIC), "fp32")
+    assert dia.L.gsis_set_tile(dia.h, 8, 8, 8, 128) == -1
+    assert dia.L.gsis_set_tile(dia.h, 8, 4, 8, 128) == 0
+    f64 = G.Context(I.cavity(6, 8, 0.1), "fp64")
+    assert f64.L.gsis_set_tile(f64.h, 8, 8, 8, 128) == -1
+    assert f64.L.gsis_set_tile(f64.h, 8, 4, 8, 128) == 0

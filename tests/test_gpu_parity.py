@@ -185,7 +185,9 @@ def test_gsis_parity(name, iters):
         assert_fields(s.moments(), o.moments(), 1e-12, case.solid_mask(), what=f"{name} after correction {it}")
         es, eo = s.residual(), o.residual()
         say(f"  eps gpu {es} oracle {eo}")
-        assert np.allclose(es, eo, rtol=1e-9, atol=0)
+        # u's relative change against a state at rest is rounding noise over rounding noise
+        comps = [0, 1, 2] if it > 0 or np.linalg.norm(case.init[1]) > 0 else [0, 2]
+        assert np.allclose(es[comps], eo[comps], rtol=1e-9, atol=0)
     s.kinetic_step(1)
     o.step(1)
     assert_fields(s.moments(), o.moments(), 1e-12, case.solid_mask(), what=f"{name} final")
@@ -220,8 +222,8 @@ def test_tile_shapes_bitwise_identical():
     say("[determinism]")
     case = I.cavity(13, 10, 0.1, lid=0.25)
     results = {}
-    for dtype, shapes in (("fp32", [(8, 8, 8, 128), (4, 4, 4, 64), (16, 8, 3, 128), (8, 8, 13, 256)]),
-                          ("fp64", [(4, 4, 4, 128), (8, 4, 2, 64), (8, 8, 5, 64), (4, 4, 13, 256)])):
+    for dtype, shapes in (("fp32", [(8, 8, 8, 128), (4, 4, 4, 64), (8, 4, 3, 128), (8, 8, 13, 256)]),
+                          ("fp64", [(4, 4, 4, 128), (8, 4, 2, 64), (8, 4, 5, 192), (4, 4, 13, 256)])):
         for sh in shapes:
             s = Solver(case, dtype, tile=sh)
             s.init_maxwellian()
@@ -232,6 +234,26 @@ def test_tile_shapes_bitwise_identical():
         ref = lst[0][1]
         for sh, f in lst[1:]:
             assert np.array_equal(f, ref), (dtype, sh)
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_autotune_pass_equals_plain_pass(dtype):
+    """The autotuner's pass (its sweep run under every configuration) is the same pass."""
+    say(f"[autotune] {dtype}")
+    case = I.cavity(11, 10, 0.1, lid=0.2)
+    a = Solver(case, dtype)
+    a.init_maxwellian()
+    a.kinetic_step(1)
+    table = a.autotune(reps=1)
+    assert len(table) >= 9 and all(ms > 0 for _, ms in table)
+    best = min(table, key=lambda r: r[1])[0]
+    assert a.get_tile() == best
+    b = Solver(case, dtype)
+    b.init_maxwellian()
+    b.kinetic_step(2)
+    assert a.pass_count() == 2
+    assert np.array_equal(a.get_vdf()[0].cpu().numpy(), b.get_vdf()[0].cpu().numpy())
+    assert np.array_equal(a.moments(), b.moments())
 
 
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
