@@ -157,8 +157,8 @@ gsis_status gsis_get_state(gsis_ctx *ctx, void *dst_device);
 gsis_status gsis_set_state(gsis_ctx *ctx, const void *src_device);
 
 /* Sweep tile (cells per tile along x, y, z in the octant's upwind frame) and
- * threads per block; 0 picks the built-in default for the VDF precision.
- * Only compiled shapes are accepted (see gsis_tile_shapes). */
+ * threads per block (128 or 256); all zeros pick the built-in default for the
+ * VDF precision.  Only compiled (tx, ty) are accepted (see gsis_tile_shapes). */
 gsis_status gsis_set_tile(gsis_ctx *ctx, int tx, int ty, int tz, int block);
 
 /* Current sweep configuration (tx, ty, tz, block) into tile[4]. */
@@ -166,7 +166,7 @@ gsis_status gsis_get_tile(const gsis_ctx *ctx, int *tile);
 
 /* Autotuner: performs the next kinetic pass, running its sweep reps >= 1 times
  * under every compiled (tx, ty) tile shape, tile depths tz in {tx/2, tx, 2 tx}
- * and blocks of 64, 128 and 256 threads, timed with HIP events; selects the
+ * and blocks of 128 and 256 threads, timed with HIP events; selects the
  * fastest configuration for the context.  Valid because every configuration
  * gives a bitwise-identical sweep; requires source iteration (inv_dt = 0),
  * where the sweep does not read f^n.  Writes up to max entries of

@@ -57,6 +57,8 @@ struct Dev {
     int *face_cell, *face_dir, *face_bc;   // [nface]
     double *fscale;    // [nface] density scale of the incoming half
     float *fscalef;
+    double *cfs64;     // [ncell][6] the same scale by (cell, face direction), for the sweep
+    float *cfs32;
     double *xi64[3];   // per-axis nodes
     float *xi32[3];
     double *w64[3];    // per-axis trapezoid weights

@@ -183,6 +183,8 @@ size_t layout(gsis_ctx *c, char *base)
     carve(off, d.face_bc, nf, base);
     carve(off, d.fscale, nf, base);
     carve(off, d.fscalef, nf, base);
+    carve(off, d.cfs64, n * 6, base);
+    carve(off, d.cfs32, n * 6, base);
     for (int a = 0; a < 3; ++a) {
         carve(off, d.xi64[a], (size_t)g.n1[a], base);
         carve(off, d.xi32[a], (size_t)g.n1[a], base);
@@ -737,7 +739,7 @@ gsis_status gsis_set_tile(gsis_ctx *ctx, int tx, int ty, int tz, int block)
         if (!sweep_shape_supported(ctx->fp32, ctx->g.species == GSIS_DIATOMIC, tx, ty))
             return fail(ctx, GSIS_EINVAL, "tile (tx, ty) not compiled for this precision and gas");
         if (tz < 1 || tz > 1024) return fail(ctx, GSIS_EINVAL, "tz must be 1..1024");
-        if (block < 64 || block > 256 || block % 64) return fail(ctx, GSIS_EINVAL, "block must be 64, 128, 192 or 256");
+        if (block != 128 && block != 256) return fail(ctx, GSIS_EINVAL, "block must be 128 or 256");
         int ntx = (ctx->g.nx + tx - 1) / tx, nty = (ctx->g.ny + ty - 1) / ty, ntz = (ctx->g.nz + tz - 1) / tz;
         if (ntx > 1023 || nty > 1023 || ntz > 1023) return fail(ctx, GSIS_EINVAL, "too many tiles per axis");
         ctx->tx = tx; ctx->ty = ty; ctx->tz = tz; ctx->bs = block;
@@ -766,7 +768,7 @@ gsis_status gsis_autotune(gsis_ctx *ctx, int reps, int *cfg_out, double *ms_out,
         int tx = shapes[2 * k], ty = shapes[2 * k + 1];
         if (!sweep_shape_supported(ctx->fp32, dia, tx, ty)) continue;
         for (int tz : {tx / 2, tx, 2 * tx})
-            for (int bs : {64, 128, 256}) cands.push_back({tx, ty, std::max(tz, 1), bs, 0.0});
+            for (int bs : {128, 256}) cands.push_back({tx, ty, std::max(tz, 1), bs, 0.0});
     }
     int save[4] = {ctx->tx, ctx->ty, ctx->tz, ctx->bs};
     HIPCHK(ctx, launch_params(g, ctx->d, ctx->stream));

@@ -243,6 +243,8 @@ __global__ void k_face_scale(Geo g, BcInfo bc, Dev d)
     }
     d.fscale[f] = sc;
     d.fscalef[f] = (float)sc;
+    d.cfs64[(size_t)cell * 6 + dir] = sc;
+    d.cfs32[(size_t)cell * 6 + dir] = (float)sc;
 }
 
 hipError_t launch_params(const Geo &g, const Dev &d, hipStream_t s)

@@ -43,8 +43,8 @@ struct SweepArgs {
     Geo g;
     void *f0, *f1;
     const void *par;
-    const int *cflag, *nbr, *face_bc, *tiles;
-    const void *fscale;
+    const int *cflag, *tiles;
+    const void *fscale;    // [ncell][6] incoming density scale of boundary faces
     const void *mb, *mb1;
     const void *xi[3];
 };
@@ -78,32 +78,23 @@ __device__ __forceinline__ void ref_dia(const T *p, T cx, T cy, T cz, T &g0, T &
     g1 = Et * rt + Er * rr;
 }
 
-// Value entering a cell through one upwind face: the neighbour's f^{n+1/2}
-// (already final: the upwind tile ran in an earlier launch) or the boundary
-// value rho_b M_b(xi) of the face.
-template <typename T>
-__device__ __forceinline__ T inflow(const SweepArgs &A, const T *f, const T *mbt, int nb, size_t node)
-{
-    const size_t nv = (size_t)A.g.nv;
-    if (nb >= 0) return f[(size_t)nb * nv + node];
-    const int fc = -nb - 1;
-    return ((const T *)A.fscale)[fc] * mbt[(size_t)A.face_bc[fc] * nv + node];
-}
-
-template <typename T, int TX, int TY, bool DIA, bool RFN>
+template <typename T, int TX, int TY, bool DIA, bool RFN, bool MASK>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_off, int nvb)
 {
     constexpr int NPL = DIA ? 36 : 16;            // parameters per cell kept in LDS
     constexpr int NC = TX * TY;                   // cells per slab
-    __shared__ T spar[2][NC * NPL];
-    __shared__ int4 sinfo[2][NC];                 // fluid flag, upwind neighbour codes x, y, z
+    constexpr int NM = NC * NPL;                  // parameter words per slab
+    constexpr int MPT = (NM + 127) / 128;         // words per thread for the smallest block (128)
+    __shared__ T spar[2][NM];
+    __shared__ int sflag[2][NC];
 
     const Geo &g = A.g;
     const int b = blockIdx.x;
     const int vb = b % nvb;
     const int o = (b / nvb) & 7;
     const int t = b / (nvb * 8);
-    const int l = vb * blockDim.x + threadIdx.x;
+    const int bs = blockDim.x;
+    const int l = vb * bs + threadIdx.x;
     const bool active = l < g.osize[o];           // inactive threads still join loads and barriers
     const int packed = A.tiles[plane_off + t];
     const int tx = packed & 0x3ff, ty = (packed >> 10) & 0x3ff, tz = (packed >> 20) & 0x3ff;
@@ -131,77 +122,94 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_of
     T *f0 = (T *)A.f0;
     T *f1 = (T *)A.f1;
     const T *par = (const T *)A.par;
+    const T *fsc = (const T *)A.fscale;
     const T *mb = (const T *)A.mb;
     const T *mb1 = (const T *)A.mb1;
 
-    auto cell_at = [&](int kx, int ky, int kz) -> int {   // -1 outside the domain
-        const int ii = i0 + kx, jj = j0 + ky, kk = k0 + kz;
-        if (ii >= nx || jj >= ny || kk >= nz) return -1;
+    // physical cell of tile-frame position, clamped into the domain (positions
+    // outside are never computed; clamping keeps every speculative load valid)
+    auto cell_of = [&](int kx, int ky, int kz) -> int {
+        int ii = min(i0 + kx, nx - 1), jj = min(j0 + ky, ny - 1), kk = min(k0 + kz, nz - 1);
         const int i = sx ? nx - 1 - ii : ii, j = sy ? ny - 1 - jj : jj, k = sz ? nz - 1 - kk : kk;
         return i + nx * (j + ny * k);
     };
-    // cooperative load of one slab's per-cell data into LDS buffer buf
-    auto load_meta = [&](int kz, int buf) {
-        for (int e = threadIdx.x; e < NC; e += blockDim.x) {
-            const int c = cell_at(e % TX, e / TX, kz);
-            int4 inf = make_int4(0, -1, -1, -1);
-            if (c >= 0 && A.cflag[c]) {
-                const int *nbc = A.nbr + (size_t)c * 6;
-                inf = make_int4(1, nbc[dxu], nbc[dyu], nbc[dzu]);
-            }
-            sinfo[buf][e] = inf;
-        }
-        for (int e = threadIdx.x; e < NC * NPL; e += blockDim.x) {
-            const int cc = e / NPL, k = e % NPL;
-            const int c = cell_at(cc % TX, cc / TX, kz);
-            spar[buf][e] = (c >= 0 && k < NPAR) ? par[(size_t)c * NPAR + k] : T(0);
+    auto inside = [&](int kx, int ky, int kz) -> bool { return i0 + kx < nx && j0 + ky < ny && k0 + kz < nz; };
+    // Value entering cell c through its upwind face d: the neighbour's f^{n+1/2}
+    // (final: the upwind tile ran earlier, the VDF is updated in place) or the
+    // boundary value rho_b M_b(xi) of the face.  All loads are independent and
+    // unconditional, so they can be issued a slab ahead.
+    auto inflow = [&](int c, int kx, int ky, int kz, int d, T &v0, T &v1) {
+        const int a = d >> 1;
+        const int ii = i0 + kx, jj = j0 + ky, kk = k0 + kz;   // tile frame; upwind = one step back
+        const bool outside = (a == 0 ? ii : (a == 1 ? jj : kk)) == 0;
+        const int step = a == 0 ? 1 : (a == 1 ? nx : nx * ny);
+        const int nb = outside ? c : ((d & 1) ? c + step : c - step);
+        const T fv0 = f0[(size_t)nb * nv + node];
+        const T sc = fsc[(size_t)c * 6 + d];
+        const int bcs = outside ? d : 6;
+        const T m0 = mb[(size_t)bcs * nv + node];
+        bool wall = outside;
+        if (MASK) wall = wall || !A.cflag[nb];
+        v0 = wall ? sc * m0 : fv0;
+        if (DIA) {
+            const T fv1 = f1[(size_t)nb * nv + node];
+            const T m1 = mb1[(size_t)bcs * nv + node];
+            v1 = wall ? sc * m1 : fv1;
         }
     };
-    // inflow of the tile's x (rows) and y (columns) faces for slab kz
-    auto load_xy = [&](int kz, T *xin0, T *xin1, T *yin0, T *yin1) {
+    // boundary value of face d of cell c when the in-tile upwind cell is solid
+    auto solid_face = [&](int c, int d, T &v0, T &v1) {
+        const T sc = fsc[(size_t)c * 6 + d];
+        v0 = sc * mb[(size_t)6 * nv + node];
+        if (DIA) v1 = sc * mb1[(size_t)6 * nv + node];
+    };
+
+    T mreg[MPT];
+    int freg = 0;
+    auto issue_meta = [&](int kz) {
 #pragma unroll
-        for (int ky = 0; ky < TY; ++ky) {
-            xin0[ky] = T(0);
-            if (DIA) xin1[ky] = T(0);
-            const int c = cell_at(0, ky, kz);
-            if (active && c >= 0 && A.cflag[c]) {
-                const int nb = A.nbr[(size_t)c * 6 + dxu];
-                xin0[ky] = inflow<T>(A, f0, mb, nb, node);
-                if (DIA) xin1[ky] = inflow<T>(A, f1, mb1, nb, node);
-            }
+        for (int r = 0; r < MPT; ++r) {
+            const int e = min((int)threadIdx.x + r * bs, NM - 1);
+            const int cc = e / NPL, k = e % NPL;
+            const int c = cell_of(cc % TX, cc / TX, kz);
+            mreg[r] = par[(size_t)c * NPAR + (k < NPAR ? k : 0)];
         }
+        // flag word of a cell: bit 0 fluid and inside the domain, bit 1 its in-tile
+        // z-upwind cell is solid (carried with this slab so that compute never
+        // reads the other buffer, which the next slab's data may be overwriting)
+        const int e = min((int)threadIdx.x, NC - 1);
+        const int c = cell_of(e % TX, e / TX, kz);
+        const int cz = cell_of(e % TX, e / TX, kz > 0 ? kz - 1 : 0);
+        const int fl = (MASK ? A.cflag[c] : 1) && inside(e % TX, e / TX, kz);
+        const int zs = (MASK && kz > 0) ? !A.cflag[cz] : 0;
+        freg = fl | (zs << 1);
+    };
+    auto store_meta = [&](int buf) {
 #pragma unroll
-        for (int kx = 0; kx < TX; ++kx) {
-            yin0[kx] = T(0);
-            if (DIA) yin1[kx] = T(0);
-            const int c = cell_at(kx, 0, kz);
-            if (active && c >= 0 && A.cflag[c]) {
-                const int nb = A.nbr[(size_t)c * 6 + dyu];
-                yin0[kx] = inflow<T>(A, f0, mb, nb, node);
-                if (DIA) yin1[kx] = inflow<T>(A, f1, mb1, nb, node);
-            }
+        for (int r = 0; r < MPT; ++r) {
+            const int e = threadIdx.x + r * bs;
+            if (e < NM) spar[buf][e] = mreg[r];
         }
+        if ((int)threadIdx.x < NC) sflag[buf][threadIdx.x] = freg;
     };
 
     T pl0[TY][TX], pl1[TY][TX];                 // z-upwind plane, then the slab just computed
     T xin0[TY], xin1[TY], yin0[TX], yin1[TX];   // inflow faces of the current slab
     T xnx0[TY], xnx1[TY], ynx0[TX], ynx1[TX];   // ... and of the next slab
+    auto issue_xy = [&](int kz, T *x0, T *x1, T *y0, T *y1) {
+#pragma unroll
+        for (int ky = 0; ky < TY; ++ky) inflow(cell_of(0, ky, kz), 0, ky, kz, dxu, x0[ky], x1[ky]);
+#pragma unroll
+        for (int kx = 0; kx < TX; ++kx) inflow(cell_of(kx, 0, kz), kx, 0, kz, dyu, y0[kx], y1[kx]);
+    };
 
-    load_meta(0, 0);
+    issue_meta(0);
+    store_meta(0);
 #pragma unroll
     for (int ky = 0; ky < TY; ++ky)
 #pragma unroll
-        for (int kx = 0; kx < TX; ++kx) {
-            pl0[ky][kx] = T(0);
-            pl1[ky][kx] = T(0);
-            const int c = cell_at(kx, ky, 0);
-            if (active && c >= 0 && A.cflag[c]) {
-                const int nb = A.nbr[(size_t)c * 6 + dzu];
-                pl0[ky][kx] = inflow<T>(A, f0, mb, nb, node);
-                if (DIA) pl1[ky][kx] = inflow<T>(A, f1, mb1, nb, node);
-            }
-        }
-    load_xy(0, xin0, xin1, yin0, yin1);
+        for (int kx = 0; kx < TX; ++kx) inflow(cell_of(kx, ky, 0), kx, ky, 0, dzu, pl0[ky][kx], pl1[ky][kx]);
+    issue_xy(0, xin0, xin1, yin0, yin1);
     __syncthreads();
 
     for (int kz = 0; kz < TZ; ++kz) {
@@ -209,8 +217,8 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_of
         const int buf = kz & 1;
         const bool more = kz + 1 < TZ && k0 + kz + 1 < nz;
         if (more) {
-            load_meta(kz + 1, buf ^ 1);
-            load_xy(kz + 1, xnx0, xnx1, ynx0, ynx1);
+            issue_meta(kz + 1);
+            issue_xy(kz + 1, xnx0, xnx1, ynx0, ynx1);
         }
         if (active) {
 #pragma unroll
@@ -218,12 +226,9 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_of
 #pragma unroll
                 for (int kx = 0; kx < TX; ++kx) {
                     const int e = ky * TX + kx;
-                    const int4 inf = sinfo[buf][e];
-                    if (!__builtin_amdgcn_readfirstlane(inf.x)) continue;
-                    const int cell = cell_at(kx, ky, kz);
-                    const int nbx = __builtin_amdgcn_readfirstlane(inf.y);
-                    const int nby = __builtin_amdgcn_readfirstlane(inf.z);
-                    const int nbz = __builtin_amdgcn_readfirstlane(inf.w);
+                    const int flag = __builtin_amdgcn_readfirstlane(sflag[buf][e]);
+                    if (!(flag & 1)) continue;
+                    const int cell = cell_of(kx, ky, kz);
                     const T *p = &spar[buf][e * NPL];
                     const T cx = xix - p[0], cy = xiy - p[1], cz = xiz - p[2];
                     T gt0, gt1 = T(0), invtau;
@@ -241,19 +246,18 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_of
                         if (DIA) num1 += idt * f1[at];
                     }
                     T F0, F1 = T(0);
-                    // x upwind: the row's inflow, the cell just computed, or a solid neighbour's wall
                     if (kx == 0) { F0 = xin0[ky]; if (DIA) F1 = xin1[ky]; }
-                    else if (nbx >= 0) { F0 = pl0[ky][kx - 1]; if (DIA) F1 = pl1[ky][kx - 1]; }
-                    else { F0 = inflow<T>(A, f0, mb, nbx, node); if (DIA) F1 = inflow<T>(A, f1, mb1, nbx, node); }
+                    else if (MASK && !(__builtin_amdgcn_readfirstlane(sflag[buf][e - 1]) & 1)) solid_face(cell, dxu, F0, F1);
+                    else { F0 = pl0[ky][kx - 1]; if (DIA) F1 = pl1[ky][kx - 1]; }
                     num0 += ax * F0;
                     if (DIA) num1 += ax * F1;
                     if (ky == 0) { F0 = yin0[kx]; if (DIA) F1 = yin1[kx]; }
-                    else if (nby >= 0) { F0 = pl0[ky - 1][kx]; if (DIA) F1 = pl1[ky - 1][kx]; }
-                    else { F0 = inflow<T>(A, f0, mb, nby, node); if (DIA) F1 = inflow<T>(A, f1, mb1, nby, node); }
+                    else if (MASK && !(__builtin_amdgcn_readfirstlane(sflag[buf][e - TX]) & 1)) solid_face(cell, dyu, F0, F1);
+                    else { F0 = pl0[ky - 1][kx]; if (DIA) F1 = pl1[ky - 1][kx]; }
                     num0 += ay * F0;
                     if (DIA) num1 += ay * F1;
-                    if (kz == 0 || nbz >= 0) { F0 = pl0[ky][kx]; if (DIA) F1 = pl1[ky][kx]; }
-                    else { F0 = inflow<T>(A, f0, mb, nbz, node); if (DIA) F1 = inflow<T>(A, f1, mb1, nbz, node); }
+                    if (MASK && (flag & 2)) solid_face(cell, dzu, F0, F1);
+                    else { F0 = pl0[ky][kx]; if (DIA) F1 = pl1[ky][kx]; }
                     num0 += az * F0;
                     if (DIA) num1 += az * F1;
                     const T den = den0 + invtau;
@@ -268,6 +272,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_of
                 }
             }
         }
+        if (more) store_meta(buf ^ 1);
         __syncthreads();
         if (more) {
 #pragma unroll
@@ -290,17 +295,19 @@ static void sweep_plane(const SweepArgs &a, bool dia, bool rfn, int tz, int off,
                         hipStream_t s)
 {
     constexpr bool kDia = TX * TY <= 32;   // two register planes only for the small slabs
-    const size_t shm = 0;
     dim3 grid((unsigned)(ntile * 8 * nvb));
+    const bool mask = a.g.nfluid != a.g.ncell;
+#define GSIS_SWEEP(D, R, M) hipLaunchKernelGGL((k_sweep<T, TX, TY, D, R, M>), grid, dim3(bs), 0, s, a, tz, off, nvb)
     if (dia) {
         if constexpr (kDia) {
-            if (rfn) hipLaunchKernelGGL((k_sweep<T, TX, TY, true, true>), grid, dim3(bs), shm, s, a, tz, off, nvb);
-            else hipLaunchKernelGGL((k_sweep<T, TX, TY, true, false>), grid, dim3(bs), shm, s, a, tz, off, nvb);
+            if (rfn) { if (mask) GSIS_SWEEP(true, true, true); else GSIS_SWEEP(true, true, false); }
+            else { if (mask) GSIS_SWEEP(true, false, true); else GSIS_SWEEP(true, false, false); }
         }
     } else {
-        if (rfn) hipLaunchKernelGGL((k_sweep<T, TX, TY, false, true>), grid, dim3(bs), shm, s, a, tz, off, nvb);
-        else hipLaunchKernelGGL((k_sweep<T, TX, TY, false, false>), grid, dim3(bs), shm, s, a, tz, off, nvb);
+        if (rfn) { if (mask) GSIS_SWEEP(false, true, true); else GSIS_SWEEP(false, true, false); }
+        else { if (mask) GSIS_SWEEP(false, false, true); else GSIS_SWEEP(false, false, false); }
     }
+#undef GSIS_SWEEP
 }
 
 bool sweep_shape_supported(bool fp32, bool dia, int tx, int ty)
@@ -336,10 +343,8 @@ hipError_t launch_sweep(const Geo &g, const Dev &d, bool fp32, int tx, int ty, i
     a.f1 = d.f1;
     a.par = fp32 ? (const void *)d.parf : (const void *)d.par;
     a.cflag = d.cflag;
-    a.nbr = d.nbr;
-    a.face_bc = d.face_bc;
     a.tiles = d.tiles;
-    a.fscale = fp32 ? (const void *)d.fscalef : (const void *)d.fscale;
+    a.fscale = fp32 ? (const void *)d.cfs32 : (const void *)d.cfs64;
     a.mb = fp32 ? (const void *)d.mb32 : (const void *)d.mb64;
     a.mb1 = fp32 ? (const void *)d.mb1_32 : (const void *)d.mb1_64;
     for (int ax = 0; ax < 3; ++ax) a.xi[ax] = fp32 ? (const void *)d.xi32[ax] : (const void *)d.xi64[ax];
