@@ -38,6 +38,7 @@ struct Geo {
     int nface, nfluid;
     double kt, kr, gam, Cd;   // macroscopic transport constants
     double hmin;
+    int fp32;      // VDF precision
 };
 
 struct BcInfo {

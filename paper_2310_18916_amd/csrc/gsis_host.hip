@@ -399,6 +399,7 @@ gsis_status gsis_create(gsis_ctx **out, const gsis_config *cfg)
         x->bc.T[b] = 1.0;
         x->bc.rho[b] = 1.0;
     }
+    g.fp32 = x->fp32 ? 1 : 0;
     default_tile(x);
     *out = x;
     return GSIS_OK;

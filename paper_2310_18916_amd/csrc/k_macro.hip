@@ -106,53 +106,58 @@ __device__ __forceinline__ void face_flux(const Geo &g, const double *L, const d
 
 // Outgoing half-range psi-moments of M(rho, u, Tt) through face dir (sum over
 // nodes with xi.n > 0 of w (xi.n) psi M), separable on the tensor grid, and
-// the face flux of the equilibrium state with the face's boundary rule.
-__device__ void equilibrium_face_flux(const Geo &g, const BcInfo &bc, const Dev &d, const double *P, int dir, int b,
-                                      double F[6])
+// the face flux of the equilibrium state with the face's boundary rule.  One
+// wave per face: lanes take the nodes of each axis, wave sums combine them
+// (every lane ends with the result).
+__device__ void wave_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev &d, const double *P, int dir, int b,
+                                      int lane, double F[6])
 {
-    int a = dir / 2;
-    double sg = (dir & 1) ? 1.0 : -1.0;
-    double T = P[4];
-    double H[4] = {0, 0, 0, 0};   // half sums along a, powers 0..3
-    double Fo[3][3];              // full sums along the other axes, powers 0..2
-    for (int ax = 0; ax < 3; ++ax) {
-        const double *xi = d.xi64[ax], *w = d.w64[ax];
-        double u = P[1 + ax];
-        if (ax == a) {
-            for (int k = 0; k < g.n1[ax]; ++k) {
-                double x = xi[k];
-                if (!(sg * x > 0.0)) continue;
-                double c = x - u;
-                double e = w[k] * exp(-c * c / T);
-                H[1] += e * x;
-                H[2] += e * x * x;
-                H[3] += e * x * x * x;
-            }
-        } else {
-            double s0 = 0, s1 = 0, s2 = 0;
-            for (int k = 0; k < g.n1[ax]; ++k) {
-                double x = xi[k], c = x - u;
-                double e = w[k] * exp(-c * c / T);
-                s0 += e;
-                s1 += e * x;
-                s2 += e * x * x;
-            }
-            Fo[ax][0] = s0; Fo[ax][1] = s1; Fo[ax][2] = s2;
+    const int a = dir / 2;
+    const double sg = (dir & 1) ? 1.0 : -1.0;
+    const double T = P[4];
+    const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+    double H1 = 0, H2 = 0, H3 = 0;
+    for (int k = lane; k < g.n1[a]; k += 64) {
+        const double x = d.xi64[a][k];
+        if (!(sg * x > 0.0)) continue;
+        const double c = x - P[1 + a];
+        const double e = d.w64[a][k] * exp(-c * c / T);
+        H1 += e * x;
+        H2 += e * x * x;
+        H3 += e * x * x * x;
+    }
+    double S[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    const int ax2[2] = {b1, b2};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int ax = ax2[q];
+        for (int k = lane; k < g.n1[ax]; k += 64) {
+            const double x = d.xi64[ax][k], c = x - P[1 + ax];
+            const double e = d.w64[ax][k] * exp(-c * c / T);
+            S[q][0] += e;
+            S[q][1] += e * x;
+            S[q][2] += e * x * x;
         }
     }
-    int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
-    double K = P[0] * pow(PI * T, -1.5) * sg;
+    H1 = wave_sum(H1);
+    H2 = wave_sum(H2);
+    H3 = wave_sum(H3);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int p = 0; p < 3; ++p) S[q][p] = wave_sum(S[q][p]);
+    const double K = P[0] * pow(PI * T, -1.5) * sg;
     double out[6];
-    out[0] = K * H[1] * Fo[b1][0] * Fo[b2][0];
-    out[1 + a] = K * H[2] * Fo[b1][0] * Fo[b2][0];
-    out[1 + b1] = K * H[1] * Fo[b1][1] * Fo[b2][0];
-    out[1 + b2] = K * H[1] * Fo[b1][0] * Fo[b2][1];
-    double h1 = g.species == 1 ? 0.5 * g.dr * P[5] : 0.0;
-    out[4] = K * (H[3] * Fo[b1][0] * Fo[b2][0] + H[1] * Fo[b1][2] * Fo[b2][0] + H[1] * Fo[b1][0] * Fo[b2][2])
-             + h1 * out[0];
+    out[0] = K * H1 * S[0][0] * S[1][0];
+    out[1 + a] = K * H2 * S[0][0] * S[1][0];
+    out[1 + b1] = K * H1 * S[0][1] * S[1][0];
+    out[1 + b2] = K * H1 * S[0][0] * S[1][1];
+    const double h1 = g.species == 1 ? 0.5 * g.dr * P[5] : 0.0;
+    out[4] = K * (H3 * S[0][0] * S[1][0] + H1 * S[0][2] * S[1][0] + H1 * S[0][0] * S[1][2]) + h1 * out[0];
     out[5] = h1 * out[0];
     const double *in = d.inpsi + (b * 6 + dir) * 6;
-    double sc = bc.kind[b] == 1 ? bc.rho[b] : out[0] / (-in[0]);
+    const double sc = bc.kind[b] == 1 ? bc.rho[b] : out[0] / (-in[0]);
+#pragma unroll
     for (int k = 0; k < 6; ++k) F[k] = out[k] + sc * in[k];
 }
 
@@ -180,10 +185,8 @@ __global__ void k_mac_init(Geo g, Dev d)
     prim_from_W(g, W, d.P + (size_t)cell * NP);
 }
 
-__global__ void k_mac_grad(Geo g, Dev d)
+__device__ void cell_grad(const Geo &g, const Dev &d, int cell)
 {
-    int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= g.ncell || !d.cflag[cell]) return;
     const int *nb = d.nbr + (size_t)cell * 6;
     const double *Pc = d.P + (size_t)cell * NP;
     double *G = d.grad + (size_t)cell * 9;
@@ -198,6 +201,31 @@ __global__ void k_mac_grad(Geo g, Dev d)
             else v = 0.0;
             G[b * 3 + c] = v;
         }
+    }
+}
+
+// Blocks [0, ngrad): central gradients of u, one cell per thread.  Blocks
+// [ngrad, ...): boundary faces, one wave per face: F_b = fixed part + F_eq(W^m)
+// and its Gamma (skipped when with_faces is 0).
+__global__ __launch_bounds__(256) void k_mac_grad(Geo g, BcInfo bc, Dev d, int ngrad, int with_faces)
+{
+    if ((int)blockIdx.x < ngrad) {
+        int cell = blockIdx.x * blockDim.x + threadIdx.x;
+        if (cell < g.ncell && d.cflag[cell]) cell_grad(g, d, cell);
+        return;
+    }
+    if (!with_faces) return;
+    const int f = ((int)blockIdx.x - ngrad) * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (f >= g.nface) return;   // whole wave: f is wave-uniform
+    const int cell = d.face_cell[f], dir = d.face_dir[f];
+    const double *P = d.P + (size_t)cell * NP;
+    double Fe[6];
+    wave_equilibrium_flux(g, bc, d, P, dir, d.face_bc[f], lane, Fe);
+    if (lane == 0) {
+        for (int k = 0; k < 6; ++k) d.Fb[(size_t)f * 6 + k] = d.fbfix[(size_t)f * 6 + k] + Fe[k];
+        const int a = dir / 2;
+        d.Gb[f] = fabs(P[1 + a]) + P[8] + g.Cd * pow(P[4], g.omega) / (g.delta * P[0] * g.h[a]);
     }
 }
 
@@ -226,14 +254,16 @@ __global__ void k_mac_hot(Geo g, Dev d)
 
 // Fixed part of each boundary face flux, F_kin(f^{n+1/2}) - F_eq(W^{n+1/2}), and
 // the face flux of the first inner iteration, fixed part + F_eq(W^{n+1/2}).
-__global__ void k_mac_fbfix(Geo g, BcInfo bc, Dev d)
+// One wave per face.
+__global__ __launch_bounds__(256) void k_mac_fbfix(Geo g, BcInfo bc, Dev d)
 {
-    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    const int f = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (f >= g.nface) return;
-    int cell = d.face_cell[f], dir = d.face_dir[f], b = d.face_bc[f];
-    int a = dir / 2;
-    int neg = (dir & 1) ? 0 : 1;
-    double sg = neg ? -1.0 : 1.0;
+    const int cell = d.face_cell[f], dir = d.face_dir[f], b = d.face_bc[f];
+    const int a = dir / 2;
+    const int neg = (dir & 1) ? 0 : 1;
+    const double sg = neg ? -1.0 : 1.0;
     double out[6] = {0, 0, 0, 0, 0, 0};
     const int m2row[3][3] = {{4, 7, 8}, {7, 5, 9}, {8, 9, 6}};
     for (int o = 0; o < 8; ++o) {
@@ -246,16 +276,18 @@ __global__ void k_mac_fbfix(Geo g, BcInfo bc, Dev d)
     }
     for (int k = 0; k < 6; ++k) out[k] *= sg;
     const double *in = d.inpsi + (b * 6 + dir) * 6;
-    double sc = bc.kind[b] == 1 ? bc.rho[b] : out[0] / (-in[0]);
+    const double sc = bc.kind[b] == 1 ? bc.rho[b] : out[0] / (-in[0]);
     const double *P = d.P + (size_t)cell * NP;
     double Fe[6];
-    equilibrium_face_flux(g, bc, d, P, dir, b, Fe);
-    for (int k = 0; k < 6; ++k) {
-        double fix = out[k] + sc * in[k] - Fe[k];
-        d.fbfix[(size_t)f * 6 + k] = fix;
-        d.Fb[(size_t)f * 6 + k] = fix + Fe[k];
+    wave_equilibrium_flux(g, bc, d, P, dir, b, lane, Fe);
+    if (lane == 0) {
+        for (int k = 0; k < 6; ++k) {
+            const double fix = out[k] + sc * in[k] - Fe[k];
+            d.fbfix[(size_t)f * 6 + k] = fix;
+            d.Fb[(size_t)f * 6 + k] = fix + Fe[k];
+        }
+        d.Gb[f] = fabs(P[1 + a]) + P[8] + g.Cd * pow(P[4], g.omega) / (g.delta * P[0] * g.h[a]);
     }
-    d.Gb[f] = fabs(P[1 + a]) + P[8] + g.Cd * pow(P[4], g.omega) / (g.delta * P[0] * g.h[a]);
 }
 
 // Residual and diagonal of every cell; D* = max D_i by an atomic max on the
@@ -309,9 +341,8 @@ __global__ __launch_bounds__(128) void k_mac_res(Geo g, Dev d, int slot)
     else atomicOr(d.errflag, 2);
 }
 
-// W += R / D*, new prims, and the flux of the cell's boundary faces at the new
-// state (fixed part + F_eq(W^{m+1})) for the next iteration.
-__global__ __launch_bounds__(128) void k_mac_update(Geo g, BcInfo bc, Dev d, int slot)
+// W += R / D* and the new prims.
+__global__ __launch_bounds__(256) void k_mac_update(Geo g, Dev d, int slot)
 {
     int cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell == 0) d.dmax[slot ^ 1] = 0ull;   // the other slot was last used by the previous iteration
@@ -321,19 +352,7 @@ __global__ __launch_bounds__(128) void k_mac_update(Geo g, BcInfo bc, Dev d, int
     const double *r = d.R + (size_t)cell * 6;
     for (int k = 0; k < 5; ++k) W[k] += r[k] / Dm;
     if (g.species == 1) W[5] += r[5] / (Dm + d.Src[cell]);
-    double *P = d.P + (size_t)cell * NP;
-    prim_from_W(g, W, P);
-    const int *nb = d.nbr + (size_t)cell * 6;
-    for (int dir = 0; dir < 6; ++dir) {
-        int n = nb[dir];
-        if (n >= 0) continue;
-        int f = -n - 1;
-        double Fe[6];
-        equilibrium_face_flux(g, bc, d, P, dir, d.face_bc[f], Fe);
-        for (int k = 0; k < 6; ++k) d.Fb[(size_t)f * 6 + k] = d.fbfix[(size_t)f * 6 + k] + Fe[k];
-        int a = dir / 2;
-        d.Gb[f] = fabs(P[1 + a]) + P[8] + g.Cd * pow(P[4], g.omega) / (g.delta * P[0] * g.h[a]);
-    }
+    prim_from_W(g, W, d.P + (size_t)cell * NP);
 }
 
 __global__ void k_mac_reset(Dev d)
@@ -356,17 +375,19 @@ __global__ void k_mac_final(Geo g, Dev d)
 hipError_t launch_gsis_macro(const Geo &g, const BcInfo &bc, const Dev &d, int iters, hipStream_t s)
 {
     dim3 blk(128), grd((g.ncell + 127) / 128);
+    const int ngrad = (g.ncell + 255) / 256;
+    const int nfb = (g.nface + 3) / 4;   // 4 faces (waves) per 256-thread block
     hipLaunchKernelGGL(k_mac_reset, dim3(1), dim3(64), 0, s, d);
     hipLaunchKernelGGL(k_mac_init, grd, blk, 0, s, g, d);
-    hipLaunchKernelGGL(k_mac_grad, grd, blk, 0, s, g, d);
+    hipLaunchKernelGGL(k_mac_grad, dim3(ngrad), dim3(256), 0, s, g, bc, d, ngrad, 0);
     hipLaunchKernelGGL(k_mac_hot, grd, blk, 0, s, g, d);
-    if (g.nface > 0) hipLaunchKernelGGL(k_mac_fbfix, dim3((g.nface + 127) / 128), blk, 0, s, g, bc, d);
+    if (g.nface > 0) hipLaunchKernelGGL(k_mac_fbfix, dim3(nfb), dim3(256), 0, s, g, bc, d);
     for (int it = 0; it < iters; ++it) {
         int slot = it & 1;
-        if (it > 0) hipLaunchKernelGGL(k_mac_grad, grd, blk, 0, s, g, d);
+        if (it > 0) hipLaunchKernelGGL(k_mac_grad, dim3(ngrad + nfb), dim3(256), 0, s, g, bc, d, ngrad, 1);
         if (g.species == 1) hipLaunchKernelGGL(k_mac_res<true>, grd, blk, 0, s, g, d, slot);
         else hipLaunchKernelGGL(k_mac_res<false>, grd, blk, 0, s, g, d, slot);
-        hipLaunchKernelGGL(k_mac_update, grd, blk, 0, s, g, bc, d, slot);
+        hipLaunchKernelGGL(k_mac_update, dim3(ngrad), dim3(256), 0, s, g, d, slot);
     }
     hipLaunchKernelGGL(k_mac_final, grd, blk, 0, s, g, d);
     return hipGetLastError();

@@ -30,13 +30,26 @@
 namespace gsis {
 
 template <typename T> struct Arith;
+// Division by the hardware reciprocal: one rounding more than IEEE division
+// (FP32: v_rcp_f32, about 1 ulp; FP64: v_rcp_f64 refined by two Newton steps
+// and a residual correction), the same code for every tile shape.
 template <> struct Arith<float> {
     static __device__ __forceinline__ float ex(float x) { return __expf(x); }
-    static __device__ __forceinline__ float div(float a, float b) { return __fdividef(a, b); }
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 };
 template <> struct Arith<double> {
     static __device__ __forceinline__ double ex(double x) { return exp(x); }
-    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double div(double a, double b)
+    {
+        double r = __builtin_amdgcn_rcp(b);
+        double e = fma(-b, r, 1.0);
+        r = fma(r, e, r);
+        e = fma(-b, r, 1.0);
+        r = fma(r, e, r);
+        double q = a * r;
+        double res = fma(-b, q, a);
+        return fma(r, res, q);
+    }
 };
 
 struct SweepArgs {
@@ -212,6 +225,9 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_of
     issue_xy(0, xin0, xin1, yin0, yin1);
     __syncthreads();
 
+    // per-tile strides of the octant frame: cell = slab base + kx dxs + ky dys
+    const int dxs = sx ? -1 : 1, dys = sy ? -nx : nx;
+    const unsigned lnode = (unsigned)node;
     for (int kz = 0; kz < TZ; ++kz) {
         if (k0 + kz >= nz) break;                 // uniform over the block
         const int buf = kz & 1;
@@ -220,6 +236,8 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_of
             issue_meta(kz + 1);
             issue_xy(kz + 1, xnx0, xnx1, ynx0, ynx1);
         }
+        const int kk = k0 + kz;
+        const int cbase = (sx ? nx - 1 - i0 : i0) + nx * ((sy ? ny - 1 - j0 : j0) + ny * (sz ? nz - 1 - kk : kk));
         if (active) {
 #pragma unroll
             for (int ky = 0; ky < TY; ++ky) {
@@ -227,8 +245,10 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_of
                 for (int kx = 0; kx < TX; ++kx) {
                     const int e = ky * TX + kx;
                     const int flag = __builtin_amdgcn_readfirstlane(sflag[buf][e]);
-                    if (!(flag & 1)) continue;
-                    const int cell = cell_of(kx, ky, kz);
+                    if (!(flag & 1)) continue;     // outside the domain or solid
+                    const int cell = cbase + kx * dxs + ky * dys;
+                    T *c0 = f0 + (size_t)cell * nv;   // uniform row; the lane adds its node
+                    T *c1 = DIA ? f1 + (size_t)cell * nv : nullptr;
                     const T *p = &spar[buf][e * NPL];
                     const T cx = xix - p[0], cy = xiy - p[1], cz = xiz - p[2];
                     T gt0, gt1 = T(0), invtau;
@@ -239,11 +259,10 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_of
                         gt0 = ref_mono<T>(p, cx, cy, cz);
                         invtau = p[13];
                     }
-                    const size_t at = (size_t)cell * nv + node;
                     T num0 = gt0, num1 = gt1;
                     if (RFN) {
-                        num0 += idt * f0[at];
-                        if (DIA) num1 += idt * f1[at];
+                        num0 += idt * c0[lnode];
+                        if (DIA) num1 += idt * c1[lnode];
                     }
                     T F0, F1 = T(0);
                     if (kx == 0) { F0 = xin0[ky]; if (DIA) F1 = xin1[ky]; }
@@ -262,11 +281,11 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_of
                     if (DIA) num1 += az * F1;
                     const T den = den0 + invtau;
                     const T v0 = Arith<T>::div(num0, den);
-                    f0[at] = v0;
+                    c0[lnode] = v0;
                     pl0[ky][kx] = v0;
                     if (DIA) {
                         const T v1 = Arith<T>::div(num1, den);
-                        f1[at] = v1;
+                        c1[lnode] = v1;
                         pl1[ky][kx] = v1;
                     }
                 }
