@@ -32,7 +32,32 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp32", action="store_true")
     p.add_argument("--tile", default=None, help="tx,ty,tz,block")
+    p.add_argument("--copy-calib-mib", type=int, default=0,
+                   help="after the run, copy a buffer of this many MiB three times (HBM counter calibration)")
     return p.parse_args()
+
+
+def sweep_traffic(dtype, tile, workload_name):
+    """HBM bytes per sweep pass from the committed rocprofv3 counter summary, or
+    None when that summary was taken on other kernel sources or another tile."""
+    import hashlib
+    tag = {"c2": "c2"}.get(workload_name)
+    if tag is None:
+        return None
+    path = os.path.join(ROOT, "profiles", f"{tag}_{dtype}_sweep_pmc.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and line.startswith("    "):
+            k, v = line.strip().split(":", 1)
+            kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in ("paper_2310_18916_amd/csrc/k_sweep.hip", "paper_2310_18916_amd/csrc/gsis_common.h"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if kv.get("source_sha256") != h.hexdigest() or kv.get("tile") != ",".join(map(str, tile)):
+        return None
+    return float(kv["sweep_fetch_bytes_per_pass"]) + float(kv["sweep_write_bytes_per_pass"])
 
 
 def workload(name):
@@ -73,26 +98,44 @@ def run_gpu(case, dtype, steps, warmup, macro_iters, tile):
             "tile": s.get_tile()}
 
 
-def cpu_baseline(case):
+def cpu_baseline(case, budget_s=12.0):
     """The FP64 oracle, as it stands, on a bounded sample of the workload: the same
-    velocity grid and gas on a 10^3-cell corner of the cavity, one kinetic pass."""
+    velocity grid and gas on a 16^3-cell cavity, kinetic passes repeated until about
+    budget_s seconds of CPU work have run."""
     from oracle.oracle import Oracle, build
     from paper_2310_18916_amd import inputs as I
     if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
         build()
-    n = 10
+    n = 16
     sample = I.cavity(n, case.nv[0], case.Kn, lid=case.bcs[5].u[0], vmax=case.vmax[0], omega=case.omega)
     o = Oracle(sample)
     o.init_maxwellian()
+    passes = 0
     t0 = time.perf_counter()
-    o.step(1)
-    dt = time.perf_counter() - t0
-    pts = sample.ncell * sample.nvel
+    while True:
+        o.step(1)
+        passes += 1
+        dt = time.perf_counter() - t0
+        if dt >= budget_s or passes >= 50:
+            break
+    pts = sample.ncell * sample.nvel * passes
     cores = len(os.sched_getaffinity(0))
     threads = int(os.environ.get("OMP_NUM_THREADS", cores))
     return {"value": pts / dt, "unit": "cell-updates/s", "cores": min(cores, threads), "kind": "oracle",
-            "sample": f"one FP64 kinetic pass of the oracle on {n}^3 cells x {sample.nv[0]}^3 nodes "
+            "sample": f"{passes} FP64 kinetic passes of the oracle on a {n}^3-cell cavity x {sample.nv[0]}^3 nodes "
                       f"(same velocity grid and Kn), {dt:.2f} s"}
+
+
+def copy_calibration(mib):
+    """A plain device-to-device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"bytes_read": n * 8, "bytes_written": n * 8, "copies": 3}
 
 
 def main():
@@ -119,6 +162,7 @@ def main():
     mom_gbs = mom_bytes / (mom_ms / mom_n * 1e-3) / 1e9
     dominant = "sweep" if sweep_ms >= mom_ms else "moments"
     ach = sweep_gbs if dominant == "sweep" else mom_gbs
+    traffic = sweep_traffic(dtype, r["tile"], a.workload) if dominant == "sweep" else None
     out = {
         "metric": "phase-space cell-updates/s (cells x velocities); FP32 vs FP64 at equal accuracy",
         "value": value,
@@ -136,7 +180,9 @@ def main():
                    "Kn": case.Kn, "gsis": case.gsis, "macro_iters": macro if case.gsis else 0,
                    "step": "kinetic pass + gsis_correct + residual" if case.gsis else "kinetic pass + residual"},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": dominant},
+                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant,
+                     "per": "one sweep pass (all hyperplane launches)",
+                     "algorithmic_bytes": sweep_bytes if dominant == "sweep" else mom_bytes},
         "phases_ms_per_step": {k: v[0] / steps for k, v in prof.items()},
         "kinetic_only_updates_per_s": pts * steps / ((prof["prep"][0] + sweep_ms + mom_ms) * 1e-3),
         "sweep_gbs": sweep_gbs,
@@ -153,6 +199,8 @@ def main():
                        "phases_ms_per_step": {k: v[0] / steps for k, v in r32["prof"].items()},
                        "autotune_top": [[list(c), round(ms, 4)] for c, ms in (r32["tune"] or [])[:6]]}
         del r32
+    if a.copy_calib_mib > 0:
+        out["copy_calibration"] = copy_calibration(a.copy_calib_mib)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)
