@@ -41,16 +41,16 @@ __device__ __forceinline__ void prim_from_W(const Geo &g, const double *W, doubl
     double Tr = g.species == 1 ? 2.0 * Er / (g.dr * rho) : Tt;
     P[0] = rho; P[1] = u0; P[2] = u1; P[3] = u2; P[4] = Tt; P[5] = Tr; P[6] = E; P[7] = Er;
     P[8] = sqrt(g.gam * Tt / 2.0);
-    P[9] = pow(Tt, g.omega) / g.delta;
-    P[10] = g.delta * rho * pow(Tt, 1.0 - g.omega);
+    const double tw = pow(Tt, g.omega);
+    P[9] = tw / g.delta;
+    P[10] = g.delta * rho * Tt / tw;
     P[11] = 0.0;
 }
 
-__device__ void nsf_face(const Geo &g, const double *L, const double *R, const double *gL, const double *gR, int a,
-                         double h, double sigN[3], double *qN, double *qrN)
+__device__ __forceinline__ void nsf_face(const Geo &g, const double *L, const double *R, const double *gL,
+                                         const double *gR, int a, double h, double mu, double sigN[3], double *qN,
+                                         double *qrN)
 {
-    double TF = 0.5 * (L[4] + R[4]);
-    double mu = pow(TF, g.omega) / g.delta;
     double G[9];
     for (int b = 0; b < 3; ++b)
         for (int c = 0; c < 3; ++c)
@@ -82,8 +82,10 @@ __device__ __forceinline__ void face_flux(const Geo &g, const double *L, const d
                                           const double *gR, int a, double h, const double *hot, double F[6],
                                           double *Gam)
 {
+    const double TF = 0.5 * (L[4] + R[4]), rF = 0.5 * (L[0] + R[0]);
+    const double tw = pow(TF, g.omega);
     double sigN[3], qN, qrN;
-    nsf_face(g, L, R, gL, gR, a, h, sigN, &qN, &qrN);
+    nsf_face(g, L, R, gL, gR, a, h, tw / g.delta, sigN, &qN, &qrN);
     double PhiL[6], WL[6], PhiR[6], WR[6];
     side(L, a, PhiL, WL);
     side(R, a, PhiR, WR);
@@ -100,28 +102,37 @@ __device__ __forceinline__ void face_flux(const Geo &g, const double *L, const d
     for (int b = 0; b < 3; ++b) F[1 + b] += 0.5 * sn[b];
     F[4] += sn[0] * uF[0] + sn[1] * uF[1] + sn[2] * uF[2] + qn + qrn;
     F[5] += qrn;
-    double TF = 0.5 * (L[4] + R[4]), rF = 0.5 * (L[0] + R[0]);
-    *Gam = smax + g.Cd * pow(TF, g.omega) / (g.delta * rF * h);
+    *Gam = smax + g.Cd * tw / (g.delta * rF * h);
 }
 
 // Outgoing half-range psi-moments of M(rho, u, Tt) through face dir (sum over
 // nodes with xi.n > 0 of w (xi.n) psi M), separable on the tensor grid, and
-// the face flux of the equilibrium state with the face's boundary rule.  One
-// wave per face: lanes take the nodes of each axis, wave sums combine them
-// (every lane ends with the result).
-__device__ void wave_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev &d, const double *P, int dir, int b,
-                                      int lane, double F[6])
+// the face flux of the equilibrium state with the face's boundary rule.  A
+// group of FG adjacent lanes evaluates one face: the lanes share the nodes of
+// each axis and a butterfly inside the group combines them, so every lane of
+// the group ends with the result.
+constexpr int FG = 8;
+
+__device__ __forceinline__ double group_sum(double v)
+{
+#pragma unroll
+    for (int m = 1; m < FG; m <<= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__device__ void group_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev &d, const double *P, int dir, int b,
+                                       int sub, double F[6])
 {
     const int a = dir / 2;
     const double sg = (dir & 1) ? 1.0 : -1.0;
-    const double T = P[4];
+    const double T = P[4], iT = 1.0 / T;
     const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
     double H1 = 0, H2 = 0, H3 = 0;
-    for (int k = lane; k < g.n1[a]; k += 64) {
+    for (int k = sub; k < g.n1[a]; k += FG) {
         const double x = d.xi64[a][k];
         if (!(sg * x > 0.0)) continue;
         const double c = x - P[1 + a];
-        const double e = d.w64[a][k] * exp(-c * c / T);
+        const double e = d.w64[a][k] * exp(-c * c * iT);
         H1 += e * x;
         H2 += e * x * x;
         H3 += e * x * x * x;
@@ -131,22 +142,23 @@ __device__ void wave_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev 
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int ax = ax2[q];
-        for (int k = lane; k < g.n1[ax]; k += 64) {
+        for (int k = sub; k < g.n1[ax]; k += FG) {
             const double x = d.xi64[ax][k], c = x - P[1 + ax];
-            const double e = d.w64[ax][k] * exp(-c * c / T);
+            const double e = d.w64[ax][k] * exp(-c * c * iT);
             S[q][0] += e;
             S[q][1] += e * x;
             S[q][2] += e * x * x;
         }
     }
-    H1 = wave_sum(H1);
-    H2 = wave_sum(H2);
-    H3 = wave_sum(H3);
+    H1 = group_sum(H1);
+    H2 = group_sum(H2);
+    H3 = group_sum(H3);
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int p = 0; p < 3; ++p) S[q][p] = wave_sum(S[q][p]);
-    const double K = P[0] * pow(PI * T, -1.5) * sg;
+        for (int p = 0; p < 3; ++p) S[q][p] = group_sum(S[q][p]);
+    const double piT = PI * T;
+    const double K = P[0] / (piT * sqrt(piT)) * sg;
     double out[6];
     out[0] = K * H1 * S[0][0] * S[1][0];
     out[1 + a] = K * H2 * S[0][0] * S[1][0];
@@ -159,6 +171,12 @@ __device__ void wave_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev 
     const double sc = bc.kind[b] == 1 ? bc.rho[b] : out[0] / (-in[0]);
 #pragma unroll
     for (int k = 0; k < 6; ++k) F[k] = out[k] + sc * in[k];
+}
+
+// Gamma of a boundary face: outward speed plus the diffusive term of the cell
+__device__ __forceinline__ double boundary_gamma(const Geo &g, const double *P, int a)
+{
+    return fabs(P[1 + a]) + P[8] + g.Cd * P[9] / (P[0] * g.h[a]);
 }
 
 // W^{n+1/2}, kinetic stress/heat flux, the old half of the correction record.
@@ -185,48 +203,43 @@ __global__ void k_mac_init(Geo g, Dev d)
     prim_from_W(g, W, d.P + (size_t)cell * NP);
 }
 
-__device__ void cell_grad(const Geo &g, const Dev &d, int cell)
+// Column a of the velocity gradient of one cell: central differences, one-sided
+// next to a non-fluid neighbour, zero with none.
+__device__ void cell_grad_col(const Geo &g, const Dev &d, int cell, int a)
 {
-    const int *nb = d.nbr + (size_t)cell * 6;
+    const int nm = d.nbr[(size_t)cell * 6 + 2 * a], np = d.nbr[(size_t)cell * 6 + 2 * a + 1];
     const double *Pc = d.P + (size_t)cell * NP;
+    const double *Pm = nm >= 0 ? d.P + (size_t)nm * NP : Pc;
+    const double *Pp = np >= 0 ? d.P + (size_t)np * NP : Pc;
+    const double h = g.h[a];
+    const double den = (nm >= 0 && np >= 0) ? 2.0 * h : h;
     double *G = d.grad + (size_t)cell * 9;
-    for (int c = 0; c < 3; ++c) {
-        int nm = nb[2 * c], np = nb[2 * c + 1];
-        double h = g.h[c];
-        for (int b = 0; b < 3; ++b) {
-            double v;
-            if (nm >= 0 && np >= 0) v = (d.P[(size_t)np * NP + 1 + b] - d.P[(size_t)nm * NP + 1 + b]) / (2.0 * h);
-            else if (np >= 0) v = (d.P[(size_t)np * NP + 1 + b] - Pc[1 + b]) / h;
-            else if (nm >= 0) v = (Pc[1 + b] - d.P[(size_t)nm * NP + 1 + b]) / h;
-            else v = 0.0;
-            G[b * 3 + c] = v;
-        }
-    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) G[b * 3 + a] = (nm < 0 && np < 0) ? 0.0 : (Pp[1 + b] - Pm[1 + b]) / den;
 }
 
-// Blocks [0, ngrad): central gradients of u, one cell per thread.  Blocks
-// [ngrad, ...): boundary faces, one wave per face: F_b = fixed part + F_eq(W^m)
-// and its Gamma (skipped when with_faces is 0).
+// Blocks [0, ngrad): central gradients of u, one (cell, axis) per thread.
+// Blocks [ngrad, ...): boundary faces, one wave per face: F_b = fixed part +
+// F_eq(W^m) and its Gamma (skipped when with_faces is 0).
 __global__ __launch_bounds__(256) void k_mac_grad(Geo g, BcInfo bc, Dev d, int ngrad, int with_faces)
 {
     if ((int)blockIdx.x < ngrad) {
-        int cell = blockIdx.x * blockDim.x + threadIdx.x;
-        if (cell < g.ncell && d.cflag[cell]) cell_grad(g, d, cell);
+        const int t = blockIdx.x * blockDim.x + threadIdx.x;
+        const int cell = t / 3, a = t - 3 * (t / 3);
+        if (cell < g.ncell && d.cflag[cell]) cell_grad_col(g, d, cell, a);
         return;
     }
     if (!with_faces) return;
-    const int f = ((int)blockIdx.x - ngrad) * (blockDim.x / 64) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (f >= g.nface) return;   // whole wave: f is wave-uniform
+    // whole groups of FG lanes share f, so the group butterflies stay inside live lanes
+    const int f = (((int)blockIdx.x - ngrad) * (int)blockDim.x + (int)threadIdx.x) / FG;
+    const int sub = threadIdx.x & (FG - 1);
+    if (f >= g.nface) return;
     const int cell = d.face_cell[f], dir = d.face_dir[f];
     const double *P = d.P + (size_t)cell * NP;
     double Fe[6];
-    wave_equilibrium_flux(g, bc, d, P, dir, d.face_bc[f], lane, Fe);
-    if (lane == 0) {
-        for (int k = 0; k < 6; ++k) d.Fb[(size_t)f * 6 + k] = d.fbfix[(size_t)f * 6 + k] + Fe[k];
-        const int a = dir / 2;
-        d.Gb[f] = fabs(P[1 + a]) + P[8] + g.Cd * pow(P[4], g.omega) / (g.delta * P[0] * g.h[a]);
-    }
+    group_equilibrium_flux(g, bc, d, P, dir, d.face_bc[f], sub, Fe);
+    if (sub < 6) d.Fb[(size_t)f * 6 + sub] = d.fbfix[(size_t)f * 6 + sub] + Fe[sub];
+    if (sub == 7) d.Gb[f] = boundary_gamma(g, P, dir / 2);
 }
 
 // HoT at the faces (cell, cell + e_a) from W^{n+1/2}.
@@ -243,8 +256,9 @@ __global__ void k_mac_hot(Geo g, Dev d)
             continue;
         }
         double sigN[3], qN, qrN;
-        nsf_face(g, d.P + (size_t)cell * NP, d.P + (size_t)nb * NP, d.grad + (size_t)cell * 9,
-                 d.grad + (size_t)nb * 9, a, g.h[a], sigN, &qN, &qrN);
+        const double *PL = d.P + (size_t)cell * NP, *PR = d.P + (size_t)nb * NP;
+        nsf_face(g, PL, PR, d.grad + (size_t)cell * 9, d.grad + (size_t)nb * 9, a, g.h[a],
+                 pow(0.5 * (PL[4] + PR[4]), g.omega) / g.delta, sigN, &qN, &qrN);
         const double *Ki = d.K + (size_t)cell * 12, *Kj = d.K + (size_t)nb * 12;
         for (int b = 0; b < 3; ++b) ho[b] = 0.5 * (Ki[col[a][b]] + Kj[col[a][b]]) - sigN[b];
         ho[3] = 0.5 * (Ki[6 + a] + Kj[6 + a]) - qN;
@@ -254,11 +268,11 @@ __global__ void k_mac_hot(Geo g, Dev d)
 
 // Fixed part of each boundary face flux, F_kin(f^{n+1/2}) - F_eq(W^{n+1/2}), and
 // the face flux of the first inner iteration, fixed part + F_eq(W^{n+1/2}).
-// One wave per face.
+// One group of FG lanes per face.
 __global__ __launch_bounds__(256) void k_mac_fbfix(Geo g, BcInfo bc, Dev d)
 {
-    const int f = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
+    const int f = (int)(blockIdx.x * blockDim.x + threadIdx.x) / FG;
+    const int sub = threadIdx.x & (FG - 1);
     if (f >= g.nface) return;
     const int cell = d.face_cell[f], dir = d.face_dir[f], b = d.face_bc[f];
     const int a = dir / 2;
@@ -279,66 +293,106 @@ __global__ __launch_bounds__(256) void k_mac_fbfix(Geo g, BcInfo bc, Dev d)
     const double sc = bc.kind[b] == 1 ? bc.rho[b] : out[0] / (-in[0]);
     const double *P = d.P + (size_t)cell * NP;
     double Fe[6];
-    wave_equilibrium_flux(g, bc, d, P, dir, b, lane, Fe);
-    if (lane == 0) {
-        for (int k = 0; k < 6; ++k) {
-            const double fix = out[k] + sc * in[k] - Fe[k];
-            d.fbfix[(size_t)f * 6 + k] = fix;
-            d.Fb[(size_t)f * 6 + k] = fix + Fe[k];
-        }
-        d.Gb[f] = fabs(P[1 + a]) + P[8] + g.Cd * pow(P[4], g.omega) / (g.delta * P[0] * g.h[a]);
+    group_equilibrium_flux(g, bc, d, P, dir, b, sub, Fe);
+    if (sub < 6) {
+        const double fix = out[sub] + sc * in[sub] - Fe[sub];
+        d.fbfix[(size_t)f * 6 + sub] = fix;
+        d.Fb[(size_t)f * 6 + sub] = fix + Fe[sub];
+    }
+    if (sub == 7) d.Gb[f] = boundary_gamma(g, P, a);
+}
+
+// Flux of face dir of a cell divided by h (outward positive), and Gamma / h.
+// dir is a compile-time constant so every index is static.
+template <int DIR, int NW>
+__device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, double out[NW], double &gam)
+{
+    constexpr int a = DIR / 2;
+    const double h = g.h[a];
+    const int n = d.nbr[(size_t)cell * 6 + DIR];
+    if (n >= 0) {
+        const int L = (DIR & 1) ? cell : n, R = (DIR & 1) ? n : cell;
+        double F[6], Gam;
+        face_flux(g, d.P + (size_t)L * NP, d.P + (size_t)R * NP, d.grad + (size_t)L * 9, d.grad + (size_t)R * 9, a, h,
+                  d.hot + (size_t)L * 15 + a * 5, F, &Gam);
+#pragma unroll
+        for (int k = 0; k < NW; ++k) out[k] = ((DIR & 1) ? F[k] : -F[k]) / h;
+        gam = Gam / h;
+    } else {
+        const int f = -n - 1;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) out[k] = d.Fb[(size_t)f * 6 + k] / h;
+        gam = d.Gb[f] / h;
     }
 }
 
 // Residual and diagonal of every cell; D* = max D_i by an atomic max on the
 // bit pattern (positive doubles order like their bits), so it is exact and
-// order independent.
+// order independent.  A block holds 64 cells and six waves; wave j evaluates
+// face j of every cell, LDS collects the six terms, and the first wave adds
+// them in face order, finishes the cells and issues one atomic for the wave's
+// largest D_i.
+constexpr int RES_CELLS = 64;
+
 template <bool DIA>
-__global__ __launch_bounds__(128) void k_mac_res(Geo g, Dev d, int slot)
+__global__ __launch_bounds__(384) void k_mac_res(Geo g, Dev d, int slot)
 {
-    int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= g.ncell || !d.cflag[cell]) return;
-    const double *Pi = d.P + (size_t)cell * NP;
-    const int *nb = d.nbr + (size_t)cell * 6;
     constexpr int NW = DIA ? 6 : 5;
-    double res[6] = {0, 0, 0, 0, 0, 0}, sumG = 0.0;
+    __shared__ double red[6][NW + 1][RES_CELLS];
+    const int lane = threadIdx.x & 63;
+    const int dir = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int cell = blockIdx.x * RES_CELLS + lane;
+    const bool live = cell < g.ncell && d.cflag[cell];
+    double out[NW], gam = 0.0;
 #pragma unroll
-    for (int dir = 0; dir < 6; ++dir) {
-        const int a = dir / 2;
-        const double h = g.h[a];
-        const int n = nb[dir];
-        double out[6], Gam;
-        if (n >= 0) {
-            const int L = (dir & 1) ? cell : n, R = (dir & 1) ? n : cell;
-            double F[6];
-            face_flux(g, d.P + (size_t)L * NP, d.P + (size_t)R * NP, d.grad + (size_t)L * 9, d.grad + (size_t)R * 9,
-                      a, h, d.hot + (size_t)L * 15 + a * 5, F, &Gam);
-#pragma unroll
-            for (int k = 0; k < 6; ++k) out[k] = (dir & 1) ? F[k] : -F[k];
-        } else {
-            const int f = -n - 1;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) out[k] = d.Fb[(size_t)f * 6 + k];
-            Gam = d.Gb[f];
+    for (int k = 0; k < NW; ++k) out[k] = 0.0;
+    if (live) {
+        switch (dir) {
+        case 0: face_term<0, NW>(g, d, cell, out, gam); break;
+        case 1: face_term<1, NW>(g, d, cell, out, gam); break;
+        case 2: face_term<2, NW>(g, d, cell, out, gam); break;
+        case 3: face_term<3, NW>(g, d, cell, out, gam); break;
+        case 4: face_term<4, NW>(g, d, cell, out, gam); break;
+        default: face_term<5, NW>(g, d, cell, out, gam); break;
         }
-#pragma unroll
-        for (int k = 0; k < NW; ++k) res[k] -= out[k] / h;
-        sumG += Gam / h;
     }
-    double invtau = g.delta * Pi[0] * pow(Pi[4], 1.0 - g.omega);
-    if (DIA) {
-        double T = (3.0 * Pi[4] + g.dr * Pi[5]) / (3.0 + g.dr);
-        res[5] += 0.5 * g.dr * Pi[0] * (T - Pi[5]) * invtau / g.Zr;
-    }
-    double umag = sqrt(Pi[1] * Pi[1] + Pi[2] * Pi[2] + Pi[3] * Pi[3]);
-    double idt = (umag + Pi[8] + g.Cd * pow(Pi[4], g.omega) / (g.delta * Pi[0] * g.hmin)) / (g.macro_cfl * g.hmin);
-    double D = idt + 0.5 * sumG;
-    double *r = d.R + (size_t)cell * 6;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) r[k] = res[k];
-    d.Src[cell] = DIA ? invtau / g.Zr : 0.0;
-    if (D > 0.0 && isfinite(D)) atomicMax(&d.dmax[slot], (unsigned long long)__double_as_longlong(D));
-    else atomicOr(d.errflag, 2);
+    for (int k = 0; k < NW; ++k) red[dir][k][lane] = out[k];
+    red[dir][NW][lane] = gam;
+    __syncthreads();
+    if (dir != 0) return;
+    double D = 0.0;
+    if (live) {
+        double res[6], sumG = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) res[k] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+#pragma unroll
+            for (int k = 0; k < NW; ++k) res[k] -= red[j][k][lane];
+            sumG += red[j][NW][lane];
+        }
+        const double *Pi = d.P + (size_t)cell * NP;
+        const double invtau = Pi[10];
+        if (DIA) {
+            double T = (3.0 * Pi[4] + g.dr * Pi[5]) / (3.0 + g.dr);
+            res[5] += 0.5 * g.dr * Pi[0] * (T - Pi[5]) * invtau / g.Zr;
+        }
+        double umag = sqrt(Pi[1] * Pi[1] + Pi[2] * Pi[2] + Pi[3] * Pi[3]);
+        double idt = (umag + Pi[8] + g.Cd * Pi[9] / (Pi[0] * g.hmin)) / (g.macro_cfl * g.hmin);
+        D = idt + 0.5 * sumG;
+        double *r = d.R + (size_t)cell * 6;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) r[k] = res[k];
+        d.Src[cell] = DIA ? invtau / g.Zr : 0.0;
+        if (!(D > 0.0 && isfinite(D))) {
+            atomicOr(d.errflag, 2);
+            D = 0.0;
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) D = fmax(D, __shfl_xor(D, m, 64));
+    if (lane == 0 && D > 0.0) atomicMax(&d.dmax[slot], (unsigned long long)__double_as_longlong(D));
 }
 
 // W += R / D* and the new prims.
@@ -375,8 +429,10 @@ __global__ void k_mac_final(Geo g, Dev d)
 hipError_t launch_gsis_macro(const Geo &g, const BcInfo &bc, const Dev &d, int iters, hipStream_t s)
 {
     dim3 blk(128), grd((g.ncell + 127) / 128);
-    const int ngrad = (g.ncell + 255) / 256;
-    const int nfb = (g.nface + 3) / 4;   // 4 faces (waves) per 256-thread block
+    const int ngrad = (3 * g.ncell + 255) / 256;   // one (cell, axis) per thread
+    const int nres = (g.ncell + RES_CELLS - 1) / RES_CELLS;
+    const int nupd = (g.ncell + 255) / 256;
+    const int nfb = (g.nface * FG + 255) / 256;   // FG lanes per boundary face
     hipLaunchKernelGGL(k_mac_reset, dim3(1), dim3(64), 0, s, d);
     hipLaunchKernelGGL(k_mac_init, grd, blk, 0, s, g, d);
     hipLaunchKernelGGL(k_mac_grad, dim3(ngrad), dim3(256), 0, s, g, bc, d, ngrad, 0);
@@ -385,9 +441,9 @@ hipError_t launch_gsis_macro(const Geo &g, const BcInfo &bc, const Dev &d, int i
     for (int it = 0; it < iters; ++it) {
         int slot = it & 1;
         if (it > 0) hipLaunchKernelGGL(k_mac_grad, dim3(ngrad + nfb), dim3(256), 0, s, g, bc, d, ngrad, 1);
-        if (g.species == 1) hipLaunchKernelGGL(k_mac_res<true>, grd, blk, 0, s, g, d, slot);
-        else hipLaunchKernelGGL(k_mac_res<false>, grd, blk, 0, s, g, d, slot);
-        hipLaunchKernelGGL(k_mac_update, dim3(ngrad), dim3(256), 0, s, g, d, slot);
+        if (g.species == 1) hipLaunchKernelGGL(k_mac_res<true>, dim3(nres), dim3(384), 0, s, g, d, slot);
+        else hipLaunchKernelGGL(k_mac_res<false>, dim3(nres), dim3(384), 0, s, g, d, slot);
+        hipLaunchKernelGGL(k_mac_update, dim3(nupd), dim3(256), 0, s, g, d, slot);
     }
     hipLaunchKernelGGL(k_mac_final, grd, blk, 0, s, g, d);
     return hipGetLastError();

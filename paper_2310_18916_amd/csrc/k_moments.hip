@@ -43,6 +43,7 @@ __global__ __launch_bounds__(512) void k_moments(Geo g, const T *__restrict__ f0
                                                  const double *__restrict__ ytab, const double *__restrict__ ztab,
                                                  double *__restrict__ mom8)
 {
+    constexpr int CH = (DIA ? 64 : 128) / (VW * (int)sizeof(T));   // vectors per chunk: 128 B of row data per lane
     const int cell = blockIdx.x;
     const int o = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -66,20 +67,31 @@ __global__ __launch_bounds__(512) void k_moments(Geo g, const T *__restrict__ f0
         const T *row0 = f0 + base + (size_t)r * nox;
         const T *row1 = DIA ? f1 + base + (size_t)r * nox : nullptr;
         double s0 = 0, s1 = 0, s2 = 0, s3 = 0, t0 = 0, t1 = 0;
-        for (int lx = 0; lx < nox; lx += VW) {
-            double v[VW], v1[VW];
-            VecLoad<T, VW>::ld(row0 + lx, v);
-            if (DIA) VecLoad<T, VW>::ld(row1 + lx, v1);
+        // a row is read in chunks of CH vectors whose loads are all issued
+        // before any is used, so the lines of a row are fetched together
+        for (int lx0 = 0; lx0 < nox; lx0 += CH * VW) {
+            double v[CH][VW], v1[CH][VW];
 #pragma unroll
-            for (int e = 0; e < VW; ++e) {
-                const double *xt = xtab + (size_t)(x0 + lx + e) * 4;
-                s0 += xt[0] * v[e];
-                s1 += xt[1] * v[e];
-                s2 += xt[2] * v[e];
-                s3 += xt[3] * v[e];
-                if (DIA) {
-                    t0 += xt[0] * v1[e];
-                    t1 += xt[1] * v1[e];
+            for (int c = 0; c < CH; ++c) {
+                if (lx0 + c * VW < nox) {
+                    VecLoad<T, VW>::ld(row0 + lx0 + c * VW, v[c]);
+                    if (DIA) VecLoad<T, VW>::ld(row1 + lx0 + c * VW, v1[c]);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                if (lx0 + c * VW >= nox) break;
+#pragma unroll
+                for (int e = 0; e < VW; ++e) {
+                    const double *xt = xtab + (size_t)(x0 + lx0 + c * VW + e) * 4;
+                    s0 += xt[0] * v[c][e];
+                    s1 += xt[1] * v[c][e];
+                    s2 += xt[2] * v[c][e];
+                    s3 += xt[3] * v[c][e];
+                    if (DIA) {
+                        t0 += xt[0] * v1[c][e];
+                        t1 += xt[1] * v1[c][e];
+                    }
                 }
             }
         }
