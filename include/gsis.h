@@ -204,6 +204,62 @@ gsis_status gsis_pass_count(const gsis_ctx *ctx, long long *passes);
 /* NUL-terminated message of the last error on ctx (static string if ctx is NULL). */
 const char *gsis_last_error(const gsis_ctx *ctx);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent problems of Algorithm 1 -- cavities of uneven cell counts,
+ * velocity grids and gas parameters -- iterated together: every kernel launch
+ * of a GSIS iteration (kinetic pass, GSIS-II correction, residual) covers all
+ * cases at once through a per-launch table of (case, block) pairs, the sweep
+ * runs one launch per global tile hyperplane across all cases, and the
+ * iteration is captured once into a HIP graph and replayed.
+ *
+ * The cases are contexts made with gsis_create and configured as usual (mask,
+ * boundaries) but NOT bound: the batch binds them all inside one caller-owned
+ * workspace.  They must share vdf_dtype and species and use inv_dt = 0
+ * (source iteration).  The batch borrows the contexts: destroy it before
+ * them, and do not bind them elsewhere.  Once bound, each context also works
+ * on its own (gsis_moments, gsis_get_vdf, gsis_residual, ...) on the batch's
+ * stream.  One tile shape (tx, ty, tz, block) serves every case. */
+typedef struct gsis_batch gsis_batch;
+
+/* ncases in 1..4096 distinct, unbound contexts (host array).  EINVAL if they
+ * differ in precision or gas, or have inv_dt != 0. */
+gsis_status gsis_batch_create(gsis_batch **out, gsis_ctx *const *cases, int ncases);
+gsis_status gsis_batch_destroy(gsis_batch *b);
+/* Bytes of device memory the batch needs (all cases plus launch tables and
+ * residual history). */
+gsis_status gsis_batch_workspace_size(gsis_batch *b, size_t *bytes);
+/* Carve the workspace (256-byte aligned, caller owned) into every case and
+ * upload the launch tables.  Synchronises. */
+gsis_status gsis_batch_bind_workspace(gsis_batch *b, void *device_ptr, size_t bytes);
+/* Stream of all batch work and of its contexts; graph capture needs a
+ * non-null stream. */
+gsis_status gsis_batch_set_stream(gsis_batch *b, void *hip_stream);
+/* One tile shape for every case (see gsis_set_tile); all zeros = default. */
+gsis_status gsis_batch_set_tile(gsis_batch *b, int tx, int ty, int tz, int block);
+gsis_status gsis_batch_get_tile(const gsis_batch *b, int *tile);
+/* Time the batched sweep of the next pass under every compiled tile
+ * configuration (reps timed launches after a warm-up) and keep the fastest;
+ * counts as one kinetic pass of every case.  Same output as gsis_autotune.
+ * Synchronises. */
+gsis_status gsis_batch_autotune(gsis_batch *b, int reps, int *cfg_out, double *ms_out, int max, int *count);
+/* gsis_init_maxwellian on every case; clears the residual history. */
+gsis_status gsis_batch_init_maxwellian(gsis_batch *b, double rho, const double u[3], double T, double Tr);
+/* iters GSIS iterations of every case, each: one kinetic pass,
+ * gsis_gsis_correct(inner_iters) (skipped when inner_iters == 0), and the
+ * residual of Sec. 4 against the previous iteration, recorded in the history.
+ * use_graph != 0 captures one iteration into a HIP graph (kept and reused
+ * while inner_iters and the tile shape stay the same) and replays it iters
+ * times; 0 launches the kernels directly.  Asynchronous. */
+gsis_status gsis_batch_run(gsis_batch *b, int iters, int inner_iters, int use_graph);
+/* Residual history since init: eps[it][case][3] (rho, |u|, Tt) for the last
+ * min(count, capacity) iterations, oldest first; *count = iterations returned
+ * (at most max).  Synchronises; ENOTFINITE if any case flagged a non-positive
+ * or non-finite state. */
+gsis_status gsis_batch_residuals(gsis_batch *b, double *eps, int max, int *count);
+/* Milliseconds of device time of the last gsis_batch_run (events around it). */
+gsis_status gsis_batch_last_run_ms(gsis_batch *b, double *ms);
+const char *gsis_batch_last_error(const gsis_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

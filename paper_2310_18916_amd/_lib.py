@@ -57,6 +57,19 @@ SIGNATURES = {
     "gsis_profile_read": (_I, [_P, _DP, C.POINTER(C.c_longlong), _I]),
     "gsis_pass_count": (_I, [_P, C.POINTER(C.c_longlong)]),
     "gsis_last_error": (C.c_char_p, [_P]),
+    "gsis_batch_create": (_I, [C.POINTER(_P), C.POINTER(_P), _I]),
+    "gsis_batch_destroy": (_I, [_P]),
+    "gsis_batch_workspace_size": (_I, [_P, C.POINTER(_SZ)]),
+    "gsis_batch_bind_workspace": (_I, [_P, _P, _SZ]),
+    "gsis_batch_set_stream": (_I, [_P, _P]),
+    "gsis_batch_set_tile": (_I, [_P, _I, _I, _I, _I]),
+    "gsis_batch_get_tile": (_I, [_P, C.POINTER(C.c_int)]),
+    "gsis_batch_autotune": (_I, [_P, _I, C.POINTER(C.c_int), _DP, _I, C.POINTER(C.c_int)]),
+    "gsis_batch_init_maxwellian": (_I, [_P, _D, _DP, _D, _D]),
+    "gsis_batch_run": (_I, [_P, _I, _I, _I]),
+    "gsis_batch_residuals": (_I, [_P, _DP, _I, C.POINTER(C.c_int)]),
+    "gsis_batch_last_run_ms": (_I, [_P, _DP]),
+    "gsis_batch_last_error": (C.c_char_p, [_P]),
 }
 
 _lib = None

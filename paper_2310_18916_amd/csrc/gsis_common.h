@@ -71,15 +71,63 @@ struct Dev {
     double *inpsi;     // [NBC][6][6] incoming half-range psi-moments of M(1,u_b,T_b)
     int *perm;         // [nv] internal node -> canonical node
     int *tiles;        // sweep tile list grouped by plane
+    int *plane_off;    // [nplane] first tile of each plane in tiles
     double *corr;      // [ncell][NCORR]
     double *snap;      // [ncell][NSNAP]
     double *W, *P, *grad, *K, *hot, *R, *Dc, *Src, *fbfix, *Fb, *Gb;   // macroscopic solve
     double *red;       // reduction scratch
     unsigned long long *dmax;   // two slots, bit pattern of a positive double
     int *errflag;
+    // residual history of a batch (nullptr for a context on its own):
+    // hist[(iteration % hist_cap) * hist_ncase + hist_index][6], iteration = *hist_ctr
+    double *hist;
+    int *hist_ctr;
+    int hist_index, hist_ncase, hist_cap;
 };
 
+// One case as the kernels of a GSIS iteration see it, resident in device
+// memory, so that one launch can cover many independent cases.
+struct Case {
+    Geo g;
+    BcInfo bc;
+    Dev d;
+    int tz;    // sweep tile depth
+    int nvb;   // sweep blocks per octant (node runs of one block size)
+};
+
+// The blocks of a launch: map[b] = (case, block within that case), or, with
+// map == nullptr, every block belongs to the first case of the table.
+struct Span {
+    const Case *cases;
+    const int2 *map;
+};
+
+// Kernels take the span as two arguments.  The case table is read-only while
+// kernels run, so it is read through the constant address space: its fields
+// load through the scalar unit and, like kernel arguments, may be reloaded
+// instead of being held in registers.
+#define GSIS_SPAN_ARGS const gsis::Case *__restrict__ span_cases, const int2 *__restrict__ span_map
+#define GSIS_SPAN(sp) (sp).cases, (sp).map
+#define GSIS_CONST_AS __attribute__((address_space(4)))
+// Buffers of a case are global memory; hot kernels keep their pointers in the
+// global address space so that accesses use scalar base + vector offset.
+#define GSIS_GLOBAL_AS __attribute__((address_space(1)))
+template <class T> using gptr = GSIS_GLOBAL_AS T *;
+
 // ------------------------------------------------------------ device helpers
+// (case, block within the case) of the calling block; uniform over the block
+__device__ __forceinline__ const Case &case_of(const Case *cases, const int2 *map, int &blk)
+{
+    int ci = 0;
+    blk = (int)blockIdx.x;
+    if (map) {
+        const GSIS_CONST_AS int *m = (const GSIS_CONST_AS int *)(map + blockIdx.x);
+        ci = m[0];
+        blk = m[1];
+    }
+    return (const Case &)*(const GSIS_CONST_AS Case *)(cases + ci);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -23,9 +23,11 @@ struct gsis_ctx {
     std::vector<int> cflag, nbr, face_cell, face_dir, face_bc, perm;
     std::vector<double> xi[3], w[3];
     int tx = 0, ty = 0, tz = 0, bs = 0;
-    std::vector<int> tiles, plane_off, plane_cnt;
+    std::vector<int> tiles, plane_off, plane_cnt, npblk;
     int vw = 1;
     Dev d;
+    Case hcase;              // host copy of the device-resident case record
+    Case *dcase = nullptr;   // in the workspace
     char *ws = nullptr;
     size_t ws_bytes = 0;
     bool bound = false, inited = false, pending = false, stepped = false;
@@ -79,6 +81,13 @@ void default_tile(gsis_ctx *c)
     else { c->tx = 4; c->ty = 4; c->tz = 4; c->bs = 128; }
 }
 
+int sweep_nvb(const Geo &g, int bs)
+{
+    int omax = 0;
+    for (int o = 0; o < 8; ++o) omax = std::max(omax, g.osize[o]);
+    return (omax + bs - 1) / bs;
+}
+
 void build_tiles(gsis_ctx *c)
 {
     const Geo &g = c->g;
@@ -87,6 +96,7 @@ void build_tiles(gsis_ctx *c)
     c->tiles.clear();
     c->plane_off.assign(nplane, 0);
     c->plane_cnt.assign(nplane, 0);
+    c->npblk.assign(nplane, 0);
     for (int s = 0; s < nplane; ++s) {
         c->plane_off[s] = (int)c->tiles.size();
         for (int z = 0; z < ntz; ++z)
@@ -96,6 +106,7 @@ void build_tiles(gsis_ctx *c)
                 c->tiles.push_back(x | (y << 10) | (z << 20));
             }
         c->plane_cnt[s] = (int)c->tiles.size() - c->plane_off[s];
+        c->npblk[s] = c->plane_cnt[s] * 8 * sweep_nvb(g, c->bs);
     }
 }
 
@@ -200,6 +211,10 @@ size_t layout(gsis_ctx *c, char *base)
     carve(off, d.inpsi, (size_t)NBC * 36, base);
     carve(off, d.perm, nv, base);
     carve(off, d.tiles, n, base);
+    carve(off, d.plane_off, (size_t)g.nx + g.ny + g.nz, base);
+    Case *dc = nullptr;
+    carve(off, dc, 1, base);
+    if (base) c->dcase = dc;
     carve(off, d.corr, n * NCORR, base);
     carve(off, d.snap, n * NSNAP, base);
     carve(off, d.W, n * 6, base);
@@ -219,6 +234,45 @@ size_t layout(gsis_ctx *c, char *base)
     return align256(off);
 }
 
+// The launch target of this context alone.
+Target target_of(const gsis_ctx *c)
+{
+    Target t;
+    t.cases = c->dcase;
+    t.ncase = 1;
+    t.host = &c->hcase;
+    for (int k = 0; k < NKIND; ++k) t.nblk[k] = kind_blocks(c->g, (Kind)k);
+    t.npblk = c->npblk.data();
+    t.nplane = (int)c->npblk.size();
+    t.fp32 = c->fp32;
+    t.dia = c->g.species == GSIS_DIATOMIC;
+    t.mask = c->g.nfluid != c->g.ncell;
+    t.rfn = c->g.inv_dt != 0.0;
+    t.vw = c->vw;
+    t.tx = c->tx;
+    t.ty = c->ty;
+    t.bs = c->bs;
+    return t;
+}
+
+// Tile lists, plane offsets and the case record to the device (stream-ordered
+// with earlier work: the host waits for the stream first).
+hipError_t upload_tiles(gsis_ctx *c)
+{
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess && !c->tiles.empty())
+        e = hipMemcpy(c->d.tiles, c->tiles.data(), c->tiles.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !c->plane_off.empty())
+        e = hipMemcpy(c->d.plane_off, c->plane_off.data(), c->plane_off.size() * sizeof(int), hipMemcpyHostToDevice);
+    c->hcase.g = c->g;
+    c->hcase.bc = c->bc;
+    c->hcase.d = c->d;
+    c->hcase.tz = c->tz;
+    c->hcase.nvb = sweep_nvb(c->g, c->bs);
+    if (e == hipSuccess) e = hipMemcpy(c->dcase, &c->hcase, sizeof(Case), hipMemcpyHostToDevice);
+    return e;
+}
+
 gsis_status reset_flags(gsis_ctx *c)
 {
     HIPCHK(c, launch_zero_int(c->d.errflag, 4, c->stream));
@@ -228,8 +282,9 @@ gsis_status reset_flags(gsis_ctx *c)
 // moments of the stored VDF (octant sums, then central moments)
 gsis_status reduce_vdf(gsis_ctx *c)
 {
-    HIPCHK(c, launch_moments(c->g, c->d, c->fp32, c->vw, c->stream));
-    HIPCHK(c, launch_derive(c->g, c->d, c->stream));
+    const Target t = target_of(c);
+    HIPCHK(c, launch_moments(t, c->stream));
+    HIPCHK(c, launch_derive(t, c->stream));
     return GSIS_OK;
 }
 
@@ -495,7 +550,7 @@ gsis_status gsis_bind_workspace(gsis_ctx *ctx, void *device_ptr, size_t bytes)
     HIPCHK(ctx, up(d.ytab, yt.data(), yt.size() * sizeof(double)));
     HIPCHK(ctx, up(d.ztab, zt.data(), zt.size() * sizeof(double)));
     HIPCHK(ctx, up(d.perm, ctx->perm.data(), ctx->perm.size() * sizeof(int)));
-    HIPCHK(ctx, up(d.tiles, ctx->tiles.data(), ctx->tiles.size() * sizeof(int)));
+    HIPCHK(ctx, upload_tiles(ctx));
     HIPCHK(ctx, hipMemset(d.errflag, 0, 4 * sizeof(int)));
     HIPCHK(ctx, hipMemset(d.dmax, 0, 2 * sizeof(unsigned long long)));
     HIPCHK(ctx, launch_setup_tables(g, ctx->bc, d, nullptr));
@@ -523,7 +578,7 @@ gsis_status gsis_init_maxwellian(gsis_ctx *ctx, double rho, const double u[3], d
     if (st) return st;
     HIPCHK(ctx, launch_init_maxwellian(ctx->g, ctx->d, ctx->fp32, rho, u, T, Tr, ctx->stream));
     if ((st = reduce_vdf(ctx))) return st;
-    HIPCHK(ctx, launch_snapshot(ctx->g, ctx->d, ctx->stream));
+    HIPCHK(ctx, launch_snapshot(target_of(ctx), ctx->stream));
     ctx->pending = false;
     ctx->inited = true;
     ctx->stepped = false;
@@ -538,6 +593,7 @@ gsis_status gsis_kinetic_step(gsis_ctx *ctx, int npasses)
     if (!ctx->inited) return fail(ctx, GSIS_ESTATE, "initialise the VDF first");
     if (npasses < 0) return fail(ctx, GSIS_EINVAL, "npasses must be >= 0");
     const Geo &g = ctx->g;
+    const Target t = target_of(ctx);
     for (int n = 0; n < npasses; ++n) {
         if (g.inv_dt != 0.0) {
             gsis_status st = materialize(ctx);
@@ -545,12 +601,11 @@ gsis_status gsis_kinetic_step(gsis_ctx *ctx, int npasses)
         }
         PhaseTimer t0, t1, t2;
         HIPCHK(ctx, t0.start(ctx, GSIS_PHASE_PREP));
-        HIPCHK(ctx, launch_params(g, ctx->d, ctx->stream));
-        HIPCHK(ctx, launch_face_scale(g, ctx->bc, ctx->d, ctx->stream));
+        HIPCHK(ctx, launch_params(t, ctx->stream));
+        HIPCHK(ctx, launch_face_scale(t, ctx->stream));
         HIPCHK(ctx, t0.stop());
         HIPCHK(ctx, t1.start(ctx, GSIS_PHASE_SWEEP));
-        HIPCHK(ctx, launch_sweep(g, ctx->d, ctx->fp32, ctx->tx, ctx->ty, ctx->tz, ctx->bs, ctx->plane_off.data(),
-                                 ctx->plane_cnt.data(), (int)ctx->plane_off.size(), ctx->stream));
+        HIPCHK(ctx, launch_sweep(t, ctx->stream));
         HIPCHK(ctx, t1.stop());
         ctx->pending = false;   // every fluid point was rewritten
         HIPCHK(ctx, t2.start(ctx, GSIS_PHASE_MOMENTS));
@@ -585,9 +640,10 @@ gsis_status gsis_gsis_correct(gsis_ctx *ctx, int inner_iters)
     if (st) return st;
     PhaseTimer t;
     HIPCHK(ctx, t.start(ctx, GSIS_PHASE_MACRO));
-    HIPCHK(ctx, launch_gsis_macro(ctx->g, ctx->bc, ctx->d, inner_iters, ctx->stream));
-    HIPCHK(ctx, launch_commit_correction(ctx->g, ctx->d, ctx->stream));
-    HIPCHK(ctx, launch_derive(ctx->g, ctx->d, ctx->stream));
+    const Target tg = target_of(ctx);
+    HIPCHK(ctx, launch_gsis_macro(tg, inner_iters, ctx->stream));
+    HIPCHK(ctx, launch_commit_correction(tg, ctx->stream));
+    HIPCHK(ctx, launch_derive(tg, ctx->stream));
     HIPCHK(ctx, t.stop());
     ctx->pending = true;
     return GSIS_OK;
@@ -601,13 +657,14 @@ gsis_status gsis_residual(gsis_ctx *ctx, double eps[3])
     const Geo &g = ctx->g;
     PhaseTimer t;
     HIPCHK(ctx, t.start(ctx, GSIS_PHASE_RESIDUAL));
-    HIPCHK(ctx, launch_residual(g, ctx->d, ctx->stream));
+    const Target tg = target_of(ctx);
+    HIPCHK(ctx, launch_residual(tg, ctx->stream));
     double sums[6];
     int flag[4];
     HIPCHK(ctx, hipMemcpyAsync(sums, ctx->d.red + (size_t)resid_blocks(g) * 6, sizeof sums, hipMemcpyDeviceToHost,
                                ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(flag, ctx->d.errflag, sizeof flag, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, launch_snapshot(g, ctx->d, ctx->stream));
+    HIPCHK(ctx, launch_snapshot(tg, ctx->stream));
     HIPCHK(ctx, t.stop());
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     for (int k = 0; k < 3; ++k) eps[k] = sums[3 + k] > 0 ? std::sqrt(sums[k] / sums[3 + k]) : std::sqrt(sums[k]);
@@ -649,7 +706,7 @@ gsis_status gsis_set_vdf(gsis_ctx *ctx, const double *f0_device, const double *f
     if (ctx->g.species == GSIS_DIATOMIC)
         HIPCHK(ctx, launch_from_canonical(ctx->g, ctx->d, ctx->fp32, f1_device, ctx->d.f1, ctx->stream));
     if ((st = reduce_vdf(ctx))) return st;
-    HIPCHK(ctx, launch_snapshot(ctx->g, ctx->d, ctx->stream));
+    HIPCHK(ctx, launch_snapshot(target_of(ctx), ctx->stream));
     ctx->pending = false;
     ctx->inited = true;
     ctx->stepped = false;
@@ -746,10 +803,7 @@ gsis_status gsis_set_tile(gsis_ctx *ctx, int tx, int ty, int tz, int block)
         ctx->tx = tx; ctx->ty = ty; ctx->tz = tz; ctx->bs = block;
     }
     if (ctx->meta_ready) build_tiles(ctx);
-    if (ctx->bound) {
-        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-        HIPCHK(ctx, hipMemcpy(ctx->d.tiles, ctx->tiles.data(), ctx->tiles.size() * sizeof(int), hipMemcpyHostToDevice));
-    }
+    if (ctx->bound) HIPCHK(ctx, upload_tiles(ctx));
     return GSIS_OK;
 }
 
@@ -772,8 +826,11 @@ gsis_status gsis_autotune(gsis_ctx *ctx, int reps, int *cfg_out, double *ms_out,
             for (int bs : {128, 256}) cands.push_back({tx, ty, std::max(tz, 1), bs, 0.0});
     }
     int save[4] = {ctx->tx, ctx->ty, ctx->tz, ctx->bs};
-    HIPCHK(ctx, launch_params(g, ctx->d, ctx->stream));
-    HIPCHK(ctx, launch_face_scale(g, ctx->bc, ctx->d, ctx->stream));
+    {
+        const Target t0 = target_of(ctx);
+        HIPCHK(ctx, launch_params(t0, ctx->stream));
+        HIPCHK(ctx, launch_face_scale(t0, ctx->stream));
+    }
     hipEvent_t e0, e1;
     HIPCHK(ctx, hipEventCreate(&e0));
     HIPCHK(ctx, hipEventCreate(&e1));
@@ -781,14 +838,11 @@ gsis_status gsis_autotune(gsis_ctx *ctx, int reps, int *cfg_out, double *ms_out,
     for (auto &c : cands) {
         ctx->tx = c.tx; ctx->ty = c.ty; ctx->tz = c.tz; ctx->bs = c.bs;
         build_tiles(ctx);
-        hipError_t e = hipMemcpy(ctx->d.tiles, ctx->tiles.data(), ctx->tiles.size() * sizeof(int), hipMemcpyHostToDevice);
-        if (e == hipSuccess)   // warm-up launch of this configuration
-            e = launch_sweep(g, ctx->d, ctx->fp32, c.tx, c.ty, c.tz, c.bs, ctx->plane_off.data(), ctx->plane_cnt.data(),
-                             (int)ctx->plane_off.size(), ctx->stream);
+        hipError_t e = upload_tiles(ctx);
+        const Target tc = target_of(ctx);
+        if (e == hipSuccess) e = launch_sweep(tc, ctx->stream);   // warm-up launch of this configuration
         if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
-        for (int r = 0; r < reps && e == hipSuccess; ++r)
-            e = launch_sweep(g, ctx->d, ctx->fp32, c.tx, c.ty, c.tz, c.bs, ctx->plane_off.data(), ctx->plane_cnt.data(),
-                             (int)ctx->plane_off.size(), ctx->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_sweep(tc, ctx->stream);
         if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.0f;
@@ -801,7 +855,7 @@ gsis_status gsis_autotune(gsis_ctx *ctx, int reps, int *cfg_out, double *ms_out,
     if (st) {
         ctx->tx = save[0]; ctx->ty = save[1]; ctx->tz = save[2]; ctx->bs = save[3];
         build_tiles(ctx);
-        hipMemcpy(ctx->d.tiles, ctx->tiles.data(), ctx->tiles.size() * sizeof(int), hipMemcpyHostToDevice);
+        upload_tiles(ctx);
         return st;
     }
     size_t best = 0;
@@ -809,7 +863,7 @@ gsis_status gsis_autotune(gsis_ctx *ctx, int reps, int *cfg_out, double *ms_out,
         if (cands[k].ms < cands[best].ms) best = k;
     ctx->tx = cands[best].tx; ctx->ty = cands[best].ty; ctx->tz = cands[best].tz; ctx->bs = cands[best].bs;
     build_tiles(ctx);
-    HIPCHK(ctx, hipMemcpy(ctx->d.tiles, ctx->tiles.data(), ctx->tiles.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(ctx, upload_tiles(ctx));
     // the VDF now holds this pass's sweep result (identical under every configuration)
     ctx->pending = false;
     st = reduce_vdf(ctx);
@@ -905,6 +959,490 @@ gsis_status gsis_pass_count(const gsis_ctx *ctx, long long *passes)
 {
     if (!ctx || !passes) return GSIS_EINVAL;
     *passes = ctx->passes;
+    return GSIS_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== batches
+
+struct gsis_batch {
+    std::vector<gsis_ctx *> cs;
+    hipStream_t stream = nullptr;
+    bool bound = false, inited = false;
+    bool fp32 = false, dia = false;
+    int tx = 4, ty = 4, tz = 4, bs = 128;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    Case *dcases = nullptr;        // device case table
+    int2 *dmap = nullptr;          // device block maps
+    size_t map_cap = 0;
+    double *hist = nullptr;        // [hist_cap][ncase][6] residual sums
+    int *hist_ctr = nullptr;
+    int hist_cap = 1024;
+    std::vector<size_t> case_off;  // workspace offset of every case
+    std::vector<Case> hcases;
+    std::vector<int2> hmap;
+    std::vector<const int2 *> pmap;
+    std::vector<int> npblk;
+    Target t;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_inner = -1;
+    long long iters_run = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+    std::string err;
+    void drop_graph()
+    {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        graph_inner = -1;
+    }
+    ~gsis_batch()
+    {
+        drop_graph();
+        if (ev0) hipEventDestroy(ev0);
+        if (ev1) hipEventDestroy(ev1);
+    }
+};
+
+namespace {
+
+gsis_status bfail(gsis_batch *b, gsis_status s, const std::string &msg)
+{
+    if (b) b->err = msg;
+    return s;
+}
+
+#define BHIPCHK(b, expr)                                                                               \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) return bfail(b, GSIS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Upper bound of the block-map entries: every launch kind, plus the sweep at
+// its finest tiling (4 x 4 x 1 tiles, 128-thread blocks).
+size_t batch_map_cap(const gsis_batch *b)
+{
+    size_t n = 0;
+    for (const gsis_ctx *c : b->cs) {
+        for (int k = 0; k < NKIND; ++k) n += (size_t)kind_blocks(c->g, (Kind)k);
+        size_t tiles = (size_t)((c->g.nx + 3) / 4) * ((c->g.ny + 3) / 4) * c->g.nz;
+        n += tiles * 8 * (size_t)sweep_nvb(c->g, 128);
+    }
+    return n;
+}
+
+size_t batch_layout(gsis_batch *b, char *base)
+{
+    const size_t nc = b->cs.size();
+    size_t off = 0;
+    carve(off, b->dcases, nc, base);
+    carve(off, b->dmap, b->map_cap, base);
+    carve(off, b->hist, (size_t)b->hist_cap * nc * 6, base);
+    carve(off, b->hist_ctr, 64, base);
+    b->case_off.assign(nc, 0);
+    for (size_t c = 0; c < nc; ++c) {
+        off = align256(off);
+        b->case_off[c] = off;
+        Dev save = b->cs[c]->d;
+        Case *dsave = b->cs[c]->dcase;
+        off += layout(b->cs[c], nullptr);
+        b->cs[c]->d = save;
+        b->cs[c]->dcase = dsave;
+    }
+    return align256(off);
+}
+
+// Case table (with the batch's residual history) to the device.
+hipError_t batch_upload_cases(gsis_batch *b)
+{
+    const int nc = (int)b->cs.size();
+    b->hcases.resize(nc);
+    for (int c = 0; c < nc; ++c) {
+        Case h = b->cs[c]->hcase;
+        h.d.hist = b->hist;
+        h.d.hist_ctr = b->hist_ctr;
+        h.d.hist_index = c;
+        h.d.hist_ncase = nc;
+        h.d.hist_cap = b->hist_cap;
+        b->hcases[c] = h;
+    }
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = hipMemcpy(b->dcases, b->hcases.data(), nc * sizeof(Case), hipMemcpyHostToDevice);
+    return e;
+}
+
+// (case, block) tables of every launch kind and every global sweep plane.
+hipError_t batch_build_maps(gsis_batch *b)
+{
+    const int nc = (int)b->cs.size();
+    std::vector<int2> &m = b->hmap;
+    m.clear();
+    size_t koff[NKIND];
+    Target &t = b->t;
+    t = Target();
+    for (int k = 0; k < NKIND; ++k) {
+        koff[k] = m.size();
+        for (int c = 0; c < nc; ++c) {
+            const int nb = kind_blocks(b->cs[c]->g, (Kind)k);
+            for (int j = 0; j < nb; ++j) m.push_back(make_int2(c, j));
+        }
+        t.nblk[k] = (int)(m.size() - koff[k]);
+    }
+    int nplane = 0;
+    for (const gsis_ctx *c : b->cs) nplane = std::max(nplane, (int)c->plane_cnt.size());
+    std::vector<size_t> poff(nplane);
+    b->npblk.assign(nplane, 0);
+    for (int p = 0; p < nplane; ++p) {
+        poff[p] = m.size();
+        for (int c = 0; c < nc; ++c) {
+            const gsis_ctx *x = b->cs[c];
+            if (p >= (int)x->plane_cnt.size()) continue;
+            const int nb = x->npblk[p];
+            for (int j = 0; j < nb; ++j) m.push_back(make_int2(c, j));
+        }
+        b->npblk[p] = (int)(m.size() - poff[p]);
+    }
+    if (m.size() > b->map_cap) return hipErrorInvalidValue;
+    for (int k = 0; k < NKIND; ++k) t.map[k] = b->dmap + koff[k];
+    b->pmap.assign(nplane, nullptr);
+    for (int p = 0; p < nplane; ++p) b->pmap[p] = b->dmap + poff[p];
+    t.cases = b->dcases;
+    t.ncase = nc;
+    t.host = b->hcases.data();
+    t.pmap = b->pmap.data();
+    t.npblk = b->npblk.data();
+    t.nplane = nplane;
+    t.fp32 = b->fp32;
+    t.dia = b->dia;
+    t.mask = false;
+    int vw = 4;
+    for (const gsis_ctx *c : b->cs) {
+        t.mask = t.mask || c->g.nfluid != c->g.ncell;
+        vw = std::min(vw, c->vw);
+    }
+    t.vw = vw;
+    t.rfn = false;
+    t.tx = b->tx;
+    t.ty = b->ty;
+    t.bs = b->bs;
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess && !m.empty()) e = hipMemcpy(b->dmap, m.data(), m.size() * sizeof(int2), hipMemcpyHostToDevice);
+    return e;
+}
+
+// One tile shape on every case, then the tables that depend on it.
+gsis_status batch_apply_tile(gsis_batch *b, int tx, int ty, int tz, int bs)
+{
+    for (gsis_ctx *c : b->cs) {
+        gsis_status st = gsis_set_tile(c, tx, ty, tz, bs);
+        if (st) return bfail(b, st, std::string("tile: ") + c->err);
+    }
+    const gsis_ctx *c0 = b->cs[0];
+    b->tx = c0->tx; b->ty = c0->ty; b->tz = c0->tz; b->bs = c0->bs;
+    b->drop_graph();
+    if (b->bound) {
+        BHIPCHK(b, batch_upload_cases(b));
+        BHIPCHK(b, batch_build_maps(b));
+    }
+    return GSIS_OK;
+}
+
+// One GSIS iteration of every case, enqueued on the batch stream.
+hipError_t batch_enqueue_iteration(gsis_batch *b, int inner)
+{
+    const Target &t = b->t;
+    hipStream_t s = b->stream;
+    hipError_t e = launch_params(t, s);
+    if (e == hipSuccess) e = launch_face_scale(t, s);
+    if (e == hipSuccess) e = launch_sweep(t, s);
+    if (e == hipSuccess) e = launch_moments(t, s);
+    if (e == hipSuccess) e = launch_derive(t, s);
+    if (inner > 0) {
+        if (e == hipSuccess) e = launch_gsis_macro(t, inner, s);
+        if (e == hipSuccess) e = launch_commit_correction(t, s);
+        if (e == hipSuccess) e = launch_derive(t, s);
+    }
+    if (e == hipSuccess) e = launch_residual(t, s);
+    if (e == hipSuccess) e = launch_snapshot(t, s);
+    if (e == hipSuccess) e = launch_hist_advance(b->hist_ctr, s);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gsis_batch_last_error(const gsis_batch *b)
+{
+    return b ? b->err.c_str() : "no batch";
+}
+
+gsis_status gsis_batch_create(gsis_batch **out, gsis_ctx *const *cases, int ncases)
+{
+    if (!out) return GSIS_EINVAL;
+    *out = nullptr;
+    if (!cases || ncases < 1 || ncases > 4096) return GSIS_EINVAL;
+    for (int i = 0; i < ncases; ++i) {
+        gsis_ctx *c = cases[i];
+        if (!c || c->bound) return GSIS_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (cases[j] == c) return GSIS_EINVAL;
+        if (c->fp32 != cases[0]->fp32 || c->g.species != cases[0]->g.species) return GSIS_EINVAL;
+        if (c->g.inv_dt != 0.0) return GSIS_EINVAL;
+    }
+    gsis_batch *b = new (std::nothrow) gsis_batch();
+    if (!b) return GSIS_ENOMEM;
+    b->cs.assign(cases, cases + ncases);
+    b->fp32 = cases[0]->fp32;
+    b->dia = cases[0]->g.species == GSIS_DIATOMIC;
+    gsis_status st = batch_apply_tile(b, 0, 0, 0, 0);
+    if (st) {
+        delete b;
+        return st;
+    }
+    for (gsis_ctx *c : b->cs)
+        if (!c->meta_ready) build_meta(c);
+    b->map_cap = batch_map_cap(b);
+    *out = b;
+    return GSIS_OK;
+}
+
+gsis_status gsis_batch_destroy(gsis_batch *b)
+{
+    if (!b) return GSIS_EINVAL;
+    delete b;
+    return GSIS_OK;
+}
+
+gsis_status gsis_batch_workspace_size(gsis_batch *b, size_t *bytes)
+{
+    if (!b || !bytes) return GSIS_EINVAL;
+    Case *dc = b->dcases;
+    int2 *dm = b->dmap;
+    double *h = b->hist;
+    int *hc = b->hist_ctr;
+    *bytes = batch_layout(b, nullptr);
+    b->dcases = dc; b->dmap = dm; b->hist = h; b->hist_ctr = hc;
+    return GSIS_OK;
+}
+
+gsis_status gsis_batch_bind_workspace(gsis_batch *b, void *device_ptr, size_t bytes)
+{
+    if (!b) return GSIS_EINVAL;
+    if (b->bound) return bfail(b, GSIS_ESTATE, "workspace already bound");
+    if (!device_ptr) return bfail(b, GSIS_EINVAL, "workspace pointer is NULL");
+    if ((uintptr_t)device_ptr % 256) return bfail(b, GSIS_EINVAL, "workspace must be 256-byte aligned");
+    size_t need;
+    gsis_batch_workspace_size(b, &need);
+    if (bytes < need) return bfail(b, GSIS_ENOMEM, "workspace smaller than gsis_batch_workspace_size");
+    char *base = (char *)device_ptr;
+    batch_layout(b, base);
+    for (size_t c = 0; c < b->cs.size(); ++c) {
+        gsis_ctx *x = b->cs[c];
+        size_t sz = 0;
+        gsis_workspace_size(x, &sz);
+        gsis_status st = gsis_bind_workspace(x, base + b->case_off[c], sz);
+        if (st) return bfail(b, st, "case " + std::to_string(c) + ": " + x->err);
+        x->stream = b->stream;
+    }
+    b->ws = base;
+    b->ws_bytes = bytes;
+    BHIPCHK(b, hipMemset(b->hist_ctr, 0, 64 * sizeof(int)));
+    BHIPCHK(b, batch_upload_cases(b));
+    BHIPCHK(b, batch_build_maps(b));
+    BHIPCHK(b, hipDeviceSynchronize());
+    b->bound = true;
+    return GSIS_OK;
+}
+
+gsis_status gsis_batch_set_stream(gsis_batch *b, void *hip_stream)
+{
+    if (!b) return GSIS_EINVAL;
+    b->stream = (hipStream_t)hip_stream;
+    for (gsis_ctx *c : b->cs) c->stream = b->stream;
+    return GSIS_OK;
+}
+
+gsis_status gsis_batch_set_tile(gsis_batch *b, int tx, int ty, int tz, int block)
+{
+    if (!b) return GSIS_EINVAL;
+    return batch_apply_tile(b, tx, ty, tz, block);
+}
+
+gsis_status gsis_batch_get_tile(const gsis_batch *b, int *tile)
+{
+    if (!b || !tile) return GSIS_EINVAL;
+    tile[0] = b->tx; tile[1] = b->ty; tile[2] = b->tz; tile[3] = b->bs;
+    return GSIS_OK;
+}
+
+gsis_status gsis_batch_init_maxwellian(gsis_batch *b, double rho, const double u[3], double T, double Tr)
+{
+    if (!b) return GSIS_EINVAL;
+    if (!b->bound) return bfail(b, GSIS_ESTATE, "bind_workspace first");
+    for (size_t c = 0; c < b->cs.size(); ++c) {
+        gsis_status st = gsis_init_maxwellian(b->cs[c], rho, u, T, Tr);
+        if (st) return bfail(b, st, "case " + std::to_string(c) + ": " + b->cs[c]->err);
+    }
+    BHIPCHK(b, launch_zero_int(b->hist_ctr, 1, b->stream));
+    b->iters_run = 0;
+    b->inited = true;
+    return GSIS_OK;
+}
+
+gsis_status gsis_batch_autotune(gsis_batch *b, int reps, int *cfg_out, double *ms_out, int max, int *count)
+{
+    if (!b) return GSIS_EINVAL;
+    if (!b->inited) return bfail(b, GSIS_ESTATE, "initialise the batch first");
+    if (reps < 1 || max < 0) return bfail(b, GSIS_EINVAL, "reps must be >= 1");
+    const gsis_ctx *c0 = b->cs[0];
+    int shapes[32];
+    int nsh = sweep_shapes(b->fp32, shapes, 16);
+    struct Cand { int tx, ty, tz, bs; double ms; };
+    std::vector<Cand> cands;
+    for (int k = 0; k < nsh; ++k) {
+        int tx = shapes[2 * k], ty = shapes[2 * k + 1];
+        if (!sweep_shape_supported(b->fp32, b->dia, tx, ty)) continue;
+        for (int tz : {tx / 2, tx, 2 * tx})
+            for (int bs : {128, 256}) cands.push_back({tx, ty, std::max(tz, 1), bs, 0.0});
+    }
+    (void)c0;
+    const int save[4] = {b->tx, b->ty, b->tz, b->bs};
+    BHIPCHK(b, launch_params(b->t, b->stream));
+    BHIPCHK(b, launch_face_scale(b->t, b->stream));
+    hipEvent_t e0, e1;
+    BHIPCHK(b, hipEventCreate(&e0));
+    BHIPCHK(b, hipEventCreate(&e1));
+    gsis_status st = GSIS_OK;
+    for (auto &c : cands) {
+        st = batch_apply_tile(b, c.tx, c.ty, c.tz, c.bs);
+        if (st) break;
+        hipError_t e = launch_sweep(b->t, b->stream);   // warm-up launch of this configuration
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_sweep(b->t, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { st = bfail(b, GSIS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e)); break; }
+        c.ms = ms / reps;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) {
+        batch_apply_tile(b, save[0], save[1], save[2], save[3]);
+        return st;
+    }
+    size_t best = 0;
+    for (size_t k = 1; k < cands.size(); ++k)
+        if (cands[k].ms < cands[best].ms) best = k;
+    st = batch_apply_tile(b, cands[best].tx, cands[best].ty, cands[best].tz, cands[best].bs);
+    if (st) return st;
+    // every case now holds this pass's sweep result (identical under every configuration)
+    BHIPCHK(b, launch_moments(b->t, b->stream));
+    BHIPCHK(b, launch_derive(b->t, b->stream));
+    for (gsis_ctx *c : b->cs) {
+        c->pending = false;
+        c->passes++;
+        c->stepped = true;
+    }
+    int n = 0;
+    for (size_t k = 0; k < cands.size() && n < max; ++k, ++n) {
+        if (cfg_out) {
+            cfg_out[4 * n] = cands[k].tx; cfg_out[4 * n + 1] = cands[k].ty;
+            cfg_out[4 * n + 2] = cands[k].tz; cfg_out[4 * n + 3] = cands[k].bs;
+        }
+        if (ms_out) ms_out[n] = cands[k].ms;
+    }
+    if (count) *count = n;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    return GSIS_OK;
+}
+
+gsis_status gsis_batch_run(gsis_batch *b, int iters, int inner_iters, int use_graph)
+{
+    if (!b) return GSIS_EINVAL;
+    if (!b->inited) return bfail(b, GSIS_ESTATE, "initialise the batch first");
+    if (iters < 0 || inner_iters < 0) return bfail(b, GSIS_EINVAL, "iters and inner_iters must be >= 0");
+    if (use_graph && !b->stream) return bfail(b, GSIS_EINVAL, "graph capture needs a non-null stream");
+    for (gsis_ctx *c : b->cs)
+        if (!c->inited) return bfail(b, GSIS_ESTATE, "a case was not initialised");
+    if (!b->ev0) BHIPCHK(b, hipEventCreate(&b->ev0));
+    if (!b->ev1) BHIPCHK(b, hipEventCreate(&b->ev1));
+    if (use_graph && iters > 0 && (!b->exec || b->graph_inner != inner_iters)) {
+        b->drop_graph();
+        BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = batch_enqueue_iteration(b, inner_iters);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return bfail(b, GSIS_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        b->graph = g;
+        BHIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->graph_inner = inner_iters;
+    }
+    BHIPCHK(b, hipEventRecord(b->ev0, b->stream));
+    for (int it = 0; it < iters; ++it) {
+        if (use_graph) BHIPCHK(b, hipGraphLaunch(b->exec, b->stream));
+        else BHIPCHK(b, batch_enqueue_iteration(b, inner_iters));
+    }
+    BHIPCHK(b, hipEventRecord(b->ev1, b->stream));
+    b->timed = true;
+    for (gsis_ctx *c : b->cs) {
+        c->passes += iters;
+        if (iters > 0) {
+            c->stepped = true;
+            c->pending = inner_iters > 0;
+        }
+    }
+    b->iters_run += iters;
+    return GSIS_OK;
+}
+
+gsis_status gsis_batch_residuals(gsis_batch *b, double *eps, int max, int *count)
+{
+    if (!b || !count || max < 0) return GSIS_EINVAL;
+    if (!b->bound) return bfail(b, GSIS_ESTATE, "bind_workspace first");
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    const int nc = (int)b->cs.size();
+    int ctr = 0;
+    BHIPCHK(b, hipMemcpy(&ctr, b->hist_ctr, sizeof(int), hipMemcpyDeviceToHost));
+    int n = std::min(std::min(ctr, b->hist_cap), max);
+    std::vector<double> h((size_t)b->hist_cap * nc * 6);
+    BHIPCHK(b, hipMemcpy(h.data(), b->hist, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int i = 0; i < n && eps; ++i) {
+        const int slot = (ctr - n + i) % b->hist_cap;
+        for (int c = 0; c < nc; ++c) {
+            const double *v = &h[((size_t)slot * nc + c) * 6];
+            for (int k = 0; k < 3; ++k)
+                eps[((size_t)i * nc + c) * 3 + k] = v[3 + k] > 0 ? std::sqrt(v[k] / v[3 + k]) : std::sqrt(v[k]);
+        }
+    }
+    *count = n;
+    for (int c = 0; c < nc; ++c) {
+        int flag = 0;
+        BHIPCHK(b, hipMemcpy(&flag, b->cs[c]->d.errflag, sizeof(int), hipMemcpyDeviceToHost));
+        if (flag) return bfail(b, GSIS_ENOTFINITE, "case " + std::to_string(c) + " flagged a non-physical state (" +
+                                                         std::to_string(flag) + ")");
+    }
+    return GSIS_OK;
+}
+
+gsis_status gsis_batch_last_run_ms(gsis_batch *b, double *ms)
+{
+    if (!b || !ms) return GSIS_EINVAL;
+    if (!b->timed) return bfail(b, GSIS_ESTATE, "no run yet");
+    BHIPCHK(b, hipEventSynchronize(b->ev1));
+    float t = 0.0f;
+    BHIPCHK(b, hipEventElapsedTime(&t, b->ev0, b->ev1));
+    *ms = t;
     return GSIS_OK;
 }
 

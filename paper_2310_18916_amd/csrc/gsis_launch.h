@@ -4,6 +4,28 @@
 
 namespace gsis {
 
+// Grid shapes of the kernels of a GSIS iteration; a launch over several cases
+// concatenates the blocks each case needs (kind_blocks) through a block map.
+enum Kind { K_CELL64, K_CELL128, K_CELL256, K_CELL1, K_FACE256, K_FACE8, K_GRAD, K_RES, K_CASE, NKIND };
+int kind_blocks(const Geo &g, Kind k);
+
+// What a launch covers: one case (maps null) or a batch of cases that share
+// precision, gas and tile shape.
+struct Target {
+    const Case *cases = nullptr;      // device table
+    int ncase = 1;
+    const Case *host = nullptr;       // host copies of the table
+    const int2 *map[NKIND] = {};      // device block maps (nullptr for one case)
+    int nblk[NKIND] = {};             // grid size per kind
+    const int2 *const *pmap = nullptr;   // sweep: block map of every global plane (nullptr for one case)
+    const int *npblk = nullptr;          // sweep: blocks of every global plane
+    int nplane = 0;
+    bool fp32 = false, dia = false, mask = false, rfn = false;
+    int vw = 1;                       // moment kernel vector width
+    int tx = 4, ty = 4, bs = 128;     // sweep tile shape and block size
+    Span span(Kind k) const { return Span{cases, map[k]}; }
+};
+
 hipError_t launch_setup_tables(const Geo &g, const BcInfo &bc, const Dev &d, hipStream_t s);
 hipError_t launch_init_maxwellian(const Geo &g, const Dev &d, bool fp32, double rho, const double *u, double Tt,
                                   double Tr, hipStream_t s);
@@ -12,23 +34,23 @@ hipError_t launch_from_canonical(const Geo &g, const Dev &d, bool fp32, const do
 hipError_t launch_vdf_node(const Geo &g, const Dev &d, bool fp32, int node, double *out, hipStream_t s);
 hipError_t launch_apply_correction(const Geo &g, const Dev &d, bool fp32, hipStream_t s);
 
-hipError_t launch_moments(const Geo &g, const Dev &d, bool fp32, int vw, hipStream_t s);
-hipError_t launch_derive(const Geo &g, const Dev &d, hipStream_t s);
-hipError_t launch_commit_correction(const Geo &g, const Dev &d, hipStream_t s);
+hipError_t launch_moments(const Target &t, hipStream_t s);
+hipError_t launch_derive(const Target &t, hipStream_t s);
+hipError_t launch_commit_correction(const Target &t, hipStream_t s);
 
-hipError_t launch_params(const Geo &g, const Dev &d, hipStream_t s);
-hipError_t launch_face_scale(const Geo &g, const BcInfo &bc, const Dev &d, hipStream_t s);
+hipError_t launch_params(const Target &t, hipStream_t s);
+hipError_t launch_face_scale(const Target &t, hipStream_t s);
 
 bool sweep_shape_supported(bool fp32, bool dia, int tx, int ty);
 int sweep_shapes(bool fp32, int *out, int max);
-hipError_t launch_sweep(const Geo &g, const Dev &d, bool fp32, int tx, int ty, int tz, int bs, const int *plane_off,
-                        const int *plane_cnt, int nplane, hipStream_t s);
+hipError_t launch_sweep(const Target &t, hipStream_t s);
 
-hipError_t launch_gsis_macro(const Geo &g, const BcInfo &bc, const Dev &d, int iters, hipStream_t s);
+hipError_t launch_gsis_macro(const Target &t, int iters, hipStream_t s);
 
 int resid_blocks(const Geo &g);
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);
-hipError_t launch_residual(const Geo &g, const Dev &d, hipStream_t s);
-hipError_t launch_snapshot(const Geo &g, const Dev &d, hipStream_t s);
+hipError_t launch_residual(const Target &t, hipStream_t s);
+hipError_t launch_snapshot(const Target &t, hipStream_t s);
+hipError_t launch_hist_advance(int *ctr, hipStream_t s);
 
 }  // namespace gsis

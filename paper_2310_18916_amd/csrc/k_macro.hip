@@ -113,6 +113,9 @@ __device__ __forceinline__ void face_flux(const Geo &g, const double *L, const d
 // the group ends with the result.
 constexpr int FG = 8;
 
+// gradient blocks of k_mac_grad: one (cell, axis) per thread, 256 threads
+__host__ __device__ inline int grad_blocks(const Geo &g) { return (3 * g.ncell + 255) / 256; }
+
 __device__ __forceinline__ double group_sum(double v)
 {
 #pragma unroll
@@ -180,9 +183,13 @@ __device__ __forceinline__ double boundary_gamma(const Geo &g, const double *P, 
 }
 
 // W^{n+1/2}, kinetic stress/heat flux, the old half of the correction record.
-__global__ void k_mac_init(Geo g, Dev d)
+__global__ __launch_bounds__(128) void k_mac_init(GSIS_SPAN_ARGS)
 {
-    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    int cell = blk * blockDim.x + threadIdx.x;
     if (cell >= g.ncell || !d.cflag[cell]) return;
     const double *m = d.cm + (size_t)cell * NMOM;
     double rho = m[0], Tt = m[4];
@@ -219,19 +226,25 @@ __device__ void cell_grad_col(const Geo &g, const Dev &d, int cell, int a)
 }
 
 // Blocks [0, ngrad): central gradients of u, one (cell, axis) per thread.
-// Blocks [ngrad, ...): boundary faces, one wave per face: F_b = fixed part +
+// Blocks [ngrad, ...): boundary faces, FG lanes per face: F_b = fixed part +
 // F_eq(W^m) and its Gamma (skipped when with_faces is 0).
-__global__ __launch_bounds__(256) void k_mac_grad(Geo g, BcInfo bc, Dev d, int ngrad, int with_faces)
+__global__ __launch_bounds__(256) void k_mac_grad(GSIS_SPAN_ARGS, int with_faces)
 {
-    if ((int)blockIdx.x < ngrad) {
-        const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    const BcInfo &bc = C.bc;
+    const int ngrad = grad_blocks(g);
+    if (blk < ngrad) {
+        const int t = blk * blockDim.x + threadIdx.x;
         const int cell = t / 3, a = t - 3 * (t / 3);
         if (cell < g.ncell && d.cflag[cell]) cell_grad_col(g, d, cell, a);
         return;
     }
     if (!with_faces) return;
     // whole groups of FG lanes share f, so the group butterflies stay inside live lanes
-    const int f = (((int)blockIdx.x - ngrad) * (int)blockDim.x + (int)threadIdx.x) / FG;
+    const int f = ((blk - ngrad) * (int)blockDim.x + (int)threadIdx.x) / FG;
     const int sub = threadIdx.x & (FG - 1);
     if (f >= g.nface) return;
     const int cell = d.face_cell[f], dir = d.face_dir[f];
@@ -243,9 +256,13 @@ __global__ __launch_bounds__(256) void k_mac_grad(Geo g, BcInfo bc, Dev d, int n
 }
 
 // HoT at the faces (cell, cell + e_a) from W^{n+1/2}.
-__global__ void k_mac_hot(Geo g, Dev d)
+__global__ __launch_bounds__(128) void k_mac_hot(GSIS_SPAN_ARGS)
 {
-    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    int cell = blk * blockDim.x + threadIdx.x;
     if (cell >= g.ncell || !d.cflag[cell]) return;
     const int col[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
     for (int a = 0; a < 3; ++a) {
@@ -269,9 +286,14 @@ __global__ void k_mac_hot(Geo g, Dev d)
 // Fixed part of each boundary face flux, F_kin(f^{n+1/2}) - F_eq(W^{n+1/2}), and
 // the face flux of the first inner iteration, fixed part + F_eq(W^{n+1/2}).
 // One group of FG lanes per face.
-__global__ __launch_bounds__(256) void k_mac_fbfix(Geo g, BcInfo bc, Dev d)
+__global__ __launch_bounds__(256) void k_mac_fbfix(GSIS_SPAN_ARGS)
 {
-    const int f = (int)(blockIdx.x * blockDim.x + threadIdx.x) / FG;
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    const BcInfo &bc = C.bc;
+    const int f = (int)(blk * blockDim.x + threadIdx.x) / FG;
     const int sub = threadIdx.x & (FG - 1);
     if (f >= g.nface) return;
     const int cell = d.face_cell[f], dir = d.face_dir[f], b = d.face_bc[f];
@@ -335,13 +357,18 @@ __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, 
 constexpr int RES_CELLS = 64;
 
 template <bool DIA>
-__global__ __launch_bounds__(384) void k_mac_res(Geo g, Dev d, int slot)
+__global__ __launch_bounds__(384) void k_mac_res(GSIS_SPAN_ARGS, int slot)
 {
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+
     constexpr int NW = DIA ? 6 : 5;
     __shared__ double red[6][NW + 1][RES_CELLS];
     const int lane = threadIdx.x & 63;
     const int dir = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int cell = blockIdx.x * RES_CELLS + lane;
+    const int cell = blk * RES_CELLS + lane;
     const bool live = cell < g.ncell && d.cflag[cell];
     double out[NW], gam = 0.0;
 #pragma unroll
@@ -396,9 +423,13 @@ __global__ __launch_bounds__(384) void k_mac_res(Geo g, Dev d, int slot)
 }
 
 // W += R / D* and the new prims.
-__global__ __launch_bounds__(256) void k_mac_update(Geo g, Dev d, int slot)
+__global__ __launch_bounds__(256) void k_mac_update(GSIS_SPAN_ARGS, int slot)
 {
-    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    int cell = blk * blockDim.x + threadIdx.x;
     if (cell == 0) d.dmax[slot ^ 1] = 0ull;   // the other slot was last used by the previous iteration
     if (cell >= g.ncell || !d.cflag[cell]) return;
     double Dm = __longlong_as_double((long long)d.dmax[slot]);
@@ -409,15 +440,22 @@ __global__ __launch_bounds__(256) void k_mac_update(Geo g, Dev d, int slot)
     prim_from_W(g, W, d.P + (size_t)cell * NP);
 }
 
-__global__ void k_mac_reset(Dev d)
+// one block per case
+__global__ void k_mac_reset(GSIS_SPAN_ARGS)
 {
-    if (threadIdx.x < 2) d.dmax[threadIdx.x] = 0ull;
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    if (threadIdx.x < 2) C.d.dmax[threadIdx.x] = 0ull;
 }
 
 // New half of the correction record; flags non-physical states.
-__global__ void k_mac_final(Geo g, Dev d)
+__global__ __launch_bounds__(128) void k_mac_final(GSIS_SPAN_ARGS)
 {
-    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    int cell = blk * blockDim.x + threadIdx.x;
     if (cell >= g.ncell || !d.cflag[cell]) return;
     const double *P = d.P + (size_t)cell * NP;
     double *c = d.corr + (size_t)cell * NCORR;
@@ -426,27 +464,39 @@ __global__ void k_mac_final(Geo g, Dev d)
     if (!(P[0] > 0.0) || !(P[4] > 0.0) || !isfinite(P[6]) || (g.species == 1 && !(P[5] > 0.0))) atomicOr(d.errflag, 4);
 }
 
-hipError_t launch_gsis_macro(const Geo &g, const BcInfo &bc, const Dev &d, int iters, hipStream_t s)
+hipError_t launch_gsis_macro(const Target &t, int iters, hipStream_t s)
 {
-    dim3 blk(128), grd((g.ncell + 127) / 128);
-    const int ngrad = (3 * g.ncell + 255) / 256;   // one (cell, axis) per thread
-    const int nres = (g.ncell + RES_CELLS - 1) / RES_CELLS;
-    const int nupd = (g.ncell + 255) / 256;
-    const int nfb = (g.nface * FG + 255) / 256;   // FG lanes per boundary face
-    hipLaunchKernelGGL(k_mac_reset, dim3(1), dim3(64), 0, s, d);
-    hipLaunchKernelGGL(k_mac_init, grd, blk, 0, s, g, d);
-    hipLaunchKernelGGL(k_mac_grad, dim3(ngrad), dim3(256), 0, s, g, bc, d, ngrad, 0);
-    hipLaunchKernelGGL(k_mac_hot, grd, blk, 0, s, g, d);
-    if (g.nface > 0) hipLaunchKernelGGL(k_mac_fbfix, dim3(nfb), dim3(256), 0, s, g, bc, d);
+    hipLaunchKernelGGL(k_mac_reset, dim3(t.nblk[K_CASE]), dim3(64), 0, s, GSIS_SPAN(t.span(K_CASE)));
+    hipLaunchKernelGGL(k_mac_init, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(t.span(K_CELL128)));
+    hipLaunchKernelGGL(k_mac_grad, dim3(t.nblk[K_GRAD]), dim3(256), 0, s, GSIS_SPAN(t.span(K_GRAD)), 0);
+    hipLaunchKernelGGL(k_mac_hot, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(t.span(K_CELL128)));
+    if (t.nblk[K_FACE8] > 0) hipLaunchKernelGGL(k_mac_fbfix, dim3(t.nblk[K_FACE8]), dim3(256), 0, s, GSIS_SPAN(t.span(K_FACE8)));
     for (int it = 0; it < iters; ++it) {
         int slot = it & 1;
-        if (it > 0) hipLaunchKernelGGL(k_mac_grad, dim3(ngrad + nfb), dim3(256), 0, s, g, bc, d, ngrad, 1);
-        if (g.species == 1) hipLaunchKernelGGL(k_mac_res<true>, dim3(nres), dim3(384), 0, s, g, d, slot);
-        else hipLaunchKernelGGL(k_mac_res<false>, dim3(nres), dim3(384), 0, s, g, d, slot);
-        hipLaunchKernelGGL(k_mac_update, dim3(nupd), dim3(256), 0, s, g, d, slot);
+        if (it > 0) hipLaunchKernelGGL(k_mac_grad, dim3(t.nblk[K_GRAD]), dim3(256), 0, s, GSIS_SPAN(t.span(K_GRAD)), 1);
+        if (t.dia) hipLaunchKernelGGL(k_mac_res<true>, dim3(t.nblk[K_RES]), dim3(384), 0, s, GSIS_SPAN(t.span(K_RES)), slot);
+        else hipLaunchKernelGGL(k_mac_res<false>, dim3(t.nblk[K_RES]), dim3(384), 0, s, GSIS_SPAN(t.span(K_RES)), slot);
+        hipLaunchKernelGGL(k_mac_update, dim3(t.nblk[K_CELL256]), dim3(256), 0, s, GSIS_SPAN(t.span(K_CELL256)), slot);
     }
-    hipLaunchKernelGGL(k_mac_final, grd, blk, 0, s, g, d);
+    hipLaunchKernelGGL(k_mac_final, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(t.span(K_CELL128)));
     return hipGetLastError();
+}
+
+// blocks one case needs for each launch shape
+int kind_blocks(const Geo &g, Kind k)
+{
+    switch (k) {
+    case K_CELL64: return (g.ncell + 63) / 64;
+    case K_CELL128: return (g.ncell + 127) / 128;
+    case K_CELL256: return (g.ncell + 255) / 256;
+    case K_CELL1: return g.ncell;
+    case K_FACE256: return (g.nface + 255) / 256;
+    case K_FACE8: return (g.nface * FG + 255) / 256;
+    case K_GRAD: return grad_blocks(g) + (g.nface * FG + 255) / 256;
+    case K_RES: return (g.ncell + RES_CELLS - 1) / RES_CELLS;
+    case K_CASE: return 1;
+    default: return 0;
+    }
 }
 
 }  // namespace gsis

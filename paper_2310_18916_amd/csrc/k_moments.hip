@@ -20,34 +20,54 @@
 
 namespace gsis {
 
+// loads of VW consecutive elements of a row (global memory), widened to FP64
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <typename T, int VW> struct VecLoad;
-template <> struct VecLoad<float, 1> { static __device__ void ld(const float *p, double *o) { o[0] = p[0]; } };
+template <> struct VecLoad<float, 1> { static __device__ void ld(gptr<const float> p, double *o) { o[0] = p[0]; } };
 template <> struct VecLoad<float, 2> {
-    static __device__ void ld(const float *p, double *o) { float2 v = *(const float2 *)p; o[0] = v.x; o[1] = v.y; }
+    static __device__ void ld(gptr<const float> p, double *o)
+    {
+        f32x2 v = *(gptr<const f32x2>)p;
+        o[0] = v.x; o[1] = v.y;
+    }
 };
 template <> struct VecLoad<float, 4> {
-    static __device__ void ld(const float *p, double *o)
+    static __device__ void ld(gptr<const float> p, double *o)
     {
-        float4 v = *(const float4 *)p;
+        f32x4 v = *(gptr<const f32x4>)p;
         o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
     }
 };
-template <> struct VecLoad<double, 1> { static __device__ void ld(const double *p, double *o) { o[0] = p[0]; } };
+template <> struct VecLoad<double, 1> { static __device__ void ld(gptr<const double> p, double *o) { o[0] = p[0]; } };
 template <> struct VecLoad<double, 2> {
-    static __device__ void ld(const double *p, double *o) { double2 v = *(const double2 *)p; o[0] = v.x; o[1] = v.y; }
+    static __device__ void ld(gptr<const double> p, double *o)
+    {
+        f64x2 v = *(gptr<const f64x2>)p;
+        o[0] = v.x; o[1] = v.y;
+    }
 };
 
 template <typename T, int VW, bool DIA>
-__global__ __launch_bounds__(512) void k_moments(Geo g, const T *__restrict__ f0, const T *__restrict__ f1,
-                                                 const int *__restrict__ cflag, const double *__restrict__ xtab,
-                                                 const double *__restrict__ ytab, const double *__restrict__ ztab,
-                                                 double *__restrict__ mom8)
+__global__ __launch_bounds__(512) void k_moments(GSIS_SPAN_ARGS)
 {
-    constexpr int CH = (DIA ? 64 : 128) / (VW * (int)sizeof(T));   // vectors per chunk: 128 B of row data per lane
-    const int cell = blockIdx.x;
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const gptr<const T> f0 = (gptr<const T>)C.d.f0;
+    const gptr<const T> f1 = (gptr<const T>)C.d.f1;
+    const gptr<const int> cflag = (gptr<const int>)C.d.cflag;
+    const gptr<const double> xtab = (gptr<const double>)C.d.xtab;
+    const gptr<const double> ytab = (gptr<const double>)C.d.ytab;
+    const gptr<const double> ztab = (gptr<const double>)C.d.ztab;
+    const gptr<double> mom8 = (gptr<double>)C.d.mom8;
+    constexpr int CH0 = (DIA ? 64 : 128) / (VW * (int)sizeof(T));   // vectors per chunk: 128 B of row data per lane
+    constexpr int CH = CH0 < 16 ? CH0 : 16;
+    const int cell = blk;
     const int o = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    double *out = mom8 + ((size_t)cell * 8 + o) * NRS;
+    const gptr<double> out = mom8 + ((size_t)cell * 8 + o) * NRS;
     if (!cflag[cell]) {
         if (lane < NRS) out[lane] = 0.0;
         return;
@@ -64,8 +84,8 @@ __global__ __launch_bounds__(512) void k_moments(Geo g, const T *__restrict__ f0
     double acc1[4] = {0.0, 0.0, 0.0, 0.0};
     for (int r = lane; r < nrow; r += 64) {
         const int ly = r % noy, lz = r / noy;
-        const T *row0 = f0 + base + (size_t)r * nox;
-        const T *row1 = DIA ? f1 + base + (size_t)r * nox : nullptr;
+        const gptr<const T> row0 = f0 + base + (size_t)r * nox;
+        const gptr<const T> row1 = DIA ? f1 + base + (size_t)r * nox : row0;
         double s0 = 0, s1 = 0, s2 = 0, s3 = 0, t0 = 0, t1 = 0;
         // a row is read in chunks of CH vectors whose loads are all issued
         // before any is used, so the lines of a row are fetched together
@@ -83,7 +103,7 @@ __global__ __launch_bounds__(512) void k_moments(Geo g, const T *__restrict__ f0
                 if (lx0 + c * VW >= nox) break;
 #pragma unroll
                 for (int e = 0; e < VW; ++e) {
-                    const double *xt = xtab + (size_t)(x0 + lx0 + c * VW + e) * 4;
+                    const gptr<const double> xt = xtab + (size_t)(x0 + lx0 + c * VW + e) * 4;
                     s0 += xt[0] * v[c][e];
                     s1 += xt[1] * v[c][e];
                     s2 += xt[2] * v[c][e];
@@ -133,9 +153,13 @@ __global__ __launch_bounds__(512) void k_moments(Geo g, const T *__restrict__ f0
 }
 
 // Central moments from the octant sums (octants added in a fixed order).
-__global__ void k_derive(Geo g, Dev d)
+__global__ __launch_bounds__(256) void k_derive(GSIS_SPAN_ARGS)
 {
-    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    int cell = blk * blockDim.x + threadIdx.x;
     if (cell >= g.ncell) return;
     double *out = d.cm + (size_t)cell * NMOM;
     if (!d.cflag[cell]) {
@@ -227,9 +251,13 @@ __device__ void octant_monomials(const double X[4], const double Y[4], const dou
 }
 
 // Octant sums += moments of M(W') - M(W) (and (dr/2)[Tr' M(W') - Tr M(W)] on f1).
-__global__ void k_commit_correction(Geo g, Dev d)
+__global__ __launch_bounds__(128) void k_commit_correction(GSIS_SPAN_ARGS)
 {
-    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    int cell = blk * blockDim.x + threadIdx.x;
     if (cell >= g.ncell || !d.cflag[cell]) return;
     const double *c = d.corr + (size_t)cell * NCORR;
     double Rn[3][2][4], Ro[3][2][4];
@@ -252,38 +280,36 @@ __global__ void k_commit_correction(Geo g, Dev d)
 
 // ------------------------------------------------------------------ launches
 template <typename T, int VW>
-static void moments_vw(const Geo &g, const Dev &d, hipStream_t s)
+static void moments_vw(const Target &t, hipStream_t s)
 {
-    if (g.species == 1)
-        hipLaunchKernelGGL((k_moments<T, VW, true>), dim3(g.ncell), dim3(512), 0, s, g, (const T *)d.f0,
-                           (const T *)d.f1, d.cflag, d.xtab, d.ytab, d.ztab, d.mom8);
+    if (t.dia)
+        hipLaunchKernelGGL((k_moments<T, VW, true>), dim3(t.nblk[K_CELL1]), dim3(512), 0, s, GSIS_SPAN(t.span(K_CELL1)));
     else
-        hipLaunchKernelGGL((k_moments<T, VW, false>), dim3(g.ncell), dim3(512), 0, s, g, (const T *)d.f0,
-                           (const T *)nullptr, d.cflag, d.xtab, d.ytab, d.ztab, d.mom8);
+        hipLaunchKernelGGL((k_moments<T, VW, false>), dim3(t.nblk[K_CELL1]), dim3(512), 0, s, GSIS_SPAN(t.span(K_CELL1)));
 }
 
-hipError_t launch_moments(const Geo &g, const Dev &d, bool fp32, int vw, hipStream_t s)
+hipError_t launch_moments(const Target &t, hipStream_t s)
 {
-    if (fp32) {
-        if (vw == 4) moments_vw<float, 4>(g, d, s);
-        else if (vw == 2) moments_vw<float, 2>(g, d, s);
-        else moments_vw<float, 1>(g, d, s);
+    if (t.fp32) {
+        if (t.vw == 4) moments_vw<float, 4>(t, s);
+        else if (t.vw == 2) moments_vw<float, 2>(t, s);
+        else moments_vw<float, 1>(t, s);
     } else {
-        if (vw >= 2) moments_vw<double, 2>(g, d, s);
-        else moments_vw<double, 1>(g, d, s);
+        if (t.vw >= 2) moments_vw<double, 2>(t, s);
+        else moments_vw<double, 1>(t, s);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_derive(const Geo &g, const Dev &d, hipStream_t s)
+hipError_t launch_derive(const Target &t, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_derive, dim3((g.ncell + 255) / 256), dim3(256), 0, s, g, d);
+    hipLaunchKernelGGL(k_derive, dim3(t.nblk[K_CELL256]), dim3(256), 0, s, GSIS_SPAN(t.span(K_CELL256)));
     return hipGetLastError();
 }
 
-hipError_t launch_commit_correction(const Geo &g, const Dev &d, hipStream_t s)
+hipError_t launch_commit_correction(const Target &t, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_commit_correction, dim3((g.ncell + 127) / 128), dim3(128), 0, s, g, d);
+    hipLaunchKernelGGL(k_commit_correction, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(t.span(K_CELL128)));
     return hipGetLastError();
 }
 

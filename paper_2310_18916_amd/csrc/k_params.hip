@@ -125,9 +125,13 @@ __device__ void correction(const Sep &S, double K, double rho, double T, const d
 //             7 P0t, 8-10 l_t, 11 l4t, 12-14 qp_t, 15 P0r, 16-18 l_r, 19 l4r, 20-22 qp_r,
 //             23 ht = (dr/2) Tr, 24-26 2 qr / (rho Tt), 27 nu_t,
 //             28 hr = (dr/2) T, 29-31 2 q1 / (rho T), 32 nu_r, 33 1/tau
-__global__ void k_params(Geo g, Dev d)
+__global__ __launch_bounds__(64) void k_params(GSIS_SPAN_ARGS)
 {
-    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    int cell = blk * blockDim.x + threadIdx.x;
     if (cell >= g.ncell) return;
     double *p = d.par + (size_t)cell * NPAR;
     float *pf = d.parf + (size_t)cell * NPAR;
@@ -224,9 +228,14 @@ __global__ void k_params(Geo g, Dev d)
 // mass flux of the cell's current state (from its octant sums) over the
 // incoming flux of M(1, u_w, T_w), so the discrete wall mass flux is zero;
 // inflow: the prescribed density.
-__global__ void k_face_scale(Geo g, BcInfo bc, Dev d)
+__global__ __launch_bounds__(256) void k_face_scale(GSIS_SPAN_ARGS)
 {
-    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const BcInfo &bc = C.bc;
+    const Dev &d = C.d;
+    int f = blk * blockDim.x + threadIdx.x;
     if (f >= g.nface) return;
     int cell = d.face_cell[f], dir = d.face_dir[f], b = d.face_bc[f];
     double sc;
@@ -247,15 +256,16 @@ __global__ void k_face_scale(Geo g, BcInfo bc, Dev d)
     d.cfs32[(size_t)cell * 6 + dir] = (float)sc;
 }
 
-hipError_t launch_params(const Geo &g, const Dev &d, hipStream_t s)
+hipError_t launch_params(const Target &t, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_params, dim3((g.ncell + 63) / 64), dim3(64), 0, s, g, d);
+    hipLaunchKernelGGL(k_params, dim3(t.nblk[K_CELL64]), dim3(64), 0, s, GSIS_SPAN(t.span(K_CELL64)));
     return hipGetLastError();
 }
 
-hipError_t launch_face_scale(const Geo &g, const BcInfo &bc, const Dev &d, hipStream_t s)
+hipError_t launch_face_scale(const Target &t, hipStream_t s)
 {
-    if (g.nface > 0) hipLaunchKernelGGL(k_face_scale, dim3((g.nface + 255) / 256), dim3(256), 0, s, g, bc, d);
+    if (t.nblk[K_FACE256] > 0)
+        hipLaunchKernelGGL(k_face_scale, dim3(t.nblk[K_FACE256]), dim3(256), 0, s, GSIS_SPAN(t.span(K_FACE256)));
     return hipGetLastError();
 }
 

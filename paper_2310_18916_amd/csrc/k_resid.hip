@@ -6,9 +6,16 @@
 
 namespace gsis {
 
-__global__ __launch_bounds__(256) void k_resid_partial(Geo g, Dev d)
+__host__ __device__ inline int resid_blocks_of(const Geo &g) { return (g.ncell + 255) / 256; }
+int resid_blocks(const Geo &g) { return resid_blocks_of(g); }
+
+__global__ __launch_bounds__(256) void k_resid_partial(GSIS_SPAN_ARGS)
 {
-    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    int cell = blk * blockDim.x + threadIdx.x;
     double v[6] = {0, 0, 0, 0, 0, 0};   // num rho, u, T; den rho, u, T
     if (cell < g.ncell && d.cflag[cell]) {
         const double *m = d.cm + (size_t)cell * NMOM;
@@ -33,11 +40,16 @@ __global__ __launch_bounds__(256) void k_resid_partial(Geo g, Dev d)
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int k = 0; k < 6; ++k) d.red[(size_t)blockIdx.x * 6 + k] = sh[k][0];
+        for (int k = 0; k < 6; ++k) d.red[(size_t)blk * 6 + k] = sh[k][0];
 }
 
-__global__ __launch_bounds__(256) void k_resid_final(Dev d, int nblk)
+// one block per case: the case's partial sums in block order
+__global__ __launch_bounds__(256) void k_resid_final(GSIS_SPAN_ARGS)
 {
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Dev &d = C.d;
+    const int nblk = resid_blocks_of(C.g);
     double v[6] = {0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblk; b += blockDim.x)
         for (int k = 0; k < 6; ++k) v[k] += d.red[(size_t)b * 6 + k];
@@ -49,13 +61,35 @@ __global__ __launch_bounds__(256) void k_resid_final(Dev d, int nblk)
             for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         for (int k = 0; k < 6; ++k) d.red[(size_t)nblk * 6 + k] = sh[k][0];
+        if (d.hist) {
+            const int it = *d.hist_ctr % d.hist_cap;
+            double *h = d.hist + ((size_t)it * d.hist_ncase + d.hist_index) * 6;
+            for (int k = 0; k < 6; ++k) h[k] = sh[k][0];
+        }
+    }
 }
 
-__global__ void k_snapshot(Geo g, Dev d)
+// advances the iteration counter of a batch's residual history
+__global__ void k_hist_advance(int *ctr)
 {
-    int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (threadIdx.x == 0) *ctr += 1;
+}
+
+hipError_t launch_hist_advance(int *ctr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_hist_advance, dim3(1), dim3(64), 0, s, ctr);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_snapshot(GSIS_SPAN_ARGS)
+{
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    int cell = blk * blockDim.x + threadIdx.x;
     if (cell >= g.ncell) return;
     const double *m = d.cm + (size_t)cell * NMOM;
     double *p = d.snap + (size_t)cell * NSNAP;
@@ -75,19 +109,16 @@ hipError_t launch_zero_int(int *p, int n, hipStream_t s)
     return hipGetLastError();
 }
 
-int resid_blocks(const Geo &g) { return (g.ncell + 255) / 256; }
-
-hipError_t launch_residual(const Geo &g, const Dev &d, hipStream_t s)
+hipError_t launch_residual(const Target &t, hipStream_t s)
 {
-    int nb = resid_blocks(g);
-    hipLaunchKernelGGL(k_resid_partial, dim3(nb), dim3(256), 0, s, g, d);
-    hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, s, d, nb);
+    hipLaunchKernelGGL(k_resid_partial, dim3(t.nblk[K_CELL256]), dim3(256), 0, s, GSIS_SPAN(t.span(K_CELL256)));
+    hipLaunchKernelGGL(k_resid_final, dim3(t.nblk[K_CASE]), dim3(256), 0, s, GSIS_SPAN(t.span(K_CASE)));
     return hipGetLastError();
 }
 
-hipError_t launch_snapshot(const Geo &g, const Dev &d, hipStream_t s)
+hipError_t launch_snapshot(const Target &t, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_snapshot, dim3((g.ncell + 255) / 256), dim3(256), 0, s, g, d);
+    hipLaunchKernelGGL(k_snapshot, dim3(t.nblk[K_CELL256]), dim3(256), 0, s, GSIS_SPAN(t.span(K_CELL256)));
     return hipGetLastError();
 }
 

@@ -52,16 +52,6 @@ template <> struct Arith<double> {
     }
 };
 
-struct SweepArgs {
-    Geo g;
-    void *f0, *f1;
-    const void *par;
-    const int *cflag, *tiles;
-    const void *fscale;    // [ncell][6] incoming density scale of boundary faces
-    const void *mb, *mb1;
-    const void *xi[3];
-};
-
 // g / tau at node (cx, cy, cz) = xi - u of a monatomic cell
 template <typename T>
 __device__ __forceinline__ T ref_mono(const T *p, T cx, T cy, T cz)
@@ -92,7 +82,7 @@ __device__ __forceinline__ void ref_dia(const T *p, T cx, T cy, T cz, T &g0, T &
 }
 
 template <typename T, int TX, int TY, bool DIA, bool RFN, bool MASK>
-__global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_off, int nvb)
+__global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
 {
     constexpr int NPL = DIA ? 36 : 16;            // parameters per cell kept in LDS
     constexpr int NC = TX * TY;                   // cells per slab
@@ -101,15 +91,20 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_of
     __shared__ T spar[2][NM];
     __shared__ int sflag[2][NC];
 
-    const Geo &g = A.g;
-    const int b = blockIdx.x;
+    int b;
+    const Case &C = case_of(span_cases, span_map, b);
+    const Geo &g = C.g;
+    constexpr bool F32 = sizeof(T) == 4;
+    const int TZ = C.tz, nvb = C.nvb;
+    const gptr<const int> cflag = (gptr<const int>)C.d.cflag;
+    const int plane_off = ((gptr<const int>)C.d.plane_off)[plane];
     const int vb = b % nvb;
     const int o = (b / nvb) & 7;
     const int t = b / (nvb * 8);
     const int bs = blockDim.x;
     const int l = vb * bs + threadIdx.x;
     const bool active = l < g.osize[o];           // inactive threads still join loads and barriers
-    const int packed = A.tiles[plane_off + t];
+    const int packed = ((gptr<const int>)C.d.tiles)[plane_off + t];
     const int tx = packed & 0x3ff, ty = (packed >> 10) & 0x3ff, tz = (packed >> 20) & 0x3ff;
     const int sx = o & 1, sy = (o >> 1) & 1, sz = (o >> 2) & 1;
     const int dxu = sx, dyu = 2 + sy, dzu = 4 + sz;   // upwind faces
@@ -122,9 +117,12 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_of
     if (active) {
         int kxn, kyn, kzn;
         node_of(g, o, l, kxn, kyn, kzn);
-        xix = ((const T *)A.xi[0])[kxn];
-        xiy = ((const T *)A.xi[1])[kyn];
-        xiz = ((const T *)A.xi[2])[kzn];
+        const gptr<const T> x0 = F32 ? (gptr<const T>)C.d.xi32[0] : (gptr<const T>)C.d.xi64[0];
+        const gptr<const T> x1 = F32 ? (gptr<const T>)C.d.xi32[1] : (gptr<const T>)C.d.xi64[1];
+        const gptr<const T> x2 = F32 ? (gptr<const T>)C.d.xi32[2] : (gptr<const T>)C.d.xi64[2];
+        xix = x0[kxn];
+        xiy = x1[kyn];
+        xiz = x2[kzn];
         node = (size_t)g.obase[o] + l;
     }
     const T ax = fabs(xix) * (T)g.invh[0];
@@ -132,12 +130,12 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_of
     const T az = fabs(xiz) * (T)g.invh[2];
     const T idt = (T)g.inv_dt;
     const T den0 = idt + ax + ay + az;
-    T *f0 = (T *)A.f0;
-    T *f1 = (T *)A.f1;
-    const T *par = (const T *)A.par;
-    const T *fsc = (const T *)A.fscale;
-    const T *mb = (const T *)A.mb;
-    const T *mb1 = (const T *)A.mb1;
+    const gptr<T> f0 = (gptr<T>)C.d.f0;
+    const gptr<T> f1 = (gptr<T>)C.d.f1;
+    const gptr<const T> par = F32 ? (gptr<const T>)C.d.parf : (gptr<const T>)C.d.par;
+    const gptr<const T> fsc = F32 ? (gptr<const T>)C.d.cfs32 : (gptr<const T>)C.d.cfs64;   // [ncell][6] incoming density scale
+    const gptr<const T> mb = F32 ? (gptr<const T>)C.d.mb32 : (gptr<const T>)C.d.mb64;
+    const gptr<const T> mb1 = F32 ? (gptr<const T>)C.d.mb1_32 : (gptr<const T>)C.d.mb1_64;
 
     // physical cell of tile-frame position, clamped into the domain (positions
     // outside are never computed; clamping keeps every speculative load valid)
@@ -162,7 +160,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_of
         const int bcs = outside ? d : 6;
         const T m0 = mb[(size_t)bcs * nv + node];
         bool wall = outside;
-        if (MASK) wall = wall || !A.cflag[nb];
+        if (MASK) wall = wall || !cflag[nb];
         v0 = wall ? sc * m0 : fv0;
         if (DIA) {
             const T fv1 = f1[(size_t)nb * nv + node];
@@ -193,8 +191,8 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_of
         const int e = min((int)threadIdx.x, NC - 1);
         const int c = cell_of(e % TX, e / TX, kz);
         const int cz = cell_of(e % TX, e / TX, kz > 0 ? kz - 1 : 0);
-        const int fl = (MASK ? A.cflag[c] : 1) && inside(e % TX, e / TX, kz);
-        const int zs = (MASK && kz > 0) ? !A.cflag[cz] : 0;
+        const int fl = (MASK ? cflag[c] : 1) && inside(e % TX, e / TX, kz);
+        const int zs = (MASK && kz > 0) ? !cflag[cz] : 0;
         freg = fl | (zs << 1);
     };
     auto store_meta = [&](int buf) {
@@ -247,8 +245,8 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs A, int TZ, int plane_of
                     const int flag = __builtin_amdgcn_readfirstlane(sflag[buf][e]);
                     if (!(flag & 1)) continue;     // outside the domain or solid
                     const int cell = cbase + kx * dxs + ky * dys;
-                    T *c0 = f0 + (size_t)cell * nv;   // uniform row; the lane adds its node
-                    T *c1 = DIA ? f1 + (size_t)cell * nv : nullptr;
+                    const gptr<T> c0 = f0 + (size_t)cell * nv;   // uniform row; the lane adds its node
+                    const gptr<T> c1 = DIA ? f1 + (size_t)cell * nv : f0;
                     const T *p = &spar[buf][e * NPL];
                     const T cx = xix - p[0], cy = xiy - p[1], cz = xiz - p[2];
                     T gt0, gt1 = T(0), invtau;
@@ -310,21 +308,20 @@ static const Shape kShapes32[] = {{4, 4}, {8, 4}, {8, 8}};
 static const Shape kShapes64[] = {{4, 4}, {8, 4}};
 
 template <typename T, int TX, int TY>
-static void sweep_plane(const SweepArgs &a, bool dia, bool rfn, int tz, int off, int ntile, int nvb, int bs,
-                        hipStream_t s)
+static void sweep_plane(const Target &t, int p, hipStream_t s)
 {
     constexpr bool kDia = TX * TY <= 32;   // two register planes only for the small slabs
-    dim3 grid((unsigned)(ntile * 8 * nvb));
-    const bool mask = a.g.nfluid != a.g.ncell;
-#define GSIS_SWEEP(D, R, M) hipLaunchKernelGGL((k_sweep<T, TX, TY, D, R, M>), grid, dim3(bs), 0, s, a, tz, off, nvb)
-    if (dia) {
+    const dim3 grid((unsigned)t.npblk[p]);
+    const Span sp{t.cases, t.pmap ? t.pmap[p] : nullptr};
+#define GSIS_SWEEP(D, R, M) hipLaunchKernelGGL((k_sweep<T, TX, TY, D, R, M>), grid, dim3(t.bs), 0, s, GSIS_SPAN(sp), p)
+    if (t.dia) {
         if constexpr (kDia) {
-            if (rfn) { if (mask) GSIS_SWEEP(true, true, true); else GSIS_SWEEP(true, true, false); }
-            else { if (mask) GSIS_SWEEP(true, false, true); else GSIS_SWEEP(true, false, false); }
+            if (t.rfn) { if (t.mask) GSIS_SWEEP(true, true, true); else GSIS_SWEEP(true, true, false); }
+            else { if (t.mask) GSIS_SWEEP(true, false, true); else GSIS_SWEEP(true, false, false); }
         }
     } else {
-        if (rfn) { if (mask) GSIS_SWEEP(false, true, true); else GSIS_SWEEP(false, true, false); }
-        else { if (mask) GSIS_SWEEP(false, false, true); else GSIS_SWEEP(false, false, false); }
+        if (t.rfn) { if (t.mask) GSIS_SWEEP(false, true, true); else GSIS_SWEEP(false, true, false); }
+        else { if (t.mask) GSIS_SWEEP(false, false, true); else GSIS_SWEEP(false, false, false); }
     }
 #undef GSIS_SWEEP
 }
@@ -353,37 +350,19 @@ int sweep_shapes(bool fp32, int *out, int max)
     return n;
 }
 
-hipError_t launch_sweep(const Geo &g, const Dev &d, bool fp32, int tx, int ty, int tz, int bs,
-                        const int *plane_off, const int *plane_cnt, int nplane, hipStream_t s)
+hipError_t launch_sweep(const Target &t, hipStream_t s)
 {
-    SweepArgs a;
-    a.g = g;
-    a.f0 = d.f0;
-    a.f1 = d.f1;
-    a.par = fp32 ? (const void *)d.parf : (const void *)d.par;
-    a.cflag = d.cflag;
-    a.tiles = d.tiles;
-    a.fscale = fp32 ? (const void *)d.cfs32 : (const void *)d.cfs64;
-    a.mb = fp32 ? (const void *)d.mb32 : (const void *)d.mb64;
-    a.mb1 = fp32 ? (const void *)d.mb1_32 : (const void *)d.mb1_64;
-    for (int ax = 0; ax < 3; ++ax) a.xi[ax] = fp32 ? (const void *)d.xi32[ax] : (const void *)d.xi64[ax];
-    int omax = 0;
-    for (int o = 0; o < 8; ++o) omax = g.osize[o] > omax ? g.osize[o] : omax;
-    int nvb = (omax + bs - 1) / bs;
-    bool dia = g.species == 1;
-    bool rfn = g.inv_dt != 0.0;
-    for (int p = 0; p < nplane; ++p) {
-        int off = plane_off[p], n = plane_cnt[p];
-        if (n == 0) continue;
-        if (fp32) {
-            if (tx == 4 && ty == 4) sweep_plane<float, 4, 4>(a, dia, rfn, tz, off, n, nvb, bs, s);
-            else if (tx == 8 && ty == 4) sweep_plane<float, 8, 4>(a, dia, rfn, tz, off, n, nvb, bs, s);
-            else if (tx == 8 && ty == 8 && !dia) sweep_plane<float, 8, 8>(a, dia, rfn, tz, off, n, nvb, bs, s);
-            else return hipErrorInvalidValue;
+    const int tx = t.tx, ty = t.ty;
+    if (!sweep_shape_supported(t.fp32, t.dia, tx, ty)) return hipErrorInvalidValue;
+    for (int p = 0; p < t.nplane; ++p) {
+        if (t.npblk[p] == 0) continue;
+        if (t.fp32) {
+            if (tx == 4 && ty == 4) sweep_plane<float, 4, 4>(t, p, s);
+            else if (tx == 8 && ty == 4) sweep_plane<float, 8, 4>(t, p, s);
+            else sweep_plane<float, 8, 8>(t, p, s);
         } else {
-            if (tx == 4 && ty == 4) sweep_plane<double, 4, 4>(a, dia, rfn, tz, off, n, nvb, bs, s);
-            else if (tx == 8 && ty == 4) sweep_plane<double, 8, 4>(a, dia, rfn, tz, off, n, nvb, bs, s);
-            else return hipErrorInvalidValue;
+            if (tx == 4 && ty == 4) sweep_plane<double, 4, 4>(t, p, s);
+            else sweep_plane<double, 8, 4>(t, p, s);
         }
     }
     return hipGetLastError();

@@ -213,3 +213,128 @@ class Solver(Context):
 
     def synchronize(self):
         self.torch.cuda.current_stream().synchronize()
+
+
+class BatchMember(Solver):
+    """One case of a Batch: a context bound inside the batch's workspace.  The
+    per-case calls of Solver work on it, on the batch's stream."""
+
+    def __init__(self, ctx: Context, batch: "Batch"):
+        import torch
+        self.torch = torch
+        self.case, self.dtype, self.L, self._cfg = ctx.case, ctx.dtype, ctx.L, ctx._cfg
+        self.h = ctx.h
+        self._ctx = ctx          # owns the handle
+        self._batch = batch      # keeps the workspace alive
+        self.nmom = _lib.NMOM[ctx.case.species]
+
+    def get_vdf(self):
+        with self.torch.cuda.stream(self._batch.stream):
+            out = super().get_vdf()
+        self._batch.synchronize()
+        return out
+
+    def moments_device(self):
+        with self.torch.cuda.stream(self._batch.stream):
+            out = super().moments_device()
+        self._batch.synchronize()
+        return out
+
+    def synchronize(self):
+        self._batch.synchronize()
+
+    def close(self):
+        self.h = None            # the context destroys the handle
+
+
+class Batch:
+    """Independent cases iterated together (gsis_batch_*): one launch per kernel
+    covers every case, and a GSIS iteration replays as one captured HIP graph.
+    Device memory and the (non-null) stream come from PyTorch."""
+
+    def __init__(self, cases, dtype: str = "fp32", tile: Optional[Tuple[int, int, int, int]] = None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libgsis needs a GPU; none is visible")
+        self.torch = torch
+        self.L = _lib.lib()
+        self.cases = list(cases)
+        self.ctxs = [Context(c, dtype) for c in self.cases]
+        arr = (C.c_void_p * len(self.ctxs))(*[c.h.value for c in self.ctxs])
+        h = C.c_void_p()
+        st = self.L.gsis_batch_create(C.byref(h), arr, len(self.ctxs))
+        if st:
+            raise GsisError(st, "gsis_batch_create", "cases must share precision and gas and use inv_dt = 0")
+        self.h = h
+        self.stream = torch.cuda.Stream()
+        self._check(self.L.gsis_batch_set_stream(self.h, C.c_void_p(self.stream.cuda_stream)), "gsis_batch_set_stream")
+        if tile is not None:
+            self.set_tile(*tile)
+        n = C.c_size_t()
+        self._check(self.L.gsis_batch_workspace_size(self.h, C.byref(n)), "gsis_batch_workspace_size")
+        self.ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        torch.cuda.current_stream().synchronize()
+        self._check(self.L.gsis_batch_bind_workspace(self.h, C.c_void_p(self.ws.data_ptr()), n.value),
+                    "gsis_batch_bind_workspace")
+        self.members = [BatchMember(c, self) for c in self.ctxs]
+
+    def _check(self, st: int, where: str):
+        if st:
+            msg = self.L.gsis_batch_last_error(self.h)
+            raise GsisError(st, where, msg.decode() if msg else "")
+
+    def __len__(self):
+        return len(self.members)
+
+    def __getitem__(self, i) -> BatchMember:
+        return self.members[i]
+
+    def set_tile(self, tx: int, ty: int, tz: int, block: int):
+        self._check(self.L.gsis_batch_set_tile(self.h, tx, ty, tz, block), "gsis_batch_set_tile")
+
+    def get_tile(self):
+        t = (C.c_int * 4)()
+        self._check(self.L.gsis_batch_get_tile(self.h, t), "gsis_batch_get_tile")
+        return tuple(t)
+
+    def autotune(self, reps: int = 2):
+        cfg = (C.c_int * 512)()
+        ms = (C.c_double * 128)()
+        n = C.c_int()
+        self._check(self.L.gsis_batch_autotune(self.h, reps, cfg, ms, 128, C.byref(n)), "gsis_batch_autotune")
+        return [((cfg[4 * k], cfg[4 * k + 1], cfg[4 * k + 2], cfg[4 * k + 3]), ms[k]) for k in range(n.value)]
+
+    def init_maxwellian(self, rho=1.0, u=(0.0, 0.0, 0.0), T=1.0, Tr=1.0):
+        self._check(self.L.gsis_batch_init_maxwellian(self.h, rho, (C.c_double * 3)(*u), T, Tr),
+                    "gsis_batch_init_maxwellian")
+
+    def run(self, iters: int, inner_iters: int, graph: bool = True):
+        self._check(self.L.gsis_batch_run(self.h, iters, inner_iters, int(graph)), "gsis_batch_run")
+
+    def residuals(self, max_iters: int = 1024) -> np.ndarray:
+        """[iteration, case, (rho, |u|, Tt)] of the recorded iterations, oldest first."""
+        out = np.empty((max_iters, len(self), 3), dtype=np.float64)
+        n = C.c_int()
+        self._check(self.L.gsis_batch_residuals(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), max_iters,
+                                                C.byref(n)), "gsis_batch_residuals")
+        return out[:n.value].copy()
+
+    def last_run_ms(self) -> float:
+        ms = C.c_double()
+        self._check(self.L.gsis_batch_last_run_ms(self.h, C.byref(ms)), "gsis_batch_last_run_ms")
+        return ms.value
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.stream.synchronize()
+            self.L.gsis_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
