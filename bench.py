@@ -32,6 +32,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp32", action="store_true")
     p.add_argument("--tile", default=None, help="tx,ty,tz,block")
+    p.add_argument("--no-converge", action="store_true", help="skip the time-to-convergence runs")
+    p.add_argument("--no-batch", action="store_true", help="skip the 64-cavity batched run")
+    p.add_argument("--batch-iters", type=int, default=50)
     p.add_argument("--copy-calib-mib", type=int, default=0,
                    help="after the run, copy a buffer of this many MiB three times (HBM counter calibration)")
     return p.parse_args()
@@ -96,6 +99,94 @@ def run_gpu(case, dtype, steps, warmup, macro_iters, tile):
     prof = s.profile_read(reset=True)
     return {"seconds": t1 - t0, "prof": prof, "eps": [float(x) for x in eps], "solver": s, "tune": tune,
             "tile": s.get_tile()}
+
+
+def converge(case, dtype, tile, tol=1e-6, max_iters=200):
+    """GSIS iterations from the initial state until the relative change of rho and
+    T drops below tol (the convergence test of the workload); returns iterations,
+    wall time and the converged moments."""
+    import torch
+    from paper_2310_18916_amd.gsis import Solver
+    s = Solver(case, dtype, tile=tuple(tile))
+    s.init_maxwellian()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it, eps = 0, None
+    while it < max_iters:
+        s.kinetic_step(1)
+        s.gsis_correct(case.macro_iters)
+        eps = s.residual()
+        it += 1
+        if eps[0] < tol and eps[2] < tol:
+            break
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"iterations": it, "seconds": dt, "eps": [float(x) for x in eps]}, s.moments()
+
+
+def field_diff(a, b):
+    """max relative difference of rho, T and u (u relative to max |u|)."""
+    import numpy as np
+    return {"rho": float(np.abs(a[:, 0] - b[:, 0]).max() / np.abs(b[:, 0]).max()),
+            "T": float(np.abs(a[:, 4] - b[:, 4]).max() / np.abs(b[:, 4]).max()),
+            "u": float(np.abs(a[:, 1:4] - b[:, 1:4]).max() / max(np.abs(b[:, 1:4]).max(), 1e-300))}
+
+
+def batched(iters):
+    """The 64-cavity workload as one batch (FP32 VDF, captured GSIS iteration,
+    autotuned tile) against the plain path: each cavity alone in FP64."""
+    import torch
+    from paper_2310_18916_amd import inputs as I
+    from paper_2310_18916_amd.gsis import Batch, Solver
+    cases = I.c5()
+    pts = sum(c.nfluid * c.nvel for c in cases)
+    out = {"workload": "c5_64_cavities", "cases": len(cases), "points_per_pass": pts, "iterations": iters}
+    res = {}
+    for dtype in ("fp32", "fp64"):
+        b = Batch(cases, dtype)
+        b.init_maxwellian()
+        tune = sorted(b.autotune(reps=1), key=lambda r: r[1])
+        b.run(1, cases[0].macro_iters, graph=True)      # capture + first replay
+        b.synchronize()
+        t0 = time.perf_counter()
+        b.run(iters, cases[0].macro_iters, graph=True)
+        b.synchronize()
+        dt = time.perf_counter() - t0
+        res[dtype] = {"seconds": dt, "ms_per_iteration": dt / iters * 1e3, "value": pts * iters / dt,
+                      "tile": list(b.get_tile()), "device_ms": b.last_run_ms(),
+                      "eps_last_max": [float(x) for x in b.residuals()[-1].max(axis=0)],
+                      "moments": [b[i].moments() for i in range(len(cases))], "tune_best": tune[0]}
+        b.close()
+        del b
+        torch.cuda.empty_cache()
+    diffs = [field_diff(a, c) for a, c in zip(res["fp32"]["moments"], res["fp64"]["moments"])]
+    worst = {k: max(d[k] for d in diffs) for k in ("rho", "T", "u")}
+    # plain path: every cavity alone, FP64, direct launches; per-iteration time measured
+    # over 2 iterations after one warm iteration, scaled to the batch's iteration count
+    plain = 0.0
+    for c in cases:
+        s = Solver(c, "fp64")
+        s.init_maxwellian()
+        s.kinetic_step(1)
+        s.gsis_correct(c.macro_iters)
+        s.residual()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            s.kinetic_step(1)
+            s.gsis_correct(c.macro_iters)
+            s.residual()
+        torch.cuda.synchronize()
+        plain += (time.perf_counter() - t0) / 2
+        del s
+    for k in ("fp32", "fp64"):
+        res[k].pop("moments")
+    out.update({"fp32": res["fp32"], "fp64": res["fp64"],
+                "fp32_vs_fp64_batch_max_rel_diff": worst,
+                "plain_fp64_single_ms_per_iteration": plain * 1e3,
+                "speedup_fp32_batch_vs_plain_fp64": plain / (res["fp32"]["seconds"] / iters),
+                "speedup_fp64_batch_vs_plain_fp64": plain / (res["fp64"]["seconds"] / iters)})
+    return out
 
 
 def cpu_baseline(case, budget_s=12.0):
@@ -199,6 +290,14 @@ def main():
                        "phases_ms_per_step": {k: v[0] / steps for k, v in r32["prof"].items()},
                        "autotune_top": [[list(c), round(ms, 4)] for c, ms in (r32["tune"] or [])[:6]]}
         del r32
+    if not a.no_converge and case.gsis and dtype == "fp64":
+        c64, m64 = converge(case, "fp64", out["sweep_tile"])
+        c32, m32 = converge(case, "fp32", out["fp32"]["sweep_tile"] if "fp32" in out else out["sweep_tile"])
+        out["converged"] = {"tol": 1e-6, "fp64": c64, "fp32": c32,
+                            "fp32_vs_fp64_max_rel_diff": field_diff(m32, m64),
+                            "speedup_fp32_vs_fp64_time_to_converge": c64["seconds"] / c32["seconds"]}
+    if not a.no_batch:
+        out["batched"] = batched(a.batch_iters)
     if a.copy_calib_mib > 0:
         out["copy_calibration"] = copy_calibration(a.copy_calib_mib)
     if not a.no_cpu_baseline:
