@@ -74,7 +74,7 @@ struct Dev {
     int *plane_off;    // [nplane] first tile of each plane in tiles
     double *corr;      // [ncell][NCORR]
     double *snap;      // [ncell][NSNAP]
-    double *W, *P, *grad, *K, *hot, *R, *Dc, *Src, *fbfix, *Fb, *Gb;   // macroscopic solve
+    double *W, *W2, *P, *grad, *K, *hot, *R, *Dc, *Src, *fbfix, *Fb, *Gb;   // macroscopic solve (W double buffered)
     double *red;       // reduction scratch
     unsigned long long *dmax;   // two slots, bit pattern of a positive double
     int *errflag;

@@ -218,6 +218,7 @@ size_t layout(gsis_ctx *c, char *base)
     carve(off, d.corr, n * NCORR, base);
     carve(off, d.snap, n * NSNAP, base);
     carve(off, d.W, n * 6, base);
+    carve(off, d.W2, n * 6, base);
     carve(off, d.P, n * 12, base);
     carve(off, d.grad, n * 9, base);
     carve(off, d.K, n * 12, base);

@@ -422,22 +422,77 @@ __global__ __launch_bounds__(384) void k_mac_res(GSIS_SPAN_ARGS, int slot)
     if (lane == 0 && D > 0.0) atomicMax(&d.dmax[slot], (unsigned long long)__double_as_longlong(D));
 }
 
-// W += R / D* and the new prims.
-__global__ __launch_bounds__(256) void k_mac_update(GSIS_SPAN_ARGS, int slot)
+// W of a cell after the pseudo-time step: W + R / D*, the rotational-energy
+// row with its relaxation source on the diagonal.
+__device__ __forceinline__ void stepped_W(const Geo &g, const Dev &d, const double *Ws, int cell, double Dm, double Wn[6])
+{
+    const double *W = Ws + (size_t)cell * 6;
+    const double *r = d.R + (size_t)cell * 6;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Wn[k] = W[k] + r[k] / Dm;
+    Wn[5] = g.species == 1 ? W[5] + r[5] / (Dm + d.Src[cell]) : W[5];
+}
+
+// End of an inner iteration: W' = W + R / D* with the new prims, and -- unless
+// it is the last iteration -- the velocity gradient and the boundary-face
+// fluxes of the new state, in one launch.  Grid as k_mac_grad: (cell, axis)
+// threads (axis 0 also writes W' and the prims of its cell), then FG lanes per
+// boundary face.  Neighbours' new velocities and the face cells' new prims are
+// formed from W and R directly, so W is double buffered (read src, write dst).
+__global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, int parity, int last)
 {
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
     const Geo &g = C.g;
     const Dev &d = C.d;
-    int cell = blk * blockDim.x + threadIdx.x;
-    if (cell == 0) d.dmax[slot ^ 1] = 0ull;   // the other slot was last used by the previous iteration
-    if (cell >= g.ncell || !d.cflag[cell]) return;
-    double Dm = __longlong_as_double((long long)d.dmax[slot]);
-    double *W = d.W + (size_t)cell * 6;
-    const double *r = d.R + (size_t)cell * 6;
-    for (int k = 0; k < 5; ++k) W[k] += r[k] / Dm;
-    if (g.species == 1) W[5] += r[5] / (Dm + d.Src[cell]);
-    prim_from_W(g, W, d.P + (size_t)cell * NP);
+    const BcInfo &bc = C.bc;
+    const double *Ws = parity ? d.W2 : d.W;
+    double *Wd = parity ? d.W : d.W2;
+    const double Dm = __longlong_as_double((long long)d.dmax[slot]);
+    const int ngrad = grad_blocks(g);
+    if (blk < ngrad) {
+        const int t = blk * blockDim.x + threadIdx.x;
+        if (t == 0) d.dmax[slot ^ 1] = 0ull;   // the other slot was last used by the previous iteration
+        const int cell = t / 3, a = t - 3 * (t / 3);
+        if (cell >= g.ncell || !d.cflag[cell]) return;
+        double Wn[6];
+        stepped_W(g, d, Ws, cell, Dm, Wn);
+        if (a == 0) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Wd[(size_t)cell * 6 + k] = Wn[k];
+            prim_from_W(g, Wn, d.P + (size_t)cell * NP);
+        }
+        if (last) return;
+        const int nm = d.nbr[(size_t)cell * 6 + 2 * a], np = d.nbr[(size_t)cell * 6 + 2 * a + 1];
+        double um[3], up[3];
+        double Wm[6], Wp[6];
+        if (nm >= 0) stepped_W(g, d, Ws, nm, Dm, Wm);
+        if (np >= 0) stepped_W(g, d, Ws, np, Dm, Wp);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double uc = Wn[1 + b] / Wn[0];
+            um[b] = nm >= 0 ? Wm[1 + b] / Wm[0] : uc;
+            up[b] = np >= 0 ? Wp[1 + b] / Wp[0] : uc;
+        }
+        const double h = g.h[a];
+        const double den = (nm >= 0 && np >= 0) ? 2.0 * h : h;
+        double *G = d.grad + (size_t)cell * 9;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) G[b * 3 + a] = (nm < 0 && np < 0) ? 0.0 : (up[b] - um[b]) / den;
+        return;
+    }
+    if (last) return;
+    const int f = ((blk - ngrad) * (int)blockDim.x + (int)threadIdx.x) / FG;
+    const int sub = threadIdx.x & (FG - 1);
+    if (f >= g.nface) return;
+    const int cell = d.face_cell[f], dir = d.face_dir[f];
+    double Wn[6], P[NP];
+    stepped_W(g, d, Ws, cell, Dm, Wn);
+    prim_from_W(g, Wn, P);
+    double Fe[6];
+    group_equilibrium_flux(g, bc, d, P, dir, d.face_bc[f], sub, Fe);
+    if (sub < 6) d.Fb[(size_t)f * 6 + sub] = d.fbfix[(size_t)f * 6 + sub] + Fe[sub];
+    if (sub == 7) d.Gb[f] = boundary_gamma(g, P, dir / 2);
 }
 
 // one block per case
@@ -472,11 +527,11 @@ hipError_t launch_gsis_macro(const Target &t, int iters, hipStream_t s)
     hipLaunchKernelGGL(k_mac_hot, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(t.span(K_CELL128)));
     if (t.nblk[K_FACE8] > 0) hipLaunchKernelGGL(k_mac_fbfix, dim3(t.nblk[K_FACE8]), dim3(256), 0, s, GSIS_SPAN(t.span(K_FACE8)));
     for (int it = 0; it < iters; ++it) {
-        int slot = it & 1;
-        if (it > 0) hipLaunchKernelGGL(k_mac_grad, dim3(t.nblk[K_GRAD]), dim3(256), 0, s, GSIS_SPAN(t.span(K_GRAD)), 1);
+        const int slot = it & 1;
         if (t.dia) hipLaunchKernelGGL(k_mac_res<true>, dim3(t.nblk[K_RES]), dim3(384), 0, s, GSIS_SPAN(t.span(K_RES)), slot);
         else hipLaunchKernelGGL(k_mac_res<false>, dim3(t.nblk[K_RES]), dim3(384), 0, s, GSIS_SPAN(t.span(K_RES)), slot);
-        hipLaunchKernelGGL(k_mac_update, dim3(t.nblk[K_CELL256]), dim3(256), 0, s, GSIS_SPAN(t.span(K_CELL256)), slot);
+        hipLaunchKernelGGL(k_mac_advance, dim3(t.nblk[K_GRAD]), dim3(256), 0, s, GSIS_SPAN(t.span(K_GRAD)), slot, it & 1,
+                           it == iters - 1 ? 1 : 0);
     }
     hipLaunchKernelGGL(k_mac_final, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(t.span(K_CELL128)));
     return hipGetLastError();
