@@ -48,7 +48,7 @@ struct BcInfo {
 
 // Device buffers, carved out of the caller's workspace.
 struct Dev {
-    void *f0, *f1;
+    void *f0, *f1;     // [ncell + 1][nv]: row ncell is the sink of the sweep's stores for dead cells
     double *mom8;      // [ncell][8][NRS]
     double *cm;        // [ncell][NMOM]
     double *par;       // [ncell][NPAR]
@@ -132,6 +132,43 @@ __device__ __forceinline__ double wave_sum(double v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// One halving step of a transposing wave reduction: lanes with bit M set keep
+// the upper half of their H + H values, the others the lower half, and each
+// adds its partner's copy of the half it keeps.
+template <int M, int H, int N>
+__device__ __forceinline__ void halve(double (&v)[N], int lane, int &base)
+{
+    const bool hi = (lane & M) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const double send = hi ? v[i] : v[i + H];
+        const double keep = hi ? v[i + H] : v[i];
+        v[i] = keep + __shfl_xor(send, M, 64);
+    }
+    if (hi) base += H;
+}
+
+// Sums N (16 or 32) values over the 64 lanes of a wave in a fixed order with
+// about N shuffles instead of N * 6: afterwards every lane holds the total of
+// value *idx, and each value is held by the 64 / N lanes that share idx.
+template <int N>
+__device__ __forceinline__ double wave_reduce_scatter(double (&v)[N], int lane, int *idx)
+{
+    static_assert(N == 16 || N == 32, "16 or 32 values");
+    int base = 0;
+    if (N == 32) halve<32, 16>(v, lane, base);
+    if (N == 32) halve<16, 8>(v, lane, base); else halve<32, 8>(v, lane, base);
+    if (N == 32) halve<8, 4>(v, lane, base); else halve<16, 4>(v, lane, base);
+    if (N == 32) halve<4, 2>(v, lane, base); else halve<8, 2>(v, lane, base);
+    if (N == 32) halve<2, 1>(v, lane, base); else halve<4, 1>(v, lane, base);
+    double r = v[0];
+    constexpr int rest = 64 / N;   // lanes that still hold partial sums of the same value
+#pragma unroll
+    for (int m = 1; m < rest; m <<= 1) r += __shfl_xor(r, m, 64);
+    *idx = base;
+    return r;
 }
 
 // Maxwellian rho (pi T)^{-3/2} exp(-|xi - u|^2 / T) in units of sqrt(2 R T0).

@@ -179,8 +179,8 @@ size_t layout(gsis_ctx *c, char *base)
     size_t off = 0, n = g.ncell, nv = g.nv, esz = c->fp32 ? 4 : 8;
     size_t nf = std::max(g.nface, 1);
     char *f0 = nullptr, *f1 = nullptr;
-    carve(off, f0, n * nv * esz, base);
-    if (g.species == 1) carve(off, f1, n * nv * esz, base);
+    carve(off, f0, (n + 1) * nv * esz, base);
+    if (g.species == 1) carve(off, f1, (n + 1) * nv * esz, base);
     d.f0 = f0;
     d.f1 = f1;
     carve(off, d.mom8, n * 8 * NRS, base);

@@ -141,15 +141,15 @@ __global__ __launch_bounds__(512) void k_moments(GSIS_SPAN_ARGS)
             acc1[3] += Z1 * t0;
         }
     }
-    double res[NRS];
+    // transposing reduction: lane groups end with one of the NRS sums each
+    constexpr int NR = DIA ? 32 : 16;
+    double v[NR];
 #pragma unroll
-    for (int k = 0; k < 13; ++k) res[k] = wave_sum(acc[k]);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) res[13 + k] = DIA ? wave_sum(acc1[k]) : 0.0;
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < NRS; ++k) out[k] = res[k];
-    }
+    for (int k = 0; k < NR; ++k) v[k] = k < 13 ? acc[k < 13 ? k : 0] : (DIA && k < NRS ? acc1[k < NRS ? k - 13 : 0] : 0.0);
+    int idx;
+    const double r = wave_reduce_scatter<NR>(v, lane, &idx);
+    if ((lane & (64 / NR - 1)) == 0 && idx < NRS) out[idx] = r;
+    if (!DIA && lane == 0) out[NRS - 1] = 0.0;   // 13..15 come from the zero padding
 }
 
 // Central moments from the octant sums (octants added in a fixed order).

@@ -56,10 +56,12 @@ template <> struct Arith<double> {
 template <typename T>
 __device__ __forceinline__ T ref_mono(const T *p, T cx, T cy, T cz)
 {
-    T c2 = cx * cx + cy * cy + cz * cz;
-    T t = c2 * p[3];
-    T E = p[4] * Arith<T>::ex(-t);
-    T poly = p[5] + p[6] * cx + p[7] * cy + p[8] * cz + p[9] * c2 + (p[10] * cx + p[11] * cy + p[12] * cz) * (t - T(2.5));
+#pragma clang fp contract(off)
+    const T c2 = fma(cz, cz, fma(cy, cy, cx * cx));
+    const T t = c2 * p[3];
+    const T E = p[4] * Arith<T>::ex(-t);
+    const T q = fma(p[12], cz, fma(p[11], cy, p[10] * cx));
+    const T poly = fma(q, t - T(2.5), fma(p[9], c2, fma(p[8], cz, fma(p[7], cy, fma(p[6], cx, p[5])))));
     return E * poly;
 }
 
@@ -67,23 +69,27 @@ __device__ __forceinline__ T ref_mono(const T *p, T cx, T cy, T cz)
 template <typename T>
 __device__ __forceinline__ void ref_dia(const T *p, T cx, T cy, T cz, T &g0, T &g1)
 {
-    T c2 = cx * cx + cy * cy + cz * cz;
-    T tt = c2 * p[3], tr = c2 * p[4];
-    T Et = p[5] * Arith<T>::ex(-tt);
-    T Er = p[6] * Arith<T>::ex(-tr);
-    T sht = (p[12] * cx + p[13] * cy + p[14] * cz) * (tt - T(2.5));
-    T shr = (p[20] * cx + p[21] * cy + p[22] * cz) * (tr - T(2.5));
-    T lt = p[7] + p[8] * cx + p[9] * cy + p[10] * cz + p[11] * c2;
-    T lr = p[15] + p[16] * cx + p[17] * cy + p[18] * cz + p[19] * c2;
-    T rt = p[23] * (T(1) + sht) + p[24] * cx + p[25] * cy + p[26] * cz + p[27];
-    T rr = p[28] * (T(1) + shr) + p[29] * cx + p[30] * cy + p[31] * cz + p[32];
-    g0 = Et * (lt + sht) + Er * (lr + shr);
-    g1 = Et * rt + Er * rr;
+#pragma clang fp contract(off)
+    const T c2 = fma(cz, cz, fma(cy, cy, cx * cx));
+    const T tt = c2 * p[3], tr = c2 * p[4];
+    const T Et = p[5] * Arith<T>::ex(-tt);
+    const T Er = p[6] * Arith<T>::ex(-tr);
+    const T sht = fma(p[14], cz, fma(p[13], cy, p[12] * cx)) * (tt - T(2.5));
+    const T shr = fma(p[22], cz, fma(p[21], cy, p[20] * cx)) * (tr - T(2.5));
+    const T lt = fma(p[11], c2, fma(p[10], cz, fma(p[9], cy, fma(p[8], cx, p[7]))));
+    const T lr = fma(p[19], c2, fma(p[18], cz, fma(p[17], cy, fma(p[16], cx, p[15]))));
+    const T rt = fma(p[26], cz, fma(p[25], cy, fma(p[24], cx, fma(p[23], T(1) + sht, p[27]))));
+    const T rr = fma(p[31], cz, fma(p[30], cy, fma(p[29], cx, fma(p[28], T(1) + shr, p[32]))));
+    g0 = fma(Et, lt + sht, Er * (lr + shr));
+    g1 = fma(Et, rt, Er * rr);
 }
 
 template <typename T, int TX, int TY, bool DIA, bool RFN, bool MASK>
 __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
 {
+    // no automatic contraction: every fused multiply-add is written out, so the
+    // operations of a cell update do not depend on the surrounding code
+#pragma clang fp contract(off)
     constexpr int NPL = DIA ? 36 : 16;            // parameters per cell kept in LDS
     constexpr int NC = TX * TY;                   // cells per slab
     constexpr int NM = NC * NPL;                  // parameter words per slab
@@ -109,7 +115,7 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
     const int sx = o & 1, sy = (o >> 1) & 1, sz = (o >> 2) & 1;
     const int dxu = sx, dyu = 2 + sy, dzu = 4 + sz;   // upwind faces
     const int i0 = tx * TX, j0 = ty * TY, k0 = tz * TZ;
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int nx = g.nx, ny = g.ny, nz = g.nz, ncell = g.ncell;
     const size_t nv = (size_t)g.nv;
 
     T xix = T(0), xiy = T(0), xiz = T(0);
@@ -242,11 +248,16 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
 #pragma unroll
                 for (int kx = 0; kx < TX; ++kx) {
                     const int e = ky * TX + kx;
-                    const int flag = __builtin_amdgcn_readfirstlane(sflag[buf][e]);
-                    if (!(flag & 1)) continue;     // outside the domain or solid
+                    // Every cell of the slab is computed, so the slab is straight-line
+                    // code; a cell outside the domain or solid stores into the sink row
+                    // (row ncell) and its value is never used upwind.
+                    const int flag = MASK ? __builtin_amdgcn_readfirstlane(sflag[buf][e]) : 1;
+                    const bool live = MASK ? (flag & 1) != 0 : (i0 + kx < nx && j0 + ky < ny);
                     const int cell = cbase + kx * dxs + ky * dys;
-                    const gptr<T> c0 = f0 + (size_t)cell * nv;   // uniform row; the lane adds its node
-                    const gptr<T> c1 = DIA ? f1 + (size_t)cell * nv : f0;
+                    const int cread = live ? cell : 0;   // in-range index for side reads
+                    const int row = live ? cell : ncell;
+                    const gptr<T> c0 = f0 + (size_t)row * nv;   // uniform row; the lane adds its node
+                    const gptr<T> c1 = DIA ? f1 + (size_t)row * nv : c0;
                     const T *p = &spar[buf][e * NPL];
                     const T cx = xix - p[0], cy = xiy - p[1], cz = xiz - p[2];
                     T gt0, gt1 = T(0), invtau;
@@ -259,24 +270,24 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
                     }
                     T num0 = gt0, num1 = gt1;
                     if (RFN) {
-                        num0 += idt * c0[lnode];
-                        if (DIA) num1 += idt * c1[lnode];
+                        num0 = fma(idt, (T)c0[lnode], num0);
+                        if (DIA) num1 = fma(idt, (T)c1[lnode], num1);
                     }
                     T F0, F1 = T(0);
                     if (kx == 0) { F0 = xin0[ky]; if (DIA) F1 = xin1[ky]; }
-                    else if (MASK && !(__builtin_amdgcn_readfirstlane(sflag[buf][e - 1]) & 1)) solid_face(cell, dxu, F0, F1);
+                    else if (MASK && !(__builtin_amdgcn_readfirstlane(sflag[buf][e - 1]) & 1)) solid_face(cread, dxu, F0, F1);
                     else { F0 = pl0[ky][kx - 1]; if (DIA) F1 = pl1[ky][kx - 1]; }
-                    num0 += ax * F0;
-                    if (DIA) num1 += ax * F1;
+                    num0 = fma(ax, F0, num0);
+                    if (DIA) num1 = fma(ax, F1, num1);
                     if (ky == 0) { F0 = yin0[kx]; if (DIA) F1 = yin1[kx]; }
-                    else if (MASK && !(__builtin_amdgcn_readfirstlane(sflag[buf][e - TX]) & 1)) solid_face(cell, dyu, F0, F1);
+                    else if (MASK && !(__builtin_amdgcn_readfirstlane(sflag[buf][e - TX]) & 1)) solid_face(cread, dyu, F0, F1);
                     else { F0 = pl0[ky - 1][kx]; if (DIA) F1 = pl1[ky - 1][kx]; }
-                    num0 += ay * F0;
-                    if (DIA) num1 += ay * F1;
-                    if (MASK && (flag & 2)) solid_face(cell, dzu, F0, F1);
+                    num0 = fma(ay, F0, num0);
+                    if (DIA) num1 = fma(ay, F1, num1);
+                    if (MASK && (flag & 2)) solid_face(cread, dzu, F0, F1);
                     else { F0 = pl0[ky][kx]; if (DIA) F1 = pl1[ky][kx]; }
-                    num0 += az * F0;
-                    if (DIA) num1 += az * F1;
+                    num0 = fma(az, F0, num0);
+                    if (DIA) num1 = fma(az, F1, num1);
                     const T den = den0 + invtau;
                     const T v0 = Arith<T>::div(num0, den);
                     c0[lnode] = v0;
