@@ -112,7 +112,7 @@ void orc_free(orc_state *s)
     free(s);
 }
 
-orc_state *orc_create(const orc_cfg *cfg, const unsigned char *solid)
+static orc_state *create_state(const orc_cfg *cfg, const unsigned char *solid, int with_vdf)
 {
     if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return NULL;
     for (int a = 0; a < 3; ++a)
@@ -137,12 +137,18 @@ orc_state *orc_create(const orc_cfg *cfg, const unsigned char *solid)
             s->w1[a][k] = (k == 0 || k == n - 1) ? 0.5 * d : d;   /* trapezoid */
         }
     }
+    s->prev = calloc((size_t)s->ncell * 5, sizeof(double));
+    if (!with_vdf) return s;
     size_t np = (size_t)s->ncell * s->nv;
     s->f0 = calloc(np, sizeof(double));
     if (cfg->species == 1) s->f1 = calloc(np, sizeof(double));
-    s->prev = calloc((size_t)s->ncell * 5, sizeof(double));
     if (!s->f0 || (cfg->species == 1 && !s->f1)) { orc_free(s); return NULL; }
     return s;
+}
+
+orc_state *orc_create(const orc_cfg *cfg, const unsigned char *solid)
+{
+    return create_state(cfg, solid, 1);
 }
 
 int orc_ncell(const orc_state *s) { return s->ncell; }
@@ -421,13 +427,66 @@ static void boundary_value(const orc_cfg *c, int bc, double scale, const double 
     *b1 = 0.5 * c->dr * c->bc_T[bc] * (*b0);
 }
 
+void orc_init_maxwellian(orc_state *s, double rho, const double u[3], double T, double Tr);
+
 /* --------------------------------------------------------------- sweep -- */
-/* One kinetic pass: Sec. 3.2, backward Euler in pseudo time with first-order
- * upwind fluxes.  For node xi and fluid cell i, with a_a = |xi_a| / h_a:
+/* The kinetic update of one velocity node v over all cells: Sec. 3.2,
+ * backward Euler in pseudo time with first-order upwind fluxes.  With
+ * a_a = |xi_a| / h_a, for fluid cell i
  *   f_i^{n+1/2} = [f_i^n / dt + g_i / tau_i + sum_a a_a F_a] / (1/dt + 1/tau_i + sum_a a_a),
  * F_a = f^{n+1/2} of the upwind cell, or the boundary value of the shared face.
  * Cells are visited in the upwind lexicographic order of the node's octant,
- * which solves the lower-triangular system exactly.  In place. */
+ * which solves the lower-triangular system exactly.  col0 (col1) holds the
+ * node's values of every cell: f^n on entry, f^{n+1/2} on return. */
+static void sweep_node(const orc_state *s, int v, const cellpar *P, const double *scale, const int *nb,
+                       double *col0, double *col1)
+{
+    const orc_cfg *c = &s->c;
+    int dia = c->species == 1;
+    int nx = c->nx, ny = c->ny, nz = c->nz;
+    double xi[3], w;
+    node_xi(s, v, xi, &w);
+    int sg[3];
+    double aa[3];
+    for (int a = 0; a < 3; ++a) { sg[a] = xi[a] >= 0 ? 1 : -1; aa[a] = fabs(xi[a]) / s->h[a]; }
+    for (int kk = 0; kk < nz; ++kk) {
+        int k = sg[2] > 0 ? kk : nz - 1 - kk;
+        for (int jj = 0; jj < ny; ++jj) {
+            int j = sg[1] > 0 ? jj : ny - 1 - jj;
+            for (int ii = 0; ii < nx; ++ii) {
+                int i = sg[0] > 0 ? ii : nx - 1 - ii;
+                int cell = cell_index(s, i, j, k);
+                if (s->solid[cell]) continue;
+                double g0, g1;
+                ref_dist(c, &P[cell], xi, &g0, &g1);
+                double it = P[cell].invtau;
+                double num0 = c->inv_dt * col0[cell] + it * g0;
+                double num1 = dia ? c->inv_dt * col1[cell] + it * g1 : 0.0;
+                double den = c->inv_dt + it;
+                for (int a = 0; a < 3; ++a) {
+                    if (aa[a] == 0.0) continue;
+                    int d = 2 * a + (sg[a] > 0 ? 0 : 1);   /* upwind face */
+                    int n = nb[cell * 6 + d];
+                    double F0, F1;
+                    if (n >= 0) {
+                        F0 = col0[n];
+                        F1 = dia ? col1[n] : 0.0;
+                    } else {
+                        boundary_value(c, -1 - n, scale[cell * 6 + d], xi, &F0, &F1);
+                    }
+                    num0 += aa[a] * F0;
+                    num1 += aa[a] * F1;
+                    den += aa[a];
+                }
+                col0[cell] = num0 / den;
+                if (dia) col1[cell] = num1 / den;
+            }
+        }
+    }
+}
+
+/* One kinetic pass: per-cell parameters and boundary densities from f^n,
+ * then every node swept independently (the wall density is lagged), in place. */
 static int one_pass(orc_state *s)
 {
     const orc_cfg *c = &s->c;
@@ -449,52 +508,78 @@ static int one_pass(orc_state *s)
         if (s->solid[cell]) continue;
         if (!isfinite(P[cell].invtau) || !(P[cell].m.rho > 0) || !(P[cell].m.Tt > 0)) s->status = -5;
     }
-    int nx = c->nx, ny = c->ny, nz = c->nz;
-    #pragma omp parallel for schedule(dynamic, 1)
-    for (int v = 0; v < nv; ++v) {
-        double xi[3], w;
-        node_xi(s, v, xi, &w);
-        int sg[3];
-        double aa[3];
-        for (int a = 0; a < 3; ++a) { sg[a] = xi[a] >= 0 ? 1 : -1; aa[a] = fabs(xi[a]) / s->h[a]; }
-        for (int kk = 0; kk < nz; ++kk) {
-            int k = sg[2] > 0 ? kk : nz - 1 - kk;
-            for (int jj = 0; jj < ny; ++jj) {
-                int j = sg[1] > 0 ? jj : ny - 1 - jj;
-                for (int ii = 0; ii < nx; ++ii) {
-                    int i = sg[0] > 0 ? ii : nx - 1 - ii;
-                    int cell = cell_index(s, i, j, k);
-                    if (s->solid[cell]) continue;
-                    size_t at = (size_t)cell * nv + v;
-                    double g0, g1;
-                    ref_dist(c, &P[cell], xi, &g0, &g1);
-                    double it = P[cell].invtau;
-                    double num0 = c->inv_dt * s->f0[at] + it * g0;
-                    double num1 = dia ? c->inv_dt * s->f1[at] + it * g1 : 0.0;
-                    double den = c->inv_dt + it;
-                    for (int a = 0; a < 3; ++a) {
-                        if (aa[a] == 0.0) continue;
-                        int d = 2 * a + (sg[a] > 0 ? 0 : 1);   /* upwind face */
-                        int n = nb[cell * 6 + d];
-                        double F0, F1;
-                        if (n >= 0) {
-                            F0 = s->f0[(size_t)n * nv + v];
-                            F1 = dia ? s->f1[(size_t)n * nv + v] : 0.0;
-                        } else {
-                            boundary_value(c, -1 - n, scale[cell * 6 + d], xi, &F0, &F1);
-                        }
-                        num0 += aa[a] * F0;
-                        num1 += aa[a] * F1;
-                        den += aa[a];
-                    }
-                    s->f0[at] = num0 / den;
-                    if (dia) s->f1[at] = num1 / den;
-                }
+    #pragma omp parallel
+    {
+        double *col0 = malloc(sizeof(double) * (size_t)ncell);
+        double *col1 = dia ? malloc(sizeof(double) * (size_t)ncell) : NULL;
+        #pragma omp for schedule(dynamic, 1)
+        for (int v = 0; v < nv; ++v) {
+            for (int cell = 0; cell < ncell; ++cell) {
+                col0[cell] = s->f0[(size_t)cell * nv + v];
+                if (dia) col1[cell] = s->f1[(size_t)cell * nv + v];
+            }
+            sweep_node(s, v, P, scale, nb, col0, col1);
+            for (int cell = 0; cell < ncell; ++cell) {
+                if (s->solid[cell]) continue;
+                s->f0[(size_t)cell * nv + v] = col0[cell];
+                if (dia) s->f1[(size_t)cell * nv + v] = col1[cell];
             }
         }
+        free(col0);
+        free(col1);
     }
     free(P); free(scale); free(nb);
     return s->status;
+}
+
+/* The first pass from a uniform Maxwellian at selected nodes only, for
+ * problems too large to hold the VDF: every fluid cell then has the same
+ * f^n, so one cell's parameters and its wall densities (per face direction
+ * and boundary slot) serve all cells, and the nodes are swept as in
+ * one_pass.  out0[k][cell] (out1 for f1) = f^{n+1/2} at canonical node
+ * nodes[k]; solid cells are 0.  Returns the status of the parameters. */
+int orc_first_pass_nodes(const orc_cfg *cfg, const unsigned char *solid, double rho, const double u[3], double T,
+                         double Tr, const int *nodes, int nn, double *out0, double *out1)
+{
+    orc_cfg one = *cfg;
+    one.nx = one.ny = one.nz = 1;
+    orc_state *s1 = create_state(&one, NULL, 1);
+    orc_state *s = create_state(cfg, solid, 0);
+    if (!s1 || !s) { orc_free(s1); orc_free(s); return -3; }
+    orc_init_maxwellian(s1, rho, u, T, Tr);
+    cellpar p1;
+    cell_params(s1, 0, &p1);
+    int status = (!isfinite(p1.invtau) || !(p1.m.rho > 0) || !(p1.m.Tt > 0)) ? -5 : 0;
+    double sc[6][ORC_NBC];
+    for (int d = 0; d < 6; ++d)
+        for (int b = 0; b < ORC_NBC; ++b) sc[d][b] = face_scale(s1, 0, d, b);
+    int ncell = s->ncell, dia = cfg->species == 1;
+    cellpar *P = malloc(sizeof(cellpar) * (size_t)ncell);
+    double *scale = malloc(sizeof(double) * (size_t)ncell * 6);
+    int *nb = malloc(sizeof(int) * (size_t)ncell * 6);
+    for (int cell = 0; cell < ncell; ++cell) {
+        P[cell] = p1;
+        for (int d = 0; d < 6; ++d) {
+            int n = neighbour(s, cell, d);
+            nb[cell * 6 + d] = n;
+            scale[cell * 6 + d] = n >= 0 ? 0.0 : sc[d][-1 - n];
+        }
+    }
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < nn; ++k) {
+        double *col0 = out0 + (size_t)k * ncell;
+        double *col1 = dia ? out1 + (size_t)k * ncell : NULL;
+        for (int cell = 0; cell < ncell; ++cell) {
+            int fl = !s->solid[cell];
+            col0[cell] = fl ? s1->f0[nodes[k]] : 0.0;
+            if (dia) col1[cell] = fl ? s1->f1[nodes[k]] : 0.0;
+        }
+        sweep_node(s, nodes[k], P, scale, nb, col0, col1);
+    }
+    free(P); free(scale); free(nb);
+    orc_free(s1);
+    orc_free(s);
+    return status;
 }
 
 int orc_step(orc_state *s, int npasses)

@@ -71,6 +71,8 @@ def lib():
         L.orc_ref_components.argtypes = [C.POINTER(_Cfg), C.c_double, D, C.c_double, C.c_double, D, D,
                                          C.c_int, D, D]
         L.orc_conductivities.argtypes = [C.POINTER(_Cfg), D]
+        L.orc_first_pass_nodes.argtypes = [C.POINTER(_Cfg), C.c_void_p, C.c_double, D, C.c_double, C.c_double,
+                                           C.POINTER(C.c_int), C.c_int, D, D]
         _lib = L
     return _lib
 
@@ -201,6 +203,23 @@ def conductivities(case) -> np.ndarray:
     out = np.empty(2)
     lib().orc_conductivities(C.byref(cfg), _dp(out))
     return out
+
+
+def first_pass_nodes(case, nodes):
+    """f^{n+1/2} after one pass from the case's uniform initial Maxwellian, at
+    canonical nodes only: ([k][cell] f0, [k][cell] f1 or None, status).  Needs no
+    VDF in memory, so it serves the full-size workloads."""
+    cfg = make_cfg(case)
+    nodes = np.ascontiguousarray(nodes, dtype=np.int32)
+    nn, n = nodes.size, case.ncell
+    out0 = np.zeros((nn, n))
+    out1 = np.zeros((nn, n)) if case.species == 1 else None
+    mask = np.ascontiguousarray(case.solid_mask(), dtype=np.uint8)
+    rho, u, T, Tr = case.init
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    st = lib().orc_first_pass_nodes(C.byref(cfg), mask.ctypes.data_as(C.c_void_p), rho, _dp(u), T, Tr,
+                                    nodes.ctypes.data_as(C.POINTER(C.c_int)), nn, _dp(out0), _dp(out1))
+    return out0, out1, st
 
 
 def node_grid(case):

@@ -463,3 +463,24 @@ def test_residual_definition():
     assert abs(eps[0] - er) <= 1e-12 * er
     assert abs(eps[1] - eu) <= 1e-12 * eu
     assert abs(eps[2] - eT) <= 1e-12 * eT
+
+
+@pytest.mark.parametrize("which", ["cavity", "block", "n2_block", "finite_dt"])
+def test_first_pass_nodes_equals_full_pass(which):
+    """The sampled first pass (no VDF held, one cell's parameters for all) is
+    the full oracle pass at those nodes, bit for bit."""
+    from oracle.oracle import Oracle, first_pass_nodes
+    case = {"cavity": I.cavity(5, 7, 0.1, lid=0.2), "block": I.small_block(m=8),
+            "n2_block": I.small_block(species=I.DIATOMIC, m=8),
+            "finite_dt": I.cavity(4, 6, 0.3, lid=0.1, inv_dt=2.0)}[which]
+    o = Oracle(case)
+    o.init_maxwellian()
+    o.step(1)
+    f0, f1 = o.get_vdf()
+    nodes = np.array([0, 3, case.nvel // 2, case.nvel - 1, 17 % case.nvel])
+    s0, s1, st = first_pass_nodes(case, nodes)
+    assert st == 0
+    fluid = ~case.solid_mask().astype(bool)
+    assert np.array_equal(s0[:, fluid], f0[fluid][:, nodes].T)
+    if f1 is not None:
+        assert np.array_equal(s1[:, fluid], f1[fluid][:, nodes].T)
