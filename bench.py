@@ -26,7 +26,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    p.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+                   help="c5 runs only the 64-cavity batch")
     p.add_argument("--dtype", default=None, choices=["fp64", "fp32"])
     p.add_argument("--macro-iters", type=int, default=None)
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -65,7 +66,7 @@ def sweep_traffic(dtype, tile, workload_name):
 
 def workload(name):
     from paper_2310_18916_amd import inputs as I
-    return {"c1": I.c1, "c2": I.c2, "c3": I.c3}[name]()
+    return {"c1": I.c1, "c2": I.c2, "c3": I.c3, "c4": I.c4}[name]()
 
 
 def run_gpu(case, dtype, steps, warmup, macro_iters, tile):
@@ -197,8 +198,14 @@ def cpu_baseline(case, budget_s=12.0):
     from paper_2310_18916_amd import inputs as I
     if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
         build()
-    n = 16
-    sample = I.cavity(n, case.nv[0], case.Kn, lid=case.bcs[5].u[0], vmax=case.vmax[0], omega=case.omega)
+    if case.solid is None:
+        n = 16
+        sample = I.cavity(n, case.nv[0], case.Kn, lid=case.bcs[5].u[0], vmax=case.vmax[0], omega=case.omega)
+        shape = f"a {n}^3-cell cavity"
+    else:
+        sample = I.block_flow(16, 12, 12, ((6, 10), (4, 8), (4, 8)), case.nv[0], case.vmax[0], case.Kn,
+                              species=case.species, omega=case.omega)
+        shape = "a 16x12x12-cell block flow"
     o = Oracle(sample)
     o.init_maxwellian()
     passes = 0
@@ -213,8 +220,8 @@ def cpu_baseline(case, budget_s=12.0):
     cores = len(os.sched_getaffinity(0))
     threads = int(os.environ.get("OMP_NUM_THREADS", cores))
     return {"value": pts / dt, "unit": "cell-updates/s", "cores": min(cores, threads), "kind": "oracle",
-            "sample": f"{passes} FP64 kinetic passes of the oracle on a {n}^3-cell cavity x {sample.nv[0]}^3 nodes "
-                      f"(same velocity grid and Kn), {dt:.2f} s"}
+            "sample": f"{passes} FP64 kinetic passes of the oracle on {shape} x {sample.nv[0]}^3 nodes "
+                      f"(same velocity grid, gas and Kn), {dt:.2f} s"}
 
 
 def copy_calibration(mib):
@@ -235,8 +242,11 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the path is single-GPU by design",
               file=sys.stderr)
         sys.exit(2)
+    if a.workload == "c5":
+        print(json.dumps({"batched": batched(a.batch_iters)}), flush=True)
+        return
     case = workload(a.workload)
-    dtype = a.dtype or ("fp32" if a.workload == "c3" else "fp64")
+    dtype = a.dtype or ("fp32" if a.workload in ("c3", "c4") else "fp64")
     macro = a.macro_iters if a.macro_iters is not None else case.macro_iters
     tile = tuple(int(x) for x in a.tile.split(",")) if a.tile else None
     r = run_gpu(case, dtype, a.steps, a.warmup, macro, tile)
@@ -283,20 +293,21 @@ def main():
         "autotune_top": [[list(c), round(ms, 4)] for c, ms in (r["tune"] or [])[:6]],
     }
     del r
-    if not a.no_fp32 and dtype == "fp64":
-        r32 = run_gpu(case, "fp32", steps, a.warmup, macro, None)
-        v32 = pts * steps / r32["seconds"]
-        out["fp32"] = {"value": v32, "speedup_vs_fp64": v32 / value, "sweep_tile": r32["tile"],
-                       "phases_ms_per_step": {k: v[0] / steps for k, v in r32["prof"].items()},
-                       "autotune_top": [[list(c), round(ms, 4)] for c, ms in (r32["tune"] or [])[:6]]}
-        del r32
+    if not a.no_fp32:
+        other = "fp32" if dtype == "fp64" else "fp64"
+        ro = run_gpu(case, other, steps, a.warmup, macro, None)
+        vo = pts * steps / ro["seconds"]
+        out[other] = {"value": vo, "speedup_fp32_vs_fp64": vo / value if other == "fp32" else value / vo,
+                      "sweep_tile": ro["tile"], "phases_ms_per_step": {k: v[0] / steps for k, v in ro["prof"].items()},
+                      "autotune_top": [[list(c), round(ms, 4)] for c, ms in (ro["tune"] or [])[:6]]}
+        del ro
     if not a.no_converge and case.gsis and dtype == "fp64":
         c64, m64 = converge(case, "fp64", out["sweep_tile"])
         c32, m32 = converge(case, "fp32", out["fp32"]["sweep_tile"] if "fp32" in out else out["sweep_tile"])
         out["converged"] = {"tol": 1e-6, "fp64": c64, "fp32": c32,
                             "fp32_vs_fp64_max_rel_diff": field_diff(m32, m64),
                             "speedup_fp32_vs_fp64_time_to_converge": c64["seconds"] / c32["seconds"]}
-    if not a.no_batch:
+    if not a.no_batch and a.workload == "c2":
         out["batched"] = batched(a.batch_iters)
     if a.copy_calib_mib > 0:
         out["copy_calibration"] = copy_calibration(a.copy_calib_mib)
