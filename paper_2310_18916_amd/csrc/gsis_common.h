@@ -54,7 +54,7 @@ struct Dev {
     double *par;       // [ncell][NPAR]
     float *parf;       // [ncell][NPAR]
     int *cflag;        // [ncell] 1 = fluid
-    int *nbr;          // [ncell][6]: neighbour cell, or -(face + 1)
+    int *nbr;          // [6][ncell]: neighbour cell, or -(face + 1)
     int *face_cell, *face_dir, *face_bc;   // [nface]
     double *fscale;    // [nface] density scale of the incoming half
     float *fscalef;
@@ -74,7 +74,10 @@ struct Dev {
     int *plane_off;    // [nplane] first tile of each plane in tiles
     double *corr;      // [ncell][NCORR]
     double *snap;      // [ncell][NSNAP]
-    double *W, *W2, *P, *grad, *K, *hot, *R, *Dc, *Src, *fbfix, *Fb, *Gb;   // macroscopic solve (W double buffered)
+    // macroscopic solve, all structures of arrays [field][ncell] ([field][nface]
+    // for fbfix, Fb): W (double buffered), prims P, velocity gradient, kinetic
+    // stress/heat flux K, HoT of the three + faces, residual R
+    double *W, *W2, *P, *grad, *K, *hot, *R, *Dc, *Src, *fbfix, *Fb, *Gb;
     double *red;       // reduction scratch
     unsigned long long *dmax;   // two slots, bit pattern of a positive double
     int *errflag;

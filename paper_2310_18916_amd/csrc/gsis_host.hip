@@ -528,7 +528,13 @@ gsis_status gsis_bind_workspace(gsis_ctx *ctx, void *device_ptr, size_t bytes)
     Dev &d = ctx->d;
     auto up = [&](void *dst, const void *src, size_t nbytes) { return hipMemcpy(dst, src, nbytes, hipMemcpyHostToDevice); };
     HIPCHK(ctx, up(d.cflag, ctx->cflag.data(), ctx->cflag.size() * sizeof(int)));
-    HIPCHK(ctx, up(d.nbr, ctx->nbr.data(), ctx->nbr.size() * sizeof(int)));
+    {
+        // the device copy is direction-major, [6][ncell], so a wave of consecutive cells reads consecutive words
+        std::vector<int> nt(ctx->nbr.size());
+        for (int cell = 0; cell < g.ncell; ++cell)
+            for (int dir = 0; dir < 6; ++dir) nt[(size_t)dir * g.ncell + cell] = ctx->nbr[(size_t)cell * 6 + dir];
+        HIPCHK(ctx, up(d.nbr, nt.data(), nt.size() * sizeof(int)));
+    }
     if (g.nface > 0) {
         HIPCHK(ctx, up(d.face_cell, ctx->face_cell.data(), g.nface * sizeof(int)));
         HIPCHK(ctx, up(d.face_dir, ctx->face_dir.data(), g.nface * sizeof(int)));

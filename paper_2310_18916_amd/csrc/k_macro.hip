@@ -28,9 +28,18 @@ namespace gsis {
 // prims per cell: rho, ux, uy, uz, Tt, Tr, E, Er, c_s, Tt^omega / delta, 1/tau, (unused)
 constexpr int NP = 12;
 
-__device__ __forceinline__ double sound(const Geo &g, const double *P) { return sqrt(g.gam * P[4] / 2.0); }
+// The per-cell (per-face) arrays of the macroscopic solve are structures of
+// arrays: field k of item i at buf[k * n + i], so the lanes of a wave, which
+// take consecutive cells, read consecutive words.  Soa is one item's view.
+template <typename T> struct Soa {
+    T *p;
+    size_t n;
+    __device__ __forceinline__ T &operator[](int k) const { return p[(size_t)k * n]; }
+};
+template <typename T> __device__ __forceinline__ Soa<T> soa(T *buf, size_t n, int i) { return Soa<T>{buf + i, n}; }
 
-__device__ __forceinline__ void prim_from_W(const Geo &g, const double *W, double *P)
+template <class PV>
+__device__ __forceinline__ void prim_from_W(const Geo &g, const double *W, PV P)
 {
     double rho = W[0];
     double u0 = W[1] / rho, u1 = W[2] / rho, u2 = W[3] / rho;
@@ -47,9 +56,9 @@ __device__ __forceinline__ void prim_from_W(const Geo &g, const double *W, doubl
     P[11] = 0.0;
 }
 
-__device__ __forceinline__ void nsf_face(const Geo &g, const double *L, const double *R, const double *gL,
-                                         const double *gR, int a, double h, double mu, double sigN[3], double *qN,
-                                         double *qrN)
+template <class PV, class GV>
+__device__ __forceinline__ void nsf_face(const Geo &g, const PV &L, const PV &R, const GV &gL, const GV &gR, int a,
+                                         double h, double mu, double sigN[3], double *qN, double *qrN)
 {
     double G[9];
     for (int b = 0; b < 3; ++b)
@@ -63,7 +72,8 @@ __device__ __forceinline__ void nsf_face(const Geo &g, const double *L, const do
 }
 
 // convective flux vector Phi(W).n and the state vector of one side
-__device__ __forceinline__ void side(const double *P, int a, double Phi[6], double Wv[6])
+template <class PV>
+__device__ __forceinline__ void side(const PV &P, int a, double Phi[6], double Wv[6])
 {
     double rho = P[0], un = P[1 + a], p = P[0] * P[4];
     Phi[0] = rho * un;
@@ -78,9 +88,9 @@ __device__ __forceinline__ void side(const double *P, int a, double Phi[6], doub
     Wv[5] = P[7];
 }
 
-__device__ __forceinline__ void face_flux(const Geo &g, const double *L, const double *R, const double *gL,
-                                          const double *gR, int a, double h, const double *hot, double F[6],
-                                          double *Gam)
+template <class PV, class GV, class HV>
+__device__ __forceinline__ void face_flux(const Geo &g, const PV &L, const PV &R, const GV &gL, const GV &gR, int a,
+                                          double h, const HV &hot, double F[6], double *Gam)
 {
     const double TF = 0.5 * (L[4] + R[4]), rF = 0.5 * (L[0] + R[0]);
     const double tw = pow(TF, g.omega);
@@ -123,7 +133,8 @@ __device__ __forceinline__ double group_sum(double v)
     return v;
 }
 
-__device__ void group_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev &d, const double *P, int dir, int b,
+template <class PV>
+__device__ void group_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev &d, const PV &P, int dir, int b,
                                        int sub, double F[6])
 {
     const int a = dir / 2;
@@ -177,7 +188,8 @@ __device__ void group_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev
 }
 
 // Gamma of a boundary face: outward speed plus the diffusive term of the cell
-__device__ __forceinline__ double boundary_gamma(const Geo &g, const double *P, int a)
+template <class PV>
+__device__ __forceinline__ double boundary_gamma(const Geo &g, const PV &P, int a)
 {
     return fabs(P[1 + a]) + P[8] + g.Cd * P[9] / (P[0] * g.h[a]);
 }
@@ -195,32 +207,35 @@ __global__ __launch_bounds__(128) void k_mac_init(GSIS_SPAN_ARGS)
     double rho = m[0], Tt = m[4];
     double uu = m[1] * m[1] + m[2] * m[2] + m[3] * m[3];
     double Er = g.species == 1 ? 0.5 * g.dr * rho * m[14] : 0.0;
-    double *W = d.W + (size_t)cell * 6;
+    const size_t n = g.ncell;
+    double W[6];
     W[0] = rho;
     W[1] = rho * m[1]; W[2] = rho * m[2]; W[3] = rho * m[3];
     W[4] = rho * uu + 1.5 * rho * Tt + Er;
     W[5] = Er;
-    double *K = d.K + (size_t)cell * 12;
+    const Soa<double> Wd = soa(d.W, n, cell);
+    for (int k = 0; k < 6; ++k) Wd[k] = W[k];
+    const Soa<double> K = soa(d.K, n, cell);
     for (int k = 0; k < 6; ++k) K[k] = m[5 + k];
     for (int k = 0; k < 3; ++k) K[6 + k] = m[11 + k];
     for (int k = 0; k < 3; ++k) K[9 + k] = g.species == 1 ? m[15 + k] : 0.0;
     double *c = d.corr + (size_t)cell * NCORR;
     c[6] = rho; c[7] = m[1]; c[8] = m[2]; c[9] = m[3]; c[10] = Tt;
     c[11] = g.species == 1 ? m[14] : Tt;
-    prim_from_W(g, W, d.P + (size_t)cell * NP);
+    prim_from_W(g, W, soa(d.P, n, cell));
 }
 
 // Column a of the velocity gradient of one cell: central differences, one-sided
 // next to a non-fluid neighbour, zero with none.
 __device__ void cell_grad_col(const Geo &g, const Dev &d, int cell, int a)
 {
-    const int nm = d.nbr[(size_t)cell * 6 + 2 * a], np = d.nbr[(size_t)cell * 6 + 2 * a + 1];
-    const double *Pc = d.P + (size_t)cell * NP;
-    const double *Pm = nm >= 0 ? d.P + (size_t)nm * NP : Pc;
-    const double *Pp = np >= 0 ? d.P + (size_t)np * NP : Pc;
+    const int nm = d.nbr[(size_t)(2 * a) * g.ncell + cell], np = d.nbr[(size_t)(2 * a + 1) * g.ncell + cell];
+    const size_t n = g.ncell;
+    const Soa<double> Pm = soa(d.P, n, nm >= 0 ? nm : cell);
+    const Soa<double> Pp = soa(d.P, n, np >= 0 ? np : cell);
     const double h = g.h[a];
     const double den = (nm >= 0 && np >= 0) ? 2.0 * h : h;
-    double *G = d.grad + (size_t)cell * 9;
+    const Soa<double> G = soa(d.grad, n, cell);
 #pragma unroll
     for (int b = 0; b < 3; ++b) G[b * 3 + a] = (nm < 0 && np < 0) ? 0.0 : (Pp[1 + b] - Pm[1 + b]) / den;
 }
@@ -248,10 +263,10 @@ __global__ __launch_bounds__(256) void k_mac_grad(GSIS_SPAN_ARGS, int with_faces
     const int sub = threadIdx.x & (FG - 1);
     if (f >= g.nface) return;
     const int cell = d.face_cell[f], dir = d.face_dir[f];
-    const double *P = d.P + (size_t)cell * NP;
+    const Soa<double> P = soa(d.P, g.ncell, cell);
     double Fe[6];
     group_equilibrium_flux(g, bc, d, P, dir, d.face_bc[f], sub, Fe);
-    if (sub < 6) d.Fb[(size_t)f * 6 + sub] = d.fbfix[(size_t)f * 6 + sub] + Fe[sub];
+    if (sub < 6) d.Fb[(size_t)sub * g.nface + f] = d.fbfix[(size_t)sub * g.nface + f] + Fe[sub];
     if (sub == 7) d.Gb[f] = boundary_gamma(g, P, dir / 2);
 }
 
@@ -265,18 +280,19 @@ __global__ __launch_bounds__(128) void k_mac_hot(GSIS_SPAN_ARGS)
     int cell = blk * blockDim.x + threadIdx.x;
     if (cell >= g.ncell || !d.cflag[cell]) return;
     const int col[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    const size_t n = g.ncell;
     for (int a = 0; a < 3; ++a) {
-        int nb = d.nbr[(size_t)cell * 6 + 2 * a + 1];
-        double *ho = d.hot + (size_t)cell * 15 + a * 5;
+        int nb = d.nbr[(size_t)(2 * a + 1) * g.ncell + cell];
+        const Soa<double> ho = soa(d.hot + (size_t)a * 5 * n, n, cell);
         if (nb < 0) {
             for (int k = 0; k < 5; ++k) ho[k] = 0.0;
             continue;
         }
         double sigN[3], qN, qrN;
-        const double *PL = d.P + (size_t)cell * NP, *PR = d.P + (size_t)nb * NP;
-        nsf_face(g, PL, PR, d.grad + (size_t)cell * 9, d.grad + (size_t)nb * 9, a, g.h[a],
+        const Soa<double> PL = soa(d.P, n, cell), PR = soa(d.P, n, nb);
+        nsf_face(g, PL, PR, soa(d.grad, n, cell), soa(d.grad, n, nb), a, g.h[a],
                  pow(0.5 * (PL[4] + PR[4]), g.omega) / g.delta, sigN, &qN, &qrN);
-        const double *Ki = d.K + (size_t)cell * 12, *Kj = d.K + (size_t)nb * 12;
+        const Soa<double> Ki = soa(d.K, n, cell), Kj = soa(d.K, n, nb);
         for (int b = 0; b < 3; ++b) ho[b] = 0.5 * (Ki[col[a][b]] + Kj[col[a][b]]) - sigN[b];
         ho[3] = 0.5 * (Ki[6 + a] + Kj[6 + a]) - qN;
         ho[4] = g.species == 1 ? 0.5 * (Ki[9 + a] + Kj[9 + a]) - qrN : 0.0;
@@ -313,37 +329,60 @@ __global__ __launch_bounds__(256) void k_mac_fbfix(GSIS_SPAN_ARGS)
     for (int k = 0; k < 6; ++k) out[k] *= sg;
     const double *in = d.inpsi + (b * 6 + dir) * 6;
     const double sc = bc.kind[b] == 1 ? bc.rho[b] : out[0] / (-in[0]);
-    const double *P = d.P + (size_t)cell * NP;
+    const Soa<double> P = soa(d.P, g.ncell, cell);
     double Fe[6];
     group_equilibrium_flux(g, bc, d, P, dir, b, sub, Fe);
     if (sub < 6) {
         const double fix = out[sub] + sc * in[sub] - Fe[sub];
-        d.fbfix[(size_t)f * 6 + sub] = fix;
-        d.Fb[(size_t)f * 6 + sub] = fix + Fe[sub];
+        d.fbfix[(size_t)sub * g.nface + f] = fix;
+        d.Fb[(size_t)sub * g.nface + f] = fix + Fe[sub];
     }
     if (sub == 7) d.Gb[f] = boundary_gamma(g, P, a);
 }
 
 // Flux of face dir of a cell divided by h (outward positive), and Gamma / h.
 // dir is a compile-time constant so every index is static.
+// Index of the neighbour across face dir on the uniform grid (cell -+ 1, nx,
+// nx ny), clamped into the array: equal to the neighbour whenever the face is
+// interior, and a valid address otherwise, so the neighbour's data can be
+// loaded without waiting for the neighbour table.
+__device__ __forceinline__ int grid_neighbour(const Geo &g, int cell, int dir)
+{
+    const int a = dir / 2;
+    const int step = a == 0 ? 1 : (a == 1 ? g.nx : g.nx * g.ny);
+    return (dir & 1) ? min(cell + step, g.ncell - 1) : max(cell - step, 0);
+}
+
 template <int DIR, int NW>
 __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, double out[NW], double &gam)
 {
     constexpr int a = DIR / 2;
     const double h = g.h[a];
-    const int n = d.nbr[(size_t)cell * 6 + DIR];
+    const size_t nc = g.ncell;
+    // both sides' data into registers first, in parallel with the table lookup
+    const int nb = grid_neighbour(g, cell, DIR);
+    const int L = (DIR & 1) ? cell : nb, R = (DIR & 1) ? nb : cell;
+    double PL[NP], PR[NP], GL[9], GR[9], HO[5];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        PL[k] = d.P[(size_t)k * nc + L];
+        PR[k] = d.P[(size_t)k * nc + R];
+        GL[k] = d.grad[(size_t)k * nc + L];
+        GR[k] = d.grad[(size_t)k * nc + R];
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) HO[k] = d.hot[(size_t)(a * 5 + k) * nc + L];
+    const int n = d.nbr[(size_t)DIR * g.ncell + cell];
     if (n >= 0) {
-        const int L = (DIR & 1) ? cell : n, R = (DIR & 1) ? n : cell;
         double F[6], Gam;
-        face_flux(g, d.P + (size_t)L * NP, d.P + (size_t)R * NP, d.grad + (size_t)L * 9, d.grad + (size_t)R * 9, a, h,
-                  d.hot + (size_t)L * 15 + a * 5, F, &Gam);
+        face_flux(g, PL, PR, GL, GR, a, h, HO, F, &Gam);
 #pragma unroll
         for (int k = 0; k < NW; ++k) out[k] = ((DIR & 1) ? F[k] : -F[k]) / h;
         gam = Gam / h;
     } else {
         const int f = -n - 1;
 #pragma unroll
-        for (int k = 0; k < NW; ++k) out[k] = d.Fb[(size_t)f * 6 + k] / h;
+        for (int k = 0; k < NW; ++k) out[k] = d.Fb[(size_t)k * g.nface + f] / h;
         gam = d.Gb[f] / h;
     }
 }
@@ -399,7 +438,7 @@ __global__ __launch_bounds__(384) void k_mac_res(GSIS_SPAN_ARGS, int slot)
             for (int k = 0; k < NW; ++k) res[k] -= red[j][k][lane];
             sumG += red[j][NW][lane];
         }
-        const double *Pi = d.P + (size_t)cell * NP;
+        const Soa<double> Pi = soa(d.P, g.ncell, cell);
         const double invtau = Pi[10];
         if (DIA) {
             double T = (3.0 * Pi[4] + g.dr * Pi[5]) / (3.0 + g.dr);
@@ -408,7 +447,7 @@ __global__ __launch_bounds__(384) void k_mac_res(GSIS_SPAN_ARGS, int slot)
         double umag = sqrt(Pi[1] * Pi[1] + Pi[2] * Pi[2] + Pi[3] * Pi[3]);
         double idt = (umag + Pi[8] + g.Cd * Pi[9] / (Pi[0] * g.hmin)) / (g.macro_cfl * g.hmin);
         D = idt + 0.5 * sumG;
-        double *r = d.R + (size_t)cell * 6;
+        const Soa<double> r = soa(d.R, g.ncell, cell);
 #pragma unroll
         for (int k = 0; k < 6; ++k) r[k] = res[k];
         d.Src[cell] = DIA ? invtau / g.Zr : 0.0;
@@ -426,8 +465,8 @@ __global__ __launch_bounds__(384) void k_mac_res(GSIS_SPAN_ARGS, int slot)
 // row with its relaxation source on the diagonal.
 __device__ __forceinline__ void stepped_W(const Geo &g, const Dev &d, const double *Ws, int cell, double Dm, double Wn[6])
 {
-    const double *W = Ws + (size_t)cell * 6;
-    const double *r = d.R + (size_t)cell * 6;
+    const Soa<const double> W = soa(Ws, g.ncell, cell);
+    const Soa<double> r = soa(d.R, g.ncell, cell);
 #pragma unroll
     for (int k = 0; k < 5; ++k) Wn[k] = W[k] + r[k] / Dm;
     Wn[5] = g.species == 1 ? W[5] + r[5] / (Dm + d.Src[cell]) : W[5];
@@ -458,16 +497,18 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
         double Wn[6];
         stepped_W(g, d, Ws, cell, Dm, Wn);
         if (a == 0) {
+            const Soa<double> Wc = soa(Wd, g.ncell, cell);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) Wd[(size_t)cell * 6 + k] = Wn[k];
-            prim_from_W(g, Wn, d.P + (size_t)cell * NP);
+            for (int k = 0; k < 6; ++k) Wc[k] = Wn[k];
+            prim_from_W(g, Wn, soa(d.P, g.ncell, cell));
         }
         if (last) return;
-        const int nm = d.nbr[(size_t)cell * 6 + 2 * a], np = d.nbr[(size_t)cell * 6 + 2 * a + 1];
-        double um[3], up[3];
+        // neighbours' states loaded at grid indices, in parallel with the table lookup
         double Wm[6], Wp[6];
-        if (nm >= 0) stepped_W(g, d, Ws, nm, Dm, Wm);
-        if (np >= 0) stepped_W(g, d, Ws, np, Dm, Wp);
+        stepped_W(g, d, Ws, grid_neighbour(g, cell, 2 * a), Dm, Wm);
+        stepped_W(g, d, Ws, grid_neighbour(g, cell, 2 * a + 1), Dm, Wp);
+        const int nm = d.nbr[(size_t)(2 * a) * g.ncell + cell], np = d.nbr[(size_t)(2 * a + 1) * g.ncell + cell];
+        double um[3], up[3];
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             const double uc = Wn[1 + b] / Wn[0];
@@ -476,7 +517,7 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
         }
         const double h = g.h[a];
         const double den = (nm >= 0 && np >= 0) ? 2.0 * h : h;
-        double *G = d.grad + (size_t)cell * 9;
+        const Soa<double> G = soa(d.grad, g.ncell, cell);
 #pragma unroll
         for (int b = 0; b < 3; ++b) G[b * 3 + a] = (nm < 0 && np < 0) ? 0.0 : (up[b] - um[b]) / den;
         return;
@@ -491,7 +532,7 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
     prim_from_W(g, Wn, P);
     double Fe[6];
     group_equilibrium_flux(g, bc, d, P, dir, d.face_bc[f], sub, Fe);
-    if (sub < 6) d.Fb[(size_t)f * 6 + sub] = d.fbfix[(size_t)f * 6 + sub] + Fe[sub];
+    if (sub < 6) d.Fb[(size_t)sub * g.nface + f] = d.fbfix[(size_t)sub * g.nface + f] + Fe[sub];
     if (sub == 7) d.Gb[f] = boundary_gamma(g, P, dir / 2);
 }
 
@@ -512,7 +553,7 @@ __global__ __launch_bounds__(128) void k_mac_final(GSIS_SPAN_ARGS)
     const Dev &d = C.d;
     int cell = blk * blockDim.x + threadIdx.x;
     if (cell >= g.ncell || !d.cflag[cell]) return;
-    const double *P = d.P + (size_t)cell * NP;
+    const Soa<double> P = soa(d.P, g.ncell, cell);
     double *c = d.corr + (size_t)cell * NCORR;
     c[0] = P[0]; c[1] = P[1]; c[2] = P[2]; c[3] = P[3]; c[4] = P[4];
     c[5] = g.species == 1 ? P[5] : P[4];
