@@ -32,13 +32,42 @@ namespace gsis {
 template <typename T> struct Arith;
 // Division by the hardware reciprocal: one rounding more than IEEE division
 // (FP32: v_rcp_f32, about 1 ulp; FP64: v_rcp_f64 refined by two Newton steps
-// and a residual correction), the same code for every tile shape.
+// and a residual correction), the same code for every tile shape.  FP32
+// exponential: the hardware exp2; FP64: exp_nonpos below.
 template <> struct Arith<float> {
     static __device__ __forceinline__ float ex(float x) { return __expf(x); }
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 };
+// e^x for x <= 0 (the argument of every Maxwellian factor here): x = n ln2 + r
+// with n = rint(x / ln2) and |r| <= ln2 / 2, the Cody-Waite two-part ln2 (the
+// high part has 32 significant bits, so n ln2_hi is exact) keeping r exact to
+// rounding; e^r by its Taylor polynomial to r^12 (truncation below 2e-16
+// relative on that interval), evaluated by Horner; 2^n through the exponent.
+// Arguments below -745 are clamped there, where e^x is zero in FP64.
+__device__ __forceinline__ double exp_nonpos(double x)
+{
+    x = fmax(x, -745.0);
+    const double n = rint(x * 1.4426950408889634074);
+    double r = fma(n, -6.93147180369123816490e-01, x);
+    r = fma(n, -1.90821492927058770002e-10, r);
+    double p = 1.0 / 479001600.0;
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)n);
+}
+
 template <> struct Arith<double> {
-    static __device__ __forceinline__ double ex(double x) { return exp(x); }
+    static __device__ __forceinline__ double ex(double x) { return exp_nonpos(x); }
     static __device__ __forceinline__ double div(double a, double b)
     {
         double r = __builtin_amdgcn_rcp(b);
