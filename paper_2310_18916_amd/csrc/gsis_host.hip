@@ -235,6 +235,8 @@ size_t layout(gsis_ctx *c, char *base)
     return align256(off);
 }
 
+int vw_class(int vw) { return vw >= 4 ? 2 : (vw == 2 ? 1 : 0); }
+
 // The launch target of this context alone.
 Target target_of(const gsis_ctx *c)
 {
@@ -249,7 +251,7 @@ Target target_of(const gsis_ctx *c)
     t.dia = c->g.species == GSIS_DIATOMIC;
     t.mask = c->g.nfluid != c->g.ncell;
     t.rfn = c->g.inv_dt != 0.0;
-    t.vw = c->vw;
+    t.mom_nblk[vw_class(c->vw)] = c->g.ncell;
     t.tx = c->tx;
     t.ty = c->ty;
     t.bs = c->bs;
@@ -1037,6 +1039,7 @@ size_t batch_map_cap(const gsis_batch *b)
     size_t n = 0;
     for (const gsis_ctx *c : b->cs) {
         for (int k = 0; k < NKIND; ++k) n += (size_t)kind_blocks(c->g, (Kind)k);
+        n += (size_t)c->g.ncell;   // moment map of its vector-width class
         size_t tiles = (size_t)((c->g.nx + 3) / 4) * ((c->g.ny + 3) / 4) * c->g.nz;
         n += tiles * 8 * (size_t)sweep_nvb(c->g, 128);
     }
@@ -1100,6 +1103,16 @@ hipError_t batch_build_maps(gsis_batch *b)
         }
         t.nblk[k] = (int)(m.size() - koff[k]);
     }
+    size_t moff[3];
+    int mcnt[3];
+    for (int w = 0; w < 3; ++w) {
+        moff[w] = m.size();
+        for (int c = 0; c < nc; ++c) {
+            if (vw_class(b->cs[c]->vw) != w) continue;
+            for (int j = 0; j < b->cs[c]->g.ncell; ++j) m.push_back(make_int2(c, j));
+        }
+        mcnt[w] = (int)(m.size() - moff[w]);
+    }
     int nplane = 0;
     for (const gsis_ctx *c : b->cs) nplane = std::max(nplane, (int)c->plane_cnt.size());
     std::vector<size_t> poff(nplane);
@@ -1116,6 +1129,10 @@ hipError_t batch_build_maps(gsis_batch *b)
     }
     if (m.size() > b->map_cap) return hipErrorInvalidValue;
     for (int k = 0; k < NKIND; ++k) t.map[k] = b->dmap + koff[k];
+    for (int w = 0; w < 3; ++w) {
+        t.mom_map[w] = b->dmap + moff[w];
+        t.mom_nblk[w] = mcnt[w];
+    }
     b->pmap.assign(nplane, nullptr);
     for (int p = 0; p < nplane; ++p) b->pmap[p] = b->dmap + poff[p];
     t.cases = b->dcases;
@@ -1127,12 +1144,7 @@ hipError_t batch_build_maps(gsis_batch *b)
     t.fp32 = b->fp32;
     t.dia = b->dia;
     t.mask = false;
-    int vw = 4;
-    for (const gsis_ctx *c : b->cs) {
-        t.mask = t.mask || c->g.nfluid != c->g.ncell;
-        vw = std::min(vw, c->vw);
-    }
-    t.vw = vw;
+    for (const gsis_ctx *c : b->cs) t.mask = t.mask || c->g.nfluid != c->g.ncell;
     t.rfn = false;
     t.tx = b->tx;
     t.ty = b->ty;

@@ -21,7 +21,9 @@ struct Target {
     const int *npblk = nullptr;          // sweep: blocks of every global plane
     int nplane = 0;
     bool fp32 = false, dia = false, mask = false, rfn = false;
-    int vw = 1;                       // moment kernel vector width
+    // the moment kernel runs once per vector width (1, 2, 4) over the cases of that width
+    const int2 *mom_map[3] = {};
+    int mom_nblk[3] = {};
     int tx = 4, ty = 4, bs = 128;     // sweep tile shape and block size
     Span span(Kind k) const { return Span{cases, map[k]}; }
 };

@@ -2,12 +2,13 @@
 //
 // k_moments: raw moments of every (cell, velocity octant) about the origin,
 // accumulated in FP64 whatever the VDF precision.  The tensor grid makes the
-// contraction separable: each lane walks rows of x-nodes (contiguous in the
-// octant-grouped layout), forms the four row sums sum_x w_x xi_x^p f
-// (p = 0..3), and folds them with the row's y/z weights into the 13 (+4 for
-// f1) monomials.  One block per cell, one wave per octant, so per-octant
-// sums -- from which every half-range wall flux follows -- need only a wave
-// reduction.  The x-weights are wave-uniform (scalar loads).
+// contraction separable: the x-rows of an octant (contiguous in the
+// octant-grouped layout) give the four sums sum_x w_x xi_x^p f (p = 0..3),
+// which fold with the row's y/z weights into the 13 (+4 for f1) monomials.
+// One block per cell, one wave per octant, so per-octant sums -- from which
+// every half-range wall flux follows -- need only a wave reduction.  Lanes
+// lie along the rows (each keeps its columns and their x-weights), so every
+// load instruction reads one contiguous stretch of the VDF.
 //
 // k_derive: central moments (rho, u, Tt, sigma, q, Tr, qr) of every cell from
 // the octant sums.
@@ -62,8 +63,6 @@ __global__ __launch_bounds__(512) void k_moments(GSIS_SPAN_ARGS)
     const gptr<const double> ytab = (gptr<const double>)C.d.ytab;
     const gptr<const double> ztab = (gptr<const double>)C.d.ztab;
     const gptr<double> mom8 = (gptr<double>)C.d.mom8;
-    constexpr int CH0 = (DIA ? 64 : 128) / (VW * (int)sizeof(T));   // vectors per chunk: 128 B of row data per lane
-    constexpr int CH = CH0 < 16 ? CH0 : 16;
     const int cell = blk;
     const int o = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -78,43 +77,15 @@ __global__ __launch_bounds__(512) void k_moments(GSIS_SPAN_ARGS)
     const int z0 = (o & 4) ? 0 : g.k0[2];
     const size_t base = (size_t)cell * g.nv + g.obase[o];
     const int nrow = noy * noz;
+    constexpr bool ALONG = sizeof(T) == 8 && VW == 2;   // the faster mapping for this layout (measured)
     double acc[13];
 #pragma unroll
     for (int k = 0; k < 13; ++k) acc[k] = 0.0;
     double acc1[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int r = lane; r < nrow; r += 64) {
-        const int ly = r % noy, lz = r / noy;
-        const gptr<const T> row0 = f0 + base + (size_t)r * nox;
-        const gptr<const T> row1 = DIA ? f1 + base + (size_t)r * nox : row0;
-        double s0 = 0, s1 = 0, s2 = 0, s3 = 0, t0 = 0, t1 = 0;
-        // a row is read in chunks of CH vectors whose loads are all issued
-        // before any is used, so the lines of a row are fetched together
-        for (int lx0 = 0; lx0 < nox; lx0 += CH * VW) {
-            double v[CH][VW], v1[CH][VW];
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                if (lx0 + c * VW < nox) {
-                    VecLoad<T, VW>::ld(row0 + lx0 + c * VW, v[c]);
-                    if (DIA) VecLoad<T, VW>::ld(row1 + lx0 + c * VW, v1[c]);
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                if (lx0 + c * VW >= nox) break;
-#pragma unroll
-                for (int e = 0; e < VW; ++e) {
-                    const gptr<const double> xt = xtab + (size_t)(x0 + lx0 + c * VW + e) * 4;
-                    s0 += xt[0] * v[c][e];
-                    s1 += xt[1] * v[c][e];
-                    s2 += xt[2] * v[c][e];
-                    s3 += xt[3] * v[c][e];
-                    if (DIA) {
-                        t0 += xt[0] * v1[c][e];
-                        t1 += xt[1] * v1[c][e];
-                    }
-                }
-            }
-        }
+    const float rcp_noy = 1.0f / (float)noy;   // exact row -> (ly, lz) split for rows < 2^16
+    // fold the x-sums s_p = sum_x w_x x^p f of row r with its y/z weights
+    auto fold = [&](int r, double s0, double s1, double s2, double s3, double t0, double t1) {
+        const int lz = (int)(((float)r + 0.5f) * rcp_noy), ly = r - lz * noy;
         const double wy = ytab[2 * (y0 + ly)], y = ytab[2 * (y0 + ly) + 1];
         const double wz = ztab[2 * (z0 + lz)], z = ztab[2 * (z0 + lz) + 1];
         const double W0 = wy * wz;
@@ -139,6 +110,116 @@ __global__ __launch_bounds__(512) void k_moments(GSIS_SPAN_ARGS)
             acc1[1] += W0 * t1;
             acc1[2] += Y1 * t0;
             acc1[3] += Z1 * t0;
+        }
+    };
+    // Two mappings, chosen by measurement.  Row per lane: each lane owns an
+    // x-row and reads it in chunks whose loads are issued together (the
+    // x-weights are wave-uniform).  Along the rows (FP64 pairs): lpr lanes
+    // cover a row with VW elements each, 64 / lpr rows per load instruction,
+    // so every load reads one contiguous stretch of the octant; a lane keeps
+    // its columns (x-weights in registers) and issues UN rows' loads first.
+    const int lpr = nox / VW;
+    if (!ALONG) {
+        // one row per lane, read in chunks of CH vectors issued together
+        constexpr int CH0 = (DIA ? 64 : 128) / (VW * (int)sizeof(T));
+        constexpr int CH = CH0 < 16 ? CH0 : 16;
+        for (int r = lane; r < nrow; r += 64) {
+            const gptr<const T> row0 = f0 + base + (size_t)r * nox;
+            const gptr<const T> row1 = DIA ? f1 + base + (size_t)r * nox : row0;
+            double s0 = 0, s1 = 0, s2 = 0, s3 = 0, t0 = 0, t1 = 0;
+            // a row is read in chunks of CH vectors whose loads are all issued
+            // before any is used, so the lines of a row are fetched together
+            for (int lx0 = 0; lx0 < nox; lx0 += CH * VW) {
+                double v[CH][VW], v1[CH][VW];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    if (lx0 + c * VW < nox) {
+                        VecLoad<T, VW>::ld(row0 + lx0 + c * VW, v[c]);
+                        if (DIA) VecLoad<T, VW>::ld(row1 + lx0 + c * VW, v1[c]);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    if (lx0 + c * VW >= nox) break;
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) {
+                        const gptr<const double> xt = xtab + (size_t)(x0 + lx0 + c * VW + e) * 4;
+                        s0 += xt[0] * v[c][e];
+                        s1 += xt[1] * v[c][e];
+                        s2 += xt[2] * v[c][e];
+                        s3 += xt[3] * v[c][e];
+                        if (DIA) {
+                            t0 += xt[0] * v1[c][e];
+                            t1 += xt[1] * v1[c][e];
+                        }
+                    }
+                }
+            }
+            fold(r, s0, s1, s2, s3, t0, t1);
+        }
+    } else if (lpr <= 64) {
+        const int rpi = 64 / lpr;
+        const int my_r = lane / lpr, my_c = lane - my_r * lpr;
+        if (my_r < rpi) {
+            double wx[VW][4];
+#pragma unroll
+            for (int e = 0; e < VW; ++e)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) wx[e][q] = xtab[(size_t)(x0 + my_c * VW + e) * 4 + q];
+            constexpr int UN0 = (DIA ? 64 : 128) / (VW * (int)sizeof(T));
+            constexpr int UN = UN0 < 16 ? UN0 : 16;
+            for (int rb = my_r; rb < nrow; rb += UN * rpi) {
+                double v[UN][VW], v1[UN][VW];
+#pragma unroll
+                for (int u = 0; u < UN; ++u) {
+                    const int r = rb + u * rpi;
+                    if (r < nrow) {
+                        VecLoad<T, VW>::ld(f0 + base + (size_t)r * nox + my_c * VW, v[u]);
+                        if (DIA) VecLoad<T, VW>::ld(f1 + base + (size_t)r * nox + my_c * VW, v1[u]);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < UN; ++u) {
+                    const int r = rb + u * rpi;
+                    if (r >= nrow) break;
+                    double s0 = 0, s1 = 0, s2 = 0, s3 = 0, t0 = 0, t1 = 0;
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) {
+                        s0 += wx[e][0] * v[u][e];
+                        s1 += wx[e][1] * v[u][e];
+                        s2 += wx[e][2] * v[u][e];
+                        s3 += wx[e][3] * v[u][e];
+                        if (DIA) {
+                            t0 += wx[e][0] * v1[u][e];
+                            t1 += wx[e][1] * v1[u][e];
+                        }
+                    }
+                    fold(r, s0, s1, s2, s3, t0, t1);
+                }
+            }
+        }
+    } else {
+        // rows longer than 64 vectors: the lanes take column groups of each row
+        for (int r = 0; r < nrow; ++r) {
+            double s0 = 0, s1 = 0, s2 = 0, s3 = 0, t0 = 0, t1 = 0;
+            for (int c = lane; c < lpr; c += 64) {
+                double v[VW], v1[VW];
+                VecLoad<T, VW>::ld(f0 + base + (size_t)r * nox + c * VW, v);
+                if (DIA) VecLoad<T, VW>::ld(f1 + base + (size_t)r * nox + c * VW, v1);
+#pragma unroll
+                for (int e = 0; e < VW; ++e) {
+                    const gptr<const double> xt = xtab + (size_t)(x0 + c * VW + e) * 4;
+                    s0 += xt[0] * v[e];
+                    s1 += xt[1] * v[e];
+                    s2 += xt[2] * v[e];
+                    s3 += xt[3] * v[e];
+                    if (DIA) {
+                        t0 += xt[0] * v1[e];
+                        t1 += xt[1] * v1[e];
+                    }
+                }
+            }
+            fold(r, s0, s1, s2, s3, t0, t1);
         }
     }
     // transposing reduction: lane groups end with one of the NRS sums each
@@ -280,23 +361,29 @@ __global__ __launch_bounds__(128) void k_commit_correction(GSIS_SPAN_ARGS)
 
 // ------------------------------------------------------------------ launches
 template <typename T, int VW>
-static void moments_vw(const Target &t, hipStream_t s)
+static void moments_vw(const Target &t, int cls, hipStream_t s)
 {
-    if (t.dia)
-        hipLaunchKernelGGL((k_moments<T, VW, true>), dim3(t.nblk[K_CELL1]), dim3(512), 0, s, GSIS_SPAN(t.span(K_CELL1)));
-    else
-        hipLaunchKernelGGL((k_moments<T, VW, false>), dim3(t.nblk[K_CELL1]), dim3(512), 0, s, GSIS_SPAN(t.span(K_CELL1)));
+    const Span sp{t.cases, t.mom_map[cls]};
+    const dim3 grid(t.mom_nblk[cls]);
+    if (t.dia) hipLaunchKernelGGL((k_moments<T, VW, true>), grid, dim3(512), 0, s, GSIS_SPAN(sp));
+    else hipLaunchKernelGGL((k_moments<T, VW, false>), grid, dim3(512), 0, s, GSIS_SPAN(sp));
 }
 
+// One launch per vector-width class present (a case's width follows its
+// octant row lengths), so every case is reduced exactly as on its own.
 hipError_t launch_moments(const Target &t, hipStream_t s)
 {
-    if (t.fp32) {
-        if (t.vw == 4) moments_vw<float, 4>(t, s);
-        else if (t.vw == 2) moments_vw<float, 2>(t, s);
-        else moments_vw<float, 1>(t, s);
-    } else {
-        if (t.vw >= 2) moments_vw<double, 2>(t, s);
-        else moments_vw<double, 1>(t, s);
+    if (t.mom_nblk[0] > 0) {
+        if (t.fp32) moments_vw<float, 1>(t, 0, s);
+        else moments_vw<double, 1>(t, 0, s);
+    }
+    if (t.mom_nblk[1] > 0) {
+        if (t.fp32) moments_vw<float, 2>(t, 1, s);
+        else moments_vw<double, 2>(t, 1, s);
+    }
+    if (t.mom_nblk[2] > 0) {
+        if (t.fp32) moments_vw<float, 4>(t, 2, s);
+        else moments_vw<double, 2>(t, 2, s);   // FP64 rows load two at a time at most
     }
     return hipGetLastError();
 }
