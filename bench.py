@@ -257,8 +257,9 @@ def main():
     esz = 8 if dtype == "fp64" else 4
     sweep_ms, sweep_n = prof["sweep"]
     mom_ms, mom_n = prof["moments"]
-    sweep_bytes = pts * esz * (2 if case.inv_dt != 0 else 1)   # write f^{n+1/2} (+ read f^n if 1/dt != 0)
-    mom_bytes = pts * esz                                       # read f^{n+1/2}
+    nvdf = 2 if case.species == 1 else 1                                # the diatomic gas carries f0 and f1
+    sweep_bytes = pts * nvdf * esz * (2 if case.inv_dt != 0 else 1)   # write f^{n+1/2} (+ read f^n if 1/dt != 0)
+    mom_bytes = pts * nvdf * esz                                       # read f^{n+1/2}
     sweep_gbs = sweep_bytes / (sweep_ms / sweep_n * 1e-3) / 1e9
     mom_gbs = mom_bytes / (mom_ms / mom_n * 1e-3) / 1e9
     dominant = "sweep" if sweep_ms >= mom_ms else "moments"
