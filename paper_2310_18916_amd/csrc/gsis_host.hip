@@ -831,7 +831,7 @@ gsis_status gsis_autotune(gsis_ctx *ctx, int reps, int *cfg_out, double *ms_out,
     for (int k = 0; k < nsh; ++k) {
         int tx = shapes[2 * k], ty = shapes[2 * k + 1];
         if (!sweep_shape_supported(ctx->fp32, dia, tx, ty)) continue;
-        for (int tz : {tx / 2, tx, 2 * tx})
+        for (int tz : {tx / 2, tx, 2 * tx, 4 * tx})
             for (int bs : {128, 256}) cands.push_back({tx, ty, std::max(tz, 1), bs, 0.0});
     }
     int save[4] = {ctx->tx, ctx->ty, ctx->tz, ctx->bs};
@@ -1327,7 +1327,7 @@ gsis_status gsis_batch_autotune(gsis_batch *b, int reps, int *cfg_out, double *m
     for (int k = 0; k < nsh; ++k) {
         int tx = shapes[2 * k], ty = shapes[2 * k + 1];
         if (!sweep_shape_supported(b->fp32, b->dia, tx, ty)) continue;
-        for (int tz : {tx / 2, tx, 2 * tx})
+        for (int tz : {tx / 2, tx, 2 * tx, 4 * tx})
             for (int bs : {128, 256}) cands.push_back({tx, ty, std::max(tz, 1), bs, 0.0});
     }
     (void)c0;

@@ -362,16 +362,21 @@ __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, 
     // both sides' data into registers first, in parallel with the table lookup
     const int nb = grid_neighbour(g, cell, DIR);
     const int L = (DIR & 1) ? cell : nb, R = (DIR & 1) ? nb : cell;
+    // only what the face flux reads: no Tr, Er, qr for the monatomic gas and no
+    // normal gradient column (the normal derivative is the two-cell difference)
+    constexpr bool DIA = NW == 6;
     double PL[NP], PR[NP], GL[9], GR[9], HO[5];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        PL[k] = d.P[(size_t)k * nc + L];
-        PR[k] = d.P[(size_t)k * nc + R];
-        GL[k] = d.grad[(size_t)k * nc + L];
-        GR[k] = d.grad[(size_t)k * nc + R];
+        const bool use = DIA || (k != 5 && k != 7);
+        PL[k] = use ? d.P[(size_t)k * nc + L] : 0.0;
+        PR[k] = use ? d.P[(size_t)k * nc + R] : 0.0;
+        const bool tan = k % 3 != a;
+        GL[k] = tan ? d.grad[(size_t)k * nc + L] : 0.0;
+        GR[k] = tan ? d.grad[(size_t)k * nc + R] : 0.0;
     }
 #pragma unroll
-    for (int k = 0; k < 5; ++k) HO[k] = d.hot[(size_t)(a * 5 + k) * nc + L];
+    for (int k = 0; k < 5; ++k) HO[k] = (DIA || k < 4) ? d.hot[(size_t)(a * 5 + k) * nc + L] : 0.0;
     const int n = d.nbr[(size_t)DIR * g.ncell + cell];
     if (n >= 0) {
         double F[6], Gam;
