@@ -157,7 +157,7 @@ gsis_status gsis_get_state(gsis_ctx *ctx, void *dst_device);
 gsis_status gsis_set_state(gsis_ctx *ctx, const void *src_device);
 
 /* Sweep tile (cells per tile along x, y, z in the octant's upwind frame) and
- * threads per block (128 or 256); all zeros pick the built-in default for the
+ * threads per block (64, 128 or 256); all zeros pick the built-in default for the
  * VDF precision.  Only compiled (tx, ty) are accepted (see gsis_tile_shapes). */
 gsis_status gsis_set_tile(gsis_ctx *ctx, int tx, int ty, int tz, int block);
 

@@ -806,7 +806,7 @@ gsis_status gsis_set_tile(gsis_ctx *ctx, int tx, int ty, int tz, int block)
         if (!sweep_shape_supported(ctx->fp32, ctx->g.species == GSIS_DIATOMIC, tx, ty))
             return fail(ctx, GSIS_EINVAL, "tile (tx, ty) not compiled for this precision and gas");
         if (tz < 1 || tz > 1024) return fail(ctx, GSIS_EINVAL, "tz must be 1..1024");
-        if (block != 128 && block != 256) return fail(ctx, GSIS_EINVAL, "block must be 128 or 256");
+        if (block != 64 && block != 128 && block != 256) return fail(ctx, GSIS_EINVAL, "block must be 64, 128 or 256");
         int ntx = (ctx->g.nx + tx - 1) / tx, nty = (ctx->g.ny + ty - 1) / ty, ntz = (ctx->g.nz + tz - 1) / tz;
         if (ntx > 1023 || nty > 1023 || ntz > 1023) return fail(ctx, GSIS_EINVAL, "too many tiles per axis");
         ctx->tx = tx; ctx->ty = ty; ctx->tz = tz; ctx->bs = block;
@@ -832,7 +832,7 @@ gsis_status gsis_autotune(gsis_ctx *ctx, int reps, int *cfg_out, double *ms_out,
         int tx = shapes[2 * k], ty = shapes[2 * k + 1];
         if (!sweep_shape_supported(ctx->fp32, dia, tx, ty)) continue;
         for (int tz : {tx / 2, tx, 2 * tx, 4 * tx})
-            for (int bs : {128, 256}) cands.push_back({tx, ty, std::max(tz, 1), bs, 0.0});
+            for (int bs : {64, 128, 256}) cands.push_back({tx, ty, std::max(tz, 1), bs, 0.0});
     }
     int save[4] = {ctx->tx, ctx->ty, ctx->tz, ctx->bs};
     {
@@ -1033,7 +1033,7 @@ gsis_status bfail(gsis_batch *b, gsis_status s, const std::string &msg)
     } while (0)
 
 // Upper bound of the block-map entries: every launch kind, plus the sweep at
-// its finest tiling (4 x 4 x 1 tiles, 128-thread blocks).
+// its finest tiling (4 x 4 x 1 tiles, 64-thread blocks).
 size_t batch_map_cap(const gsis_batch *b)
 {
     size_t n = 0;
@@ -1041,7 +1041,7 @@ size_t batch_map_cap(const gsis_batch *b)
         for (int k = 0; k < NKIND; ++k) n += (size_t)kind_blocks(c->g, (Kind)k);
         n += (size_t)c->g.ncell;   // moment map of its vector-width class
         size_t tiles = (size_t)((c->g.nx + 3) / 4) * ((c->g.ny + 3) / 4) * c->g.nz;
-        n += tiles * 8 * (size_t)sweep_nvb(c->g, 128);
+        n += tiles * 8 * (size_t)sweep_nvb(c->g, 64);
     }
     return n;
 }
@@ -1328,7 +1328,7 @@ gsis_status gsis_batch_autotune(gsis_batch *b, int reps, int *cfg_out, double *m
         int tx = shapes[2 * k], ty = shapes[2 * k + 1];
         if (!sweep_shape_supported(b->fp32, b->dia, tx, ty)) continue;
         for (int tz : {tx / 2, tx, 2 * tx, 4 * tx})
-            for (int bs : {128, 256}) cands.push_back({tx, ty, std::max(tz, 1), bs, 0.0});
+            for (int bs : {64, 128, 256}) cands.push_back({tx, ty, std::max(tz, 1), bs, 0.0});
     }
     (void)c0;
     const int save[4] = {b->tx, b->ty, b->tz, b->bs};

@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
     constexpr int NPL = DIA ? 36 : 16;            // parameters per cell kept in LDS
     constexpr int NC = TX * TY;                   // cells per slab
     constexpr int NM = NC * NPL;                  // parameter words per slab
-    constexpr int MPT = (NM + 127) / 128;         // words per thread for the smallest block (128)
+    constexpr int MPT = (NM + 63) / 64;           // words per thread for the smallest block (64)
     __shared__ T spar[2][NM];
     __shared__ int sflag[2][NC];
 
@@ -215,6 +215,7 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
     auto issue_meta = [&](int kz) {
 #pragma unroll
         for (int r = 0; r < MPT; ++r) {
+            if (r * bs >= NM) break;                      // uniform: larger blocks need fewer rounds
             const int e = min((int)threadIdx.x + r * bs, NM - 1);
             const int cc = e / NPL, k = e % NPL;
             const int c = cell_of(cc % TX, cc / TX, kz);
@@ -233,6 +234,7 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
     auto store_meta = [&](int buf) {
 #pragma unroll
         for (int r = 0; r < MPT; ++r) {
+            if (r * bs >= NM) break;
             const int e = threadIdx.x + r * bs;
             if (e < NM) spar[buf][e] = mreg[r];
         }

@@ -121,8 +121,8 @@ def test_tile_shapes_and_set_tile_validation():
     assert L.gsis_set_tile(ctx.h, 8, 8, 4, 128) == 0
     assert L.gsis_set_tile(ctx.h, 5, 5, 4, 128) == -1     # not compiled
     assert L.gsis_set_tile(ctx.h, 8, 8, 0, 128) == -1
-    assert L.gsis_set_tile(ctx.h, 8, 8, 4, 100) == -1     # block must be 128 or 256
-    assert L.gsis_set_tile(ctx.h, 8, 8, 4, 64) == -1
+    assert L.gsis_set_tile(ctx.h, 8, 8, 4, 100) == -1     # block must be 64, 128 or 256
+    assert L.gsis_set_tile(ctx.h, 8, 8, 4, 32) == -1
     assert L.gsis_set_tile(ctx.h, 16, 8, 4, 128) == -1    # not compiled
     assert L.gsis_set_tile(ctx.h, 8, 4, 16, 256) == 0
     tile = (C.c_int * 4)()

@@ -222,8 +222,8 @@ def test_tile_shapes_bitwise_identical():
     say("[determinism]")
     case = I.cavity(13, 10, 0.1, lid=0.25)
     results = {}
-    for dtype, shapes in (("fp32", [(8, 8, 8, 128), (4, 4, 4, 256), (8, 4, 3, 128), (8, 8, 13, 256)]),
-                          ("fp64", [(4, 4, 4, 128), (8, 4, 2, 256), (8, 4, 5, 128), (4, 4, 13, 256)])):
+    for dtype, shapes in (("fp32", [(8, 8, 8, 128), (4, 4, 4, 256), (8, 4, 3, 128), (8, 8, 13, 256), (4, 4, 6, 64)]),
+                          ("fp64", [(4, 4, 4, 128), (8, 4, 2, 256), (8, 4, 5, 128), (4, 4, 13, 256), (4, 4, 16, 64)])):
         for sh in shapes:
             s = Solver(case, dtype, tile=sh)
             s.init_maxwellian()
