@@ -134,3 +134,55 @@ def test_tile_shapes_and_set_tile_validation():
     f64 = G.Context(I.cavity(6, 8, 0.1), "fp64")
     assert f64.L.gsis_set_tile(f64.h, 8, 8, 8, 128) == -1
     assert f64.L.gsis_set_tile(f64.h, 8, 4, 8, 128) == 0
+
+
+def _batch(ctxs):
+    arr = (C.c_void_p * len(ctxs))(*[c.h.value for c in ctxs])
+    h = C.c_void_p()
+    st = _lib.lib().gsis_batch_create(C.byref(h), arr, len(ctxs))
+    return st, h
+
+
+def test_batch_create_rejects_mixed_or_invalid_cases():
+    L = _lib.lib()
+    a = G.Context(I.cavity(4, 6, 0.1), "fp32")
+    b = G.Context(I.cavity(5, 7, 0.3), "fp32")
+    c64 = G.Context(I.cavity(4, 6, 0.1), "fp64")
+    dia = G.Context(I.small_block(species=I.DIATOMIC, m=6), "fp32")
+    fin = G.Context(I.cavity(4, 6, 0.1, inv_dt=2.0), "fp32")
+    assert _batch([a, c64])[0] == -1          # precision differs
+    assert _batch([a, dia])[0] == -1          # gas differs
+    assert _batch([a, fin])[0] == -1          # finite pseudo time step
+    assert _batch([a, a])[0] == -1            # a case twice
+    h = C.c_void_p()
+    assert L.gsis_batch_create(C.byref(h), None, 1) == -1
+    assert L.gsis_batch_create(C.byref(h), (C.c_void_p * 1)(a.h.value), 0) == -1
+    st, bh = _batch([a, b])
+    assert st == 0 and bh.value
+    assert L.gsis_batch_destroy(bh) == 0
+
+
+def test_batch_host_checks_before_device_work():
+    """Sizes, tile validation and call order, all on the host."""
+    L = _lib.lib()
+    cases = [I.cavity(4, 6, 0.1), I.cavity(6, 9, 0.05), I.cavity(5, 8, 0.2)]
+    ctxs = [G.Context(c, "fp32") for c in cases]
+    st, bh = _batch(ctxs)
+    assert st == 0
+    n = C.c_size_t()
+    assert L.gsis_batch_workspace_size(bh, C.byref(n)) == 0
+    assert n.value >= sum(c.workspace_size() for c in ctxs)
+    assert L.gsis_batch_set_tile(bh, 5, 5, 4, 128) != 0      # not compiled
+    assert L.gsis_batch_set_tile(bh, 8, 4, 8, 256) == 0
+    t = (C.c_int * 4)()
+    assert L.gsis_batch_get_tile(bh, t) == 0 and tuple(t) == (8, 4, 8, 256)
+    assert L.gsis_batch_run(bh, 1, 10, 0) == -2               # not initialised
+    assert L.gsis_batch_run(bh, -1, 10, 0) == -2
+    cnt = C.c_int()
+    eps = (C.c_double * 30)()
+    assert L.gsis_batch_residuals(bh, eps, 10, C.byref(cnt)) == -2   # not bound
+    ms = C.c_double()
+    assert L.gsis_batch_last_run_ms(bh, C.byref(ms)) == -2
+    assert L.gsis_batch_bind_workspace(bh, None, n.value) == -1
+    assert L.gsis_batch_bind_workspace(bh, C.c_void_p(256), 16) == -3   # smaller than required
+    assert L.gsis_batch_destroy(bh) == 0
