@@ -131,6 +131,63 @@ __device__ __forceinline__ const Case &case_of(const Case *cases, const int2 *ma
     return (const Case &)*(const GSIS_CONST_AS Case *)(cases + ci);
 }
 
+// e^x for |x| < 708: x = n ln2 + r with n = rint(x / ln2) and |r| <= ln2 / 2,
+// the Cody-Waite two-part ln2 (the high part has 32 significant bits, so
+// n ln2_hi is exact) keeping r exact to rounding; e^r by its Taylor
+// polynomial to r^12 (truncation below 2e-16 relative on that interval),
+// evaluated by Horner; 2^n through the exponent.
+__device__ __forceinline__ double exp_core(double x)
+{
+    const double n = rint(x * 1.4426950408889634074);
+    double r = fma(n, -6.93147180369123816490e-01, x);
+    r = fma(n, -1.90821492927058770002e-10, r);
+    double p = 1.0 / 479001600.0;
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)n);
+}
+
+// x^y for a normal x > 0 and moderate y (|y ln x| < 708), as e^{y ln x}:
+// x = m 2^e with m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s) with
+// s = (m - 1) / (m + 1), |s| < 0.172, by the odd series of atanh to s^23
+// (truncation below 1e-18 relative), e ln2 in the two parts of exp_core.
+// Within 8 ulp of the exact power for x in [1e-3, 1e3].
+__device__ __forceinline__ double pow_pos(double x, double y)
+{
+    int e;
+    double m = frexp(x, &e);
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0), s2 = s * s;
+    double p = 1.0 / 23.0;
+    p = fma(p, s2, 1.0 / 21.0);
+    p = fma(p, s2, 1.0 / 19.0);
+    p = fma(p, s2, 1.0 / 17.0);
+    p = fma(p, s2, 1.0 / 15.0);
+    p = fma(p, s2, 1.0 / 13.0);
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    p = fma(p, s2, 1.0);
+    const double de = (double)e;
+    const double lx = fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, 2.0 * s * p));
+    return exp_core(y * lx);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

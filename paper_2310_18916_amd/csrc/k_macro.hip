@@ -41,16 +41,16 @@ template <typename T> __device__ __forceinline__ Soa<T> soa(T *buf, size_t n, in
 template <class PV>
 __device__ __forceinline__ void prim_from_W(const Geo &g, const double *W, PV P)
 {
-    double rho = W[0];
-    double u0 = W[1] / rho, u1 = W[2] / rho, u2 = W[3] / rho;
+    double rho = W[0], irho = 1.0 / rho;
+    double u0 = W[1] * irho, u1 = W[2] * irho, u2 = W[3] * irho;
     double E = W[4];
     double Er = g.species == 1 ? W[5] : 0.0;
     double uu = u0 * u0 + u1 * u1 + u2 * u2;
-    double Tt = (2.0 / 3.0) * (E - Er - rho * uu) / rho;
+    double Tt = (2.0 / 3.0) * (E - Er - rho * uu) * irho;
     double Tr = g.species == 1 ? 2.0 * Er / (g.dr * rho) : Tt;
     P[0] = rho; P[1] = u0; P[2] = u1; P[3] = u2; P[4] = Tt; P[5] = Tr; P[6] = E; P[7] = Er;
     P[8] = sqrt(g.gam * Tt / 2.0);
-    const double tw = pow(Tt, g.omega);
+    const double tw = pow_pos(Tt, g.omega);
     P[9] = tw / g.delta;
     P[10] = g.delta * rho * Tt / tw;
     P[11] = 0.0;
@@ -58,17 +58,17 @@ __device__ __forceinline__ void prim_from_W(const Geo &g, const double *W, PV P)
 
 template <class PV, class GV>
 __device__ __forceinline__ void nsf_face(const Geo &g, const PV &L, const PV &R, const GV &gL, const GV &gR, int a,
-                                         double h, double mu, double sigN[3], double *qN, double *qrN)
+                                         double ih, double mu, double sigN[3], double *qN, double *qrN)
 {
     double G[9];
     for (int b = 0; b < 3; ++b)
         for (int c = 0; c < 3; ++c)
-            G[b * 3 + c] = (c == a) ? (R[1 + b] - L[1 + b]) / h : 0.5 * (gL[b * 3 + c] + gR[b * 3 + c]);
+            G[b * 3 + c] = (c == a) ? (R[1 + b] - L[1 + b]) * ih : 0.5 * (gL[b * 3 + c] + gR[b * 3 + c]);
     double div = G[0] + G[4] + G[8];
     for (int b = 0; b < 3; ++b)
         sigN[b] = -mu * (G[b * 3 + a] + G[a * 3 + b] - (b == a ? (2.0 / 3.0) * div : 0.0));
-    *qN = -g.kt * mu * (R[4] - L[4]) / h;
-    *qrN = g.species == 1 ? -g.kr * mu * (R[5] - L[5]) / h : 0.0;
+    *qN = -g.kt * mu * (R[4] - L[4]) * ih;
+    *qrN = g.species == 1 ? -g.kr * mu * (R[5] - L[5]) * ih : 0.0;
 }
 
 // convective flux vector Phi(W).n and the state vector of one side
@@ -90,12 +90,12 @@ __device__ __forceinline__ void side(const PV &P, int a, double Phi[6], double W
 
 template <class PV, class GV, class HV>
 __device__ __forceinline__ void face_flux(const Geo &g, const PV &L, const PV &R, const GV &gL, const GV &gR, int a,
-                                          double h, const HV &hot, double F[6], double *Gam)
+                                          double ih, const HV &hot, double F[6], double *Gam)
 {
     const double TF = 0.5 * (L[4] + R[4]), rF = 0.5 * (L[0] + R[0]);
-    const double tw = pow(TF, g.omega);
+    const double mu = pow_pos(TF, g.omega) / g.delta;
     double sigN[3], qN, qrN;
-    nsf_face(g, L, R, gL, gR, a, h, tw / g.delta, sigN, &qN, &qrN);
+    nsf_face(g, L, R, gL, gR, a, ih, mu, sigN, &qN, &qrN);
     double PhiL[6], WL[6], PhiR[6], WR[6];
     side(L, a, PhiL, WL);
     side(R, a, PhiR, WR);
@@ -112,7 +112,7 @@ __device__ __forceinline__ void face_flux(const Geo &g, const PV &L, const PV &R
     for (int b = 0; b < 3; ++b) F[1 + b] += 0.5 * sn[b];
     F[4] += sn[0] * uF[0] + sn[1] * uF[1] + sn[2] * uF[2] + qn + qrn;
     F[5] += qrn;
-    *Gam = smax + g.Cd * tw / (g.delta * rF * h);
+    *Gam = smax + g.Cd * mu * ih / rF;
 }
 
 // Outgoing half-range psi-moments of M(rho, u, Tt) through face dir (sum over
@@ -146,7 +146,7 @@ __device__ void group_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev
         const double x = d.xi64[a][k];
         if (!(sg * x > 0.0)) continue;
         const double c = x - P[1 + a];
-        const double e = d.w64[a][k] * exp(-c * c * iT);
+        const double e = d.w64[a][k] * exp_core(fmax(-c * c * iT, -745.0));
         H1 += e * x;
         H2 += e * x * x;
         H3 += e * x * x * x;
@@ -158,7 +158,7 @@ __device__ void group_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev
         const int ax = ax2[q];
         for (int k = sub; k < g.n1[ax]; k += FG) {
             const double x = d.xi64[ax][k], c = x - P[1 + ax];
-            const double e = d.w64[ax][k] * exp(-c * c * iT);
+            const double e = d.w64[ax][k] * exp_core(fmax(-c * c * iT, -745.0));
             S[q][0] += e;
             S[q][1] += e * x;
             S[q][2] += e * x * x;
@@ -233,11 +233,10 @@ __device__ void cell_grad_col(const Geo &g, const Dev &d, int cell, int a)
     const size_t n = g.ncell;
     const Soa<double> Pm = soa(d.P, n, nm >= 0 ? nm : cell);
     const Soa<double> Pp = soa(d.P, n, np >= 0 ? np : cell);
-    const double h = g.h[a];
-    const double den = (nm >= 0 && np >= 0) ? 2.0 * h : h;
+    const double iden = (nm >= 0 && np >= 0) ? 0.5 * g.invh[a] : g.invh[a];
     const Soa<double> G = soa(d.grad, n, cell);
 #pragma unroll
-    for (int b = 0; b < 3; ++b) G[b * 3 + a] = (nm < 0 && np < 0) ? 0.0 : (Pp[1 + b] - Pm[1 + b]) / den;
+    for (int b = 0; b < 3; ++b) G[b * 3 + a] = (nm < 0 && np < 0) ? 0.0 : (Pp[1 + b] - Pm[1 + b]) * iden;
 }
 
 // Blocks [0, ngrad): central gradients of u, one (cell, axis) per thread.
@@ -290,8 +289,8 @@ __global__ __launch_bounds__(128) void k_mac_hot(GSIS_SPAN_ARGS)
         }
         double sigN[3], qN, qrN;
         const Soa<double> PL = soa(d.P, n, cell), PR = soa(d.P, n, nb);
-        nsf_face(g, PL, PR, soa(d.grad, n, cell), soa(d.grad, n, nb), a, g.h[a],
-                 pow(0.5 * (PL[4] + PR[4]), g.omega) / g.delta, sigN, &qN, &qrN);
+        nsf_face(g, PL, PR, soa(d.grad, n, cell), soa(d.grad, n, nb), a, g.invh[a],
+                 pow_pos(0.5 * (PL[4] + PR[4]), g.omega) / g.delta, sigN, &qN, &qrN);
         const Soa<double> Ki = soa(d.K, n, cell), Kj = soa(d.K, n, nb);
         for (int b = 0; b < 3; ++b) ho[b] = 0.5 * (Ki[col[a][b]] + Kj[col[a][b]]) - sigN[b];
         ho[3] = 0.5 * (Ki[6 + a] + Kj[6 + a]) - qN;
@@ -357,7 +356,7 @@ template <int DIR, int NW>
 __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, double out[NW], double &gam)
 {
     constexpr int a = DIR / 2;
-    const double h = g.h[a];
+    const double ih = g.invh[a];
     const size_t nc = g.ncell;
     // both sides' data into registers first, in parallel with the table lookup
     const int nb = grid_neighbour(g, cell, DIR);
@@ -380,15 +379,15 @@ __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, 
     const int n = d.nbr[(size_t)DIR * g.ncell + cell];
     if (n >= 0) {
         double F[6], Gam;
-        face_flux(g, PL, PR, GL, GR, a, h, HO, F, &Gam);
+        face_flux(g, PL, PR, GL, GR, a, ih, HO, F, &Gam);
 #pragma unroll
-        for (int k = 0; k < NW; ++k) out[k] = ((DIR & 1) ? F[k] : -F[k]) / h;
-        gam = Gam / h;
+        for (int k = 0; k < NW; ++k) out[k] = ((DIR & 1) ? F[k] : -F[k]) * ih;
+        gam = Gam * ih;
     } else {
         const int f = -n - 1;
 #pragma unroll
-        for (int k = 0; k < NW; ++k) out[k] = d.Fb[(size_t)k * g.nface + f] / h;
-        gam = d.Gb[f] / h;
+        for (int k = 0; k < NW; ++k) out[k] = d.Fb[(size_t)k * g.nface + f] * ih;
+        gam = d.Gb[f] * ih;
     }
 }
 
@@ -466,14 +465,15 @@ __global__ __launch_bounds__(384) void k_mac_res(GSIS_SPAN_ARGS, int slot)
     if (lane == 0 && D > 0.0) atomicMax(&d.dmax[slot], (unsigned long long)__double_as_longlong(D));
 }
 
-// W of a cell after the pseudo-time step: W + R / D*, the rotational-energy
-// row with its relaxation source on the diagonal.
-__device__ __forceinline__ void stepped_W(const Geo &g, const Dev &d, const double *Ws, int cell, double Dm, double Wn[6])
+// W of a cell after the pseudo-time step: W + R / D* (as R times 1/D*), the
+// rotational-energy row with its relaxation source on the diagonal.
+__device__ __forceinline__ void stepped_W(const Geo &g, const Dev &d, const double *Ws, int cell, double Dm, double iDm,
+                                          double Wn[6])
 {
     const Soa<const double> W = soa(Ws, g.ncell, cell);
     const Soa<double> r = soa(d.R, g.ncell, cell);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) Wn[k] = W[k] + r[k] / Dm;
+    for (int k = 0; k < 5; ++k) Wn[k] = W[k] + r[k] * iDm;
     Wn[5] = g.species == 1 ? W[5] + r[5] / (Dm + d.Src[cell]) : W[5];
 }
 
@@ -492,7 +492,7 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
     const BcInfo &bc = C.bc;
     const double *Ws = parity ? d.W2 : d.W;
     double *Wd = parity ? d.W : d.W2;
-    const double Dm = __longlong_as_double((long long)d.dmax[slot]);
+    const double Dm = __longlong_as_double((long long)d.dmax[slot]), iDm = 1.0 / Dm;
     const int ngrad = grad_blocks(g);
     if (blk < ngrad) {
         const int t = blk * blockDim.x + threadIdx.x;
@@ -500,7 +500,7 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
         const int cell = t / 3, a = t - 3 * (t / 3);
         if (cell >= g.ncell || !d.cflag[cell]) return;
         double Wn[6];
-        stepped_W(g, d, Ws, cell, Dm, Wn);
+        stepped_W(g, d, Ws, cell, Dm, iDm, Wn);
         if (a == 0) {
             const Soa<double> Wc = soa(Wd, g.ncell, cell);
 #pragma unroll
@@ -510,21 +510,21 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
         if (last) return;
         // neighbours' states loaded at grid indices, in parallel with the table lookup
         double Wm[6], Wp[6];
-        stepped_W(g, d, Ws, grid_neighbour(g, cell, 2 * a), Dm, Wm);
-        stepped_W(g, d, Ws, grid_neighbour(g, cell, 2 * a + 1), Dm, Wp);
+        stepped_W(g, d, Ws, grid_neighbour(g, cell, 2 * a), Dm, iDm, Wm);
+        stepped_W(g, d, Ws, grid_neighbour(g, cell, 2 * a + 1), Dm, iDm, Wp);
         const int nm = d.nbr[(size_t)(2 * a) * g.ncell + cell], np = d.nbr[(size_t)(2 * a + 1) * g.ncell + cell];
         double um[3], up[3];
+        const double ic = 1.0 / Wn[0], im = 1.0 / Wm[0], ip = 1.0 / Wp[0];
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            const double uc = Wn[1 + b] / Wn[0];
-            um[b] = nm >= 0 ? Wm[1 + b] / Wm[0] : uc;
-            up[b] = np >= 0 ? Wp[1 + b] / Wp[0] : uc;
+            const double uc = Wn[1 + b] * ic;
+            um[b] = nm >= 0 ? Wm[1 + b] * im : uc;
+            up[b] = np >= 0 ? Wp[1 + b] * ip : uc;
         }
-        const double h = g.h[a];
-        const double den = (nm >= 0 && np >= 0) ? 2.0 * h : h;
+        const double iden = (nm >= 0 && np >= 0) ? 0.5 * g.invh[a] : g.invh[a];
         const Soa<double> G = soa(d.grad, g.ncell, cell);
 #pragma unroll
-        for (int b = 0; b < 3; ++b) G[b * 3 + a] = (nm < 0 && np < 0) ? 0.0 : (up[b] - um[b]) / den;
+        for (int b = 0; b < 3; ++b) G[b * 3 + a] = (nm < 0 && np < 0) ? 0.0 : (up[b] - um[b]) * iden;
         return;
     }
     if (last) return;
@@ -533,7 +533,7 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
     if (f >= g.nface) return;
     const int cell = d.face_cell[f], dir = d.face_dir[f];
     double Wn[6], P[NP];
-    stepped_W(g, d, Ws, cell, Dm, Wn);
+    stepped_W(g, d, Ws, cell, Dm, iDm, Wn);
     prim_from_W(g, Wn, P);
     double Fe[6];
     group_equilibrium_flux(g, bc, d, P, dir, d.face_bc[f], sub, Fe);

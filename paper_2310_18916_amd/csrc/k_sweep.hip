@@ -19,7 +19,9 @@
 // slab are loaded cooperatively into LDS (double buffered, one barrier per
 // slab), and the tile's inflow faces -- read from the VDF, which the upwind
 // tile already holds in place, or the boundary values -- are prefetched into
-// registers one slab ahead.  The reference distribution is evaluated on the
+// registers one slab ahead; the VDF stores and the inflow-face reads are
+// non-temporal (streamed past the caches: nothing reads them back soon).
+// The reference distribution is evaluated on the
 // fly from the per-cell parameters (FP32 copies on the FP32 path), one
 // exponential per Maxwellian shape.  Every cell's update has a fixed operand
 // order, so the result is bitwise independent of the tile shape and of the
@@ -38,33 +40,9 @@ template <> struct Arith<float> {
     static __device__ __forceinline__ float ex(float x) { return __expf(x); }
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 };
-// e^x for x <= 0 (the argument of every Maxwellian factor here): x = n ln2 + r
-// with n = rint(x / ln2) and |r| <= ln2 / 2, the Cody-Waite two-part ln2 (the
-// high part has 32 significant bits, so n ln2_hi is exact) keeping r exact to
-// rounding; e^r by its Taylor polynomial to r^12 (truncation below 2e-16
-// relative on that interval), evaluated by Horner; 2^n through the exponent.
-// Arguments below -745 are clamped there, where e^x is zero in FP64.
-__device__ __forceinline__ double exp_nonpos(double x)
-{
-    x = fmax(x, -745.0);
-    const double n = rint(x * 1.4426950408889634074);
-    double r = fma(n, -6.93147180369123816490e-01, x);
-    r = fma(n, -1.90821492927058770002e-10, r);
-    double p = 1.0 / 479001600.0;
-    p = fma(p, r, 1.0 / 39916800.0);
-    p = fma(p, r, 1.0 / 3628800.0);
-    p = fma(p, r, 1.0 / 362880.0);
-    p = fma(p, r, 1.0 / 40320.0);
-    p = fma(p, r, 1.0 / 5040.0);
-    p = fma(p, r, 1.0 / 720.0);
-    p = fma(p, r, 1.0 / 120.0);
-    p = fma(p, r, 1.0 / 24.0);
-    p = fma(p, r, 1.0 / 6.0);
-    p = fma(p, r, 0.5);
-    p = fma(p, r, 1.0);
-    p = fma(p, r, 1.0);
-    return ldexp(p, (int)n);
-}
+// e^x for x <= 0 (the argument of every Maxwellian factor here): exp_core,
+// with arguments below -745 clamped there, where e^x is zero in FP64.
+__device__ __forceinline__ double exp_nonpos(double x) { return exp_core(fmax(x, -745.0)); }
 
 template <> struct Arith<double> {
     static __device__ __forceinline__ double ex(double x) { return exp_nonpos(x); }
@@ -190,7 +168,7 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
         const bool outside = (a == 0 ? ii : (a == 1 ? jj : kk)) == 0;
         const int step = a == 0 ? 1 : (a == 1 ? nx : nx * ny);
         const int nb = outside ? c : ((d & 1) ? c + step : c - step);
-        const T fv0 = f0[(size_t)nb * nv + node];
+        const T fv0 = __builtin_nontemporal_load((const T *)&f0[(size_t)nb * nv + node]);
         const T sc = fsc[(size_t)c * 6 + d];
         const int bcs = outside ? d : 6;
         const T m0 = mb[(size_t)bcs * nv + node];
@@ -198,7 +176,7 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
         if (MASK) wall = wall || !cflag[nb];
         v0 = wall ? sc * m0 : fv0;
         if (DIA) {
-            const T fv1 = f1[(size_t)nb * nv + node];
+            const T fv1 = __builtin_nontemporal_load((const T *)&f1[(size_t)nb * nv + node]);
             const T m1 = mb1[(size_t)bcs * nv + node];
             v1 = wall ? sc * m1 : fv1;
         }
@@ -321,11 +299,11 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
                     if (DIA) num1 = fma(az, F1, num1);
                     const T den = den0 + invtau;
                     const T v0 = Arith<T>::div(num0, den);
-                    c0[lnode] = v0;
+                    __builtin_nontemporal_store(v0, (T *)&c0[lnode]);
                     pl0[ky][kx] = v0;
                     if (DIA) {
                         const T v1 = Arith<T>::div(num1, den);
-                        c1[lnode] = v1;
+                        __builtin_nontemporal_store(v1, (T *)&c1[lnode]);
                         pl1[ky][kx] = v1;
                     }
                 }
