@@ -47,6 +47,12 @@ struct BcInfo {
 };
 
 // Device buffers, carved out of the caller's workspace.
+// The global pseudo-time diagonal D* = max_i D_i is gathered by atomic max
+// into DSLOT partial slots on separate cache lines (block b uses slot b mod
+// DSLOT), so the atomics of different blocks do not queue on one address;
+// readers take the max of the DSLOT partials.
+constexpr int DSLOT = 64, DSTRIDE = 16;
+
 struct Dev {
     void *f0, *f1;     // [ncell + 1][nv]: row ncell is the sink of the sweep's stores for dead cells
     double *mom8;      // [ncell][8][NRS]
@@ -79,7 +85,8 @@ struct Dev {
     // stress/heat flux K, HoT of the three + faces, residual R
     double *W, *W2, *P, *grad, *K, *hot, *R, *Dc, *Src, *fbfix, *Fb, *Gb;
     double *red;       // reduction scratch
-    unsigned long long *dmax;   // two slots, bit pattern of a positive double
+    unsigned long long *dmax;   // [2][DSLOT] partial maxima, one per 128-byte line (DSTRIDE words apart),
+                                // bit patterns of positive doubles
     int *errflag;
     // residual history of a batch (nullptr for a context on its own):
     // hist[(iteration % hist_cap) * hist_ncase + hist_index][6], iteration = *hist_ctr

@@ -230,7 +230,7 @@ size_t layout(gsis_ctx *c, char *base)
     carve(off, d.Fb, nf * 6, base);
     carve(off, d.Gb, nf, base);
     carve(off, d.red, (size_t)(resid_blocks(g) + 1) * 6, base);
-    carve(off, d.dmax, 2, base);
+    carve(off, d.dmax, (size_t)2 * DSLOT * DSTRIDE, base);
     carve(off, d.errflag, 4, base);
     return align256(off);
 }
@@ -561,7 +561,7 @@ gsis_status gsis_bind_workspace(gsis_ctx *ctx, void *device_ptr, size_t bytes)
     HIPCHK(ctx, up(d.perm, ctx->perm.data(), ctx->perm.size() * sizeof(int)));
     HIPCHK(ctx, upload_tiles(ctx));
     HIPCHK(ctx, hipMemset(d.errflag, 0, 4 * sizeof(int)));
-    HIPCHK(ctx, hipMemset(d.dmax, 0, 2 * sizeof(unsigned long long)));
+    HIPCHK(ctx, hipMemset(d.dmax, 0, (size_t)2 * DSLOT * DSTRIDE * sizeof(unsigned long long)));
     HIPCHK(ctx, launch_setup_tables(g, ctx->bc, d, nullptr));
     HIPCHK(ctx, hipDeviceSynchronize());
     ctx->bound = true;

@@ -123,8 +123,11 @@ __device__ __forceinline__ void face_flux(const Geo &g, const PV &L, const PV &R
 // the group ends with the result.
 constexpr int FG = 8;
 
-// gradient blocks of k_mac_grad: one (cell, axis) per thread, 256 threads
-__host__ __device__ inline int grad_blocks(const Geo &g) { return (3 * g.ncell + 255) / 256; }
+// gradient blocks of k_mac_grad and k_mac_advance: one (cell, axis) per
+// thread, 256 threads, axis-major (a block holds one axis of 256 cells), so a
+// wave's neighbour reads are coalesced and its work is uniform
+__host__ __device__ inline int grad_axis_blocks(const Geo &g) { return (g.ncell + 255) / 256; }
+__host__ __device__ inline int grad_blocks(const Geo &g) { return 3 * grad_axis_blocks(g); }
 
 __device__ __forceinline__ double group_sum(double v)
 {
@@ -251,8 +254,8 @@ __global__ __launch_bounds__(256) void k_mac_grad(GSIS_SPAN_ARGS, int with_faces
     const BcInfo &bc = C.bc;
     const int ngrad = grad_blocks(g);
     if (blk < ngrad) {
-        const int t = blk * blockDim.x + threadIdx.x;
-        const int cell = t / 3, a = t - 3 * (t / 3);
+        const int npa = grad_axis_blocks(g), a = blk / npa;
+        const int cell = (blk - a * npa) * (int)blockDim.x + (int)threadIdx.x;
         if (cell < g.ncell && d.cflag[cell]) cell_grad_col(g, d, cell, a);
         return;
     }
@@ -352,8 +355,11 @@ __device__ __forceinline__ int grid_neighbour(const Geo &g, int cell, int dir)
     return (dir & 1) ? min(cell + step, g.ncell - 1) : max(cell - step, 0);
 }
 
-template <int DIR, int NW>
-__device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, double out[NW], double &gam)
+// With KEEP the cell's own prims 0..10 are also returned in own[], loaded with
+// the face data, so the caller needs no second round trip to memory.
+template <int DIR, int NW, bool KEEP>
+__device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, double out[NW], double &gam,
+                                          double *own)
 {
     constexpr int a = DIR / 2;
     const double ih = g.invh[a];
@@ -376,6 +382,12 @@ __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, 
     }
 #pragma unroll
     for (int k = 0; k < 5; ++k) HO[k] = (DIA || k < 4) ? d.hot[(size_t)(a * 5 + k) * nc + L] : 0.0;
+    if (KEEP) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) own[k] = (DIR & 1) ? PL[k] : PR[k];
+        own[9] = d.P[(size_t)9 * nc + cell];
+        own[10] = d.P[(size_t)10 * nc + cell];
+    }
     const int n = d.nbr[(size_t)DIR * g.ncell + cell];
     if (n >= 0) {
         double F[6], Gam;
@@ -413,17 +425,17 @@ __global__ __launch_bounds__(384) void k_mac_res(GSIS_SPAN_ARGS, int slot)
     const int dir = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int cell = blk * RES_CELLS + lane;
     const bool live = cell < g.ncell && d.cflag[cell];
-    double out[NW], gam = 0.0;
+    double out[NW], gam = 0.0, Pi[11];
 #pragma unroll
     for (int k = 0; k < NW; ++k) out[k] = 0.0;
     if (live) {
         switch (dir) {
-        case 0: face_term<0, NW>(g, d, cell, out, gam); break;
-        case 1: face_term<1, NW>(g, d, cell, out, gam); break;
-        case 2: face_term<2, NW>(g, d, cell, out, gam); break;
-        case 3: face_term<3, NW>(g, d, cell, out, gam); break;
-        case 4: face_term<4, NW>(g, d, cell, out, gam); break;
-        default: face_term<5, NW>(g, d, cell, out, gam); break;
+        case 0: face_term<0, NW, true>(g, d, cell, out, gam, Pi); break;
+        case 1: face_term<1, NW, false>(g, d, cell, out, gam, nullptr); break;
+        case 2: face_term<2, NW, false>(g, d, cell, out, gam, nullptr); break;
+        case 3: face_term<3, NW, false>(g, d, cell, out, gam, nullptr); break;
+        case 4: face_term<4, NW, false>(g, d, cell, out, gam, nullptr); break;
+        default: face_term<5, NW, false>(g, d, cell, out, gam, nullptr); break;
         }
     }
 #pragma unroll
@@ -442,7 +454,6 @@ __global__ __launch_bounds__(384) void k_mac_res(GSIS_SPAN_ARGS, int slot)
             for (int k = 0; k < NW; ++k) res[k] -= red[j][k][lane];
             sumG += red[j][NW][lane];
         }
-        const Soa<double> Pi = soa(d.P, g.ncell, cell);
         const double invtau = Pi[10];
         if (DIA) {
             double T = (3.0 * Pi[4] + g.dr * Pi[5]) / (3.0 + g.dr);
@@ -462,7 +473,9 @@ __global__ __launch_bounds__(384) void k_mac_res(GSIS_SPAN_ARGS, int slot)
     }
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) D = fmax(D, __shfl_xor(D, m, 64));
-    if (lane == 0 && D > 0.0) atomicMax(&d.dmax[slot], (unsigned long long)__double_as_longlong(D));
+    if (lane == 0 && D > 0.0)
+        atomicMax(&d.dmax[(size_t)(slot * DSLOT + (blk & (DSLOT - 1))) * DSTRIDE],
+                  (unsigned long long)__double_as_longlong(D));
 }
 
 // W of a cell after the pseudo-time step: W + R / D* (as R times 1/D*), the
@@ -480,7 +493,7 @@ __device__ __forceinline__ void stepped_W(const Geo &g, const Dev &d, const doub
 // End of an inner iteration: W' = W + R / D* with the new prims, and -- unless
 // it is the last iteration -- the velocity gradient and the boundary-face
 // fluxes of the new state, in one launch.  Grid as k_mac_grad: (cell, axis)
-// threads (axis 0 also writes W' and the prims of its cell), then FG lanes per
+// threads (the axis-0 blocks also write W' and the prims), then FG lanes per
 // boundary face.  Neighbours' new velocities and the face cells' new prims are
 // formed from W and R directly, so W is double buffered (read src, write dst).
 __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, int parity, int last)
@@ -492,12 +505,18 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
     const BcInfo &bc = C.bc;
     const double *Ws = parity ? d.W2 : d.W;
     double *Wd = parity ? d.W : d.W2;
-    const double Dm = __longlong_as_double((long long)d.dmax[slot]), iDm = 1.0 / Dm;
+    // D*: each lane loads one partial slot, the wave takes their max
+    double Dm = __longlong_as_double((long long)d.dmax[(size_t)(slot * DSLOT + (threadIdx.x & (DSLOT - 1))) * DSTRIDE]);
+#pragma unroll
+    for (int m = 1; m < DSLOT; m <<= 1) Dm = fmax(Dm, __shfl_xor(Dm, m, 64));
+    const double iDm = 1.0 / Dm;
     const int ngrad = grad_blocks(g);
     if (blk < ngrad) {
-        const int t = blk * blockDim.x + threadIdx.x;
-        if (t == 0) d.dmax[slot ^ 1] = 0ull;   // the other slot was last used by the previous iteration
-        const int cell = t / 3, a = t - 3 * (t / 3);
+        // the other slot was last used by the previous iteration
+        if (blk == 0 && (int)threadIdx.x < DSLOT) d.dmax[(size_t)((slot ^ 1) * DSLOT + threadIdx.x) * DSTRIDE] = 0ull;
+        const int npa = grad_axis_blocks(g), a = blk / npa;
+        if (a != 0 && last) return;
+        const int cell = (blk - a * npa) * (int)blockDim.x + (int)threadIdx.x;
         if (cell >= g.ncell || !d.cflag[cell]) return;
         double Wn[6];
         stepped_W(g, d, Ws, cell, Dm, iDm, Wn);
@@ -546,7 +565,7 @@ __global__ void k_mac_reset(GSIS_SPAN_ARGS)
 {
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
-    if (threadIdx.x < 2) C.d.dmax[threadIdx.x] = 0ull;
+    for (int j = threadIdx.x; j < 2 * DSLOT; j += blockDim.x) C.d.dmax[(size_t)j * DSTRIDE] = 0ull;
 }
 
 // New half of the correction record; flags non-physical states.
