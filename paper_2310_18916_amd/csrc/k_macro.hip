@@ -128,6 +128,9 @@ constexpr int FG = 8;
 // wave's neighbour reads are coalesced and its work is uniform
 __host__ __device__ inline int grad_axis_blocks(const Geo &g) { return (g.ncell + 255) / 256; }
 __host__ __device__ inline int grad_blocks(const Geo &g) { return 3 * grad_axis_blocks(g); }
+// boundary-face blocks (FG lanes per face); they come first in a launch that
+// also has gradient blocks, so the longer face work starts first
+__host__ __device__ inline int face_blocks(const Geo &g) { return (g.nface * FG + 255) / 256; }
 
 __device__ __forceinline__ double group_sum(double v)
 {
@@ -242,9 +245,9 @@ __device__ void cell_grad_col(const Geo &g, const Dev &d, int cell, int a)
     for (int b = 0; b < 3; ++b) G[b * 3 + a] = (nm < 0 && np < 0) ? 0.0 : (Pp[1 + b] - Pm[1 + b]) * iden;
 }
 
-// Blocks [0, ngrad): central gradients of u, one (cell, axis) per thread.
-// Blocks [ngrad, ...): boundary faces, FG lanes per face: F_b = fixed part +
-// F_eq(W^m) and its Gamma (skipped when with_faces is 0).
+// Blocks [0, nfb): boundary faces, FG lanes per face: F_b = fixed part +
+// F_eq(W^m) and its Gamma (skipped when with_faces is 0).  Blocks [nfb, ...):
+// central gradients of u, one (cell, axis) per thread.
 __global__ __launch_bounds__(256) void k_mac_grad(GSIS_SPAN_ARGS, int with_faces)
 {
     int blk;
@@ -252,16 +255,16 @@ __global__ __launch_bounds__(256) void k_mac_grad(GSIS_SPAN_ARGS, int with_faces
     const Geo &g = C.g;
     const Dev &d = C.d;
     const BcInfo &bc = C.bc;
-    const int ngrad = grad_blocks(g);
-    if (blk < ngrad) {
-        const int npa = grad_axis_blocks(g), a = blk / npa;
-        const int cell = (blk - a * npa) * (int)blockDim.x + (int)threadIdx.x;
+    const int nfb = face_blocks(g);
+    if (blk >= nfb) {
+        const int gb = blk - nfb, npa = grad_axis_blocks(g), a = gb / npa;
+        const int cell = (gb - a * npa) * (int)blockDim.x + (int)threadIdx.x;
         if (cell < g.ncell && d.cflag[cell]) cell_grad_col(g, d, cell, a);
         return;
     }
     if (!with_faces) return;
     // whole groups of FG lanes share f, so the group butterflies stay inside live lanes
-    const int f = ((blk - ngrad) * (int)blockDim.x + (int)threadIdx.x) / FG;
+    const int f = (blk * (int)blockDim.x + (int)threadIdx.x) / FG;
     const int sub = threadIdx.x & (FG - 1);
     if (f >= g.nface) return;
     const int cell = d.face_cell[f], dir = d.face_dir[f];
@@ -411,8 +414,9 @@ __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, 
 // largest D_i.
 constexpr int RES_CELLS = 64;
 
+// Six waves per SIMD (at most 80 VGPRs): four blocks per CU instead of three.
 template <bool DIA>
-__global__ __launch_bounds__(384) void k_mac_res(GSIS_SPAN_ARGS, int slot)
+__global__ __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(6))) void k_mac_res(GSIS_SPAN_ARGS, int slot)
 {
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
@@ -490,11 +494,21 @@ __device__ __forceinline__ void stepped_W(const Geo &g, const Dev &d, const doub
     Wn[5] = g.species == 1 ? W[5] + r[5] / (Dm + d.Src[cell]) : W[5];
 }
 
+// Density and momentum rows of stepped_W only (what a neighbour's velocity needs).
+__device__ __forceinline__ void stepped_mass_momentum(const Geo &g, const Dev &d, const double *Ws, int cell,
+                                                      double iDm, double Wn[4])
+{
+    const Soa<const double> W = soa(Ws, g.ncell, cell);
+    const Soa<double> r = soa(d.R, g.ncell, cell);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Wn[k] = W[k] + r[k] * iDm;
+}
+
 // End of an inner iteration: W' = W + R / D* with the new prims, and -- unless
 // it is the last iteration -- the velocity gradient and the boundary-face
-// fluxes of the new state, in one launch.  Grid as k_mac_grad: (cell, axis)
-// threads (the axis-0 blocks also write W' and the prims), then FG lanes per
-// boundary face.  Neighbours' new velocities and the face cells' new prims are
+// fluxes of the new state, in one launch.  Grid as k_mac_grad: FG lanes per
+// boundary face, then (cell, axis) threads (the axis-0 blocks also write W'
+// and the prims).  Neighbours' new velocities and the face cells' new prims are
 // formed from W and R directly, so W is double buffered (read src, write dst).
 __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, int parity, int last)
 {
@@ -510,13 +524,14 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
 #pragma unroll
     for (int m = 1; m < DSLOT; m <<= 1) Dm = fmax(Dm, __shfl_xor(Dm, m, 64));
     const double iDm = 1.0 / Dm;
-    const int ngrad = grad_blocks(g);
-    if (blk < ngrad) {
+    const int nfb = face_blocks(g);
+    if (blk >= nfb) {
+        const int gb = blk - nfb;
         // the other slot was last used by the previous iteration
-        if (blk == 0 && (int)threadIdx.x < DSLOT) d.dmax[(size_t)((slot ^ 1) * DSLOT + threadIdx.x) * DSTRIDE] = 0ull;
-        const int npa = grad_axis_blocks(g), a = blk / npa;
+        if (gb == 0 && (int)threadIdx.x < DSLOT) d.dmax[(size_t)((slot ^ 1) * DSLOT + threadIdx.x) * DSTRIDE] = 0ull;
+        const int npa = grad_axis_blocks(g), a = gb / npa;
         if (a != 0 && last) return;
-        const int cell = (blk - a * npa) * (int)blockDim.x + (int)threadIdx.x;
+        const int cell = (gb - a * npa) * (int)blockDim.x + (int)threadIdx.x;
         if (cell >= g.ncell || !d.cflag[cell]) return;
         double Wn[6];
         stepped_W(g, d, Ws, cell, Dm, iDm, Wn);
@@ -528,9 +543,9 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
         }
         if (last) return;
         // neighbours' states loaded at grid indices, in parallel with the table lookup
-        double Wm[6], Wp[6];
-        stepped_W(g, d, Ws, grid_neighbour(g, cell, 2 * a), Dm, iDm, Wm);
-        stepped_W(g, d, Ws, grid_neighbour(g, cell, 2 * a + 1), Dm, iDm, Wp);
+        double Wm[4], Wp[4];
+        stepped_mass_momentum(g, d, Ws, grid_neighbour(g, cell, 2 * a), iDm, Wm);
+        stepped_mass_momentum(g, d, Ws, grid_neighbour(g, cell, 2 * a + 1), iDm, Wp);
         const int nm = d.nbr[(size_t)(2 * a) * g.ncell + cell], np = d.nbr[(size_t)(2 * a + 1) * g.ncell + cell];
         double um[3], up[3];
         const double ic = 1.0 / Wn[0], im = 1.0 / Wm[0], ip = 1.0 / Wp[0];
@@ -547,7 +562,7 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
         return;
     }
     if (last) return;
-    const int f = ((blk - ngrad) * (int)blockDim.x + (int)threadIdx.x) / FG;
+    const int f = (blk * (int)blockDim.x + (int)threadIdx.x) / FG;
     const int sub = threadIdx.x & (FG - 1);
     if (f >= g.nface) return;
     const int cell = d.face_cell[f], dir = d.face_dir[f];
@@ -611,8 +626,8 @@ int kind_blocks(const Geo &g, Kind k)
     case K_CELL256: return (g.ncell + 255) / 256;
     case K_CELL1: return g.ncell;
     case K_FACE256: return (g.nface + 255) / 256;
-    case K_FACE8: return (g.nface * FG + 255) / 256;
-    case K_GRAD: return grad_blocks(g) + (g.nface * FG + 255) / 256;
+    case K_FACE8: return face_blocks(g);
+    case K_GRAD: return grad_blocks(g) + face_blocks(g);
     case K_RES: return (g.ncell + RES_CELLS - 1) / RES_CELLS;
     case K_CASE: return 1;
     default: return 0;
