@@ -31,12 +31,16 @@ constexpr int NP = 12;
 // The per-cell (per-face) arrays of the macroscopic solve are structures of
 // arrays: field k of item i at buf[k * n + i], so the lanes of a wave, which
 // take consecutive cells, read consecutive words.  Soa is one item's view.
+// Every buffer is read and written through global-address-space pointers
+// (gptr), so the loads and stores are global rather than flat instructions.
 template <typename T> struct Soa {
-    T *p;
+    gptr<T> p;
     size_t n;
-    __device__ __forceinline__ T &operator[](int k) const { return p[(size_t)k * n]; }
+    __device__ __forceinline__ GSIS_GLOBAL_AS T &operator[](int k) const { return p[(size_t)k * n]; }
 };
-template <typename T> __device__ __forceinline__ Soa<T> soa(T *buf, size_t n, int i) { return Soa<T>{buf + i, n}; }
+template <typename T> __device__ __forceinline__ Soa<T> soa(T *buf, size_t n, int i) { return Soa<T>{(gptr<T>)buf + i, n}; }
+template <typename T> __device__ __forceinline__ Soa<T> soa(gptr<T> buf, size_t n, int i) { return Soa<T>{buf + i, n}; }
+template <typename T> __device__ __forceinline__ gptr<T> G(T *p) { return (gptr<T>)p; }
 
 template <class PV>
 __device__ __forceinline__ void prim_from_W(const Geo &g, const double *W, PV P)
@@ -149,10 +153,10 @@ __device__ void group_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev
     const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
     double H1 = 0, H2 = 0, H3 = 0;
     for (int k = sub; k < g.n1[a]; k += FG) {
-        const double x = d.xi64[a][k];
+        const double x = G(d.xi64[a])[k];
         if (!(sg * x > 0.0)) continue;
         const double c = x - P[1 + a];
-        const double e = d.w64[a][k] * exp_core(fmax(-c * c * iT, -745.0));
+        const double e = G(d.w64[a])[k] * exp_core(fmax(-c * c * iT, -745.0));
         H1 += e * x;
         H2 += e * x * x;
         H3 += e * x * x * x;
@@ -163,8 +167,8 @@ __device__ void group_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev
     for (int q = 0; q < 2; ++q) {
         const int ax = ax2[q];
         for (int k = sub; k < g.n1[ax]; k += FG) {
-            const double x = d.xi64[ax][k], c = x - P[1 + ax];
-            const double e = d.w64[ax][k] * exp_core(fmax(-c * c * iT, -745.0));
+            const double x = G(d.xi64[ax])[k], c = x - P[1 + ax];
+            const double e = G(d.w64[ax])[k] * exp_core(fmax(-c * c * iT, -745.0));
             S[q][0] += e;
             S[q][1] += e * x;
             S[q][2] += e * x * x;
@@ -187,7 +191,7 @@ __device__ void group_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev
     const double h1 = g.species == 1 ? 0.5 * g.dr * P[5] : 0.0;
     out[4] = K * (H3 * S[0][0] * S[1][0] + H1 * S[0][2] * S[1][0] + H1 * S[0][0] * S[1][2]) + h1 * out[0];
     out[5] = h1 * out[0];
-    const double *in = d.inpsi + (b * 6 + dir) * 6;
+    const gptr<const double> in = G((const double *)d.inpsi) + (b * 6 + dir) * 6;
     const double sc = bc.kind[b] == 1 ? bc.rho[b] : out[0] / (-in[0]);
 #pragma unroll
     for (int k = 0; k < 6; ++k) F[k] = out[k] + sc * in[k];
@@ -208,8 +212,8 @@ __global__ __launch_bounds__(128) void k_mac_init(GSIS_SPAN_ARGS)
     const Geo &g = C.g;
     const Dev &d = C.d;
     int cell = blk * blockDim.x + threadIdx.x;
-    if (cell >= g.ncell || !d.cflag[cell]) return;
-    const double *m = d.cm + (size_t)cell * NMOM;
+    if (cell >= g.ncell || !G(d.cflag)[cell]) return;
+    const gptr<const double> m = G((const double *)d.cm) + (size_t)cell * NMOM;
     double rho = m[0], Tt = m[4];
     double uu = m[1] * m[1] + m[2] * m[2] + m[3] * m[3];
     double Er = g.species == 1 ? 0.5 * g.dr * rho * m[14] : 0.0;
@@ -225,7 +229,7 @@ __global__ __launch_bounds__(128) void k_mac_init(GSIS_SPAN_ARGS)
     for (int k = 0; k < 6; ++k) K[k] = m[5 + k];
     for (int k = 0; k < 3; ++k) K[6 + k] = m[11 + k];
     for (int k = 0; k < 3; ++k) K[9 + k] = g.species == 1 ? m[15 + k] : 0.0;
-    double *c = d.corr + (size_t)cell * NCORR;
+    const gptr<double> c = G(d.corr) + (size_t)cell * NCORR;
     c[6] = rho; c[7] = m[1]; c[8] = m[2]; c[9] = m[3]; c[10] = Tt;
     c[11] = g.species == 1 ? m[14] : Tt;
     prim_from_W(g, W, soa(d.P, n, cell));
@@ -235,7 +239,7 @@ __global__ __launch_bounds__(128) void k_mac_init(GSIS_SPAN_ARGS)
 // next to a non-fluid neighbour, zero with none.
 __device__ void cell_grad_col(const Geo &g, const Dev &d, int cell, int a)
 {
-    const int nm = d.nbr[(size_t)(2 * a) * g.ncell + cell], np = d.nbr[(size_t)(2 * a + 1) * g.ncell + cell];
+    const int nm = G(d.nbr)[(size_t)(2 * a) * g.ncell + cell], np = G(d.nbr)[(size_t)(2 * a + 1) * g.ncell + cell];
     const size_t n = g.ncell;
     const Soa<double> Pm = soa(d.P, n, nm >= 0 ? nm : cell);
     const Soa<double> Pp = soa(d.P, n, np >= 0 ? np : cell);
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(256) void k_mac_grad(GSIS_SPAN_ARGS, int with_faces
     if (blk >= nfb) {
         const int gb = blk - nfb, npa = grad_axis_blocks(g), a = gb / npa;
         const int cell = (gb - a * npa) * (int)blockDim.x + (int)threadIdx.x;
-        if (cell < g.ncell && d.cflag[cell]) cell_grad_col(g, d, cell, a);
+        if (cell < g.ncell && G(d.cflag)[cell]) cell_grad_col(g, d, cell, a);
         return;
     }
     if (!with_faces) return;
@@ -267,12 +271,12 @@ __global__ __launch_bounds__(256) void k_mac_grad(GSIS_SPAN_ARGS, int with_faces
     const int f = (blk * (int)blockDim.x + (int)threadIdx.x) / FG;
     const int sub = threadIdx.x & (FG - 1);
     if (f >= g.nface) return;
-    const int cell = d.face_cell[f], dir = d.face_dir[f];
+    const int cell = G(d.face_cell)[f], dir = G(d.face_dir)[f];
     const Soa<double> P = soa(d.P, g.ncell, cell);
     double Fe[6];
-    group_equilibrium_flux(g, bc, d, P, dir, d.face_bc[f], sub, Fe);
-    if (sub < 6) d.Fb[(size_t)sub * g.nface + f] = d.fbfix[(size_t)sub * g.nface + f] + Fe[sub];
-    if (sub == 7) d.Gb[f] = boundary_gamma(g, P, dir / 2);
+    group_equilibrium_flux(g, bc, d, P, dir, G(d.face_bc)[f], sub, Fe);
+    if (sub < 6) G(d.Fb)[(size_t)sub * g.nface + f] = G(d.fbfix)[(size_t)sub * g.nface + f] + Fe[sub];
+    if (sub == 7) G(d.Gb)[f] = boundary_gamma(g, P, dir / 2);
 }
 
 // HoT at the faces (cell, cell + e_a) from W^{n+1/2}.
@@ -283,11 +287,11 @@ __global__ __launch_bounds__(128) void k_mac_hot(GSIS_SPAN_ARGS)
     const Geo &g = C.g;
     const Dev &d = C.d;
     int cell = blk * blockDim.x + threadIdx.x;
-    if (cell >= g.ncell || !d.cflag[cell]) return;
+    if (cell >= g.ncell || !G(d.cflag)[cell]) return;
     const int col[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
     const size_t n = g.ncell;
     for (int a = 0; a < 3; ++a) {
-        int nb = d.nbr[(size_t)(2 * a + 1) * g.ncell + cell];
+        int nb = G(d.nbr)[(size_t)(2 * a + 1) * g.ncell + cell];
         const Soa<double> ho = soa(d.hot + (size_t)a * 5 * n, n, cell);
         if (nb < 0) {
             for (int k = 0; k < 5; ++k) ho[k] = 0.0;
@@ -317,7 +321,7 @@ __global__ __launch_bounds__(256) void k_mac_fbfix(GSIS_SPAN_ARGS)
     const int f = (int)(blk * blockDim.x + threadIdx.x) / FG;
     const int sub = threadIdx.x & (FG - 1);
     if (f >= g.nface) return;
-    const int cell = d.face_cell[f], dir = d.face_dir[f], b = d.face_bc[f];
+    const int cell = G(d.face_cell)[f], dir = G(d.face_dir)[f], b = G(d.face_bc)[f];
     const int a = dir / 2;
     const int neg = (dir & 1) ? 0 : 1;
     const double sg = neg ? -1.0 : 1.0;
@@ -325,24 +329,24 @@ __global__ __launch_bounds__(256) void k_mac_fbfix(GSIS_SPAN_ARGS)
     const int m2row[3][3] = {{4, 7, 8}, {7, 5, 9}, {8, 9, 6}};
     for (int o = 0; o < 8; ++o) {
         if (((o >> a) & 1) != neg) continue;
-        const double *m = d.mom8 + ((size_t)cell * 8 + o) * NRS;
+        const gptr<const double> m = G((const double *)d.mom8) + ((size_t)cell * 8 + o) * NRS;
         out[0] += m[1 + a];
         for (int c = 0; c < 3; ++c) out[1 + c] += m[m2row[a][c]];
         out[4] += m[10 + a] + m[14 + a];
         out[5] += m[14 + a];
     }
     for (int k = 0; k < 6; ++k) out[k] *= sg;
-    const double *in = d.inpsi + (b * 6 + dir) * 6;
+    const gptr<const double> in = G((const double *)d.inpsi) + (b * 6 + dir) * 6;
     const double sc = bc.kind[b] == 1 ? bc.rho[b] : out[0] / (-in[0]);
     const Soa<double> P = soa(d.P, g.ncell, cell);
     double Fe[6];
     group_equilibrium_flux(g, bc, d, P, dir, b, sub, Fe);
     if (sub < 6) {
         const double fix = out[sub] + sc * in[sub] - Fe[sub];
-        d.fbfix[(size_t)sub * g.nface + f] = fix;
-        d.Fb[(size_t)sub * g.nface + f] = fix + Fe[sub];
+        G(d.fbfix)[(size_t)sub * g.nface + f] = fix;
+        G(d.Fb)[(size_t)sub * g.nface + f] = fix + Fe[sub];
     }
-    if (sub == 7) d.Gb[f] = boundary_gamma(g, P, a);
+    if (sub == 7) G(d.Gb)[f] = boundary_gamma(g, P, a);
 }
 
 // Flux of face dir of a cell divided by h (outward positive), and Gamma / h.
@@ -377,21 +381,21 @@ __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, 
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const bool use = DIA || (k != 5 && k != 7);
-        PL[k] = use ? d.P[(size_t)k * nc + L] : 0.0;
-        PR[k] = use ? d.P[(size_t)k * nc + R] : 0.0;
+        PL[k] = use ? G(d.P)[(size_t)k * nc + L] : 0.0;
+        PR[k] = use ? G(d.P)[(size_t)k * nc + R] : 0.0;
         const bool tan = k % 3 != a;
-        GL[k] = tan ? d.grad[(size_t)k * nc + L] : 0.0;
-        GR[k] = tan ? d.grad[(size_t)k * nc + R] : 0.0;
+        GL[k] = tan ? G(d.grad)[(size_t)k * nc + L] : 0.0;
+        GR[k] = tan ? G(d.grad)[(size_t)k * nc + R] : 0.0;
     }
 #pragma unroll
-    for (int k = 0; k < 5; ++k) HO[k] = (DIA || k < 4) ? d.hot[(size_t)(a * 5 + k) * nc + L] : 0.0;
+    for (int k = 0; k < 5; ++k) HO[k] = (DIA || k < 4) ? G(d.hot)[(size_t)(a * 5 + k) * nc + L] : 0.0;
     if (KEEP) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) own[k] = (DIR & 1) ? PL[k] : PR[k];
-        own[9] = d.P[(size_t)9 * nc + cell];
-        own[10] = d.P[(size_t)10 * nc + cell];
+        own[9] = G(d.P)[(size_t)9 * nc + cell];
+        own[10] = G(d.P)[(size_t)10 * nc + cell];
     }
-    const int n = d.nbr[(size_t)DIR * g.ncell + cell];
+    const int n = G(d.nbr)[(size_t)DIR * g.ncell + cell];
     if (n >= 0) {
         double F[6], Gam;
         face_flux(g, PL, PR, GL, GR, a, ih, HO, F, &Gam);
@@ -401,8 +405,8 @@ __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, 
     } else {
         const int f = -n - 1;
 #pragma unroll
-        for (int k = 0; k < NW; ++k) out[k] = d.Fb[(size_t)k * g.nface + f] * ih;
-        gam = d.Gb[f] * ih;
+        for (int k = 0; k < NW; ++k) out[k] = G(d.Fb)[(size_t)k * g.nface + f] * ih;
+        gam = G(d.Gb)[f] * ih;
     }
 }
 
@@ -428,7 +432,7 @@ __global__ __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(6))) void k
     const int lane = threadIdx.x & 63;
     const int dir = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int cell = blk * RES_CELLS + lane;
-    const bool live = cell < g.ncell && d.cflag[cell];
+    const bool live = cell < g.ncell && G(d.cflag)[cell];
     double out[NW], gam = 0.0, Pi[11];
 #pragma unroll
     for (int k = 0; k < NW; ++k) out[k] = 0.0;
@@ -469,7 +473,7 @@ __global__ __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(6))) void k
         const Soa<double> r = soa(d.R, g.ncell, cell);
 #pragma unroll
         for (int k = 0; k < 6; ++k) r[k] = res[k];
-        d.Src[cell] = DIA ? invtau / g.Zr : 0.0;
+        G(d.Src)[cell] = DIA ? invtau / g.Zr : 0.0;
         if (!(D > 0.0 && isfinite(D))) {
             atomicOr(d.errflag, 2);
             D = 0.0;
@@ -484,18 +488,18 @@ __global__ __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(6))) void k
 
 // W of a cell after the pseudo-time step: W + R / D* (as R times 1/D*), the
 // rotational-energy row with its relaxation source on the diagonal.
-__device__ __forceinline__ void stepped_W(const Geo &g, const Dev &d, const double *Ws, int cell, double Dm, double iDm,
+__device__ __forceinline__ void stepped_W(const Geo &g, const Dev &d, gptr<const double> Ws, int cell, double Dm, double iDm,
                                           double Wn[6])
 {
     const Soa<const double> W = soa(Ws, g.ncell, cell);
     const Soa<double> r = soa(d.R, g.ncell, cell);
 #pragma unroll
     for (int k = 0; k < 5; ++k) Wn[k] = W[k] + r[k] * iDm;
-    Wn[5] = g.species == 1 ? W[5] + r[5] / (Dm + d.Src[cell]) : W[5];
+    Wn[5] = g.species == 1 ? W[5] + r[5] / (Dm + G(d.Src)[cell]) : W[5];
 }
 
 // Density and momentum rows of stepped_W only (what a neighbour's velocity needs).
-__device__ __forceinline__ void stepped_mass_momentum(const Geo &g, const Dev &d, const double *Ws, int cell,
+__device__ __forceinline__ void stepped_mass_momentum(const Geo &g, const Dev &d, gptr<const double> Ws, int cell,
                                                       double iDm, double Wn[4])
 {
     const Soa<const double> W = soa(Ws, g.ncell, cell);
@@ -517,10 +521,10 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
     const Geo &g = C.g;
     const Dev &d = C.d;
     const BcInfo &bc = C.bc;
-    const double *Ws = parity ? d.W2 : d.W;
-    double *Wd = parity ? d.W : d.W2;
+    const gptr<const double> Ws = G((const double *)(parity ? d.W2 : d.W));
+    const gptr<double> Wd = G(parity ? d.W : d.W2);
     // D*: each lane loads one partial slot, the wave takes their max
-    double Dm = __longlong_as_double((long long)d.dmax[(size_t)(slot * DSLOT + (threadIdx.x & (DSLOT - 1))) * DSTRIDE]);
+    double Dm = __longlong_as_double((long long)G(d.dmax)[(size_t)(slot * DSLOT + (threadIdx.x & (DSLOT - 1))) * DSTRIDE]);
 #pragma unroll
     for (int m = 1; m < DSLOT; m <<= 1) Dm = fmax(Dm, __shfl_xor(Dm, m, 64));
     const double iDm = 1.0 / Dm;
@@ -528,11 +532,11 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
     if (blk >= nfb) {
         const int gb = blk - nfb;
         // the other slot was last used by the previous iteration
-        if (gb == 0 && (int)threadIdx.x < DSLOT) d.dmax[(size_t)((slot ^ 1) * DSLOT + threadIdx.x) * DSTRIDE] = 0ull;
+        if (gb == 0 && (int)threadIdx.x < DSLOT) G(d.dmax)[(size_t)((slot ^ 1) * DSLOT + threadIdx.x) * DSTRIDE] = 0ull;
         const int npa = grad_axis_blocks(g), a = gb / npa;
         if (a != 0 && last) return;
         const int cell = (gb - a * npa) * (int)blockDim.x + (int)threadIdx.x;
-        if (cell >= g.ncell || !d.cflag[cell]) return;
+        if (cell >= g.ncell || !G(d.cflag)[cell]) return;
         double Wn[6];
         stepped_W(g, d, Ws, cell, Dm, iDm, Wn);
         if (a == 0) {
@@ -546,7 +550,7 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
         double Wm[4], Wp[4];
         stepped_mass_momentum(g, d, Ws, grid_neighbour(g, cell, 2 * a), iDm, Wm);
         stepped_mass_momentum(g, d, Ws, grid_neighbour(g, cell, 2 * a + 1), iDm, Wp);
-        const int nm = d.nbr[(size_t)(2 * a) * g.ncell + cell], np = d.nbr[(size_t)(2 * a + 1) * g.ncell + cell];
+        const int nm = G(d.nbr)[(size_t)(2 * a) * g.ncell + cell], np = G(d.nbr)[(size_t)(2 * a + 1) * g.ncell + cell];
         double um[3], up[3];
         const double ic = 1.0 / Wn[0], im = 1.0 / Wm[0], ip = 1.0 / Wp[0];
 #pragma unroll
@@ -565,14 +569,14 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
     const int f = (blk * (int)blockDim.x + (int)threadIdx.x) / FG;
     const int sub = threadIdx.x & (FG - 1);
     if (f >= g.nface) return;
-    const int cell = d.face_cell[f], dir = d.face_dir[f];
+    const int cell = G(d.face_cell)[f], dir = G(d.face_dir)[f];
     double Wn[6], P[NP];
     stepped_W(g, d, Ws, cell, Dm, iDm, Wn);
     prim_from_W(g, Wn, P);
     double Fe[6];
-    group_equilibrium_flux(g, bc, d, P, dir, d.face_bc[f], sub, Fe);
-    if (sub < 6) d.Fb[(size_t)sub * g.nface + f] = d.fbfix[(size_t)sub * g.nface + f] + Fe[sub];
-    if (sub == 7) d.Gb[f] = boundary_gamma(g, P, dir / 2);
+    group_equilibrium_flux(g, bc, d, P, dir, G(d.face_bc)[f], sub, Fe);
+    if (sub < 6) G(d.Fb)[(size_t)sub * g.nface + f] = G(d.fbfix)[(size_t)sub * g.nface + f] + Fe[sub];
+    if (sub == 7) G(d.Gb)[f] = boundary_gamma(g, P, dir / 2);
 }
 
 // one block per case
@@ -580,7 +584,7 @@ __global__ void k_mac_reset(GSIS_SPAN_ARGS)
 {
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
-    for (int j = threadIdx.x; j < 2 * DSLOT; j += blockDim.x) C.d.dmax[(size_t)j * DSTRIDE] = 0ull;
+    for (int j = threadIdx.x; j < 2 * DSLOT; j += blockDim.x) G(C.d.dmax)[(size_t)j * DSTRIDE] = 0ull;
 }
 
 // New half of the correction record; flags non-physical states.
@@ -591,9 +595,9 @@ __global__ __launch_bounds__(128) void k_mac_final(GSIS_SPAN_ARGS)
     const Geo &g = C.g;
     const Dev &d = C.d;
     int cell = blk * blockDim.x + threadIdx.x;
-    if (cell >= g.ncell || !d.cflag[cell]) return;
+    if (cell >= g.ncell || !G(d.cflag)[cell]) return;
     const Soa<double> P = soa(d.P, g.ncell, cell);
-    double *c = d.corr + (size_t)cell * NCORR;
+    const gptr<double> c = G(d.corr) + (size_t)cell * NCORR;
     c[0] = P[0]; c[1] = P[1]; c[2] = P[2]; c[3] = P[3]; c[4] = P[4];
     c[5] = g.species == 1 ? P[5] : P[4];
     if (!(P[0] > 0.0) || !(P[4] > 0.0) || !isfinite(P[6]) || (g.species == 1 && !(P[5] > 0.0))) atomicOr(d.errflag, 4);
