@@ -88,6 +88,13 @@ int sweep_nvb(const Geo &g, int bs)
     return (omax + bs - 1) / bs;
 }
 
+// velocity nodes per sweep block: one run of 64 for a wave grid (its waves
+// share the nodes), the block size otherwise
+int block_nodes(const gsis_ctx *c)
+{
+    return sweep_shape_waves(c->fp32, c->tx, c->ty) > 1 ? 64 : c->bs;
+}
+
 void build_tiles(gsis_ctx *c)
 {
     const Geo &g = c->g;
@@ -106,7 +113,7 @@ void build_tiles(gsis_ctx *c)
                 c->tiles.push_back(x | (y << 10) | (z << 20));
             }
         c->plane_cnt[s] = (int)c->tiles.size() - c->plane_off[s];
-        c->npblk[s] = c->plane_cnt[s] * 8 * sweep_nvb(g, c->bs);
+        c->npblk[s] = c->plane_cnt[s] * 8 * sweep_nvb(g, block_nodes(c));
     }
 }
 
@@ -271,7 +278,7 @@ hipError_t upload_tiles(gsis_ctx *c)
     c->hcase.bc = c->bc;
     c->hcase.d = c->d;
     c->hcase.tz = c->tz;
-    c->hcase.nvb = sweep_nvb(c->g, c->bs);
+    c->hcase.nvb = sweep_nvb(c->g, block_nodes(c));
     if (e == hipSuccess) e = hipMemcpy(c->dcase, &c->hcase, sizeof(Case), hipMemcpyHostToDevice);
     return e;
 }
@@ -806,7 +813,9 @@ gsis_status gsis_set_tile(gsis_ctx *ctx, int tx, int ty, int tz, int block)
         if (!sweep_shape_supported(ctx->fp32, ctx->g.species == GSIS_DIATOMIC, tx, ty))
             return fail(ctx, GSIS_EINVAL, "tile (tx, ty) not compiled for this precision and gas");
         if (tz < 1 || tz > 1024) return fail(ctx, GSIS_EINVAL, "tz must be 1..1024");
-        if (block != 64 && block != 128 && block != 256) return fail(ctx, GSIS_EINVAL, "block must be 64, 128 or 256");
+        const int nw = sweep_shape_waves(ctx->fp32, tx, ty);
+        if (nw > 1 && block != 64 * nw) return fail(ctx, GSIS_EINVAL, "block must be 64 x the waves of this tile's wave grid");
+        if (nw == 1 && block != 64 && block != 128 && block != 256) return fail(ctx, GSIS_EINVAL, "block must be 64, 128 or 256");
         int ntx = (ctx->g.nx + tx - 1) / tx, nty = (ctx->g.ny + ty - 1) / ty, ntz = (ctx->g.nz + tz - 1) / tz;
         if (ntx > 1023 || nty > 1023 || ntz > 1023) return fail(ctx, GSIS_EINVAL, "too many tiles per axis");
         ctx->tx = tx; ctx->ty = ty; ctx->tz = tz; ctx->bs = block;
@@ -831,8 +840,10 @@ gsis_status gsis_autotune(gsis_ctx *ctx, int reps, int *cfg_out, double *ms_out,
     for (int k = 0; k < nsh; ++k) {
         int tx = shapes[2 * k], ty = shapes[2 * k + 1];
         if (!sweep_shape_supported(ctx->fp32, dia, tx, ty)) continue;
+        const int nw = sweep_shape_waves(ctx->fp32, tx, ty);
         for (int tz : {tx / 2, tx, 2 * tx, 4 * tx})
-            for (int bs : {64, 128, 256}) cands.push_back({tx, ty, std::max(tz, 1), bs, 0.0});
+            for (int bs : {64, 128, 256})
+                if (nw == 1 || bs == 64 * nw) cands.push_back({tx, ty, std::max(tz, 1), bs, 0.0});
     }
     int save[4] = {ctx->tx, ctx->ty, ctx->tz, ctx->bs};
     {
@@ -1327,8 +1338,10 @@ gsis_status gsis_batch_autotune(gsis_batch *b, int reps, int *cfg_out, double *m
     for (int k = 0; k < nsh; ++k) {
         int tx = shapes[2 * k], ty = shapes[2 * k + 1];
         if (!sweep_shape_supported(b->fp32, b->dia, tx, ty)) continue;
+        const int nw = sweep_shape_waves(b->fp32, tx, ty);
         for (int tz : {tx / 2, tx, 2 * tx, 4 * tx})
-            for (int bs : {64, 128, 256}) cands.push_back({tx, ty, std::max(tz, 1), bs, 0.0});
+            for (int bs : {64, 128, 256})
+                if (nw == 1 || bs == 64 * nw) cands.push_back({tx, ty, std::max(tz, 1), bs, 0.0});
     }
     (void)c0;
     const int save[4] = {b->tx, b->ty, b->tz, b->bs};

@@ -44,6 +44,8 @@ hipError_t launch_params(const Target &t, hipStream_t s);
 hipError_t launch_face_scale(const Target &t, hipStream_t s);
 
 bool sweep_shape_supported(bool fp32, bool dia, int tx, int ty);
+// waves of the wave grid serving tile (tx, ty): 1 for a single-wave slab, 0 if not compiled
+int sweep_shape_waves(bool fp32, int tx, int ty);
 int sweep_shapes(bool fp32, int *out, int max);
 hipError_t launch_sweep(const Target &t, hipStream_t s);
 

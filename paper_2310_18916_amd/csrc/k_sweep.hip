@@ -91,18 +91,36 @@ __device__ __forceinline__ void ref_dia(const T *p, T cx, T cy, T cz, T &g0, T &
     g1 = fma(Et, rt, Er * rr);
 }
 
-template <typename T, int TX, int TY, bool DIA, bool RFN, bool MASK>
+// TX x TY is the slab one wave holds.  With a wave grid (WX x WY > 1) a
+// block of WX WY waves owns a (WX TX) x (WY TY) tile for one run of 64 nodes:
+// wave (wx, wy) holds sub-tile (wx, wy) and runs WX + WY - 2 steps behind
+// (wx + wy steps after the first), so at every step the slab it works on has
+// its x- and y-upwind slabs finished by the waves before it, which hand over
+// their exit faces through LDS (double buffered by step parity, one barrier
+// per step).  Only the tile's own inflow faces are read from the VDF, so a
+// wave grid reads 1/(WX TX) + 1/(WY TY) + 1/TZ of the points again instead of
+// 1/TX + 1/TY + 1/TZ.
+template <typename T, int TX, int TY, int WX, int WY, bool DIA, bool RFN, bool MASK>
 __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
 {
     // no automatic contraction: every fused multiply-add is written out, so the
     // operations of a cell update do not depend on the surrounding code
 #pragma clang fp contract(off)
+    constexpr int NWV = WX * WY;                  // waves sharing the nodes of a block
+    constexpr bool GRID = NWV > 1;
     constexpr int NPL = DIA ? 36 : 16;            // parameters per cell kept in LDS
     constexpr int NC = TX * TY;                   // cells per slab
     constexpr int NM = NC * NPL;                  // parameter words per slab
     constexpr int MPT = (NM + 63) / 64;           // words per thread for the smallest block (64)
-    __shared__ T spar[2][NM];
-    __shared__ int sflag[2][NC];
+    __shared__ T spar[NWV][2][NM];
+    __shared__ int sflag[NWV][2][NC];
+    // exit faces handed downstream inside a wave grid: x faces written by the
+    // waves with wx < WX - 1, y faces by those with wy < WY - 1
+    constexpr int ND = DIA ? 2 : 1;
+    constexpr int XWN = GRID && WX > 1 ? (WX - 1) * WY : 1, YWN = GRID && WY > 1 ? WX * (WY - 1) : 1;
+    constexpr int FXN = GRID ? TY : 1, FYN = GRID ? TX : 1, FL = GRID ? 64 : 1;
+    __shared__ T xface[ND][XWN][2][FXN][FL];
+    __shared__ T yface[ND][YWN][2][FYN][FL];
 
     int b;
     const Case &C = case_of(span_cases, span_map, b);
@@ -114,14 +132,19 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
     const int vb = b % nvb;
     const int o = (b / nvb) & 7;
     const int t = b / (nvb * 8);
-    const int bs = blockDim.x;
-    const int l = vb * bs + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int w = GRID ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
+    const int wx = w % WX, wy = w / WX;
+    const int bs = GRID ? 64 : (int)blockDim.x;   // nodes per block, and threads of the meta loads
+    const int ml = GRID ? lane : (int)threadIdx.x;
+    const int l = vb * bs + ml;
     const bool active = l < g.osize[o];           // inactive threads still join loads and barriers
     const int packed = ((gptr<const int>)C.d.tiles)[plane_off + t];
     const int tx = packed & 0x3ff, ty = (packed >> 10) & 0x3ff, tz = (packed >> 20) & 0x3ff;
     const int sx = o & 1, sy = (o >> 1) & 1, sz = (o >> 2) & 1;
     const int dxu = sx, dyu = 2 + sy, dzu = 4 + sz;   // upwind faces
-    const int i0 = tx * TX, j0 = ty * TY, k0 = tz * TZ;
+    // origin of this wave's slab column (the tile's, for a single wave)
+    const int i0 = tx * (TX * WX) + wx * TX, j0 = ty * (TY * WY) + wy * TY, k0 = tz * TZ;
     const int nx = g.nx, ny = g.ny, nz = g.nz, ncell = g.ncell;
     const size_t nv = (size_t)g.nv;
 
@@ -162,21 +185,23 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
     // (final: the upwind tile ran earlier, the VDF is updated in place) or the
     // boundary value rho_b M_b(xi) of the face.  All loads are independent and
     // unconditional, so they can be issued a slab ahead.
-    auto inflow = [&](int c, int kx, int ky, int kz, int d, T &v0, T &v1) {
+    // With handed (a face inside a wave grid) the neighbour's value arrives in
+    // LDS later: only the wall value and flag are prepared here.
+    auto inflow = [&](int c, int kx, int ky, int kz, int d, T &v0, T &v1, bool handed, bool &wall) {
         const int a = d >> 1;
         const int ii = i0 + kx, jj = j0 + ky, kk = k0 + kz;   // tile frame; upwind = one step back
         const bool outside = (a == 0 ? ii : (a == 1 ? jj : kk)) == 0;
         const int step = a == 0 ? 1 : (a == 1 ? nx : nx * ny);
         const int nb = outside ? c : ((d & 1) ? c + step : c - step);
-        const T fv0 = __builtin_nontemporal_load((const T *)&f0[(size_t)nb * nv + node]);
+        const T fv0 = handed ? T(0) : __builtin_nontemporal_load((const T *)&f0[(size_t)nb * nv + node]);
         const T sc = fsc[(size_t)c * 6 + d];
         const int bcs = outside ? d : 6;
         const T m0 = mb[(size_t)bcs * nv + node];
-        bool wall = outside;
+        wall = outside;
         if (MASK) wall = wall || !cflag[nb];
         v0 = wall ? sc * m0 : fv0;
         if (DIA) {
-            const T fv1 = __builtin_nontemporal_load((const T *)&f1[(size_t)nb * nv + node]);
+            const T fv1 = handed ? T(0) : __builtin_nontemporal_load((const T *)&f1[(size_t)nb * nv + node]);
             const T m1 = mb1[(size_t)bcs * nv + node];
             v1 = wall ? sc * m1 : fv1;
         }
@@ -194,7 +219,7 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
 #pragma unroll
         for (int r = 0; r < MPT; ++r) {
             if (r * bs >= NM) break;                      // uniform: larger blocks need fewer rounds
-            const int e = min((int)threadIdx.x + r * bs, NM - 1);
+            const int e = min(ml + r * bs, NM - 1);
             const int cc = e / NPL, k = e % NPL;
             const int c = cell_of(cc % TX, cc / TX, kz);
             mreg[r] = par[(size_t)c * NPAR + (k < NPAR ? k : 0)];
@@ -202,7 +227,7 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
         // flag word of a cell: bit 0 fluid and inside the domain, bit 1 its in-tile
         // z-upwind cell is solid (carried with this slab so that compute never
         // reads the other buffer, which the next slab's data may be overwriting)
-        const int e = min((int)threadIdx.x, NC - 1);
+        const int e = min(ml, NC - 1);
         const int c = cell_of(e % TX, e / TX, kz);
         const int cz = cell_of(e % TX, e / TX, kz > 0 ? kz - 1 : 0);
         const int fl = (MASK ? cflag[c] : 1) && inside(e % TX, e / TX, kz);
@@ -213,20 +238,22 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
 #pragma unroll
         for (int r = 0; r < MPT; ++r) {
             if (r * bs >= NM) break;
-            const int e = threadIdx.x + r * bs;
-            if (e < NM) spar[buf][e] = mreg[r];
+            const int e = ml + r * bs;
+            if (e < NM) spar[w][buf][e] = mreg[r];
         }
-        if ((int)threadIdx.x < NC) sflag[buf][threadIdx.x] = freg;
+        if (ml < NC) sflag[w][buf][ml] = freg;
     };
 
     T pl0[TY][TX], pl1[TY][TX];                 // z-upwind plane, then the slab just computed
     T xin0[TY], xin1[TY], yin0[TX], yin1[TX];   // inflow faces of the current slab
     T xnx0[TY], xnx1[TY], ynx0[TX], ynx1[TX];   // ... and of the next slab
-    auto issue_xy = [&](int kz, T *x0, T *x1, T *y0, T *y1) {
+    bool xwl[TY], ywl[TX], xwn[TY], ywn[TX];    // their wall flags (used for faces handed in LDS)
+    const bool xhand = GRID && wx > 0, yhand = GRID && wy > 0;   // uniform per wave
+    auto issue_xy = [&](int kz, T *x0, T *x1, T *y0, T *y1, bool *xw, bool *yw) {
 #pragma unroll
-        for (int ky = 0; ky < TY; ++ky) inflow(cell_of(0, ky, kz), 0, ky, kz, dxu, x0[ky], x1[ky]);
+        for (int ky = 0; ky < TY; ++ky) inflow(cell_of(0, ky, kz), 0, ky, kz, dxu, x0[ky], x1[ky], xhand, xw[ky]);
 #pragma unroll
-        for (int kx = 0; kx < TX; ++kx) inflow(cell_of(kx, 0, kz), kx, 0, kz, dyu, y0[kx], y1[kx]);
+        for (int kx = 0; kx < TX; ++kx) inflow(cell_of(kx, 0, kz), kx, 0, kz, dyu, y0[kx], y1[kx], yhand, yw[kx]);
     };
 
     issue_meta(0);
@@ -234,24 +261,59 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
 #pragma unroll
     for (int ky = 0; ky < TY; ++ky)
 #pragma unroll
-        for (int kx = 0; kx < TX; ++kx) inflow(cell_of(kx, ky, 0), kx, ky, 0, dzu, pl0[ky][kx], pl1[ky][kx]);
-    issue_xy(0, xin0, xin1, yin0, yin1);
+        for (int kx = 0; kx < TX; ++kx) {
+            bool wz;
+            inflow(cell_of(kx, ky, 0), kx, ky, 0, dzu, pl0[ky][kx], pl1[ky][kx], false, wz);
+        }
+    issue_xy(0, xin0, xin1, yin0, yin1, xwl, ywl);
     __syncthreads();
 
     // per-tile strides of the octant frame: cell = slab base + kx dxs + ky dys
     const int dxs = sx ? -1 : 1, dys = sy ? -nx : nx;
     const unsigned lnode = (unsigned)node;
-    for (int kz = 0; kz < TZ; ++kz) {
-        if (k0 + kz >= nz) break;                 // uniform over the block
+    // slabs of this tile and steps of the block (uniform over the block)
+    const int TZe = max(0, min(TZ, nz - k0));
+    const int nstep = TZe + (WX - 1) + (WY - 1);
+    const int xr = wy * (WX - 1) + wx - 1, xw = wy * (WX - 1) + wx;   // x-face slots read / written
+    const int yr = (wy - 1) * WX + wx, yw = wy * WX + wx;             // y-face slots read / written
+    for (int st = 0; st < nstep; ++st) {
+        const int kz = st - (wx + wy);            // the slab of this wave at this step
+        const bool run = kz >= 0 && kz < TZe;     // uniform over the wave
         const int buf = kz & 1;
-        const bool more = kz + 1 < TZ && k0 + kz + 1 < nz;
+        const bool more = run && kz + 1 < TZe;
         if (more) {
             issue_meta(kz + 1);
-            issue_xy(kz + 1, xnx0, xnx1, ynx0, ynx1);
+            issue_xy(kz + 1, xnx0, xnx1, ynx0, ynx1, xwn, ywn);
         }
         const int kk = k0 + kz;
         const int cbase = (sx ? nx - 1 - i0 : i0) + nx * ((sy ? ny - 1 - j0 : j0) + ny * (sz ? nz - 1 - kk : kk));
-        if (active) {
+        if (GRID && run) {
+            // exit faces of the upwind waves' slab kz, written at the previous step
+            const int pb = (st - 1) & 1;
+            if (xhand) {
+#pragma unroll
+                for (int ky = 0; ky < TY; ++ky) {
+                    const T h0 = xface[0][xr][pb][ky][lane];
+                    xin0[ky] = (MASK && xwl[ky]) ? xin0[ky] : h0;
+                    if (DIA) {
+                        const T h1 = xface[ND - 1][xr][pb][ky][lane];
+                        xin1[ky] = (MASK && xwl[ky]) ? xin1[ky] : h1;
+                    }
+                }
+            }
+            if (yhand) {
+#pragma unroll
+                for (int kx = 0; kx < TX; ++kx) {
+                    const T h0 = yface[0][yr][pb][kx][lane];
+                    yin0[kx] = (MASK && ywl[kx]) ? yin0[kx] : h0;
+                    if (DIA) {
+                        const T h1 = yface[ND - 1][yr][pb][kx][lane];
+                        yin1[kx] = (MASK && ywl[kx]) ? yin1[kx] : h1;
+                    }
+                }
+            }
+        }
+        if (run && active) {
 #pragma unroll
             for (int ky = 0; ky < TY; ++ky) {
 #pragma unroll
@@ -260,14 +322,14 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
                     // Every cell of the slab is computed, so the slab is straight-line
                     // code; a cell outside the domain or solid stores into the sink row
                     // (row ncell) and its value is never used upwind.
-                    const int flag = MASK ? __builtin_amdgcn_readfirstlane(sflag[buf][e]) : 1;
+                    const int flag = MASK ? __builtin_amdgcn_readfirstlane(sflag[w][buf][e]) : 1;
                     const bool live = MASK ? (flag & 1) != 0 : (i0 + kx < nx && j0 + ky < ny);
                     const int cell = cbase + kx * dxs + ky * dys;
                     const int cread = live ? cell : 0;   // in-range index for side reads
                     const int row = live ? cell : ncell;
                     const gptr<T> c0 = f0 + (size_t)row * nv;   // uniform row; the lane adds its node
                     const gptr<T> c1 = DIA ? f1 + (size_t)row * nv : c0;
-                    const T *p = &spar[buf][e * NPL];
+                    const T *p = &spar[w][buf][e * NPL];
                     const T cx = xix - p[0], cy = xiy - p[1], cz = xiz - p[2];
                     T gt0, gt1 = T(0), invtau;
                     if (DIA) {
@@ -284,12 +346,12 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
                     }
                     T F0, F1 = T(0);
                     if (kx == 0) { F0 = xin0[ky]; if (DIA) F1 = xin1[ky]; }
-                    else if (MASK && !(__builtin_amdgcn_readfirstlane(sflag[buf][e - 1]) & 1)) solid_face(cread, dxu, F0, F1);
+                    else if (MASK && !(__builtin_amdgcn_readfirstlane(sflag[w][buf][e - 1]) & 1)) solid_face(cread, dxu, F0, F1);
                     else { F0 = pl0[ky][kx - 1]; if (DIA) F1 = pl1[ky][kx - 1]; }
                     num0 = fma(ax, F0, num0);
                     if (DIA) num1 = fma(ax, F1, num1);
                     if (ky == 0) { F0 = yin0[kx]; if (DIA) F1 = yin1[kx]; }
-                    else if (MASK && !(__builtin_amdgcn_readfirstlane(sflag[buf][e - TX]) & 1)) solid_face(cread, dyu, F0, F1);
+                    else if (MASK && !(__builtin_amdgcn_readfirstlane(sflag[w][buf][e - TX]) & 1)) solid_face(cread, dyu, F0, F1);
                     else { F0 = pl0[ky - 1][kx]; if (DIA) F1 = pl1[ky - 1][kx]; }
                     num0 = fma(ay, F0, num0);
                     if (DIA) num1 = fma(ay, F1, num1);
@@ -309,31 +371,60 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
                 }
             }
         }
+        if (GRID && run) {
+            // this slab's exit faces for the downstream waves (every lane, so the
+            // reads of inactive lanes stay defined)
+            if (WX > 1 && wx < WX - 1) {
+#pragma unroll
+                for (int ky = 0; ky < TY; ++ky) {
+                    xface[0][xw][st & 1][ky][lane] = pl0[ky][TX - 1];
+                    if (DIA) xface[ND - 1][xw][st & 1][ky][lane] = pl1[ky][TX - 1];
+                }
+            }
+            if (WY > 1 && wy < WY - 1) {
+#pragma unroll
+                for (int kx = 0; kx < TX; ++kx) {
+                    yface[0][yw][st & 1][kx][lane] = pl0[TY - 1][kx];
+                    if (DIA) yface[ND - 1][yw][st & 1][kx][lane] = pl1[TY - 1][kx];
+                }
+            }
+        }
         if (more) store_meta(buf ^ 1);
         __syncthreads();
         if (more) {
 #pragma unroll
-            for (int ky = 0; ky < TY; ++ky) { xin0[ky] = xnx0[ky]; if (DIA) xin1[ky] = xnx1[ky]; }
+            for (int ky = 0; ky < TY; ++ky) { xin0[ky] = xnx0[ky]; if (DIA) xin1[ky] = xnx1[ky]; xwl[ky] = xwn[ky]; }
 #pragma unroll
-            for (int kx = 0; kx < TX; ++kx) { yin0[kx] = ynx0[kx]; if (DIA) yin1[kx] = ynx1[kx]; }
+            for (int kx = 0; kx < TX; ++kx) { yin0[kx] = ynx0[kx]; if (DIA) yin1[kx] = ynx1[kx]; ywl[kx] = ywn[kx]; }
         }
     }
 }
 
 // ------------------------------------------------------------------ launches
-struct Shape { int tx, ty; };
-// compiled (tx, ty) per precision; tz is a run-time loop length.  The slab is
-// held in registers, so the diatomic gas (two planes) uses the small shapes.
-static const Shape kShapes32[] = {{4, 4}, {8, 4}, {8, 8}};
-static const Shape kShapes64[] = {{4, 4}, {8, 4}};
+// A tile shape (tx, ty) is served by slabs of (tx / wx) x (ty / wy) cells held
+// by a wx x wy wave grid (one wave: wx = wy = 1).  tz is a run-time loop
+// length.  The slab is held in registers, so the diatomic gas (two planes)
+// uses slabs of at most 32 cells.
+struct Shape { int tx, ty, wx, wy; };
+static const Shape kShapes32[] = {{4, 4, 1, 1}, {8, 4, 1, 1}, {8, 8, 1, 1}, {16, 8, 2, 2}};
+static const Shape kShapes64[] = {{4, 4, 1, 1}, {8, 4, 1, 1}, {8, 8, 2, 2}};
 
-template <typename T, int TX, int TY>
+static const Shape *find_shape(bool fp32, int tx, int ty)
+{
+    const Shape *sh = fp32 ? kShapes32 : kShapes64;
+    const int cnt = fp32 ? (int)(sizeof(kShapes32) / sizeof(Shape)) : (int)(sizeof(kShapes64) / sizeof(Shape));
+    for (int k = 0; k < cnt; ++k)
+        if (sh[k].tx == tx && sh[k].ty == ty) return &sh[k];
+    return nullptr;
+}
+
+template <typename T, int TX, int TY, int WX, int WY>
 static void sweep_plane(const Target &t, int p, hipStream_t s)
 {
     constexpr bool kDia = TX * TY <= 32;   // two register planes only for the small slabs
     const dim3 grid((unsigned)t.npblk[p]);
     const Span sp{t.cases, t.pmap ? t.pmap[p] : nullptr};
-#define GSIS_SWEEP(D, R, M) hipLaunchKernelGGL((k_sweep<T, TX, TY, D, R, M>), grid, dim3(t.bs), 0, s, GSIS_SPAN(sp), p)
+#define GSIS_SWEEP(D, R, M) hipLaunchKernelGGL((k_sweep<T, TX, TY, WX, WY, D, R, M>), grid, dim3(t.bs), 0, s, GSIS_SPAN(sp), p)
     if (t.dia) {
         if constexpr (kDia) {
             if (t.rfn) { if (t.mask) GSIS_SWEEP(true, true, true); else GSIS_SWEEP(true, true, false); }
@@ -348,13 +439,15 @@ static void sweep_plane(const Target &t, int p, hipStream_t s)
 
 bool sweep_shape_supported(bool fp32, bool dia, int tx, int ty)
 {
-    if (dia && tx * ty > 32) return false;
-    if (fp32) {
-        for (const Shape &s : kShapes32) if (s.tx == tx && s.ty == ty) return true;
-    } else {
-        for (const Shape &s : kShapes64) if (s.tx == tx && s.ty == ty) return true;
-    }
-    return false;
+    const Shape *sh = find_shape(fp32, tx, ty);
+    if (!sh) return false;
+    return !(dia && (tx / sh->wx) * (ty / sh->wy) > 32);
+}
+
+int sweep_shape_waves(bool fp32, int tx, int ty)
+{
+    const Shape *sh = find_shape(fp32, tx, ty);
+    return sh ? sh->wx * sh->wy : 0;
 }
 
 int sweep_shapes(bool fp32, int *out, int max)
@@ -374,15 +467,19 @@ hipError_t launch_sweep(const Target &t, hipStream_t s)
 {
     const int tx = t.tx, ty = t.ty;
     if (!sweep_shape_supported(t.fp32, t.dia, tx, ty)) return hipErrorInvalidValue;
+    const int nw = sweep_shape_waves(t.fp32, tx, ty);
+    if (nw > 1 && t.bs != 64 * nw) return hipErrorInvalidValue;
     for (int p = 0; p < t.nplane; ++p) {
         if (t.npblk[p] == 0) continue;
         if (t.fp32) {
-            if (tx == 4 && ty == 4) sweep_plane<float, 4, 4>(t, p, s);
-            else if (tx == 8 && ty == 4) sweep_plane<float, 8, 4>(t, p, s);
-            else sweep_plane<float, 8, 8>(t, p, s);
+            if (tx == 4 && ty == 4) sweep_plane<float, 4, 4, 1, 1>(t, p, s);
+            else if (tx == 8 && ty == 4) sweep_plane<float, 8, 4, 1, 1>(t, p, s);
+            else if (tx == 8 && ty == 8) sweep_plane<float, 8, 8, 1, 1>(t, p, s);
+            else sweep_plane<float, 8, 4, 2, 2>(t, p, s);
         } else {
-            if (tx == 4 && ty == 4) sweep_plane<double, 4, 4>(t, p, s);
-            else sweep_plane<double, 8, 4>(t, p, s);
+            if (tx == 4 && ty == 4) sweep_plane<double, 4, 4, 1, 1>(t, p, s);
+            else if (tx == 8 && ty == 4) sweep_plane<double, 8, 4, 1, 1>(t, p, s);
+            else sweep_plane<double, 4, 4, 2, 2>(t, p, s);
         }
     }
     return hipGetLastError();

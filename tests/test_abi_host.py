@@ -123,7 +123,11 @@ def test_tile_shapes_and_set_tile_validation():
     assert L.gsis_set_tile(ctx.h, 8, 8, 0, 128) == -1
     assert L.gsis_set_tile(ctx.h, 8, 8, 4, 100) == -1     # block must be 64, 128 or 256
     assert L.gsis_set_tile(ctx.h, 8, 8, 4, 32) == -1
-    assert L.gsis_set_tile(ctx.h, 16, 8, 4, 128) == -1    # not compiled
+    assert L.gsis_set_tile(ctx.h, 16, 16, 4, 256) == -1   # not compiled
+    # 16 x 8 is a 2 x 2 grid of 8 x 4 waves: the block is exactly its four waves
+    assert (16, 8, 32) in shapes and (8, 8, 64) in shapes
+    assert L.gsis_set_tile(ctx.h, 16, 8, 4, 128) == -1
+    assert L.gsis_set_tile(ctx.h, 16, 8, 4, 256) == 0
     assert L.gsis_set_tile(ctx.h, 8, 4, 16, 256) == 0
     tile = (C.c_int * 4)()
     assert L.gsis_get_tile(ctx.h, tile) == 0 and tuple(tile) == (8, 4, 16, 256)
@@ -131,8 +135,10 @@ def test_tile_shapes_and_set_tile_validation():
     dia = G.Context(I.small_block(species=I.DIATOMIC), "fp32")
     assert dia.L.gsis_set_tile(dia.h, 8, 8, 8, 128) == -1
     assert dia.L.gsis_set_tile(dia.h, 8, 4, 8, 128) == 0
+    assert dia.L.gsis_set_tile(dia.h, 16, 8, 8, 256) == 0    # wave grid of 8 x 4 slabs
     f64 = G.Context(I.cavity(6, 8, 0.1), "fp64")
-    assert f64.L.gsis_set_tile(f64.h, 8, 8, 8, 128) == -1
+    assert f64.L.gsis_set_tile(f64.h, 8, 8, 8, 128) == -1    # 2 x 2 waves of 4 x 4: block 256 only
+    assert f64.L.gsis_set_tile(f64.h, 8, 8, 8, 256) == 0
     assert f64.L.gsis_set_tile(f64.h, 8, 4, 8, 128) == 0
 
 

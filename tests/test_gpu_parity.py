@@ -222,8 +222,10 @@ def test_tile_shapes_bitwise_identical():
     say("[determinism]")
     case = I.cavity(13, 10, 0.1, lid=0.25)
     results = {}
-    for dtype, shapes in (("fp32", [(8, 8, 8, 128), (4, 4, 4, 256), (8, 4, 3, 128), (8, 8, 13, 256), (4, 4, 6, 64)]),
-                          ("fp64", [(4, 4, 4, 128), (8, 4, 2, 256), (8, 4, 5, 128), (4, 4, 13, 256), (4, 4, 16, 64)])):
+    for dtype, shapes in (("fp32", [(8, 8, 8, 128), (4, 4, 4, 256), (8, 4, 3, 128), (8, 8, 13, 256), (4, 4, 6, 64),
+                                    (16, 8, 5, 256), (16, 8, 13, 256)]),
+                          ("fp64", [(4, 4, 4, 128), (8, 4, 2, 256), (8, 4, 5, 128), (4, 4, 13, 256), (4, 4, 16, 64),
+                                    (8, 8, 3, 256), (8, 8, 16, 256)])):
         for sh in shapes:
             s = Solver(case, dtype, tile=sh)
             s.init_maxwellian()
@@ -234,6 +236,32 @@ def test_tile_shapes_bitwise_identical():
         ref = lst[0][1]
         for sh, f in lst[1:]:
             assert np.array_equal(f, ref), (dtype, sh)
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", ["mono_block", "diatomic_block", "finite_dt"])
+def test_wave_grid_tiles_match_single_wave(dtype, kind):
+    """A wave-grid tile hands slab faces between its waves through LDS; its VDF
+    must be bitwise the single-wave result, with solid cells inside and across
+    the sub-tiles (mono, diatomic: both VDFs) and with the f^n term of a finite
+    pseudo time step."""
+    say(f"[wave grid] {dtype} {kind}")
+    if kind == "finite_dt":
+        case = I.cavity(11, 8, 0.1, lid=0.2, inv_dt=3.0)
+    else:
+        case = I.small_block(species=I.DIATOMIC if kind == "diatomic_block" else I.MONATOMIC)
+    grid = {"fp64": [(8, 8, 3, 256), (8, 8, 8, 256)], "fp32": [(16, 8, 3, 256), (16, 8, 8, 256)]}[dtype]
+    out = []
+    for sh in [(4, 4, 4, 128)] + grid:
+        s = Solver(case, dtype, tile=sh)
+        s.init_maxwellian()
+        s.kinetic_step(2)
+        f0, f1 = s.get_vdf()
+        out.append((sh, f0.cpu().numpy(), None if f1 is None else f1.cpu().numpy()))
+    for sh, f0, f1 in out[1:]:
+        assert np.array_equal(f0, out[0][1]), (dtype, kind, sh)
+        if f1 is not None:
+            assert np.array_equal(f1, out[0][2]), (dtype, kind, sh)
 
 
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
