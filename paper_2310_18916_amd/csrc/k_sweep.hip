@@ -61,11 +61,11 @@ template <> struct Arith<double> {
 
 // g / tau at node (cx, cy, cz) = xi - u of a monatomic cell
 template <typename T>
-__device__ __forceinline__ T ref_mono(const T *p, T cx, T cy, T cz)
+__device__ __forceinline__ T ref_mono(const T *p, T cx, T cy, T cz, T it)
 {
 #pragma clang fp contract(off)
     const T c2 = fma(cz, cz, fma(cy, cy, cx * cx));
-    const T t = c2 * p[3];
+    const T t = c2 * it;
     const T E = p[4] * Arith<T>::ex(-t);
     const T q = fma(p[12], cz, fma(p[11], cy, p[10] * cx));
     const T poly = fma(q, t - T(2.5), fma(p[9], c2, fma(p[8], cz, fma(p[7], cy, fma(p[6], cx, p[5])))));
@@ -74,11 +74,11 @@ __device__ __forceinline__ T ref_mono(const T *p, T cx, T cy, T cz)
 
 // g0 / tau, g1 / tau of a diatomic cell (Rykov mixture of the four components)
 template <typename T>
-__device__ __forceinline__ void ref_dia(const T *p, T cx, T cy, T cz, T &g0, T &g1)
+__device__ __forceinline__ void ref_dia(const T *p, T cx, T cy, T cz, T itt, T itr, T &g0, T &g1)
 {
 #pragma clang fp contract(off)
     const T c2 = fma(cz, cz, fma(cy, cy, cx * cx));
-    const T tt = c2 * p[3], tr = c2 * p[4];
+    const T tt = c2 * itt, tr = c2 * itr;
     const T Et = p[5] * Arith<T>::ex(-tt);
     const T Er = p[6] * Arith<T>::ex(-tr);
     const T sht = fma(p[14], cz, fma(p[13], cy, p[12] * cx)) * (tt - T(2.5));
@@ -314,11 +314,29 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
             }
         }
         if (run && active) {
+            // the parameters that start a cell's exponential (u and the inverse
+            // temperatures) are read from LDS one cell ahead
+            constexpr int NPRE = DIA ? 5 : 4;
+            T pre[NPRE];
+#pragma unroll
+            for (int k = 0; k < NPRE; ++k) pre[k] = spar[w][buf][k];
 #pragma unroll
             for (int ky = 0; ky < TY; ++ky) {
 #pragma unroll
                 for (int kx = 0; kx < TX; ++kx) {
                     const int e = ky * TX + kx;
+                    T cur[NPRE];
+#pragma unroll
+                    for (int k = 0; k < NPRE; ++k) cur[k] = pre[k];
+                    if (e + 1 < NC) {
+#pragma unroll
+                        for (int k = 0; k < NPRE; ++k) pre[k] = spar[w][buf][(e + 1) * NPL + k];
+                    }
+                    // the rest of this cell's parameters, issued before the exponential
+                    T rest[NPL];
+#pragma unroll
+                    for (int k = NPRE; k < (DIA ? 34 : 14); ++k) rest[k] = spar[w][buf][e * NPL + k];
+                    __builtin_amdgcn_sched_barrier(0);
                     // Every cell of the slab is computed, so the slab is straight-line
                     // code; a cell outside the domain or solid stores into the sink row
                     // (row ncell) and its value is never used upwind.
@@ -329,14 +347,14 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
                     const int row = live ? cell : ncell;
                     const gptr<T> c0 = f0 + (size_t)row * nv;   // uniform row; the lane adds its node
                     const gptr<T> c1 = DIA ? f1 + (size_t)row * nv : c0;
-                    const T *p = &spar[w][buf][e * NPL];
-                    const T cx = xix - p[0], cy = xiy - p[1], cz = xiz - p[2];
+                    const T *p = rest;
+                    const T cx = xix - cur[0], cy = xiy - cur[1], cz = xiz - cur[2];
                     T gt0, gt1 = T(0), invtau;
                     if (DIA) {
-                        ref_dia<T>(p, cx, cy, cz, gt0, gt1);
+                        ref_dia<T>(p, cx, cy, cz, cur[3], cur[NPRE - 1], gt0, gt1);
                         invtau = p[33];
                     } else {
-                        gt0 = ref_mono<T>(p, cx, cy, cz);
+                        gt0 = ref_mono<T>(p, cx, cy, cz, cur[3]);
                         invtau = p[13];
                     }
                     T num0 = gt0, num1 = gt1;
