@@ -50,9 +50,15 @@ template <> struct VecLoad<double, 2> {
     }
 };
 
+// y and z (weight, node) tables staged in LDS when an axis has at most TABMAX
+// nodes: the fold reads them once per row, which as global loads would
+// outnumber the VDF loads
+constexpr int TABMAX = 256;
+
 template <typename T, int VW, bool DIA>
 __global__ __launch_bounds__(512) void k_moments(GSIS_SPAN_ARGS)
 {
+    __shared__ double sty[2 * TABMAX], stz[2 * TABMAX];
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
     const Geo &g = C.g;
@@ -71,6 +77,12 @@ __global__ __launch_bounds__(512) void k_moments(GSIS_SPAN_ARGS)
         if (lane < NRS) out[lane] = 0.0;
         return;
     }
+    const bool staged = g.n1[1] <= TABMAX && g.n1[2] <= TABMAX;   // uniform over the block
+    if (staged) {
+        for (int i = threadIdx.x; i < 2 * g.n1[1]; i += blockDim.x) sty[i] = ytab[i];
+        for (int i = threadIdx.x; i < 2 * g.n1[2]; i += blockDim.x) stz[i] = ztab[i];
+    }
+    __syncthreads();
     const int nox = g.on[o][0], noy = g.on[o][1], noz = g.on[o][2];
     const int x0 = (o & 1) ? 0 : g.k0[0];
     const int y0 = (o & 2) ? 0 : g.k0[1];
@@ -86,8 +98,14 @@ __global__ __launch_bounds__(512) void k_moments(GSIS_SPAN_ARGS)
     // fold the x-sums s_p = sum_x w_x x^p f of row r with its y/z weights
     auto fold = [&](int r, double s0, double s1, double s2, double s3, double t0, double t1) {
         const int lz = (int)(((float)r + 0.5f) * rcp_noy), ly = r - lz * noy;
-        const double wy = ytab[2 * (y0 + ly)], y = ytab[2 * (y0 + ly) + 1];
-        const double wz = ztab[2 * (z0 + lz)], z = ztab[2 * (z0 + lz) + 1];
+        double wy, y, wz, z;
+        if (staged) {
+            wy = sty[2 * (y0 + ly)]; y = sty[2 * (y0 + ly) + 1];
+            wz = stz[2 * (z0 + lz)]; z = stz[2 * (z0 + lz) + 1];
+        } else {
+            wy = ytab[2 * (y0 + ly)]; y = ytab[2 * (y0 + ly) + 1];
+            wz = ztab[2 * (z0 + lz)]; z = ztab[2 * (z0 + lz) + 1];
+        }
         const double W0 = wy * wz;
         const double Y1 = W0 * y, Z1 = W0 * z;
         const double Y2 = Y1 * y, Z2 = Z1 * z, YZ = Y1 * z;

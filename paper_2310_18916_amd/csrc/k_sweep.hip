@@ -314,29 +314,35 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
             }
         }
         if (run && active) {
-            // the parameters that start a cell's exponential (u and the inverse
-            // temperatures) are read from LDS one cell ahead
-            constexpr int NPRE = DIA ? 5 : 4;
+            // Monatomic gas without solid cells: the parameters that start a
+            // cell's exponential (u and 1/T) are read from LDS one cell ahead and
+            // the rest before the exponential, held there by a scheduling
+            // barrier (measured: slower with the per-cell branches of solid
+            // cells and with the diatomic gas's larger register planes).
+            constexpr bool PRE = !MASK && !DIA;
+            constexpr int NPRE = 4;
             T pre[NPRE];
+            if (PRE) {
 #pragma unroll
-            for (int k = 0; k < NPRE; ++k) pre[k] = spar[w][buf][k];
+                for (int k = 0; k < NPRE; ++k) pre[k] = spar[w][buf][k];
+            }
 #pragma unroll
             for (int ky = 0; ky < TY; ++ky) {
 #pragma unroll
                 for (int kx = 0; kx < TX; ++kx) {
                     const int e = ky * TX + kx;
-                    T cur[NPRE];
+                    T cur[NPRE], rest[NPL];
+                    if constexpr (PRE) {
 #pragma unroll
-                    for (int k = 0; k < NPRE; ++k) cur[k] = pre[k];
-                    if (e + 1 < NC) {
+                        for (int k = 0; k < NPRE; ++k) cur[k] = pre[k];
+                        if (e + 1 < NC) {
 #pragma unroll
-                        for (int k = 0; k < NPRE; ++k) pre[k] = spar[w][buf][(e + 1) * NPL + k];
+                            for (int k = 0; k < NPRE; ++k) pre[k] = spar[w][buf][(e + 1) * NPL + k];
+                        }
+#pragma unroll
+                        for (int k = NPRE; k < 14; ++k) rest[k] = spar[w][buf][e * NPL + k];
+                        __builtin_amdgcn_sched_barrier(0);
                     }
-                    // the rest of this cell's parameters, issued before the exponential
-                    T rest[NPL];
-#pragma unroll
-                    for (int k = NPRE; k < (DIA ? 34 : 14); ++k) rest[k] = spar[w][buf][e * NPL + k];
-                    __builtin_amdgcn_sched_barrier(0);
                     // Every cell of the slab is computed, so the slab is straight-line
                     // code; a cell outside the domain or solid stores into the sink row
                     // (row ncell) and its value is never used upwind.
@@ -347,14 +353,14 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
                     const int row = live ? cell : ncell;
                     const gptr<T> c0 = f0 + (size_t)row * nv;   // uniform row; the lane adds its node
                     const gptr<T> c1 = DIA ? f1 + (size_t)row * nv : c0;
-                    const T *p = rest;
-                    const T cx = xix - cur[0], cy = xiy - cur[1], cz = xiz - cur[2];
+                    const T *p = PRE ? rest : &spar[w][buf][e * NPL];
+                    const T cx = xix - (PRE ? cur[0] : p[0]), cy = xiy - (PRE ? cur[1] : p[1]), cz = xiz - (PRE ? cur[2] : p[2]);
                     T gt0, gt1 = T(0), invtau;
                     if (DIA) {
-                        ref_dia<T>(p, cx, cy, cz, cur[3], cur[NPRE - 1], gt0, gt1);
+                        ref_dia<T>(p, cx, cy, cz, p[3], p[4], gt0, gt1);
                         invtau = p[33];
                     } else {
-                        gt0 = ref_mono<T>(p, cx, cy, cz, cur[3]);
+                        gt0 = ref_mono<T>(p, cx, cy, cz, PRE ? cur[3] : p[3]);
                         invtau = p[13];
                     }
                     T num0 = gt0, num1 = gt1;
