@@ -43,7 +43,8 @@ def parse():
 
 def sweep_traffic(dtype, tile, workload_name):
     """HBM bytes per sweep pass from the committed rocprofv3 counter summary, or
-    None when that summary was taken on other kernel sources or another tile."""
+    None when that summary was taken on other kernel sources or has no entry
+    for this tile."""
     import hashlib
     tag = {"c2": "c2"}.get(workload_name)
     if tag is None:
@@ -59,9 +60,10 @@ def sweep_traffic(dtype, tile, workload_name):
     h = hashlib.sha256()
     for f in ("paper_2310_18916_amd/csrc/k_sweep.hip", "paper_2310_18916_amd/csrc/gsis_common.h"):
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    if kv.get("source_sha256") != h.hexdigest() or kv.get("tile") != ",".join(map(str, tile)):
+    key = "tile " + ",".join(map(str, tile))
+    if kv.get("source_sha256") != h.hexdigest() or f"{key} fetch_bytes_per_pass" not in kv:
         return None
-    return float(kv["sweep_fetch_bytes_per_pass"]) + float(kv["sweep_write_bytes_per_pass"])
+    return float(kv[f"{key} fetch_bytes_per_pass"]) + float(kv[f"{key} write_bytes_per_pass"])
 
 
 def workload(name):
