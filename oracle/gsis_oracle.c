@@ -269,13 +269,16 @@ static void phi5(const double xi[3], double phi[5])
     phi[4] = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
 }
 
-/* Dense solve with partial pivoting; n <= 5. */
+/* Dense solve with partial pivoting; n <= 5.  A pivot below 1e-12 of the
+ * largest entry of A counts as zero: the system is singular (returns -1). */
 static int solve_dense(int n, double *A, double *b)
 {
+    double amax = 0.0;
+    for (int i = 0; i < n * n; ++i) amax = fmax(amax, fabs(A[i]));
     for (int k = 0; k < n; ++k) {
         int piv = k;
         for (int i = k + 1; i < n; ++i) if (fabs(A[i * n + k]) > fabs(A[piv * n + k])) piv = i;
-        if (A[piv * n + k] == 0.0) return -1;
+        if (!(fabs(A[piv * n + k]) > 1e-12 * amax)) return -1;
         if (piv != k) {
             for (int j = 0; j < n; ++j) { double t = A[k * n + j]; A[k * n + j] = A[piv * n + j]; A[piv * n + j] = t; }
             double t = b[k]; b[k] = b[piv]; b[piv] = t;
@@ -339,7 +342,10 @@ static void cell_params(const orc_state *s, int cell, cellpar *p)
             b[i] = target[i] - nval(&bs[i]);
             for (int j = 0; j < 5; ++j) G[i * 5 + j] = nval(&Gs[i * 5 + j]);
         }
-        solve_dense(5, G, b);
+        /* A grid on which (1, xi, |xi|^2) are linearly dependent (e.g. two
+         * nodes +-a on every axis: |xi|^2 is constant) cannot match mass and
+         * energy separately: the correction is then not applied. */
+        if (solve_dense(5, G, b) != 0) memset(b, 0, sizeof b);
         memcpy(X == 0 ? p->lam_t : p->lam_r, b, sizeof b);
     }
     if (c->species == 1) {

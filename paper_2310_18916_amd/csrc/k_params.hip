@@ -77,13 +77,19 @@ __device__ void gram_and_shakhov(const Sep &S, const double qp[3], double kT, do
     }
 }
 
+// Dense 5x5 solve with partial pivoting; a pivot below 1e-12 of the largest
+// entry counts as zero (singular: false).  On a velocity grid where 1, xi and
+// |xi|^2 are linearly dependent (two nodes +-a per axis) the conservative
+// correction is singular and is then not applied.
 __device__ bool solve5(double *A, double *b)
 {
+    double amax = 0.0;
+    for (int i = 0; i < 25; ++i) amax = fmax(amax, fabs(A[i]));
     for (int k = 0; k < 5; ++k) {
         int piv = k;
         for (int i = k + 1; i < 5; ++i)
             if (fabs(A[i * 5 + k]) > fabs(A[piv * 5 + k])) piv = i;
-        if (A[piv * 5 + k] == 0.0) return false;
+        if (!(fabs(A[piv * 5 + k]) > 1e-12 * amax)) return false;
         if (piv != k) {
             for (int j = 0; j < 5; ++j) { double t = A[k * 5 + j]; A[k * 5 + j] = A[piv * 5 + j]; A[piv * 5 + j] = t; }
             double t = b[k]; b[k] = b[piv]; b[piv] = t;

@@ -138,6 +138,36 @@ def test_collision_conserves_exactly(species):
     assert abs((w * (g0 - f0[0])).sum()) > 1e-9
 
 
+def test_correction_skipped_where_the_grid_cannot_separate_mass_and_energy():
+    """With two nodes on every axis, xi_a^2 is affine in xi_a on the grid, so
+    |xi|^2 lies in the span of 1 and xi and no correction can match mass,
+    momentum and energy separately: the reference distribution is then
+    exactly the uncorrected one.  A third node on one axis makes them
+    independent: the correction applies and conserves as on any other grid."""
+    for nv, singular in (((2, 2, 2), True), ((3, 2, 2), False)):
+        case = I.cavity(2, 2, 0.1, vmax=2.0)
+        case.nv = nv
+        f0, f1 = I.random_vdf(case, seed=8)
+        ref = {}
+        for cons in (1, 0):
+            case.conservative = cons
+            o = O.Oracle(case)
+            o.set_vdf(f0, f1)
+            ref[cons] = o.ref_dist(0)[0]
+        assert np.all(np.isfinite(ref[1]))
+        if singular:
+            assert np.array_equal(ref[1], ref[0])
+        else:
+            assert not np.array_equal(ref[1], ref[0])
+            xi, w = O.node_grid(case)
+            d0 = ref[1] - f0[0]
+            scale = (w * f0[0] * (1 + (xi * xi).sum(1))).sum()
+            assert abs((w * d0).sum()) < 1e-13 * scale
+            for a in range(3):
+                assert abs((w * xi[:, a] * d0).sum()) < 1e-13 * scale
+            assert abs((w * (xi * xi).sum(1) * d0).sum()) < 1e-13 * scale
+
+
 # ------------------------------------------------------------ fixed point
 def test_uniform_maxwellian_is_a_fixed_point():
     """Rest cavity with f = M(1,0,1): a pass and a GSIS correction leave f unchanged."""
