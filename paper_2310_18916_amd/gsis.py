@@ -304,9 +304,23 @@ class Batch:
         self._check(self.L.gsis_batch_autotune(self.h, reps, cfg, ms, 128, C.byref(n)), "gsis_batch_autotune")
         return [((cfg[4 * k], cfg[4 * k + 1], cfg[4 * k + 2], cfg[4 * k + 3]), ms[k]) for k in range(n.value)]
 
-    def init_maxwellian(self, rho=1.0, u=(0.0, 0.0, 0.0), T=1.0, Tr=1.0):
+    def init_maxwellian(self, rho=None, u=None, T=None, Tr=None):
+        """With no arguments every case starts from the Maxwellian of its own
+        initial state (Case.init); with arguments every case from that one
+        state (missing ones: rho = 1, u = 0, T = Tr = 1)."""
+        own = rho is None and u is None and T is None and Tr is None
+        rho = 1.0 if rho is None else rho
+        u = (0.0, 0.0, 0.0) if u is None else u
+        T = 1.0 if T is None else T
+        Tr = 1.0 if Tr is None else Tr
         self._check(self.L.gsis_batch_init_maxwellian(self.h, rho, (C.c_double * 3)(*u), T, Tr),
                     "gsis_batch_init_maxwellian")
+        if own:
+            for m in self.members:
+                r0, u0, T0, Tr0 = m.case.init
+                if (r0, tuple(u0), T0, Tr0) != (rho, tuple(u), T, Tr):
+                    m.init_maxwellian()     # the case's context, on the batch's stream
+            self.synchronize()
 
     def run(self, iters: int, inner_iters: int, graph: bool = True):
         self._check(self.L.gsis_batch_run(self.h, iters, inner_iters, int(graph)), "gsis_batch_run")

@@ -91,3 +91,23 @@ def test_degenerate_gsis(name):
          "u": np.abs(mg[:, 1:4] - mo[:, 1:4]).max() / max(np.abs(mo[:, 1:4]).max(), 1e-300)}
     say(f"  errors {e}")
     assert max(e.values()) <= 1e-12
+
+
+def test_degenerate_shapes_in_one_batch():
+    """The degenerate shapes batched together (masked and unmasked, one cell to
+    a thousand) are each bitwise the case run alone."""
+    say("[degenerate batch]")
+    from paper_2310_18916_amd.gsis import Batch
+    cases = list(CASES.values())
+    b = Batch(cases, "fp64")
+    tile = b.get_tile()
+    b.init_maxwellian()
+    b.run(2, 15, graph=True)
+    for i, case in enumerate(cases):
+        s = Solver(case, "fp64", tile=tile)
+        s.init_maxwellian()
+        for _ in range(2):
+            s.kinetic_step(1)
+            s.gsis_correct(15)
+        assert np.array_equal(b[i].moments(), s.moments(), equal_nan=True), i   # solid cells hold NaN
+    b.close()
