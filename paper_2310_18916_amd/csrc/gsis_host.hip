@@ -44,7 +44,7 @@ struct gsis_ctx {
     long long prof_calls[GSIS_NPHASE] = {0};
     ~gsis_ctx()
     {
-        for (auto &e : ev_open) { hipEventDestroy(e.second.first); hipEventDestroy(e.second.second); }
+        for (auto &e : ev_open) { (void)hipEventDestroy(e.second.first); (void)hipEventDestroy(e.second.second); }
         for (auto e : ev_pool) hipEventDestroy(e);
     }
 };
@@ -1015,8 +1015,8 @@ struct gsis_batch {
     std::string err;
     void drop_graph()
     {
-        if (exec) hipGraphExecDestroy(exec);
-        if (graph) hipGraphDestroy(graph);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
         graph_inner = -1;
@@ -1024,8 +1024,8 @@ struct gsis_batch {
     ~gsis_batch()
     {
         drop_graph();
-        if (ev0) hipEventDestroy(ev0);
-        if (ev1) hipEventDestroy(ev1);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
     }
 };
 
@@ -1364,8 +1364,8 @@ gsis_status gsis_batch_autotune(gsis_batch *b, int reps, int *cfg_out, double *m
         if (e != hipSuccess) { st = bfail(b, GSIS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e)); break; }
         c.ms = ms / reps;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st) {
         batch_apply_tile(b, save[0], save[1], save[2], save[3]);
         return st;
@@ -1413,7 +1413,7 @@ gsis_status gsis_batch_run(gsis_batch *b, int iters, int inner_iters, int use_gr
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(b->stream, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return bfail(b, GSIS_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
         }
         b->graph = g;
