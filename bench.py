@@ -238,6 +238,35 @@ def copy_calibration(mib):
     return {"bytes_read": n * 8, "bytes_written": n * 8, "copies": 3}
 
 
+def hbm_rates(gib=4):
+    """Achievable HBM rates of plain streaming on this GPU (torch's own kernels on
+    gib-GiB FP64 buffers, best of three): read (sum), write (fill), copy."""
+    import torch
+    n = gib * (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def best(fn):
+        ms = []
+        for _ in range(3):
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return min(ms) * 1e-3
+
+    nbytes = n * 8
+    out = {"read_gbs": nbytes / best(lambda: a.sum()) / 1e9,
+           "write_gbs": nbytes / best(lambda: b.fill_(2.0)) / 1e9,
+           "copy_gbs": 2 * nbytes / best(lambda: b.copy_(a)) / 1e9,
+           "buffer_gib": gib, "how": "torch sum / fill_ / copy_, best of 3, device events"}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -296,6 +325,12 @@ def main():
         "autotune_top": [[list(c), round(ms, 4)] for c, ms in (r["tune"] or [])[:6]],
     }
     del r
+    rates = hbm_rates()
+    # the sweep's algorithmic bytes are writes, the moments' reads
+    ceiling = rates["write_gbs"] if dominant == "sweep" else rates["read_gbs"]
+    out["roofline"]["measured_ceiling"] = ceiling
+    out["roofline"]["frac_of_measured"] = ach / ceiling
+    out["hbm_measured"] = rates
     if not a.no_fp32:
         other = "fp32" if dtype == "fp64" else "fp64"
         ro = run_gpu(case, other, steps, a.warmup, macro, None)
