@@ -98,6 +98,16 @@ gsis_status gsis_destroy(gsis_ctx *ctx);
  * gsis_workspace_size.  Solid cells carry no VDF update and report NaN. */
 gsis_status gsis_set_solid_mask(gsis_ctx *ctx, const uint8_t *mask, size_t n);
 
+/* Non-uniform Cartesian velocity grid (Sec. 3.1 allows non-uniform Cartesian
+ * grids; a tensor-product step towards its locally refined velocity meshes):
+ * axis (0, 1, 2) gets the n host nodes given (n = the
+ * configured nvx, nvy or nvz; finite, strictly increasing; copied) instead of
+ * the uniform nodes on [vmin, vmax], with trapezoid weights (half of each
+ * neighbouring gap).  The grid stays a tensor product, so every separable sum
+ * keeps working.  Must precede gsis_workspace_size; EINVAL on a bad axis,
+ * count or node array, ESTATE once the workspace is sized. */
+gsis_status gsis_set_velocity_nodes(gsis_ctx *ctx, int axis, const double *nodes, int n);
+
 /* Boundary condition of slot face (GSIS_FACE_*): kind GSIS_DIFFUSE_WALL with
  * wall velocity u and temperature T (rho ignored; the wall density is set so
  * the discrete mass flux is zero), or GSIS_MAXWELL_INFLOW with the Maxwellian

@@ -61,6 +61,9 @@ typedef struct {
     double bc_u[ORC_NBC][3];
     double bc_T[ORC_NBC];
     double bc_rho[ORC_NBC];
+    /* optional per-axis node positions (strictly increasing, nv[a] of them);
+     * NULL: nv[a] uniform nodes on [vmin, vmax].  Read once, at creation. */
+    const double *nodes[3];
 } orc_cfg;
 
 typedef struct {
@@ -115,8 +118,15 @@ void orc_free(orc_state *s)
 static orc_state *create_state(const orc_cfg *cfg, const unsigned char *solid, int with_vdf)
 {
     if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return NULL;
-    for (int a = 0; a < 3; ++a)
-        if (cfg->nv[a] < 2 || !(cfg->vmax[a] > cfg->vmin[a])) return NULL;
+    for (int a = 0; a < 3; ++a) {
+        if (cfg->nv[a] < 2) return NULL;
+        if (cfg->nodes[a]) {
+            for (int k = 0; k < cfg->nv[a]; ++k)
+                if (!isfinite(cfg->nodes[a][k]) || (k > 0 && !(cfg->nodes[a][k] > cfg->nodes[a][k - 1]))) return NULL;
+        } else if (!(cfg->vmax[a] > cfg->vmin[a])) {
+            return NULL;
+        }
+    }
     orc_state *s = calloc(1, sizeof(*s));
     s->c = *cfg;
     s->ncell = cfg->nx * cfg->ny * cfg->nz;
@@ -132,10 +142,20 @@ static orc_state *create_state(const orc_cfg *cfg, const unsigned char *solid, i
         double d = (cfg->vmax[a] - cfg->vmin[a]) / (n - 1);
         s->xi[a] = malloc(sizeof(double) * n);
         s->w1[a] = malloc(sizeof(double) * n);
-        for (int k = 0; k < n; ++k) {
-            s->xi[a][k] = cfg->vmin[a] + k * d;
-            s->w1[a][k] = (k == 0 || k == n - 1) ? 0.5 * d : d;   /* trapezoid */
+        if (cfg->nodes[a]) {
+            /* trapezoid rule on the given nodes: half of each neighbouring gap */
+            const double *x = cfg->nodes[a];
+            for (int k = 0; k < n; ++k) {
+                s->xi[a][k] = x[k];
+                s->w1[a][k] = 0.5 * ((k < n - 1 ? x[k + 1] : x[k]) - (k > 0 ? x[k - 1] : x[k]));
+            }
+        } else {
+            for (int k = 0; k < n; ++k) {
+                s->xi[a][k] = cfg->vmin[a] + k * d;
+                s->w1[a][k] = (k == 0 || k == n - 1) ? 0.5 * d : d;   /* trapezoid */
+            }
         }
+        s->c.nodes[a] = NULL;   /* copied: the caller's array is not kept */
     }
     s->prev = calloc((size_t)s->ncell * 5, sizeof(double));
     if (!with_vdf) return s;

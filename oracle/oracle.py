@@ -35,6 +35,7 @@ class _Cfg(C.Structure):
         ("inv_dt", C.c_double), ("conservative", C.c_int), ("macro_cfl", C.c_double),
         ("bc_kind", C.c_int * 7), ("bc_u", (C.c_double * 3) * 7), ("bc_T", C.c_double * 7),
         ("bc_rho", C.c_double * 7),
+        ("nodes", C.POINTER(C.c_double) * 3),
     ]
 
 
@@ -105,6 +106,15 @@ def make_cfg(case) -> _Cfg:
             c.bc_u[b][a] = bc.u[a]
         c.bc_T[b] = bc.T
         c.bc_rho[b] = bc.rho
+    # explicit node positions: the arrays live on the config object (the C side
+    # copies them when it creates its state)
+    c._keep = []
+    for a in range(3):
+        x = axis_nodes(case, a, explicit_only=True)
+        if x is not None:
+            x = np.ascontiguousarray(x, dtype=np.float64)
+            c._keep.append(x)
+            c.nodes[a] = x.ctypes.data_as(C.POINTER(C.c_double))
     return c
 
 
@@ -222,15 +232,31 @@ def first_pass_nodes(case, nodes):
     return out0, out1, st
 
 
+def axis_nodes(case, a, explicit_only=False):
+    """The nodes of axis a: the case's explicit array, else uniform on [vmin, vmax]
+    (None for that with explicit_only)."""
+    nodes = getattr(case, "nodes", None)
+    if nodes is not None and nodes[a] is not None:
+        return np.asarray(nodes[a], dtype=np.float64)
+    if explicit_only:
+        return None
+    return np.linspace(case.vmin[a], case.vmax[a], case.nv[a])
+
+
 def node_grid(case):
     """Nodes (n,3) and trapezoid weights (n,) in canonical order (x fastest)."""
     axes, wts = [], []
     for a in range(3):
-        x = np.linspace(case.vmin[a], case.vmax[a], case.nv[a])
-        d = (case.vmax[a] - case.vmin[a]) / (case.nv[a] - 1)
-        w = np.full(case.nv[a], d)
-        w[0] *= 0.5
-        w[-1] *= 0.5
+        x = axis_nodes(case, a, explicit_only=True)
+        if x is None:
+            x = np.linspace(case.vmin[a], case.vmax[a], case.nv[a])
+            d = (case.vmax[a] - case.vmin[a]) / (case.nv[a] - 1)
+            w = np.full(case.nv[a], d)
+            w[0] *= 0.5
+            w[-1] *= 0.5
+        else:
+            # trapezoid rule on the given nodes: half of each neighbouring gap
+            w = 0.5 * (np.append(x[1:], x[-1]) - np.insert(x[:-1], 0, x[0]))
         axes.append(x)
         wts.append(w)
     Z, Y, X = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")

@@ -368,6 +368,31 @@ const char *gsis_last_error(const gsis_ctx *ctx)
     return ctx ? ctx->err.c_str() : "no context";
 }
 
+// Octant layout of the node set: the first non-negative node per axis (a node
+// at 0 belongs to the positive half), octant extents, sizes and bases.
+static void octant_layout(gsis_ctx *x)
+{
+    Geo &g = x->g;
+    for (int a = 0; a < 3; ++a) {
+        const int n = g.n1[a];
+        int k0 = n;
+        for (int k = 0; k < n; ++k)
+            if (k0 == n && x->xi[a][k] >= 0.0) k0 = k;
+        g.k0[a] = k0;
+    }
+    int base = 0;
+    for (int o = 0; o < 8; ++o) {
+        int sz = 1;
+        for (int a = 0; a < 3; ++a) {
+            g.on[o][a] = ((o >> a) & 1) ? g.k0[a] : g.n1[a] - g.k0[a];
+            sz *= g.on[o][a];
+        }
+        g.osize[o] = sz;
+        g.obase[o] = base;
+        base += sz;
+    }
+}
+
 gsis_status gsis_create(gsis_ctx **out, const gsis_config *cfg)
 {
     if (!out) return GSIS_EINVAL;
@@ -413,26 +438,13 @@ gsis_status gsis_create(gsis_ctx **out, const gsis_config *cfg)
         double dv = (c.vmax[a] - c.vmin[a]) / (n - 1);
         x->xi[a].resize(n);
         x->w[a].resize(n);
-        int k0 = n;
         for (int k = 0; k < n; ++k) {
             x->xi[a][k] = c.vmin[a] + k * dv;
             x->w[a][k] = (k == 0 || k == n - 1) ? 0.5 * dv : dv;
-            if (k0 == n && x->xi[a][k] >= 0.0) k0 = k;
         }
-        g.k0[a] = k0;
     }
     g.nv = (int)nv;
-    int base = 0;
-    for (int o = 0; o < 8; ++o) {
-        int sz = 1;
-        for (int a = 0; a < 3; ++a) {
-            g.on[o][a] = ((o >> a) & 1) ? g.k0[a] : g.n1[a] - g.k0[a];
-            sz *= g.on[o][a];
-        }
-        g.osize[o] = sz;
-        g.obase[o] = base;
-        base += sz;
-    }
+    octant_layout(x);
     g.species = c.species;
     g.delta = std::sqrt(PI) / (2.0 * c.Kn);
     g.omega = c.omega;
@@ -474,6 +486,26 @@ gsis_status gsis_destroy(gsis_ctx *ctx)
 {
     if (!ctx) return GSIS_EINVAL;
     delete ctx;
+    return GSIS_OK;
+}
+
+gsis_status gsis_set_velocity_nodes(gsis_ctx *ctx, int axis, const double *nodes, int n)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (ctx->bound || ctx->meta_ready) return fail(ctx, GSIS_ESTATE, "set_velocity_nodes must precede workspace_size/bind");
+    if (axis < 0 || axis > 2) return fail(ctx, GSIS_EINVAL, "axis must be 0, 1 or 2");
+    if (!nodes) return fail(ctx, GSIS_EINVAL, "nodes is NULL");
+    if (n != ctx->g.n1[axis]) return fail(ctx, GSIS_EINVAL, "n must equal the configured node count of the axis");
+    for (int k = 0; k < n; ++k)
+        if (!std::isfinite(nodes[k]) || (k > 0 && !(nodes[k] > nodes[k - 1])))
+            return fail(ctx, GSIS_EINVAL, "nodes must be finite and strictly increasing");
+    std::vector<double> &xi = ctx->xi[axis], &w = ctx->w[axis];
+    for (int k = 0; k < n; ++k) {
+        xi[k] = nodes[k];
+        // trapezoid rule on the given nodes: half of each neighbouring gap
+        w[k] = 0.5 * ((k < n - 1 ? nodes[k + 1] : nodes[k]) - (k > 0 ? nodes[k - 1] : nodes[k]));
+    }
+    octant_layout(ctx);
     return GSIS_OK;
 }
 

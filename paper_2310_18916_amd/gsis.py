@@ -72,6 +72,13 @@ class Context:
         for face, bc in enumerate(case.bcs):
             u = (C.c_double * 3)(*bc.u)
             self._check(self.L.gsis_set_boundary(self.h, face, bc.kind, u, bc.T, bc.rho), "gsis_set_boundary")
+        if case.nodes is not None:
+            for a, x in enumerate(case.nodes):
+                if x is None:
+                    continue
+                x = np.ascontiguousarray(x, dtype=np.float64)
+                self._check(self.L.gsis_set_velocity_nodes(self.h, a, x.ctypes.data_as(C.c_void_p), x.size),
+                            "gsis_set_velocity_nodes")
 
     def _check(self, st: int, where: str):
         if st:

@@ -70,6 +70,9 @@ class Case:
     bcs: List[Boundary] = dataclasses.field(default_factory=lambda: [Boundary() for _ in range(7)])
     solid: Optional[np.ndarray] = None
     init: Tuple[float, Tuple[float, float, float], float, float] = (1.0, (0.0, 0.0, 0.0), 1.0, 1.0)
+    # optional node positions per axis (strictly increasing, nv[a] each); None:
+    # nv[a] uniform nodes on [vmin[a], vmax[a]]
+    nodes: Optional[Tuple[Optional[np.ndarray], Optional[np.ndarray], Optional[np.ndarray]]] = None
     # iteration plan of the workload
     passes: int = 10
     gsis: bool = False
@@ -138,6 +141,24 @@ def block_flow(nx: int, ny: int, nz: int, block: Tuple[Tuple[int, int], Tuple[in
 
 
 # ----------------------------------------------------------------- workloads
+def stretched_nodes(n: int, vmax: float, s: float) -> np.ndarray:
+    """n nodes on [-vmax, vmax] clustered at the origin: vmax sinh(s t) / sinh(s)
+    for t uniform on [-1, 1] (s -> 0 gives the uniform grid)."""
+    t = np.linspace(-1.0, 1.0, n)
+    return vmax * np.sinh(s * t) / np.sinh(s)
+
+
+def with_nodes(case: Case, nodes) -> Case:
+    """The case on a tensor grid with the given per-axis nodes (vmin/vmax follow)."""
+    case.nodes = tuple(None if x is None else np.asarray(x, dtype=np.float64) for x in nodes)
+    vmin, vmax, nv = list(case.vmin), list(case.vmax), list(case.nv)
+    for a, x in enumerate(case.nodes):
+        if x is not None:
+            vmin[a], vmax[a], nv[a] = float(x[0]), float(x[-1]), int(x.size)
+    case.vmin, case.vmax, case.nv = tuple(vmin), tuple(vmax), tuple(nv)
+    return case
+
+
 def c1() -> Case:
     """16^3 cavity, 16^3 nodes on [-4,4]^3, Kn = 0.1, lid 0.1, 10 source iterations, FP64."""
     return cavity(16, 16, 0.1, name="c1_cavity16_v16", passes=10)

@@ -192,3 +192,26 @@ def test_batch_host_checks_before_device_work():
     assert L.gsis_batch_bind_workspace(bh, None, n.value) == -1
     assert L.gsis_batch_bind_workspace(bh, C.c_void_p(256), 16) == -3   # smaller than required
     assert L.gsis_batch_destroy(bh) == 0
+
+
+def test_velocity_nodes_validation():
+    L = _lib.lib()
+    st, h = _create(_cfg())            # 4^3 cells, 6 nodes per axis
+    assert st == 0
+    try:
+        good = np.linspace(-3.0, 4.0, 6)
+        P = lambda a: a.ctypes.data_as(C.c_void_p)
+        assert L.gsis_set_velocity_nodes(h, 3, P(good), 6) == -1          # axis
+        assert L.gsis_set_velocity_nodes(h, 0, P(good), 5) == -1          # count
+        assert L.gsis_set_velocity_nodes(h, 0, None, 6) == -1
+        bad = good.copy()
+        bad[3] = bad[2]
+        assert L.gsis_set_velocity_nodes(h, 1, P(bad), 6) == -1           # not strictly increasing
+        bad[3] = np.nan
+        assert L.gsis_set_velocity_nodes(h, 1, P(bad), 6) == -1
+        assert L.gsis_set_velocity_nodes(h, 2, P(good), 6) == 0
+        n = C.c_size_t()
+        assert L.gsis_workspace_size(h, C.byref(n)) == 0
+        assert L.gsis_set_velocity_nodes(h, 2, P(good), 6) == -2          # frozen once sized
+    finally:
+        L.gsis_destroy(h)

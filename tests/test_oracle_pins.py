@@ -168,6 +168,52 @@ def test_correction_skipped_where_the_grid_cannot_separate_mass_and_energy():
             assert abs((w * (xi * xi).sum(1) * d0).sum()) < 1e-13 * scale
 
 
+# ------------------------------------------------- non-uniform velocity grid
+def test_nonuniform_nodes_trapezoid_and_uniform_limit():
+    """Explicit nodes: the trapezoid weights (half of each neighbouring gap) sum
+    to the range and integrate linear functions exactly; the uniform nodes
+    given explicitly reproduce the implicit uniform grid's pass."""
+    case = I.with_nodes(I.cavity(3, 9, 0.1, lid=0.2), [I.stretched_nodes(9, 4.0, 1.8),
+                                                       I.stretched_nodes(8, 4.0, 1.2), None])
+    xi, w = O.node_grid(case)
+    assert abs(w.sum() - 8.0 ** 3) < 1e-12 * 8.0 ** 3
+    for a in range(3):
+        lin = 0.3 + 0.7 * xi[:, a]
+        assert abs((w * lin).sum() - 0.3 * 8.0 ** 3) < 1e-12 * 8.0 ** 3
+    # the nodes are where the case says, clustered at the origin
+    x0 = np.unique(xi[:, 0])
+    assert np.allclose(x0, I.stretched_nodes(9, 4.0, 1.8), rtol=0, atol=0)
+    assert np.diff(x0)[4] < np.diff(x0)[0]
+    uni = I.cavity(3, 8, 0.1, lid=0.2)
+    exp = I.with_nodes(I.cavity(3, 8, 0.1, lid=0.2), [np.linspace(-4.0, 4.0, 8)] * 3)
+    res = []
+    for c in (uni, exp):
+        o = O.Oracle(c)
+        o.init_maxwellian()
+        o.step(2)
+        res.append(o.moments())
+    assert np.abs(res[0] - res[1]).max() < 1e-13 * np.abs(res[0]).max()
+
+
+def test_collision_conserves_on_a_stretched_grid():
+    """The conservative correction is exact on non-uniform nodes too."""
+    case = I.with_nodes(I.cavity(2, 10, 0.1), [I.stretched_nodes(10, 5.0, 2.0), I.stretched_nodes(9, 5.0, 1.0),
+                                               I.stretched_nodes(11, 5.0, 1.5)])
+    o = O.Oracle(case)
+    f0, f1 = I.random_vdf(case, seed=9)
+    o.set_vdf(f0, f1)
+    xi, w = O.node_grid(case)
+    x2 = (xi * xi).sum(1)
+    for cell in range(case.ncell):
+        g0, _ = o.ref_dist(cell)
+        d0 = g0 - f0[cell]
+        scale = (w * f0[cell] * (1 + x2)).sum()
+        assert abs((w * d0).sum()) < 1e-13 * scale
+        for a in range(3):
+            assert abs((w * xi[:, a] * d0).sum()) < 1e-13 * scale
+        assert abs((w * x2 * d0).sum()) < 1e-13 * scale
+
+
 # ------------------------------------------------------------ fixed point
 def test_uniform_maxwellian_is_a_fixed_point():
     """Rest cavity with f = M(1,0,1): a pass and a GSIS correction leave f unchanged."""
