@@ -36,6 +36,9 @@ def parse():
     p.add_argument("--no-converge", action="store_true", help="skip the time-to-convergence runs")
     p.add_argument("--no-batch", action="store_true", help="skip the 64-cavity batched run")
     p.add_argument("--batch-iters", type=int, default=50)
+    p.add_argument("--stretch", type=float, default=0.0,
+                   help="non-uniform velocity grid: the same node counts clustered at the origin by a sinh map "
+                        "of this strength (0: the workload's uniform grid)")
     p.add_argument("--copy-calib-mib", type=int, default=0,
                    help="after the run, copy a buffer of this many MiB three times (HBM counter calibration)")
     return p.parse_args()
@@ -277,6 +280,11 @@ def main():
         print(json.dumps({"batched": batched(a.batch_iters)}), flush=True)
         return
     case = workload(a.workload)
+    if a.stretch > 0:
+        from paper_2310_18916_amd import inputs as I
+        case = I.with_nodes(case, [I.stretched_nodes(case.nv[k], max(-case.vmin[k], case.vmax[k]), a.stretch)
+                                   for k in range(3)])
+        case.name += f"_stretch{a.stretch:g}"
     dtype = a.dtype or ("fp32" if a.workload in ("c3", "c4") else "fp64")
     macro = a.macro_iters if a.macro_iters is not None else case.macro_iters
     tile = tuple(int(x) for x in a.tile.split(",")) if a.tile else None
