@@ -145,6 +145,16 @@ gsis_status gsis_moments(gsis_ctx *ctx, double *out, int out_is_device);
  * VDF is next read.  Needs a kinetic step since init.  Asynchronous. */
 gsis_status gsis_gsis_correct(gsis_ctx *ctx, int inner_iters);
 
+/* Initial field of Alg. 1, line 1: macro_steps iterations of the macroscopic
+ * solver of gsis_gsis_correct with the Euler constitutive relations (no
+ * stress, heat flux or HoT; no diffusive term in the pseudo-time diagonal; the
+ * boundary faces take the flux of the iterate's own Maxwellian), started from
+ * the current moments; the VDF is corrected to the result as in Eq. (updatef);
+ * then kinetic_steps kinetic passes.  Typically after gsis_init_maxwellian,
+ * with 1000 and 10.  Asynchronous; EINVAL for negative counts, ESTATE before
+ * initialisation. */
+gsis_status gsis_precondition(gsis_ctx *ctx, int macro_steps, int kinetic_steps);
+
 /* Convergence criterion of Sec. 4 (volume-weighted relative L2 change of rho,
  * |u| as a vector, Tt since the previous call or init; a zero denominator
  * gives the absolute change).  Synchronises.  Returns GSIS_ENOTFINITE if a

@@ -809,6 +809,7 @@ typedef struct { double rho, u[3], Tt, Tr, p, cs, E, Er; } prim_t;
 
 typedef struct {
     int dia, nw;
+    int euler;              /* Euler constitutive relations: no stress, heat flux or HoT */
     double dr, Z, delta, omega, gam, kt, kr, Cd, cfl;
 } macpar;
 
@@ -892,8 +893,8 @@ static void nsf_face(const macpar *mp, const prim_t *L, const prim_t *R, const d
 static void face_flux(const macpar *mp, const prim_t *L, const prim_t *R, const double *gL,
                       const double *gR, int a, double h, const double hot[5], double F[6], double *Gam)
 {
-    double sigN[3], qN, qrN;
-    nsf_face(mp, L, R, gL, gR, a, h, sigN, &qN, &qrN);
+    double sigN[3] = {0, 0, 0}, qN = 0, qrN = 0;
+    if (!mp->euler) nsf_face(mp, L, R, gL, gR, a, h, sigN, &qN, &qrN);
     const prim_t *S[2] = {L, R};
     double Phi[2][6], Wv[2][6];
     for (int k = 0; k < 2; ++k) {
@@ -918,7 +919,7 @@ static void face_flux(const macpar *mp, const prim_t *L, const prim_t *R, const 
     F[4] += sn[0] * uF[0] + sn[1] * uF[1] + sn[2] * uF[2] + qn + qrn;
     F[5] += qrn;
     double TF = 0.5 * (L->Tt + R->Tt), rF = 0.5 * (L->rho + R->rho);
-    *Gam = smax + mp->Cd * pow(TF, mp->omega) / (mp->delta * rF * h);
+    *Gam = mp->euler ? smax : smax + mp->Cd * pow(TF, mp->omega) / (mp->delta * rF * h);
 }
 
 /* Kinetic boundary flux of face (cell, d) out of the cell (O6 in the text above):
@@ -999,11 +1000,16 @@ static void equilibrium_face_flux(const orc_state *s, const prim_t *P, int d, in
     for (int k = 0; k < 6; ++k) F[k] = nval(&acc[k]);
 }
 
-int orc_gsis_correct(orc_state *s, int iters)
+/* euler = 1: the same iteration with the Euler constitutive relations (no
+ * stress, heat flux or HoT, no diffusive part in Gamma and dtau) and the
+ * boundary flux of the iterate's own Maxwellian, F_b(W^m) = F_eq(W^m): the
+ * initial-field computation of Alg. 1, line 1. */
+static int gsis_correct_mode(orc_state *s, int iters, int euler)
 {
     const orc_cfg *c = &s->c;
     macpar mp;
     macro_params(s, &mp);
+    mp.euler = euler;
     int ncell = s->ncell, nw = mp.nw;
     double hmin = s->h[0];
     if (s->h[1] < hmin) hmin = s->h[1];
@@ -1033,16 +1039,16 @@ int orc_gsis_correct(orc_state *s, int iters)
         w[5] = Er;
         for (int d = 0; d < 6; ++d) {
             int n = neighbour(s, cell, d);
-            if (n < 0) kinetic_face_flux(s, cell, d, -1 - n, Fb + (size_t)cell * 36 + d * 6);
+            if (n < 0 && !euler) kinetic_face_flux(s, cell, d, -1 - n, Fb + (size_t)cell * 36 + d * 6);
         }
     }
     /* HoT at interior faces (cell, cell + e_a), from W^{n+1/2} */
     for (int cell = 0; cell < ncell; ++cell)
         if (!s->solid[cell]) prim_of(&mp, W + (size_t)cell * 6, &P[cell]);
-    /* fixed part of the boundary fluxes: F_kin - F_eq(W^{n+1/2}) */
+    /* fixed part of the boundary fluxes: F_kin - F_eq(W^{n+1/2}) (zero for Euler) */
     #pragma omp parallel for schedule(dynamic, 16)
     for (int cell = 0; cell < ncell; ++cell) {
-        if (s->solid[cell]) continue;
+        if (s->solid[cell] || euler) continue;
         for (int d = 0; d < 6; ++d) {
             int n = neighbour(s, cell, d);
             if (n >= 0) continue;
@@ -1054,7 +1060,7 @@ int orc_gsis_correct(orc_state *s, int iters)
     for (int cell = 0; cell < ncell; ++cell)
         if (!s->solid[cell]) cell_grad(s, P, cell, grad + (size_t)cell * 9);
     for (int cell = 0; cell < ncell; ++cell) {
-        if (s->solid[cell]) continue;
+        if (s->solid[cell] || euler) continue;    /* no HoT for Euler */
         for (int a = 0; a < 3; ++a) {
             int nb = neighbour(s, cell, 2 * a + 1);
             if (nb < 0) continue;
@@ -1094,7 +1100,8 @@ int orc_gsis_correct(orc_state *s, int iters)
                     double Fe[6];
                     equilibrium_face_flux(s, Pi, d, -1 - n, Fe);
                     for (int k = 0; k < 6; ++k) out[k] = Fb[(size_t)cell * 36 + d * 6 + k] + Fe[k];
-                    Gam = fabs(Pi->u[a]) + Pi->cs + mp.Cd * pow(Pi->Tt, mp.omega) / (mp.delta * Pi->rho * h);
+                    Gam = fabs(Pi->u[a]) + Pi->cs;
+                    if (!euler) Gam += mp.Cd * pow(Pi->Tt, mp.omega) / (mp.delta * Pi->rho * h);
                 }
                 for (int k = 0; k < nw; ++k) res[k] -= out[k] / h;
                 sumG += Gam / h;
@@ -1105,7 +1112,8 @@ int orc_gsis_correct(orc_state *s, int iters)
                 res[5] += 0.5 * mp.dr * Pi->rho * (T - Pi->Tr) * invtau / mp.Z;
             }
             double umag = sqrt(Pi->u[0] * Pi->u[0] + Pi->u[1] * Pi->u[1] + Pi->u[2] * Pi->u[2]);
-            double idt = (umag + Pi->cs + mp.Cd * pow(Pi->Tt, mp.omega) / (mp.delta * Pi->rho * hmin)) / (mp.cfl * hmin);
+            double vis = euler ? 0.0 : mp.Cd * pow(Pi->Tt, mp.omega) / (mp.delta * Pi->rho * hmin);
+            double idt = (umag + Pi->cs + vis) / (mp.cfl * hmin);
             double *r = R + (size_t)cell * 6;
             for (int k = 0; k < 6; ++k) r[k] = res[k];
             Dc[cell] = idt + 0.5 * sumG;
@@ -1146,6 +1154,19 @@ int orc_gsis_correct(orc_state *s, int iters)
         }
     }
     free(K); free(W); free(Fb); free(hot); free(grad); free(P); free(R); free(Dc); free(Src);
+    return s->status;
+}
+
+int orc_gsis_correct(orc_state *s, int iters) { return gsis_correct_mode(s, iters, 0); }
+
+/* Initial field of Alg. 1, line 1: macro_steps iterations of the macroscopic
+ * solver with the Euler constitutive relations from the current state, the
+ * VDF corrected to the result (Eq. updatef), then kinetic_steps passes. */
+int orc_gsis_precondition(orc_state *s, int macro_steps, int kinetic_steps)
+{
+    int st = gsis_correct_mode(s, macro_steps, 1);
+    if (st) return st;
+    orc_step(s, kinetic_steps);
     return s->status;
 }
 

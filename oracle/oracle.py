@@ -63,6 +63,7 @@ def lib():
         L.orc_moments.argtypes = [P, D]
         L.orc_residual.argtypes = [P, D]
         L.orc_gsis_correct.argtypes = [P, C.c_int]
+        L.orc_gsis_precondition.argtypes = [P, C.c_int, C.c_int]
         L.orc_ref_dist.argtypes = [P, C.c_int, D, D]
         L.orc_invtau.argtypes = [P, C.c_int]
         L.orc_invtau.restype = C.c_double
@@ -150,6 +151,11 @@ class Oracle:
 
     def gsis_correct(self, iters: int) -> int:
         return lib().orc_gsis_correct(self.h, iters)
+
+    def precondition(self, macro_steps: int = 1000, kinetic_steps: int = 10) -> int:
+        """Alg. 1, line 1: Euler macroscopic steps, the VDF corrected to their
+        result, then kinetic passes."""
+        return lib().orc_gsis_precondition(self.h, macro_steps, kinetic_steps)
 
     def status(self) -> int:
         return lib().orc_status(self.h)

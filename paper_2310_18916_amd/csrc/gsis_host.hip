@@ -697,6 +697,26 @@ gsis_status gsis_gsis_correct(gsis_ctx *ctx, int inner_iters)
     return GSIS_OK;
 }
 
+gsis_status gsis_precondition(gsis_ctx *ctx, int macro_steps, int kinetic_steps)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (!ctx->inited) return fail(ctx, GSIS_ESTATE, "initialise the VDF first");
+    if (macro_steps < 0 || kinetic_steps < 0) return fail(ctx, GSIS_EINVAL, "steps must be >= 0");
+    gsis_status st = materialize(ctx);
+    if (st) return st;
+    {
+        PhaseTimer t;
+        HIPCHK(ctx, t.start(ctx, GSIS_PHASE_MACRO));
+        const Target tg = target_of(ctx);
+        HIPCHK(ctx, launch_gsis_macro(tg, macro_steps, ctx->stream, 1));
+        HIPCHK(ctx, launch_commit_correction(tg, ctx->stream));
+        HIPCHK(ctx, launch_derive(tg, ctx->stream));
+        HIPCHK(ctx, t.stop());
+    }
+    ctx->pending = true;
+    return gsis_kinetic_step(ctx, kinetic_steps);
+}
+
 gsis_status gsis_residual(gsis_ctx *ctx, double eps[3])
 {
     if (!ctx) return GSIS_EINVAL;

@@ -49,7 +49,9 @@ int sweep_shape_waves(bool fp32, int tx, int ty);
 int sweep_shapes(bool fp32, int *out, int max);
 hipError_t launch_sweep(const Target &t, hipStream_t s);
 
-hipError_t launch_gsis_macro(const Target &t, int iters, hipStream_t s);
+// euler != 0: the Euler constitutive relations (no stress, heat flux, HoT or
+// diffusive pseudo-time terms) and the iterate's own boundary flux
+hipError_t launch_gsis_macro(const Target &t, int iters, hipStream_t s, int euler = 0);
 
 int resid_blocks(const Geo &g);
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);

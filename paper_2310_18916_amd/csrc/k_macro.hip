@@ -94,12 +94,13 @@ __device__ __forceinline__ void side(const PV &P, int a, double Phi[6], double W
 
 template <class PV, class GV, class HV>
 __device__ __forceinline__ void face_flux(const Geo &g, const PV &L, const PV &R, const GV &gL, const GV &gR, int a,
-                                          double ih, const HV &hot, double F[6], double *Gam)
+                                          double ih, const HV &hot, bool euler, double F[6], double *Gam)
 {
     const double TF = 0.5 * (L[4] + R[4]), rF = 0.5 * (L[0] + R[0]);
-    const double mu = pow_pos(TF, g.omega) / g.delta;
-    double sigN[3], qN, qrN;
-    nsf_face(g, L, R, gL, gR, a, ih, mu, sigN, &qN, &qrN);
+    // Euler constitutive relations: no stress or heat flux, no diffusive part in Gamma
+    const double mu = euler ? 0.0 : pow_pos(TF, g.omega) / g.delta;
+    double sigN[3] = {0.0, 0.0, 0.0}, qN = 0.0, qrN = 0.0;
+    if (!euler) nsf_face(g, L, R, gL, gR, a, ih, mu, sigN, &qN, &qrN);
     double PhiL[6], WL[6], PhiR[6], WR[6];
     side(L, a, PhiL, WL);
     side(R, a, PhiR, WR);
@@ -116,7 +117,7 @@ __device__ __forceinline__ void face_flux(const Geo &g, const PV &L, const PV &R
     for (int b = 0; b < 3; ++b) F[1 + b] += 0.5 * sn[b];
     F[4] += sn[0] * uF[0] + sn[1] * uF[1] + sn[2] * uF[2] + qn + qrn;
     F[5] += qrn;
-    *Gam = smax + g.Cd * mu * ih / rF;
+    *Gam = euler ? smax : smax + g.Cd * mu * ih / rF;
 }
 
 // Outgoing half-range psi-moments of M(rho, u, Tt) through face dir (sum over
@@ -199,9 +200,9 @@ __device__ void group_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev
 
 // Gamma of a boundary face: outward speed plus the diffusive term of the cell
 template <class PV>
-__device__ __forceinline__ double boundary_gamma(const Geo &g, const PV &P, int a)
+__device__ __forceinline__ double boundary_gamma(const Geo &g, const PV &P, int a, bool euler)
 {
-    return fabs(P[1 + a]) + P[8] + g.Cd * P[9] / (P[0] * g.h[a]);
+    return fabs(P[1 + a]) + P[8] + (euler ? 0.0 : g.Cd * P[9] / (P[0] * g.h[a]));
 }
 
 // W^{n+1/2}, kinetic stress/heat flux, the old half of the correction record.
@@ -252,7 +253,7 @@ __device__ void cell_grad_col(const Geo &g, const Dev &d, int cell, int a)
 // Blocks [0, nfb): boundary faces, FG lanes per face: F_b = fixed part +
 // F_eq(W^m) and its Gamma (skipped when with_faces is 0).  Blocks [nfb, ...):
 // central gradients of u, one (cell, axis) per thread.
-__global__ __launch_bounds__(256) void k_mac_grad(GSIS_SPAN_ARGS, int with_faces)
+__global__ __launch_bounds__(256) void k_mac_grad(GSIS_SPAN_ARGS, int with_faces, int euler)
 {
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
@@ -276,11 +277,11 @@ __global__ __launch_bounds__(256) void k_mac_grad(GSIS_SPAN_ARGS, int with_faces
     double Fe[6];
     group_equilibrium_flux(g, bc, d, P, dir, G(d.face_bc)[f], sub, Fe);
     if (sub < 6) G(d.Fb)[(size_t)sub * g.nface + f] = G(d.fbfix)[(size_t)sub * g.nface + f] + Fe[sub];
-    if (sub == 7) G(d.Gb)[f] = boundary_gamma(g, P, dir / 2);
+    if (sub == 7) G(d.Gb)[f] = boundary_gamma(g, P, dir / 2, euler);
 }
 
 // HoT at the faces (cell, cell + e_a) from W^{n+1/2}.
-__global__ __launch_bounds__(128) void k_mac_hot(GSIS_SPAN_ARGS)
+__global__ __launch_bounds__(128) void k_mac_hot(GSIS_SPAN_ARGS, int euler)
 {
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
@@ -290,6 +291,10 @@ __global__ __launch_bounds__(128) void k_mac_hot(GSIS_SPAN_ARGS)
     if (cell >= g.ncell || !G(d.cflag)[cell]) return;
     const int col[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
     const size_t n = g.ncell;
+    if (euler) {                                  // Euler constitutive relations: no HoT
+        for (int k = 0; k < 15; ++k) soa(d.hot, n, cell)[k] = 0.0;
+        return;
+    }
     for (int a = 0; a < 3; ++a) {
         int nb = G(d.nbr)[(size_t)(2 * a + 1) * g.ncell + cell];
         const Soa<double> ho = soa(d.hot + (size_t)a * 5 * n, n, cell);
@@ -311,7 +316,7 @@ __global__ __launch_bounds__(128) void k_mac_hot(GSIS_SPAN_ARGS)
 // Fixed part of each boundary face flux, F_kin(f^{n+1/2}) - F_eq(W^{n+1/2}), and
 // the face flux of the first inner iteration, fixed part + F_eq(W^{n+1/2}).
 // One group of FG lanes per face.
-__global__ __launch_bounds__(256) void k_mac_fbfix(GSIS_SPAN_ARGS)
+__global__ __launch_bounds__(256) void k_mac_fbfix(GSIS_SPAN_ARGS, int euler)
 {
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
@@ -342,11 +347,12 @@ __global__ __launch_bounds__(256) void k_mac_fbfix(GSIS_SPAN_ARGS)
     double Fe[6];
     group_equilibrium_flux(g, bc, d, P, dir, b, sub, Fe);
     if (sub < 6) {
-        const double fix = out[sub] + sc * in[sub] - Fe[sub];
+        // Euler: the boundary flux is the iterate's own F_eq, no fixed kinetic part
+        const double fix = euler ? 0.0 : out[sub] + sc * in[sub] - Fe[sub];
         G(d.fbfix)[(size_t)sub * g.nface + f] = fix;
         G(d.Fb)[(size_t)sub * g.nface + f] = fix + Fe[sub];
     }
-    if (sub == 7) G(d.Gb)[f] = boundary_gamma(g, P, a);
+    if (sub == 7) G(d.Gb)[f] = boundary_gamma(g, P, a, euler);
 }
 
 // Flux of face dir of a cell divided by h (outward positive), and Gamma / h.
@@ -366,7 +372,7 @@ __device__ __forceinline__ int grid_neighbour(const Geo &g, int cell, int dir)
 // the face data, so the caller needs no second round trip to memory.
 template <int DIR, int NW, bool KEEP>
 __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, double out[NW], double &gam,
-                                          double *own)
+                                          double *own, bool euler)
 {
     constexpr int a = DIR / 2;
     const double ih = g.invh[a];
@@ -398,7 +404,7 @@ __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, 
     const int n = G(d.nbr)[(size_t)DIR * g.ncell + cell];
     if (n >= 0) {
         double F[6], Gam;
-        face_flux(g, PL, PR, GL, GR, a, ih, HO, F, &Gam);
+        face_flux(g, PL, PR, GL, GR, a, ih, HO, euler, F, &Gam);
 #pragma unroll
         for (int k = 0; k < NW; ++k) out[k] = ((DIR & 1) ? F[k] : -F[k]) * ih;
         gam = Gam * ih;
@@ -420,7 +426,7 @@ constexpr int RES_CELLS = 64;
 
 // Six waves per SIMD (at most 80 VGPRs): four blocks per CU instead of three.
 template <bool DIA>
-__global__ __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(6))) void k_mac_res(GSIS_SPAN_ARGS, int slot)
+__global__ __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(6))) void k_mac_res(GSIS_SPAN_ARGS, int slot, int euler)
 {
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
@@ -438,12 +444,12 @@ __global__ __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(6))) void k
     for (int k = 0; k < NW; ++k) out[k] = 0.0;
     if (live) {
         switch (dir) {
-        case 0: face_term<0, NW, true>(g, d, cell, out, gam, Pi); break;
-        case 1: face_term<1, NW, false>(g, d, cell, out, gam, nullptr); break;
-        case 2: face_term<2, NW, false>(g, d, cell, out, gam, nullptr); break;
-        case 3: face_term<3, NW, false>(g, d, cell, out, gam, nullptr); break;
-        case 4: face_term<4, NW, false>(g, d, cell, out, gam, nullptr); break;
-        default: face_term<5, NW, false>(g, d, cell, out, gam, nullptr); break;
+        case 0: face_term<0, NW, true>(g, d, cell, out, gam, Pi, euler); break;
+        case 1: face_term<1, NW, false>(g, d, cell, out, gam, nullptr, euler); break;
+        case 2: face_term<2, NW, false>(g, d, cell, out, gam, nullptr, euler); break;
+        case 3: face_term<3, NW, false>(g, d, cell, out, gam, nullptr, euler); break;
+        case 4: face_term<4, NW, false>(g, d, cell, out, gam, nullptr, euler); break;
+        default: face_term<5, NW, false>(g, d, cell, out, gam, nullptr, euler); break;
         }
     }
 #pragma unroll
@@ -468,7 +474,7 @@ __global__ __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(6))) void k
             res[5] += 0.5 * g.dr * Pi[0] * (T - Pi[5]) * invtau / g.Zr;
         }
         double umag = sqrt(Pi[1] * Pi[1] + Pi[2] * Pi[2] + Pi[3] * Pi[3]);
-        double idt = (umag + Pi[8] + g.Cd * Pi[9] / (Pi[0] * g.hmin)) / (g.macro_cfl * g.hmin);
+        double idt = (umag + Pi[8] + (euler ? 0.0 : g.Cd * Pi[9] / (Pi[0] * g.hmin))) / (g.macro_cfl * g.hmin);
         D = idt + 0.5 * sumG;
         const Soa<double> r = soa(d.R, g.ncell, cell);
 #pragma unroll
@@ -514,7 +520,7 @@ __device__ __forceinline__ void stepped_mass_momentum(const Geo &g, const Dev &d
 // boundary face, then (cell, axis) threads (the axis-0 blocks also write W'
 // and the prims).  Neighbours' new velocities and the face cells' new prims are
 // formed from W and R directly, so W is double buffered (read src, write dst).
-__global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, int parity, int last)
+__global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, int parity, int last, int euler)
 {
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
@@ -576,7 +582,7 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
     double Fe[6];
     group_equilibrium_flux(g, bc, d, P, dir, G(d.face_bc)[f], sub, Fe);
     if (sub < 6) G(d.Fb)[(size_t)sub * g.nface + f] = G(d.fbfix)[(size_t)sub * g.nface + f] + Fe[sub];
-    if (sub == 7) G(d.Gb)[f] = boundary_gamma(g, P, dir / 2);
+    if (sub == 7) G(d.Gb)[f] = boundary_gamma(g, P, dir / 2, euler);
 }
 
 // one block per case
@@ -603,19 +609,22 @@ __global__ __launch_bounds__(128) void k_mac_final(GSIS_SPAN_ARGS)
     if (!(P[0] > 0.0) || !(P[4] > 0.0) || !isfinite(P[6]) || (g.species == 1 && !(P[5] > 0.0))) atomicOr(d.errflag, 4);
 }
 
-hipError_t launch_gsis_macro(const Target &t, int iters, hipStream_t s)
+hipError_t launch_gsis_macro(const Target &t, int iters, hipStream_t s, int euler)
 {
     hipLaunchKernelGGL(k_mac_reset, dim3(t.nblk[K_CASE]), dim3(64), 0, s, GSIS_SPAN(t.span(K_CASE)));
     hipLaunchKernelGGL(k_mac_init, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(t.span(K_CELL128)));
-    hipLaunchKernelGGL(k_mac_grad, dim3(t.nblk[K_GRAD]), dim3(256), 0, s, GSIS_SPAN(t.span(K_GRAD)), 0);
-    hipLaunchKernelGGL(k_mac_hot, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(t.span(K_CELL128)));
-    if (t.nblk[K_FACE8] > 0) hipLaunchKernelGGL(k_mac_fbfix, dim3(t.nblk[K_FACE8]), dim3(256), 0, s, GSIS_SPAN(t.span(K_FACE8)));
+    hipLaunchKernelGGL(k_mac_grad, dim3(t.nblk[K_GRAD]), dim3(256), 0, s, GSIS_SPAN(t.span(K_GRAD)), 0, euler);
+    hipLaunchKernelGGL(k_mac_hot, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(t.span(K_CELL128)), euler);
+    if (t.nblk[K_FACE8] > 0)
+        hipLaunchKernelGGL(k_mac_fbfix, dim3(t.nblk[K_FACE8]), dim3(256), 0, s, GSIS_SPAN(t.span(K_FACE8)), euler);
     for (int it = 0; it < iters; ++it) {
         const int slot = it & 1;
-        if (t.dia) hipLaunchKernelGGL(k_mac_res<true>, dim3(t.nblk[K_RES]), dim3(384), 0, s, GSIS_SPAN(t.span(K_RES)), slot);
-        else hipLaunchKernelGGL(k_mac_res<false>, dim3(t.nblk[K_RES]), dim3(384), 0, s, GSIS_SPAN(t.span(K_RES)), slot);
+        if (t.dia)
+            hipLaunchKernelGGL(k_mac_res<true>, dim3(t.nblk[K_RES]), dim3(384), 0, s, GSIS_SPAN(t.span(K_RES)), slot, euler);
+        else
+            hipLaunchKernelGGL(k_mac_res<false>, dim3(t.nblk[K_RES]), dim3(384), 0, s, GSIS_SPAN(t.span(K_RES)), slot, euler);
         hipLaunchKernelGGL(k_mac_advance, dim3(t.nblk[K_GRAD]), dim3(256), 0, s, GSIS_SPAN(t.span(K_GRAD)), slot, it & 1,
-                           it == iters - 1 ? 1 : 0);
+                           it == iters - 1 ? 1 : 0, euler);
     }
     hipLaunchKernelGGL(k_mac_final, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(t.span(K_CELL128)));
     return hipGetLastError();

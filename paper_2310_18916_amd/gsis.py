@@ -151,6 +151,11 @@ class Solver(Context):
     def gsis_correct(self, inner_iters: int):
         self._check(self.L.gsis_gsis_correct(self.h, inner_iters), "gsis_gsis_correct")
 
+    def precondition(self, macro_steps: int = 1000, kinetic_steps: int = 10):
+        """Alg. 1, line 1: Euler macroscopic steps, the VDF corrected to their
+        result, then kinetic passes."""
+        self._check(self.L.gsis_precondition(self.h, macro_steps, kinetic_steps), "gsis_precondition")
+
     def moments(self) -> np.ndarray:
         out = np.empty((self.case.ncell, self.nmom), dtype=np.float64)
         self._check(self.L.gsis_moments(self.h, out.ctypes.data_as(C.c_void_p), 0), "gsis_moments")

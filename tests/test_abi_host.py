@@ -84,6 +84,7 @@ def test_mask_boundary_and_order_checks():
         assert L.gsis_init_maxwellian(h, 1.0, u, 1.0, 1.0) == -2
         assert L.gsis_kinetic_step(h, 1) == -2
         assert L.gsis_gsis_correct(h, 1) == -2
+        assert L.gsis_precondition(h, 10, 1) == -2
         eps = (C.c_double * 3)()
         assert L.gsis_residual(h, eps) == -2
         out = np.empty(64 * 14)

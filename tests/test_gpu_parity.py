@@ -201,6 +201,29 @@ def test_gsis_parity(name, iters):
     assert e0 <= 1e-12
 
 
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["cav_odd", "block", "n2_block"])
+def test_precondition_parity(name, dtype):
+    """Initial field of Alg. 1 (Euler macroscopic steps, the VDF corrected to
+    them, kinetic passes), then a GSIS iteration, against the oracle."""
+    say(f"[precondition] {name} {dtype}")
+    case = SMALL[name]
+    s = Solver(case, dtype)
+    o = Oracle(case)
+    s.init_maxwellian()
+    o.init_maxwellian()
+    s.precondition(30, 2)
+    assert o.precondition(30, 2) == 0
+    assert_fields(s.moments(), o.moments(), TOL[dtype], case.solid_mask(), what=f"{name} preconditioned")
+    s.kinetic_step(1)
+    o.step(1)
+    s.gsis_correct(20)
+    assert o.gsis_correct(20) == 0
+    s.kinetic_step(1)
+    o.step(1)
+    assert_fields(s.moments(), o.moments(), TOL[dtype], case.solid_mask(), what=f"{name} after a GSIS iteration")
+
+
 def test_uniform_rest_state_is_fixed_point():
     say("[fixed point]")
     case = I.cavity(6, 20, 0.1, lid=0.0, vmax=5.0)
