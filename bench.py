@@ -36,6 +36,9 @@ def parse():
     p.add_argument("--no-converge", action="store_true", help="skip the time-to-convergence runs")
     p.add_argument("--no-batch", action="store_true", help="skip the 64-cavity batched run")
     p.add_argument("--batch-iters", type=int, default=50)
+    p.add_argument("--precondition", default="1000,10",
+                   help="macro_steps,kinetic_steps of the initial field (Alg. 1) for an extra time-to-convergence "
+                        "run; 'none' skips it")
     p.add_argument("--stretch", type=float, default=0.0,
                    help="non-uniform velocity grid: the same node counts clustered at the origin by a sinh map "
                         "of this strength (0: the workload's uniform grid)")
@@ -107,16 +110,20 @@ def run_gpu(case, dtype, steps, warmup, macro_iters, tile):
             "tile": s.get_tile()}
 
 
-def converge(case, dtype, tile, tol=1e-6, max_iters=200):
+def converge(case, dtype, tile, tol=1e-6, max_iters=200, pre=None):
     """GSIS iterations from the initial state until the relative change of rho and
     T drops below tol (the convergence test of the workload); returns iterations,
-    wall time and the converged moments."""
+    wall time and the converged moments.  pre = (macro_steps, kinetic_steps):
+    the initial field of Alg. 1 first (inside the timed region)."""
     import torch
     from paper_2310_18916_amd.gsis import Solver
     s = Solver(case, dtype, tile=tuple(tile))
     s.init_maxwellian()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    if pre is not None:
+        s.precondition(*pre)
+        s.residual()            # the preconditioned state becomes the reference of the first change
     it, eps = 0, None
     while it < max_iters:
         s.kinetic_step(1)
@@ -353,6 +360,12 @@ def main():
         out["converged"] = {"tol": 1e-6, "fp64": c64, "fp32": c32,
                             "fp32_vs_fp64_max_rel_diff": field_diff(m32, m64),
                             "speedup_fp32_vs_fp64_time_to_converge": c64["seconds"] / c32["seconds"]}
+        if a.precondition != "none":
+            pre = tuple(int(x) for x in a.precondition.split(","))
+            cp, mp = converge(case, "fp64", out["sweep_tile"], pre=pre)
+            cp["initial_field"] = {"euler_macro_steps": pre[0], "kinetic_steps": pre[1]}
+            out["converged"]["fp64_preconditioned"] = cp
+            out["converged"]["preconditioned_vs_plain_max_rel_diff"] = field_diff(mp, m64)
     if not a.no_batch and a.workload == "c2":
         out["batched"] = batched(a.batch_iters)
     if a.copy_calib_mib > 0:
