@@ -370,9 +370,9 @@ __device__ __forceinline__ int grid_neighbour(const Geo &g, int cell, int dir)
 
 // With KEEP the cell's own prims 0..10 are also returned in own[], loaded with
 // the face data, so the caller needs no second round trip to memory.
-template <int DIR, int NW, bool KEEP>
+template <int DIR, int NW, bool KEEP, bool EULER>
 __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, double out[NW], double &gam,
-                                          double *own, bool euler)
+                                          double *own)
 {
     constexpr int a = DIR / 2;
     const double ih = g.invh[a];
@@ -404,7 +404,7 @@ __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, 
     const int n = G(d.nbr)[(size_t)DIR * g.ncell + cell];
     if (n >= 0) {
         double F[6], Gam;
-        face_flux(g, PL, PR, GL, GR, a, ih, HO, euler, F, &Gam);
+        face_flux(g, PL, PR, GL, GR, a, ih, HO, EULER, F, &Gam);
 #pragma unroll
         for (int k = 0; k < NW; ++k) out[k] = ((DIR & 1) ? F[k] : -F[k]) * ih;
         gam = Gam * ih;
@@ -425,8 +425,8 @@ __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, 
 constexpr int RES_CELLS = 64;
 
 // Six waves per SIMD (at most 80 VGPRs): four blocks per CU instead of three.
-template <bool DIA>
-__global__ __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(6))) void k_mac_res(GSIS_SPAN_ARGS, int slot, int euler)
+template <bool DIA, bool EULER>
+__global__ __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(6))) void k_mac_res(GSIS_SPAN_ARGS, int slot)
 {
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
@@ -444,12 +444,12 @@ __global__ __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(6))) void k
     for (int k = 0; k < NW; ++k) out[k] = 0.0;
     if (live) {
         switch (dir) {
-        case 0: face_term<0, NW, true>(g, d, cell, out, gam, Pi, euler); break;
-        case 1: face_term<1, NW, false>(g, d, cell, out, gam, nullptr, euler); break;
-        case 2: face_term<2, NW, false>(g, d, cell, out, gam, nullptr, euler); break;
-        case 3: face_term<3, NW, false>(g, d, cell, out, gam, nullptr, euler); break;
-        case 4: face_term<4, NW, false>(g, d, cell, out, gam, nullptr, euler); break;
-        default: face_term<5, NW, false>(g, d, cell, out, gam, nullptr, euler); break;
+        case 0: face_term<0, NW, true, EULER>(g, d, cell, out, gam, Pi); break;
+        case 1: face_term<1, NW, false, EULER>(g, d, cell, out, gam, nullptr); break;
+        case 2: face_term<2, NW, false, EULER>(g, d, cell, out, gam, nullptr); break;
+        case 3: face_term<3, NW, false, EULER>(g, d, cell, out, gam, nullptr); break;
+        case 4: face_term<4, NW, false, EULER>(g, d, cell, out, gam, nullptr); break;
+        default: face_term<5, NW, false, EULER>(g, d, cell, out, gam, nullptr); break;
         }
     }
 #pragma unroll
@@ -474,7 +474,7 @@ __global__ __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(6))) void k
             res[5] += 0.5 * g.dr * Pi[0] * (T - Pi[5]) * invtau / g.Zr;
         }
         double umag = sqrt(Pi[1] * Pi[1] + Pi[2] * Pi[2] + Pi[3] * Pi[3]);
-        double idt = (umag + Pi[8] + (euler ? 0.0 : g.Cd * Pi[9] / (Pi[0] * g.hmin))) / (g.macro_cfl * g.hmin);
+        double idt = (umag + Pi[8] + (EULER ? 0.0 : g.Cd * Pi[9] / (Pi[0] * g.hmin))) / (g.macro_cfl * g.hmin);
         D = idt + 0.5 * sumG;
         const Soa<double> r = soa(d.R, g.ncell, cell);
 #pragma unroll
@@ -619,10 +619,17 @@ hipError_t launch_gsis_macro(const Target &t, int iters, hipStream_t s, int eule
         hipLaunchKernelGGL(k_mac_fbfix, dim3(t.nblk[K_FACE8]), dim3(256), 0, s, GSIS_SPAN(t.span(K_FACE8)), euler);
     for (int it = 0; it < iters; ++it) {
         const int slot = it & 1;
-        if (t.dia)
-            hipLaunchKernelGGL(k_mac_res<true>, dim3(t.nblk[K_RES]), dim3(384), 0, s, GSIS_SPAN(t.span(K_RES)), slot, euler);
-        else
-            hipLaunchKernelGGL(k_mac_res<false>, dim3(t.nblk[K_RES]), dim3(384), 0, s, GSIS_SPAN(t.span(K_RES)), slot, euler);
+        // the Euler form is its own instantiation: a run-time flag costs the
+        // residual registers (and spills) on the common path
+        const dim3 gr(t.nblk[K_RES]), bl(384);
+        const Span sp = t.span(K_RES);
+        if (t.dia) {
+            if (euler) hipLaunchKernelGGL((k_mac_res<true, true>), gr, bl, 0, s, GSIS_SPAN(sp), slot);
+            else hipLaunchKernelGGL((k_mac_res<true, false>), gr, bl, 0, s, GSIS_SPAN(sp), slot);
+        } else {
+            if (euler) hipLaunchKernelGGL((k_mac_res<false, true>), gr, bl, 0, s, GSIS_SPAN(sp), slot);
+            else hipLaunchKernelGGL((k_mac_res<false, false>), gr, bl, 0, s, GSIS_SPAN(sp), slot);
+        }
         hipLaunchKernelGGL(k_mac_advance, dim3(t.nblk[K_GRAD]), dim3(256), 0, s, GSIS_SPAN(t.span(K_GRAD)), slot, it & 1,
                            it == iters - 1 ? 1 : 0, euler);
     }
