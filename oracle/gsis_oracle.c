@@ -27,7 +27,11 @@
  *                      equal their continuous values exactly.
  *   sweep              Sec. 3.2, backward-Euler kinetic update in delta form
  *                      with first-order upwind fluxes on both sides, solved
- *                      exactly by visiting cells in upwind order.
+ *                      exactly by visiting cells in upwind order; or (order
+ *                      2) the same first-order left-hand side with the
+ *                      right-hand side's interface values reconstructed to
+ *                      second order (least-squares gradient, Venkatakrishnan
+ *                      limiter), solved for the increment.
  *   boundary           diffuse wall (discrete half-range zero mass flux, wall
  *                      density lagged to f^n) and Maxwellian inflow.
  *   gsis_correct       Sec. 3.3, GSIS-II macroscopic equations with the
@@ -64,6 +68,11 @@ typedef struct {
     /* optional per-axis node positions (strictly increasing, nv[a] of them);
      * NULL: nv[a] uniform nodes on [vmin, vmax].  Read once, at creation. */
     const double *nodes[3];
+    /* spatial order of the explicit interface values of the kinetic update:
+     * 1 first-order upwind, 2 second-order reconstruction (Sec. 3.2); and
+     * the Venkatakrishnan constant K (eps^2 = (K h)^3; K < 0: no limiter) */
+    int order;
+    double limiter_k;
 } orc_cfg;
 
 typedef struct {
@@ -118,6 +127,8 @@ void orc_free(orc_state *s)
 static orc_state *create_state(const orc_cfg *cfg, const unsigned char *solid, int with_vdf)
 {
     if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return NULL;
+    if (cfg->order != 1 && cfg->order != 2) return NULL;
+    if (!isfinite(cfg->limiter_k)) return NULL;
     for (int a = 0; a < 3; ++a) {
         if (cfg->nv[a] < 2) return NULL;
         if (cfg->nodes[a]) {
@@ -511,6 +522,190 @@ static void sweep_node(const orc_state *s, int v, const cellpar *P, const double
     }
 }
 
+/* ------------------------------------------------ second-order values -- */
+/* Sec. 3.2: the interface values in the right-hand side of Eq.
+ * (delta_equations) come from a second-order upwind reconstruction,
+ * f_ij = f_up + phi_up grad f_up . (x_ij - x_up), with the gradient from a
+ * least-squares fit and phi the Venkatakrishnan limiter; the increments on
+ * the left-hand side stay first-order upwind.  What the paper leaves open is
+ * read as follows:
+ *  - only faces between two fluid cells are reconstructed.  A box face or a
+ *    solid surface keeps its first-order values (the cell's own value going
+ *    out, the boundary value coming in), so the zero-mass-flux wall density
+ *    is computed exactly as in the first-order scheme;
+ *  - the least-squares fit runs over the fluid face neighbours.  Their offsets
+ *    are axis-aligned, so the normal matrix is diagonal and each component is
+ *    a 1-D fit; an axis with no fluid neighbour gets a zero component (the
+ *    minimum-norm solution);
+ *  - Venkatakrishnan's limiter: phi_i is the minimum over the reconstructed
+ *    faces of psi(D, d2), with d2 = grad f_i . (x_ij - x_i) and D the largest
+ *    (d2 > 0) or smallest (d2 < 0) of f_j - f_i over the cell and its fluid
+ *    neighbours, psi = (D^2 + e2 + 2 D d2) / (D^2 + 2 d2^2 + D d2 + e2) and
+ *    psi = 1 for d2 = 0; e2 = (K h)^3 with h the cube root of the cell volume
+ *    and K = limiter_k; K < 0 leaves the reconstruction unlimited (phi = 1). */
+static void lsq_gradient(const orc_state *s, const int *nb, const double *col, int cell, double g[3])
+{
+    double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, b[3] = {0, 0, 0};
+    for (int d = 0; d < 6; ++d) {
+        int n = nb[cell * 6 + d];
+        if (n < 0) continue;
+        double off[3] = {0, 0, 0};
+        off[d / 2] = ((d & 1) ? 1.0 : -1.0) * s->h[d / 2];
+        for (int p = 0; p < 3; ++p) {
+            for (int q = 0; q < 3; ++q) A[p][q] += off[p] * off[q];
+            b[p] += off[p] * (col[n] - col[cell]);
+        }
+    }
+    for (int p = 0; p < 3; ++p) g[p] = A[p][p] > 0 ? b[p] / A[p][p] : 0.0;   /* A is diagonal */
+}
+
+static double venkatakrishnan(double D, double d2, double e2)
+{
+    if (d2 == 0.0) return 1.0;
+    return (D * D + e2 + 2.0 * D * d2) / (D * D + 2.0 * d2 * d2 + D * d2 + e2);
+}
+
+/* offset of face d from the cell centre along its axis */
+static double face_offset(const orc_state *s, int d)
+{
+    return ((d & 1) ? 0.5 : -0.5) * s->h[d / 2];
+}
+
+static double limiter(const orc_state *s, const int *nb, const double *col, int cell, const double g[3])
+{
+    double K = s->c.limiter_k;
+    if (K < 0) return 1.0;
+    double hc = cbrt(s->h[0] * s->h[1] * s->h[2]);
+    double e2 = (K * hc) * (K * hc) * (K * hc);
+    double fi = col[cell], fmax = fi, fmin = fi;
+    for (int d = 0; d < 6; ++d) {
+        int n = nb[cell * 6 + d];
+        if (n < 0) continue;
+        if (col[n] > fmax) fmax = col[n];
+        if (col[n] < fmin) fmin = col[n];
+    }
+    double phi = 1.0;
+    for (int d = 0; d < 6; ++d) {
+        if (nb[cell * 6 + d] < 0) continue;
+        double d2 = g[d / 2] * face_offset(s, d);
+        double psi = venkatakrishnan(d2 > 0 ? fmax - fi : fmin - fi, d2, e2);
+        if (psi < phi) phi = psi;
+    }
+    return phi;
+}
+
+/* Value of every fluid cell at each of its faces, fv[cell][6]: reconstructed
+ * at faces shared with a fluid cell when order = 2, the cell value otherwise. */
+static void face_values(const orc_state *s, const int *nb, const double *col, int order, double *fv)
+{
+    for (int cell = 0; cell < s->ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        double g[3] = {0, 0, 0}, phi = 0.0;
+        if (order == 2) {
+            lsq_gradient(s, nb, col, cell, g);
+            phi = limiter(s, nb, col, cell, g);
+        }
+        for (int d = 0; d < 6; ++d)
+            fv[cell * 6 + d] = col[cell] + (order == 2 && nb[cell * 6 + d] >= 0
+                                            ? phi * g[d / 2] * face_offset(s, d) : 0.0);
+    }
+}
+
+/* (1/V) sum_j xi_n f_ij S_ij of every fluid cell for node xi: the upwind face
+ * value (fv of the upwind cell, or the boundary value bv[cell][6] on a box or
+ * solid face) times the normal velocity, over the six faces. */
+static void flux_divergence(const orc_state *s, const int *nb, const double *fv, const double *bv,
+                            const double xi[3], double *div)
+{
+    for (int cell = 0; cell < s->ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        double sum = 0.0;
+        for (int d = 0; d < 6; ++d) {
+            int a = d / 2;
+            double xn = ((d & 1) ? 1.0 : -1.0) * xi[a];   /* outward normal velocity */
+            double v;
+            if (xn > 0) v = fv[cell * 6 + d];                              /* leaving: this cell */
+            else if (nb[cell * 6 + d] >= 0) v = fv[nb[cell * 6 + d] * 6 + (d ^ 1)];   /* entering: neighbour */
+            else v = bv[cell * 6 + d];                                     /* entering: boundary */
+            sum += xn * v / s->h[a];
+        }
+        div[cell] = sum;
+    }
+}
+
+/* The kinetic update of one node with the second-order right-hand side, in
+ * the delta form of Sec. 3.2:
+ *   (1/dt + 1/tau_i + sum_a a_a) Df_i - sum_{upwind fluid j} a_a Df_j = r_i,
+ *   r_i = (g_i - f_i) / tau_i - (1/V) sum_j xi_n f_ij S_ij,
+ * a_a = |xi_a| / h_a, with the increment of a boundary value zero (it is
+ * lagged to f^n); solved in upwind order, then f^{n+1/2} = f^n + Df. */
+static void sweep_node_second_order(const orc_state *s, int v, const cellpar *P, const double *scale, const int *nb,
+                                    double *col0, double *col1)
+{
+    const orc_cfg *c = &s->c;
+    int dia = c->species == 1, ncell = s->ncell;
+    int nx = c->nx, ny = c->ny, nz = c->nz;
+    double xi[3], w;
+    node_xi(s, v, xi, &w);
+    double *fv = malloc(sizeof(double) * (size_t)ncell * 6);
+    double *bv = malloc(sizeof(double) * (size_t)ncell * 6);
+    double *bv1 = malloc(sizeof(double) * (size_t)ncell * 6);
+    double *r[2], *df[2];
+    for (int q = 0; q < 2; ++q) { r[q] = calloc((size_t)ncell, sizeof(double)); df[q] = calloc((size_t)ncell, sizeof(double)); }
+    for (int cell = 0; cell < ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        for (int d = 0; d < 6; ++d) {
+            int n = nb[cell * 6 + d];
+            bv[cell * 6 + d] = bv1[cell * 6 + d] = 0.0;
+            if (n < 0) boundary_value(c, -1 - n, scale[cell * 6 + d], xi, &bv[cell * 6 + d], &bv1[cell * 6 + d]);
+        }
+    }
+    for (int q = 0; q < 1 + dia; ++q) {
+        double *col = q ? col1 : col0;
+        face_values(s, nb, col, 2, fv);
+        flux_divergence(s, nb, fv, q ? bv1 : bv, xi, r[q]);
+        for (int cell = 0; cell < ncell; ++cell) {
+            if (s->solid[cell]) continue;
+            double g0, g1;
+            ref_dist(c, &P[cell], xi, &g0, &g1);
+            r[q][cell] = ((q ? g1 : g0) - col[cell]) * P[cell].invtau - r[q][cell];
+        }
+    }
+    int sg[3];
+    double aa[3];
+    for (int a = 0; a < 3; ++a) { sg[a] = xi[a] >= 0 ? 1 : -1; aa[a] = fabs(xi[a]) / s->h[a]; }
+    for (int kk = 0; kk < nz; ++kk) {
+        int k = sg[2] > 0 ? kk : nz - 1 - kk;
+        for (int jj = 0; jj < ny; ++jj) {
+            int j = sg[1] > 0 ? jj : ny - 1 - jj;
+            for (int ii = 0; ii < nx; ++ii) {
+                int i = sg[0] > 0 ? ii : nx - 1 - ii;
+                int cell = cell_index(s, i, j, k);
+                if (s->solid[cell]) continue;
+                double den = c->inv_dt + P[cell].invtau;
+                double num[2] = {r[0][cell], r[1][cell]};
+                for (int a = 0; a < 3; ++a) {
+                    if (aa[a] == 0.0) continue;
+                    den += aa[a];
+                    int n = nb[cell * 6 + 2 * a + (sg[a] > 0 ? 0 : 1)];
+                    if (n < 0) continue;
+                    num[0] += aa[a] * df[0][n];
+                    num[1] += aa[a] * df[1][n];
+                }
+                df[0][cell] = num[0] / den;
+                df[1][cell] = num[1] / den;
+            }
+        }
+    }
+    for (int cell = 0; cell < ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        col0[cell] += df[0][cell];
+        if (dia) col1[cell] += df[1][cell];
+    }
+    free(fv); free(bv); free(bv1);
+    for (int q = 0; q < 2; ++q) { free(r[q]); free(df[q]); }
+}
+
 /* One kinetic pass: per-cell parameters and boundary densities from f^n,
  * then every node swept independently (the wall density is lagged), in place. */
 static int one_pass(orc_state *s)
@@ -544,7 +739,8 @@ static int one_pass(orc_state *s)
                 col0[cell] = s->f0[(size_t)cell * nv + v];
                 if (dia) col1[cell] = s->f1[(size_t)cell * nv + v];
             }
-            sweep_node(s, v, P, scale, nb, col0, col1);
+            if (c->order == 2) sweep_node_second_order(s, v, P, scale, nb, col0, col1);
+            else sweep_node(s, v, P, scale, nb, col0, col1);
             for (int cell = 0; cell < ncell; ++cell) {
                 if (s->solid[cell]) continue;
                 s->f0[(size_t)cell * nv + v] = col0[cell];
@@ -743,6 +939,56 @@ int orc_boundary_values(const orc_state *s, int cell, int d, double *b0, double 
         if (b1) b1[v] = incoming ? x1 : 0.0;
     }
     return bc;
+}
+
+/* The column of VDF `which` (0: f0, 1: f1) at canonical node v, the
+ * neighbour table and the boundary values of every face, for the pins of
+ * the second-order values. */
+static void node_column(const orc_state *s, int v, int which, double *col, int *nb, double *bv)
+{
+    const double *f = which ? s->f1 : s->f0;
+    double xi[3], w;
+    node_xi(s, v, xi, &w);
+    for (int cell = 0; cell < s->ncell; ++cell) {
+        col[cell] = s->solid[cell] ? 0.0 : f[(size_t)cell * s->nv + v];
+        for (int d = 0; d < 6; ++d) {
+            int n = s->solid[cell] ? -1 : neighbour(s, cell, d);
+            nb[cell * 6 + d] = n;
+            double b0 = 0.0, b1 = 0.0;
+            if (n < 0 && !s->solid[cell]) boundary_value(&s->c, -1 - n, face_scale(s, cell, d, -1 - n), xi, &b0, &b1);
+            bv[cell * 6 + d] = which ? b1 : b0;
+        }
+    }
+}
+
+/* Face values fv[cell][6] of node v (order 1: the cell value; order 2: the
+ * limited reconstruction on faces between fluid cells); NaN in solid cells. */
+void orc_face_values(const orc_state *s, int v, int which, int order, double *fv)
+{
+    int ncell = s->ncell;
+    double *col = malloc(sizeof(double) * ncell), *bv = malloc(sizeof(double) * ncell * 6);
+    int *nb = malloc(sizeof(int) * ncell * 6);
+    node_column(s, v, which, col, nb, bv);
+    for (int k = 0; k < ncell * 6; ++k) fv[k] = NAN;
+    face_values(s, nb, col, order, fv);
+    free(col); free(bv); free(nb);
+}
+
+/* (1/V) sum_j xi_n f_ij S_ij of node v in every fluid cell with face values
+ * of the given order and the current boundary values; NaN in solid cells. */
+void orc_flux_divergence(const orc_state *s, int v, int which, int order, double *div)
+{
+    int ncell = s->ncell;
+    double *col = malloc(sizeof(double) * ncell), *bv = malloc(sizeof(double) * ncell * 6);
+    double *fv = malloc(sizeof(double) * ncell * 6);
+    int *nb = malloc(sizeof(int) * ncell * 6);
+    double xi[3], w;
+    node_xi(s, v, xi, &w);
+    node_column(s, v, which, col, nb, bv);
+    for (int k = 0; k < ncell; ++k) div[k] = NAN;
+    face_values(s, nb, col, order, fv);
+    flux_divergence(s, nb, fv, bv, xi, div);
+    free(col); free(bv); free(fv); free(nb);
 }
 
 /* The four uncorrected reference components (g0t, g0r, g1t, g1r) at n

@@ -36,6 +36,7 @@ class _Cfg(C.Structure):
         ("bc_kind", C.c_int * 7), ("bc_u", (C.c_double * 3) * 7), ("bc_T", C.c_double * 7),
         ("bc_rho", C.c_double * 7),
         ("nodes", C.POINTER(C.c_double) * 3),
+        ("order", C.c_int), ("limiter_k", C.c_double),
     ]
 
 
@@ -68,6 +69,8 @@ def lib():
         L.orc_invtau.argtypes = [P, C.c_int]
         L.orc_invtau.restype = C.c_double
         L.orc_boundary_values.argtypes = [P, C.c_int, C.c_int, D, D]
+        L.orc_face_values.argtypes = [P, C.c_int, C.c_int, C.c_int, D]
+        L.orc_flux_divergence.argtypes = [P, C.c_int, C.c_int, C.c_int, D]
         L.orc_total_mass.argtypes = [P]
         L.orc_total_mass.restype = C.c_double
         L.orc_ref_components.argtypes = [C.POINTER(_Cfg), C.c_double, D, C.c_double, C.c_double, D, D,
@@ -101,6 +104,8 @@ def make_cfg(case) -> _Cfg:
     c.inv_dt = case.inv_dt
     c.conservative = case.conservative
     c.macro_cfl = case.macro_cfl
+    c.order = case.order
+    c.limiter_k = case.limiter_k
     for b, bc in enumerate(case.bcs):
         c.bc_kind[b] = bc.kind
         for a in range(3):
@@ -198,6 +203,19 @@ class Oracle:
 
     def total_mass(self) -> float:
         return lib().orc_total_mass(self.h)
+
+    def face_values(self, v: int, which: int = 0, order: int = 2) -> np.ndarray:
+        """[cell][6] value of canonical node v at each face of each cell
+        (order 2: the limited reconstruction on faces between fluid cells)."""
+        out = np.empty((self.ncell, 6))
+        lib().orc_face_values(self.h, v, which, order, _dp(out))
+        return out
+
+    def flux_divergence(self, v: int, which: int = 0, order: int = 2) -> np.ndarray:
+        """[cell] (1/V) sum_j xi_n f_ij S_ij of canonical node v."""
+        out = np.empty(self.ncell)
+        lib().orc_flux_divergence(self.h, v, which, order, _dp(out))
+        return out
 
 
 def ref_components(case, rho, u, Tt, Tr, qt, qr, xi: np.ndarray) -> np.ndarray:

@@ -67,6 +67,11 @@ class Case:
     inv_dt: float = 0.0
     conservative: int = 1
     macro_cfl: float = 10.0
+    # spatial order of the explicit interface values of the kinetic update
+    # (1 first-order upwind; 2 least-squares reconstruction with the
+    # Venkatakrishnan limiter, eps^2 = (limiter_k h)^3, limiter_k < 0: none)
+    order: int = 1
+    limiter_k: float = 1.0
     bcs: List[Boundary] = dataclasses.field(default_factory=lambda: [Boundary() for _ in range(7)])
     solid: Optional[np.ndarray] = None
     init: Tuple[float, Tuple[float, float, float], float, float] = (1.0, (0.0, 0.0, 0.0), 1.0, 1.0)
