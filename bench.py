@@ -39,6 +39,9 @@ def parse():
     p.add_argument("--precondition", default="1000,10",
                    help="macro_steps,kinetic_steps of the initial field (Alg. 1) for an extra time-to-convergence "
                         "run; 'none' skips it")
+    p.add_argument("--second-order", default="0",
+                   help="Venkatakrishnan K of the extra second-order-RHS runs (c2: step and convergence), "
+                        "'none' to skip them, a negative K for no limiter")
     p.add_argument("--stretch", type=float, default=0.0,
                    help="non-uniform velocity grid: the same node counts clustered at the origin by a sinh map "
                         "of this strength (0: the workload's uniform grid)")
@@ -135,6 +138,38 @@ def converge(case, dtype, tile, tol=1e-6, max_iters=200, pre=None):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return {"iterations": it, "seconds": dt, "eps": [float(x) for x in eps]}, s.moments()
+
+
+def second_order(case, k, steps, warmup, macro, out, converge_too=True):
+    """The same step with the second-order right-hand side (Sec. 3.2), FP64 and
+    FP32, on the tiles the first-order runs chose; the reconstruction's
+    algorithmic bytes per pass: the limiter reads f and writes phi, the source
+    reads f and phi and writes the sweep's per-point term (5 elements per
+    point and VDF); the sweep then reads that term and writes f."""
+    import dataclasses
+    c2 = dataclasses.replace(case, order=2, limiter_k=k)
+    pts = c2.nfluid * c2.nvel
+    nvdf = 2 if c2.species == 1 else 1
+    res = {"limiter_k": k}
+    for dt in ("fp64", "fp32"):
+        tile = out["sweep_tile"] if dt == "fp64" else out.get("fp32", {}).get("sweep_tile", out["sweep_tile"])
+        r = run_gpu(c2, dt, steps, warmup, macro, tuple(tile))
+        prof = r["prof"]
+        esz = 8 if dt == "fp64" else 4
+        rec_ms, rec_n = prof["recon"]
+        sw_ms, sw_n = prof["sweep"]
+        res[dt] = {"value": pts * steps / r["seconds"], "ms_per_step": r["seconds"] / steps * 1e3,
+                   "sweep_tile": r["tile"], "phases_ms_per_step": {kk: v[0] / steps for kk, v in prof.items()},
+                   "recon_gbs": pts * nvdf * esz * 5 / (rec_ms / rec_n * 1e-3) / 1e9,
+                   "sweep_gbs": pts * nvdf * esz * 2 / (sw_ms / sw_n * 1e-3) / 1e9}
+        del r
+    if converge_too and case.gsis:
+        c1st, m1st = converge(case, "fp64", out["sweep_tile"])
+        c2nd, m2nd = converge(c2, "fp64", out["sweep_tile"])
+        res["converged_fp64"] = c2nd
+        res["converged_fp64_first_order"] = c1st
+        res["second_vs_first_order_max_rel_diff"] = field_diff(m2nd, m1st)
+    return res
 
 
 def field_diff(a, b):
@@ -354,6 +389,9 @@ def main():
                       "sweep_tile": ro["tile"], "phases_ms_per_step": {k: v[0] / steps for k, v in ro["prof"].items()},
                       "autotune_top": [[list(c), round(ms, 4)] for c, ms in (ro["tune"] or [])[:6]]}
         del ro
+    if a.second_order != "none" and a.workload == "c2":
+        out["second_order"] = second_order(case, float(a.second_order), steps, a.warmup, macro, out,
+                                           converge_too=not a.no_converge)
     if not a.no_converge and case.gsis and dtype == "fp64":
         c64, m64 = converge(case, "fp64", out["sweep_tile"])
         c32, m32 = converge(case, "fp32", out["fp32"]["sweep_tile"] if "fp32" in out else out["sweep_tile"])

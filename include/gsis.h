@@ -83,6 +83,16 @@ typedef struct {
     int conservative;          /* 1: reference distribution corrected to conserve the
                                   discrete mass, momentum and energy exactly */
     double macro_cfl;          /* pseudo-time CFL of the macroscopic iteration (e.g. 10) */
+    int order;                 /* interface values of the explicit flux divergence of the
+                                  kinetic update (Sec. 3.2): 0 or 1 first-order upwind; 2
+                                  reconstructed to second order from the upwind cell with a
+                                  least-squares gradient and the Venkatakrishnan limiter
+                                  (faces on the box or a solid stay first order); the
+                                  implicit increments stay first-order upwind either way.
+                                  Order 2 adds two VDF-sized buffers (four diatomic) to the
+                                  workspace and is not accepted by gsis_batch_create */
+    double limiter_k;          /* order 2: Venkatakrishnan constant K, eps^2 = (K h)^3 with h
+                                  the cube root of the cell volume; K < 0: no limiter */
 } gsis_config;
 
 /* Create a context for cfg.  Validates sizes (n >= 1, nv >= 2, vmax > vmin,
@@ -188,8 +198,9 @@ gsis_status gsis_get_tile(const gsis_ctx *ctx, int *tile);
  * under every compiled (tx, ty) tile shape, tile depths tz in {tx/2, tx, 2 tx}
  * and blocks of 128 and 256 threads, timed with HIP events; selects the
  * fastest configuration for the context.  Valid because every configuration
- * gives a bitwise-identical sweep; requires source iteration (inv_dt = 0),
- * where the sweep does not read f^n.  Writes up to max entries of
+ * gives a bitwise-identical sweep; requires source iteration (inv_dt = 0)
+ * and order 1, where the sweep does not read f^n (an order-2 context takes
+ * the tile found for its first-order twin through gsis_set_tile).  Writes up to max entries of
  * (tx, ty, tz, block) to cfg_out[4*k] and their mean sweep time in ms to
  * ms_out[k], and the number of entries to *count (any output may be NULL).
  * Synchronises. */
@@ -210,7 +221,8 @@ enum { GSIS_PHASE_PREP = 0,      /* per-cell parameters and boundary densities *
        GSIS_PHASE_MOMENTS = 2,   /* moment reduction and central moments */
        GSIS_PHASE_MACRO = 3,     /* gsis_correct: macroscopic solve and moment update */
        GSIS_PHASE_RESIDUAL = 4,  /* gsis_residual */
-       GSIS_NPHASE = 5 };
+       GSIS_PHASE_RECON = 5,     /* order 2: limiter and second-order right-hand side of a pass */
+       GSIS_NPHASE = 6 };
 /* enable != 0 starts recording (events are created on first use and kept by the
  * context); 0 stops. */
 gsis_status gsis_profile_enable(gsis_ctx *ctx, int enable);
@@ -235,14 +247,14 @@ const char *gsis_last_error(const gsis_ctx *ctx);
  * The cases are contexts made with gsis_create and configured as usual (mask,
  * boundaries) but NOT bound: the batch binds them all inside one caller-owned
  * workspace.  They must share vdf_dtype and species and use inv_dt = 0
- * (source iteration).  The batch borrows the contexts: destroy it before
+ * (source iteration) and order 1.  The batch borrows the contexts: destroy it before
  * them, and do not bind them elsewhere.  Once bound, each context also works
  * on its own (gsis_moments, gsis_get_vdf, gsis_residual, ...) on the batch's
  * stream.  One tile shape (tx, ty, tz, block) serves every case. */
 typedef struct gsis_batch gsis_batch;
 
 /* ncases in 1..4096 distinct, unbound contexts (host array).  EINVAL if they
- * differ in precision or gas, or have inv_dt != 0. */
+ * differ in precision or gas, or have inv_dt != 0 or order 2. */
 gsis_status gsis_batch_create(gsis_batch **out, gsis_ctx *const *cases, int ncases);
 gsis_status gsis_batch_destroy(gsis_batch *b);
 /* Bytes of device memory the batch needs (all cases plus launch tables and

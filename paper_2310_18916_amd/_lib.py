@@ -11,7 +11,7 @@ GSIS_OK = 0
 STATUS = {0: "GSIS_OK", -1: "GSIS_EINVAL", -2: "GSIS_ESTATE", -3: "GSIS_ENOMEM", -4: "GSIS_EDEVICE",
           -5: "GSIS_ENOTFINITE", -6: "GSIS_EDIVERGED"}
 NMOM = {0: 14, 1: 18}
-PHASES = ("prep", "sweep", "moments", "macro", "residual")
+PHASES = ("prep", "sweep", "moments", "macro", "residual", "recon")
 
 
 class Config(C.Structure):
@@ -23,7 +23,7 @@ class Config(C.Structure):
         ("species", C.c_int), ("Kn", C.c_double), ("omega", C.c_double),
         ("dr", C.c_double), ("Zr", C.c_double), ("A", C.c_double * 4),
         ("inv_dt", C.c_double), ("vdf_dtype", C.c_int), ("conservative", C.c_int),
-        ("macro_cfl", C.c_double),
+        ("macro_cfl", C.c_double), ("order", C.c_int), ("limiter_k", C.c_double),
     ]
 
 

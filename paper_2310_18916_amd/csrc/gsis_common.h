@@ -33,6 +33,12 @@ struct Geo {
     int species;
     double delta, omega, dr, Zr, A[4];
     double inv_dt;
+    // explicit interface values of the kinetic update: order 1 (upwind) or 2
+    // (limited least-squares reconstruction); Venkatakrishnan eps^2 and
+    // whether the limiter is on
+    int order, limited;
+    double venk_e2;
+    double rs_scale;   // factor of the sweep's per-point term: inv_dt (order 1) or 1 (order 2)
     int conservative;
     double macro_cfl;
     int nface, nfluid;
@@ -55,6 +61,11 @@ constexpr int DSLOT = 64, DSTRIDE = 16;
 
 struct Dev {
     void *f0, *f1;     // [ncell + 1][nv]: row ncell is the sink of the sweep's stores for dead cells
+    // per-point term of the sweep's right-hand side, [ncell + 1][nv]: f0/f1
+    // themselves (order 1, times inv_dt), or ho0/ho1 (order 2)
+    void *rs0, *rs1;
+    void *ho0, *ho1;   // order 2: inv_dt f^n - (second-order - first-order flux divergence), [ncell + 1][nv]
+    void *lim0, *lim1; // order 2: Venkatakrishnan limiter per point, [ncell][nv]
     double *mom8;      // [ncell][8][NRS]
     double *cm;        // [ncell][NMOM]
     double *par;       // [ncell][NPAR]

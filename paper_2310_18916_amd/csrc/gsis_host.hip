@@ -190,6 +190,20 @@ size_t layout(gsis_ctx *c, char *base)
     if (g.species == 1) carve(off, f1, (n + 1) * nv * esz, base);
     d.f0 = f0;
     d.f1 = f1;
+    d.rs0 = f0;
+    d.rs1 = f1;
+    d.ho0 = d.ho1 = d.lim0 = d.lim1 = nullptr;
+    if (g.order == 2) {
+        char *h0 = nullptr, *h1 = nullptr, *l0 = nullptr, *l1 = nullptr;
+        carve(off, h0, (n + 1) * nv * esz, base);
+        carve(off, l0, n * nv * esz, base);
+        if (g.species == 1) {
+            carve(off, h1, (n + 1) * nv * esz, base);
+            carve(off, l1, n * nv * esz, base);
+        }
+        d.ho0 = h0; d.ho1 = h1; d.lim0 = l0; d.lim1 = l1;
+        d.rs0 = h0; d.rs1 = h1;
+    }
     carve(off, d.mom8, n * 8 * NRS, base);
     carve(off, d.cm, n * NMOM, base);
     carve(off, d.par, n * NPAR, base);
@@ -257,7 +271,7 @@ Target target_of(const gsis_ctx *c)
     t.fp32 = c->fp32;
     t.dia = c->g.species == GSIS_DIATOMIC;
     t.mask = c->g.nfluid != c->g.ncell;
-    t.rfn = c->g.inv_dt != 0.0;
+    t.rfn = c->g.inv_dt != 0.0 || c->g.order == 2;
     t.mom_nblk[vw_class(c->vw)] = c->g.ncell;
     t.tx = c->tx;
     t.ty = c->ty;
@@ -420,6 +434,7 @@ gsis_status gsis_create(gsis_ctx **out, const gsis_config *cfg)
     if (c.vdf_dtype != GSIS_FP64 && c.vdf_dtype != GSIS_FP32) return GSIS_EINVAL;
     if (c.conservative != 0 && c.conservative != 1) return GSIS_EINVAL;
     if (!(c.macro_cfl > 0) || !std::isfinite(c.macro_cfl)) return GSIS_EINVAL;
+    if (c.order < 0 || c.order > 2 || !std::isfinite(c.limiter_k)) return GSIS_EINVAL;
 
     gsis_ctx *x = new (std::nothrow) gsis_ctx();
     if (!x) return GSIS_ENOMEM;
@@ -452,6 +467,13 @@ gsis_status gsis_create(gsis_ctx **out, const gsis_config *cfg)
     g.Zr = c.species == GSIS_DIATOMIC ? c.Zr : 1.0;
     for (int k = 0; k < 4; ++k) g.A[k] = c.A[k];
     g.inv_dt = c.inv_dt;
+    g.order = c.order == 2 ? 2 : 1;
+    g.limited = c.limiter_k >= 0;
+    {
+        const double kh = g.limited ? c.limiter_k * std::cbrt(g.h[0] * g.h[1] * g.h[2]) : 0.0;
+        g.venk_e2 = kh * kh * kh;
+    }
+    g.rs_scale = g.order == 2 ? 1.0 : c.inv_dt;
     g.conservative = c.conservative;
     g.macro_cfl = c.macro_cfl;
     if (c.species == GSIS_DIATOMIC) {
@@ -643,15 +665,20 @@ gsis_status gsis_kinetic_step(gsis_ctx *ctx, int npasses)
     const Geo &g = ctx->g;
     const Target t = target_of(ctx);
     for (int n = 0; n < npasses; ++n) {
-        if (g.inv_dt != 0.0) {
+        if (g.inv_dt != 0.0 || g.order == 2) {   // the pass reads f^n pointwise
             gsis_status st = materialize(ctx);
             if (st) return st;
         }
-        PhaseTimer t0, t1, t2;
+        PhaseTimer t0, t1, t2, t3;
         HIPCHK(ctx, t0.start(ctx, GSIS_PHASE_PREP));
         HIPCHK(ctx, launch_params(t, ctx->stream));
         HIPCHK(ctx, launch_face_scale(t, ctx->stream));
         HIPCHK(ctx, t0.stop());
+        if (g.order == 2) {
+            HIPCHK(ctx, t3.start(ctx, GSIS_PHASE_RECON));
+            HIPCHK(ctx, launch_recon(g, ctx->d, ctx->fp32, ctx->stream));
+            HIPCHK(ctx, t3.stop());
+        }
         HIPCHK(ctx, t1.start(ctx, GSIS_PHASE_SWEEP));
         HIPCHK(ctx, launch_sweep(t, ctx->stream));
         HIPCHK(ctx, t1.stop());
@@ -882,7 +909,8 @@ gsis_status gsis_autotune(gsis_ctx *ctx, int reps, int *cfg_out, double *ms_out,
     if (!ctx) return GSIS_EINVAL;
     if (!ctx->inited) return fail(ctx, GSIS_ESTATE, "initialise the VDF first");
     if (reps < 1 || max < 0) return fail(ctx, GSIS_EINVAL, "reps must be >= 1");
-    if (ctx->g.inv_dt != 0.0) return fail(ctx, GSIS_EINVAL, "autotune needs source iteration (inv_dt = 0)");
+    if (ctx->g.inv_dt != 0.0 || ctx->g.order != 1)
+        return fail(ctx, GSIS_EINVAL, "autotune needs the first-order source iteration (inv_dt = 0, order 1)");
     const Geo &g = ctx->g;
     bool dia = g.species == GSIS_DIATOMIC;
     int shapes[32];
@@ -1275,7 +1303,7 @@ gsis_status gsis_batch_create(gsis_batch **out, gsis_ctx *const *cases, int ncas
         for (int j = 0; j < i; ++j)
             if (cases[j] == c) return GSIS_EINVAL;
         if (c->fp32 != cases[0]->fp32 || c->g.species != cases[0]->g.species) return GSIS_EINVAL;
-        if (c->g.inv_dt != 0.0) return GSIS_EINVAL;
+        if (c->g.inv_dt != 0.0 || c->g.order != 1) return GSIS_EINVAL;
     }
     gsis_batch *b = new (std::nothrow) gsis_batch();
     if (!b) return GSIS_ENOMEM;

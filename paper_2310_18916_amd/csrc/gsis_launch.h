@@ -35,6 +35,8 @@ hipError_t launch_to_canonical(const Geo &g, const Dev &d, bool fp32, const void
 hipError_t launch_from_canonical(const Geo &g, const Dev &d, bool fp32, const double *src, void *dst, hipStream_t s);
 hipError_t launch_vdf_node(const Geo &g, const Dev &d, bool fp32, int node, double *out, hipStream_t s);
 hipError_t launch_apply_correction(const Geo &g, const Dev &d, bool fp32, hipStream_t s);
+// order 2: limiter, then inv_dt f^n - (D2 - D1) into d.ho0/ho1, from the stored f^n
+hipError_t launch_recon(const Geo &g, const Dev &d, bool fp32, hipStream_t s);
 
 hipError_t launch_moments(const Target &t, hipStream_t s);
 hipError_t launch_derive(const Target &t, hipStream_t s);

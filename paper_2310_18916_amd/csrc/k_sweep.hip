@@ -168,6 +168,9 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
     const T den0 = idt + ax + ay + az;
     const gptr<T> f0 = (gptr<T>)C.d.f0;
     const gptr<T> f1 = (gptr<T>)C.d.f1;
+    const gptr<const T> rs0 = (gptr<const T>)C.d.rs0;   // per-point term (RFN)
+    const gptr<const T> rs1 = (gptr<const T>)C.d.rs1;
+    const T rsc = (T)g.rs_scale;
     const gptr<const T> par = F32 ? (gptr<const T>)C.d.parf : (gptr<const T>)C.d.par;
     const gptr<const T> fsc = F32 ? (gptr<const T>)C.d.cfs32 : (gptr<const T>)C.d.cfs64;   // [ncell][6] incoming density scale
     const gptr<const T> mb = F32 ? (gptr<const T>)C.d.mb32 : (gptr<const T>)C.d.mb64;
@@ -365,8 +368,8 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
                     }
                     T num0 = gt0, num1 = gt1;
                     if (RFN) {
-                        num0 = fma(idt, (T)c0[lnode], num0);
-                        if (DIA) num1 = fma(idt, (T)c1[lnode], num1);
+                        num0 = fma(rsc, (T)rs0[(size_t)row * nv + lnode], num0);
+                        if (DIA) num1 = fma(rsc, (T)rs1[(size_t)row * nv + lnode], num1);
                     }
                     T F0, F1 = T(0);
                     if (kx == 0) { F0 = xin0[ky]; if (DIA) F1 = xin1[ky]; }

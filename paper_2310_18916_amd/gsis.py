@@ -38,6 +38,8 @@ def make_config(case: Case, dtype: str = "fp64") -> _lib.Config:
     c.vdf_dtype = {"fp64": 0, "fp32": 1}[dtype]
     c.conservative = case.conservative
     c.macro_cfl = case.macro_cfl
+    c.order = case.order
+    c.limiter_k = case.limiter_k
     return c
 
 
@@ -276,7 +278,7 @@ class Batch:
         h = C.c_void_p()
         st = self.L.gsis_batch_create(C.byref(h), arr, len(self.ctxs))
         if st:
-            raise GsisError(st, "gsis_batch_create", "cases must share precision and gas and use inv_dt = 0")
+            raise GsisError(st, "gsis_batch_create", "cases must share precision and gas and use inv_dt = 0 and order 1")
         self.h = h
         self.stream = torch.cuda.Stream()
         self._check(self.L.gsis_batch_set_stream(self.h, C.c_void_p(self.stream.cuda_stream)), "gsis_batch_set_stream")

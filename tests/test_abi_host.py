@@ -48,6 +48,7 @@ def _create(cfg):
 @pytest.mark.parametrize("field,value", [
     ("nx", 0), ("nvy", 1), ("Kn", 0.0), ("Kn", -1.0), ("lx", 0.0), ("species", 2), ("vdf_dtype", 3),
     ("conservative", 2), ("inv_dt", -1.0), ("macro_cfl", 0.0), ("nz", 5000),
+    ("order", 3), ("order", -1), ("limiter_k", float("nan")), ("limiter_k", float("inf")),
 ])
 def test_create_rejects_bad_config(field, value):
     st, h = _create(_cfg(**{field: value}))
@@ -114,6 +115,19 @@ def test_workspace_grows_with_precision_and_species():
     assert dia - mono >= case.ncell * case.nvel * 4
 
 
+def test_second_order_adds_two_vdf_buffers():
+    """Order 2 keeps the sweep's per-point term (one row more: the sink of
+    dead cells) and the limiter of every point: two VDF-sized buffers per VDF."""
+    import dataclasses
+    for dt, esz in (("fp32", 4), ("fp64", 8)):
+        for case in (I.cavity(6, 8, 0.1), I.small_block(species=I.DIATOMIC, m=6)):
+            one = G.Context(case, dt).workspace_size()
+            two = G.Context(dataclasses.replace(case, order=2), dt).workspace_size()
+            nvdf = 2 if case.species == I.DIATOMIC else 1
+            want = nvdf * (2 * case.ncell + 1) * case.nvel * esz
+            assert want <= two - one <= want + 4 * 256, (dt, case.name)
+
+
 def test_tile_shapes_and_set_tile_validation():
     shapes = G.tile_shapes()
     assert (8, 8, 32) in shapes and (4, 4, 64) in shapes
@@ -160,6 +174,9 @@ def test_batch_create_rejects_mixed_or_invalid_cases():
     assert _batch([a, c64])[0] == -1          # precision differs
     assert _batch([a, dia])[0] == -1          # gas differs
     assert _batch([a, fin])[0] == -1          # finite pseudo time step
+    import dataclasses
+    ho = G.Context(dataclasses.replace(I.cavity(4, 6, 0.1), order=2), "fp32")
+    assert _batch([a, ho])[0] == -1           # second-order right-hand side
     assert _batch([a, a])[0] == -1            # a case twice
     h = C.c_void_p()
     assert L.gsis_batch_create(C.byref(h), None, 1) == -1
