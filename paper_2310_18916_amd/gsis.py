@@ -215,8 +215,8 @@ class Solver(Context):
 
     def profile_read(self, reset: bool = True):
         """{phase: (milliseconds, calls)} measured with HIP events on the bound stream."""
-        ms = (C.c_double * 5)()
-        calls = (C.c_longlong * 5)()
+        ms = (C.c_double * len(_lib.PHASES))()
+        calls = (C.c_longlong * len(_lib.PHASES))()
         self._check(self.L.gsis_profile_read(self.h, ms, calls, int(reset)), "gsis_profile_read")
         return {name: (ms[k], calls[k]) for k, name in enumerate(_lib.PHASES)}
 

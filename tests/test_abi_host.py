@@ -32,6 +32,16 @@ def test_exports_every_declared_symbol():
     assert sorted(_lib.SIGNATURES) == names
 
 
+def test_phase_names_match_header():
+    """gsis_profile_read fills GSIS_NPHASE entries: the binding's phase list
+    (which sizes its arrays) has exactly that many, in the header's order."""
+    text = open(os.path.join(ROOT, "include", "gsis.h")).read()
+    n = int(re.search(r"GSIS_NPHASE\s*=\s*(\d+)", text).group(1))
+    assert len(_lib.PHASES) == n
+    for k, name in enumerate(_lib.PHASES):
+        assert re.search(rf"GSIS_PHASE_{name.upper()}\s*=\s*{k}\b", text), name
+
+
 def _cfg(**kw):
     c = G.make_config(I.cavity(4, 6, 0.1))
     for k, v in kw.items():
