@@ -45,6 +45,38 @@ __device__ __forceinline__ ReconBlock recon_block(const Geo &g, int nvb)
     return r;
 }
 
+// The face neighbours of a cell from its coordinates: index (the cell itself
+// where there is none, so every load stays in range and none waits for a
+// table) and whether it is a fluid cell; and, per axis, the second cell on
+// the upwind side of octant o (the upwind neighbour's own upwind neighbour).
+struct Around {
+    int nb[6];
+    bool has[6];
+    int uu[3];
+    bool huu[3];
+};
+
+__device__ __forceinline__ Around around(const Geo &g, const gptr<const int> &cflag, int cell, int o)
+{
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int i = cell % nx, j = (cell / nx) % ny, k = cell / (nx * ny);
+    const int co[3] = {i, j, k}, n[3] = {nx, ny, nz}, step[3] = {1, nx, nx * ny};
+    Around a;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const bool lo = co[ax] > 0, hi = co[ax] < n[ax] - 1;
+        a.nb[2 * ax] = lo ? cell - step[ax] : cell;
+        a.nb[2 * ax + 1] = hi ? cell + step[ax] : cell;
+        a.has[2 * ax] = lo && cflag[a.nb[2 * ax]];
+        a.has[2 * ax + 1] = hi && cflag[a.nb[2 * ax + 1]];
+        const int s = (o >> ax) & 1;   // 1: xi < 0, the upwind side is +
+        const bool in2 = s ? co[ax] < n[ax] - 2 : co[ax] > 1;
+        a.uu[ax] = in2 ? (s ? cell + 2 * step[ax] : cell - 2 * step[ax]) : cell;
+        a.huu[ax] = in2 && (s ? a.has[2 * ax + 1] : a.has[2 * ax]) && cflag[a.uu[ax]];
+    }
+    return a;
+}
+
 // psi of Venkatakrishnan's limiter for a face: d2 = grad f . (x_face - x_c),
 // D = (max or min of the neighbourhood) - f_c on the side of d2
 template <typename T>
@@ -74,21 +106,22 @@ __global__ __launch_bounds__(RB) void k_recon_limiter(Geo g, Dev d, int nvb)
     const size_t nv = (size_t)g.nv, node = (size_t)g.obase[rb.o] + rb.l;
     const int ncell = g.ncell;
     const T e2 = (T)g.venk_e2;
-    const gptr<const int> nbr = (gptr<const int>)d.nbr;
     const gptr<const int> cflag = (gptr<const int>)d.cflag;
-    for (int r = 0; r < RCELLS; ++r) {
-        const int cell = rb.cell0 + r;
-        if (cell >= ncell || !cflag[cell]) continue;   // uniform over the block
-        int nb[6];
 #pragma unroll
-        for (int dir = 0; dir < 6; ++dir) nb[dir] = nbr[(size_t)dir * ncell + cell];
+    for (int r = 0; r < RCELLS; ++r) {
+        const int cell = min(rb.cell0 + r, ncell - 1);   // loads stay in range; the store is skipped
+        const bool store = rb.cell0 + r < ncell && cflag[cell];
+        const Around A = around(g, cflag, cell, rb.o);
 #pragma unroll
         for (int q = 0; q < (DIA ? 2 : 1); ++q) {
             const gptr<const T> f = (gptr<const T>)(q ? d.f1 : d.f0);
             const T fc = f[(size_t)cell * nv + node];
             T fn[6];
 #pragma unroll
-            for (int dir = 0; dir < 6; ++dir) fn[dir] = nb[dir] >= 0 ? f[(size_t)nb[dir] * nv + node] : fc;
+            for (int dir = 0; dir < 6; ++dir) {
+                const T v = f[(size_t)A.nb[dir] * nv + node];
+                fn[dir] = A.has[dir] ? v : fc;
+            }
             T phi = T(1);
             if (g.limited) {
                 T mx = fc, mn = fc;
@@ -96,7 +129,7 @@ __global__ __launch_bounds__(RB) void k_recon_limiter(Geo g, Dev d, int nvb)
                 for (int dir = 0; dir < 6; ++dir) { mx = fmax(mx, fn[dir]); mn = fmin(mn, fn[dir]); }
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const bool hm = nb[2 * a] >= 0, hp = nb[2 * a + 1] >= 0;
+                    const bool hm = A.has[2 * a], hp = A.has[2 * a + 1];
                     const T ga = lsq_component<T>(fn[2 * a], fc, fn[2 * a + 1], hm, hp, (T)g.invh[a]);
                     const T half = T(0.5) * (T)g.h[a];
                     if (hm) {
@@ -109,8 +142,10 @@ __global__ __launch_bounds__(RB) void k_recon_limiter(Geo g, Dev d, int nvb)
                     }
                 }
             }
-            const gptr<T> lim = (gptr<T>)(q ? d.lim1 : d.lim0);
-            lim[(size_t)cell * nv + node] = phi;
+            if (store) {
+                const gptr<T> lim = (gptr<T>)(q ? d.lim1 : d.lim0);
+                lim[(size_t)cell * nv + node] = phi;
+            }
         }
     }
 }
@@ -135,20 +170,12 @@ __global__ __launch_bounds__(RB) void k_recon_source(Geo g, Dev d, int nvb)
     xi[1] = F32 ? (T)d.xi32[1][ky] : (T)d.xi64[1][ky];
     xi[2] = F32 ? (T)d.xi32[2][kz] : (T)d.xi64[2][kz];
     const T idt = (T)g.inv_dt;
-    const gptr<const int> nbr = (gptr<const int>)d.nbr;
     const gptr<const int> cflag = (gptr<const int>)d.cflag;
+#pragma unroll
     for (int r = 0; r < RCELLS; ++r) {
-        const int cell = rb.cell0 + r;
-        if (cell >= ncell || !cflag[cell]) continue;   // uniform over the block
-        int nb[6], nn[3];
-#pragma unroll
-        for (int dir = 0; dir < 6; ++dir) nb[dir] = nbr[(size_t)dir * ncell + cell];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            // second upwind neighbour: beyond the upwind one, same direction
-            const int du = 2 * a + ((rb.o >> a) & 1);
-            nn[a] = nb[du] >= 0 ? nbr[(size_t)du * ncell + nb[du]] : -1;
-        }
+        const int cell = min(rb.cell0 + r, ncell - 1);   // loads stay in range; the store is skipped
+        const bool store = rb.cell0 + r < ncell && cflag[cell];
+        const Around A = around(g, cflag, cell, rb.o);
 #pragma unroll
         for (int q = 0; q < (DIA ? 2 : 1); ++q) {
             const gptr<const T> f = (gptr<const T>)(q ? d.f1 : d.f0);
@@ -159,24 +186,31 @@ __global__ __launch_bounds__(RB) void k_recon_source(Geo g, Dev d, int nvb)
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int s = (rb.o >> a) & 1;            // 1: xi_a < 0, upwind is the + side
-                const int up = nb[2 * a + s], dn = nb[2 * a + 1 - s], uu = nn[a];
+                const bool hm = A.has[2 * a], hp = A.has[2 * a + 1];
+                const int up = s ? A.nb[2 * a + 1] : A.nb[2 * a];   // selects: no indexing by s
+                const bool hup = s ? hp : hm, hdn = s ? hm : hp;
                 const T invh = (T)g.invh[a];
-                const T fm = nb[2 * a] >= 0 ? f[(size_t)nb[2 * a] * nv + node] : fc;
-                const T fp = nb[2 * a + 1] >= 0 ? f[(size_t)nb[2 * a + 1] * nv + node] : fc;
-                const T gc = lsq_component<T>(fm, fc, fp, nb[2 * a] >= 0, nb[2 * a + 1] >= 0, invh);
-                T term = dn >= 0 ? phic * gc : T(0);
-                if (up >= 0) {
+                const T vm = f[(size_t)A.nb[2 * a] * nv + node];
+                const T vp = f[(size_t)A.nb[2 * a + 1] * nv + node];
+                const T vuu = f[(size_t)A.uu[a] * nv + node];
+                const T phup = lim[(size_t)up * nv + node];
+                const T fm = hm ? vm : fc, fp = hp ? vp : fc;
+                const T gc = lsq_component<T>(fm, fc, fp, hm, hp, invh);
+                T term = hdn ? phic * gc : T(0);
+                if (hup) {
                     // the upwind cell's neighbours along a: this cell, and uu beyond it
                     const T fu = s ? fp : fm;
-                    const T fuu = uu >= 0 ? f[(size_t)uu * nv + node] : fu;
-                    const T gu = s ? lsq_component<T>(fc, fu, fuu, true, uu >= 0, invh)
-                                   : lsq_component<T>(fuu, fu, fc, uu >= 0, true, invh);
-                    term -= lim[(size_t)up * nv + node] * gu;
+                    const T fuu = A.huu[a] ? vuu : fu;
+                    const T gu = s ? lsq_component<T>(fc, fu, fuu, true, A.huu[a], invh)
+                                   : lsq_component<T>(fuu, fu, fc, A.huu[a], true, invh);
+                    term -= phup * gu;
                 }
                 corr += T(0.5) * xi[a] * term;
             }
-            const gptr<T> out = (gptr<T>)(q ? d.ho1 : d.ho0);
-            out[(size_t)cell * nv + node] = idt * fc - corr;
+            if (store) {
+                const gptr<T> out = (gptr<T>)(q ? d.ho1 : d.ho0);
+                out[(size_t)cell * nv + node] = idt * fc - corr;
+            }
         }
     }
 }

@@ -368,8 +368,8 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
                     }
                     T num0 = gt0, num1 = gt1;
                     if (RFN) {
-                        num0 = fma(rsc, (T)rs0[(size_t)row * nv + lnode], num0);
-                        if (DIA) num1 = fma(rsc, (T)rs1[(size_t)row * nv + lnode], num1);
+                        num0 = fma(rsc, __builtin_nontemporal_load((const T *)&rs0[(size_t)row * nv + lnode]), num0);
+                        if (DIA) num1 = fma(rsc, __builtin_nontemporal_load((const T *)&rs1[(size_t)row * nv + lnode]), num1);
                     }
                     T F0, F1 = T(0);
                     if (kx == 0) { F0 = xin0[ky]; if (DIA) F1 = xin1[ky]; }

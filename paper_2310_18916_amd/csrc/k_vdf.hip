@@ -3,6 +3,8 @@
 #include "gsis_common.h"
 #include "gsis_launch.h"
 
+#include <algorithm>
+
 namespace gsis {
 
 // M(1, u_b, T_b) at every node, per boundary slot, in the internal node order;
@@ -118,20 +120,31 @@ __global__ void k_vdf_node(Geo g, Dev d, int node, double *out)
 }
 
 // Eq. (updatef) pointwise: f0 += M(W') - M(W), f1 += (dr/2)[Tr' M(W') - Tr M(W)],
-// both Maxwellians with the translational temperature.
+// both Maxwellians with the translational temperature.  The cell is uniform
+// over the block: its prefactors rho (pi T)^{-3/2} and 1/T are computed once
+// per wave, then one exponential per Maxwellian and point (the library's own
+// FP64 exponential, clamped where it underflows).  A block covers a run of
+// 256 nodes of one octant (blockIdx.y = octant * runs + run), so the octant's
+// node counts are uniform over it.
 template <typename T>
-__global__ void k_apply_correction(Geo g, Dev d)
+__global__ __launch_bounds__(256) void k_apply_correction(Geo g, Dev d, int nvb)
 {
-    int node = blockIdx.y * blockDim.x + threadIdx.x;
-    int cell = blockIdx.x;
-    if (node >= g.nv || !d.cflag[cell]) return;
+    const int cell = blockIdx.x;
+    const int o = (int)blockIdx.y / nvb;
+    const int l = ((int)blockIdx.y - o * nvb) * 256 + (int)threadIdx.x;
+    if (l >= g.osize[o] || !d.cflag[cell]) return;
+    const int node = g.obase[o] + l;
     const double *c = d.corr + (size_t)cell * NCORR;
-    int l, kx, ky, kz;
-    int o = octant_of(g, node, l);
+    const double pn = PI * c[4], po = PI * c[10];
+    const double an = c[0] / (pn * sqrt(pn)), ao = c[6] / (po * sqrt(po));
+    const double itn = 1.0 / c[4], ito = 1.0 / c[10];
+    int kx, ky, kz;
     node_of(g, o, l, kx, ky, kz);
-    double x = d.xi64[0][kx], y = d.xi64[1][ky], z = d.xi64[2][kz];
-    double mn = maxwell64(c[0], c + 1, c[4], x, y, z);
-    double mo = maxwell64(c[6], c + 7, c[10], x, y, z);
+    const double x = d.xi64[0][kx], y = d.xi64[1][ky], z = d.xi64[2][kz];
+    const double nx = x - c[1], ny = y - c[2], nz = z - c[3];
+    const double ox = x - c[7], oy = y - c[8], oz = z - c[9];
+    const double mn = an * exp_core(fmax(-(nx * nx + ny * ny + nz * nz) * itn, -745.0));
+    const double mo = ao * exp_core(fmax(-(ox * ox + oy * oy + oz * oz) * ito, -745.0));
     size_t at = (size_t)cell * g.nv + node;
     T *f0 = (T *)d.f0;
     f0[at] = (T)((double)f0[at] + (mn - mo));
@@ -194,10 +207,15 @@ hipError_t launch_vdf_node(const Geo &g, const Dev &d, bool fp32, int node, doub
 
 hipError_t launch_apply_correction(const Geo &g, const Dev &d, bool fp32, hipStream_t s)
 {
+    int omax = 0;
+    for (int o = 0; o < 8; ++o) omax = std::max(omax, g.osize[o]);
+    const int nvb = (omax + 255) / 256;
+    if (8 * nvb > 65535) return hipErrorInvalidConfiguration;
+    const dim3 grid(g.ncell, 8 * nvb);
     if (fp32)
-        hipLaunchKernelGGL(k_apply_correction<float>, node_grid(g, g.ncell), dim3(256), 0, s, g, d);
+        hipLaunchKernelGGL(k_apply_correction<float>, grid, dim3(256), 0, s, g, d, nvb);
     else
-        hipLaunchKernelGGL(k_apply_correction<double>, node_grid(g, g.ncell), dim3(256), 0, s, g, d);
+        hipLaunchKernelGGL(k_apply_correction<double>, grid, dim3(256), 0, s, g, d, nvb);
     return hipGetLastError();
 }
 
