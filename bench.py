@@ -39,7 +39,7 @@ def parse():
     p.add_argument("--precondition", default="1000,10",
                    help="macro_steps,kinetic_steps of the initial field (Alg. 1) for an extra time-to-convergence "
                         "run; 'none' skips it")
-    p.add_argument("--second-order", default="0",
+    p.add_argument("--second-order", default="1",
                    help="Venkatakrishnan K of the extra second-order-RHS runs (c2: step and convergence), "
                         "'none' to skip them, a negative K for no limiter")
     p.add_argument("--stretch", type=float, default=0.0,

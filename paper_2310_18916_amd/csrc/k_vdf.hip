@@ -154,6 +154,54 @@ __global__ __launch_bounds__(256) void k_apply_correction(Geo g, Dev d, int nvb)
     }
 }
 
+// The same update with the Maxwellians factored per axis: exp(-|xi - u|^2/T)
+// = prod_a exp(-(xi_a - u_a)^2 / T), so one block per cell stages the 1-D
+// factors of both Maxwellians in LDS (the prefactor folded into the x
+// factor) and every point takes three products instead of two exponentials.
+// Used when every axis has at most CTAB nodes.
+constexpr int CTAB = 256;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_correction_sep(Geo g, Dev d)
+{
+    __shared__ double ex[2][3][CTAB];
+    const int cell = blockIdx.x;
+    if (!d.cflag[cell]) return;   // uniform over the block
+    const double *c = d.corr + (size_t)cell * NCORR;
+    const double pn = PI * c[4], po = PI * c[10];
+    const double an = c[0] / (pn * sqrt(pn)), ao = c[6] / (po * sqrt(po));
+    const double itn = 1.0 / c[4], ito = 1.0 / c[10];
+    const int n1x = g.n1[0], n1y = g.n1[1], span = g.n1[0] + g.n1[1] + g.n1[2];
+    for (int e = threadIdx.x; e < 2 * span; e += blockDim.x) {
+        const int m = e >= span, r = e - m * span;
+        const int a = r < n1x ? 0 : (r < n1x + n1y ? 1 : 2);
+        const int k = r - (a == 0 ? 0 : (a == 1 ? n1x : n1x + n1y));
+        const double dx = d.xi64[a][k] - (m ? c[7 + a] : c[1 + a]);
+        double v = exp_core(fmax(-dx * dx * (m ? ito : itn), -745.0));
+        if (a == 0) v *= m ? ao : an;
+        ex[m][a][k] = v;
+    }
+    __syncthreads();
+    T *f0 = (T *)d.f0;
+    T *f1 = (T *)d.f1;
+    const bool dia = g.species == 1;
+    const double h1 = 0.5 * g.dr;
+    const size_t row = (size_t)cell * g.nv;
+    for (int o = 0; o < 8; ++o) {
+        const int nox = g.on[o][0], noy = g.on[o][1], n = g.osize[o];
+        const int bx = (o & 1) ? 0 : g.k0[0], by = (o & 2) ? 0 : g.k0[1], bz = (o & 4) ? 0 : g.k0[2];
+        for (int l = threadIdx.x; l < n; l += blockDim.x) {
+            const int r = l / nox, lx = l - r * nox, lz = r / noy, ly = r - lz * noy;
+            const int kx = bx + lx, ky = by + ly, kz = bz + lz;
+            const double mn = ex[0][0][kx] * ex[0][1][ky] * ex[0][2][kz];
+            const double mo = ex[1][0][kx] * ex[1][1][ky] * ex[1][2][kz];
+            const size_t at = row + g.obase[o] + l;
+            f0[at] = (T)((double)f0[at] + (mn - mo));
+            if (dia) f1[at] = (T)((double)f1[at] + h1 * (c[5] * mn - c[11] * mo));
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launches
 // blockIdx.x = row (cell or boundary slot), blockIdx.y * 256 + tid = node
 static dim3 node_grid(const Geo &g, int rows) { return dim3(rows, (g.nv + 255) / 256); }
@@ -207,6 +255,11 @@ hipError_t launch_vdf_node(const Geo &g, const Dev &d, bool fp32, int node, doub
 
 hipError_t launch_apply_correction(const Geo &g, const Dev &d, bool fp32, hipStream_t s)
 {
+    if (g.n1[0] <= CTAB && g.n1[1] <= CTAB && g.n1[2] <= CTAB) {
+        if (fp32) hipLaunchKernelGGL(k_apply_correction_sep<float>, dim3(g.ncell), dim3(256), 0, s, g, d);
+        else hipLaunchKernelGGL(k_apply_correction_sep<double>, dim3(g.ncell), dim3(256), 0, s, g, d);
+        return hipGetLastError();
+    }
     int omax = 0;
     for (int o = 0; o < 8; ++o) omax = std::max(omax, g.osize[o]);
     const int nvb = (omax + 255) / 256;

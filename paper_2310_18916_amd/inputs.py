@@ -70,11 +70,11 @@ class Case:
     # spatial order of the explicit interface values of the kinetic update
     # (1 first-order upwind; 2 least-squares reconstruction with the
     # Venkatakrishnan limiter, eps^2 = (limiter_k h)^3, limiter_k < 0: none).
-    # eps is an absolute threshold while a VDF spans many decades, so the
-    # default is the strict limiter (no new extrema): with any K > 0 the
-    # Mach-5 block flows lose positivity in the distribution's tails
+    # K = 1 suits smooth flows (the cavity); the strict limiter K = 0 (no new
+    # extrema) is needed by the Mach-5 block flows, which lose positivity in
+    # the distribution's tails with K > 0 since eps is an absolute threshold
     order: int = 1
-    limiter_k: float = 0.0
+    limiter_k: float = 1.0
     bcs: List[Boundary] = dataclasses.field(default_factory=lambda: [Boundary() for _ in range(7)])
     solid: Optional[np.ndarray] = None
     init: Tuple[float, Tuple[float, float, float], float, float] = (1.0, (0.0, 0.0, 0.0), 1.0, 1.0)

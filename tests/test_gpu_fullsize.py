@@ -5,7 +5,8 @@ can compute one by one: the first pass from the uniform initial Maxwellian at
 selected velocity nodes, for every cell (oracle.first_pass_nodes), after the
 pass run by the autotuner in the launch configuration bench.py uses.  Beyond
 the first pass, properties that hold at any size are checked: mirror symmetry
-of the cavity and the agreement of the FP32 and FP64 paths.
+of the cavity and the agreement of the FP32 and FP64 paths, with first- and
+second-order right-hand sides.
 """
 import sys
 
@@ -95,6 +96,38 @@ def test_c2_gsis_mirror_symmetry():
     d = np.abs(m[..., 2] - mir[..., 2]).max() / np.abs(m[..., 1]).max()
     say(f"  uy asymmetry {d:.2e}")
     assert d <= 1e-10
+
+
+def test_c2_second_order_symmetry_and_precision():
+    """The second-order right-hand side at full size (Venkatakrishnan K = 1):
+    after GSIS iterations the c2 fields keep the cavity's mirror symmetry
+    (FP64), and the FP32 path tracks the FP64 one within 1e-5."""
+    import dataclasses
+    say("[c2 second order]")
+    case = dataclasses.replace(I.c2(), order=2, limiter_k=1.0)
+    res = {}
+    for dtype in ("fp64", "fp32"):
+        s = Solver(case, dtype, tile=(8, 8, 32, 256) if dtype == "fp64" else (16, 8, 32, 256))
+        s.init_maxwellian()
+        for _ in range(3):
+            s.kinetic_step(1)
+            s.gsis_correct(case.macro_iters)
+        res[dtype] = s.moments()
+        del s
+        torch.cuda.empty_cache()
+    m = res["fp64"].reshape(case.nz, case.ny, case.nx, -1)
+    mir = m[:, ::-1, :, :].copy()
+    mir[..., 2] *= -1.0
+    for k, name in ((0, "rho"), (4, "T"), (1, "ux"), (3, "uz")):
+        d = np.abs(m[..., k] - mir[..., k]).max() / np.abs(m[..., k]).max()
+        say(f"  {name} asymmetry {d:.2e}")
+        assert d <= 1e-10
+    a, b = res["fp32"], res["fp64"]
+    errs = {"rho": np.abs(a[:, 0] - b[:, 0]).max() / np.abs(b[:, 0]).max(),
+            "T": np.abs(a[:, 4] - b[:, 4]).max() / np.abs(b[:, 4]).max(),
+            "u": np.abs(a[:, 1:4] - b[:, 1:4]).max() / np.abs(b[:, 1:4]).max()}
+    say(f"  fp32 vs fp64 {errs}")
+    assert max(errs.values()) <= 1e-5
 
 
 @pytest.mark.parametrize("workload,steps", [("c3", 20), ("c4", 3)])
