@@ -158,10 +158,16 @@ def second_order(case, k, steps, warmup, macro, out, converge_too=True):
         esz = 8 if dt == "fp64" else 4
         rec_ms, rec_n = prof["recon"]
         sw_ms, sw_n = prof["sweep"]
+        recon_gbs = pts * nvdf * esz * 5 / (rec_ms / rec_n * 1e-3) / 1e9
         res[dt] = {"value": pts * steps / r["seconds"], "ms_per_step": r["seconds"] / steps * 1e3,
                    "sweep_tile": r["tile"], "phases_ms_per_step": {kk: v[0] / steps for kk, v in prof.items()},
-                   "recon_gbs": pts * nvdf * esz * 5 / (rec_ms / rec_n * 1e-3) / 1e9,
-                   "sweep_gbs": pts * nvdf * esz * 2 / (sw_ms / sw_n * 1e-3) / 1e9}
+                   "recon_gbs": recon_gbs,
+                   "sweep_gbs": pts * nvdf * esz * 2 / (sw_ms / sw_n * 1e-3) / 1e9,
+                   # the dominant phase of a second-order pass: limiter + source, per pass
+                   "roofline": {"bound": "hbm", "kernel": "k_recon_limiter + k_recon_source",
+                                "achieved": recon_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": recon_gbs / HBM_PEAK_GBS, "traffic": None,
+                                "algorithmic_bytes": pts * nvdf * esz * 5}}
         del r
     if converge_too and case.gsis:
         c1st, m1st = converge(case, "fp64", out["sweep_tile"])
