@@ -317,6 +317,25 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
             }
         }
         if (run && active) {
+            // The per-point term of every cell of the slab (RFN), read before
+            // the slab's first store: a read placed at its cell would wait for
+            // the stores before it (the two buffers may alias as far as the
+            // compiler knows), one load latency per cell.
+            T rv0[RFN ? TY : 1][RFN ? TX : 1], rv1[RFN && DIA ? TY : 1][RFN && DIA ? TX : 1];
+            if constexpr (RFN) {
+#pragma unroll
+                for (int ky = 0; ky < TY; ++ky) {
+#pragma unroll
+                    for (int kx = 0; kx < TX; ++kx) {
+                        const int e = ky * TX + kx;
+                        const int flag = MASK ? __builtin_amdgcn_readfirstlane(sflag[w][buf][e]) : 1;
+                        const bool live = MASK ? (flag & 1) != 0 : (i0 + kx < nx && j0 + ky < ny);
+                        const int row = live ? cbase + kx * dxs + ky * dys : ncell;
+                        rv0[ky][kx] = __builtin_nontemporal_load((const T *)&rs0[(size_t)row * nv + lnode]);
+                        if (DIA) rv1[ky][kx] = __builtin_nontemporal_load((const T *)&rs1[(size_t)row * nv + lnode]);
+                    }
+                }
+            }
             // Monatomic gas without solid cells: the parameters that start a
             // cell's exponential (u and 1/T) are read from LDS one cell ahead and
             // the rest before the exponential, held there by a scheduling
@@ -367,9 +386,9 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
                         invtau = p[13];
                     }
                     T num0 = gt0, num1 = gt1;
-                    if (RFN) {
-                        num0 = fma(rsc, __builtin_nontemporal_load((const T *)&rs0[(size_t)row * nv + lnode]), num0);
-                        if (DIA) num1 = fma(rsc, __builtin_nontemporal_load((const T *)&rs1[(size_t)row * nv + lnode]), num1);
+                    if constexpr (RFN) {
+                        num0 = fma(rsc, rv0[ky][kx], num0);
+                        if (DIA) num1 = fma(rsc, rv1[ky][DIA ? kx : 0], num1);
                     }
                     T F0, F1 = T(0);
                     if (kx == 0) { F0 = xin0[ky]; if (DIA) F1 = xin1[ky]; }
