@@ -320,9 +320,12 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
             // The per-point term of every cell of the slab (RFN), read before
             // the slab's first store: a read placed at its cell would wait for
             // the stores before it (the two buffers may alias as far as the
-            // compiler knows), one load latency per cell.
-            T rv0[RFN ? TY : 1][RFN ? TX : 1], rv1[RFN && DIA ? TY : 1][RFN && DIA ? TX : 1];
-            if constexpr (RFN) {
+            // compiler knows), one load latency per cell.  Not for the FP64
+            // diatomic masked 8 x 4 slab, whose registers are already full
+            // (the held terms spilled to scratch); it reads at the cell.
+            constexpr bool HOIST = RFN && !(DIA && MASK && !F32 && TX * TY > 16);
+            T rv0[HOIST ? TY : 1][HOIST ? TX : 1], rv1[HOIST && DIA ? TY : 1][HOIST && DIA ? TX : 1];
+            if constexpr (HOIST) {
 #pragma unroll
                 for (int ky = 0; ky < TY; ++ky) {
 #pragma unroll
@@ -386,9 +389,12 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
                         invtau = p[13];
                     }
                     T num0 = gt0, num1 = gt1;
-                    if constexpr (RFN) {
+                    if constexpr (HOIST) {
                         num0 = fma(rsc, rv0[ky][kx], num0);
                         if (DIA) num1 = fma(rsc, rv1[ky][DIA ? kx : 0], num1);
+                    } else if constexpr (RFN) {
+                        num0 = fma(rsc, __builtin_nontemporal_load((const T *)&rs0[(size_t)row * nv + lnode]), num0);
+                        if (DIA) num1 = fma(rsc, __builtin_nontemporal_load((const T *)&rs1[(size_t)row * nv + lnode]), num1);
                     }
                     T F0, F1 = T(0);
                     if (kx == 0) { F0 = xin0[ky]; if (DIA) F1 = xin1[ky]; }
