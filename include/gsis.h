@@ -10,7 +10,8 @@
  * on both sides) exactly by upwind sweeps, and reduces the distribution to
  * the moments of Eq. (getmoment).  gsis_gsis_correct runs the GSIS-II
  * macroscopic synthetic solve of Sec. 3.3 and schedules the VDF update of
- * Eq. (updatef); gsis_residual evaluates the convergence criterion of Sec. 4.
+ * Eq. (updatef); gsis_residual evaluates the convergence criterion of Sec. 5,
+ * Eq. (convergence_critertion).
  * The calls mirror the Require/Ensure lists of Algorithms 1-3: the kinetic
  * solver takes f and returns W, the high-order terms and the boundary flux;
  * the macroscopic solver takes those and returns W.
@@ -165,7 +166,7 @@ gsis_status gsis_gsis_correct(gsis_ctx *ctx, int inner_iters);
  * initialisation. */
 gsis_status gsis_precondition(gsis_ctx *ctx, int macro_steps, int kinetic_steps);
 
-/* Convergence criterion of Sec. 4 (volume-weighted relative L2 change of rho,
+/* Convergence criterion of Sec. 5, Eq. (convergence_critertion) (volume-weighted relative L2 change of rho,
  * |u| as a vector, Tt since the previous call or init; a zero denominator
  * gives the absolute change).  Synchronises.  Returns GSIS_ENOTFINITE if a
  * kernel met a non-positive/non-finite density or temperature, and
@@ -278,7 +279,7 @@ gsis_status gsis_batch_autotune(gsis_batch *b, int reps, int *cfg_out, double *m
 gsis_status gsis_batch_init_maxwellian(gsis_batch *b, double rho, const double u[3], double T, double Tr);
 /* iters GSIS iterations of every case, each: one kinetic pass,
  * gsis_gsis_correct(inner_iters) (skipped when inner_iters == 0), and the
- * residual of Sec. 4 against the previous iteration, recorded in the history.
+ * residual of Sec. 5 against the previous iteration, recorded in the history.
  * use_graph != 0 captures one iteration into a HIP graph (kept and reused
  * while inner_iters and the tile shape stay the same) and replays it iters
  * times; 0 launches the kernels directly.  Asynchronous. */

@@ -38,7 +38,7 @@
  *                      high-order terms of Eq. (full_constitutive), Rusanov
  *                      convective flux, the diagonal of Eq. (res_macro) in a
  *                      point-Jacobi iteration, then Eq. (updatef).
- *   residual           Eq. (convergence_critertion), Sec. 4.
+ *   residual           Eq. (convergence_critertion), Sec. 5.
  */
 #define _GNU_SOURCE
 #include <math.h>
@@ -84,6 +84,7 @@ typedef struct {
     double *xi[3], *w1[3];
     double *f0, *f1;
     double *prev;           /* residual snapshot: rho, ux, uy, uz, Tt per cell */
+    double *lastW;          /* W^{n+1} of the last macroscopic solve, [ncell][6] (NULL before one) */
     int status;
 } orc_state;
 
@@ -120,7 +121,7 @@ void orc_free(orc_state *s)
     if (!s) return;
     free(s->solid);
     for (int a = 0; a < 3; ++a) { free(s->xi[a]); free(s->w1[a]); }
-    free(s->f0); free(s->f1); free(s->prev);
+    free(s->f0); free(s->f1); free(s->prev); free(s->lastW);
     free(s);
 }
 
@@ -1384,6 +1385,8 @@ static int gsis_correct_mode(orc_state *s, int iters, int euler)
         if (!(P[cell].rho > 0) || !(P[cell].Tt > 0) || !isfinite(P[cell].E)) bad = 1;
     }
     if (bad) s->status = -5;
+    if (!s->lastW) s->lastW = malloc(sizeof(double) * (size_t)ncell * 6);
+    memcpy(s->lastW, W, sizeof(double) * (size_t)ncell * 6);
     #pragma omp parallel for schedule(static)
     for (int cell = 0; cell < ncell; ++cell) {
         if (s->solid[cell]) continue;
@@ -1414,6 +1417,43 @@ int orc_gsis_precondition(orc_state *s, int macro_steps, int kinetic_steps)
     if (st) return st;
     orc_step(s, kinetic_steps);
     return s->status;
+}
+
+/* W^{n+1} = (rho, rho u, E, Er) of the last macroscopic solve, out[ncell][6]
+ * (zeros in solid cells); returns -1 before any solve. */
+int orc_last_macro_W(const orc_state *s, double *out)
+{
+    if (!s->lastW) return -1;
+    for (int cell = 0; cell < s->ncell; ++cell)
+        for (int k = 0; k < 6; ++k) out[(size_t)cell * 6 + k] = s->solid[cell] ? 0.0 : s->lastW[(size_t)cell * 6 + k];
+    return 0;
+}
+
+/* The Navier-Stokes-Fourier closure of the macroscopic solve at the face
+ * between fluid cell `cell` and its +a neighbour, for the conservative field
+ * W[ncell][6] (rho, rho u, E, Er): out = (sigma_xa, sigma_ya, sigma_za, q_a,
+ * qr_a), exactly as the face flux of the iteration evaluates it (no HoT).
+ * Returns -1 if that neighbour is not a fluid cell. */
+int orc_nsf_face(const orc_state *s, const double *W, int cell, int a, double out[5])
+{
+    if (cell < 0 || cell >= s->ncell || a < 0 || a > 2 || s->solid[cell]) return -1;
+    int nb = neighbour(s, cell, 2 * a + 1);
+    if (nb < 0) return -1;
+    macpar mp;
+    macro_params(s, &mp);
+    mp.euler = 0;
+    prim_t *P = calloc((size_t)s->ncell, sizeof(prim_t));
+    for (int c = 0; c < s->ncell; ++c)
+        if (!s->solid[c]) prim_of(&mp, W + (size_t)c * 6, &P[c]);
+    double gL[9], gR[9], sig[3], q, qr;
+    cell_grad(s, P, cell, gL);
+    cell_grad(s, P, nb, gR);
+    nsf_face(&mp, &P[cell], &P[nb], gL, gR, a, s->h[a], sig, &q, &qr);
+    for (int b = 0; b < 3; ++b) out[b] = sig[b];
+    out[3] = q;
+    out[4] = qr;
+    free(P);
+    return 0;
 }
 
 /* Total mass sum rho V of the current VDF (closed-cavity drift diagnostic). */

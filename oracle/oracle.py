@@ -76,6 +76,8 @@ def lib():
         L.orc_ref_components.argtypes = [C.POINTER(_Cfg), C.c_double, D, C.c_double, C.c_double, D, D,
                                          C.c_int, D, D]
         L.orc_conductivities.argtypes = [C.POINTER(_Cfg), D]
+        L.orc_last_macro_W.argtypes = [P, D]
+        L.orc_nsf_face.argtypes = [P, D, C.c_int, C.c_int, D]
         L.orc_first_pass_nodes.argtypes = [C.POINTER(_Cfg), C.c_void_p, C.c_double, D, C.c_double, C.c_double,
                                            C.POINTER(C.c_int), C.c_int, D, D]
         _lib = L
@@ -200,6 +202,22 @@ class Oracle:
         b1 = np.empty(self.nv)
         bc = lib().orc_boundary_values(self.h, cell, d, _dp(b0), _dp(b1))
         return bc, b0, b1
+
+    def last_macro_W(self) -> np.ndarray:
+        """[cell][6] W^{n+1} = (rho, rho u, E, Er) of the last macroscopic solve."""
+        out = np.empty((self.ncell, 6))
+        if lib().orc_last_macro_W(self.h, _dp(out)) != 0:
+            raise RuntimeError("no macroscopic solve yet")
+        return out
+
+    def nsf_face(self, W: np.ndarray, cell: int, a: int) -> np.ndarray:
+        """NSF closure (sigma_xa, sigma_ya, sigma_za, q_a, qr_a) of the macroscopic
+        solve at the face between `cell` and its +a neighbour for the field W[cell][6]."""
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        out = np.empty(5)
+        if lib().orc_nsf_face(self.h, _dp(W), cell, a, _dp(out)) != 0:
+            raise ValueError("not an interior fluid face")
+        return out
 
     def total_mass(self) -> float:
         return lib().orc_total_mass(self.h)

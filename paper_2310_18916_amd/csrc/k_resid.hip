@@ -1,4 +1,4 @@
-// Convergence criterion of Sec. 4: volume-weighted relative L2 change of
+// Convergence criterion of Sec. 5, Eq. (convergence_critertion): volume-weighted relative L2 change of
 // rho, u (as a vector) and Tt between two states; uniform cells, so the
 // weights cancel.  Two-stage fixed-order reduction (deterministic).
 #include "gsis_common.h"

@@ -7,8 +7,8 @@ read the same case description without sharing any computation.
 
 The workloads stand in for the paper's test problems, whose meshes and
 reference data are not published: a 3-D lid-driven cavity for the 2-D cavity
-of Sec. 4.1, and a cube in a Ma = 5 stream for the Apollo reentry capsule of
-Sec. 4.2.  Velocities are in units of the most probable speed sqrt(2 R T0),
+of Sec. 5.1, and a cube in a Ma = 5 stream for the Apollo reentry capsule of
+Sec. 5.2.  Velocities are in units of the most probable speed sqrt(2 R T0),
 lengths in the cavity side (or the block side).
 """
 from __future__ import annotations
@@ -25,7 +25,7 @@ INFLOW = 1
 MONATOMIC = 0
 DIATOMIC = 1
 
-# Nitrogen (Sec. 4): internal degrees of freedom, rotational collision number,
+# Nitrogen (Sec. 5): internal degrees of freedom, rotational collision number,
 # viscosity index and the heat-flux relaxation rates A_tt, A_tr, A_rt, A_rr.
 N2_DR = 2.0
 N2_ZR = 3.5

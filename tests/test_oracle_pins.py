@@ -88,7 +88,7 @@ def test_rykov_components_and_heat_flux_relaxation():
 
 
 def test_n2_eucken_factors_golden():
-    """Sec. 4: with the printed A for nitrogen, Eq. (mu_kappa) gives f_t = 2.365, f_r = 1.435."""
+    """Sec. 5: with the printed A for nitrogen, Eq. (mu_kappa) gives f_t = 2.365, f_r = 1.435."""
     gold = json.load(open(os.path.join(HERE, "golden", "n2_eucken.json")))
     case = _n2_case()
     case.A = tuple(gold["A"])
