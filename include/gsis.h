@@ -166,11 +166,15 @@ gsis_status gsis_gsis_correct(gsis_ctx *ctx, int inner_iters);
  * initialisation. */
 gsis_status gsis_precondition(gsis_ctx *ctx, int macro_steps, int kinetic_steps);
 
-/* Convergence criterion of Sec. 5, Eq. (convergence_critertion) (volume-weighted relative L2 change of rho,
- * |u| as a vector, Tt since the previous call or init; a zero denominator
- * gives the absolute change).  Synchronises.  Returns GSIS_ENOTFINITE if a
+/* Convergence criterion of Sec. 5, Eq. (convergence_critertion): volume-weighted
+ * relative L2 change of rho, |u| as a vector and Tt since the previous call or
+ * init, into eps[3].  A denominator at or below its noise floor gives the
+ * absolute change instead: zero for rho and Tt; for u, (1e3 eps)^2 times the
+ * sum of Tt^2, eps the unit roundoff of the VDF precision (the velocity of a
+ * gas at rest is rounding noise).  Synchronises.  Returns GSIS_ENOTFINITE if a
  * kernel met a non-positive/non-finite density or temperature, and
- * GSIS_EDIVERGED if any component exceeds 1e6 times its first value. */
+ * GSIS_EDIVERGED if a component exceeds 1e6 times its reference, the first
+ * value of that component computed against a denominator above the floor. */
 gsis_status gsis_residual(gsis_ctx *ctx, double eps[3]);
 
 /* Copy the VDF(s) out / in, canonical [cell][node] FP64 in device memory

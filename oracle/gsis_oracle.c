@@ -873,9 +873,11 @@ void orc_moments(const orc_state *s, double *out)
     }
 }
 
-/* Eq. (convergence_critertion) with uniform cell volumes; u is a vector,
- * a zero denominator reports the absolute value.  Compares with the last
- * snapshot and takes a new one. */
+/* Eq. (convergence_critertion) with uniform cell volumes; u is a vector.  A
+ * denominator that is zero, or for u at most (1000 times the FP64 unit
+ * roundoff)^2 times the sum of Tt^2 -- the velocity of a gas at rest is only
+ * rounding noise -- reports the absolute change instead.  Compares with the
+ * last snapshot and takes a new one. */
 void orc_residual(orc_state *s, double eps[3])
 {
     nsum num[3], den[3];
@@ -890,9 +892,10 @@ void orc_residual(orc_state *s, double eps[3])
         for (int a = 0; a < 3; ++a) { double du = m.u[a] - pv[1 + a]; nadd(&num[1], du * du); nadd(&den[1], pv[1 + a] * pv[1 + a]); }
         nadd(&num[2], dT * dT); nadd(&den[2], pv[4] * pv[4]);
     }
+    double ufloor = (1e3 * 2.220446049250313e-16) * (1e3 * 2.220446049250313e-16) * nval(&den[2]);
     for (int k = 0; k < 3; ++k) {
         double n = nval(&num[k]), d = nval(&den[k]);
-        eps[k] = d > 0 ? sqrt(n / d) : sqrt(n);
+        eps[k] = d > (k == 1 ? ufloor : 0.0) ? sqrt(n / d) : sqrt(n);
     }
     snapshot(s);
 }

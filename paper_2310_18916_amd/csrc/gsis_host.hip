@@ -3,6 +3,7 @@
 #include "gsis.h"
 #include "gsis_common.h"
 #include "gsis_launch.h"
+#include "gsis_resid_host.h"
 
 #include <algorithm>
 #include <cmath>
@@ -33,8 +34,7 @@ struct gsis_ctx {
     bool bound = false, inited = false, pending = false, stepped = false;
     long long passes = 0;
     hipStream_t stream = nullptr;
-    bool have_first = false;
-    double first_eps[3] = {0, 0, 0};
+    DivWatch watch;          // divergence reference of the residual
     std::string err;
     // phase timing
     bool prof = false;
@@ -351,7 +351,7 @@ struct PhaseTimer {
 
 struct StateHeader {
     char magic[8];
-    int version, ncell, nv, fp32, species, pending, stepped, have_first;
+    int version, ncell, nv, fp32, species, pending, stepped, have_first;   // have_first: bit k = watch.have[k]
     long long passes;
     double first_eps[3];
     char pad[128 - 8 - 9 * 4 - 8 - 24];
@@ -371,6 +371,28 @@ void state_parts(const gsis_ctx *c, std::vector<StatePart> &parts)
     parts.push_back({c->d.cm, n * NMOM * sizeof(double)});
     parts.push_back({c->d.corr, n * NCORR * sizeof(double)});
     parts.push_back({c->d.snap, n * NSNAP * sizeof(double)});
+}
+
+// The rest of a residual once its sums are queued at `total` (device): read
+// them and the error flag, take the new snapshot, evaluate eps and the
+// divergence watch.  Synchronises.
+gsis_status residual_finish(gsis_ctx *ctx, const double *total, PhaseTimer *t, double eps[3])
+{
+    double sums[6];
+    int flag[4];
+    HIPCHK(ctx, hipMemcpyAsync(sums, total, sizeof sums, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(flag, ctx->d.errflag, sizeof flag, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, launch_snapshot(target_of(ctx), ctx->stream));
+    if (t) HIPCHK(ctx, t->stop());
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const ResidEval r = resid_eval(sums, ctx->fp32);
+    for (int k = 0; k < 3; ++k) eps[k] = r.eps[k];
+    if (flag[0] || !std::isfinite(eps[0]) || !std::isfinite(eps[1]) || !std::isfinite(eps[2]))
+        return fail(ctx, GSIS_ENOTFINITE, "non-positive or non-finite density/temperature (flag " +
+                                              std::to_string(flag[0]) + ")");
+    if (resid_diverged(ctx->watch, r, 1e6))
+        return fail(ctx, GSIS_EDIVERGED, "residual grew beyond 1e6 times its first relative value");
+    return GSIS_OK;
 }
 
 }  // namespace
@@ -653,7 +675,7 @@ gsis_status gsis_init_maxwellian(gsis_ctx *ctx, double rho, const double u[3], d
     ctx->inited = true;
     ctx->stepped = false;
     ctx->passes = 0;
-    ctx->have_first = false;
+    ctx->watch = DivWatch();
     return GSIS_OK;
 }
 
@@ -749,32 +771,11 @@ gsis_status gsis_residual(gsis_ctx *ctx, double eps[3])
     if (!ctx) return GSIS_EINVAL;
     if (!ctx->inited) return fail(ctx, GSIS_ESTATE, "initialise the VDF first");
     if (!eps) return fail(ctx, GSIS_EINVAL, "eps is NULL");
-    const Geo &g = ctx->g;
     PhaseTimer t;
     HIPCHK(ctx, t.start(ctx, GSIS_PHASE_RESIDUAL));
-    const Target tg = target_of(ctx);
-    HIPCHK(ctx, launch_residual(tg, ctx->stream));
-    double sums[6];
-    int flag[4];
-    HIPCHK(ctx, hipMemcpyAsync(sums, ctx->d.red + (size_t)resid_blocks(g) * 6, sizeof sums, hipMemcpyDeviceToHost,
-                               ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(flag, ctx->d.errflag, sizeof flag, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, launch_snapshot(tg, ctx->stream));
-    HIPCHK(ctx, t.stop());
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    for (int k = 0; k < 3; ++k) eps[k] = sums[3 + k] > 0 ? std::sqrt(sums[k] / sums[3 + k]) : std::sqrt(sums[k]);
-    if (flag[0] || !std::isfinite(eps[0]) || !std::isfinite(eps[1]) || !std::isfinite(eps[2]))
-        return fail(ctx, GSIS_ENOTFINITE, "non-positive or non-finite density/temperature (flag " +
-                                              std::to_string(flag[0]) + ")");
-    if (!ctx->have_first) {
-        for (int k = 0; k < 3; ++k) ctx->first_eps[k] = eps[k];
-        ctx->have_first = true;
-    } else {
-        for (int k = 0; k < 3; ++k)
-            if (ctx->first_eps[k] > 0 && eps[k] > 1e6 * ctx->first_eps[k])
-                return fail(ctx, GSIS_EDIVERGED, "residual grew beyond 1e6 times its first value");
-    }
-    return GSIS_OK;
+    HIPCHK(ctx, launch_residual(target_of(ctx), ctx->stream));
+    double *total = ctx->d.red + (size_t)resid_blocks(ctx->g) * 6;
+    return residual_finish(ctx, total, &t, eps);
 }
 
 gsis_status gsis_get_vdf(gsis_ctx *ctx, double *f0_device, double *f1_device)
@@ -806,7 +807,7 @@ gsis_status gsis_set_vdf(gsis_ctx *ctx, const double *f0_device, const double *f
     ctx->inited = true;
     ctx->stepped = false;
     ctx->passes = 0;
-    ctx->have_first = false;
+    ctx->watch = DivWatch();
     return GSIS_OK;
 }
 
@@ -830,16 +831,19 @@ gsis_status gsis_get_state(gsis_ctx *ctx, void *dst_device)
     StateHeader h;
     std::memset(&h, 0, sizeof h);
     std::memcpy(h.magic, "GSISSTA", 8);
-    h.version = 1;
+    h.version = 2;
     h.ncell = ctx->g.ncell;
     h.nv = ctx->g.nv;
     h.fp32 = ctx->fp32;
     h.species = ctx->g.species;
     h.pending = ctx->pending;
     h.stepped = ctx->stepped;
-    h.have_first = ctx->have_first;
+    h.have_first = 0;
     h.passes = ctx->passes;
-    for (int k = 0; k < 3; ++k) h.first_eps[k] = ctx->first_eps[k];
+    for (int k = 0; k < 3; ++k) {
+        h.have_first |= ctx->watch.have[k] ? 1 << k : 0;
+        h.first_eps[k] = ctx->watch.first[k];
+    }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     HIPCHK(ctx, hipMemcpy(dst_device, &h, sizeof h, hipMemcpyHostToDevice));
     std::vector<StatePart> parts;
@@ -861,7 +865,7 @@ gsis_status gsis_set_state(gsis_ctx *ctx, const void *src_device)
     StateHeader h;
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     HIPCHK(ctx, hipMemcpy(&h, src_device, sizeof h, hipMemcpyDeviceToHost));
-    if (std::memcmp(h.magic, "GSISSTA", 8) != 0 || h.version != 1 || h.ncell != ctx->g.ncell || h.nv != ctx->g.nv ||
+    if (std::memcmp(h.magic, "GSISSTA", 8) != 0 || h.version != 2 || h.ncell != ctx->g.ncell || h.nv != ctx->g.nv ||
         h.fp32 != (int)ctx->fp32 || h.species != ctx->g.species)
         return fail(ctx, GSIS_EINVAL, "state blob does not match this context");
     std::vector<StatePart> parts;
@@ -876,9 +880,11 @@ gsis_status gsis_set_state(gsis_ctx *ctx, const void *src_device)
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     ctx->pending = h.pending != 0;
     ctx->stepped = h.stepped != 0;
-    ctx->have_first = h.have_first != 0;
     ctx->passes = h.passes;
-    for (int k = 0; k < 3; ++k) ctx->first_eps[k] = h.first_eps[k];
+    for (int k = 0; k < 3; ++k) {
+        ctx->watch.have[k] = (h.have_first >> k) & 1;
+        ctx->watch.first[k] = h.first_eps[k];
+    }
     ctx->inited = true;
     return GSIS_OK;
 }
@@ -1533,8 +1539,8 @@ gsis_status gsis_batch_residuals(gsis_batch *b, double *eps, int max, int *count
         const int slot = (ctr - n + i) % b->hist_cap;
         for (int c = 0; c < nc; ++c) {
             const double *v = &h[((size_t)slot * nc + c) * 6];
-            for (int k = 0; k < 3; ++k)
-                eps[((size_t)i * nc + c) * 3 + k] = v[3 + k] > 0 ? std::sqrt(v[k] / v[3 + k]) : std::sqrt(v[k]);
+            const ResidEval r = resid_eval(v, b->cs[c]->fp32);
+            for (int k = 0; k < 3; ++k) eps[((size_t)i * nc + c) * 3 + k] = r.eps[k];
         }
     }
     *count = n;

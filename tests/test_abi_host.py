@@ -243,3 +243,13 @@ def test_velocity_nodes_validation():
         assert L.gsis_set_velocity_nodes(h, 2, P(good), 6) == -2          # frozen once sized
     finally:
         L.gsis_destroy(h)
+
+
+def test_build_keeps_packed_fp32_off():
+    """Every HIP source is compiled with the packed-FP32 instructions disabled
+    (-Xclang -target-feature -Xclang -packed-fp32-ops, in that order)."""
+    from paper_2310_18916_amd.csrc import build as B
+    f = B.COMPILE_FLAGS
+    i = f.index("-packed-fp32-ops")
+    assert f[i - 3:i + 1] == ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+    assert "--offload-arch=gfx950" in f

@@ -185,9 +185,9 @@ def test_gsis_parity(name, iters):
         assert_fields(s.moments(), o.moments(), 1e-12, case.solid_mask(), what=f"{name} after correction {it}")
         es, eo = s.residual(), o.residual()
         say(f"  eps gpu {es} oracle {eo}")
-        # u's relative change against a state at rest is rounding noise over rounding noise
-        comps = [0, 1, 2] if it > 0 or np.linalg.norm(case.init[1]) > 0 else [0, 2]
-        assert np.allclose(es[comps], eo[comps], rtol=1e-9, atol=0)
+        # from a state at rest u's denominator is noise on both sides: below the
+        # floor, both report the absolute change
+        assert np.allclose(es, eo, rtol=1e-9, atol=0)
     s.kinetic_step(1)
     o.step(1)
     assert_fields(s.moments(), o.moments(), 1e-12, case.solid_mask(), what=f"{name} final")
