@@ -177,6 +177,18 @@ gsis_status gsis_precondition(gsis_ctx *ctx, int macro_steps, int kinetic_steps)
  * value of that component computed against a denominator above the floor. */
 gsis_status gsis_residual(gsis_ctx *ctx, double eps[3]);
 
+/* Allocation-free variant of gsis_residual, for callers that cannot allocate
+ * device memory at all (HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): same result, bit for bit, but the partial sums of its
+ * reduction live in a static device array of the library instead of the
+ * context's workspace, and the call allocates nothing (no hipMalloc, no
+ * events: it is not phase-timed).  The array holds the partial sums of at most
+ * 4096 blocks of 256 cells, so contexts of more than 1,048,576 cells get
+ * GSIS_EINVAL (checked before anything else).  One array per GPU, shared by
+ * every call on that GPU: calls that overlap on one GPU (other streams or host
+ * threads) race; the context's device must be the current one. */
+gsis_status gsis_residual_noalloc(gsis_ctx *ctx, double eps[3]);
+
 /* Copy the VDF(s) out / in, canonical [cell][node] FP64 in device memory
  * (f1 may be NULL for monatomic).  set_vdf resets the residual snapshot.
  * Asynchronous. */

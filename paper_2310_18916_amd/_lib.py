@@ -45,6 +45,7 @@ SIGNATURES = {
     "gsis_moments": (_I, [_P, _P, _I]),
     "gsis_gsis_correct": (_I, [_P, _I]),
     "gsis_residual": (_I, [_P, _DP]),
+    "gsis_residual_noalloc": (_I, [_P, _DP]),
     "gsis_get_vdf": (_I, [_P, _P, _P]),
     "gsis_set_vdf": (_I, [_P, _P, _P]),
     "gsis_state_size": (_I, [_P, C.POINTER(_SZ)]),

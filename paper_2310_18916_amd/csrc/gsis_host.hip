@@ -778,6 +778,20 @@ gsis_status gsis_residual(gsis_ctx *ctx, double eps[3])
     return residual_finish(ctx, total, &t, eps);
 }
 
+gsis_status gsis_residual_noalloc(gsis_ctx *ctx, double eps[3])
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (resid_blocks(ctx->g) > RESID_STATIC_BLOCKS)
+        return fail(ctx, GSIS_EINVAL, "gsis_residual_noalloc takes at most " +
+                                          std::to_string((long long)RESID_STATIC_BLOCKS * 256) + " cells");
+    if (!ctx->inited) return fail(ctx, GSIS_ESTATE, "initialise the VDF first");
+    if (!eps) return fail(ctx, GSIS_EINVAL, "eps is NULL");
+    double *red = nullptr;
+    HIPCHK(ctx, resid_static_scratch(&red));
+    HIPCHK(ctx, launch_residual(target_of(ctx), ctx->stream, red));
+    return residual_finish(ctx, red + (size_t)resid_blocks(ctx->g) * 6, nullptr, eps);
+}
+
 gsis_status gsis_get_vdf(gsis_ctx *ctx, double *f0_device, double *f1_device)
 {
     if (!ctx) return GSIS_EINVAL;

@@ -57,7 +57,12 @@ hipError_t launch_gsis_macro(const Target &t, int iters, hipStream_t s, int eule
 
 int resid_blocks(const Geo &g);
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);
-hipError_t launch_residual(const Target &t, hipStream_t s);
+// red: partial-sum buffer [resid_blocks + 1][6]; nullptr = each case's workspace buffer
+hipError_t launch_residual(const Target &t, hipStream_t s, double *red = nullptr);
+// blocks of 256 cells the allocation-free residual can take, and the device
+// address of its static partial-sum array on the current device
+constexpr int RESID_STATIC_BLOCKS = 4096;
+hipError_t resid_static_scratch(double **out);
 hipError_t launch_snapshot(const Target &t, hipStream_t s);
 hipError_t launch_hist_advance(int *ctr, hipStream_t s);
 

@@ -173,6 +173,13 @@ class Solver(Context):
         self._check(self.L.gsis_residual(self.h, eps), "gsis_residual")
         return np.array(eps[:])
 
+    def residual_noalloc(self) -> np.ndarray:
+        """gsis_residual_noalloc: the same criterion with the library's static
+        partial-sum array instead of the workspace's (allocates nothing)."""
+        eps = (C.c_double * 3)()
+        self._check(self.L.gsis_residual_noalloc(self.h, eps), "gsis_residual_noalloc")
+        return np.array(eps[:])
+
     def get_vdf(self):
         t = self.torch
         shape = (self.case.ncell, self.case.nvel)

@@ -245,6 +245,28 @@ def test_velocity_nodes_validation():
         L.gsis_destroy(h)
 
 
+def test_noalloc_residual_checks_before_device_work():
+    """gsis_residual_noalloc refuses contexts beyond its static array (more than
+    4096 blocks of 256 cells) before anything else, and otherwise checks the
+    state as gsis_residual does."""
+    L = _lib.lib()
+    eps = (C.c_double * 3)()
+    st, h = _create(_cfg(nx=128, ny=128, nz=64))        # 1,048,576 cells: the largest accepted
+    assert st == 0
+    try:
+        assert L.gsis_residual_noalloc(h, eps) == -2    # accepted size, not initialised
+    finally:
+        L.gsis_destroy(h)
+    st, h = _create(_cfg(nx=128, ny=128, nz=65))        # one plane more
+    assert st == 0
+    try:
+        assert L.gsis_residual_noalloc(h, eps) == -1
+        assert b"at most 1048576 cells" in L.gsis_last_error(h)
+    finally:
+        L.gsis_destroy(h)
+    assert L.gsis_residual_noalloc(None, eps) == -1
+
+
 def test_build_keeps_packed_fp32_off():
     """Every HIP source is compiled with the packed-FP32 instructions disabled
     (-Xclang -target-feature -Xclang -packed-fp32-ops, in that order)."""
