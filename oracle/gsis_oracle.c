@@ -45,6 +45,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <stdio.h>
+#include <omp.h>
 
 #define ORC_NBC 7
 #define ORC_WALL 0
@@ -85,6 +86,9 @@ typedef struct {
     double *f0, *f1;
     double *prev;           /* residual snapshot: rho, ux, uy, uz, Tt per cell */
     double *lastW;          /* W^{n+1} of the last macroscopic solve, [ncell][6] (NULL before one) */
+    double *ntab;           /* [nv][4]: xi_x, xi_y, xi_z, weight of every node */
+    double *mbw;            /* [ORC_NBC][nv] boundary Maxwellians M(1, u_b, T_b) at every node */
+    double in_half[6][ORC_NBC]; /* sum_{xi_n < 0} w |xi_n| M(1, u_b, T_b) per face direction and slot */
     int status;
 } orc_state;
 
@@ -107,13 +111,27 @@ static int cell_index(const orc_state *s, int i, int j, int k)
 
 static void node_xi(const orc_state *s, int v, double xi[3], double *w)
 {
-    int kx = v % s->c.nv[0];
-    int ky = (v / s->c.nv[0]) % s->c.nv[1];
-    int kz = v / (s->c.nv[0] * s->c.nv[1]);
-    xi[0] = s->xi[0][kx];
-    xi[1] = s->xi[1][ky];
-    xi[2] = s->xi[2][kz];
-    *w = s->w1[0][kx] * s->w1[1][ky] * s->w1[2][kz];
+    const double *t = s->ntab + (size_t)v * 4;
+    xi[0] = t[0];
+    xi[1] = t[1];
+    xi[2] = t[2];
+    *w = t[3];
+}
+
+/* Node v (x fastest) of the tensor grid: its velocity and its weight, the
+ * product of the three 1-D weights; tabulated once (node_xi reads it). */
+static void fill_node_table(orc_state *s)
+{
+    for (int v = 0; v < s->nv; ++v) {
+        int kx = v % s->c.nv[0];
+        int ky = (v / s->c.nv[0]) % s->c.nv[1];
+        int kz = v / (s->c.nv[0] * s->c.nv[1]);
+        double *t = s->ntab + (size_t)v * 4;
+        t[0] = s->xi[0][kx];
+        t[1] = s->xi[1][ky];
+        t[2] = s->xi[2][kz];
+        t[3] = s->w1[0][kx] * s->w1[1][ky] * s->w1[2][kz];
+    }
 }
 
 void orc_free(orc_state *s)
@@ -121,9 +139,11 @@ void orc_free(orc_state *s)
     if (!s) return;
     free(s->solid);
     for (int a = 0; a < 3; ++a) { free(s->xi[a]); free(s->w1[a]); }
-    free(s->f0); free(s->f1); free(s->prev); free(s->lastW);
+    free(s->f0); free(s->f1); free(s->prev); free(s->lastW); free(s->mbw); free(s->ntab);
     free(s);
 }
+
+static double maxwellian(double rho, const double u[3], double T, const double xi[3]);
 
 static orc_state *create_state(const orc_cfg *cfg, const unsigned char *solid, int with_vdf)
 {
@@ -170,6 +190,30 @@ static orc_state *create_state(const orc_cfg *cfg, const unsigned char *solid, i
         s->c.nodes[a] = NULL;   /* copied: the caller's array is not kept */
     }
     s->prev = calloc((size_t)s->ncell * 5, sizeof(double));
+    s->ntab = malloc(sizeof(double) * (size_t)s->nv * 4);
+    fill_node_table(s);
+    /* the boundary Maxwellians do not change: tabulated once, with the incoming
+     * half-range mass flux of each (face direction, slot) */
+    s->mbw = malloc(sizeof(double) * (size_t)ORC_NBC * s->nv);
+    for (int b = 0; b < ORC_NBC; ++b)
+        for (int v = 0; v < s->nv; ++v) {
+            double xi[3], w;
+            node_xi(s, v, xi, &w);
+            s->mbw[(size_t)b * s->nv + v] = maxwellian(1.0, cfg->bc_u[b], cfg->bc_T[b], xi);
+        }
+    for (int d = 0; d < 6; ++d)
+        for (int b = 0; b < ORC_NBC; ++b) {
+            int a = d / 2;
+            double sg = (d & 1) ? 1.0 : -1.0;
+            nsum in = {0, 0};
+            for (int v = 0; v < s->nv; ++v) {
+                double xi[3], w;
+                node_xi(s, v, xi, &w);
+                double xn = sg * xi[a];
+                if (xn < 0) nadd(&in, w * (-xn) * s->mbw[(size_t)b * s->nv + v]);
+            }
+            s->in_half[d][b] = nval(&in);
+        }
     if (!with_vdf) return s;
     size_t np = (size_t)s->ncell * s->nv;
     s->f0 = calloc(np, sizeof(double));
@@ -193,6 +237,15 @@ static double maxwellian(double rho, const double u[3], double T, const double x
     double c2 = 0;
     for (int a = 0; a < 3; ++a) c2 += (xi[a] - u[a]) * (xi[a] - u[a]);
     return rho * pow(M_PI * T, -1.5) * exp(-c2 / T);
+}
+
+/* The same value with pre = pow(M_PI * T, -1.5) computed by the caller once
+ * for many nodes (identical operations, so identical results). */
+static double maxwellian_pre(double rho, double pre, const double u[3], double T, const double xi[3])
+{
+    double c2 = 0;
+    for (int a = 0; a < 3; ++a) c2 += (xi[a] - u[a]) * (xi[a] - u[a]);
+    return rho * pre * exp(-c2 / T);
 }
 
 /* ------------------------------------------------------------- moments -- */
@@ -333,11 +386,11 @@ static int solve_dense(int n, double *A, double *b)
  * conservative correction.  The correction of a component X with
  * Maxwellian shape M_X solves  [sum w phi phi^T M_X] lambda = target - sum w phi S_X,
  * target = (rho, rho u, rho |u|^2 + (3/2) rho T_X), brute force over every node. */
-static void cell_params(const orc_state *s, int cell, cellpar *p)
+static void params_from_moments(const orc_state *s, const moms *mom, cellpar *p)
 {
     const orc_cfg *c = &s->c;
     memset(p, 0, sizeof(*p));
-    cell_moments(s, cell, &p->m);
+    p->m = *mom;
     const moms *m = &p->m;
     p->invtau = s->delta * m->rho * pow(m->Tt, 1.0 - c->omega);
     if (c->species == 1) {
@@ -395,6 +448,13 @@ static void cell_params(const orc_state *s, int cell, cellpar *p)
         p->nu_t = (0.5 * c->dr * m->rho * m->Tr - nval(&s1t)) / nval(&mt);
         p->nu_r = (0.5 * c->dr * m->rho * m->T - nval(&s1r)) / nval(&mr);
     }
+}
+
+static void cell_params(const orc_state *s, int cell, cellpar *p)
+{
+    moms m;
+    cell_moments(s, cell, &m);
+    params_from_moments(s, &m, p);
 }
 
 /* The relaxation targets g0, g1 at one node (corrected components mixed
@@ -1214,16 +1274,24 @@ static void equilibrium_face_flux(const orc_state *s, const prim_t *P, int d, in
     double sg = (d & 1) ? 1.0 : -1.0;
     int dia = c->species == 1;
     double sc = c->bc_rho[bc];
+    const double pc = pow(M_PI * P->Tt, -1.5);
+    const double *Mb = s->mbw + (size_t)bc * s->nv;
+    /* the cell's Maxwellian at the outgoing nodes, evaluated once */
+    double *Mc = malloc(sizeof(double) * (size_t)s->nv);
+    for (int v = 0; v < s->nv; ++v) {
+        double xi[3], w;
+        node_xi(s, v, xi, &w);
+        Mc[v] = sg * xi[a] > 0 ? maxwellian_pre(P->rho, pc, P->u, P->Tt, xi) : 0.0;
+    }
     if (c->bc_kind[bc] == ORC_WALL) {
-        nsum out = {0, 0}, in = {0, 0};
+        nsum out = {0, 0};
         for (int v = 0; v < s->nv; ++v) {
             double xi[3], w;
             node_xi(s, v, xi, &w);
             double xn = sg * xi[a];
-            if (xn > 0) nadd(&out, w * xn * maxwellian(P->rho, P->u, P->Tt, xi));
-            else if (xn < 0) nadd(&in, w * (-xn) * maxwellian(1.0, c->bc_u[bc], c->bc_T[bc], xi));
+            if (xn > 0) nadd(&out, w * xn * Mc[v]);
         }
-        sc = nval(&out) / nval(&in);
+        sc = nval(&out) / s->in_half[d][bc];
     }
     nsum acc[6];
     memset(acc, 0, sizeof acc);
@@ -1234,11 +1302,12 @@ static void equilibrium_face_flux(const orc_state *s, const prim_t *P, int d, in
         if (xn == 0.0) continue;
         double a0, a1;
         if (xn > 0) {
-            a0 = maxwellian(P->rho, P->u, P->Tt, xi);
+            a0 = Mc[v];
             a1 = dia ? 0.5 * c->dr * P->Tr * a0 : 0.0;
         } else {
-            boundary_value(c, bc, sc, xi, &a0, &a1);
-            if (!dia) a1 = 0.0;
+            /* the boundary value sc M(1, u_b, T_b) (f1: (dr/2) T_b times it) */
+            a0 = sc * Mb[v];
+            a1 = dia ? 0.5 * c->dr * c->bc_T[bc] * a0 : 0.0;
         }
         double x2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
         double ww = w * xn;
@@ -1248,13 +1317,19 @@ static void equilibrium_face_flux(const orc_state *s, const prim_t *P, int d, in
         nadd(&acc[5], ww * a1);
     }
     for (int k = 0; k < 6; ++k) F[k] = nval(&acc[k]);
+    free(Mc);
 }
 
-/* euler = 1: the same iteration with the Euler constitutive relations (no
+/* The macroscopic solve from the kinetic moments K[cell] of f^{n+1/2} and
+ * the kinetic boundary fluxes Fkin[cell][6][6] (out of the cell through each
+ * boundary face; unused for euler), iters point-Jacobi iterations; returns
+ * the primitive variables of W^{n+1} in Pn[cell] and keeps W^{n+1} in
+ * s->lastW.  Sets s->status to -5 on a non-physical result.
+ * euler = 1: the same iteration with the Euler constitutive relations (no
  * stress, heat flux or HoT, no diffusive part in Gamma and dtau) and the
  * boundary flux of the iterate's own Maxwellian, F_b(W^m) = F_eq(W^m): the
  * initial-field computation of Alg. 1, line 1. */
-static int gsis_correct_mode(orc_state *s, int iters, int euler)
+static int macro_solve(orc_state *s, const moms *K, const double *Fkin, int iters, int euler, prim_t *P)
 {
     const orc_cfg *c = &s->c;
     macpar mp;
@@ -1264,21 +1339,17 @@ static int gsis_correct_mode(orc_state *s, int iters, int euler)
     double hmin = s->h[0];
     if (s->h[1] < hmin) hmin = s->h[1];
     if (s->h[2] < hmin) hmin = s->h[2];
-    moms *K = calloc((size_t)ncell, sizeof(moms));
     double *W = calloc((size_t)ncell * 6, sizeof(double));
     double *Fb = calloc((size_t)ncell * 36, sizeof(double));
     double *hot = calloc((size_t)ncell * 15, sizeof(double));
     double *grad = calloc((size_t)ncell * 9, sizeof(double));
-    prim_t *P = calloc((size_t)ncell, sizeof(prim_t));
     double *R = calloc((size_t)ncell * 6, sizeof(double));
     double *Dc = calloc((size_t)ncell, sizeof(double));
     double *Src = calloc((size_t)ncell, sizeof(double));
 
-    /* kinetic moments of f^{n+1/2}, the starting W and the fixed boundary fluxes */
-    #pragma omp parallel for schedule(dynamic, 16)
+    /* the starting W from the kinetic moments, and the fixed boundary fluxes */
     for (int cell = 0; cell < ncell; ++cell) {
         if (s->solid[cell]) continue;
-        cell_moments(s, cell, &K[cell]);
         const moms *m = &K[cell];
         double u2 = m->u[0] * m->u[0] + m->u[1] * m->u[1] + m->u[2] * m->u[2];
         double *w = W + (size_t)cell * 6;
@@ -1287,10 +1358,7 @@ static int gsis_correct_mode(orc_state *s, int iters, int euler)
         double Er = mp.dia ? 0.5 * c->dr * m->rho * m->Tr : 0.0;
         w[4] = m->rho * u2 + 1.5 * m->rho * m->Tt + Er;
         w[5] = Er;
-        for (int d = 0; d < 6; ++d) {
-            int n = neighbour(s, cell, d);
-            if (n < 0 && !euler) kinetic_face_flux(s, cell, d, -1 - n, Fb + (size_t)cell * 36 + d * 6);
-        }
+        if (!euler) memcpy(Fb + (size_t)cell * 36, Fkin + (size_t)cell * 36, 36 * sizeof(double));
     }
     /* HoT at interior faces (cell, cell + e_a), from W^{n+1/2} */
     for (int cell = 0; cell < ncell; ++cell)
@@ -1331,7 +1399,7 @@ static int gsis_correct_mode(orc_state *s, int iters, int euler)
             if (!s->solid[cell]) prim_of(&mp, W + (size_t)cell * 6, &P[cell]);
         for (int cell = 0; cell < ncell; ++cell)
             if (!s->solid[cell]) cell_grad(s, P, cell, grad + (size_t)cell * 9);
-        #pragma omp parallel for schedule(static)
+        #pragma omp parallel for schedule(dynamic, 16)
         for (int cell = 0; cell < ncell; ++cell) {
             if (s->solid[cell]) continue;
             const prim_t *Pi = &P[cell];
@@ -1380,7 +1448,6 @@ static int gsis_correct_mode(orc_state *s, int iters, int euler)
             if (mp.dia) w[5] += r[5] / (Dmax + Src[cell]);
         }
     }
-    /* Eq. (updatef) */
     int bad = 0;
     for (int cell = 0; cell < ncell; ++cell) {
         if (s->solid[cell]) continue;
@@ -1390,6 +1457,32 @@ static int gsis_correct_mode(orc_state *s, int iters, int euler)
     if (bad) s->status = -5;
     if (!s->lastW) s->lastW = malloc(sizeof(double) * (size_t)ncell * 6);
     memcpy(s->lastW, W, sizeof(double) * (size_t)ncell * 6);
+    free(W); free(Fb); free(hot); free(grad); free(R); free(Dc); free(Src);
+    return s->status;
+}
+
+/* gsis_correct on the stored VDF: kinetic moments and boundary fluxes of
+ * f^{n+1/2}, the macroscopic solve, then Eq. (updatef):
+ * f0 += M(W^{n+1}) - M(W^{n+1/2}), f1 += (dr/2)[Tr' M(W^{n+1}) - Tr M(W^{n+1/2})],
+ * M with the translational temperature (the zero-order solution of the
+ * Chapman-Enskog expansion). */
+static int gsis_correct_mode(orc_state *s, int iters, int euler)
+{
+    const orc_cfg *c = &s->c;
+    int ncell = s->ncell, dia = c->species == 1;
+    moms *K = calloc((size_t)ncell, sizeof(moms));
+    double *Fkin = calloc((size_t)ncell * 36, sizeof(double));
+    prim_t *P = calloc((size_t)ncell, sizeof(prim_t));
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int cell = 0; cell < ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        cell_moments(s, cell, &K[cell]);
+        for (int d = 0; d < 6; ++d) {
+            int n = neighbour(s, cell, d);
+            if (n < 0 && !euler) kinetic_face_flux(s, cell, d, -1 - n, Fkin + (size_t)cell * 36 + d * 6);
+        }
+    }
+    macro_solve(s, K, Fkin, iters, euler, P);
     #pragma omp parallel for schedule(static)
     for (int cell = 0; cell < ncell; ++cell) {
         if (s->solid[cell]) continue;
@@ -1402,10 +1495,10 @@ static int gsis_correct_mode(orc_state *s, int iters, int euler)
             double Mo = maxwellian(m->rho, m->u, m->Tt, xi);
             size_t at = (size_t)cell * s->nv + v;
             s->f0[at] += Mn - Mo;
-            if (mp.dia) s->f1[at] += 0.5 * c->dr * (Pn->Tr * Mn - m->Tr * Mo);
+            if (dia) s->f1[at] += 0.5 * c->dr * (Pn->Tr * Mn - m->Tr * Mo);
         }
     }
-    free(K); free(W); free(Fb); free(hot); free(grad); free(P); free(R); free(Dc); free(Src);
+    free(K); free(Fkin); free(P);
     return s->status;
 }
 
@@ -1490,3 +1583,371 @@ void orc_conductivities(const orc_cfg *c, double out[2])
     out[0] = mp.kt;
     out[1] = mp.kr;
 }
+
+/* ----------------------------------------------------------- streaming -- */
+/* The same iteration for problems whose VDF does not fit in host memory
+ * (source iteration 1/dt = 0, first-order fluxes).  A pass needs of f^n only
+ * the per-cell moments (the reference distribution) and the outgoing
+ * half-range mass flux of each wall face (the wall density), and Eq.
+ * (updatef) adds a Maxwellian difference whose sums can be formed directly:
+ * so the VDF is never stored.  Each velocity node is swept over all cells as
+ * in one_pass, and its values are added to per-cell sums of
+ *   w (1, c, c c, c |c|^2) f0  and  w (1, c) f1,   c = xi - u_r,
+ * taken about the cell's velocity u_r at the start of the pass (so that the
+ * central moments come out without large cancellation), and to per-face sums
+ * of the outgoing flux w xi_n (1, xi, |xi|^2 f0 + f1, f1).  This is the
+ * stored-VDF path's arithmetic in another loop order (pinned to it on small
+ * problems). */
+#define ST_NS 17   /* per-cell sums: 1, c (3), cc (xx yy zz xy xz yz), c|c|^2 (3); f1: 1, c (3) */
+
+typedef struct {
+    orc_state *s;
+    int nface;
+    int *fcell, *fdir, *fbc;   /* boundary faces of fluid cells */
+    int *cface;                /* [ncell][6] face index, or -1 for an interior face */
+    double *ur;                /* [ncell][3] centre of the per-cell sums */
+    nsum *acc;                 /* [ncell][ST_NS] */
+    nsum *fout;                /* [nface][6] */
+    double in_mass[6][ORC_NBC];    /* sum_{xi_n < 0} w |xi_n| M(1, u_b, T_b) per face direction and slot */
+    double in_flux[6][ORC_NBC][6]; /* sum_{xi_n < 0} w xi_n psi M(1, u_b, T_b) (f1 part: (dr/2) T_b M) */
+} orc_stream;
+
+void orc_stream_free(orc_stream *st)
+{
+    if (!st) return;
+    orc_free(st->s);
+    free(st->fcell); free(st->fdir); free(st->fbc); free(st->cface);
+    free(st->ur); free(st->acc); free(st->fout);
+    free(st);
+}
+
+orc_stream *orc_stream_create(const orc_cfg *cfg, const unsigned char *solid)
+{
+    if (cfg->inv_dt != 0.0 || cfg->order != 1) return NULL;
+    orc_stream *st = calloc(1, sizeof(*st));
+    st->s = create_state(cfg, solid, 0);
+    if (!st->s) { free(st); return NULL; }
+    orc_state *s = st->s;
+    const orc_cfg *c = &s->c;
+    int ncell = s->ncell;
+    st->cface = malloc(sizeof(int) * (size_t)ncell * 6);
+    int nf = 0;
+    for (int cell = 0; cell < ncell; ++cell)
+        for (int d = 0; d < 6; ++d) {
+            int n = s->solid[cell] ? 0 : neighbour(s, cell, d);
+            st->cface[cell * 6 + d] = n < 0 ? nf++ : -1;
+        }
+    st->nface = nf;
+    st->fcell = malloc(sizeof(int) * (size_t)(nf + 1));
+    st->fdir = malloc(sizeof(int) * (size_t)(nf + 1));
+    st->fbc = malloc(sizeof(int) * (size_t)(nf + 1));
+    for (int cell = 0; cell < ncell; ++cell)
+        for (int d = 0; d < 6; ++d) {
+            int f = st->cface[cell * 6 + d];
+            if (f < 0) continue;
+            st->fcell[f] = cell;
+            st->fdir[f] = d;
+            st->fbc[f] = -1 - neighbour(s, cell, d);
+        }
+    st->ur = calloc((size_t)ncell * 3, sizeof(double));
+    st->acc = calloc((size_t)ncell * ST_NS, sizeof(nsum));
+    st->fout = calloc((size_t)(nf + 1) * 6, sizeof(nsum));
+    /* the incoming halves of the boundary Maxwellians, once per direction and slot */
+    for (int d = 0; d < 6; ++d)
+        for (int b = 0; b < ORC_NBC; ++b) {
+            int a = d / 2;
+            double sg = (d & 1) ? 1.0 : -1.0;
+            nsum in = {0, 0}, fl[6];
+            memset(fl, 0, sizeof fl);
+            for (int v = 0; v < s->nv; ++v) {
+                double xi[3], w;
+                node_xi(s, v, xi, &w);
+                double xn = sg * xi[a];
+                if (!(xn < 0)) continue;
+                double M = maxwellian(1.0, c->bc_u[b], c->bc_T[b], xi);
+                double M1 = c->species == 1 ? 0.5 * c->dr * c->bc_T[b] * M : 0.0;
+                double x2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+                double ww = w * xn;
+                nadd(&in, w * (-xn) * M);
+                nadd(&fl[0], ww * M);
+                for (int k = 0; k < 3; ++k) nadd(&fl[1 + k], ww * xi[k] * M);
+                nadd(&fl[4], ww * (x2 * M + M1));
+                nadd(&fl[5], ww * M1);
+            }
+            st->in_mass[d][b] = nval(&in);
+            for (int k = 0; k < 6; ++k) st->in_flux[d][b][k] = nval(&fl[k]);
+        }
+    return st;
+}
+
+/* Adds the contribution of value f0 (f1) at node xi, weight w, to the sums of
+ * one cell (centre ur) and of its outgoing boundary faces. */
+static void stream_add(const orc_stream *st, nsum *A, nsum *F, const int *cf, const double ur[3],
+                       const double xi[3], double w, double f0, double f1, int dia)
+{
+    double cp[3] = {xi[0] - ur[0], xi[1] - ur[1], xi[2] - ur[2]};
+    double c2 = cp[0] * cp[0] + cp[1] * cp[1] + cp[2] * cp[2];
+    double wf = w * f0;
+    nadd(&A[0], wf);
+    for (int a = 0; a < 3; ++a) nadd(&A[1 + a], wf * cp[a]);
+    nadd(&A[4], wf * cp[0] * cp[0]);
+    nadd(&A[5], wf * cp[1] * cp[1]);
+    nadd(&A[6], wf * cp[2] * cp[2]);
+    nadd(&A[7], wf * cp[0] * cp[1]);
+    nadd(&A[8], wf * cp[0] * cp[2]);
+    nadd(&A[9], wf * cp[1] * cp[2]);
+    for (int a = 0; a < 3; ++a) nadd(&A[10 + a], wf * cp[a] * c2);
+    if (dia) {
+        double w1 = w * f1;
+        nadd(&A[13], w1);
+        for (int a = 0; a < 3; ++a) nadd(&A[14 + a], w1 * cp[a]);
+    }
+    double x2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+    for (int d = 0; d < 6; ++d) {
+        int f = cf[d];
+        if (f < 0) continue;
+        double xn = ((d & 1) ? 1.0 : -1.0) * xi[d / 2];
+        if (!(xn > 0)) continue;
+        nsum *o = F + (size_t)f * 6;
+        double ww = w * xn;
+        double g1 = dia ? f1 : 0.0;
+        nadd(&o[0], ww * f0);
+        for (int k = 0; k < 3; ++k) nadd(&o[1 + k], ww * xi[k] * f0);
+        nadd(&o[4], ww * (x2 * f0 + g1));
+        nadd(&o[5], ww * g1);
+    }
+    (void)st;
+}
+
+/* Eq. (getmoment) from the sums of a cell: with d = u - u_r = S1 / rho,
+ * sum w c c f = S2 - rho d d and sum w c |c|^2 f = S3 - 2 S2 d - d tr S2 + 2 rho |d|^2 d. */
+static void stream_moments(const orc_stream *st, int cell, moms *m)
+{
+    const nsum *A = st->acc + (size_t)cell * ST_NS;
+    const double *ur = st->ur + (size_t)cell * 3;
+    double S[ST_NS];
+    for (int k = 0; k < ST_NS; ++k) S[k] = nval(&A[k]);
+    double rho = S[0], d[3];
+    for (int a = 0; a < 3; ++a) d[a] = S[1 + a] / rho;
+    m->rho = rho;
+    for (int a = 0; a < 3; ++a) m->u[a] = ur[a] + d[a];
+    double M2[3][3] = {{S[4], S[7], S[8]}, {S[7], S[5], S[9]}, {S[8], S[9], S[6]}};
+    double C[6] = {S[4] - rho * d[0] * d[0], S[5] - rho * d[1] * d[1], S[6] - rho * d[2] * d[2],
+                   S[7] - rho * d[0] * d[1], S[8] - rho * d[0] * d[2], S[9] - rho * d[1] * d[2]};
+    double tr = C[0] + C[1] + C[2];
+    m->Tt = (2.0 / 3.0) * tr / rho;
+    for (int k = 0; k < 6; ++k) m->sig[k] = 2.0 * (C[k] - (k < 3 ? tr / 3.0 : 0.0));
+    double trS = S[4] + S[5] + S[6], dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    for (int a = 0; a < 3; ++a) {
+        double Md = M2[a][0] * d[0] + M2[a][1] * d[1] + M2[a][2] * d[2];
+        m->q[a] = S[10 + a] - 2.0 * Md - d[a] * trS + 2.0 * rho * dd * d[a];
+    }
+    if (st->s->c.species == 1) {
+        double dr = st->s->c.dr;
+        m->Tr = 2.0 * S[13] / (dr * rho);
+        for (int a = 0; a < 3; ++a) m->qr[a] = S[14 + a] - d[a] * S[13];
+        m->T = (3.0 * m->Tt + dr * m->Tr) / (3.0 + dr);
+    } else {
+        m->Tr = m->Tt;
+        m->qr[0] = m->qr[1] = m->qr[2] = 0.0;
+        m->T = m->Tt;
+    }
+}
+
+static void stream_snapshot(orc_stream *st)
+{
+    orc_state *s = st->s;
+    for (int cell = 0; cell < s->ncell; ++cell) {
+        double *pv = s->prev + (size_t)cell * 5;
+        if (s->solid[cell]) { memset(pv, 0, 5 * sizeof(double)); continue; }
+        moms m;
+        stream_moments(st, cell, &m);
+        pv[0] = m.rho; pv[1] = m.u[0]; pv[2] = m.u[1]; pv[3] = m.u[2]; pv[4] = m.Tt;
+    }
+}
+
+/* f0 = M(rho, u, T), f1 = (dr/2) Tr f0 in every fluid cell: the same values
+ * in every cell, so their sums are formed once (about u) and copied. */
+void orc_stream_init_maxwellian(orc_stream *st, double rho, const double u[3], double T, double Tr)
+{
+    orc_state *s = st->s;
+    int dia = s->c.species == 1;
+    nsum A[ST_NS], F[6 * 6];
+    memset(A, 0, sizeof A);
+    memset(F, 0, sizeof F);
+    int cf[6] = {0, 1, 2, 3, 4, 5};   /* all six directions, one sum each */
+    for (int v = 0; v < s->nv; ++v) {
+        double xi[3], w;
+        node_xi(s, v, xi, &w);
+        double f0 = maxwellian(rho, u, T, xi);
+        double f1 = dia ? 0.5 * s->c.dr * Tr * f0 : 0.0;
+        stream_add(st, A, F, cf, u, xi, w, f0, f1, dia);
+    }
+    memset(st->fout, 0, sizeof(nsum) * (size_t)(st->nface + 1) * 6);
+    for (int cell = 0; cell < s->ncell; ++cell) {
+        for (int a = 0; a < 3; ++a) st->ur[cell * 3 + a] = u[a];
+        nsum *dst = st->acc + (size_t)cell * ST_NS;
+        if (s->solid[cell]) { memset(dst, 0, sizeof(nsum) * ST_NS); continue; }
+        memcpy(dst, A, sizeof A);
+    }
+    for (int f = 0; f < st->nface; ++f) memcpy(st->fout + (size_t)f * 6, F + (size_t)st->fdir[f] * 6, 6 * sizeof(nsum));
+    s->status = 0;
+    stream_snapshot(st);
+}
+
+int orc_stream_step(orc_stream *st, int npasses)
+{
+    orc_state *s = st->s;
+    const orc_cfg *c = &s->c;
+    int ncell = s->ncell, nv = s->nv, dia = c->species == 1, nf = st->nface;
+    cellpar *P = malloc(sizeof(cellpar) * (size_t)ncell);
+    double *scale = calloc((size_t)ncell * 6, sizeof(double));
+    int *nb = malloc(sizeof(int) * (size_t)ncell * 6);
+    for (int pass = 0; pass < npasses; ++pass) {
+        #pragma omp parallel for schedule(dynamic, 16)
+        for (int cell = 0; cell < ncell; ++cell) {
+            if (s->solid[cell]) continue;
+            moms m;
+            stream_moments(st, cell, &m);
+            params_from_moments(s, &m, &P[cell]);
+            for (int d = 0; d < 6; ++d) {
+                int n = neighbour(s, cell, d);
+                nb[cell * 6 + d] = n;
+                if (n >= 0) { scale[cell * 6 + d] = 0.0; continue; }
+                int bc = -1 - n, f = st->cface[cell * 6 + d];
+                scale[cell * 6 + d] = c->bc_kind[bc] == ORC_INFLOW ? c->bc_rho[bc]
+                                      : nval(&st->fout[(size_t)f * 6]) / st->in_mass[d][bc];
+            }
+        }
+        for (int cell = 0; cell < ncell; ++cell) {
+            if (s->solid[cell]) continue;
+            if (!isfinite(P[cell].invtau) || !(P[cell].m.rho > 0) || !(P[cell].m.Tt > 0)) s->status = -5;
+            for (int a = 0; a < 3; ++a) st->ur[cell * 3 + a] = P[cell].m.u[a];
+        }
+        memset(st->acc, 0, sizeof(nsum) * (size_t)ncell * ST_NS);
+        memset(st->fout, 0, sizeof(nsum) * (size_t)(nf + 1) * 6);
+        #pragma omp parallel
+        {
+            double *col0 = calloc((size_t)ncell, sizeof(double));
+            double *col1 = calloc((size_t)ncell, sizeof(double));
+            nsum *A = calloc((size_t)ncell * ST_NS, sizeof(nsum));
+            nsum *F = calloc((size_t)(nf + 1) * 6, sizeof(nsum));
+            /* f^n enters the update only times 1/dt = 0: the columns keep the
+             * previous node's (finite) values, or zeros */
+            #pragma omp for schedule(static)
+            for (int v = 0; v < nv; ++v) {
+                double xi[3], w;
+                node_xi(s, v, xi, &w);
+                sweep_node(s, v, P, scale, nb, col0, col1);
+                for (int cell = 0; cell < ncell; ++cell) {
+                    if (s->solid[cell]) continue;
+                    stream_add(st, A + (size_t)cell * ST_NS, F, st->cface + (size_t)cell * 6, st->ur + (size_t)cell * 3,
+                               xi, w, col0[cell], col1[cell], dia);
+                }
+            }
+            /* combine the threads' sums in thread order */
+            #pragma omp for ordered schedule(static, 1)
+            for (int t = 0; t < omp_get_num_threads(); ++t) {
+                #pragma omp ordered
+                {
+                    for (size_t k = 0; k < (size_t)ncell * ST_NS; ++k) { nadd(&st->acc[k], A[k].s); nadd(&st->acc[k], A[k].c); }
+                    for (size_t k = 0; k < (size_t)nf * 6; ++k) { nadd(&st->fout[k], F[k].s); nadd(&st->fout[k], F[k].c); }
+                }
+            }
+            free(col0); free(col1); free(A); free(F);
+        }
+    }
+    free(P); free(scale); free(nb);
+    return s->status;
+}
+
+/* gsis_correct without the VDF: the kinetic boundary flux of each face is its
+ * outgoing sums plus the incoming boundary values (wall density recomputed
+ * from the outgoing mass flux of f^{n+1/2}), the macroscopic solve as on the
+ * stored VDF, and Eq. (updatef) added to the sums node by node. */
+int orc_stream_gsis_correct(orc_stream *st, int iters)
+{
+    orc_state *s = st->s;
+    const orc_cfg *c = &s->c;
+    int ncell = s->ncell, dia = c->species == 1;
+    moms *K = calloc((size_t)ncell, sizeof(moms));
+    double *Fkin = calloc((size_t)ncell * 36, sizeof(double));
+    prim_t *P = calloc((size_t)ncell, sizeof(prim_t));
+    for (int cell = 0; cell < ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        stream_moments(st, cell, &K[cell]);
+        for (int d = 0; d < 6; ++d) {
+            int f = st->cface[cell * 6 + d];
+            if (f < 0) continue;
+            int bc = st->fbc[f];
+            const nsum *o = st->fout + (size_t)f * 6;
+            double sc = c->bc_kind[bc] == ORC_INFLOW ? c->bc_rho[bc] : nval(&o[0]) / st->in_mass[d][bc];
+            double *F = Fkin + (size_t)cell * 36 + d * 6;
+            for (int k = 0; k < 6; ++k) F[k] = nval(&o[k]) + sc * st->in_flux[d][bc][k];
+            if (!dia) F[5] = 0.0;
+        }
+    }
+    macro_solve(s, K, Fkin, iters, 0, P);
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int cell = 0; cell < ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        const moms *m = &K[cell];
+        const prim_t *Pn = &P[cell];
+        double pn = pow(M_PI * Pn->Tt, -1.5), po = pow(M_PI * m->Tt, -1.5);
+        nsum *A = st->acc + (size_t)cell * ST_NS;
+        for (int v = 0; v < s->nv; ++v) {
+            double xi[3], w;
+            node_xi(s, v, xi, &w);
+            double Mn = maxwellian_pre(Pn->rho, pn, Pn->u, Pn->Tt, xi);
+            double Mo = maxwellian_pre(m->rho, po, m->u, m->Tt, xi);
+            double d0 = Mn - Mo;
+            double d1 = dia ? 0.5 * c->dr * (Pn->Tr * Mn - m->Tr * Mo) : 0.0;
+            stream_add(st, A, st->fout, st->cface + (size_t)cell * 6, st->ur + (size_t)cell * 3, xi, w, d0, d1, dia);
+        }
+    }
+    free(K); free(Fkin); free(P);
+    return s->status;
+}
+
+/* out[ncell][14 or 18] as orc_moments; NaN in solid cells. */
+void orc_stream_moments(const orc_stream *st, double *out)
+{
+    const orc_state *s = st->s;
+    int nm = s->c.species == 1 ? 18 : 14;
+    for (int cell = 0; cell < s->ncell; ++cell) {
+        double *o = out + (size_t)cell * nm;
+        if (s->solid[cell]) { for (int k = 0; k < nm; ++k) o[k] = NAN; continue; }
+        moms m;
+        stream_moments(st, cell, &m);
+        o[0] = m.rho; o[1] = m.u[0]; o[2] = m.u[1]; o[3] = m.u[2]; o[4] = m.Tt;
+        for (int k = 0; k < 6; ++k) o[5 + k] = m.sig[k];
+        for (int a = 0; a < 3; ++a) o[11 + a] = m.q[a];
+        if (nm == 18) { o[14] = m.Tr; for (int a = 0; a < 3; ++a) o[15 + a] = m.qr[a]; }
+    }
+}
+
+/* Eq. (convergence_critertion) as orc_residual, from the sums. */
+void orc_stream_residual(orc_stream *st, double eps[3])
+{
+    orc_state *s = st->s;
+    nsum num[3], den[3];
+    memset(num, 0, sizeof num); memset(den, 0, sizeof den);
+    for (int cell = 0; cell < s->ncell; ++cell) {
+        if (s->solid[cell]) continue;
+        moms m;
+        stream_moments(st, cell, &m);
+        const double *pv = s->prev + (size_t)cell * 5;
+        double dr = m.rho - pv[0], dT = m.Tt - pv[4];
+        nadd(&num[0], dr * dr); nadd(&den[0], pv[0] * pv[0]);
+        for (int a = 0; a < 3; ++a) { double du = m.u[a] - pv[1 + a]; nadd(&num[1], du * du); nadd(&den[1], pv[1 + a] * pv[1 + a]); }
+        nadd(&num[2], dT * dT); nadd(&den[2], pv[4] * pv[4]);
+    }
+    double ufloor = (1e3 * 2.220446049250313e-16) * (1e3 * 2.220446049250313e-16) * nval(&den[2]);
+    for (int k = 0; k < 3; ++k) {
+        double n = nval(&num[k]), d = nval(&den[k]);
+        eps[k] = d > (k == 1 ? ufloor : 0.0) ? sqrt(n / d) : sqrt(n);
+    }
+    stream_snapshot(st);
+}
+
+int orc_stream_status(const orc_stream *st) { return st->s->status; }

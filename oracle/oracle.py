@@ -77,6 +77,15 @@ def lib():
                                          C.c_int, D, D]
         L.orc_conductivities.argtypes = [C.POINTER(_Cfg), D]
         L.orc_last_macro_W.argtypes = [P, D]
+        L.orc_stream_create.restype = P
+        L.orc_stream_create.argtypes = [C.POINTER(_Cfg), C.c_void_p]
+        L.orc_stream_free.argtypes = [P]
+        L.orc_stream_init_maxwellian.argtypes = [P, C.c_double, D, C.c_double, C.c_double]
+        L.orc_stream_step.argtypes = [P, C.c_int]
+        L.orc_stream_gsis_correct.argtypes = [P, C.c_int]
+        L.orc_stream_moments.argtypes = [P, D]
+        L.orc_stream_residual.argtypes = [P, D]
+        L.orc_stream_status.argtypes = [P]
         L.orc_nsf_face.argtypes = [P, D, C.c_int, C.c_int, D]
         L.orc_first_pass_nodes.argtypes = [C.POINTER(_Cfg), C.c_void_p, C.c_double, D, C.c_double, C.c_double,
                                            C.POINTER(C.c_int), C.c_int, D, D]
@@ -234,6 +243,51 @@ class Oracle:
         out = np.empty(self.ncell)
         lib().orc_flux_divergence(self.h, v, which, order, _dp(out))
         return out
+
+
+class StreamOracle:
+    """The oracle's iteration without the VDF in memory (source iteration,
+    first order): per-cell moment sums and per-face outgoing fluxes only, so
+    it serves the full-size workloads.  Same calls as Oracle."""
+
+    def __init__(self, case):
+        self.case = case
+        self._cfg = make_cfg(case)
+        self._mask = case.solid_mask()
+        self.h = lib().orc_stream_create(C.byref(self._cfg), self._mask.ctypes.data_as(C.c_void_p))
+        if not self.h:
+            raise ValueError("streaming oracle needs inv_dt = 0 and order 1")
+        self.ncell = case.ncell
+        self.nmom = 18 if case.species == 1 else 14
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_stream_free(self.h)
+            self.h = None
+
+    def init_maxwellian(self):
+        rho, u, T, Tr = self.case.init
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        lib().orc_stream_init_maxwellian(self.h, rho, _dp(u), T, Tr)
+
+    def step(self, n: int = 1) -> int:
+        return lib().orc_stream_step(self.h, n)
+
+    def gsis_correct(self, iters: int) -> int:
+        return lib().orc_stream_gsis_correct(self.h, iters)
+
+    def status(self) -> int:
+        return lib().orc_stream_status(self.h)
+
+    def moments(self) -> np.ndarray:
+        out = np.empty((self.ncell, self.nmom), dtype=np.float64)
+        lib().orc_stream_moments(self.h, _dp(out))
+        return out
+
+    def residual(self) -> np.ndarray:
+        e = np.empty(3, dtype=np.float64)
+        lib().orc_stream_residual(self.h, _dp(e))
+        return e
 
 
 def ref_components(case, rho, u, Tt, Tr, qt, qr, xi: np.ndarray) -> np.ndarray:
