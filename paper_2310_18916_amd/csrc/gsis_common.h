@@ -89,6 +89,8 @@ struct Dev {
     int *perm;         // [nv] internal node -> canonical node
     int *tiles;        // sweep tile list grouped by plane
     int *plane_off;    // [nplane] first tile of each plane in tiles
+    int *tent;         // [8 * tiles] (tile in plane << 3 | octant) entries of a split sweep: plane p's
+                       // entries start at 8 plane_off[p], those without solid cells first
     double *corr;      // [ncell][NCORR]
     double *snap;      // [ncell][NSNAP]
     // macroscopic solve, all structures of arrays [field][ncell] ([field][nface]

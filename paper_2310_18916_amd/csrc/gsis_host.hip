@@ -25,6 +25,7 @@ struct gsis_ctx {
     std::vector<double> xi[3], w[3];
     int tx = 0, ty = 0, tz = 0, bs = 0;
     std::vector<int> tiles, plane_off, plane_cnt, npblk;
+    std::vector<int> tent, nclean;   // split sweep entries (cases with solid cells)
     int vw = 1;
     Dev d;
     Case hcase;              // host copy of the device-resident case record
@@ -95,6 +96,62 @@ int block_nodes(const gsis_ctx *c)
     return sweep_shape_waves(c->fp32, c->tx, c->ty) > 1 ? 64 : c->bs;
 }
 
+// The (tile, octant) entries of every plane for a case with solid cells: an
+// entry is clean when no cell of the tile, nor of its upwind halo (one cell
+// layer on the inflow side of each axis, in the octant's frame), is solid, so
+// the sweep kernel without the solid-cell logic gives the same values there.
+// Clean entries come first within each plane.
+void build_split(gsis_ctx *c)
+{
+    const Geo &g = c->g;
+    c->tent.clear();
+    c->nclean.clear();
+    if (g.nfluid == g.ncell || c->cflag.empty()) return;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    // prefix counts of solid cells: P[k][j][i] = solid cells in [0,i) x [0,j) x [0,k)
+    const size_t sx = nx + 1, sy = ny + 1;
+    std::vector<int> P(sx * sy * (nz + 1), 0);
+    auto at = [&](int i, int j, int k) -> int & { return P[(size_t)i + sx * ((size_t)j + sy * k)]; };
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int s = c->cflag[i + nx * (j + ny * k)] ? 0 : 1;
+                at(i + 1, j + 1, k + 1) = s + at(i, j + 1, k + 1) + at(i + 1, j, k + 1) + at(i + 1, j + 1, k)
+                                          - at(i, j, k + 1) - at(i, j + 1, k) - at(i + 1, j, k) + at(i, j, k);
+            }
+    auto solid_in = [&](int i0, int i1, int j0, int j1, int k0, int k1) {
+        return at(i1, j1, k1) - at(i0, j1, k1) - at(i1, j0, k1) - at(i1, j1, k0) + at(i0, j0, k1) + at(i0, j1, k0)
+                   + at(i1, j0, k0) - at(i0, j0, k0) > 0;
+    };
+    // frame range [lo, hi) along an axis of n cells -> physical range, mirrored for a negative octant half
+    auto phys = [](int lo, int hi, int n, bool neg, int &a, int &b) {
+        lo = std::max(lo, 0);
+        hi = std::min(hi, n);
+        a = neg ? n - hi : lo;
+        b = neg ? n - lo : hi;
+    };
+    const int np = (int)c->plane_cnt.size();
+    c->nclean.assign(np, 0);
+    c->tent.resize(c->tiles.size() * 8);
+    for (int p = 0; p < np; ++p) {
+        std::vector<int> clean, dirty;
+        for (int t = 0; t < c->plane_cnt[p]; ++t) {
+            const int pk = c->tiles[c->plane_off[p] + t];
+            const int x = pk & 0x3ff, y = (pk >> 10) & 0x3ff, z = (pk >> 20) & 0x3ff;
+            for (int o = 0; o < 8; ++o) {
+                int a0, a1, b0, b1, d0, d1;
+                phys(x * c->tx - 1, (x + 1) * c->tx, nx, o & 1, a0, a1);
+                phys(y * c->ty - 1, (y + 1) * c->ty, ny, o & 2, b0, b1);
+                phys(z * c->tz - 1, (z + 1) * c->tz, nz, o & 4, d0, d1);
+                (solid_in(a0, a1, b0, b1, d0, d1) ? dirty : clean).push_back(t << 3 | o);
+            }
+        }
+        c->nclean[p] = (int)clean.size();
+        std::copy(clean.begin(), clean.end(), c->tent.begin() + 8 * (size_t)c->plane_off[p]);
+        std::copy(dirty.begin(), dirty.end(), c->tent.begin() + 8 * (size_t)c->plane_off[p] + clean.size());
+    }
+}
+
 void build_tiles(gsis_ctx *c)
 {
     const Geo &g = c->g;
@@ -115,6 +172,7 @@ void build_tiles(gsis_ctx *c)
         c->plane_cnt[s] = (int)c->tiles.size() - c->plane_off[s];
         c->npblk[s] = c->plane_cnt[s] * 8 * sweep_nvb(g, block_nodes(c));
     }
+    build_split(c);
 }
 
 // neighbour table, boundary faces, node permutation, moment vector width
@@ -233,6 +291,7 @@ size_t layout(gsis_ctx *c, char *base)
     carve(off, d.perm, nv, base);
     carve(off, d.tiles, n, base);
     carve(off, d.plane_off, (size_t)g.nx + g.ny + g.nz, base);
+    carve(off, d.tent, 8 * n, base);
     Case *dc = nullptr;
     carve(off, dc, 1, base);
     if (base) c->dcase = dc;
@@ -273,6 +332,11 @@ Target target_of(const gsis_ctx *c)
     t.mask = c->g.nfluid != c->g.ncell;
     t.rfn = c->g.inv_dt != 0.0 || c->g.order == 2;
     t.mom_nblk[vw_class(c->vw)] = c->g.ncell;
+    if (!c->nclean.empty()) {
+        t.nclean = c->nclean.data();
+        t.pcnt = c->plane_cnt.data();
+        t.nvb = sweep_nvb(c->g, block_nodes(c));
+    }
     t.tx = c->tx;
     t.ty = c->ty;
     t.bs = c->bs;
@@ -288,6 +352,8 @@ hipError_t upload_tiles(gsis_ctx *c)
         e = hipMemcpy(c->d.tiles, c->tiles.data(), c->tiles.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess && !c->plane_off.empty())
         e = hipMemcpy(c->d.plane_off, c->plane_off.data(), c->plane_off.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !c->tent.empty())
+        e = hipMemcpy(c->d.tent, c->tent.data(), c->tent.size() * sizeof(int), hipMemcpyHostToDevice);
     c->hcase.g = c->g;
     c->hcase.bc = c->bc;
     c->hcase.d = c->d;

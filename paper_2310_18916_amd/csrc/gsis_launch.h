@@ -20,6 +20,12 @@ struct Target {
     const int2 *const *pmap = nullptr;   // sweep: block map of every global plane (nullptr for one case)
     const int *npblk = nullptr;          // sweep: blocks of every global plane
     int nplane = 0;
+    // split sweep of one case with solid cells: per plane, the (tile, octant)
+    // entries whose tile and upwind halo hold no solid cell (the first
+    // nclean[p] of the plane's 8 pcnt[p] entries) run the kernel without the
+    // solid-cell logic, the rest the masked one; nullptr: one kernel for all
+    const int *nclean = nullptr, *pcnt = nullptr;
+    int nvb = 0;
     bool fp32 = false, dia = false, mask = false, rfn = false;
     // the moment kernel runs once per vector width (1, 2, 4) over the cases of that width
     const int2 *mom_map[3] = {};

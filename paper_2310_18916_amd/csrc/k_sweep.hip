@@ -100,8 +100,12 @@ __device__ __forceinline__ void ref_dia(const T *p, T cx, T cy, T cz, T itt, T i
 // per step).  Only the tile's own inflow faces are read from the VDF, so a
 // wave grid reads 1/(WX TX) + 1/(WY TY) + 1/TZ of the points again instead of
 // 1/TX + 1/TY + 1/TZ.
+// eoff >= 0: the launch covers the plane's (tile, octant) entries from eoff
+// on (a split sweep: clean entries in the kernel without the solid-cell
+// logic, the rest in the masked one); eoff < 0: every tile of the plane for
+// all 8 octants.
 template <typename T, int TX, int TY, int WX, int WY, bool DIA, bool RFN, bool MASK>
-__global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
+__global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane, int eoff)
 {
     // no automatic contraction: every fused multiply-add is written out, so the
     // operations of a cell update do not depend on the surrounding code
@@ -130,8 +134,15 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane)
     const gptr<const int> cflag = (gptr<const int>)C.d.cflag;
     const int plane_off = ((gptr<const int>)C.d.plane_off)[plane];
     const int vb = b % nvb;
-    const int o = (b / nvb) & 7;
-    const int t = b / (nvb * 8);
+    int o, t;
+    if (eoff >= 0) {
+        const int ent = ((gptr<const int>)C.d.tent)[8 * plane_off + eoff + b / nvb];
+        o = ent & 7;
+        t = ent >> 3;
+    } else {
+        o = (b / nvb) & 7;
+        t = b / (nvb * 8);
+    }
     const int lane = threadIdx.x & 63;
     const int w = GRID ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
     const int wx = w % WX, wy = w / WX;
@@ -471,22 +482,36 @@ static const Shape *find_shape(bool fp32, int tx, int ty)
 }
 
 template <typename T, int TX, int TY, int WX, int WY>
-static void sweep_plane(const Target &t, int p, hipStream_t s)
+static void sweep_launch(const Target &t, int p, hipStream_t s, unsigned nblk, bool mask, int eoff)
 {
     constexpr bool kDia = TX * TY <= 32;   // two register planes only for the small slabs
-    const dim3 grid((unsigned)t.npblk[p]);
+    const dim3 grid(nblk);
     const Span sp{t.cases, t.pmap ? t.pmap[p] : nullptr};
-#define GSIS_SWEEP(D, R, M) hipLaunchKernelGGL((k_sweep<T, TX, TY, WX, WY, D, R, M>), grid, dim3(t.bs), 0, s, GSIS_SPAN(sp), p)
+#define GSIS_SWEEP(D, R, M) \
+    hipLaunchKernelGGL((k_sweep<T, TX, TY, WX, WY, D, R, M>), grid, dim3(t.bs), 0, s, GSIS_SPAN(sp), p, eoff)
     if (t.dia) {
         if constexpr (kDia) {
-            if (t.rfn) { if (t.mask) GSIS_SWEEP(true, true, true); else GSIS_SWEEP(true, true, false); }
-            else { if (t.mask) GSIS_SWEEP(true, false, true); else GSIS_SWEEP(true, false, false); }
+            if (t.rfn) { if (mask) GSIS_SWEEP(true, true, true); else GSIS_SWEEP(true, true, false); }
+            else { if (mask) GSIS_SWEEP(true, false, true); else GSIS_SWEEP(true, false, false); }
         }
     } else {
-        if (t.rfn) { if (t.mask) GSIS_SWEEP(false, true, true); else GSIS_SWEEP(false, true, false); }
-        else { if (t.mask) GSIS_SWEEP(false, false, true); else GSIS_SWEEP(false, false, false); }
+        if (t.rfn) { if (mask) GSIS_SWEEP(false, true, true); else GSIS_SWEEP(false, true, false); }
+        else { if (mask) GSIS_SWEEP(false, false, true); else GSIS_SWEEP(false, false, false); }
     }
 #undef GSIS_SWEEP
+}
+
+template <typename T, int TX, int TY, int WX, int WY>
+static void sweep_plane(const Target &t, int p, hipStream_t s)
+{
+    if (!t.nclean) {
+        sweep_launch<T, TX, TY, WX, WY>(t, p, s, (unsigned)t.npblk[p], t.mask, -1);
+        return;
+    }
+    // split: the clean entries without the solid-cell logic, then the rest
+    const int nc = t.nclean[p], nd = 8 * t.pcnt[p] - nc;
+    if (nc > 0) sweep_launch<T, TX, TY, WX, WY>(t, p, s, (unsigned)(nc * t.nvb), false, 0);
+    if (nd > 0) sweep_launch<T, TX, TY, WX, WY>(t, p, s, (unsigned)(nd * t.nvb), true, nc);
 }
 
 bool sweep_shape_supported(bool fp32, bool dia, int tx, int ty)
