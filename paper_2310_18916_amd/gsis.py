@@ -159,6 +159,12 @@ class Solver(Context):
         self._check(self.L.gsis_precondition(self.h, macro_steps, kinetic_steps), "gsis_precondition")
 
     def moments(self) -> np.ndarray:
+        # through a contiguous device buffer: the library's strided copy straight
+        # into pageable host memory goes row by row
+        return self.moments_device().cpu().numpy()
+
+    def moments_host_copy(self) -> np.ndarray:
+        """gsis_moments straight into host memory (the library's own copy)."""
         out = np.empty((self.case.ncell, self.nmom), dtype=np.float64)
         self._check(self.L.gsis_moments(self.h, out.ctypes.data_as(C.c_void_p), 0), "gsis_moments")
         return out

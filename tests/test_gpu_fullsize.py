@@ -69,7 +69,7 @@ def first_pass_parity(case, dtype, tol):
 
 @pytest.mark.parametrize("workload,dtype,tol", [("c2", "fp64", 1e-13), ("c2", "fp32", 3e-6),
                                                 ("c3", "fp32", 3e-6), ("c3", "fp64", 1e-13),
-                                                ("c4", "fp32", 3e-6)])
+                                                ("c4", "fp32", 3e-6), ("c4", "fp64", 1e-13)])
 def test_full_size_first_pass_matches_oracle(workload, dtype, tol):
     say(f"[full-size first pass] {workload} {dtype}")
     first_pass_parity(getattr(I, workload)(), dtype, tol)
