@@ -136,6 +136,9 @@ struct Span {
 // global address space so that accesses use scalar base + vector offset.
 #define GSIS_GLOBAL_AS __attribute__((address_space(1)))
 template <class T> using gptr = GSIS_GLOBAL_AS T *;
+// Read-only data every lane of a wave reads at the same index: the constant
+// address space, so the reads go through the scalar unit.
+template <class T> using cptr = const GSIS_CONST_AS T *;
 
 // ------------------------------------------------------------ device helpers
 // (case, block within the case) of the calling block; uniform over the block

@@ -104,8 +104,14 @@ __device__ __forceinline__ void ref_dia(const T *p, T cx, T cy, T cz, T itt, T i
 // on (a split sweep: clean entries in the kernel without the solid-cell
 // logic, the rest in the masked one); eoff < 0: every tile of the plane for
 // all 8 octants.
+//
+// Occupancy: the FP64 monatomic 4 x 4 slab is held to 168 VGPRs, three waves
+// per SIMD (measured 5-7% faster than two waves without the few spills this
+// costs); the other shapes take what they need.
 template <typename T, int TX, int TY, int WX, int WY, bool DIA, bool RFN, bool MASK>
-__global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane, int eoff)
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 && TX * TY == 16 && !DIA) ? 3 : 1)))
+void k_sweep(GSIS_SPAN_ARGS, int plane, int eoff)
 {
     // no automatic contraction: every fused multiply-add is written out, so the
     // operations of a cell update do not depend on the surrounding code
@@ -113,6 +119,9 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane, int eo
     constexpr int NWV = WX * WY;                  // waves sharing the nodes of a block
     constexpr bool GRID = NWV > 1;
     constexpr int NPL = DIA ? 36 : 16;            // parameters per cell kept in LDS
+    // the last two LDS slots of a cell (unused by the parameters) carry the
+    // density scales of its x- and y-upwind faces, for the tile's inflow faces
+    constexpr int SXS = NPL - 2, SYS = NPL - 1;
     constexpr int NC = TX * TY;                   // cells per slab
     constexpr int NM = NC * NPL;                  // parameter words per slab
     constexpr int MPT = (NM + 63) / 64;           // words per thread for the smallest block (64)
@@ -132,11 +141,15 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane, int eo
     constexpr bool F32 = sizeof(T) == 4;
     const int TZ = C.tz, nvb = C.nvb;
     const gptr<const int> cflag = (gptr<const int>)C.d.cflag;
-    const int plane_off = ((gptr<const int>)C.d.plane_off)[plane];
+    // data every lane reads at the same index (neighbour flags, face scales, the
+    // tile lists) go through the scalar unit: the constant address space, as for
+    // the case record (none of it changes while the sweep runs)
+    const cptr<int> cflags = (cptr<int>)C.d.cflag;
+    const int plane_off = ((cptr<int>)C.d.plane_off)[plane];
     const int vb = b % nvb;
     int o, t;
     if (eoff >= 0) {
-        const int ent = ((gptr<const int>)C.d.tent)[8 * plane_off + eoff + b / nvb];
+        const int ent = ((cptr<int>)C.d.tent)[8 * plane_off + eoff + b / nvb];
         o = ent & 7;
         t = ent >> 3;
     } else {
@@ -150,7 +163,7 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane, int eo
     const int ml = GRID ? lane : (int)threadIdx.x;
     const int l = vb * bs + ml;
     const bool active = l < g.osize[o];           // inactive threads still join loads and barriers
-    const int packed = ((gptr<const int>)C.d.tiles)[plane_off + t];
+    const int packed = ((cptr<int>)C.d.tiles)[plane_off + t];
     const int tx = packed & 0x3ff, ty = (packed >> 10) & 0x3ff, tz = (packed >> 20) & 0x3ff;
     const int sx = o & 1, sy = (o >> 1) & 1, sz = (o >> 2) & 1;
     const int dxu = sx, dyu = 2 + sy, dzu = 4 + sz;   // upwind faces
@@ -183,9 +196,30 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane, int eo
     const gptr<const T> rs1 = (gptr<const T>)C.d.rs1;
     const T rsc = (T)g.rs_scale;
     const gptr<const T> par = F32 ? (gptr<const T>)C.d.parf : (gptr<const T>)C.d.par;
-    const gptr<const T> fsc = F32 ? (gptr<const T>)C.d.cfs32 : (gptr<const T>)C.d.cfs64;   // [ncell][6] incoming density scale
+    const cptr<T> fsc = F32 ? (cptr<T>)C.d.cfs32 : (cptr<T>)C.d.cfs64;   // [ncell][6] incoming density scale
+    const gptr<const T> fscv = F32 ? (gptr<const T>)C.d.cfs32 : (gptr<const T>)C.d.cfs64;   // the same, per lane
     const gptr<const T> mb = F32 ? (gptr<const T>)C.d.mb32 : (gptr<const T>)C.d.mb64;
     const gptr<const T> mb1 = F32 ? (gptr<const T>)C.d.mb1_32 : (gptr<const T>)C.d.mb1_64;
+    // VDF rows by pointer: row r of buffer p starts at p + r nv elements, and a
+    // lane adds the 32-bit byte offset of its node (every VDF access is a
+    // uniform row address plus this lane offset)
+    const size_t rowb = nv * sizeof(T);
+    const unsigned loff = (unsigned)node * (unsigned)sizeof(T);
+    auto rowp = [&](auto base, int r) -> gptr<char> { return (gptr<char>)base + (size_t)r * rowb; };
+    auto lane_at = [&](gptr<char> rp) -> T * { return (T *)(rp + loff); };
+    // boundary Maxwellians of this lane's node, for the whole tile: the box
+    // faces upwind along x, y, z and the solid surface
+    T mbu[3], mbu1[3], mbs = T(0), mbs1 = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int d = a == 0 ? dxu : (a == 1 ? dyu : dzu);
+        mbu[a] = mb[(size_t)d * nv + node];
+        mbu1[a] = DIA ? mb1[(size_t)d * nv + node] : T(0);
+    }
+    if (MASK) {
+        mbs = mb[(size_t)6 * nv + node];
+        if (DIA) mbs1 = mb1[(size_t)6 * nv + node];
+    }
 
     // physical cell of tile-frame position, clamped into the domain (positions
     // outside are never computed; clamping keeps every speculative load valid)
@@ -201,30 +235,42 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane, int eo
     // unconditional, so they can be issued a slab ahead.
     // With handed (a face inside a wave grid) the neighbour's value arrives in
     // LDS later: only the wall value and flag are prepared here.
-    auto inflow = [&](int c, int kx, int ky, int kz, int d, T &v0, T &v1, bool handed, bool &wall) {
+    // upwind neighbour of cell c across face d (c itself where the face is on the box)
+    auto upwind_of = [&](int c, int kx, int ky, int kz, int d, bool &outside) -> int {
         const int a = d >> 1;
         const int ii = i0 + kx, jj = j0 + ky, kk = k0 + kz;   // tile frame; upwind = one step back
-        const bool outside = (a == 0 ? ii : (a == 1 ? jj : kk)) == 0;
+        outside = (a == 0 ? ii : (a == 1 ? jj : kk)) == 0;
         const int step = a == 0 ? 1 : (a == 1 ? nx : nx * ny);
-        const int nb = outside ? c : ((d & 1) ? c + step : c - step);
-        const T fv0 = handed ? T(0) : __builtin_nontemporal_load((const T *)&f0[(size_t)nb * nv + node]);
-        const T sc = fsc[(size_t)c * 6 + d];
-        const int bcs = outside ? d : 6;
-        const T m0 = mb[(size_t)bcs * nv + node];
-        wall = outside;
-        if (MASK) wall = wall || !cflag[nb];
-        v0 = wall ? sc * m0 : fv0;
+        return outside ? c : ((d & 1) ? c + step : c - step);
+    };
+    // the neighbour's value across an x or y inflow face of the slab (the wall
+    // value of a face on the box or a solid cell is formed where it is used,
+    // from the face scale staged with the slab's parameters)
+    auto inflow = [&](int c, int kx, int ky, int kz, int d, T &v0, T &v1, bool handed) {
+        bool outside;
+        const int nb = upwind_of(c, kx, ky, kz, d, outside);
+        v0 = handed ? T(0) : __builtin_nontemporal_load(lane_at(rowp(f0, nb)));
+        if (DIA) v1 = handed ? T(0) : __builtin_nontemporal_load(lane_at(rowp(f1, nb)));
+    };
+    // the value entering the tile's first slab through its z face: the
+    // neighbour's or the boundary value rho_b M_b(xi) of the face
+    auto inflow_z = [&](int c, int kx, int ky, T &v0, T &v1) {
+        bool outside;
+        const int nb = upwind_of(c, kx, ky, 0, dzu, outside);
+        const T fv0 = __builtin_nontemporal_load(lane_at(rowp(f0, nb)));
+        const T sc = fsc[(size_t)c * 6 + dzu];
+        const bool wall = outside || (MASK && !cflags[nb]);
+        v0 = wall ? sc * (outside ? mbu[2] : mbs) : fv0;
         if (DIA) {
-            const T fv1 = handed ? T(0) : __builtin_nontemporal_load((const T *)&f1[(size_t)nb * nv + node]);
-            const T m1 = mb1[(size_t)bcs * nv + node];
-            v1 = wall ? sc * m1 : fv1;
+            const T fv1 = __builtin_nontemporal_load(lane_at(rowp(f1, nb)));
+            v1 = wall ? sc * (outside ? mbu1[2] : mbs1) : fv1;
         }
     };
     // boundary value of face d of cell c when the in-tile upwind cell is solid
     auto solid_face = [&](int c, int d, T &v0, T &v1) {
         const T sc = fsc[(size_t)c * 6 + d];
-        v0 = sc * mb[(size_t)6 * nv + node];
-        if (DIA) v1 = sc * mb1[(size_t)6 * nv + node];
+        v0 = sc * mbs;
+        if (DIA) v1 = sc * mbs1;
     };
 
     T mreg[MPT];
@@ -236,17 +282,21 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane, int eo
             const int e = min(ml + r * bs, NM - 1);
             const int cc = e / NPL, k = e % NPL;
             const int c = cell_of(cc % TX, cc / TX, kz);
-            mreg[r] = par[(size_t)c * NPAR + (k < NPAR ? k : 0)];
+            mreg[r] = k < SXS ? par[(size_t)c * NPAR + k] : fscv[(size_t)c * 6 + (k == SXS ? dxu : dyu)];
         }
         // flag word of a cell: bit 0 fluid and inside the domain, bit 1 its in-tile
-        // z-upwind cell is solid (carried with this slab so that compute never
-        // reads the other buffer, which the next slab's data may be overwriting)
+        // z-upwind cell is solid, bits 2 and 3 the cell of the previous column
+        // (row) that sends the slab's x (y) inflow is solid (carried with this
+        // slab so that compute never reads the other buffer, which the next
+        // slab's data may be overwriting)
         const int e = min(ml, NC - 1);
         const int c = cell_of(e % TX, e / TX, kz);
         const int cz = cell_of(e % TX, e / TX, kz > 0 ? kz - 1 : 0);
         const int fl = (MASK ? cflag[c] : 1) && inside(e % TX, e / TX, kz);
         const int zs = (MASK && kz > 0) ? !cflag[cz] : 0;
-        freg = fl | (zs << 1);
+        const int xs = (MASK && e % TX == 0 && i0 > 0) ? !cflag[sx ? c + 1 : c - 1] : 0;
+        const int ys = (MASK && e / TX == 0 && j0 > 0) ? !cflag[sy ? c + nx : c - nx] : 0;
+        freg = fl | (zs << 1) | (xs << 2) | (ys << 3);
     };
     auto store_meta = [&](int buf) {
 #pragma unroll
@@ -261,13 +311,13 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane, int eo
     T pl0[TY][TX], pl1[TY][TX];                 // z-upwind plane, then the slab just computed
     T xin0[TY], xin1[TY], yin0[TX], yin1[TX];   // inflow faces of the current slab
     T xnx0[TY], xnx1[TY], ynx0[TX], ynx1[TX];   // ... and of the next slab
-    bool xwl[TY], ywl[TX], xwn[TY], ywn[TX];    // their wall flags (used for faces handed in LDS)
     const bool xhand = GRID && wx > 0, yhand = GRID && wy > 0;   // uniform per wave
-    auto issue_xy = [&](int kz, T *x0, T *x1, T *y0, T *y1, bool *xw, bool *yw) {
+    const bool xbox = i0 == 0, ybox = j0 == 0;  // the slab column's x (y) inflow face is on the box
+    auto issue_xy = [&](int kz, T *x0, T *x1, T *y0, T *y1) {
 #pragma unroll
-        for (int ky = 0; ky < TY; ++ky) inflow(cell_of(0, ky, kz), 0, ky, kz, dxu, x0[ky], x1[ky], xhand, xw[ky]);
+        for (int ky = 0; ky < TY; ++ky) inflow(cell_of(0, ky, kz), 0, ky, kz, dxu, x0[ky], x1[ky], xhand);
 #pragma unroll
-        for (int kx = 0; kx < TX; ++kx) inflow(cell_of(kx, 0, kz), kx, 0, kz, dyu, y0[kx], y1[kx], yhand, yw[kx]);
+        for (int kx = 0; kx < TX; ++kx) inflow(cell_of(kx, 0, kz), kx, 0, kz, dyu, y0[kx], y1[kx], yhand);
     };
 
     issue_meta(0);
@@ -275,16 +325,12 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane, int eo
 #pragma unroll
     for (int ky = 0; ky < TY; ++ky)
 #pragma unroll
-        for (int kx = 0; kx < TX; ++kx) {
-            bool wz;
-            inflow(cell_of(kx, ky, 0), kx, ky, 0, dzu, pl0[ky][kx], pl1[ky][kx], false, wz);
-        }
-    issue_xy(0, xin0, xin1, yin0, yin1, xwl, ywl);
+        for (int kx = 0; kx < TX; ++kx) inflow_z(cell_of(kx, ky, 0), kx, ky, pl0[ky][kx], pl1[ky][kx]);
+    issue_xy(0, xin0, xin1, yin0, yin1);
     __syncthreads();
 
     // per-tile strides of the octant frame: cell = slab base + kx dxs + ky dys
     const int dxs = sx ? -1 : 1, dys = sy ? -nx : nx;
-    const unsigned lnode = (unsigned)node;
     // slabs of this tile and steps of the block (uniform over the block)
     const int TZe = max(0, min(TZ, nz - k0));
     const int nstep = TZe + (WX - 1) + (WY - 1);
@@ -297,33 +343,31 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane, int eo
         const bool more = run && kz + 1 < TZe;
         if (more) {
             issue_meta(kz + 1);
-            issue_xy(kz + 1, xnx0, xnx1, ynx0, ynx1, xwn, ywn);
+            issue_xy(kz + 1, xnx0, xnx1, ynx0, ynx1);
         }
         const int kk = k0 + kz;
         const int cbase = (sx ? nx - 1 - i0 : i0) + nx * ((sy ? ny - 1 - j0 : j0) + ny * (sz ? nz - 1 - kk : kk));
+        // cell (kx, ky) of the slab is row cbase + kx dxs + ky dys; its row pointer
+        // is the slab's plus constant strides (a dead cell's is the sink row's)
+        const ptrdiff_t sxb = (ptrdiff_t)dxs * (ptrdiff_t)rowb, syb = (ptrdiff_t)dys * (ptrdiff_t)rowb;
+        auto cellp = [&](auto base, int kx, int ky, bool live) -> gptr<char> {
+            return live ? rowp(base, cbase) + ((ptrdiff_t)kx * sxb + (ptrdiff_t)ky * syb) : rowp(base, ncell);
+        };
         if (GRID && run) {
             // exit faces of the upwind waves' slab kz, written at the previous step
             const int pb = (st - 1) & 1;
             if (xhand) {
 #pragma unroll
                 for (int ky = 0; ky < TY; ++ky) {
-                    const T h0 = xface[0][xr][pb][ky][lane];
-                    xin0[ky] = (MASK && xwl[ky]) ? xin0[ky] : h0;
-                    if (DIA) {
-                        const T h1 = xface[ND - 1][xr][pb][ky][lane];
-                        xin1[ky] = (MASK && xwl[ky]) ? xin1[ky] : h1;
-                    }
+                    xin0[ky] = xface[0][xr][pb][ky][lane];
+                    if (DIA) xin1[ky] = xface[ND - 1][xr][pb][ky][lane];
                 }
             }
             if (yhand) {
 #pragma unroll
                 for (int kx = 0; kx < TX; ++kx) {
-                    const T h0 = yface[0][yr][pb][kx][lane];
-                    yin0[kx] = (MASK && ywl[kx]) ? yin0[kx] : h0;
-                    if (DIA) {
-                        const T h1 = yface[ND - 1][yr][pb][kx][lane];
-                        yin1[kx] = (MASK && ywl[kx]) ? yin1[kx] : h1;
-                    }
+                    yin0[kx] = yface[0][yr][pb][kx][lane];
+                    if (DIA) yin1[kx] = yface[ND - 1][yr][pb][kx][lane];
                 }
             }
         }
@@ -344,9 +388,8 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane, int eo
                         const int e = ky * TX + kx;
                         const int flag = MASK ? __builtin_amdgcn_readfirstlane(sflag[w][buf][e]) : 1;
                         const bool live = MASK ? (flag & 1) != 0 : (i0 + kx < nx && j0 + ky < ny);
-                        const int row = live ? cbase + kx * dxs + ky * dys : ncell;
-                        rv0[ky][kx] = __builtin_nontemporal_load((const T *)&rs0[(size_t)row * nv + lnode]);
-                        if (DIA) rv1[ky][kx] = __builtin_nontemporal_load((const T *)&rs1[(size_t)row * nv + lnode]);
+                        rv0[ky][kx] = __builtin_nontemporal_load(lane_at(cellp(rs0, kx, ky, live)));
+                        if (DIA) rv1[ky][kx] = __builtin_nontemporal_load(lane_at(cellp(rs1, kx, ky, live)));
                     }
                 }
             }
@@ -386,9 +429,8 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane, int eo
                     const bool live = MASK ? (flag & 1) != 0 : (i0 + kx < nx && j0 + ky < ny);
                     const int cell = cbase + kx * dxs + ky * dys;
                     const int cread = live ? cell : 0;   // in-range index for side reads
-                    const int row = live ? cell : ncell;
-                    const gptr<T> c0 = f0 + (size_t)row * nv;   // uniform row; the lane adds its node
-                    const gptr<T> c1 = DIA ? f1 + (size_t)row * nv : c0;
+                    const gptr<char> c0 = cellp(f0, kx, ky, live);   // uniform row; the lane adds its node
+                    const gptr<char> c1 = DIA ? cellp(f1, kx, ky, live) : c0;
                     const T *p = PRE ? rest : &spar[w][buf][e * NPL];
                     const T cx = xix - (PRE ? cur[0] : p[0]), cy = xiy - (PRE ? cur[1] : p[1]), cz = xiz - (PRE ? cur[2] : p[2]);
                     T gt0, gt1 = T(0), invtau;
@@ -404,16 +446,28 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane, int eo
                         num0 = fma(rsc, rv0[ky][kx], num0);
                         if (DIA) num1 = fma(rsc, rv1[ky][DIA ? kx : 0], num1);
                     } else if constexpr (RFN) {
-                        num0 = fma(rsc, __builtin_nontemporal_load((const T *)&rs0[(size_t)row * nv + lnode]), num0);
-                        if (DIA) num1 = fma(rsc, __builtin_nontemporal_load((const T *)&rs1[(size_t)row * nv + lnode]), num1);
+                        num0 = fma(rsc, __builtin_nontemporal_load(lane_at(cellp(rs0, kx, ky, live))), num0);
+                        if (DIA) num1 = fma(rsc, __builtin_nontemporal_load(lane_at(cellp(rs1, kx, ky, live))), num1);
                     }
                     T F0, F1 = T(0);
-                    if (kx == 0) { F0 = xin0[ky]; if (DIA) F1 = xin1[ky]; }
+                    if (kx == 0) {
+                        if (xbox || (MASK && (flag & 4))) {   // a wall: the box face or a solid cell
+                            const T sc = spar[w][buf][e * NPL + SXS];
+                            F0 = sc * (xbox ? mbu[0] : mbs);
+                            if (DIA) F1 = sc * (xbox ? mbu1[0] : mbs1);
+                        } else { F0 = xin0[ky]; if (DIA) F1 = xin1[ky]; }
+                    }
                     else if (MASK && !(__builtin_amdgcn_readfirstlane(sflag[w][buf][e - 1]) & 1)) solid_face(cread, dxu, F0, F1);
                     else { F0 = pl0[ky][kx - 1]; if (DIA) F1 = pl1[ky][kx - 1]; }
                     num0 = fma(ax, F0, num0);
                     if (DIA) num1 = fma(ax, F1, num1);
-                    if (ky == 0) { F0 = yin0[kx]; if (DIA) F1 = yin1[kx]; }
+                    if (ky == 0) {
+                        if (ybox || (MASK && (flag & 8))) {
+                            const T sc = spar[w][buf][e * NPL + SYS];
+                            F0 = sc * (ybox ? mbu[1] : mbs);
+                            if (DIA) F1 = sc * (ybox ? mbu1[1] : mbs1);
+                        } else { F0 = yin0[kx]; if (DIA) F1 = yin1[kx]; }
+                    }
                     else if (MASK && !(__builtin_amdgcn_readfirstlane(sflag[w][buf][e - TX]) & 1)) solid_face(cread, dyu, F0, F1);
                     else { F0 = pl0[ky - 1][kx]; if (DIA) F1 = pl1[ky - 1][kx]; }
                     num0 = fma(ay, F0, num0);
@@ -424,11 +478,11 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane, int eo
                     if (DIA) num1 = fma(az, F1, num1);
                     const T den = den0 + invtau;
                     const T v0 = Arith<T>::div(num0, den);
-                    __builtin_nontemporal_store(v0, (T *)&c0[lnode]);
+                    __builtin_nontemporal_store(v0, lane_at(c0));
                     pl0[ky][kx] = v0;
                     if (DIA) {
                         const T v1 = Arith<T>::div(num1, den);
-                        __builtin_nontemporal_store(v1, (T *)&c1[lnode]);
+                        __builtin_nontemporal_store(v1, lane_at(c1));
                         pl1[ky][kx] = v1;
                     }
                 }
@@ -456,9 +510,9 @@ __global__ __launch_bounds__(256) void k_sweep(GSIS_SPAN_ARGS, int plane, int eo
         __syncthreads();
         if (more) {
 #pragma unroll
-            for (int ky = 0; ky < TY; ++ky) { xin0[ky] = xnx0[ky]; if (DIA) xin1[ky] = xnx1[ky]; xwl[ky] = xwn[ky]; }
+            for (int ky = 0; ky < TY; ++ky) { xin0[ky] = xnx0[ky]; if (DIA) xin1[ky] = xnx1[ky]; }
 #pragma unroll
-            for (int kx = 0; kx < TX; ++kx) { yin0[kx] = ynx0[kx]; if (DIA) yin1[kx] = ynx1[kx]; ywl[kx] = ywn[kx]; }
+            for (int kx = 0; kx < TX; ++kx) { yin0[kx] = ynx0[kx]; if (DIA) yin1[kx] = ynx1[kx]; }
         }
     }
 }
