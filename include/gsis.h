@@ -31,8 +31,9 @@
  *    where a call says it synchronises.
  *  - One context per host thread; calls on one context must not overlap.
  *  - Canonical external layouts: cells x fastest, c = i + nx (j + ny k);
- *    velocity nodes x fastest, v = kx + nvx (ky + nvy kz); a VDF is
- *    [cell][node].  The internal octant-grouped VDF layout is not exposed.
+ *    velocity nodes x fastest, v = kx + nvx (ky + nvy kz) (a node list: its
+ *    own order); a VDF is [cell][node].  The internal octant-grouped VDF
+ *    layout is not exposed.
  */
 #ifndef GSIS_H
 #define GSIS_H
@@ -118,6 +119,19 @@ gsis_status gsis_set_solid_mask(gsis_ctx *ctx, const uint8_t *mask, size_t n);
  * keeps working.  Must precede gsis_workspace_size; EINVAL on a bad axis,
  * count or node array, ESTATE once the workspace is sized. */
 gsis_status gsis_set_velocity_nodes(gsis_ctx *ctx, int axis, const double *nodes, int n);
+
+/* General velocity set (Sec. 3.1: a locally refined or unstructured velocity
+ * mesh, whose cells are represented by one node each): nodes is a host array
+ * [n][4] of (xi_x, xi_y, xi_z, w), w > 0 the volume of the node's velocity
+ * cell (the quadrature weight); copied.  Replaces the tensor grid of the
+ * configuration: the node count becomes n (2 <= n <= 2^24) and canonical
+ * node k is entry k of the list (gsis_get_vdf, gsis_set_vdf,
+ * gsis_get_vdf_nodes).  Nothing factors per axis any more, so moments,
+ * relaxation parameters and equilibrium wall fluxes are summed node by node.
+ * Not accepted by gsis_batch_create.  Must precede gsis_workspace_size;
+ * EINVAL on a bad count or a non-finite node or weight, ESTATE once the
+ * workspace is sized (and from gsis_set_velocity_nodes afterwards). */
+gsis_status gsis_set_velocity_list(gsis_ctx *ctx, const double *nodes, int n);
 
 /* Boundary condition of slot face (GSIS_FACE_*): kind GSIS_DIFFUSE_WALL with
  * wall velocity u and temperature T (rho ignored; the wall density is set so
@@ -271,7 +285,8 @@ const char *gsis_last_error(const gsis_ctx *ctx);
 typedef struct gsis_batch gsis_batch;
 
 /* ncases in 1..4096 distinct, unbound contexts (host array).  EINVAL if they
- * differ in precision or gas, or have inv_dt != 0 or order 2. */
+ * differ in precision or gas, or have inv_dt != 0, order 2 or a velocity node
+ * list. */
 gsis_status gsis_batch_create(gsis_batch **out, gsis_ctx *const *cases, int ncases);
 gsis_status gsis_batch_destroy(gsis_batch *b);
 /* Bytes of device memory the batch needs (all cases plus launch tables and

@@ -74,6 +74,14 @@ typedef struct {
      * the Venkatakrishnan constant K (eps^2 = (K h)^3; K < 0: no limiter) */
     int order;
     double limiter_k;
+    /* optional general velocity set (Sec. 3.1: a locally refined or
+     * unstructured velocity mesh, each node standing for one velocity cell):
+     * nlist > 0 nodes, node_list[4 k + 0..2] = xi of node k and
+     * node_list[4 k + 3] = its weight, the volume of its cell.  Replaces the
+     * tensor grid (nv, vmin, vmax, nodes are then ignored); read once, at
+     * creation. */
+    int nlist;
+    const double *node_list;
 } orc_cfg;
 
 typedef struct {
@@ -119,9 +127,14 @@ static void node_xi(const orc_state *s, int v, double xi[3], double *w)
 }
 
 /* Node v (x fastest) of the tensor grid: its velocity and its weight, the
- * product of the three 1-D weights; tabulated once (node_xi reads it). */
-static void fill_node_table(orc_state *s)
+ * product of the three 1-D weights; or node v of a general node list as
+ * given.  Tabulated once (node_xi reads it). */
+static void fill_node_table(orc_state *s, const double *list)
 {
+    if (list) {
+        memcpy(s->ntab, list, sizeof(double) * (size_t)s->nv * 4);
+        return;
+    }
     for (int v = 0; v < s->nv; ++v) {
         int kx = v % s->c.nv[0];
         int ky = (v / s->c.nv[0]) % s->c.nv[1];
@@ -150,7 +163,13 @@ static orc_state *create_state(const orc_cfg *cfg, const unsigned char *solid, i
     if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return NULL;
     if (cfg->order != 1 && cfg->order != 2) return NULL;
     if (!isfinite(cfg->limiter_k)) return NULL;
-    for (int a = 0; a < 3; ++a) {
+    const int list = cfg->nlist > 0;
+    if (cfg->nlist < 0 || (list && !cfg->node_list)) return NULL;
+    for (int k = 0; k < cfg->nlist; ++k) {
+        const double *t = cfg->node_list + (size_t)k * 4;
+        if (!isfinite(t[0]) || !isfinite(t[1]) || !isfinite(t[2]) || !(t[3] > 0) || !isfinite(t[3])) return NULL;
+    }
+    for (int a = 0; a < 3 && !list; ++a) {
         if (cfg->nv[a] < 2) return NULL;
         if (cfg->nodes[a]) {
             for (int k = 0; k < cfg->nv[a]; ++k)
@@ -162,14 +181,14 @@ static orc_state *create_state(const orc_cfg *cfg, const unsigned char *solid, i
     orc_state *s = calloc(1, sizeof(*s));
     s->c = *cfg;
     s->ncell = cfg->nx * cfg->ny * cfg->nz;
-    s->nv = cfg->nv[0] * cfg->nv[1] * cfg->nv[2];
+    s->nv = list ? cfg->nlist : cfg->nv[0] * cfg->nv[1] * cfg->nv[2];
     s->h[0] = cfg->lx / cfg->nx;
     s->h[1] = cfg->ly / cfg->ny;
     s->h[2] = cfg->lz / cfg->nz;
     s->delta = sqrt(M_PI) / (2.0 * cfg->Kn);
     s->solid = calloc((size_t)s->ncell, 1);
     if (solid) memcpy(s->solid, solid, (size_t)s->ncell);
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < 3 && !list; ++a) {
         int n = cfg->nv[a];
         double d = (cfg->vmax[a] - cfg->vmin[a]) / (n - 1);
         s->xi[a] = malloc(sizeof(double) * n);
@@ -191,7 +210,9 @@ static orc_state *create_state(const orc_cfg *cfg, const unsigned char *solid, i
     }
     s->prev = calloc((size_t)s->ncell * 5, sizeof(double));
     s->ntab = malloc(sizeof(double) * (size_t)s->nv * 4);
-    fill_node_table(s);
+    fill_node_table(s, list ? cfg->node_list : NULL);
+    for (int a = 0; a < 3; ++a) s->c.nodes[a] = NULL;
+    s->c.node_list = NULL;   /* copied: the caller's array is not kept */
     /* the boundary Maxwellians do not change: tabulated once, with the incoming
      * half-range mass flux of each (face direction, slot) */
     s->mbw = malloc(sizeof(double) * (size_t)ORC_NBC * s->nv);

@@ -37,6 +37,7 @@ class _Cfg(C.Structure):
         ("bc_rho", C.c_double * 7),
         ("nodes", C.POINTER(C.c_double) * 3),
         ("order", C.c_int), ("limiter_k", C.c_double),
+        ("nlist", C.c_int), ("node_list", C.POINTER(C.c_double)),
     ]
 
 
@@ -126,6 +127,12 @@ def make_cfg(case) -> _Cfg:
     # explicit node positions: the arrays live on the config object (the C side
     # copies them when it creates its state)
     c._keep = []
+    if getattr(case, "velocity_list", None) is not None:
+        t = np.ascontiguousarray(case.velocity_list, dtype=np.float64)
+        c._keep.append(t)
+        c.nlist = t.shape[0]
+        c.node_list = t.ctypes.data_as(C.POINTER(C.c_double))
+        return c
     for a in range(3):
         x = axis_nodes(case, a, explicit_only=True)
         if x is not None:
@@ -340,7 +347,12 @@ def axis_nodes(case, a, explicit_only=False):
 
 
 def node_grid(case):
-    """Nodes (n,3) and trapezoid weights (n,) in canonical order (x fastest)."""
+    """Nodes (n,3) and weights (n,) in canonical order: a node list as given, else
+    the tensor grid (x fastest) with trapezoid weights."""
+    lst = getattr(case, "velocity_list", None)
+    if lst is not None:
+        lst = np.asarray(lst, dtype=np.float64)
+        return lst[:, :3].copy(), lst[:, 3].copy()
     axes, wts = [], []
     for a in range(3):
         x = axis_nodes(case, a, explicit_only=True)

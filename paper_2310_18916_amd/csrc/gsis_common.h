@@ -19,14 +19,18 @@ constexpr double PI = 3.14159265358979323846;
 // Geometry, velocity grid and gas constants, passed to kernels by value.
 //
 // Velocity octant o = sx + 2 sy + 4 sz with s_a = 1 when xi_a < 0 (a node with
-// xi_a = 0 belongs to the positive half).  Along axis a the negative half is
-// nodes [0, k0[a]) and the positive half [k0[a], n1[a]).  Inside an octant the
-// nodes are ordered x fastest; the VDF of a cell is the 8 octants back to back.
+// xi_a = 0 belongs to the positive half); the VDF of a cell is the 8 octants
+// back to back.  Tensor grid (vlist = 0): along axis a the negative half is
+// nodes [0, k0[a]) and the positive half [k0[a], n1[a]), and inside an octant
+// the nodes are ordered x fastest.  Node list (vlist = 1, a refined or
+// unstructured velocity mesh): an octant holds its nodes in the caller's
+// order, n1 and k0 are 0 and on[o] = (osize[o], 1, 1).
 struct Geo {
     int nx, ny, nz, ncell;
     double h[3], invh[3];
     int n1[3], k0[3];
     int nv;
+    int vlist;
     int on[8][3];
     int osize[8];
     int obase[8];
@@ -77,7 +81,9 @@ struct Dev {
     float *fscalef;
     double *cfs64;     // [ncell][6] the same scale by (cell, face direction), for the sweep
     float *cfs32;
-    double *xi64[3];   // per-axis nodes
+    double *nt64;      // [nv][4] every node in the internal order: xi_x, xi_y, xi_z, weight
+    float *nt32;       // [nv][4] the same in FP32
+    double *xi64[3];   // per-axis nodes (tensor grid)
     float *xi32[3];
     double *w64[3];    // per-axis trapezoid weights
     double *xtab;      // [n1x][4]: w, w xi, w xi^2, w xi^3 along x
@@ -259,26 +265,6 @@ __device__ __forceinline__ double maxwell64(double rho, const double *u, double 
 {
     double cx = x - u[0], cy = y - u[1], cz = z - u[2];
     return rho * pow(PI * T, -1.5) * exp(-(cx * cx + cy * cy + cz * cz) / T);
-}
-
-__device__ __forceinline__ void node_of(const Geo &g, int o, int l, int &kx, int &ky, int &kz)
-{
-    int nox = g.on[o][0], noy = g.on[o][1];
-    int lx = l % nox, r = l / nox;
-    int ly = r % noy, lz = r / noy;
-    kx = ((o & 1) ? 0 : g.k0[0]) + lx;
-    ky = ((o & 2) ? 0 : g.k0[1]) + ly;
-    kz = ((o & 4) ? 0 : g.k0[2]) + lz;
-}
-
-// internal node index l in [0, nv) -> (octant, local index)
-__device__ __forceinline__ int octant_of(const Geo &g, int node, int &l)
-{
-    int o = 0;
-#pragma unroll
-    for (int k = 1; k < 8; ++k) if (node >= g.obase[k]) o = k;
-    l = node - g.obase[o];
-    return o;
 }
 
 }  // namespace gsis

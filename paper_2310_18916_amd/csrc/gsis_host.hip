@@ -23,6 +23,7 @@ struct gsis_ctx {
     bool meta_ready = false;
     std::vector<int> cflag, nbr, face_cell, face_dir, face_bc, perm;
     std::vector<double> xi[3], w[3];
+    std::vector<double> vlist;   // node list [nv][4] in the caller's order (list mode)
     int tx = 0, ty = 0, tz = 0, bs = 0;
     std::vector<int> tiles, plane_off, plane_cnt, npblk;
     std::vector<int> tent, nclean;   // split sweep entries (cases with solid cells)
@@ -175,6 +176,9 @@ void build_tiles(gsis_ctx *c)
     build_split(c);
 }
 
+// octant of a node (s_a = 1 when xi_a < 0)
+int list_octant(const double *t) { return (t[0] < 0.0 ? 1 : 0) | (t[1] < 0.0 ? 2 : 0) | (t[2] < 0.0 ? 4 : 0); }
+
 // neighbour table, boundary faces, node permutation, moment vector width
 void build_meta(gsis_ctx *c)
 {
@@ -214,7 +218,12 @@ void build_meta(gsis_ctx *c)
     g.nfluid = 0;
     for (int cell = 0; cell < n; ++cell) g.nfluid += c->cflag[cell];
     c->perm.assign(g.nv, 0);
-    for (int o = 0; o < 8; ++o)
+    if (g.vlist) {
+        // octant by octant, each in the caller's order
+        std::vector<int> at(g.obase, g.obase + 8);
+        for (int k = 0; k < g.nv; ++k) c->perm[at[list_octant(&c->vlist[(size_t)k * 4])]++] = k;
+    }
+    for (int o = 0; o < 8 && !g.vlist; ++o)
         for (int l = 0; l < g.osize[o]; ++l) {
             int nox = g.on[o][0], noy = g.on[o][1];
             int lx = l % nox, r = l / nox, ly = r % noy, lz = r / noy;
@@ -223,7 +232,7 @@ void build_meta(gsis_ctx *c)
             int kz = ((o & 4) ? 0 : g.k0[2]) + lz;
             c->perm[g.obase[o] + l] = kx + g.n1[0] * (ky + g.n1[1] * kz);
         }
-    int vw = c->fp32 ? 4 : 2;
+    int vw = g.vlist ? 1 : (c->fp32 ? 4 : 2);
     while (vw > 1) {
         bool ok = true;
         for (int o = 0; o < 8; ++o)
@@ -275,6 +284,8 @@ size_t layout(gsis_ctx *c, char *base)
     carve(off, d.fscalef, nf, base);
     carve(off, d.cfs64, n * 6, base);
     carve(off, d.cfs32, n * 6, base);
+    carve(off, d.nt64, nv * 4, base);
+    carve(off, d.nt32, nv * 4, base);
     for (int a = 0; a < 3; ++a) {
         carve(off, d.xi64[a], (size_t)g.n1[a], base);
         carve(off, d.xi32[a], (size_t)g.n1[a], base);
@@ -332,6 +343,7 @@ Target target_of(const gsis_ctx *c)
     t.mask = c->g.nfluid != c->g.ncell;
     t.rfn = c->g.inv_dt != 0.0 || c->g.order == 2;
     t.mom_nblk[vw_class(c->vw)] = c->g.ncell;
+    t.vlist = c->g.vlist != 0;
     if (!c->nclean.empty()) {
         t.nclean = c->nclean.data();
         t.pcnt = c->plane_cnt.data();
@@ -475,6 +487,20 @@ const char *gsis_last_error(const gsis_ctx *ctx)
 static void octant_layout(gsis_ctx *x)
 {
     Geo &g = x->g;
+    if (g.vlist) {
+        int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int k = 0; k < g.nv; ++k) ++cnt[list_octant(&x->vlist[(size_t)k * 4])];
+        int base = 0;
+        for (int o = 0; o < 8; ++o) {
+            g.on[o][0] = cnt[o];
+            g.on[o][1] = g.on[o][2] = 1;
+            g.osize[o] = cnt[o];
+            g.obase[o] = base;
+            base += cnt[o];
+        }
+        for (int a = 0; a < 3; ++a) g.n1[a] = g.k0[a] = 0;
+        return;
+    }
     for (int a = 0; a < 3; ++a) {
         const int n = g.n1[a];
         int k0 = n;
@@ -604,6 +630,7 @@ gsis_status gsis_set_velocity_nodes(gsis_ctx *ctx, int axis, const double *nodes
     if (!ctx) return GSIS_EINVAL;
     if (ctx->bound || ctx->meta_ready) return fail(ctx, GSIS_ESTATE, "set_velocity_nodes must precede workspace_size/bind");
     if (axis < 0 || axis > 2) return fail(ctx, GSIS_EINVAL, "axis must be 0, 1 or 2");
+    if (ctx->g.vlist) return fail(ctx, GSIS_ESTATE, "the context holds a velocity node list, not a tensor grid");
     if (!nodes) return fail(ctx, GSIS_EINVAL, "nodes is NULL");
     if (n != ctx->g.n1[axis]) return fail(ctx, GSIS_EINVAL, "n must equal the configured node count of the axis");
     for (int k = 0; k < n; ++k)
@@ -615,6 +642,27 @@ gsis_status gsis_set_velocity_nodes(gsis_ctx *ctx, int axis, const double *nodes
         // trapezoid rule on the given nodes: half of each neighbouring gap
         w[k] = 0.5 * ((k < n - 1 ? nodes[k + 1] : nodes[k]) - (k > 0 ? nodes[k - 1] : nodes[k]));
     }
+    octant_layout(ctx);
+    return GSIS_OK;
+}
+
+gsis_status gsis_set_velocity_list(gsis_ctx *ctx, const double *nodes, int n)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (ctx->bound || ctx->meta_ready) return fail(ctx, GSIS_ESTATE, "set_velocity_list must precede workspace_size/bind");
+    if (!nodes) return fail(ctx, GSIS_EINVAL, "nodes is NULL");
+    if (n < 2 || n > (1 << 24)) return fail(ctx, GSIS_EINVAL, "the node count must be in [2, 2^24]");
+    for (int k = 0; k < n; ++k) {
+        const double *t = nodes + (size_t)k * 4;
+        if (!std::isfinite(t[0]) || !std::isfinite(t[1]) || !std::isfinite(t[2]))
+            return fail(ctx, GSIS_EINVAL, "node velocities must be finite");
+        if (!(t[3] > 0.0) || !std::isfinite(t[3])) return fail(ctx, GSIS_EINVAL, "node weights must be positive and finite");
+    }
+    if ((long long)n * ctx->g.ncell > (1ll << 40)) return fail(ctx, GSIS_EINVAL, "cells x nodes too large");
+    ctx->vlist.assign(nodes, nodes + (size_t)n * 4);
+    for (int a = 0; a < 3; ++a) { ctx->xi[a].clear(); ctx->w[a].clear(); }
+    ctx->g.vlist = 1;
+    ctx->g.nv = n;
     octant_layout(ctx);
     return GSIS_OK;
 }
@@ -691,22 +739,46 @@ gsis_status gsis_bind_workspace(gsis_ctx *ctx, void *device_ptr, size_t bytes)
         HIPCHK(ctx, up(d.face_dir, ctx->face_dir.data(), g.nface * sizeof(int)));
         HIPCHK(ctx, up(d.face_bc, ctx->face_bc.data(), g.nface * sizeof(int)));
     }
-    std::vector<double> xt((size_t)g.n1[0] * 4), yt((size_t)g.n1[1] * 2), zt((size_t)g.n1[2] * 2);
-    for (int a = 0; a < 3; ++a) {
-        std::vector<float> x32(ctx->xi[a].begin(), ctx->xi[a].end());
-        HIPCHK(ctx, up(d.xi64[a], ctx->xi[a].data(), g.n1[a] * sizeof(double)));
-        HIPCHK(ctx, up(d.xi32[a], x32.data(), g.n1[a] * sizeof(float)));
-        HIPCHK(ctx, up(d.w64[a], ctx->w[a].data(), g.n1[a] * sizeof(double)));
+    if (!g.vlist) {
+        // per-axis tables of the separable kernels (tensor grid)
+        std::vector<double> xt((size_t)g.n1[0] * 4), yt((size_t)g.n1[1] * 2), zt((size_t)g.n1[2] * 2);
+        for (int a = 0; a < 3; ++a) {
+            std::vector<float> x32(ctx->xi[a].begin(), ctx->xi[a].end());
+            HIPCHK(ctx, up(d.xi64[a], ctx->xi[a].data(), g.n1[a] * sizeof(double)));
+            HIPCHK(ctx, up(d.xi32[a], x32.data(), g.n1[a] * sizeof(float)));
+            HIPCHK(ctx, up(d.w64[a], ctx->w[a].data(), g.n1[a] * sizeof(double)));
+        }
+        for (int k = 0; k < g.n1[0]; ++k) {
+            double x = ctx->xi[0][k], w = ctx->w[0][k];
+            xt[4 * k] = w; xt[4 * k + 1] = w * x; xt[4 * k + 2] = w * x * x; xt[4 * k + 3] = w * x * x * x;
+        }
+        for (int k = 0; k < g.n1[1]; ++k) { yt[2 * k] = ctx->w[1][k]; yt[2 * k + 1] = ctx->xi[1][k]; }
+        for (int k = 0; k < g.n1[2]; ++k) { zt[2 * k] = ctx->w[2][k]; zt[2 * k + 1] = ctx->xi[2][k]; }
+        HIPCHK(ctx, up(d.xtab, xt.data(), xt.size() * sizeof(double)));
+        HIPCHK(ctx, up(d.ytab, yt.data(), yt.size() * sizeof(double)));
+        HIPCHK(ctx, up(d.ztab, zt.data(), zt.size() * sizeof(double)));
     }
-    for (int k = 0; k < g.n1[0]; ++k) {
-        double x = ctx->xi[0][k], w = ctx->w[0][k];
-        xt[4 * k] = w; xt[4 * k + 1] = w * x; xt[4 * k + 2] = w * x * x; xt[4 * k + 3] = w * x * x * x;
+    {
+        // every node in the internal order: (xi_x, xi_y, xi_z, weight)
+        std::vector<double> nt((size_t)g.nv * 4);
+        std::vector<float> nt32((size_t)g.nv * 4);
+        for (int i = 0; i < g.nv; ++i) {
+            const int k = ctx->perm[i];
+            double *t = &nt[(size_t)i * 4];
+            if (g.vlist) {
+                for (int q = 0; q < 4; ++q) t[q] = ctx->vlist[(size_t)k * 4 + q];
+            } else {
+                const int kx = k % g.n1[0], ky = (k / g.n1[0]) % g.n1[1], kz = k / (g.n1[0] * g.n1[1]);
+                t[0] = ctx->xi[0][kx];
+                t[1] = ctx->xi[1][ky];
+                t[2] = ctx->xi[2][kz];
+                t[3] = ctx->w[0][kx] * ctx->w[1][ky] * ctx->w[2][kz];
+            }
+            for (int q = 0; q < 4; ++q) nt32[(size_t)i * 4 + q] = (float)t[q];
+        }
+        HIPCHK(ctx, up(d.nt64, nt.data(), nt.size() * sizeof(double)));
+        HIPCHK(ctx, up(d.nt32, nt32.data(), nt32.size() * sizeof(float)));
     }
-    for (int k = 0; k < g.n1[1]; ++k) { yt[2 * k] = ctx->w[1][k]; yt[2 * k + 1] = ctx->xi[1][k]; }
-    for (int k = 0; k < g.n1[2]; ++k) { zt[2 * k] = ctx->w[2][k]; zt[2 * k + 1] = ctx->xi[2][k]; }
-    HIPCHK(ctx, up(d.xtab, xt.data(), xt.size() * sizeof(double)));
-    HIPCHK(ctx, up(d.ytab, yt.data(), yt.size() * sizeof(double)));
-    HIPCHK(ctx, up(d.ztab, zt.data(), zt.size() * sizeof(double)));
     HIPCHK(ctx, up(d.perm, ctx->perm.data(), ctx->perm.size() * sizeof(int)));
     HIPCHK(ctx, upload_tiles(ctx));
     HIPCHK(ctx, hipMemset(d.errflag, 0, 4 * sizeof(int)));
@@ -1389,7 +1461,7 @@ gsis_status gsis_batch_create(gsis_batch **out, gsis_ctx *const *cases, int ncas
         for (int j = 0; j < i; ++j)
             if (cases[j] == c) return GSIS_EINVAL;
         if (c->fp32 != cases[0]->fp32 || c->g.species != cases[0]->g.species) return GSIS_EINVAL;
-        if (c->g.inv_dt != 0.0 || c->g.order != 1) return GSIS_EINVAL;
+        if (c->g.inv_dt != 0.0 || c->g.order != 1 || c->g.vlist) return GSIS_EINVAL;
     }
     gsis_batch *b = new (std::nothrow) gsis_batch();
     if (!b) return GSIS_ENOMEM;

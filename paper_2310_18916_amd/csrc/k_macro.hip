@@ -121,7 +121,8 @@ __device__ __forceinline__ void face_flux(const Geo &g, const PV &L, const PV &R
 }
 
 // Outgoing half-range psi-moments of M(rho, u, Tt) through face dir (sum over
-// nodes with xi.n > 0 of w (xi.n) psi M), separable on the tensor grid, and
+// nodes with xi.n > 0 of w (xi.n) psi M), separable on the tensor grid and
+// summed node by node on a node list, and
 // the face flux of the equilibrium state with the face's boundary rule.  A
 // group of FG adjacent lanes evaluates one face: the lanes share the nodes of
 // each axis and a butterfly inside the group combines them, so every lane of
@@ -151,6 +152,41 @@ __device__ void group_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev
     const int a = dir / 2;
     const double sg = (dir & 1) ? 1.0 : -1.0;
     const double T = P[4], iT = 1.0 / T;
+    const double piT = PI * T;
+    const double K = P[0] / (piT * sqrt(piT)) * sg;
+    const double h1 = g.species == 1 ? 0.5 * g.dr * P[5] : 0.0;
+    const gptr<const double> in = G((const double *)d.inpsi) + (b * 6 + dir) * 6;
+    double out[6];
+    if (g.vlist) {
+        // node list: the half-range sums over the outgoing nodes directly
+        double s0 = 0.0, s1[3] = {0.0, 0.0, 0.0}, s4 = 0.0;
+        const gptr<const double> nt = G((const double *)d.nt64);
+        for (int k = sub; k < g.nv; k += FG) {
+            const double x = nt[4 * (size_t)k + a];
+            if (!(sg * x > 0.0)) continue;
+            const double v0 = nt[4 * (size_t)k], v1 = nt[4 * (size_t)k + 1], v2 = nt[4 * (size_t)k + 2];
+            const double cx = v0 - P[1], cy = v1 - P[2], cz = v2 - P[3];
+            const double ex = nt[4 * (size_t)k + 3] * exp_core(fmax(-(cx * cx + cy * cy + cz * cz) * iT, -745.0)) * x;
+            s0 += ex;
+            s1[0] += ex * v0;
+            s1[1] += ex * v1;
+            s1[2] += ex * v2;
+            s4 += ex * (v0 * v0 + v1 * v1 + v2 * v2);
+        }
+        s0 = group_sum(s0);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) s1[q] = group_sum(s1[q]);
+        s4 = group_sum(s4);
+        out[0] = K * s0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) out[1 + q] = K * s1[q];
+        out[4] = K * s4 + h1 * out[0];
+        out[5] = h1 * out[0];
+        const double sc = bc.kind[b] == 1 ? bc.rho[b] : out[0] / (-in[0]);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) F[k] = out[k] + sc * in[k];
+        return;
+    }
     const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
     double H1 = 0, H2 = 0, H3 = 0;
     for (int k = sub; k < g.n1[a]; k += FG) {
@@ -182,17 +218,12 @@ __device__ void group_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev
     for (int q = 0; q < 2; ++q)
 #pragma unroll
         for (int p = 0; p < 3; ++p) S[q][p] = group_sum(S[q][p]);
-    const double piT = PI * T;
-    const double K = P[0] / (piT * sqrt(piT)) * sg;
-    double out[6];
     out[0] = K * H1 * S[0][0] * S[1][0];
     out[1 + a] = K * H2 * S[0][0] * S[1][0];
     out[1 + b1] = K * H1 * S[0][1] * S[1][0];
     out[1 + b2] = K * H1 * S[0][0] * S[1][1];
-    const double h1 = g.species == 1 ? 0.5 * g.dr * P[5] : 0.0;
     out[4] = K * (H3 * S[0][0] * S[1][0] + H1 * S[0][2] * S[1][0] + H1 * S[0][0] * S[1][2]) + h1 * out[0];
     out[5] = h1 * out[0];
-    const gptr<const double> in = G((const double *)d.inpsi) + (b * 6 + dir) * 6;
     const double sc = bc.kind[b] == 1 ? bc.rho[b] : out[0] / (-in[0]);
 #pragma unroll
     for (int k = 0; k < 6; ++k) F[k] = out[k] + sc * in[k];

@@ -16,6 +16,10 @@
 // k_commit_correction: adds to the octant sums the discrete raw moments of
 // M(W') - M(W) of Eq. (updatef), which factor into 1-D sums on the tensor grid,
 // so the corrected state's moments are exact without touching the VDF.
+//
+// On a node list (a refined or unstructured velocity mesh, Sec. 3.1) nothing
+// factors: k_moments_list and k_commit_correction_list sum over the nodes
+// directly, one wave per (cells, octant).
 #include "gsis_common.h"
 #include "gsis_launch.h"
 
@@ -251,6 +255,106 @@ __global__ __launch_bounds__(512) void k_moments(GSIS_SPAN_ARGS)
     if (!DIA && lane == 0) out[NRS - 1] = 0.0;   // 13..15 come from the zero padding
 }
 
+// The 13 raw monomials of one node times its weight: 1, x, y, z, xx, yy, zz,
+// xy, xz, yz, x|xi|^2, y|xi|^2, z|xi|^2.
+__device__ __forceinline__ void node_monomials(const double *t, double m[13])
+{
+    const double x = t[0], y = t[1], z = t[2], w = t[3];
+    m[0] = w;
+    m[1] = w * x;
+    m[2] = w * y;
+    m[3] = w * z;
+    m[4] = m[1] * x;
+    m[5] = m[2] * y;
+    m[6] = m[3] * z;
+    m[7] = m[1] * y;
+    m[8] = m[1] * z;
+    m[9] = m[2] * z;
+    const double s2 = x * x + y * y + z * z;
+    m[10] = m[1] * s2;
+    m[11] = m[2] * s2;
+    m[12] = m[3] * s2;
+}
+
+// Writes the NRS sums of one (cell, octant) from the lanes' partial sums
+// acc[0..12] (f0) and acc1[0..3] (f1), reduced over the wave in a fixed order.
+template <bool DIA>
+__device__ __forceinline__ void store_octant_sums(const double *acc, const double *acc1, int lane, gptr<double> out,
+                                                  bool add)
+{
+    constexpr int NR = DIA ? 32 : 16;
+    double v[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) v[k] = k < 13 ? acc[k < 13 ? k : 0] : (DIA && k < NRS ? acc1[k < NRS ? k - 13 : 0] : 0.0);
+    int idx;
+    const double r = wave_reduce_scatter<NR>(v, lane, &idx);
+    if ((lane & (64 / NR - 1)) == 0 && idx < NRS) {
+        if (add) out[idx] += r;
+        else out[idx] = r;
+    }
+    if (!DIA && !add && lane == 0) out[NRS - 1] = 0.0;
+}
+
+// Node list: one wave per octant of a group of CG consecutive cells (block =
+// 8 waves, one per octant).  A lane takes the octant's nodes 64 apart, reads
+// each node's (xi, w) once and applies its monomials to the node's value in
+// every cell of the group, so the node table is read once per CG cells while
+// each VDF load covers 64 consecutive nodes of one cell.
+template <typename T, bool DIA, int CG>
+__global__ __launch_bounds__(512) void k_moments_list(GSIS_SPAN_ARGS)
+{
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const gptr<const T> f0 = (gptr<const T>)C.d.f0;
+    const gptr<const T> f1 = (gptr<const T>)C.d.f1;
+    const gptr<const int> cflag = (gptr<const int>)C.d.cflag;
+    const gptr<const double> nt = (gptr<const double>)C.d.nt64;
+    const gptr<double> mom8 = (gptr<double>)C.d.mom8;
+    const int o = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int cell0 = blk * CG;
+    const int n = g.osize[o], ob = g.obase[o];
+    const size_t nv = (size_t)g.nv;
+    bool live[CG];
+#pragma unroll
+    for (int c = 0; c < CG; ++c) live[c] = cell0 + c < g.ncell && cflag[cell0 + c];   // uniform over the wave
+    double acc[CG][13], acc1[CG][4];
+#pragma unroll
+    for (int c = 0; c < CG; ++c) {
+#pragma unroll
+        for (int k = 0; k < 13; ++k) acc[c][k] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc1[c][k] = 0.0;
+    }
+    for (int l = lane; l < n; l += 64) {
+        const size_t node = (size_t)ob + l;
+        double v[CG], v1[CG];
+#pragma unroll
+        for (int c = 0; c < CG; ++c) {
+            v[c] = live[c] ? (double)f0[(size_t)(cell0 + c) * nv + node] : 0.0;
+            if (DIA) v1[c] = live[c] ? (double)f1[(size_t)(cell0 + c) * nv + node] : 0.0;
+        }
+        double t[4] = {nt[4 * node], nt[4 * node + 1], nt[4 * node + 2], nt[4 * node + 3]};
+        double m[13];
+        node_monomials(t, m);
+#pragma unroll
+        for (int c = 0; c < CG; ++c) {
+#pragma unroll
+            for (int k = 0; k < 13; ++k) acc[c][k] += m[k] * v[c];
+            if (DIA) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc1[c][k] += m[k] * v1[c];
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CG; ++c) {
+        if (cell0 + c >= g.ncell) break;
+        store_octant_sums<DIA>(acc[c], acc1[c], lane, mom8 + ((size_t)(cell0 + c) * 8 + o) * NRS, false);
+    }
+}
+
 // Central moments from the octant sums (octants added in a fixed order).
 __global__ __launch_bounds__(256) void k_derive(GSIS_SPAN_ARGS)
 {
@@ -377,6 +481,51 @@ __global__ __launch_bounds__(128) void k_commit_correction(GSIS_SPAN_ARGS)
     }
 }
 
+// Node list: octant sums += moments of M(W') - M(W) (and (dr/2)[Tr' M(W') -
+// Tr M(W)] on f1), one wave per octant of one cell, summed over the nodes.
+__global__ __launch_bounds__(512) void k_commit_correction_list(GSIS_SPAN_ARGS)
+{
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const int cell = blk;
+    const gptr<const int> cflag = (gptr<const int>)C.d.cflag;
+    if (!cflag[cell]) return;   // uniform over the block
+    const int o = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const gptr<const double> nt = (gptr<const double>)C.d.nt64;
+    const gptr<const double> c = (gptr<const double>)C.d.corr + (size_t)cell * NCORR;
+    const double pn = PI * c[4], po = PI * c[10];
+    const double Kn = c[0] / (pn * sqrt(pn)), Ko = c[6] / (po * sqrt(po));
+    const double itn = 1.0 / c[4], ito = 1.0 / c[10];
+    const bool dia = g.species == 1;
+    const double hn = dia ? 0.5 * g.dr * c[5] : 0.0, ho = dia ? 0.5 * g.dr * c[11] : 0.0;
+    double acc[13], acc1[4];
+#pragma unroll
+    for (int k = 0; k < 13; ++k) acc[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc1[k] = 0.0;
+    const int n = g.osize[o], ob = g.obase[o];
+    for (int l = lane; l < n; l += 64) {
+        const size_t node = (size_t)ob + l;
+        const double t[4] = {nt[4 * node], nt[4 * node + 1], nt[4 * node + 2], nt[4 * node + 3]};
+        const double nx = t[0] - c[1], ny = t[1] - c[2], nz = t[2] - c[3];
+        const double ox = t[0] - c[7], oy = t[1] - c[8], oz = t[2] - c[9];
+        const double en = Kn * exp_core(fmax(-(nx * nx + ny * ny + nz * nz) * itn, -745.0));
+        const double eo = Ko * exp_core(fmax(-(ox * ox + oy * oy + oz * oz) * ito, -745.0));
+        const double d0 = en - eo, d1 = hn * en - ho * eo;
+        double m[13];
+        node_monomials(t, m);
+#pragma unroll
+        for (int k = 0; k < 13; ++k) acc[k] += m[k] * d0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc1[k] += m[k] * d1;
+    }
+    const gptr<double> out = (gptr<double>)C.d.mom8 + ((size_t)cell * 8 + o) * NRS;
+    if (dia) store_octant_sums<true>(acc, acc1, lane, out, true);
+    else store_octant_sums<false>(acc, acc1, lane, out, true);
+}
+
 // ------------------------------------------------------------------ launches
 template <typename T, int VW>
 static void moments_vw(const Target &t, int cls, hipStream_t s)
@@ -389,8 +538,26 @@ static void moments_vw(const Target &t, int cls, hipStream_t s)
 
 // One launch per vector-width class present (a case's width follows its
 // octant row lengths), so every case is reduced exactly as on its own.
+// cells per block of the node-list moment kernel
+template <bool DIA> constexpr int list_cg() { return DIA ? 2 : 4; }
+
+template <typename T, bool DIA>
+static void moments_list(const Target &t, hipStream_t s)
+{
+    constexpr int CG = list_cg<DIA>();
+    const int ncell = t.host[0].g.ncell;
+    hipLaunchKernelGGL((k_moments_list<T, DIA, CG>), dim3((ncell + CG - 1) / CG), dim3(512), 0, s,
+                       GSIS_SPAN(t.span(K_CELL1)));
+}
+
 hipError_t launch_moments(const Target &t, hipStream_t s)
 {
+    if (t.vlist) {
+        // one case (batches hold tensor grids only)
+        if (t.fp32) { if (t.dia) moments_list<float, true>(t, s); else moments_list<float, false>(t, s); }
+        else { if (t.dia) moments_list<double, true>(t, s); else moments_list<double, false>(t, s); }
+        return hipGetLastError();
+    }
     if (t.mom_nblk[0] > 0) {
         if (t.fp32) moments_vw<float, 1>(t, 0, s);
         else moments_vw<double, 1>(t, 0, s);
@@ -414,6 +581,11 @@ hipError_t launch_derive(const Target &t, hipStream_t s)
 
 hipError_t launch_commit_correction(const Target &t, hipStream_t s)
 {
+    if (t.vlist) {
+        hipLaunchKernelGGL(k_commit_correction_list, dim3(t.host[0].g.ncell), dim3(512), 0, s,
+                           GSIS_SPAN(t.span(K_CELL1)));
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_commit_correction, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(t.span(K_CELL128)));
     return hipGetLastError();
 }

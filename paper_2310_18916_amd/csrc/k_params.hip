@@ -11,7 +11,10 @@
 // each component equal their continuous values exactly.  On the tensor grid
 // the 5x5 Gram matrix sum w phi phi^T M and the Shakhov term's moments factor
 // into 1-D sums C_a(p) = sum_k w_k c^p exp(-c^2/T), p <= 5, so the correction
-// costs O(n per axis) per cell.
+// costs O(n per axis) per cell.  On a node list (a refined or unstructured
+// velocity mesh, Sec. 3.1) the same products are read from a table of the
+// moments sum_k w_k c_x^p c_y^q c_z^r exp(-|c|^2/T), p + q + r <= 5 (56 of
+// them), summed over the nodes by one wave per cell.
 #include "gsis_common.h"
 #include "gsis_launch.h"
 
@@ -37,6 +40,12 @@ struct Sep {
     __device__ double m(int p, int q, int r) const { return C[0][p] * C[1][q] * C[2][r]; }
 };
 
+// moments m(p, q, r), p + q + r <= 5, held in a dense 6x6x6 table (LDS)
+struct Tab {
+    const double *t;
+    __device__ double m(int p, int q, int r) const { return t[(p * 6 + q) * 6 + r]; }
+};
+
 // phi = (1, c_x, c_y, c_z, |c|^2) as monomial lists
 __device__ __forceinline__ int phi_terms(int i, int t[3][3])
 {
@@ -50,7 +59,8 @@ __device__ __forceinline__ int phi_terms(int i, int t[3][3])
 
 // Gram G_ij = sum phi_i phi_j E and Shakhov moments bS_i = sum phi_i E [1 + (qp.c)(|c|^2 kT - 5/2)],
 // both without the prefactor rho (pi T)^{-3/2}.
-__device__ void gram_and_shakhov(const Sep &S, const double qp[3], double kT, double G[25], double bS[5])
+template <class S3>
+__device__ void gram_and_shakhov(const S3 &S, const double qp[3], double kT, double G[25], double bS[5])
 {
     int ti[3][3], tj[3][3];
     for (int i = 0; i < 5; ++i) {
@@ -110,7 +120,8 @@ __device__ bool solve5(double *A, double *b)
 
 // Correction lambda (c-basis) of one component with shape rho (pi T)^{-3/2} E:
 // K G lambda = target - K bS, target = (rho, 0, 0, 0, 1.5 rho T).
-__device__ void correction(const Sep &S, double K, double rho, double T, const double qp[3], double kT,
+template <class S3>
+__device__ void correction(const S3 &S, double K, double rho, double T, const double qp[3], double kT,
                            bool conservative, double lam[5], double bS[5])
 {
     double G[25];
@@ -124,6 +135,37 @@ __device__ void correction(const Sep &S, double K, double rho, double T, const d
         for (int i = 0; i < 5; ++i) lam[i] = 0.0;
 }
 
+// Moments of one cell and the temperatures of its shapes.
+struct CellState {
+    double rho, u[3], Tt, q[3], invtau;
+    double Tr, qr[3], T;   // diatomic; T = (3 Tt + dr Tr) / (3 + dr)
+};
+
+// false for a solid cell (its parameters are zeroed)
+__device__ bool cell_state(const Geo &g, const Dev &d, int cell, CellState &st)
+{
+    double *p = d.par + (size_t)cell * NPAR;
+    float *pf = d.parf + (size_t)cell * NPAR;
+    if (!d.cflag[cell]) {
+        for (int k = 0; k < NPAR; ++k) { p[k] = 0.0; pf[k] = 0.0f; }
+        return false;
+    }
+    const double *m = d.cm + (size_t)cell * NMOM;
+    st.rho = m[0];
+    for (int a = 0; a < 3; ++a) { st.u[a] = m[1 + a]; st.q[a] = m[11 + a]; }
+    st.Tt = m[4];
+    st.invtau = g.delta * st.rho * pow(st.Tt, 1.0 - g.omega);
+    if (!(st.rho > 0.0) || !(st.Tt > 0.0) || !isfinite(st.invtau)) atomicOr(d.errflag, 1);
+    st.Tr = st.T = st.Tt;
+    for (int a = 0; a < 3; ++a) st.qr[a] = 0.0;
+    if (g.species != 0) {
+        st.Tr = m[14];
+        for (int a = 0; a < 3; ++a) st.qr[a] = m[15 + a];
+        st.T = (3.0 * st.Tt + g.dr * st.Tr) / (3.0 + g.dr);
+    }
+    return true;
+}
+
 // Parameter layout (NPAR doubles per cell):
 //  monatomic: 0-2 u, 3 1/Tt, 4 A = rho (pi Tt)^{-3/2} / tau, 5 P0 = 1 + l0, 6-8 l_c, 9 l4,
 //             10-12 qp = (4/15) q / (rho Tt^2), 13 1/tau
@@ -131,36 +173,24 @@ __device__ void correction(const Sep &S, double K, double rho, double T, const d
 //             7 P0t, 8-10 l_t, 11 l4t, 12-14 qp_t, 15 P0r, 16-18 l_r, 19 l4r, 20-22 qp_r,
 //             23 ht = (dr/2) Tr, 24-26 2 qr / (rho Tt), 27 nu_t,
 //             28 hr = (dr/2) T, 29-31 2 q1 / (rho T), 32 nu_r, 33 1/tau
-__global__ __launch_bounds__(64) void k_params(GSIS_SPAN_ARGS)
+// St: the moments of the shape exp(-|c|^2/Tt) on the velocity grid; Sr: of
+// exp(-|c|^2/T) (diatomic only).
+template <class S3>
+__device__ void cell_params(const Geo &g, const Dev &d, int cell, const CellState &st, const S3 &St, const S3 &Sr)
 {
-    int blk;
-    const Case &C = case_of(span_cases, span_map, blk);
-    const Geo &g = C.g;
-    const Dev &d = C.d;
-    int cell = blk * blockDim.x + threadIdx.x;
-    if (cell >= g.ncell) return;
     double *p = d.par + (size_t)cell * NPAR;
     float *pf = d.parf + (size_t)cell * NPAR;
-    if (!d.cflag[cell]) {
-        for (int k = 0; k < NPAR; ++k) { p[k] = 0.0; pf[k] = 0.0f; }
-        return;
-    }
-    const double *m = d.cm + (size_t)cell * NMOM;
-    double rho = m[0], u[3] = {m[1], m[2], m[3]}, Tt = m[4];
-    double q[3] = {m[11], m[12], m[13]};
-    double invtau = g.delta * rho * pow(Tt, 1.0 - g.omega);
-    if (!(rho > 0.0) || !(Tt > 0.0) || !isfinite(invtau)) atomicOr(d.errflag, 1);
+    const double rho = st.rho, Tt = st.Tt, invtau = st.invtau;
+    const double *u = st.u, *q = st.q;
     for (int k = 0; k < NPAR; ++k) p[k] = 0.0;
     bool cons = g.conservative != 0;
     if (g.species == 0) {
-        Sep S;
-        for (int a = 0; a < 3; ++a) axis_central(d.xi64[a], d.w64[a], g.n1[a], u[a], Tt, S.C[a]);
         double K = rho * pow(PI * Tt, -1.5);
         double kT = 1.0 / Tt;
         double qp[3];
         for (int a = 0; a < 3; ++a) qp[a] = (4.0 / 15.0) * q[a] / (rho * Tt * Tt);
         double lam[5], bS[5];
-        correction(S, K, rho, Tt, qp, kT, cons, lam, bS);
+        correction(St, K, rho, Tt, qp, kT, cons, lam, bS);
         p[0] = u[0]; p[1] = u[1]; p[2] = u[2];
         p[3] = kT;
         p[4] = K * invtau;
@@ -170,19 +200,13 @@ __global__ __launch_bounds__(64) void k_params(GSIS_SPAN_ARGS)
         p[10] = qp[0]; p[11] = qp[1]; p[12] = qp[2];
         p[13] = invtau;
     } else {
-        double Tr = m[14], qr[3] = {m[15], m[16], m[17]};
+        const double Tr = st.Tr, T = st.T, *qr = st.qr;
         double dr = g.dr, Z = g.Zr;
-        double T = (3.0 * Tt + dr * Tr) / (3.0 + dr);
         double Att = g.A[0], Atr = g.A[1], Art = g.A[2], Arr = g.A[3];
         double q0[3], q1[3];
         for (int a = 0; a < 3; ++a) {
             q0[a] = ((2.0 - 3.0 * Att) * Z + 1.0) * q[a] + (-3.0 * Atr * Z) * qr[a];
             q1[a] = (-Art * Z) * q[a] + (-Arr * Z + 1.0) * qr[a];
-        }
-        Sep St, Sr;
-        for (int a = 0; a < 3; ++a) {
-            axis_central(d.xi64[a], d.w64[a], g.n1[a], u[a], Tt, St.C[a]);
-            axis_central(d.xi64[a], d.w64[a], g.n1[a], u[a], T, Sr.C[a]);
         }
         double Kt = rho * pow(PI * Tt, -1.5), Kr = rho * pow(PI * T, -1.5);
         double kTt = 1.0 / Tt, kT = 1.0 / T;
@@ -230,6 +254,89 @@ __global__ __launch_bounds__(64) void k_params(GSIS_SPAN_ARGS)
     for (int k = 0; k < NPAR; ++k) pf[k] = (float)p[k];
 }
 
+// Tensor grid: one thread per cell, the shape moments from 1-D sums.
+__global__ __launch_bounds__(64) void k_params(GSIS_SPAN_ARGS)
+{
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    int cell = blk * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell) return;
+    CellState st;
+    if (!cell_state(g, d, cell, st)) return;
+    Sep St, Sr;
+    for (int a = 0; a < 3; ++a) axis_central(d.xi64[a], d.w64[a], g.n1[a], st.u[a], st.Tt, St.C[a]);
+    if (g.species != 0)
+        for (int a = 0; a < 3; ++a) axis_central(d.xi64[a], d.w64[a], g.n1[a], st.u[a], st.T, Sr.C[a]);
+    cell_params(g, d, cell, st, St, g.species != 0 ? Sr : St);
+}
+
+// Node list: one wave per cell.  Each lane sums the 56 moments of the shape
+// over the nodes 64 apart; the partial sums go through LDS, where lane k adds
+// the 64 partials of moment k in lane order; lane 0 then builds the
+// parameters from the table.
+constexpr int NTAB = 56;
+
+__global__ __launch_bounds__(64) void k_params_list(GSIS_SPAN_ARGS)
+{
+    __shared__ double part[NTAB][65];
+    __shared__ double tab[2][216];
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    const int cell = blk;
+    const int lane = threadIdx.x;
+    CellState st;
+    if (!cell_state(g, d, cell, st)) return;   // uniform over the block
+    const int nsh = g.species != 0 ? 2 : 1;
+    const gptr<const double> nt = (gptr<const double>)d.nt64;
+    for (int sh = 0; sh < nsh; ++sh) {
+        const double iT = 1.0 / (sh ? st.T : st.Tt);
+        double acc[NTAB];
+#pragma unroll
+        for (int k = 0; k < NTAB; ++k) acc[k] = 0.0;
+        for (int node = lane; node < g.nv; node += 64) {
+            const double cx = nt[4 * (size_t)node] - st.u[0];
+            const double cy = nt[4 * (size_t)node + 1] - st.u[1];
+            const double cz = nt[4 * (size_t)node + 2] - st.u[2];
+            const double e = nt[4 * (size_t)node + 3] * exp_core(fmax(-(cx * cx + cy * cy + cz * cz) * iT, -745.0));
+            double X[6], Y[6], Z[6];
+            X[0] = e; Y[0] = 1.0; Z[0] = 1.0;
+#pragma unroll
+            for (int p = 1; p < 6; ++p) { X[p] = X[p - 1] * cx; Y[p] = Y[p - 1] * cy; Z[p] = Z[p - 1] * cz; }
+            int k = 0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+#pragma unroll
+                for (int r = 0; r + q < 6; ++r) {
+                    const double yz = Y[q] * Z[r];
+#pragma unroll
+                    for (int p = 0; p + q + r < 6; ++p) acc[k++] += X[p] * yz;
+                }
+        }
+#pragma unroll
+        for (int k = 0; k < NTAB; ++k) part[k][lane] = acc[k];
+        __syncthreads();
+        if (lane < NTAB) {
+            // moment number lane -> (p, q, r) in the order of the loops above
+            int k = 0, pp = 0, qq = 0, rr = 0;
+            for (int q = 0; q < 6; ++q)
+                for (int r = 0; r + q < 6; ++r)
+                    for (int p = 0; p + q + r < 6; ++p) {
+                        if (k == lane) { pp = p; qq = q; rr = r; }
+                        ++k;
+                    }
+            double sum = 0.0;
+            for (int j = 0; j < 64; ++j) sum += part[lane][j];
+            tab[sh][(pp * 6 + qq) * 6 + rr] = sum;
+        }
+        __syncthreads();
+    }
+    if (lane == 0) cell_params(g, d, cell, st, Tab{tab[0]}, Tab{tab[nsh - 1]});
+}
+
 // Incoming density scale of every boundary face.  Diffuse wall: the outgoing
 // mass flux of the cell's current state (from its octant sums) over the
 // incoming flux of M(1, u_w, T_w), so the discrete wall mass flux is zero;
@@ -264,6 +371,10 @@ __global__ __launch_bounds__(256) void k_face_scale(GSIS_SPAN_ARGS)
 
 hipError_t launch_params(const Target &t, hipStream_t s)
 {
+    if (t.vlist) {
+        hipLaunchKernelGGL(k_params_list, dim3(t.host[0].g.ncell), dim3(64), 0, s, GSIS_SPAN(t.span(K_CELL1)));
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_params, dim3(t.nblk[K_CELL64]), dim3(64), 0, s, GSIS_SPAN(t.span(K_CELL64)));
     return hipGetLastError();
 }

@@ -214,12 +214,10 @@ __global__ __launch_bounds__(RB) void k_recon_source(Geo g, Dev d, int nvb)
     if (rb.o >= 8 || rb.l >= g.osize[rb.o]) return;
     const size_t nv = (size_t)g.nv, node = (size_t)g.obase[rb.o] + rb.l;
     const int nz = g.nz, nxy = g.nx * g.ny;
-    int kx, ky, kz;
-    node_of(g, rb.o, rb.l, kx, ky, kz);
     constexpr bool F32 = sizeof(T) == 4;
-    const T xi0 = F32 ? (T)d.xi32[0][kx] : (T)d.xi64[0][kx];
-    const T xi1 = F32 ? (T)d.xi32[1][ky] : (T)d.xi64[1][ky];
-    const T xi2 = F32 ? (T)d.xi32[2][kz] : (T)d.xi64[2][kz];
+    const T xi0 = F32 ? (T)d.nt32[4 * node] : (T)d.nt64[4 * node];
+    const T xi1 = F32 ? (T)d.nt32[4 * node + 1] : (T)d.nt64[4 * node + 1];
+    const T xi2 = F32 ? (T)d.nt32[4 * node + 2] : (T)d.nt64[4 * node + 2];
     const T idt = (T)g.inv_dt;
     const int sz = (rb.o >> 2) & 1;   // 1: xi_z < 0, the z-upwind side is +
     const gptr<const int> cflag = (gptr<const int>)d.cflag;

@@ -175,15 +175,11 @@ void k_sweep(GSIS_SPAN_ARGS, int plane, int eoff)
     T xix = T(0), xiy = T(0), xiz = T(0);
     size_t node = 0;
     if (active) {
-        int kxn, kyn, kzn;
-        node_of(g, o, l, kxn, kyn, kzn);
-        const gptr<const T> x0 = F32 ? (gptr<const T>)C.d.xi32[0] : (gptr<const T>)C.d.xi64[0];
-        const gptr<const T> x1 = F32 ? (gptr<const T>)C.d.xi32[1] : (gptr<const T>)C.d.xi64[1];
-        const gptr<const T> x2 = F32 ? (gptr<const T>)C.d.xi32[2] : (gptr<const T>)C.d.xi64[2];
-        xix = x0[kxn];
-        xiy = x1[kyn];
-        xiz = x2[kzn];
         node = (size_t)g.obase[o] + l;
+        const gptr<const T> nt = (F32 ? (gptr<const T>)C.d.nt32 : (gptr<const T>)C.d.nt64) + 4 * node;
+        xix = nt[0];
+        xiy = nt[1];
+        xiz = nt[2];
     }
     const T ax = fabs(xix) * (T)g.invh[0];
     const T ay = fabs(xiy) * (T)g.invh[1];

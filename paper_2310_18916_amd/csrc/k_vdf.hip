@@ -14,10 +14,8 @@ __global__ void k_boundary_tables(Geo g, BcInfo bc, Dev d)
     int node = blockIdx.y * blockDim.x + threadIdx.x;
     int b = blockIdx.x;
     if (node >= g.nv) return;
-    int l, kx, ky, kz;
-    int o = octant_of(g, node, l);
-    node_of(g, o, l, kx, ky, kz);
-    double m = maxwell64(1.0, bc.u[b], bc.T[b], d.xi64[0][kx], d.xi64[1][ky], d.xi64[2][kz]);
+    const double *t = d.nt64 + 4 * (size_t)node;
+    double m = maxwell64(1.0, bc.u[b], bc.T[b], t[0], t[1], t[2]);
     double m1 = 0.5 * g.dr * bc.T[b] * m;
     size_t at = (size_t)b * g.nv + node;
     d.mb64[at] = m;
@@ -38,14 +36,11 @@ __global__ __launch_bounds__(256) void k_incoming_moments(Geo g, BcInfo bc, Dev 
     double acc[6] = {0, 0, 0, 0, 0, 0};
     double h1 = 0.5 * g.dr * bc.T[b];
     for (int node = threadIdx.x; node < g.nv; node += blockDim.x) {
-        int l, kx, ky, kz;
-        int o = octant_of(g, node, l);
-        node_of(g, o, l, kx, ky, kz);
-        double x = d.xi64[0][kx], y = d.xi64[1][ky], z = d.xi64[2][kz];
-        double xa = a == 0 ? x : (a == 1 ? y : z);
-        double xn = sg * xa;
+        const double *t = d.nt64 + 4 * (size_t)node;
+        double x = t[0], y = t[1], z = t[2];
+        double xn = sg * t[a];
         if (!(xn < 0.0)) continue;
-        double w = d.w64[0][kx] * d.w64[1][ky] * d.w64[2][kz];
+        double w = t[3];
         double m = d.mb64[(size_t)b * g.nv + node];
         double ww = w * xn * m;
         acc[0] += ww;
@@ -81,11 +76,9 @@ __global__ void k_init_maxwellian(Geo g, Dev d, double rho, double ux, double uy
         if (g.species == 1) f1[at] = T(0);
         return;
     }
-    int l, kx, ky, kz;
-    int o = octant_of(g, node, l);
-    node_of(g, o, l, kx, ky, kz);
+    const double *t = d.nt64 + 4 * (size_t)node;
     double u[3] = {ux, uy, uz};
-    double m = maxwell64(rho, u, Tt, d.xi64[0][kx], d.xi64[1][ky], d.xi64[2][kz]);
+    double m = maxwell64(rho, u, Tt, t[0], t[1], t[2]);
     f0[at] = (T)m;
     if (g.species == 1) f1[at] = (T)(0.5 * g.dr * Tr * m);
 }
@@ -119,7 +112,7 @@ __global__ void k_vdf_node(Geo g, Dev d, int node, double *out)
     out[cell] = (double)((const T *)d.f0)[(size_t)cell * g.nv + node];
 }
 
-// Eq. (updatef) pointwise: f0 += M(W') - M(W), f1 += (dr/2)[Tr' M(W') - Tr M(W)],
+// Eq. (updatef) pointwise (any node set): f0 += M(W') - M(W), f1 += (dr/2)[Tr' M(W') - Tr M(W)],
 // both Maxwellians with the translational temperature.  The cell is uniform
 // over the block: its prefactors rho (pi T)^{-3/2} and 1/T are computed once
 // per wave, then one exponential per Maxwellian and point (the library's own
@@ -138,9 +131,8 @@ __global__ __launch_bounds__(256) void k_apply_correction(Geo g, Dev d, int nvb)
     const double pn = PI * c[4], po = PI * c[10];
     const double an = c[0] / (pn * sqrt(pn)), ao = c[6] / (po * sqrt(po));
     const double itn = 1.0 / c[4], ito = 1.0 / c[10];
-    int kx, ky, kz;
-    node_of(g, o, l, kx, ky, kz);
-    const double x = d.xi64[0][kx], y = d.xi64[1][ky], z = d.xi64[2][kz];
+    const double *t = d.nt64 + 4 * (size_t)node;
+    const double x = t[0], y = t[1], z = t[2];
     const double nx = x - c[1], ny = y - c[2], nz = z - c[3];
     const double ox = x - c[7], oy = y - c[8], oz = z - c[9];
     const double mn = an * exp_core(fmax(-(nx * nx + ny * ny + nz * nz) * itn, -745.0));
@@ -158,7 +150,7 @@ __global__ __launch_bounds__(256) void k_apply_correction(Geo g, Dev d, int nvb)
 // = prod_a exp(-(xi_a - u_a)^2 / T), so one block per cell stages the 1-D
 // factors of both Maxwellians in LDS (the prefactor folded into the x
 // factor) and every point takes three products instead of two exponentials.
-// Used when every axis has at most CTAB nodes.
+// Used on a tensor grid whose axes have at most CTAB nodes each.
 constexpr int CTAB = 256;
 
 template <typename T>
@@ -255,7 +247,7 @@ hipError_t launch_vdf_node(const Geo &g, const Dev &d, bool fp32, int node, doub
 
 hipError_t launch_apply_correction(const Geo &g, const Dev &d, bool fp32, hipStream_t s)
 {
-    if (g.n1[0] <= CTAB && g.n1[1] <= CTAB && g.n1[2] <= CTAB) {
+    if (!g.vlist && g.n1[0] <= CTAB && g.n1[1] <= CTAB && g.n1[2] <= CTAB) {
         if (fp32) hipLaunchKernelGGL(k_apply_correction_sep<float>, dim3(g.ncell), dim3(256), 0, s, g, d);
         else hipLaunchKernelGGL(k_apply_correction_sep<double>, dim3(g.ncell), dim3(256), 0, s, g, d);
         return hipGetLastError();

@@ -81,6 +81,11 @@ class Context:
                 x = np.ascontiguousarray(x, dtype=np.float64)
                 self._check(self.L.gsis_set_velocity_nodes(self.h, a, x.ctypes.data_as(C.c_void_p), x.size),
                             "gsis_set_velocity_nodes")
+        if case.velocity_list is not None:
+            t = np.ascontiguousarray(case.velocity_list, dtype=np.float64)
+            self._vlist = t
+            self._check(self.L.gsis_set_velocity_list(self.h, t.ctypes.data_as(C.c_void_p), t.shape[0]),
+                        "gsis_set_velocity_list")
 
     def _check(self, st: int, where: str):
         if st:

@@ -81,6 +81,10 @@ class Case:
     # optional node positions per axis (strictly increasing, nv[a] each); None:
     # nv[a] uniform nodes on [vmin[a], vmax[a]]
     nodes: Optional[Tuple[Optional[np.ndarray], Optional[np.ndarray], Optional[np.ndarray]]] = None
+    # optional general velocity set, [n][4] = (xi_x, xi_y, xi_z, w): one node per
+    # velocity cell of a refined or unstructured mesh, its weight the cell's
+    # volume; replaces the tensor grid (nv, vmin, vmax and nodes are then unused)
+    velocity_list: Optional[np.ndarray] = None
     # iteration plan of the workload
     passes: int = 10
     gsis: bool = False
@@ -94,6 +98,8 @@ class Case:
 
     @property
     def nvel(self) -> int:
+        if self.velocity_list is not None:
+            return int(self.velocity_list.shape[0])
         return self.nv[0] * self.nv[1] * self.nv[2]
 
     @property
@@ -167,6 +173,63 @@ def with_nodes(case: Case, nodes) -> Case:
     return case
 
 
+def refined_velocity_mesh(center, radius: float, refine, H: float, r: int = 2) -> np.ndarray:
+    """A locally refined velocity mesh of Sec. 3.1 as a node list [n][4].
+
+    The ball |xi - center| <= radius is tiled by cubes of side H on a lattice
+    aligned with the origin; a cube is kept when its centre lies in the ball.
+    A kept cube that overlaps one of the refinement cubes (centre c, half
+    side L, given as ``refine = [(c, L), ...]``) is split into r^3 cubes of
+    side H / r, each kept when its own centre lies in the ball.  A node is the
+    centre of a cube and its weight the cube's volume.  Nodes are ordered by
+    (z, y, x) of their centres."""
+    center = np.asarray(center, dtype=np.float64)
+    lo = np.floor((center - radius) / H).astype(int)
+    hi = np.ceil((center + radius) / H).astype(int)
+    ax = [np.arange(lo[a], hi[a]) for a in range(3)]
+    K = np.stack(np.meshgrid(ax[0], ax[1], ax[2], indexing="ij"), axis=-1).reshape(-1, 3)
+    cen = (K + 0.5) * H
+    inside = np.sum((cen - center) ** 2, axis=1) <= radius * radius
+    cen = cen[inside]
+    split = np.zeros(cen.shape[0], dtype=bool)
+    for c, L in refine:
+        c = np.asarray(c, dtype=np.float64)
+        split |= np.all(np.abs(cen - c) < 0.5 * H + L, axis=1)   # the two cubes overlap
+    coarse = cen[~split]
+    off = (np.arange(r) + 0.5) / r - 0.5
+    sub = np.stack(np.meshgrid(off, off, off, indexing="ij"), axis=-1).reshape(-1, 3) * H
+    fine = (cen[split][:, None, :] + sub[None, :, :]).reshape(-1, 3)
+    fine = fine[np.sum((fine - center) ** 2, axis=1) <= radius * radius]
+    xi = np.concatenate([coarse, fine])
+    w = np.concatenate([np.full(coarse.shape[0], H ** 3), np.full(fine.shape[0], (H / r) ** 3)])
+    order = np.lexsort((xi[:, 0], xi[:, 1], xi[:, 2]))
+    return np.ascontiguousarray(np.column_stack([xi[order], w[order]]))
+
+
+def hypersonic_velocity_mesh(Ma: float, gamma: float, H: float, r: int = 2, T_inf: float = 1.0,
+                             T_w: float = 1.0) -> np.ndarray:
+    """The velocity mesh of Sec. 3.1 for a stream along +x at Mach Ma (units of
+    sqrt(2 R T_inf)): the ball centred at U_s = U_inf / (density ratio of the
+    normal shock) with radius 5 sqrt(R T_s), T_s the largest of the stagnation,
+    wall and free-stream temperatures, refined (cells of side H / r) on the
+    cubes of half side 3 sqrt(R T_inf) about U_inf and 3 sqrt(R T_w) about 0."""
+    U = free_stream_speed(Ma, gamma) * math.sqrt(T_inf)
+    ratio = (gamma + 1.0) * Ma * Ma / (2.0 + (gamma - 1.0) * Ma * Ma)
+    Tm = T_inf * (1.0 + 0.5 * (gamma - 1.0) * Ma * Ma)
+    Ts = max(Tm, T_w, T_inf)
+    srt = lambda T: math.sqrt(0.5 * T)   # sqrt(R T) in units of sqrt(2 R T0)
+    return refined_velocity_mesh((U / ratio, 0.0, 0.0), 5.0 * srt(Ts),
+                                 [((U, 0.0, 0.0), 3.0 * srt(T_inf)), ((0.0, 0.0, 0.0), 3.0 * srt(T_w))], H, r)
+
+
+def with_velocity_list(case: Case, nodes: np.ndarray, name: Optional[str] = None) -> Case:
+    """The case on the general velocity set ``nodes`` ([n][4])."""
+    case.velocity_list = np.ascontiguousarray(nodes, dtype=np.float64)
+    if name:
+        case.name = name
+    return case
+
+
 def c1() -> Case:
     """16^3 cavity, 16^3 nodes on [-4,4]^3, Kn = 0.1, lid 0.1, 10 source iterations, FP64."""
     return cavity(16, 16, 0.1, name="c1_cavity16_v16", passes=10)
@@ -181,6 +244,16 @@ def c3() -> Case:
     """Ma = 5 past a 16^3 block in 96x64x64 cells, 40^3 nodes on [-12,12]^3, Kn = 0.05, 20 passes."""
     return block_flow(96, 64, 64, ((40, 56), (24, 40), (24, 40)), 40, 12.0, 0.05,
                       name="c3_block96x64x64_v40", passes=20)
+
+
+def c3r() -> Case:
+    """The Ma = 5 block flow of c3 (96x64x64 cells, Kn = 0.05, 20 passes) on the
+    refined velocity mesh of Sec. 3.1: the ball of radius 10.8 about the
+    post-shock velocity, cells of side 1.0, and 0.5 in the refinement cubes
+    about the free-stream and wall velocities (7788 nodes)."""
+    c = block_flow(96, 64, 64, ((40, 56), (24, 40), (24, 40)), 40, 12.0, 0.05,
+                   name="c3r_block96x64x64_refined7788", passes=20)
+    return with_velocity_list(c, hypersonic_velocity_mesh(5.0, 5.0 / 3.0, 1.0, 2))
 
 
 def c4() -> Case:
@@ -228,9 +301,14 @@ def random_vdf(case: Case, seed: int, dtype=np.float64) -> Tuple[np.ndarray, Opt
     a Maxwellian-like envelope in node index times U(0.5, 1.5) noise."""
     rng = np.random.default_rng(seed)
     shape = (case.ncell, case.nvel)
-    axes = [np.linspace(case.vmin[a], case.vmax[a], case.nv[a]) for a in range(3)]
-    xz, xy, xx = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
-    env = np.exp(-(xx ** 2 + xy ** 2 + xz ** 2) / (1.0 + 0.25 * max(case.vmax) ** 2 / 16.0)).reshape(-1)
+    if case.velocity_list is not None:
+        xi = case.velocity_list[:, :3]
+        vm = float(np.abs(xi).max())
+        env = np.exp(-np.sum(xi ** 2, axis=1) / (1.0 + 0.25 * vm ** 2 / 16.0))
+    else:
+        axes = [np.linspace(case.vmin[a], case.vmax[a], case.nv[a]) for a in range(3)]
+        xz, xy, xx = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+        env = np.exp(-(xx ** 2 + xy ** 2 + xz ** 2) / (1.0 + 0.25 * max(case.vmax) ** 2 / 16.0)).reshape(-1)
     f0 = (env[None, :] * rng.uniform(0.5, 1.5, size=shape)).astype(dtype)
     f1 = None
     if case.species == DIATOMIC:

@@ -245,6 +245,41 @@ def test_velocity_nodes_validation():
         L.gsis_destroy(h)
 
 
+def test_velocity_list_validation():
+    """A general node list: argument checks, the node count it sets (the
+    workspace follows it), its exclusion from batches and from per-axis nodes."""
+    L = _lib.lib()
+    P = lambda a: a.ctypes.data_as(C.c_void_p)
+    nodes = I.hypersonic_velocity_mesh(5.0, 5.0 / 3.0, 2.0, 2)
+    n = nodes.shape[0]
+    st, h = _create(_cfg())
+    st2, h2 = _create(_cfg())
+    assert st == 0 and st2 == 0
+    try:
+        assert L.gsis_set_velocity_list(h, None, n) == -1
+        assert L.gsis_set_velocity_list(h, P(nodes), 1) == -1            # fewer than 2 nodes
+        bad = nodes.copy()
+        bad[7, 3] = 0.0
+        assert L.gsis_set_velocity_list(h, P(bad), n) == -1              # weight must be > 0
+        bad = nodes.copy()
+        bad[3, 1] = np.inf
+        assert L.gsis_set_velocity_list(h, P(bad), n) == -1
+        sz = [C.c_size_t(), C.c_size_t()]
+        assert L.gsis_workspace_size(h2, C.byref(sz[0])) == 0            # 6^3 = 216 nodes
+        assert L.gsis_set_velocity_list(h, P(nodes), n) == 0
+        good = np.linspace(-3.0, 4.0, 6)
+        assert L.gsis_set_velocity_nodes(h, 0, P(good), 6) == -2         # not a tensor grid now
+        assert L.gsis_workspace_size(h, C.byref(sz[1])) == 0
+        assert sz[1].value > sz[0].value * (n / 216) * 0.5
+        assert L.gsis_set_velocity_list(h, P(nodes), n) == -2            # frozen once sized
+    finally:
+        L.gsis_destroy(h)
+        L.gsis_destroy(h2)
+    a = G.Context(I.cavity(4, 6, 0.1), "fp32")
+    lst = G.Context(I.with_velocity_list(I.cavity(4, 6, 0.1), nodes), "fp32")
+    assert _batch([a, lst])[0] == -1
+
+
 def test_noalloc_residual_checks_before_device_work():
     """gsis_residual_noalloc refuses contexts beyond its static array (more than
     4096 blocks of 256 cells) before anything else, and otherwise checks the

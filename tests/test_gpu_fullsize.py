@@ -13,7 +13,7 @@ import sys
 import numpy as np
 import pytest
 
-from oracle.oracle import first_pass_nodes
+from oracle.oracle import first_pass_nodes, node_grid
 from paper_2310_18916_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -32,19 +32,15 @@ def say(msg):
 
 def sample_nodes(case, extra=6, seed=7):
     """The fastest and the slowest node of every octant, plus seeded random nodes."""
-    nvx, nvy, nvz = case.nv
-    xs = [np.linspace(case.vmin[a], case.vmax[a], case.nv[a]) for a in range(3)]
+    xi, _ = node_grid(case)
+    octant = (xi[:, 0] < 0) * 1 + (xi[:, 1] < 0) * 2 + (xi[:, 2] < 0) * 4
+    speed = (xi * xi).sum(1)
     picks = set()
     for o in range(8):
-        sel = []
-        for a in range(3):
-            neg = (o >> a) & 1
-            idx = np.nonzero(xs[a] < 0)[0] if neg else np.nonzero(xs[a] >= 0)[0]
-            sel.append(idx)
-        fast = [s[np.argmax(np.abs(xs[a][s]))] for a, s in enumerate(sel)]
-        slow = [s[np.argmin(np.abs(xs[a][s]))] for a, s in enumerate(sel)]
-        for k in (fast, slow):
-            picks.add(int(k[0] + nvx * (k[1] + nvy * k[2])))
+        idx = np.nonzero(octant == o)[0]
+        if idx.size:
+            picks.add(int(idx[np.argmax(speed[idx])]))
+            picks.add(int(idx[np.argmin(speed[idx])]))
     rng = np.random.default_rng(seed)
     picks.update(int(v) for v in rng.integers(0, case.nvel, extra))
     return np.array(sorted(picks), dtype=np.int32)
@@ -69,7 +65,8 @@ def first_pass_parity(case, dtype, tol):
 
 @pytest.mark.parametrize("workload,dtype,tol", [("c2", "fp64", 1e-13), ("c2", "fp32", 3e-6),
                                                 ("c3", "fp32", 3e-6), ("c3", "fp64", 1e-13),
-                                                ("c4", "fp32", 3e-6), ("c4", "fp64", 1e-13)])
+                                                ("c4", "fp32", 3e-6), ("c4", "fp64", 1e-13),
+                                                ("c3r", "fp32", 3e-6), ("c3r", "fp64", 1e-13)])
 def test_full_size_first_pass_matches_oracle(workload, dtype, tol):
     say(f"[full-size first pass] {workload} {dtype}")
     first_pass_parity(getattr(I, workload)(), dtype, tol)

@@ -15,7 +15,11 @@ cells, and the residual (tests/golden/make_fullsize.py):
 The GPU runs the same plan at full size, its first pass being the
 autotuner's (the launch configuration bench.py uses), in FP64 and FP32.
 Norm: max over the sampled cells of |X_gpu - X_oracle| divided by the
-oracle's max |X| over all fluid cells (u: over the three components).  Bars:
+oracle's max |X| over all fluid cells (u: over the three components); for
+sigma, q and q_r by that max or 1, the reference pressure (heat flux) of the
+dimensionless variables, whichever is larger, since a field that vanishes
+analytically (q_r after the first pass of the diatomic block flow is 1e-6)
+keeps the absolute rounding of the raw sums it is computed from.  Bars:
 FP64 1e-12 and FP32 1e-5 on rho, u, T (and T_r); sigma and q are held to
 1e-10 (FP64) and 1e-4 (FP32), which bounds the cancellation of the raw-moment
 reduction at Mach 5.
@@ -53,7 +57,7 @@ def groups(nm):
 
 
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
-@pytest.mark.parametrize("workload", ["c2"])
+@pytest.mark.parametrize("workload", ["c2", "c4"])
 def test_full_size_matches_streaming_oracle(workload, dtype):
     path = os.path.join(GOLDEN, f"fullsize_{workload}.npz")
     gold = np.load(path, allow_pickle=False)
@@ -86,7 +90,8 @@ def test_full_size_matches_streaming_oracle(workload, dtype):
                 assert np.all(np.isfinite(m))
                 errs = {}
                 for g, cols in groups(m.shape[1]).items():
-                    errs[g] = float(np.abs(m[:, cols] - mo[:, cols]).max() / fmax[cols].max())
+                    scale = fmax[cols].max() if g in ("rho", "u", "T", "Tr") else max(fmax[cols].max(), 1.0)
+                    errs[g] = float(np.abs(m[:, cols] - mo[:, cols]).max() / scale)
                 ee = float(np.abs(eps - eo).max() / np.abs(eo).max())
                 say(f"  stage {rec} (after step {k}): " + ", ".join(f"{g} {v:.2e}" for g, v in errs.items())
                     + f"; eps {eps} oracle {eo} (rel {ee:.1e})")
