@@ -32,10 +32,12 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"],
+    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c3r", "c4", "c5"],
                    help="headline workload (c5 runs only the 64-cavity batch)")
     p.add_argument("--no-gsis-extras", action="store_true",
                    help="skip the c2 GSIS step, convergence and second-order runs beside a c3/c4 headline")
+    p.add_argument("--no-refined", action="store_true",
+                   help="skip the passes of the block flow on the refined velocity mesh beside a c3 headline")
     p.add_argument("--dtype", default=None, choices=["fp64", "fp32"])
     p.add_argument("--macro-iters", type=int, default=None)
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -85,7 +87,7 @@ def sweep_traffic(dtype, tile, workload_name):
 
 def workload(name):
     from paper_2310_18916_amd import inputs as I
-    return {"c1": I.c1, "c2": I.c2, "c3": I.c3, "c4": I.c4}[name]()
+    return {"c1": I.c1, "c2": I.c2, "c3": I.c3, "c3r": I.c3r, "c4": I.c4}[name]()
 
 
 def run_gpu(case, dtype, steps, warmup, macro_iters, tile):
@@ -379,6 +381,29 @@ def gsis_extras(a, steps, warmup):
     return out
 
 
+def refined_mesh(steps, warmup):
+    """Kinetic passes of the c3 block flow on the refined velocity mesh of
+    Sec. 3.1 (a node list: per-node tables and direct-sum kernels), FP64 and
+    FP32, with the phase times and the sweep's and moments' HBM rates."""
+    import torch
+    case = workload("c3r")
+    pts = case.nfluid * case.nvel
+    res = {"workload": case.name, "nodes": case.nvel, "cells": case.ncell}
+    for dtype in ("fp64", "fp32"):
+        r = run_gpu(case, dtype, steps, warmup, 0, None)
+        esz = 8 if dtype == "fp64" else 4
+        prof = r["prof"]
+        sweep_ms, n = prof["sweep"]
+        mom_ms, _ = prof["moments"]
+        res[dtype] = {"value": pts * steps / r["seconds"], "ms_per_pass": r["seconds"] / steps * 1e3,
+                      "phases_ms_per_pass": {k: v[0] / steps for k, v in prof.items() if v[1]},
+                      "sweep_gbs": pts * esz / (sweep_ms / n * 1e-3) / 1e9,
+                      "moments_gbs": pts * esz / (mom_ms / n * 1e-3) / 1e9, "sweep_tile": r["tile"]}
+        del r
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -480,6 +505,8 @@ def main():
                                 "speedup_fp32_vs_fp64_time_to_converge": c64["seconds"] / c32["seconds"]}
     elif not a.no_gsis_extras:
         out["gsis_c2"] = gsis_extras(a, steps, a.warmup)
+    if a.workload == "c3" and not a.no_refined:
+        out["refined_velocity_mesh"] = refined_mesh(max(3, steps // 4), 2)
     if not a.no_batch:
         out["batched"] = batched(a.batch_iters)
     if a.copy_calib_mib > 0:

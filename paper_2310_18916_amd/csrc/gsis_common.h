@@ -15,6 +15,8 @@ constexpr int NBC = 7;     // 6 box faces + solid surface
 constexpr int NCORR = 12;  // pending GSIS correction per cell: new (rho,u,Tt,Tr), old (rho,u,Tt,Tr)
 constexpr int NSNAP = 5;   // residual snapshot per cell: rho, u, Tt
 constexpr double PI = 3.14159265358979323846;
+constexpr int LSUM_SHAPE = 20;        // node list: Gram entries (15) and Shakhov moments (5) of one shape
+constexpr int LSUM = 2 * LSUM_SHAPE;  // per cell: the Tt shape, then the T shape (diatomic)
 
 // Geometry, velocity grid and gas constants, passed to kernels by value.
 //
@@ -81,6 +83,7 @@ struct Dev {
     float *fscalef;
     double *cfs64;     // [ncell][6] the same scale by (cell, face direction), for the sweep
     float *cfs32;
+    double *lsum;      // node list: [ncell][LSUM] shape sums of the relaxation parameters (else null)
     double *nt64;      // [nv][4] every node in the internal order: xi_x, xi_y, xi_z, weight
     float *nt32;       // [nv][4] the same in FP32
     double *xi64[3];   // per-axis nodes (tensor grid)

@@ -284,6 +284,8 @@ size_t layout(gsis_ctx *c, char *base)
     carve(off, d.fscalef, nf, base);
     carve(off, d.cfs64, n * 6, base);
     carve(off, d.cfs32, n * 6, base);
+    d.lsum = nullptr;
+    if (g.vlist) carve(off, d.lsum, n * LSUM, base);
     carve(off, d.nt64, nv * 4, base);
     carve(off, d.nt32, nv * 4, base);
     for (int a = 0; a < 3; ++a) {

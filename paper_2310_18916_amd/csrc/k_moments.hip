@@ -295,30 +295,36 @@ __device__ __forceinline__ void store_octant_sums(const double *acc, const doubl
     if (!DIA && !add && lane == 0) out[NRS - 1] = 0.0;
 }
 
-// Node list: one wave per octant of a group of CG consecutive cells (block =
-// 8 waves, one per octant).  A lane takes the octant's nodes 64 apart, reads
-// each node's (xi, w) once and applies its monomials to the node's value in
-// every cell of the group, so the node table is read once per CG cells while
-// each VDF load covers 64 consecutive nodes of one cell.
+// Node list: one wave (block) per octant of a group of CG consecutive cells.
+// A lane takes the octant's nodes 64 apart, reads each node's (xi, w) once
+// and applies its monomials to the node's value in every cell of the group,
+// so the node table is read once per CG cells while each VDF load covers 64
+// consecutive nodes of one cell.  Two nodes per lane and step, and the loads
+// of all cells issued unconditionally (rows clamped to the last cell, a dead
+// or missing cell's sums discarded at the end), keep 2 CG loads in flight.
 template <typename T, bool DIA, int CG>
-__global__ __launch_bounds__(512) void k_moments_list(GSIS_SPAN_ARGS)
+__global__ __launch_bounds__(64) void k_moments_list(GSIS_SPAN_ARGS)
 {
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
     const Geo &g = C.g;
-    const gptr<const T> f0 = (gptr<const T>)C.d.f0;
-    const gptr<const T> f1 = (gptr<const T>)C.d.f1;
     const gptr<const int> cflag = (gptr<const int>)C.d.cflag;
     const gptr<const double> nt = (gptr<const double>)C.d.nt64;
     const gptr<double> mom8 = (gptr<double>)C.d.mom8;
-    const int o = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    const int cell0 = blk * CG;
+    const int o = blk & 7;
+    const int cell0 = (blk >> 3) * CG;
+    const int lane = threadIdx.x;
     const int n = g.osize[o], ob = g.obase[o];
     const size_t nv = (size_t)g.nv;
+    gptr<const T> r0[CG], r1[CG];
     bool live[CG];
 #pragma unroll
-    for (int c = 0; c < CG; ++c) live[c] = cell0 + c < g.ncell && cflag[cell0 + c];   // uniform over the wave
+    for (int c = 0; c < CG; ++c) {
+        const int cc = min(cell0 + c, g.ncell - 1);
+        live[c] = cell0 + c < g.ncell && cflag[cc];   // uniform over the wave
+        r0[c] = (gptr<const T>)C.d.f0 + (size_t)cc * nv + ob;
+        r1[c] = DIA ? (gptr<const T>)C.d.f1 + (size_t)cc * nv + ob : r0[c];
+    }
     double acc[CG][13], acc1[CG][4];
 #pragma unroll
     for (int c = 0; c < CG; ++c) {
@@ -327,30 +333,55 @@ __global__ __launch_bounds__(512) void k_moments_list(GSIS_SPAN_ARGS)
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc1[c][k] = 0.0;
     }
-    for (int l = lane; l < n; l += 64) {
-        const size_t node = (size_t)ob + l;
-        double v[CG], v1[CG];
+    for (int l0 = 0; l0 < n; l0 += 128) {
+        int li[2];
+        double sc[2];
 #pragma unroll
-        for (int c = 0; c < CG; ++c) {
-            v[c] = live[c] ? (double)f0[(size_t)(cell0 + c) * nv + node] : 0.0;
-            if (DIA) v1[c] = live[c] ? (double)f1[(size_t)(cell0 + c) * nv + node] : 0.0;
+        for (int h = 0; h < 2; ++h) {
+            const int l = l0 + h * 64 + lane;
+            li[h] = min(l, n - 1);
+            sc[h] = l < n ? 1.0 : 0.0;   // a repeated last node counts zero
         }
-        double t[4] = {nt[4 * node], nt[4 * node + 1], nt[4 * node + 2], nt[4 * node + 3]};
-        double m[13];
-        node_monomials(t, m);
+        T v[2][CG], v1[2][CG];
+        double t[2][4];
 #pragma unroll
-        for (int c = 0; c < CG; ++c) {
+        for (int h = 0; h < 2; ++h) {
 #pragma unroll
-            for (int k = 0; k < 13; ++k) acc[c][k] += m[k] * v[c];
-            if (DIA) {
+            for (int c = 0; c < CG; ++c) {
+                v[h][c] = r0[c][li[h]];
+                if (DIA) v1[h][c] = r1[c][li[h]];
+            }
+            const gptr<const double> tp = nt + 4 * ((size_t)ob + li[h]);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) acc1[c][k] += m[k] * v1[c];
+            for (int q = 0; q < 4; ++q) t[h][q] = tp[q];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            t[h][3] *= sc[h];
+            double m[13];
+            node_monomials(t[h], m);
+#pragma unroll
+            for (int c = 0; c < CG; ++c) {
+                const double x = (double)v[h][c];
+#pragma unroll
+                for (int k = 0; k < 13; ++k) acc[c][k] += m[k] * x;
+                if (DIA) {
+                    const double x1 = (double)v1[h][c];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) acc1[c][k] += m[k] * x1;
+                }
             }
         }
     }
 #pragma unroll
     for (int c = 0; c < CG; ++c) {
         if (cell0 + c >= g.ncell) break;
+        if (!live[c]) {
+#pragma unroll
+            for (int k = 0; k < 13; ++k) acc[c][k] = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc1[c][k] = 0.0;
+        }
         store_octant_sums<DIA>(acc[c], acc1[c], lane, mom8 + ((size_t)(cell0 + c) * 8 + o) * NRS, false);
     }
 }
@@ -546,7 +577,7 @@ static void moments_list(const Target &t, hipStream_t s)
 {
     constexpr int CG = list_cg<DIA>();
     const int ncell = t.host[0].g.ncell;
-    hipLaunchKernelGGL((k_moments_list<T, DIA, CG>), dim3((ncell + CG - 1) / CG), dim3(512), 0, s,
+    hipLaunchKernelGGL((k_moments_list<T, DIA, CG>), dim3(8 * ((ncell + CG - 1) / CG)), dim3(64), 0, s,
                        GSIS_SPAN(t.span(K_CELL1)));
 }
 

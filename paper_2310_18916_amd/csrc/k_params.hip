@@ -12,9 +12,8 @@
 // the 5x5 Gram matrix sum w phi phi^T M and the Shakhov term's moments factor
 // into 1-D sums C_a(p) = sum_k w_k c^p exp(-c^2/T), p <= 5, so the correction
 // costs O(n per axis) per cell.  On a node list (a refined or unstructured
-// velocity mesh, Sec. 3.1) the same products are read from a table of the
-// moments sum_k w_k c_x^p c_y^q c_z^r exp(-|c|^2/T), p + q + r <= 5 (56 of
-// them), summed over the nodes by one wave per cell.
+// velocity mesh, Sec. 3.1) nothing factors: the Gram matrix and the Shakhov
+// moments are summed over the nodes directly, one wave per cell.
 #include "gsis_common.h"
 #include "gsis_launch.h"
 
@@ -40,12 +39,6 @@ struct Sep {
     __device__ double m(int p, int q, int r) const { return C[0][p] * C[1][q] * C[2][r]; }
 };
 
-// moments m(p, q, r), p + q + r <= 5, held in a dense 6x6x6 table (LDS)
-struct Tab {
-    const double *t;
-    __device__ double m(int p, int q, int r) const { return t[(p * 6 + q) * 6 + r]; }
-};
-
 // phi = (1, c_x, c_y, c_z, |c|^2) as monomial lists
 __device__ __forceinline__ int phi_terms(int i, int t[3][3])
 {
@@ -59,8 +52,7 @@ __device__ __forceinline__ int phi_terms(int i, int t[3][3])
 
 // Gram G_ij = sum phi_i phi_j E and Shakhov moments bS_i = sum phi_i E [1 + (qp.c)(|c|^2 kT - 5/2)],
 // both without the prefactor rho (pi T)^{-3/2}.
-template <class S3>
-__device__ void gram_and_shakhov(const S3 &S, const double qp[3], double kT, double G[25], double bS[5])
+__device__ void gram_and_shakhov(const Sep &S, const double qp[3], double kT, double G[25], double bS[5])
 {
     int ti[3][3], tj[3][3];
     for (int i = 0; i < 5; ++i) {
@@ -118,27 +110,33 @@ __device__ bool solve5(double *A, double *b)
     return true;
 }
 
+// Gram matrix and Shakhov moments of one shape on the velocity grid (without
+// the prefactor): G_ij = sum w phi_i phi_j E, bS_i = sum w phi_i E [1 +
+// (qp.c)(|c|^2 kT - 5/2)].  G_00 = sum w E and G_0a = sum w c_a E.
+struct ShapeSums {
+    double G[25], bS[5];
+};
+
 // Correction lambda (c-basis) of one component with shape rho (pi T)^{-3/2} E:
 // K G lambda = target - K bS, target = (rho, 0, 0, 0, 1.5 rho T).
-template <class S3>
-__device__ void correction(const S3 &S, double K, double rho, double T, const double qp[3], double kT,
-                           bool conservative, double lam[5], double bS[5])
+__device__ void correction(const ShapeSums &S, double K, double rho, double T, bool conservative, double lam[5])
 {
-    double G[25];
-    gram_and_shakhov(S, qp, kT, G, bS);
     for (int i = 0; i < 5; ++i) lam[i] = 0.0;
     if (!conservative) return;
+    double G[25];
+    for (int i = 0; i < 25; ++i) G[i] = K * S.G[i];
     double tgt[5] = {rho, 0.0, 0.0, 0.0, 1.5 * rho * T};
-    for (int i = 0; i < 25; ++i) G[i] *= K;
-    for (int i = 0; i < 5; ++i) lam[i] = tgt[i] - K * bS[i];
+    for (int i = 0; i < 5; ++i) lam[i] = tgt[i] - K * S.bS[i];
     if (!solve5(G, lam))
         for (int i = 0; i < 5; ++i) lam[i] = 0.0;
 }
 
-// Moments of one cell and the temperatures of its shapes.
+// Moments of one cell and what follows from them alone.
 struct CellState {
     double rho, u[3], Tt, q[3], invtau;
-    double Tr, qr[3], T;   // diatomic; T = (3 Tt + dr Tr) / (3 + dr)
+    double qpt[3];          // (4/15) q / (rho Tt^2), the Shakhov vector of the Tt shape
+    double Tr, qr[3], T;    // diatomic; T = (3 Tt + dr Tr) / (3 + dr)
+    double q1[3], qpr[3];   // diatomic: q1 = -A_rt Z q + (1 - A_rr Z) qr; qpr of the T shape
 };
 
 // false for a solid cell (its parameters are zeroed)
@@ -156,12 +154,20 @@ __device__ bool cell_state(const Geo &g, const Dev &d, int cell, CellState &st)
     st.Tt = m[4];
     st.invtau = g.delta * st.rho * pow(st.Tt, 1.0 - g.omega);
     if (!(st.rho > 0.0) || !(st.Tt > 0.0) || !isfinite(st.invtau)) atomicOr(d.errflag, 1);
+    for (int a = 0; a < 3; ++a) st.qpt[a] = (4.0 / 15.0) * st.q[a] / (st.rho * st.Tt * st.Tt);
     st.Tr = st.T = st.Tt;
-    for (int a = 0; a < 3; ++a) st.qr[a] = 0.0;
+    for (int a = 0; a < 3; ++a) st.qr[a] = st.q1[a] = st.qpr[a] = 0.0;
     if (g.species != 0) {
         st.Tr = m[14];
         for (int a = 0; a < 3; ++a) st.qr[a] = m[15 + a];
-        st.T = (3.0 * st.Tt + g.dr * st.Tr) / (3.0 + g.dr);
+        const double T = (3.0 * st.Tt + g.dr * st.Tr) / (3.0 + g.dr);
+        st.T = T;
+        const double Z = g.Zr, Att = g.A[0], Atr = g.A[1], Art = g.A[2], Arr = g.A[3];
+        for (int a = 0; a < 3; ++a) {
+            const double q0 = ((2.0 - 3.0 * Att) * Z + 1.0) * st.q[a] + (-3.0 * Atr * Z) * st.qr[a];
+            st.q1[a] = (-Art * Z) * st.q[a] + (-Arr * Z + 1.0) * st.qr[a];
+            st.qpr[a] = (4.0 / 15.0) * q0 / (st.rho * T * T);
+        }
     }
     return true;
 }
@@ -173,76 +179,61 @@ __device__ bool cell_state(const Geo &g, const Dev &d, int cell, CellState &st)
 //             7 P0t, 8-10 l_t, 11 l4t, 12-14 qp_t, 15 P0r, 16-18 l_r, 19 l4r, 20-22 qp_r,
 //             23 ht = (dr/2) Tr, 24-26 2 qr / (rho Tt), 27 nu_t,
 //             28 hr = (dr/2) T, 29-31 2 q1 / (rho T), 32 nu_r, 33 1/tau
-// St: the moments of the shape exp(-|c|^2/Tt) on the velocity grid; Sr: of
-// exp(-|c|^2/T) (diatomic only).
-template <class S3>
-__device__ void cell_params(const Geo &g, const Dev &d, int cell, const CellState &st, const S3 &St, const S3 &Sr)
+// Et: the sums of the shape exp(-|c|^2/Tt) with qp_t on the velocity grid;
+// Er: of exp(-|c|^2/T) with qp_r (diatomic only).
+__device__ void cell_params(const Geo &g, const Dev &d, int cell, const CellState &st, const ShapeSums &Et,
+                            const ShapeSums &Er)
 {
     double *p = d.par + (size_t)cell * NPAR;
     float *pf = d.parf + (size_t)cell * NPAR;
     const double rho = st.rho, Tt = st.Tt, invtau = st.invtau;
-    const double *u = st.u, *q = st.q;
+    const double *u = st.u;
     for (int k = 0; k < NPAR; ++k) p[k] = 0.0;
     bool cons = g.conservative != 0;
     if (g.species == 0) {
         double K = rho * pow(PI * Tt, -1.5);
-        double kT = 1.0 / Tt;
-        double qp[3];
-        for (int a = 0; a < 3; ++a) qp[a] = (4.0 / 15.0) * q[a] / (rho * Tt * Tt);
-        double lam[5], bS[5];
-        correction(St, K, rho, Tt, qp, kT, cons, lam, bS);
+        double lam[5];
+        correction(Et, K, rho, Tt, cons, lam);
         p[0] = u[0]; p[1] = u[1]; p[2] = u[2];
-        p[3] = kT;
+        p[3] = 1.0 / Tt;
         p[4] = K * invtau;
         p[5] = 1.0 + lam[0];
         p[6] = lam[1]; p[7] = lam[2]; p[8] = lam[3];
         p[9] = lam[4];
-        p[10] = qp[0]; p[11] = qp[1]; p[12] = qp[2];
+        p[10] = st.qpt[0]; p[11] = st.qpt[1]; p[12] = st.qpt[2];
         p[13] = invtau;
     } else {
-        const double Tr = st.Tr, T = st.T, *qr = st.qr;
+        const double Tr = st.Tr, T = st.T, *qr = st.qr, *q1 = st.q1;
         double dr = g.dr, Z = g.Zr;
-        double Att = g.A[0], Atr = g.A[1], Art = g.A[2], Arr = g.A[3];
-        double q0[3], q1[3];
-        for (int a = 0; a < 3; ++a) {
-            q0[a] = ((2.0 - 3.0 * Att) * Z + 1.0) * q[a] + (-3.0 * Atr * Z) * qr[a];
-            q1[a] = (-Art * Z) * q[a] + (-Arr * Z + 1.0) * qr[a];
-        }
         double Kt = rho * pow(PI * Tt, -1.5), Kr = rho * pow(PI * T, -1.5);
-        double kTt = 1.0 / Tt, kT = 1.0 / T;
-        double qpt[3], qpr[3];
-        for (int a = 0; a < 3; ++a) {
-            qpt[a] = (4.0 / 15.0) * q[a] / (rho * Tt * Tt);
-            qpr[a] = (4.0 / 15.0) * q0[a] / (rho * T * T);
-        }
-        double lt[5], lr[5], bSt[5], bSr[5];
-        correction(St, Kt, rho, Tt, qpt, kTt, cons, lt, bSt);
-        correction(Sr, Kr, rho, T, qpr, kT, cons, lr, bSr);
+        double lt[5], lr[5];
+        correction(Et, Kt, rho, Tt, cons, lt);
+        correction(Er, Kr, rho, T, cons, lr);
         double ht = 0.5 * dr * Tr, hr = 0.5 * dr * T;
         double qrt[3], q1r[3];
         for (int a = 0; a < 3; ++a) {
             qrt[a] = 2.0 * qr[a] / (rho * Tt);
             q1r[a] = 2.0 * q1[a] / (rho * T);
         }
-        // sum_w g_1t = ht Kt bSt[0] + Kt qrt.m(e_a); the correction nu Kt E matches (dr/2) rho Tr
-        double s1t = ht * Kt * bSt[0] + Kt * (qrt[0] * St.m(1, 0, 0) + qrt[1] * St.m(0, 1, 0) + qrt[2] * St.m(0, 0, 1));
-        double s1r = hr * Kr * bSr[0] + Kr * (q1r[0] * Sr.m(1, 0, 0) + q1r[1] * Sr.m(0, 1, 0) + q1r[2] * Sr.m(0, 0, 1));
-        double nut = cons ? (0.5 * dr * rho * Tr - s1t) / (Kt * St.m(0, 0, 0)) : 0.0;
-        double nur = cons ? (0.5 * dr * rho * T - s1r) / (Kr * Sr.m(0, 0, 0)) : 0.0;
+        // sum_w g_1t = ht Kt bSt[0] + Kt qrt.(sum w c E); the correction nu Kt E matches (dr/2) rho Tr
+        double s1t = ht * Kt * Et.bS[0] + Kt * (qrt[0] * Et.G[1] + qrt[1] * Et.G[2] + qrt[2] * Et.G[3]);
+        double s1r = hr * Kr * Er.bS[0] + Kr * (q1r[0] * Er.G[1] + q1r[1] * Er.G[2] + q1r[2] * Er.G[3]);
+        double nut = cons ? (0.5 * dr * rho * Tr - s1t) / (Kt * Et.G[0]) : 0.0;
+        double nur = cons ? (0.5 * dr * rho * T - s1r) / (Kr * Er.G[0]) : 0.0;
         double iz = 1.0 / Z;
         p[0] = u[0]; p[1] = u[1]; p[2] = u[2];
-        p[3] = kTt;
-        p[4] = kT;
+        p[3] = 1.0 / Tt;
+        p[4] = 1.0 / T;
         p[5] = (1.0 - iz) * Kt * invtau;
         p[6] = iz * Kr * invtau;
         p[7] = 1.0 + lt[0];
         p[8] = lt[1]; p[9] = lt[2]; p[10] = lt[3];
         p[11] = lt[4];
-        p[12] = qpt[0]; p[13] = qpt[1]; p[14] = qpt[2];
+        p[12] = st.qpt[0]; p[13] = st.qpt[1]; p[14] = st.qpt[2];
         p[15] = 1.0 + lr[0];
         p[16] = lr[1]; p[17] = lr[2]; p[18] = lr[3];
         p[19] = lr[4];
-        p[20] = qpr[0]; p[21] = qpr[1]; p[22] = qpr[2];
+        p[20] = st.qpr[0]; p[21] = st.qpr[1]; p[22] = st.qpr[2];
         p[23] = ht;
         p[24] = qrt[0]; p[25] = qrt[1]; p[26] = qrt[2];
         p[27] = nut;
@@ -254,7 +245,7 @@ __device__ void cell_params(const Geo &g, const Dev &d, int cell, const CellStat
     for (int k = 0; k < NPAR; ++k) pf[k] = (float)p[k];
 }
 
-// Tensor grid: one thread per cell, the shape moments from 1-D sums.
+// Tensor grid: one thread per cell, the shape sums from 1-D sums.
 __global__ __launch_bounds__(64) void k_params(GSIS_SPAN_ARGS)
 {
     int blk;
@@ -265,23 +256,33 @@ __global__ __launch_bounds__(64) void k_params(GSIS_SPAN_ARGS)
     if (cell >= g.ncell) return;
     CellState st;
     if (!cell_state(g, d, cell, st)) return;
-    Sep St, Sr;
-    for (int a = 0; a < 3; ++a) axis_central(d.xi64[a], d.w64[a], g.n1[a], st.u[a], st.Tt, St.C[a]);
-    if (g.species != 0)
-        for (int a = 0; a < 3; ++a) axis_central(d.xi64[a], d.w64[a], g.n1[a], st.u[a], st.T, Sr.C[a]);
-    cell_params(g, d, cell, st, St, g.species != 0 ? Sr : St);
+    ShapeSums Et, Er;
+    {
+        Sep S;
+        for (int a = 0; a < 3; ++a) axis_central(d.xi64[a], d.w64[a], g.n1[a], st.u[a], st.Tt, S.C[a]);
+        gram_and_shakhov(S, st.qpt, 1.0 / st.Tt, Et.G, Et.bS);
+    }
+    if (g.species != 0) {
+        Sep S;
+        for (int a = 0; a < 3; ++a) axis_central(d.xi64[a], d.w64[a], g.n1[a], st.u[a], st.T, S.C[a]);
+        gram_and_shakhov(S, st.qpr, 1.0 / st.T, Er.G, Er.bS);
+    }
+    cell_params(g, d, cell, st, Et, g.species != 0 ? Er : Et);
 }
 
-// Node list: one wave per cell.  Each lane sums the 56 moments of the shape
-// over the nodes 64 apart; the partial sums go through LDS, where lane k adds
-// the 64 partials of moment k in lane order; lane 0 then builds the
-// parameters from the table.
-constexpr int NTAB = 56;
-
-__global__ __launch_bounds__(64) void k_params_list(GSIS_SPAN_ARGS)
+// Node list, in two kernels.  k_params_list_sums: one wave per cell; each
+// lane sums, over the nodes 64 apart (two nodes per step, two independent
+// exponentials in flight), the 15 distinct Gram entries and the 5 Shakhov
+// moments of each shape directly; the partial sums go through LDS, where lane
+// k adds the 64 partials of sum k in lane order, into d.lsum.
+// k_params_list_finish: one thread per cell builds the parameters from them
+// (kept apart so the summing kernel's register count, and so its occupancy,
+// does not carry the dense solves).
+template <int NSH>
+__global__ __launch_bounds__(64) void k_params_list_sums(GSIS_SPAN_ARGS)
 {
-    __shared__ double part[NTAB][65];
-    __shared__ double tab[2][216];
+    constexpr int NS = LSUM_SHAPE, NA = NS * NSH;
+    __shared__ double part[NA][65];
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
     const Geo &g = C.g;
@@ -290,51 +291,79 @@ __global__ __launch_bounds__(64) void k_params_list(GSIS_SPAN_ARGS)
     const int lane = threadIdx.x;
     CellState st;
     if (!cell_state(g, d, cell, st)) return;   // uniform over the block
-    const int nsh = g.species != 0 ? 2 : 1;
     const gptr<const double> nt = (gptr<const double>)d.nt64;
-    for (int sh = 0; sh < nsh; ++sh) {
-        const double iT = 1.0 / (sh ? st.T : st.Tt);
-        double acc[NTAB];
+    double iT[NSH], qp[NSH][3];
 #pragma unroll
-        for (int k = 0; k < NTAB; ++k) acc[k] = 0.0;
-        for (int node = lane; node < g.nv; node += 64) {
-            const double cx = nt[4 * (size_t)node] - st.u[0];
-            const double cy = nt[4 * (size_t)node + 1] - st.u[1];
-            const double cz = nt[4 * (size_t)node + 2] - st.u[2];
-            const double e = nt[4 * (size_t)node + 3] * exp_core(fmax(-(cx * cx + cy * cy + cz * cz) * iT, -745.0));
-            double X[6], Y[6], Z[6];
-            X[0] = e; Y[0] = 1.0; Z[0] = 1.0;
+    for (int sh = 0; sh < NSH; ++sh) {
+        iT[sh] = 1.0 / (sh ? st.T : st.Tt);
 #pragma unroll
-            for (int p = 1; p < 6; ++p) { X[p] = X[p - 1] * cx; Y[p] = Y[p - 1] * cy; Z[p] = Z[p - 1] * cz; }
-            int k = 0;
-#pragma unroll
-            for (int q = 0; q < 6; ++q)
-#pragma unroll
-                for (int r = 0; r + q < 6; ++r) {
-                    const double yz = Y[q] * Z[r];
-#pragma unroll
-                    for (int p = 0; p + q + r < 6; ++p) acc[k++] += X[p] * yz;
-                }
-        }
-#pragma unroll
-        for (int k = 0; k < NTAB; ++k) part[k][lane] = acc[k];
-        __syncthreads();
-        if (lane < NTAB) {
-            // moment number lane -> (p, q, r) in the order of the loops above
-            int k = 0, pp = 0, qq = 0, rr = 0;
-            for (int q = 0; q < 6; ++q)
-                for (int r = 0; r + q < 6; ++r)
-                    for (int p = 0; p + q + r < 6; ++p) {
-                        if (k == lane) { pp = p; qq = q; rr = r; }
-                        ++k;
-                    }
-            double sum = 0.0;
-            for (int j = 0; j < 64; ++j) sum += part[lane][j];
-            tab[sh][(pp * 6 + qq) * 6 + rr] = sum;
-        }
-        __syncthreads();
+        for (int a = 0; a < 3; ++a) qp[sh][a] = sh ? st.qpr[a] : st.qpt[a];
     }
-    if (lane == 0) cell_params(g, d, cell, st, Tab{tab[0]}, Tab{tab[nsh - 1]});
+    double acc[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) acc[k] = 0.0;
+    const int nv = g.nv;
+    for (int l0 = 0; l0 < nv; l0 += 128) {
+        double t[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int l = l0 + h * 64 + lane;
+            const gptr<const double> tp = nt + 4 * (size_t)min(l, nv - 1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t[h][q] = tp[q];
+            if (l >= nv) t[h][3] = 0.0;   // a repeated last node counts zero
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double cx = t[h][0] - st.u[0], cy = t[h][1] - st.u[1], cz = t[h][2] - st.u[2];
+            const double c2 = cx * cx + cy * cy + cz * cz;
+            const double phi[5] = {1.0, cx, cy, cz, c2};
+#pragma unroll
+            for (int sh = 0; sh < NSH; ++sh) {
+                const double E = t[h][3] * exp_core(fmax(-c2 * iT[sh], -745.0));
+                const double sE = E * (1.0 + (qp[sh][0] * cx + qp[sh][1] * cy + qp[sh][2] * cz) * (c2 * iT[sh] - 2.5));
+                int k = sh * NS;
+#pragma unroll
+                for (int i = 0; i < 5; ++i) {
+                    const double ei = phi[i] * E;
+#pragma unroll
+                    for (int j = i; j < 5; ++j) acc[k++] += ei * phi[j];
+                }
+#pragma unroll
+                for (int i = 0; i < 5; ++i) acc[k++] += phi[i] * sE;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NA; ++k) part[k][lane] = acc[k];
+    __syncthreads();
+    if (lane < NA) {
+        double s = 0.0;
+        for (int j = 0; j < 64; ++j) s += part[lane][j];
+        d.lsum[(size_t)cell * LSUM + lane] = s;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_params_list_finish(GSIS_SPAN_ARGS)
+{
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    const int cell = blk * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell || !d.cflag[cell]) return;   // a solid cell's parameters are zero already
+    CellState st;
+    cell_state(g, d, cell, st);
+    const double *sums = d.lsum + (size_t)cell * LSUM;
+    const int nsh = g.species != 0 ? 2 : 1;
+    ShapeSums E[2];
+    for (int sh = 0; sh < nsh; ++sh) {
+        int k = sh * LSUM_SHAPE;
+        for (int i = 0; i < 5; ++i)
+            for (int j = i; j < 5; ++j) E[sh].G[i * 5 + j] = E[sh].G[j * 5 + i] = sums[k++];
+        for (int i = 0; i < 5; ++i) E[sh].bS[i] = sums[k++];
+    }
+    cell_params(g, d, cell, st, E[0], E[nsh - 1]);
 }
 
 // Incoming density scale of every boundary face.  Diffuse wall: the outgoing
@@ -372,7 +401,10 @@ __global__ __launch_bounds__(256) void k_face_scale(GSIS_SPAN_ARGS)
 hipError_t launch_params(const Target &t, hipStream_t s)
 {
     if (t.vlist) {
-        hipLaunchKernelGGL(k_params_list, dim3(t.host[0].g.ncell), dim3(64), 0, s, GSIS_SPAN(t.span(K_CELL1)));
+        const dim3 grid(t.host[0].g.ncell);
+        if (t.dia) hipLaunchKernelGGL(k_params_list_sums<2>, grid, dim3(64), 0, s, GSIS_SPAN(t.span(K_CELL1)));
+        else hipLaunchKernelGGL(k_params_list_sums<1>, grid, dim3(64), 0, s, GSIS_SPAN(t.span(K_CELL1)));
+        hipLaunchKernelGGL(k_params_list_finish, dim3(t.nblk[K_CELL64]), dim3(64), 0, s, GSIS_SPAN(t.span(K_CELL64)));
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_params, dim3(t.nblk[K_CELL64]), dim3(64), 0, s, GSIS_SPAN(t.span(K_CELL64)));

@@ -161,6 +161,7 @@ void k_sweep(GSIS_SPAN_ARGS, int plane, int eoff)
     const int wx = w % WX, wy = w / WX;
     const int bs = GRID ? 64 : (int)blockDim.x;   // nodes per block, and threads of the meta loads
     const int ml = GRID ? lane : (int)threadIdx.x;
+    if (vb * bs >= g.osize[o]) return;            // a node run past the end of a smaller octant
     const int l = vb * bs + ml;
     const bool active = l < g.osize[o];           // inactive threads still join loads and barriers
     const int packed = ((cptr<int>)C.d.tiles)[plane_off + t];
