@@ -1107,9 +1107,16 @@ void orc_ref_components(const orc_cfg *c, double rho, const double u[3], double 
  *   mass rho u_n;  momentum rho u u_n + (p n + sigma.n)/2;
  *   energy (E + p) u_n + (sigma.n).u + q.n + qr.n;  Er: Er u_n + qr.n,  p = rho Tt.
  * Constitutive relations of Eq. (full_constitutive): sigma = sigma_NSF(W) +
- * HoT_sigma, q = q_NSF(W) + HoT_q, with the high-order terms evaluated once at
- * each face from the kinetic moments of f^{n+1/2}:
- *   HoT = (K_i + K_j)/2 - NSF_face(W^{n+1/2}).
+ * HoT_sigma, q = q_NSF(W) + HoT_q, the high-order terms frozen at each face
+ * at the kinetic state:  everything the NSF face flux misses is carried as
+ *   HoT_face = F_kin,face(f^{n+1/2}) - F_face(W^{n+1/2}),
+ * F_kin the kinetic scheme's own face flux of the moments (first-order
+ * upwind: sum over xi_n > 0 of w xi_n psi f of the left cell plus sum over
+ * xi_n < 0 of the right cell), F_face the macroscopic face flux below without
+ * HoT.  In the continuum limit this is the difference of the kinetic and NSF
+ * stress and heat flux of Eq. (full_constitutive); discretely it makes the
+ * macroscopic face flux at W^{n+1/2} the kinetic one, so a fixed point of the
+ * kinetic iteration is a fixed point of the macroscopic solve and of GSIS.
  * NSF laws of Eq. (NSF_constitutive), Eq. (mu_kappa) in these units:
  *   sigma_NSF = -(Tt^omega/delta) (grad u + grad u^T - (2/3) div u I),
  *   q_NSF = -(k_t Tt^omega/delta) grad Tt,  qr_NSF = -(k_r Tt^omega/delta) grad Tr,
@@ -1286,6 +1293,34 @@ static void kinetic_face_flux(const orc_state *s, int cell, int d, int bc, doubl
     for (int k = 0; k < 6; ++k) F[k] = nval(&acc[k]);
 }
 
+/* Kinetic flux across the interior face between fluid cells L and R = L + e_a,
+ * in the +a direction: sum over xi_a > 0 of w xi_a psi f_L plus sum over
+ * xi_a < 0 of w xi_a psi f_R, psi = (1, xi, |xi|^2 f0 + f1, f1) (first-order
+ * upwind interface values, as in the kinetic update). */
+static void kinetic_interior_flux(const orc_state *s, int L, int R, int a, double F[6])
+{
+    const double *f0L = s->f0 + (size_t)L * s->nv, *f0R = s->f0 + (size_t)R * s->nv;
+    const double *f1L = s->f1 ? s->f1 + (size_t)L * s->nv : NULL;
+    const double *f1R = s->f1 ? s->f1 + (size_t)R * s->nv : NULL;
+    nsum acc[6];
+    memset(acc, 0, sizeof acc);
+    for (int v = 0; v < s->nv; ++v) {
+        double xi[3], w;
+        node_xi(s, v, xi, &w);
+        double xn = xi[a];
+        if (xn == 0.0) continue;
+        double a0 = xn > 0 ? f0L[v] : f0R[v];
+        double a1 = s->f1 ? (xn > 0 ? f1L[v] : f1R[v]) : 0.0;
+        double x2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+        double ww = w * xn;
+        nadd(&acc[0], ww * a0);
+        for (int b = 0; b < 3; ++b) nadd(&acc[1 + b], ww * xi[b] * a0);
+        nadd(&acc[4], ww * (x2 * a0 + a1));
+        nadd(&acc[5], ww * a1);
+    }
+    for (int k = 0; k < 6; ++k) F[k] = nval(&acc[k]);
+}
+
 /* F_eq of a boundary face: the flux of the face when the cell holds the
  * Maxwellian of W (f1 = (dr/2) Tr M), with the same boundary rule. */
 static void equilibrium_face_flux(const orc_state *s, const prim_t *P, int d, int bc, double F[6])
@@ -1341,16 +1376,19 @@ static void equilibrium_face_flux(const orc_state *s, const prim_t *P, int d, in
     free(Mc);
 }
 
-/* The macroscopic solve from the kinetic moments K[cell] of f^{n+1/2} and
- * the kinetic boundary fluxes Fkin[cell][6][6] (out of the cell through each
- * boundary face; unused for euler), iters point-Jacobi iterations; returns
+/* The macroscopic solve from the kinetic moments K[cell] of f^{n+1/2}, the
+ * kinetic boundary fluxes Fkin[cell][6][6] (out of the cell through each
+ * boundary face) and the kinetic interior fluxes Fint[cell][3][6] (through
+ * the face to the +a neighbour, where that is a fluid cell) (both unused for
+ * euler), iters point-Jacobi iterations; returns
  * the primitive variables of W^{n+1} in Pn[cell] and keeps W^{n+1} in
  * s->lastW.  Sets s->status to -5 on a non-physical result.
  * euler = 1: the same iteration with the Euler constitutive relations (no
  * stress, heat flux or HoT, no diffusive part in Gamma and dtau) and the
  * boundary flux of the iterate's own Maxwellian, F_b(W^m) = F_eq(W^m): the
  * initial-field computation of Alg. 1, line 1. */
-static int macro_solve(orc_state *s, const moms *K, const double *Fkin, int iters, int euler, prim_t *P)
+static int macro_solve(orc_state *s, const moms *K, const double *Fkin, const double *Fint, int iters, int euler,
+                       prim_t *P)
 {
     const orc_cfg *c = &s->c;
     macpar mp;
@@ -1362,7 +1400,8 @@ static int macro_solve(orc_state *s, const moms *K, const double *Fkin, int iter
     if (s->h[2] < hmin) hmin = s->h[2];
     double *W = calloc((size_t)ncell * 6, sizeof(double));
     double *Fb = calloc((size_t)ncell * 36, sizeof(double));
-    double *hot = calloc((size_t)ncell * 15, sizeof(double));
+    double *fix = calloc((size_t)ncell * 18, sizeof(double));   /* HoT_face per (cell, +a face), 6 each */
+    static const double nohot[5] = {0, 0, 0, 0, 0};
     double *grad = calloc((size_t)ncell * 9, sizeof(double));
     double *R = calloc((size_t)ncell * 6, sizeof(double));
     double *Dc = calloc((size_t)ncell, sizeof(double));
@@ -1403,15 +1442,12 @@ static int macro_solve(orc_state *s, const moms *K, const double *Fkin, int iter
         for (int a = 0; a < 3; ++a) {
             int nb = neighbour(s, cell, 2 * a + 1);
             if (nb < 0) continue;
-            double sigN[3], qN, qrN;
-            nsf_face(&mp, &P[cell], &P[nb], grad + (size_t)cell * 9, grad + (size_t)nb * 9, a, s->h[a], sigN, &qN, &qrN);
-            /* sigma column a of the kinetic stress, order xx yy zz xy xz yz */
-            static const int col[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
-            double *ho = hot + (size_t)cell * 15 + a * 5;
-            for (int b = 0; b < 3; ++b)
-                ho[b] = 0.5 * (K[cell].sig[col[a][b]] + K[nb].sig[col[a][b]]) - sigN[b];
-            ho[3] = 0.5 * (K[cell].q[a] + K[nb].q[a]) - qN;
-            ho[4] = mp.dia ? 0.5 * (K[cell].qr[a] + K[nb].qr[a]) - qrN : 0.0;
+            double F[6], Gam;
+            face_flux(&mp, &P[cell], &P[nb], grad + (size_t)cell * 9, grad + (size_t)nb * 9, a, s->h[a], nohot, F, &Gam);
+            double *fx = fix + (size_t)cell * 18 + a * 6;
+            const double *fk = Fint + (size_t)cell * 18 + a * 6;
+            for (int k = 0; k < 6; ++k) fx[k] = fk[k] - F[k];
+            if (!mp.dia) fx[5] = 0.0;
         }
     }
     /* point-Jacobi iterations */
@@ -1432,9 +1468,9 @@ static int macro_solve(orc_state *s, const moms *K, const double *Fkin, int iter
                 double F[6], out[6], Gam;
                 if (n >= 0) {
                     int L = (d & 1) ? cell : n, Rr = (d & 1) ? n : cell;
-                    face_flux(&mp, &P[L], &P[Rr], grad + (size_t)L * 9, grad + (size_t)Rr * 9, a, h,
-                              hot + (size_t)L * 15 + a * 5, F, &Gam);
-                    for (int k = 0; k < 6; ++k) out[k] = (d & 1) ? F[k] : -F[k];
+                    face_flux(&mp, &P[L], &P[Rr], grad + (size_t)L * 9, grad + (size_t)Rr * 9, a, h, nohot, F, &Gam);
+                    const double *fx = fix + (size_t)L * 18 + a * 6;
+                    for (int k = 0; k < 6; ++k) out[k] = (d & 1) ? F[k] + fx[k] : -(F[k] + fx[k]);
                 } else {
                     double Fe[6];
                     equilibrium_face_flux(s, Pi, d, -1 - n, Fe);
@@ -1478,7 +1514,7 @@ static int macro_solve(orc_state *s, const moms *K, const double *Fkin, int iter
     if (bad) s->status = -5;
     if (!s->lastW) s->lastW = malloc(sizeof(double) * (size_t)ncell * 6);
     memcpy(s->lastW, W, sizeof(double) * (size_t)ncell * 6);
-    free(W); free(Fb); free(hot); free(grad); free(R); free(Dc); free(Src);
+    free(W); free(Fb); free(fix); free(grad); free(R); free(Dc); free(Src);
     return s->status;
 }
 
@@ -1493,6 +1529,7 @@ static int gsis_correct_mode(orc_state *s, int iters, int euler)
     int ncell = s->ncell, dia = c->species == 1;
     moms *K = calloc((size_t)ncell, sizeof(moms));
     double *Fkin = calloc((size_t)ncell * 36, sizeof(double));
+    double *Fint = calloc((size_t)ncell * 18, sizeof(double));
     prim_t *P = calloc((size_t)ncell, sizeof(prim_t));
     #pragma omp parallel for schedule(dynamic, 16)
     for (int cell = 0; cell < ncell; ++cell) {
@@ -1501,9 +1538,10 @@ static int gsis_correct_mode(orc_state *s, int iters, int euler)
         for (int d = 0; d < 6; ++d) {
             int n = neighbour(s, cell, d);
             if (n < 0 && !euler) kinetic_face_flux(s, cell, d, -1 - n, Fkin + (size_t)cell * 36 + d * 6);
+            if (n >= 0 && (d & 1) && !euler) kinetic_interior_flux(s, cell, n, d / 2, Fint + (size_t)cell * 18 + (d / 2) * 6);
         }
     }
-    macro_solve(s, K, Fkin, iters, euler, P);
+    macro_solve(s, K, Fkin, Fint, iters, euler, P);
     #pragma omp parallel for schedule(static)
     for (int cell = 0; cell < ncell; ++cell) {
         if (s->solid[cell]) continue;
@@ -1519,7 +1557,7 @@ static int gsis_correct_mode(orc_state *s, int iters, int euler)
             if (dia) s->f1[at] += 0.5 * c->dr * (Pn->Tr * Mn - m->Tr * Mo);
         }
     }
-    free(K); free(Fkin); free(P);
+    free(K); free(Fkin); free(Fint); free(P);
     return s->status;
 }
 
@@ -1620,6 +1658,7 @@ void orc_conductivities(const orc_cfg *c, double out[2])
  * stored-VDF path's arithmetic in another loop order (pinned to it on small
  * problems). */
 #define ST_NS 17   /* per-cell sums: 1, c (3), cc (xx yy zz xy xz yz), c|c|^2 (3); f1: 1, c (3) */
+#define ST_NH 36   /* per-cell half-range fluxes: 3 axes x 2 halves x psi (1, xi, |xi|^2 f0 + f1, f1) */
 
 typedef struct {
     orc_state *s;
@@ -1628,6 +1667,7 @@ typedef struct {
     int *cface;                /* [ncell][6] face index, or -1 for an interior face */
     double *ur;                /* [ncell][3] centre of the per-cell sums */
     nsum *acc;                 /* [ncell][ST_NS] */
+    nsum *half;                /* [ncell][3][2][6] per axis a: sum over xi_a > 0 (then xi_a < 0) of w xi_a psi f */
     nsum *fout;                /* [nface][6] */
     double in_mass[6][ORC_NBC];    /* sum_{xi_n < 0} w |xi_n| M(1, u_b, T_b) per face direction and slot */
     double in_flux[6][ORC_NBC][6]; /* sum_{xi_n < 0} w xi_n psi M(1, u_b, T_b) (f1 part: (dr/2) T_b M) */
@@ -1638,7 +1678,7 @@ void orc_stream_free(orc_stream *st)
     if (!st) return;
     orc_free(st->s);
     free(st->fcell); free(st->fdir); free(st->fbc); free(st->cface);
-    free(st->ur); free(st->acc); free(st->fout);
+    free(st->ur); free(st->acc); free(st->half); free(st->fout);
     free(st);
 }
 
@@ -1672,6 +1712,7 @@ orc_stream *orc_stream_create(const orc_cfg *cfg, const unsigned char *solid)
         }
     st->ur = calloc((size_t)ncell * 3, sizeof(double));
     st->acc = calloc((size_t)ncell * ST_NS, sizeof(nsum));
+    st->half = calloc((size_t)ncell * ST_NH, sizeof(nsum));
     st->fout = calloc((size_t)(nf + 1) * 6, sizeof(nsum));
     /* the incoming halves of the boundary Maxwellians, once per direction and slot */
     for (int d = 0; d < 6; ++d)
@@ -1702,8 +1743,9 @@ orc_stream *orc_stream_create(const orc_cfg *cfg, const unsigned char *solid)
 }
 
 /* Adds the contribution of value f0 (f1) at node xi, weight w, to the sums of
- * one cell (centre ur) and of its outgoing boundary faces. */
-static void stream_add(const orc_stream *st, nsum *A, nsum *F, const int *cf, const double ur[3],
+ * one cell (centre ur), its half-range fluxes H and its outgoing boundary
+ * faces. */
+static void stream_add(const orc_stream *st, nsum *A, nsum *H, nsum *F, const int *cf, const double ur[3],
                        const double xi[3], double w, double f0, double f1, int dia)
 {
     double cp[3] = {xi[0] - ur[0], xi[1] - ur[1], xi[2] - ur[2]};
@@ -1724,6 +1766,16 @@ static void stream_add(const orc_stream *st, nsum *A, nsum *F, const int *cf, co
         for (int a = 0; a < 3; ++a) nadd(&A[14 + a], w1 * cp[a]);
     }
     double x2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+    for (int a = 0; a < 3; ++a) {
+        if (xi[a] == 0.0) continue;
+        nsum *h = H + a * 12 + (xi[a] > 0 ? 0 : 6);
+        double ww = w * xi[a];
+        double g1 = dia ? f1 : 0.0;
+        nadd(&h[0], ww * f0);
+        for (int k = 0; k < 3; ++k) nadd(&h[1 + k], ww * xi[k] * f0);
+        nadd(&h[4], ww * (x2 * f0 + g1));
+        nadd(&h[5], ww * g1);
+    }
     for (int d = 0; d < 6; ++d) {
         int f = cf[d];
         if (f < 0) continue;
@@ -1793,8 +1845,9 @@ void orc_stream_init_maxwellian(orc_stream *st, double rho, const double u[3], d
 {
     orc_state *s = st->s;
     int dia = s->c.species == 1;
-    nsum A[ST_NS], F[6 * 6];
+    nsum A[ST_NS], H[ST_NH], F[6 * 6];
     memset(A, 0, sizeof A);
+    memset(H, 0, sizeof H);
     memset(F, 0, sizeof F);
     int cf[6] = {0, 1, 2, 3, 4, 5};   /* all six directions, one sum each */
     for (int v = 0; v < s->nv; ++v) {
@@ -1802,14 +1855,19 @@ void orc_stream_init_maxwellian(orc_stream *st, double rho, const double u[3], d
         node_xi(s, v, xi, &w);
         double f0 = maxwellian(rho, u, T, xi);
         double f1 = dia ? 0.5 * s->c.dr * Tr * f0 : 0.0;
-        stream_add(st, A, F, cf, u, xi, w, f0, f1, dia);
+        stream_add(st, A, H, F, cf, u, xi, w, f0, f1, dia);
     }
     memset(st->fout, 0, sizeof(nsum) * (size_t)(st->nface + 1) * 6);
     for (int cell = 0; cell < s->ncell; ++cell) {
         for (int a = 0; a < 3; ++a) st->ur[cell * 3 + a] = u[a];
-        nsum *dst = st->acc + (size_t)cell * ST_NS;
-        if (s->solid[cell]) { memset(dst, 0, sizeof(nsum) * ST_NS); continue; }
+        nsum *dst = st->acc + (size_t)cell * ST_NS, *hd = st->half + (size_t)cell * ST_NH;
+        if (s->solid[cell]) {
+            memset(dst, 0, sizeof(nsum) * ST_NS);
+            memset(hd, 0, sizeof(nsum) * ST_NH);
+            continue;
+        }
         memcpy(dst, A, sizeof A);
+        memcpy(hd, H, sizeof H);
     }
     for (int f = 0; f < st->nface; ++f) memcpy(st->fout + (size_t)f * 6, F + (size_t)st->fdir[f] * 6, 6 * sizeof(nsum));
     s->status = 0;
@@ -1846,12 +1904,14 @@ int orc_stream_step(orc_stream *st, int npasses)
             for (int a = 0; a < 3; ++a) st->ur[cell * 3 + a] = P[cell].m.u[a];
         }
         memset(st->acc, 0, sizeof(nsum) * (size_t)ncell * ST_NS);
+        memset(st->half, 0, sizeof(nsum) * (size_t)ncell * ST_NH);
         memset(st->fout, 0, sizeof(nsum) * (size_t)(nf + 1) * 6);
         #pragma omp parallel
         {
             double *col0 = calloc((size_t)ncell, sizeof(double));
             double *col1 = calloc((size_t)ncell, sizeof(double));
             nsum *A = calloc((size_t)ncell * ST_NS, sizeof(nsum));
+            nsum *Hh = calloc((size_t)ncell * ST_NH, sizeof(nsum));
             nsum *F = calloc((size_t)(nf + 1) * 6, sizeof(nsum));
             /* f^n enters the update only times 1/dt = 0: the columns keep the
              * previous node's (finite) values, or zeros */
@@ -1862,8 +1922,8 @@ int orc_stream_step(orc_stream *st, int npasses)
                 sweep_node(s, v, P, scale, nb, col0, col1);
                 for (int cell = 0; cell < ncell; ++cell) {
                     if (s->solid[cell]) continue;
-                    stream_add(st, A + (size_t)cell * ST_NS, F, st->cface + (size_t)cell * 6, st->ur + (size_t)cell * 3,
-                               xi, w, col0[cell], col1[cell], dia);
+                    stream_add(st, A + (size_t)cell * ST_NS, Hh + (size_t)cell * ST_NH, F, st->cface + (size_t)cell * 6,
+                               st->ur + (size_t)cell * 3, xi, w, col0[cell], col1[cell], dia);
                 }
             }
             /* combine the threads' sums in thread order */
@@ -1872,10 +1932,11 @@ int orc_stream_step(orc_stream *st, int npasses)
                 #pragma omp ordered
                 {
                     for (size_t k = 0; k < (size_t)ncell * ST_NS; ++k) { nadd(&st->acc[k], A[k].s); nadd(&st->acc[k], A[k].c); }
+                    for (size_t k = 0; k < (size_t)ncell * ST_NH; ++k) { nadd(&st->half[k], Hh[k].s); nadd(&st->half[k], Hh[k].c); }
                     for (size_t k = 0; k < (size_t)nf * 6; ++k) { nadd(&st->fout[k], F[k].s); nadd(&st->fout[k], F[k].c); }
                 }
             }
-            free(col0); free(col1); free(A); free(F);
+            free(col0); free(col1); free(A); free(Hh); free(F);
         }
     }
     free(P); free(scale); free(nb);
@@ -1893,10 +1954,19 @@ int orc_stream_gsis_correct(orc_stream *st, int iters)
     int ncell = s->ncell, dia = c->species == 1;
     moms *K = calloc((size_t)ncell, sizeof(moms));
     double *Fkin = calloc((size_t)ncell * 36, sizeof(double));
+    double *Fint = calloc((size_t)ncell * 18, sizeof(double));
     prim_t *P = calloc((size_t)ncell, sizeof(prim_t));
     for (int cell = 0; cell < ncell; ++cell) {
         if (s->solid[cell]) continue;
         stream_moments(st, cell, &K[cell]);
+        for (int a = 0; a < 3; ++a) {
+            /* interior face to the +a neighbour: this cell's xi_a > 0 half plus
+             * the neighbour's xi_a < 0 half */
+            int n = neighbour(s, cell, 2 * a + 1);
+            if (n < 0) continue;
+            const nsum *hp = st->half + (size_t)cell * ST_NH + a * 12, *hm = st->half + (size_t)n * ST_NH + a * 12 + 6;
+            for (int k = 0; k < 6; ++k) Fint[(size_t)cell * 18 + a * 6 + k] = nval(&hp[k]) + nval(&hm[k]);
+        }
         for (int d = 0; d < 6; ++d) {
             int f = st->cface[cell * 6 + d];
             if (f < 0) continue;
@@ -1908,7 +1978,7 @@ int orc_stream_gsis_correct(orc_stream *st, int iters)
             if (!dia) F[5] = 0.0;
         }
     }
-    macro_solve(s, K, Fkin, iters, 0, P);
+    macro_solve(s, K, Fkin, Fint, iters, 0, P);
     #pragma omp parallel for schedule(dynamic, 16)
     for (int cell = 0; cell < ncell; ++cell) {
         if (s->solid[cell]) continue;
@@ -1923,10 +1993,11 @@ int orc_stream_gsis_correct(orc_stream *st, int iters)
             double Mo = maxwellian_pre(m->rho, po, m->u, m->Tt, xi);
             double d0 = Mn - Mo;
             double d1 = dia ? 0.5 * c->dr * (Pn->Tr * Mn - m->Tr * Mo) : 0.0;
-            stream_add(st, A, st->fout, st->cface + (size_t)cell * 6, st->ur + (size_t)cell * 3, xi, w, d0, d1, dia);
+            stream_add(st, A, st->half + (size_t)cell * ST_NH, st->fout, st->cface + (size_t)cell * 6,
+                       st->ur + (size_t)cell * 3, xi, w, d0, d1, dia);
         }
     }
-    free(K); free(Fkin); free(P);
+    free(K); free(Fkin); free(Fint); free(P);
     return s->status;
 }
 
