@@ -103,9 +103,10 @@ struct Dev {
     double *corr;      // [ncell][NCORR]
     double *snap;      // [ncell][NSNAP]
     // macroscopic solve, all structures of arrays [field][ncell] ([field][nface]
-    // for fbfix, Fb): W (double buffered), prims P, velocity gradient, kinetic
-    // stress/heat flux K, HoT of the three + faces, residual R
-    double *W, *W2, *P, *grad, *K, *hot, *R, *Dc, *Src, *fbfix, *Fb, *Gb;
+    // for fbfix, Fb): W (double buffered), prims P, velocity gradient,
+    // high-order terms of the three + faces (six flux components each),
+    // residual R
+    double *W, *W2, *P, *grad, *hot, *R, *Dc, *Src, *fbfix, *Fb, *Gb;
     double *red;       // reduction scratch
     unsigned long long *dmax;   // [2][DSLOT] partial maxima, one per 128-byte line (DSTRIDE words apart),
                                 // bit patterns of positive doubles

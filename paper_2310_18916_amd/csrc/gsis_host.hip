@@ -314,8 +314,7 @@ size_t layout(gsis_ctx *c, char *base)
     carve(off, d.W2, n * 6, base);
     carve(off, d.P, n * 12, base);
     carve(off, d.grad, n * 9, base);
-    carve(off, d.K, n * 12, base);
-    carve(off, d.hot, n * 15, base);
+    carve(off, d.hot, n * 18, base);
     carve(off, d.R, n * 6, base);
     carve(off, d.Dc, n, base);
     carve(off, d.Src, n, base);

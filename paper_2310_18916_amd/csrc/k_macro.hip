@@ -92,9 +92,11 @@ __device__ __forceinline__ void side(const PV &P, int a, double Phi[6], double W
     Wv[5] = P[7];
 }
 
-template <class PV, class GV, class HV>
+// Macroscopic flux (Rusanov + NSF, no high-order terms) across the face from
+// L to R = L + e_a.
+template <class PV, class GV>
 __device__ __forceinline__ void face_flux(const Geo &g, const PV &L, const PV &R, const GV &gL, const GV &gR, int a,
-                                          double ih, const HV &hot, bool euler, double F[6], double *Gam)
+                                          double ih, bool euler, double F[6], double *Gam)
 {
     const double TF = 0.5 * (L[4] + R[4]), rF = 0.5 * (L[0] + R[0]);
     // Euler constitutive relations: no stress or heat flux, no diffusive part in Gamma
@@ -108,14 +110,13 @@ __device__ __forceinline__ void face_flux(const Geo &g, const PV &L, const PV &R
     double smax = sL > sR ? sL : sR;
 #pragma unroll
     for (int k = 0; k < 6; ++k) F[k] = 0.5 * (PhiL[k] + PhiR[k]) - 0.5 * smax * (WR[k] - WL[k]);
-    double sn[3], uF[3];
+    double uF[3];
 #pragma unroll
-    for (int b = 0; b < 3; ++b) { sn[b] = sigN[b] + hot[b]; uF[b] = 0.5 * (L[1 + b] + R[1 + b]); }
-    double qn = qN + hot[3];
-    double qrn = g.species == 1 ? qrN + hot[4] : 0.0;
+    for (int b = 0; b < 3; ++b) uF[b] = 0.5 * (L[1 + b] + R[1 + b]);
+    const double qrn = g.species == 1 ? qrN : 0.0;
 #pragma unroll
-    for (int b = 0; b < 3; ++b) F[1 + b] += 0.5 * sn[b];
-    F[4] += sn[0] * uF[0] + sn[1] * uF[1] + sn[2] * uF[2] + qn + qrn;
+    for (int b = 0; b < 3; ++b) F[1 + b] += 0.5 * sigN[b];
+    F[4] += sigN[0] * uF[0] + sigN[1] * uF[1] + sigN[2] * uF[2] + qN + qrn;
     F[5] += qrn;
     *Gam = euler ? smax : smax + g.Cd * mu * ih / rF;
 }
@@ -236,7 +237,7 @@ __device__ __forceinline__ double boundary_gamma(const Geo &g, const PV &P, int 
     return fabs(P[1 + a]) + P[8] + (euler ? 0.0 : g.Cd * P[9] / (P[0] * g.h[a]));
 }
 
-// W^{n+1/2}, kinetic stress/heat flux, the old half of the correction record.
+// W^{n+1/2} and the old half of the correction record.
 __global__ __launch_bounds__(128) void k_mac_init(GSIS_SPAN_ARGS)
 {
     int blk;
@@ -257,10 +258,6 @@ __global__ __launch_bounds__(128) void k_mac_init(GSIS_SPAN_ARGS)
     W[5] = Er;
     const Soa<double> Wd = soa(d.W, n, cell);
     for (int k = 0; k < 6; ++k) Wd[k] = W[k];
-    const Soa<double> K = soa(d.K, n, cell);
-    for (int k = 0; k < 6; ++k) K[k] = m[5 + k];
-    for (int k = 0; k < 3; ++k) K[6 + k] = m[11 + k];
-    for (int k = 0; k < 3; ++k) K[9 + k] = g.species == 1 ? m[15 + k] : 0.0;
     const gptr<double> c = G(d.corr) + (size_t)cell * NCORR;
     c[6] = rho; c[7] = m[1]; c[8] = m[2]; c[9] = m[3]; c[10] = Tt;
     c[11] = g.species == 1 ? m[14] : Tt;
@@ -311,7 +308,12 @@ __global__ __launch_bounds__(256) void k_mac_grad(GSIS_SPAN_ARGS, int with_faces
     if (sub == 7) G(d.Gb)[f] = boundary_gamma(g, P, dir / 2, euler);
 }
 
-// HoT at the faces (cell, cell + e_a) from W^{n+1/2}.
+// High-order terms at the faces (cell, cell + e_a), frozen at the kinetic
+// state: the kinetic scheme's face flux of the moments of f^{n+1/2} (first-order
+// upwind: the xi_a > 0 octant sums of the cell plus the xi_a < 0 octant sums of
+// the neighbour) minus the macroscopic face flux at W^{n+1/2}, six values per
+// face; the face flux of an iterate is its macroscopic flux plus these.  Zero
+// for the Euler relations.
 __global__ __launch_bounds__(128) void k_mac_hot(GSIS_SPAN_ARGS, int euler)
 {
     int blk;
@@ -320,27 +322,29 @@ __global__ __launch_bounds__(128) void k_mac_hot(GSIS_SPAN_ARGS, int euler)
     const Dev &d = C.d;
     int cell = blk * blockDim.x + threadIdx.x;
     if (cell >= g.ncell || !G(d.cflag)[cell]) return;
-    const int col[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
     const size_t n = g.ncell;
-    if (euler) {                                  // Euler constitutive relations: no HoT
-        for (int k = 0; k < 15; ++k) soa(d.hot, n, cell)[k] = 0.0;
-        return;
-    }
+    const int m2row[3][3] = {{4, 7, 8}, {7, 5, 9}, {8, 9, 6}};
     for (int a = 0; a < 3; ++a) {
-        int nb = G(d.nbr)[(size_t)(2 * a + 1) * g.ncell + cell];
-        const Soa<double> ho = soa(d.hot + (size_t)a * 5 * n, n, cell);
-        if (nb < 0) {
-            for (int k = 0; k < 5; ++k) ho[k] = 0.0;
+        const Soa<double> fx = soa(d.hot + (size_t)a * 6 * n, n, cell);
+        const int nb = G(d.nbr)[(size_t)(2 * a + 1) * g.ncell + cell];
+        if (euler || nb < 0) {
+            for (int k = 0; k < 6; ++k) fx[k] = 0.0;
             continue;
         }
-        double sigN[3], qN, qrN;
+        double Fk[6] = {0, 0, 0, 0, 0, 0};
+        for (int o = 0; o < 8; ++o) {
+            const int up = ((o >> a) & 1) ? nb : cell;   // xi_a < 0: the neighbour's value enters the face
+            const gptr<const double> m = G((const double *)d.mom8) + ((size_t)up * 8 + o) * NRS;
+            Fk[0] += m[1 + a];
+            for (int b = 0; b < 3; ++b) Fk[1 + b] += m[m2row[a][b]];
+            Fk[4] += m[10 + a] + m[14 + a];
+            Fk[5] += m[14 + a];
+        }
         const Soa<double> PL = soa(d.P, n, cell), PR = soa(d.P, n, nb);
-        nsf_face(g, PL, PR, soa(d.grad, n, cell), soa(d.grad, n, nb), a, g.invh[a],
-                 pow_pos(0.5 * (PL[4] + PR[4]), g.omega) / g.delta, sigN, &qN, &qrN);
-        const Soa<double> Ki = soa(d.K, n, cell), Kj = soa(d.K, n, nb);
-        for (int b = 0; b < 3; ++b) ho[b] = 0.5 * (Ki[col[a][b]] + Kj[col[a][b]]) - sigN[b];
-        ho[3] = 0.5 * (Ki[6 + a] + Kj[6 + a]) - qN;
-        ho[4] = g.species == 1 ? 0.5 * (Ki[9 + a] + Kj[9 + a]) - qrN : 0.0;
+        double F[6], Gam;
+        face_flux(g, PL, PR, soa(d.grad, n, cell), soa(d.grad, n, nb), a, g.invh[a], false, F, &Gam);
+        for (int k = 0; k < 6; ++k) fx[k] = Fk[k] - F[k];
+        if (g.species != 1) fx[5] = 0.0;
     }
 }
 
@@ -414,7 +418,7 @@ __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, 
     // only what the face flux reads: no Tr, Er, qr for the monatomic gas and no
     // normal gradient column (the normal derivative is the two-cell difference)
     constexpr bool DIA = NW == 6;
-    double PL[NP], PR[NP], GL[9], GR[9], HO[5];
+    double PL[NP], PR[NP], GL[9], GR[9], HO[6];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const bool use = DIA || (k != 5 && k != 7);
@@ -425,7 +429,7 @@ __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, 
         GR[k] = tan ? G(d.grad)[(size_t)k * nc + R] : 0.0;
     }
 #pragma unroll
-    for (int k = 0; k < 5; ++k) HO[k] = (DIA || k < 4) ? G(d.hot)[(size_t)(a * 5 + k) * nc + L] : 0.0;
+    for (int k = 0; k < 6; ++k) HO[k] = (DIA || k < 5) ? G(d.hot)[(size_t)(a * 6 + k) * nc + L] : 0.0;
     if (KEEP) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) own[k] = (DIR & 1) ? PL[k] : PR[k];
@@ -435,9 +439,9 @@ __device__ __forceinline__ void face_term(const Geo &g, const Dev &d, int cell, 
     const int n = G(d.nbr)[(size_t)DIR * g.ncell + cell];
     if (n >= 0) {
         double F[6], Gam;
-        face_flux(g, PL, PR, GL, GR, a, ih, HO, EULER, F, &Gam);
+        face_flux(g, PL, PR, GL, GR, a, ih, EULER, F, &Gam);
 #pragma unroll
-        for (int k = 0; k < NW; ++k) out[k] = ((DIR & 1) ? F[k] : -F[k]) * ih;
+        for (int k = 0; k < NW; ++k) out[k] = ((DIR & 1) ? F[k] + HO[k] : -(F[k] + HO[k])) * ih;
         gam = Gam * ih;
     } else {
         const int f = -n - 1;

@@ -57,7 +57,7 @@ def groups(nm):
 
 
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
-@pytest.mark.parametrize("workload", ["c2", "c4"])
+@pytest.mark.parametrize("workload", ["c2", "c3", "c4"])
 def test_full_size_matches_streaming_oracle(workload, dtype):
     path = os.path.join(GOLDEN, f"fullsize_{workload}.npz")
     gold = np.load(path, allow_pickle=False)
