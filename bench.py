@@ -237,8 +237,18 @@ def batched(iters):
         b.close()
         del b
         torch.cuda.empty_cache()
-    diffs = [field_diff(a, c) for a, c in zip(res["fp32"]["moments"], res["fp64"]["moments"])]
+    # a closed box's steady states form a family along its total mass, which the
+    # kinetic passes do not conserve on the way: the two precisions reach members
+    # a path-dependent mass apart, so the fields are compared with the density
+    # divided by its mean, and that mass offset is reported beside them
+    def normalised(m):
+        m = m.copy()
+        m[:, 0] /= m[:, 0].mean()
+        return m
+    diffs = [field_diff(normalised(a), normalised(c)) for a, c in zip(res["fp32"]["moments"], res["fp64"]["moments"])]
     worst = {k: max(d[k] for d in diffs) for k in ("rho", "T", "u")}
+    mass_offset = max(abs(a[:, 0].mean() / c[:, 0].mean() - 1.0)
+                      for a, c in zip(res["fp32"]["moments"], res["fp64"]["moments"]))
     # plain path: every cavity alone, FP64, direct launches; per-iteration time measured
     # over 2 iterations after one warm iteration, scaled to the batch's iteration count
     plain = 0.0
@@ -261,6 +271,7 @@ def batched(iters):
         res[k].pop("moments")
     out.update({"fp32": res["fp32"], "fp64": res["fp64"],
                 "fp32_vs_fp64_batch_max_rel_diff": worst,
+                "fp32_vs_fp64_total_mass_offset": mass_offset,
                 "plain_fp64_single_ms_per_iteration": plain * 1e3,
                 "speedup_fp32_batch_vs_plain_fp64": plain / (res["fp32"]["seconds"] / iters),
                 "speedup_fp64_batch_vs_plain_fp64": plain / (res["fp64"]["seconds"] / iters)})

@@ -93,8 +93,10 @@ typedef struct {
                                   implicit increments stay first-order upwind either way.
                                   Order 2 adds two VDF-sized buffers (four diatomic) to the
                                   workspace and is not accepted by gsis_batch_create */
-    double limiter_k;          /* order 2: Venkatakrishnan constant K, eps^2 = (K h)^3 with h
-                                  the cube root of the cell volume; K < 0: no limiter */
+    double limiter_k;          /* order 2: Venkatakrishnan constant K, eps^2 = (K h)^3 S^2 with
+                                  h the cube root of the cell volume and S the largest |f| of
+                                  the point's stencil (the cell and its fluid neighbours);
+                                  K < 0: no limiter */
 } gsis_config;
 
 /* Create a context for cfg.  Validates sizes (n >= 1, nv >= 2, vmax > vmin,

@@ -71,7 +71,8 @@ typedef struct {
     const double *nodes[3];
     /* spatial order of the explicit interface values of the kinetic update:
      * 1 first-order upwind, 2 second-order reconstruction (Sec. 3.2); and
-     * the Venkatakrishnan constant K (eps^2 = (K h)^3; K < 0: no limiter) */
+     * the Venkatakrishnan constant K (eps^2 = (K h)^3 times the square of the
+     * local largest |f|; K < 0: no limiter) */
     int order;
     double limiter_k;
     /* optional general velocity set (Sec. 3.1: a locally refined or
@@ -623,8 +624,11 @@ static void sweep_node(const orc_state *s, int v, const cellpar *P, const double
  *    faces of psi(D, d2), with d2 = grad f_i . (x_ij - x_i) and D the largest
  *    (d2 > 0) or smallest (d2 < 0) of f_j - f_i over the cell and its fluid
  *    neighbours, psi = (D^2 + e2 + 2 D d2) / (D^2 + 2 d2^2 + D d2 + e2) and
- *    psi = 1 for d2 = 0; e2 = (K h)^3 with h the cube root of the cell volume
- *    and K = limiter_k; K < 0 leaves the reconstruction unlimited (phi = 1). */
+ *    psi = 1 for d2 = 0; e2 = (K h)^3 S^2 with h the cube root of the cell
+ *    volume, K = limiter_k and S the largest |f| over the cell and its fluid
+ *    neighbours (the threshold relative to the local size of f, which spans
+ *    decades across velocity space); K < 0 leaves the reconstruction
+ *    unlimited (phi = 1). */
 static void lsq_gradient(const orc_state *s, const int *nb, const double *col, int cell, double g[3])
 {
     double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, b[3] = {0, 0, 0};
@@ -666,6 +670,8 @@ static double limiter(const orc_state *s, const int *nb, const double *col, int 
         if (col[n] > fmax) fmax = col[n];
         if (col[n] < fmin) fmin = col[n];
     }
+    double S = fabs(fmax) > fabs(fmin) ? fabs(fmax) : fabs(fmin);
+    e2 *= S * S;
     double phi = 1.0;
     for (int d = 0; d < 6; ++d) {
         if (nb[cell * 6 + d] < 0) continue;

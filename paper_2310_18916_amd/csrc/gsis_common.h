@@ -40,8 +40,9 @@ struct Geo {
     double delta, omega, dr, Zr, A[4];
     double inv_dt;
     // explicit interface values of the kinetic update: order 1 (upwind) or 2
-    // (limited least-squares reconstruction); Venkatakrishnan eps^2 and
-    // whether the limiter is on
+    // (limited least-squares reconstruction); (K h)^3 of the Venkatakrishnan
+    // threshold (times the square of the stencil's largest |f| at each point)
+    // and whether the limiter is on
     int order, limited;
     double venk_e2;
     double rs_scale;   // factor of the sweep's per-point term: inv_dt (order 1) or 1 (order 2)

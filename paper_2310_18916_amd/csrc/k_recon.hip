@@ -101,7 +101,8 @@ __device__ __forceinline__ AroundXY around_xy(const Geo &g, const gptr<const int
 }
 
 // Venkatakrishnan phi of one point from the cell value and its six
-// neighbours (value, and whether it is a fluid cell), x-, x+, y-, y+, z-, z+.
+// neighbours (value, and whether it is a fluid cell), x-, x+, y-, y+, z-, z+;
+// e2 = (K h)^3, multiplied here by the square of the stencil's largest |f|.
 template <typename T>
 __device__ __forceinline__ T point_limiter(const Geo &g, T fc, const T *fv, const bool *has, T e2)
 {
@@ -111,6 +112,9 @@ __device__ __forceinline__ T point_limiter(const Geo &g, T fc, const T *fv, cons
     T mx = fc, mn = fc;
 #pragma unroll
     for (int dir = 0; dir < 6; ++dir) { mx = fmax(mx, fn[dir]); mn = fmin(mn, fn[dir]); }
+    // the threshold relative to the local size of f: (K h)^3 S^2, S the largest |f| of the stencil
+    const T S = fmax(fabs(mx), fabs(mn));
+    e2 *= S * S;
     T phi = T(1);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {

@@ -69,10 +69,12 @@ class Case:
     macro_cfl: float = 10.0
     # spatial order of the explicit interface values of the kinetic update
     # (1 first-order upwind; 2 least-squares reconstruction with the
-    # Venkatakrishnan limiter, eps^2 = (limiter_k h)^3, limiter_k < 0: none).
-    # K = 1 suits smooth flows (the cavity); the strict limiter K = 0 (no new
-    # extrema) is needed by the Mach-5 block flows, which lose positivity in
-    # the distribution's tails with K > 0 since eps is an absolute threshold
+    # Venkatakrishnan limiter, eps^2 = (limiter_k h)^3 times the square of
+    # the stencil's largest |f|, limiter_k < 0: none).  K = 0.3 to 1 suits the
+    # cavities; the strict K = 0 switches at smooth extrema (FP32 and FP64
+    # then part by 1e-4); the Mach-5 block flows lose positivity in the wake
+    # at second order beyond the smallest grids whatever K, so they run first
+    # order
     order: int = 1
     limiter_k: float = 1.0
     bcs: List[Boundary] = dataclasses.field(default_factory=lambda: [Boundary() for _ in range(7)])

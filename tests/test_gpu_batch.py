@@ -132,28 +132,40 @@ def test_batch_autotune_keeps_the_pass():
     a.close()
 
 
-def test_c5_batch_runs_and_matches_oracle_on_sampled_cases():
-    """The 64-cavity workload (FP32, graph, autotuned tiles): every case stays
-    finite with shrinking residuals; the three smallest cases match the oracle."""
-    say("[c5 full]")
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_c5_batch_matches_oracle_on_every_case(dtype):
+    """The 64-cavity workload as one batch (graph, autotuned tile): every case
+    after the autotuner's pass and three GSIS iterations against the oracle's
+    fields of the same plan (tests/golden/make_c5.py), on a sample of cells
+    per case, normalised by the case's largest |value| (sigma, q: or 1, the
+    dimensionless reference, if larger).  FP64: 1e-12 on rho, u, T and 1e-10
+    on sigma, q; FP32: 1e-5 and 1e-4; the residual of the last iteration."""
+    import os
+    say(f"[c5 vs oracle] {dtype}")
+    gold = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_oracle.npz"))
     cases = I.c5()
-    b = Batch(cases, "fp32")
+    assert int(gold["ncase"]) == len(cases)
+    b = Batch(cases, dtype)
     b.init_maxwellian()
     b.autotune(reps=1)
-    b.run(4, 300, graph=True)
-    eps = b.residuals()
-    assert np.all(np.isfinite(eps))
-    say(f"  eps first {eps[0].max(axis=0)} last {eps[-1].max(axis=0)}")
-    assert np.all(eps[-1, :, 0] < eps[0, :, 0])
-    sizes = [c.ncell * c.nvel for c in cases]
-    for i in np.argsort(sizes)[:3]:
-        o = Oracle(cases[i])
-        o.init_maxwellian()
-        o.step(1)                       # the autotuner's pass
-        for _ in range(4):
-            o.step(1)
-            assert o.gsis_correct(300) == 0
-        e = field_errors(b[int(i)].moments(), o.moments())
-        say(f"  case {i} (n={cases[i].nx}, m={cases[i].nv[0]}, Kn={cases[i].Kn:.4g}) errors {e}")
-        assert max(e.values()) <= 1e-5, (i, e)
+    b.run(int(gold["gsis_iters"]), int(gold["macro_iters"]), graph=True)
+    eps = b.residuals()[-1]
+    main, high = (1e-12, 1e-10) if dtype == "fp64" else (1e-5, 1e-4)
+    worst = {"main": 0.0, "high": 0.0, "eps": 0.0}
+    for ci in range(len(cases)):
+        cells = gold["cells"][ci]
+        ok = cells >= 0
+        m = b[ci].moments()[cells[ok]]
+        mo = gold["moments"][ci][ok]
+        fmax = gold["field_max"][ci]
+        for cols, kind in (([0], "main"), ([1, 2, 3], "main"), ([4], "main"), (list(range(5, 11)), "high"),
+                           ([11, 12, 13], "high")):
+            scale = fmax[cols].max() if kind == "main" else max(fmax[cols].max(), 1.0)
+            e = float(np.abs(m[:, cols] - mo[:, cols]).max() / scale)
+            worst[kind] = max(worst[kind], e)
+            assert e <= (main if kind == "main" else high), (ci, cols, e)
+        ee = float(np.abs(eps[ci] - gold["eps"][ci]).max() / np.abs(gold["eps"][ci]).max())
+        worst["eps"] = max(worst["eps"], ee)
+        assert ee <= (1e-8 if dtype == "fp64" else 1e-2), (ci, eps[ci], gold["eps"][ci])
+    say(f"  worst over 64 cases {worst}")
     b.close()

@@ -6,7 +6,7 @@ The GPU sweep solves the first-order system in direct form with the change
 of divergence on its right-hand side; the oracle solves the paper's delta
 form for the increment.  One pass from a seeded random VDF on a cavity of
 non-cubic cells, a masked block flow, the diatomic gas, the limiter off and
-strict (K = 0, as the block flows need), a finite pseudo-time step, a
+strict (K = 0), a finite pseudo-time step, a
 stretched velocity grid and a one-cell slab, the low-Mach cavities also with
 K = 1 (FP64 1e-12,
 FP32 1e-5 relative to the largest value); GSIS iterations (FP64 1e-12); c1

@@ -151,6 +151,33 @@ def test_strict_limiter_bounds_face_values():
     assert overshoots > 100
 
 
+def test_limiter_threshold_scales_with_the_distribution():
+    """The threshold is (K h)^3 times the square of the stencil's largest |f|:
+    multiplying f by 10^6 or 10^-6 multiplies every face value by the same
+    factor (the limiter sees the shape of f, not its size: f spans decades
+    across velocity space), and at K = 1 the limiter is active (the face
+    values differ from the unlimited ones)."""
+    case = dataclasses.replace(I.small_block(m=6), order=2, limiter_k=1.0)
+    f0, _ = I.random_vdf(case, seed=12)
+    fluid = ~case.solid_mask().astype(bool)
+    base = Oracle(case)
+    base.set_vdf(f0)
+    free = Oracle(dataclasses.replace(case, limiter_k=-1.0))
+    free.set_vdf(f0)
+    limited = 0
+    for scale in (1e6, 1e-6):
+        o = Oracle(case)
+        o.set_vdf(f0 * scale)
+        for v in range(0, case.nvel, 7):
+            fb = base.face_values(v, 0, 2)[fluid]
+            fs = o.face_values(v, 0, 2)[fluid] / scale
+            assert np.abs(fs - fb).max() <= 1e-13 * np.abs(fb).max(), (scale, v)
+            if scale > 1:
+                fu = free.face_values(v, 0, 2)[fluid]
+                limited += int(np.sum(np.abs(fu - fb) > 1e-6 * np.abs(fb).max()))
+    assert limited > 100
+
+
 @pytest.mark.parametrize("k", [1.0, -1.0])
 def test_reconstruction_adds_no_net_flux(k):
     """Summed over all fluid cells the second-order divergence equals the
