@@ -6,9 +6,10 @@
 // octant-grouped layout) give the four sums sum_x w_x xi_x^p f (p = 0..3),
 // which fold with the row's y/z weights into the 13 (+4 for f1) monomials.
 // One block per cell, one wave per octant, so per-octant sums -- from which
-// every half-range wall flux follows -- need only a wave reduction.  Lanes
-// lie along the rows (each keeps its columns and their x-weights), so every
-// load instruction reads one contiguous stretch of the VDF.
+// every half-range wall flux follows -- need only a wave reduction.  Every
+// load instruction reads one contiguous stretch of the VDF: FP64 lanes lie
+// along the rows (each keeps its columns and their x-weights); FP32 rows are
+// staged through LDS 64 at a time and read back one row per lane.
 //
 // k_derive: central moments (rho, u, Tt, sigma, q, Tr, qr) of every cell from
 // the octant sums.
@@ -63,6 +64,10 @@ template <typename T, int VW, bool DIA>
 __global__ __launch_bounds__(512) void k_moments(GSIS_SPAN_ARGS)
 {
     __shared__ double sty[2 * TABMAX], stz[2 * TABMAX];
+    // FP32 rows of 4k values staged through LDS (64 rows per wave at a time)
+    constexpr bool STG = sizeof(T) == 4 && VW == 4;
+    constexpr int SROW = 32;
+    __shared__ __attribute__((aligned(16))) float stg[STG ? 8 * 64 * SROW : 4];
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
     const Geo &g = C.g;
@@ -141,7 +146,74 @@ __global__ __launch_bounds__(512) void k_moments(GSIS_SPAN_ARGS)
     // so every load reads one contiguous stretch of the octant; a lane keeps
     // its columns (x-weights in registers) and issues UN rows' loads first.
     const int lpr = nox / VW;
-    if (!ALONG) {
+    if (STG && nox <= SROW) {
+        // FP32 rows of at most SROW values: 64 rows at a time are staged
+        // through this wave's LDS region with coalesced 16-byte loads (the 64
+        // rows are one contiguous stretch of the octant), then each lane reads
+        // its own row from LDS (rows of 4k floats: conflict-free b128 reads).
+        // f1 passes through the same region after f0.  Only the lanes of one
+        // wave share a region, so a wave barrier orders its writes and reads.
+        float *sw = stg + o * 64 * SROW;
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        auto stage = [&](gptr<const T> fq, int r0, int nr) {
+            const int nvec = (nr * nox) >> 2;
+            const gptr<const f4> src = (gptr<const f4>)(fq + base + (size_t)r0 * nox);
+            f4 tmp[SROW / 4];
+#pragma unroll
+            for (int k = 0; k < SROW / 4; ++k)
+                if (lane + 64 * k < nvec) tmp[k] = __builtin_nontemporal_load(src + lane + 64 * k);
+#pragma unroll
+            for (int k = 0; k < SROW / 4; ++k)
+                if (lane + 64 * k < nvec) ((f4 *)sw)[lane + 64 * k] = tmp[k];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+        auto done = [&]() {   // every lane has read its row before the region is overwritten
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+        for (int r0 = 0; r0 < nrow; r0 += 64) {
+            const int nr = nrow - r0 < 64 ? nrow - r0 : 64;
+            double s0 = 0, s1 = 0, s2 = 0, s3 = 0, t0 = 0, t1 = 0;
+            stage(f0, r0, nr);
+            if (lane < nr) {
+                const f4 *row = (const f4 *)(sw + lane * nox);
+                for (int c = 0; c < (nox >> 2); ++c) {
+                    const f4 v = row[c];
+                    const double e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const gptr<const double> xt = xtab + (size_t)(x0 + 4 * c + q) * 4;
+                        s0 += xt[0] * e[q];
+                        s1 += xt[1] * e[q];
+                        s2 += xt[2] * e[q];
+                        s3 += xt[3] * e[q];
+                    }
+                }
+            }
+            done();
+            if (DIA) {
+                stage(f1, r0, nr);
+                if (lane < nr) {
+                    const f4 *row = (const f4 *)(sw + lane * nox);
+                    for (int c = 0; c < (nox >> 2); ++c) {
+                        const f4 v = row[c];
+                        const double e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const gptr<const double> xt = xtab + (size_t)(x0 + 4 * c + q) * 4;
+                            t0 += xt[0] * e[q];
+                            t1 += xt[1] * e[q];
+                        }
+                    }
+                }
+                done();
+            }
+            if (lane < nr) fold(r0 + lane, s0, s1, s2, s3, t0, t1);
+        }
+    } else if (!ALONG) {
         // one row per lane, read in chunks of CH vectors issued together
         constexpr int CH0 = (DIA ? 64 : 128) / (VW * (int)sizeof(T));
         constexpr int CH = CH0 < 16 ? CH0 : 16;
