@@ -7,9 +7,10 @@
 // which fold with the row's y/z weights into the 13 (+4 for f1) monomials.
 // One block per cell, one wave per octant, so per-octant sums -- from which
 // every half-range wall flux follows -- need only a wave reduction.  Every
-// load instruction reads one contiguous stretch of the VDF: FP64 lanes lie
-// along the rows (each keeps its columns and their x-weights); FP32 rows are
-// staged through LDS 64 at a time and read back one row per lane.
+// load instruction reads one contiguous stretch of the VDF: rows of up to 20
+// FP64 (32 FP32) values are staged through the wave's LDS region, 32 (64)
+// rows at a time, and read back one row per lane; longer FP64 rows are read
+// with the lanes along the rows (each keeping its columns and x-weights).
 //
 // k_derive: central moments (rho, u, Tt, sigma, q, Tr, qr) of every cell from
 // the octant sums.
@@ -68,6 +69,9 @@ __global__ __launch_bounds__(512) void k_moments(GSIS_SPAN_ARGS)
     constexpr bool STG = sizeof(T) == 4 && VW == 4;
     constexpr int SROW = 32;
     __shared__ __attribute__((aligned(16))) float stg[STG ? 8 * 64 * SROW : 4];
+    // FP64 rows of up to 20 values staged 32 at a time, each in a slot of at most 44 words
+    constexpr bool STG64 = sizeof(T) == 8 && VW == 2;
+    __shared__ __attribute__((aligned(16))) float stg64[STG64 ? 8 * 32 * 44 : 4];
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
     const Geo &g = C.g;
@@ -146,7 +150,76 @@ __global__ __launch_bounds__(512) void k_moments(GSIS_SPAN_ARGS)
     // so every load reads one contiguous stretch of the octant; a lane keeps
     // its columns (x-weights in registers) and issues UN rows' loads first.
     const int lpr = nox / VW;
-    if (STG && nox <= SROW) {
+    if (STG64 && nox <= 20) {
+        // FP64 rows of at most 20 values: 32 rows at a time staged through the
+        // wave's LDS region, each row in a slot of W words, W/4 odd, so the
+        // 16 lanes of a b128 pass read disjoint banks
+        const int W0 = nox * 2, W = (W0 >> 2) & 1 ? W0 : W0 + 4;
+        const int vpr = nox >> 1;                  // 16-byte vectors per row
+        float *sw = stg64 + o * 32 * 44;
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        auto stage = [&](gptr<const T> fq, int r0, int nr) {
+            const int nvec = nr * vpr;
+            const gptr<const f4> src = (gptr<const f4>)(fq + base + (size_t)r0 * nox);
+            f4 tmp[10];
+#pragma unroll
+            for (int k = 0; k < 10; ++k)
+                if (lane + 64 * k < nvec) tmp[k] = __builtin_nontemporal_load(src + lane + 64 * k);
+#pragma unroll
+            for (int k = 0; k < 10; ++k) {
+                const int v = lane + 64 * k;
+                if (v < nvec) {
+                    const int r = v / vpr, c = v - r * vpr;
+                    *(f4 *)(sw + r * W + 4 * c) = tmp[k];
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+        auto done = [&]() {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+        for (int r0 = 0; r0 < nrow; r0 += 32) {
+            const int nr = nrow - r0 < 32 ? nrow - r0 : 32;
+            double s0 = 0, s1 = 0, s2 = 0, s3 = 0, t0 = 0, t1 = 0;
+            stage(f0, r0, nr);
+            if (lane < nr) {
+                const double *row = (const double *)(sw + lane * W);
+                for (int c = 0; c < nox; c += 2) {
+                    const double e[2] = {row[c], row[c + 1]};
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const gptr<const double> xt = xtab + (size_t)(x0 + c + q) * 4;
+                        s0 += xt[0] * e[q];
+                        s1 += xt[1] * e[q];
+                        s2 += xt[2] * e[q];
+                        s3 += xt[3] * e[q];
+                    }
+                }
+            }
+            done();
+            if (DIA) {
+                stage(f1, r0, nr);
+                if (lane < nr) {
+                    const double *row = (const double *)(sw + lane * W);
+                    for (int c = 0; c < nox; c += 2) {
+                        const double e[2] = {row[c], row[c + 1]};
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) {
+                            const gptr<const double> xt = xtab + (size_t)(x0 + c + q) * 4;
+                            t0 += xt[0] * e[q];
+                            t1 += xt[1] * e[q];
+                        }
+                    }
+                }
+                done();
+            }
+            if (lane < nr) fold(r0 + lane, s0, s1, s2, s3, t0, t1);
+        }
+    } else if (STG && nox <= SROW) {
         // FP32 rows of at most SROW values: 64 rows at a time are staged
         // through this wave's LDS region with coalesced 16-byte loads (the 64
         // rows are one contiguous stretch of the octant), then each lane reads
