@@ -31,7 +31,11 @@
  *                      2) the same first-order left-hand side with the
  *                      right-hand side's interface values reconstructed to
  *                      second order (least-squares gradient, Venkatakrishnan
- *                      limiter), solved for the increment.
+ *                      limiter), solved for the increment.  On an
+ *                      unstructured mesh (cells with volumes, faces with
+ *                      areas and normals) the first-order update of the
+ *                      same equation, cells visited in a topological order
+ *                      of each node's upwind graph.
  *   boundary           diffuse wall (discrete half-range zero mass flux, wall
  *                      density lagged to f^n) and Maxwellian inflow.
  *   gsis_correct       Sec. 3.3, GSIS-II macroscopic equations with the
@@ -83,6 +87,17 @@ typedef struct {
      * creation. */
     int nlist;
     const double *node_list;
+    /* optional unstructured spatial mesh (Sec. 3.2: cells i of volume V_i,
+     * interfaces ij of area S_ij and unit normal n pointing from i to j):
+     * ucells > 0 cells replace the nx x ny x nz box (nx, ny, nz, lx, ly, lz and
+     * the solid mask are then ignored); uface_cell[2 f] is the owner of face f,
+     * uface_cell[2 f + 1] the neighbour cell or -1 - slot for a boundary face
+     * of boundary slot 0..6; uface_geom[4 f] its area and [4 f + 1..3] its unit
+     * normal out of the owner.  First order only; read once, at creation. */
+    int ucells, ufaces;
+    const double *uvol;
+    const int *uface_cell;
+    const double *uface_geom;
 } orc_cfg;
 
 typedef struct {
@@ -98,6 +113,12 @@ typedef struct {
     double *ntab;           /* [nv][4]: xi_x, xi_y, xi_z, weight of every node */
     double *mbw;            /* [ORC_NBC][nv] boundary Maxwellians M(1, u_b, T_b) at every node */
     double in_half[6][ORC_NBC]; /* sum_{xi_n < 0} w |xi_n| M(1, u_b, T_b) per face direction and slot */
+    /* unstructured mesh (umesh = 1): copies of the cell volumes and faces, and
+     * the faces of every cell, cf[cf_off[i] .. cf_off[i + 1]) = 2 f + side
+     * (side 0: the cell owns face f, 1: it is the neighbour) */
+    int umesh, nface;
+    double *uvol, *ufg;
+    int *ufc, *cf_off, *cf;
     int status;
 } orc_state;
 
@@ -154,14 +175,31 @@ void orc_free(orc_state *s)
     free(s->solid);
     for (int a = 0; a < 3; ++a) { free(s->xi[a]); free(s->w1[a]); }
     free(s->f0); free(s->f1); free(s->prev); free(s->lastW); free(s->mbw); free(s->ntab);
+    free(s->uvol); free(s->ufg); free(s->ufc); free(s->cf_off); free(s->cf);
     free(s);
 }
 
 static double maxwellian(double rho, const double u[3], double T, const double xi[3]);
 
+static int check_mesh(const orc_cfg *cfg)
+{
+    if (cfg->ufaces < 1 || !cfg->uvol || !cfg->uface_cell || !cfg->uface_geom || cfg->order != 1) return 0;
+    for (int i = 0; i < cfg->ucells; ++i)
+        if (!(cfg->uvol[i] > 0) || !isfinite(cfg->uvol[i])) return 0;
+    for (int f = 0; f < cfg->ufaces; ++f) {
+        int o = cfg->uface_cell[2 * f], n = cfg->uface_cell[2 * f + 1];
+        const double *g = cfg->uface_geom + (size_t)f * 4;
+        if (o < 0 || o >= cfg->ucells || n >= cfg->ucells || n == o || n < -ORC_NBC) return 0;
+        if (!(g[0] >= 0) || !isfinite(g[0]) || !isfinite(g[1]) || !isfinite(g[2]) || !isfinite(g[3])) return 0;
+    }
+    return 1;
+}
+
 static orc_state *create_state(const orc_cfg *cfg, const unsigned char *solid, int with_vdf)
 {
-    if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return NULL;
+    const int um = cfg->ucells > 0;
+    if (um && !check_mesh(cfg)) return NULL;
+    if (!um && (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1)) return NULL;
     if (cfg->order != 1 && cfg->order != 2) return NULL;
     if (!isfinite(cfg->limiter_k)) return NULL;
     const int list = cfg->nlist > 0;
@@ -181,14 +219,40 @@ static orc_state *create_state(const orc_cfg *cfg, const unsigned char *solid, i
     }
     orc_state *s = calloc(1, sizeof(*s));
     s->c = *cfg;
-    s->ncell = cfg->nx * cfg->ny * cfg->nz;
+    s->ncell = um ? cfg->ucells : cfg->nx * cfg->ny * cfg->nz;
     s->nv = list ? cfg->nlist : cfg->nv[0] * cfg->nv[1] * cfg->nv[2];
     s->h[0] = cfg->lx / cfg->nx;
     s->h[1] = cfg->ly / cfg->ny;
     s->h[2] = cfg->lz / cfg->nz;
     s->delta = sqrt(M_PI) / (2.0 * cfg->Kn);
     s->solid = calloc((size_t)s->ncell, 1);
-    if (solid) memcpy(s->solid, solid, (size_t)s->ncell);
+    if (solid && !um) memcpy(s->solid, solid, (size_t)s->ncell);
+    if (um) {
+        int nc = s->ncell, nf = cfg->ufaces;
+        s->umesh = 1;
+        s->nface = nf;
+        s->uvol = malloc(sizeof(double) * nc);
+        s->ufg = malloc(sizeof(double) * 4 * (size_t)nf);
+        s->ufc = malloc(sizeof(int) * 2 * (size_t)nf);
+        memcpy(s->uvol, cfg->uvol, sizeof(double) * nc);
+        memcpy(s->ufg, cfg->uface_geom, sizeof(double) * 4 * (size_t)nf);
+        memcpy(s->ufc, cfg->uface_cell, sizeof(int) * 2 * (size_t)nf);
+        s->cf_off = calloc((size_t)nc + 1, sizeof(int));
+        for (int f = 0; f < nf; ++f) {
+            s->cf_off[s->ufc[2 * f] + 1]++;
+            if (s->ufc[2 * f + 1] >= 0) s->cf_off[s->ufc[2 * f + 1] + 1]++;
+        }
+        for (int i = 0; i < nc; ++i) s->cf_off[i + 1] += s->cf_off[i];
+        s->cf = malloc(sizeof(int) * (size_t)s->cf_off[nc]);
+        int *at = malloc(sizeof(int) * nc);
+        memcpy(at, s->cf_off, sizeof(int) * nc);
+        for (int f = 0; f < nf; ++f) {
+            s->cf[at[s->ufc[2 * f]]++] = 2 * f;
+            if (s->ufc[2 * f + 1] >= 0) s->cf[at[s->ufc[2 * f + 1]]++] = 2 * f + 1;
+        }
+        free(at);
+        s->c.uvol = NULL; s->c.uface_cell = NULL; s->c.uface_geom = NULL;   /* copied */
+    }
     for (int a = 0; a < 3 && !list; ++a) {
         int n = cfg->nv[a];
         double d = (cfg->vmax[a] - cfg->vmin[a]) / (n - 1);
@@ -605,6 +669,152 @@ static void sweep_node(const orc_state *s, int v, const cellpar *P, const double
     }
 }
 
+/* ------------------------------------------------- unstructured sweep -- */
+/* Face entry e = 2 f + side of cell i: the unit normal out of i, S_f / V_i and
+ * what lies on the other side (a cell, or -1 - slot for a boundary face). */
+static void uface_of(const orc_state *s, int i, int e, double n[3], double *sv, int *other)
+{
+    int f = e >> 1, side = e & 1;
+    const double *g = s->ufg + (size_t)f * 4;
+    double sg = side ? -1.0 : 1.0;
+    n[0] = sg * g[1];
+    n[1] = sg * g[2];
+    n[2] = sg * g[3];
+    *sv = g[0] / s->uvol[i];
+    *other = side ? s->ufc[2 * f] : s->ufc[2 * f + 1];
+}
+
+/* Density scale of the incoming half of boundary face f (unit normal n out
+ * of its cell): diffuse wall rho_w = sum_{xi.n>0} w xi.n f0 /
+ * sum_{xi.n<0} w |xi.n| M(1,u_w,T_w) (zero discrete mass flux through the
+ * wall), inflow the fixed density. */
+static double uface_scale(const orc_state *s, int f)
+{
+    const orc_cfg *c = &s->c;
+    int cell = s->ufc[2 * f], bc = -1 - s->ufc[2 * f + 1];
+    if (c->bc_kind[bc] == ORC_INFLOW) return c->bc_rho[bc];
+    const double *g = s->ufg + (size_t)f * 4;
+    const double *f0 = s->f0 + (size_t)cell * s->nv;
+    nsum out = {0, 0}, in = {0, 0};
+    for (int v = 0; v < s->nv; ++v) {
+        double xi[3], w;
+        node_xi(s, v, xi, &w);
+        double xn = xi[0] * g[1] + xi[1] * g[2] + xi[2] * g[3];
+        if (xn > 0) nadd(&out, w * xn * f0[v]);
+        else if (xn < 0) nadd(&in, w * (-xn) * s->mbw[(size_t)bc * s->nv + v]);
+    }
+    return nval(&out) / nval(&in);
+}
+
+/* The kinetic update of node v on an unstructured mesh: Eq.
+ * (delta_equations) with first-order upwind interface values on both sides.
+ * With a_ij = (xi . n_ij) S_ij / V_i over the faces of cell i,
+ *   f_i^{n+1/2} = [f_i^n / dt + g_i / tau_i + sum_{a_ij < 0} |a_ij| F_ij]
+ *                 / (1/dt + 1/tau_i + sum_{a_ij > 0} a_ij),
+ * F_ij the new value of neighbour j, or the boundary value of the face.  The
+ * cells are visited in a topological order of the node's upwind graph (a
+ * face carries the node from the cell it leaves into the cell it enters):
+ * first the cells no face enters, then every cell once all cells upwind of it
+ * are done (Kahn's algorithm), which solves the lower-triangular system
+ * exactly.  A cycle in the graph -- a mesh that no sweep can order for this
+ * node -- leaves cells unvisited and sets status -7. */
+static void usweep_node(orc_state *s, int v, const cellpar *P, const double *bscale, double *col0, double *col1,
+                        int *indeg, int *queue)
+{
+    const orc_cfg *c = &s->c;
+    int dia = c->species == 1, nc = s->ncell;
+    double xi[3], w;
+    node_xi(s, v, xi, &w);
+    for (int i = 0; i < nc; ++i) indeg[i] = 0;
+    for (int f = 0; f < s->nface; ++f) {
+        int o = s->ufc[2 * f], nb = s->ufc[2 * f + 1];
+        if (nb < 0) continue;
+        const double *g = s->ufg + (size_t)f * 4;
+        double xn = xi[0] * g[1] + xi[1] * g[2] + xi[2] * g[3];
+        if (xn > 0) indeg[nb]++;
+        else if (xn < 0) indeg[o]++;
+    }
+    int head = 0, tail = 0;
+    for (int i = 0; i < nc; ++i)
+        if (indeg[i] == 0) queue[tail++] = i;
+    while (head < tail) {
+        int i = queue[head++];
+        double g0, g1;
+        ref_dist(c, &P[i], xi, &g0, &g1);
+        double it = P[i].invtau;
+        double num0 = c->inv_dt * col0[i] + it * g0;
+        double num1 = dia ? c->inv_dt * col1[i] + it * g1 : 0.0;
+        double den = c->inv_dt + it;
+        for (int e = s->cf_off[i]; e < s->cf_off[i + 1]; ++e) {
+            double n[3], sv;
+            int other;
+            uface_of(s, i, s->cf[e], n, &sv, &other);
+            double a = (xi[0] * n[0] + xi[1] * n[1] + xi[2] * n[2]) * sv;
+            if (a > 0) {
+                den += a;
+            } else if (a < 0) {
+                double F0, F1;
+                if (other >= 0) {
+                    F0 = col0[other];
+                    F1 = dia ? col1[other] : 0.0;
+                } else {
+                    boundary_value(c, -1 - other, bscale[s->cf[e] >> 1], xi, &F0, &F1);
+                }
+                num0 += -a * F0;
+                num1 += -a * F1;
+            }
+        }
+        col0[i] = num0 / den;
+        if (dia) col1[i] = num1 / den;
+        for (int e = s->cf_off[i]; e < s->cf_off[i + 1]; ++e) {
+            double n[3], sv;
+            int other;
+            uface_of(s, i, s->cf[e], n, &sv, &other);
+            if (other >= 0 && xi[0] * n[0] + xi[1] * n[1] + xi[2] * n[2] > 0 && --indeg[other] == 0)
+                queue[tail++] = other;
+        }
+    }
+    if (tail < nc) s->status = -7;
+}
+
+/* One kinetic pass on an unstructured mesh: per-cell parameters and boundary
+ * densities from f^n, then every node swept on its own. */
+static int one_pass_umesh(orc_state *s)
+{
+    const orc_cfg *c = &s->c;
+    int ncell = s->ncell, nv = s->nv, dia = c->species == 1;
+    cellpar *P = malloc(sizeof(cellpar) * (size_t)ncell);
+    double *bscale = calloc((size_t)s->nface, sizeof(double));
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int cell = 0; cell < ncell; ++cell) cell_params(s, cell, &P[cell]);
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int f = 0; f < s->nface; ++f)
+        if (s->ufc[2 * f + 1] < 0) bscale[f] = uface_scale(s, f);
+    for (int cell = 0; cell < ncell; ++cell)
+        if (!isfinite(P[cell].invtau) || !(P[cell].m.rho > 0) || !(P[cell].m.Tt > 0)) s->status = -5;
+    #pragma omp parallel
+    {
+        double *col0 = malloc(sizeof(double) * (size_t)ncell);
+        double *col1 = dia ? malloc(sizeof(double) * (size_t)ncell) : NULL;
+        int *indeg = malloc(sizeof(int) * (size_t)ncell), *queue = malloc(sizeof(int) * (size_t)ncell);
+        #pragma omp for schedule(dynamic, 1)
+        for (int v = 0; v < nv; ++v) {
+            for (int cell = 0; cell < ncell; ++cell) {
+                col0[cell] = s->f0[(size_t)cell * nv + v];
+                if (dia) col1[cell] = s->f1[(size_t)cell * nv + v];
+            }
+            usweep_node(s, v, P, bscale, col0, col1, indeg, queue);
+            for (int cell = 0; cell < ncell; ++cell) {
+                s->f0[(size_t)cell * nv + v] = col0[cell];
+                if (dia) s->f1[(size_t)cell * nv + v] = col1[cell];
+            }
+        }
+        free(col0); free(col1); free(indeg); free(queue);
+    }
+    free(P); free(bscale);
+    return s->status;
+}
+
 /* ------------------------------------------------ second-order values -- */
 /* Sec. 3.2: the interface values in the right-hand side of Eq.
  * (delta_equations) come from a second-order upwind reconstruction,
@@ -798,6 +1008,7 @@ static void sweep_node_second_order(const orc_state *s, int v, const cellpar *P,
  * then every node swept independently (the wall density is lagged), in place. */
 static int one_pass(orc_state *s)
 {
+    if (s->umesh) return one_pass_umesh(s);
     const orc_cfg *c = &s->c;
     int ncell = s->ncell, nv = s->nv, dia = c->species == 1;
     cellpar *P = malloc(sizeof(cellpar) * (size_t)ncell);
@@ -851,6 +1062,7 @@ static int one_pass(orc_state *s)
 int orc_first_pass_nodes(const orc_cfg *cfg, const unsigned char *solid, double rho, const double u[3], double T,
                          double Tr, const int *nodes, int nn, double *out0, double *out1)
 {
+    if (cfg->ucells > 0) return -2;
     orc_cfg one = *cfg;
     one.nx = one.ny = one.nz = 1;
     orc_state *s1 = create_state(&one, NULL, 1);
@@ -935,6 +1147,15 @@ void orc_set_vdf(orc_state *s, const double *f0, const double *f1)
     snapshot(s);
 }
 
+/* The VDF replaced without a new residual snapshot (the next residual
+ * compares with the state before). */
+void orc_replace_vdf(orc_state *s, const double *f0, const double *f1)
+{
+    size_t np = (size_t)s->ncell * s->nv;
+    memcpy(s->f0, f0, np * sizeof(double));
+    if (s->f1 && f1) memcpy(s->f1, f1, np * sizeof(double));
+}
+
 void orc_get_vdf(const orc_state *s, double *f0, double *f1)
 {
     size_t np = (size_t)s->ncell * s->nv;
@@ -960,7 +1181,7 @@ void orc_moments(const orc_state *s, double *out)
     }
 }
 
-/* Eq. (convergence_critertion) with uniform cell volumes; u is a vector.  A
+/* Eq. (convergence_critertion), volume-weighted (uniform hex cells: weight 1); u is a vector.  A
  * denominator that is zero, or for u at most (1000 times the FP64 unit
  * roundoff)^2 times the sum of Tt^2 -- the velocity of a gas at rest is only
  * rounding noise -- reports the absolute change instead.  Compares with the
@@ -974,10 +1195,15 @@ void orc_residual(orc_state *s, double eps[3])
         moms m;
         cell_moments(s, cell, &m);
         const double *pv = s->prev + (size_t)cell * 5;
+        double V = s->umesh ? s->uvol[cell] : 1.0;
         double dr = m.rho - pv[0], dT = m.Tt - pv[4];
-        nadd(&num[0], dr * dr); nadd(&den[0], pv[0] * pv[0]);
-        for (int a = 0; a < 3; ++a) { double du = m.u[a] - pv[1 + a]; nadd(&num[1], du * du); nadd(&den[1], pv[1 + a] * pv[1 + a]); }
-        nadd(&num[2], dT * dT); nadd(&den[2], pv[4] * pv[4]);
+        nadd(&num[0], V * dr * dr); nadd(&den[0], V * pv[0] * pv[0]);
+        for (int a = 0; a < 3; ++a) {
+            double du = m.u[a] - pv[1 + a];
+            nadd(&num[1], V * du * du);
+            nadd(&den[1], V * pv[1 + a] * pv[1 + a]);
+        }
+        nadd(&num[2], V * dT * dT); nadd(&den[2], V * pv[4] * pv[4]);
     }
     double ufloor = (1e3 * 2.220446049250313e-16) * (1e3 * 2.220446049250313e-16) * nval(&den[2]);
     for (int k = 0; k < 3; ++k) {
@@ -1015,6 +1241,7 @@ double orc_invtau(const orc_state *s, int cell)
  * is interior. */
 int orc_boundary_values(const orc_state *s, int cell, int d, double *b0, double *b1)
 {
+    if (s->umesh) return -2;
     int n = neighbour(s, cell, d);
     if (n >= 0) return -1;
     int bc = -1 - n;
@@ -1056,6 +1283,7 @@ static void node_column(const orc_state *s, int v, int which, double *col, int *
  * limited reconstruction on faces between fluid cells); NaN in solid cells. */
 void orc_face_values(const orc_state *s, int v, int which, int order, double *fv)
 {
+    if (s->umesh) return;
     int ncell = s->ncell;
     double *col = malloc(sizeof(double) * ncell), *bv = malloc(sizeof(double) * ncell * 6);
     int *nb = malloc(sizeof(int) * ncell * 6);
@@ -1069,6 +1297,7 @@ void orc_face_values(const orc_state *s, int v, int which, int order, double *fv
  * of the given order and the current boundary values; NaN in solid cells. */
 void orc_flux_divergence(const orc_state *s, int v, int which, int order, double *div)
 {
+    if (s->umesh) return;
     int ncell = s->ncell;
     double *col = malloc(sizeof(double) * ncell), *bv = malloc(sizeof(double) * ncell * 6);
     double *fv = malloc(sizeof(double) * ncell * 6);
@@ -1531,6 +1760,7 @@ static int macro_solve(orc_state *s, const moms *K, const double *Fkin, const do
  * Chapman-Enskog expansion). */
 static int gsis_correct_mode(orc_state *s, int iters, int euler)
 {
+    if (s->umesh) return -2;   /* the macroscopic solve is built for the box of hex cells */
     const orc_cfg *c = &s->c;
     int ncell = s->ncell, dia = c->species == 1;
     moms *K = calloc((size_t)ncell, sizeof(moms));
@@ -1597,6 +1827,7 @@ int orc_last_macro_W(const orc_state *s, double *out)
  * Returns -1 if that neighbour is not a fluid cell. */
 int orc_nsf_face(const orc_state *s, const double *W, int cell, int a, double out[5])
 {
+    if (s->umesh) return -2;
     if (cell < 0 || cell >= s->ncell || a < 0 || a > 2 || s->solid[cell]) return -1;
     int nb = neighbour(s, cell, 2 * a + 1);
     if (nb < 0) return -1;
@@ -1630,9 +1861,9 @@ double orc_total_mass(const orc_state *s)
             node_xi(s, v, xi, &w);
             nadd(&r, w * f0[v]);
         }
-        nadd(&m, nval(&r));
+        nadd(&m, nval(&r) * (s->umesh ? s->uvol[cell] : 1.0));
     }
-    return nval(&m) * s->h[0] * s->h[1] * s->h[2];
+    return nval(&m) * (s->umesh ? 1.0 : s->h[0] * s->h[1] * s->h[2]);
 }
 
 /* Heat-conduction coefficients k_t, k_r of the macroscopic solve, with
@@ -1690,7 +1921,7 @@ void orc_stream_free(orc_stream *st)
 
 orc_stream *orc_stream_create(const orc_cfg *cfg, const unsigned char *solid)
 {
-    if (cfg->inv_dt != 0.0 || cfg->order != 1) return NULL;
+    if (cfg->inv_dt != 0.0 || cfg->order != 1 || cfg->ucells > 0) return NULL;
     orc_stream *st = calloc(1, sizeof(*st));
     st->s = create_state(cfg, solid, 0);
     if (!st->s) { free(st); return NULL; }

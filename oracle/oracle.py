@@ -38,6 +38,8 @@ class _Cfg(C.Structure):
         ("nodes", C.POINTER(C.c_double) * 3),
         ("order", C.c_int), ("limiter_k", C.c_double),
         ("nlist", C.c_int), ("node_list", C.POINTER(C.c_double)),
+        ("ucells", C.c_int), ("ufaces", C.c_int), ("uvol", C.POINTER(C.c_double)),
+        ("uface_cell", C.POINTER(C.c_int)), ("uface_geom", C.POINTER(C.c_double)),
     ]
 
 
@@ -62,6 +64,7 @@ def lib():
         L.orc_init_maxwellian.argtypes = [P, C.c_double, D, C.c_double, C.c_double]
         L.orc_set_vdf.argtypes = [P, D, D]
         L.orc_get_vdf.argtypes = [P, D, D]
+        L.orc_replace_vdf.argtypes = [P, D, D]
         L.orc_moments.argtypes = [P, D]
         L.orc_residual.argtypes = [P, D]
         L.orc_gsis_correct.argtypes = [P, C.c_int]
@@ -127,6 +130,16 @@ def make_cfg(case) -> _Cfg:
     # explicit node positions: the arrays live on the config object (the C side
     # copies them when it creates its state)
     c._keep = []
+    mesh = getattr(case, "mesh", None)
+    if mesh is not None:
+        vol = np.ascontiguousarray(mesh.volume, dtype=np.float64)
+        fc = np.ascontiguousarray(mesh.face_cell, dtype=np.int32)
+        fg = np.ascontiguousarray(mesh.face_geom, dtype=np.float64)
+        c._keep += [vol, fc, fg]
+        c.ucells, c.ufaces = mesh.ncell, mesh.nface
+        c.uvol = vol.ctypes.data_as(C.POINTER(C.c_double))
+        c.uface_cell = fc.ctypes.data_as(C.POINTER(C.c_int))
+        c.uface_geom = fg.ctypes.data_as(C.POINTER(C.c_double))
     if getattr(case, "velocity_list", None) is not None:
         t = np.ascontiguousarray(case.velocity_list, dtype=np.float64)
         c._keep.append(t)
@@ -203,6 +216,12 @@ class Oracle:
         f0 = np.ascontiguousarray(f0, dtype=np.float64)
         f1 = None if f1 is None else np.ascontiguousarray(f1, dtype=np.float64)
         lib().orc_set_vdf(self.h, _dp(f0), _dp(f1))
+
+    def replace_vdf(self, f0: np.ndarray, f1: Optional[np.ndarray] = None):
+        """Replace the VDF keeping the residual snapshot of the state before."""
+        f0 = np.ascontiguousarray(f0, dtype=np.float64)
+        f1 = None if f1 is None else np.ascontiguousarray(f1, dtype=np.float64)
+        lib().orc_replace_vdf(self.h, _dp(f0), _dp(f1))
 
     def ref_dist(self, cell: int):
         g0 = np.empty(self.nv)

@@ -87,6 +87,10 @@ class Case:
     # velocity cell of a refined or unstructured mesh, its weight the cell's
     # volume; replaces the tensor grid (nv, vmin, vmax and nodes are then unused)
     velocity_list: Optional[np.ndarray] = None
+    # optional unstructured spatial mesh (SpatialMesh): replaces the box of
+    # nx x ny x nz hex cells (nx then holds the cell count, ny = nz = 1, and
+    # solid cells are simply not part of the mesh)
+    mesh: Optional["SpatialMesh"] = None
     # iteration plan of the workload
     passes: int = 10
     gsis: bool = False
@@ -322,3 +326,202 @@ def random_vdf(case: Case, seed: int, dtype=np.float64) -> Tuple[np.ndarray, Opt
         if f1 is not None:
             f1[case.solid.astype(bool)] = 0
     return f0, f1
+
+
+# ------------------------------------------------------- unstructured meshes
+# Cell kinds of a lattice mesh: every cube of the lattice is kept whole or cut
+# into tetrahedra, pyramids or prisms.
+TET, PYRAMID, PRISM, HEX = 0, 1, 2, 3
+
+
+@dataclasses.dataclass
+class SpatialMesh:
+    """A finite-volume mesh of convex polyhedral cells (Sec. 3.2: cells i of
+    volume V_i, interfaces ij of area S_ij with unit normal n from i to j).
+
+    ``face_cell[f] = (owner, neighbour)``, the neighbour a cell index or
+    ``-1 - slot`` for a boundary face of boundary slot 0..6 (the box faces
+    -x, +x, -y, +y, -z, +z, then the surface of a solid body);
+    ``face_geom[f] = (area, n_x, n_y, n_z)`` with n the unit normal pointing
+    out of the owner.  ``centroid`` and ``kind`` serve sampling and reports."""
+    volume: np.ndarray
+    face_cell: np.ndarray
+    face_geom: np.ndarray
+    centroid: np.ndarray
+    kind: np.ndarray
+
+    @property
+    def ncell(self) -> int:
+        return int(self.volume.shape[0])
+
+    @property
+    def nface(self) -> int:
+        return int(self.face_cell.shape[0])
+
+
+def _cube_cells():
+    """Cells of one lattice cube by kind, each a list of boundary triangles over
+    the cube's local points: corner b = bx + 2 by + 4 bz (0..7) and the centre
+    (8).  A cube face is always cut along the diagonal from its (0, 0) to its
+    (1, 1) corner in the face's own axes (the lower axis first), the cut the
+    Kuhn tetrahedra make, so that any two kinds meet on matching triangles."""
+    def face_tris(a, s):
+        b, c = [x for x in range(3) if x != a]
+        def pt(ub, uc):
+            bits = [0, 0, 0]
+            bits[a], bits[b], bits[c] = s, ub, uc
+            return bits[0] + 2 * bits[1] + 4 * bits[2]
+        return [(pt(0, 0), pt(1, 0), pt(1, 1)), (pt(0, 0), pt(0, 1), pt(1, 1))]
+
+    def face_edges(a, s):
+        b, c = [x for x in range(3) if x != a]
+        def pt(ub, uc):
+            bits = [0, 0, 0]
+            bits[a], bits[b], bits[c] = s, ub, uc
+            return bits[0] + 2 * bits[1] + 4 * bits[2]
+        ring = [pt(0, 0), pt(1, 0), pt(1, 1), pt(0, 1)]
+        return [(ring[k], ring[(k + 1) % 4]) for k in range(4)]
+
+    faces = [(a, s) for a in range(3) for s in (0, 1)]
+    hexcell = [[t for a, s in faces for t in face_tris(a, s)]]
+    tets = []
+    for p in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        v1 = 1 << p[0]
+        v2 = v1 | (1 << p[1])
+        v = (0, v1, v2, 7)
+        tets.append([(v[0], v[1], v[2]), (v[0], v[1], v[3]), (v[0], v[2], v[3]), (v[1], v[2], v[3])])
+    pyramids = []
+    for a, s in faces:
+        pyramids.append(face_tris(a, s) + [(e0, e1, 8) for e0, e1 in face_edges(a, s)])
+    diag = [(0, 3, 7), (0, 4, 7)]                      # the cut x = y through the z edges
+    prism_a = [(0, 1, 3), (4, 5, 7)] + face_tris(1, 0) + face_tris(0, 1) + diag   # x >= y
+    prism_b = [(0, 2, 3), (4, 6, 7)] + face_tris(0, 0) + face_tris(1, 1) + diag   # x <= y
+    return {TET: tets, PYRAMID: pyramids, PRISM: [prism_a, prism_b], HEX: hexcell}
+
+
+def lattice_mesh(nx: int, ny: int, nz: int, lx: float, ly: float, lz: float, split=TET,
+                 solid: Optional[np.ndarray] = None) -> SpatialMesh:
+    """An unstructured mesh on the nx x ny x nz lattice of the box [0,lx]x[0,ly]x[0,lz]:
+    cube (i, j, k) is cut by ``split`` (one kind for all, or an int array of
+    shape (nz, ny, nx)) into 6 Kuhn tetrahedra, 6 pyramids about its centre, 2
+    triangular prisms, or kept as one hexahedron; cubes flagged in ``solid``
+    (shape (nz, ny, nx) or flat, x fastest) are left out and their faces
+    become the solid surface (slot 6).  Cells are numbered cube by cube (x
+    fastest); coplanar triangles between the same two cells (or the same cell
+    and slot) are merged into one face."""
+    h = np.array([lx / nx, ly / ny, lz / nz])
+    kinds = np.broadcast_to(np.asarray(split, dtype=np.int64), (nz, ny, nx)).reshape(-1)
+    keep = np.ones(nx * ny * nz, dtype=bool)
+    if solid is not None:
+        keep = np.asarray(solid).reshape(-1) == 0
+    cube = np.flatnonzero(keep)
+    ci, cj, ck = cube % nx, (cube // nx) % ny, cube // (nx * ny)
+    nvl = (nx + 1) * (ny + 1) * (nz + 1)
+    bits = np.array([[b & 1, (b >> 1) & 1, (b >> 2) & 1] for b in range(8)])
+    # global ids of the 9 local points of every kept cube; the centres follow the lattice points
+    pid = np.empty((cube.size, 9), dtype=np.int64)
+    for b in range(8):
+        pid[:, b] = (ci + bits[b, 0]) + (nx + 1) * ((cj + bits[b, 1]) + (ny + 1) * (ck + bits[b, 2]))
+    pid[:, 8] = nvl + np.arange(cube.size)
+    lat = np.stack(np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij"),
+                   axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3)
+    pts = np.concatenate([lat * h, (np.stack([ci, cj, ck], axis=1) + 0.5) * h])
+    lat_i = np.concatenate([lat, np.full((cube.size, 3), -1)])   # lattice indices (-1: a centre)
+    table = _cube_cells()
+    ncell_of = np.array([len(table[k]) for k in (TET, PYRAMID, PRISM, HEX)])
+    kc = kinds[cube]
+    first = np.concatenate([[0], np.cumsum(ncell_of[kc])])   # first cell of every kept cube
+    tri_cell, tri_v = [], []
+    for k in (TET, PYRAMID, PRISM, HEX):
+        sel = np.flatnonzero(kc == k)
+        if sel.size == 0:
+            continue
+        for lc, tris in enumerate(table[k]):
+            for t in tris:
+                tri_cell.append(first[sel] + lc)
+                tri_v.append(pid[sel][:, list(t)])
+    tri_cell = np.concatenate(tri_cell)
+    tri_v = np.concatenate(tri_v)
+    ncell = int(first[-1])
+    kind = np.empty(ncell, dtype=np.int8)
+    for k in (TET, PYRAMID, PRISM, HEX):
+        sel = np.flatnonzero(kc == k)
+        for lc in range(ncell_of[k]):
+            kind[first[sel] + lc] = k
+    # cell centroid (mean of its triangles' vertices: inside a convex cell), triangle geometry
+    tp = pts[tri_v]
+    cen = np.zeros((ncell, 3))
+    np.add.at(cen, tri_cell, tp.sum(axis=1))
+    cen /= np.bincount(tri_cell, minlength=ncell)[:, None] * 3
+    cr = np.cross(tp[:, 1] - tp[:, 0], tp[:, 2] - tp[:, 0])
+    area = 0.5 * np.linalg.norm(cr, axis=1)
+    nrm = cr / (2.0 * area[:, None])
+    tc = tp.mean(axis=1)
+    flip = np.einsum("ij,ij->i", nrm, tc - cen[tri_cell]) < 0
+    nrm[flip] *= -1.0                                   # out of the triangle's own cell
+    vol = np.zeros(ncell)
+    np.add.at(vol, tri_cell, area * np.einsum("ij,ij->i", nrm, tc) / 3.0)
+    # pair the triangles: equal vertex sets are the two sides of one interface
+    key = np.sort(tri_v, axis=1)
+    order = np.lexsort((key[:, 2], key[:, 1], key[:, 0]))
+    ks = key[order]
+    same = np.all(ks[1:] == ks[:-1], axis=1)
+    a_idx = order[:-1][same]
+    b_idx = order[1:][same]
+    paired = np.zeros(tri_cell.size, dtype=bool)
+    paired[a_idx] = paired[b_idx] = True
+    lone = np.flatnonzero(~paired)
+    li = lat_i[tri_v[lone]]                             # [n, 3 vertices, 3 axes]
+    slot = np.full(lone.size, 6)
+    for a, n_a in enumerate((nx, ny, nz)):
+        slot[np.all(li[:, :, a] == 0, axis=1)] = 2 * a
+        slot[np.all(li[:, :, a] == n_a, axis=1)] = 2 * a + 1
+    owner = np.concatenate([tri_cell[a_idx], tri_cell[lone]])
+    other = np.concatenate([tri_cell[b_idx], -1 - slot])
+    geom = np.concatenate([np.column_stack([area[a_idx], nrm[a_idx]]), np.column_stack([area[lone], nrm[lone]])])
+    # merge coplanar triangles of the same (owner, other) pair
+    nkey = np.round(geom[:, 1:] * 1e9).astype(np.int64)
+    mk = np.column_stack([owner, other, nkey])
+    uq, inv = np.unique(mk, axis=0, return_inverse=True)
+    inv = inv.reshape(-1)
+    fa = np.zeros(uq.shape[0])
+    np.add.at(fa, inv, geom[:, 0])
+    rep = np.zeros(uq.shape[0], dtype=np.int64)
+    rep[inv[::-1]] = np.arange(inv.size)[::-1]          # first triangle of every face
+    fn = geom[rep, 1:]
+    fc = np.column_stack([owner[rep], other[rep]]).astype(np.int32)
+    fo = np.lexsort((fc[:, 1], fc[:, 0]))
+    return SpatialMesh(volume=vol, face_cell=np.ascontiguousarray(fc[fo]),
+                       face_geom=np.ascontiguousarray(np.column_stack([fa, fn])[fo]),
+                       centroid=cen, kind=kind)
+
+
+def tensor_velocity_list(nv, vmin, vmax) -> np.ndarray:
+    """The uniform tensor grid of a case as a node list [n][4], x fastest,
+    trapezoid weights (products of the 1-D weights)."""
+    ax, wt = [], []
+    for a in range(3):
+        x = np.linspace(vmin[a], vmax[a], nv[a])
+        d = (vmax[a] - vmin[a]) / (nv[a] - 1)
+        w = np.full(nv[a], d)
+        w[0] = w[-1] = 0.5 * d
+        ax.append(x)
+        wt.append(w)
+    X = np.stack(np.meshgrid(ax[0], ax[1], ax[2], indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3)
+    W = (wt[0][None, None, :] * wt[1][None, :, None] * wt[2][:, None, None]).reshape(-1)
+    return np.ascontiguousarray(np.column_stack([X, W]))
+
+
+def on_mesh(case: Case, mesh: SpatialMesh, name: Optional[str] = None) -> Case:
+    """The case on the unstructured spatial mesh ``mesh`` (same gas, velocity
+    set and boundary slots; a tensor velocity grid becomes its node list)."""
+    c = dataclasses.replace(case)
+    c.mesh = mesh
+    c.nx, c.ny, c.nz = mesh.ncell, 1, 1
+    c.solid = None
+    c.order = 1
+    if c.velocity_list is None:
+        c.velocity_list = tensor_velocity_list(c.nv, c.vmin, c.vmax)
+    if name:
+        c.name = name
+    return c
