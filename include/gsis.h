@@ -135,6 +135,33 @@ gsis_status gsis_set_velocity_nodes(gsis_ctx *ctx, int axis, const double *nodes
  * workspace is sized (and from gsis_set_velocity_nodes afterwards). */
 gsis_status gsis_set_velocity_list(gsis_ctx *ctx, const double *nodes, int n);
 
+/* Unstructured spatial mesh (Sec. 3.2: the kinetic update of Eq.
+ * (delta_equations) on cells i of volume V_i whose interfaces ij have area
+ * S_ij and unit normal n_ij pointing from i to j; the paper's hypersonic
+ * cases use tetrahedral and mixed-element meshes).  Host arrays, copied:
+ * volume[ncell] > 0; face_cell[nface][2] = (owner cell, neighbour cell or
+ * -1 - slot for a boundary face of boundary slot 0..6, whose condition
+ * gsis_set_boundary gives); face_geom[nface][4] = (area >= 0, unit normal
+ * out of the owner).  Replaces the box of hex cells of the configuration
+ * (its nx, ny, nz, lx, ly, lz are then unused; cells are numbered as given,
+ * gsis_moments has ncell rows) and runs the first-order update, solved
+ * exactly: the library groups the velocity nodes into classes that agree on
+ * the sign of xi . n for every face orientation of the mesh and sorts each
+ * class's upwind graph into levels, swept one after another.  Requires
+ * gsis_set_velocity_list first, order 1 and no solid mask (a body is a hole
+ * in the mesh, its surface boundary slot 6); must precede
+ * gsis_workspace_size.  Kinetic passes, moments, residual (volume-weighted)
+ * and state calls work as on the box; gsis_gsis_correct, gsis_precondition,
+ * gsis_set_tile, gsis_autotune and gsis_batch_create return GSIS_ESTATE
+ * (GSIS_EINVAL for the batch).  EINVAL when an index, area, normal or volume
+ * is invalid, a cell has more than 16 faces or is not closed (its area times
+ * outward normals do not sum to zero within 1e-9 of its area), the faces
+ * have more than 32 distinct orientations up to sign, the nodes fall into
+ * more than 256 classes, or a class's upwind graph has a cycle (a mesh no
+ * sweep orders exactly); ESTATE out of order. */
+gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume, int nface, const int *face_cell,
+                                  const double *face_geom);
+
 /* Boundary condition of slot face (GSIS_FACE_*): kind GSIS_DIFFUSE_WALL with
  * wall velocity u and temperature T (rho ignored; the wall density is set so
  * the discrete mass flux is zero), or GSIS_MAXWELL_INFLOW with the Maxwellian

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
-SOURCES = ["gsis_host.hip", "k_vdf.hip", "k_moments.hip", "k_params.hip", "k_sweep.hip", "k_macro.hip", "k_resid.hip", "k_recon.hip"]
+SOURCES = ["gsis_host.hip", "k_vdf.hip", "k_moments.hip", "k_params.hip", "k_sweep.hip", "k_macro.hip", "k_resid.hip", "k_recon.hip", "k_usweep.hip"]
 OUT = os.path.join(PKG, "libgsis.so")
 
 # compile flags of every HIP source; packed FP32 instructions stay off

@@ -17,6 +17,8 @@ constexpr int NSNAP = 5;   // residual snapshot per cell: rho, u, Tt
 constexpr double PI = 3.14159265358979323846;
 constexpr int LSUM_SHAPE = 20;        // node list: Gram entries (15) and Shakhov moments (5) of one shape
 constexpr int LSUM = 2 * LSUM_SHAPE;  // per cell: the Tt shape, then the T shape (diatomic)
+constexpr int UMAXORI = 32;   // unstructured mesh: distinct face orientations (axes included)
+constexpr int UMAXF = 16;     // unstructured mesh: faces per cell
 
 // Geometry, velocity grid and gas constants, passed to kernels by value.
 //
@@ -52,6 +54,11 @@ struct Geo {
     double kt, kr, gam, Cd;   // macroscopic transport constants
     double hmin;
     int fp32;      // VDF precision
+    // unstructured spatial mesh (umesh = 1; nx = ncell, ny = nz = 1): ucls
+    // velocity classes (the nodes whose signs of xi . n_k agree for every face
+    // orientation n_k of the mesh, so that they share one upwind order), unbf
+    // boundary faces, nori orientations
+    int umesh, ucls, unbf, nori;
 };
 
 struct BcInfo {
@@ -101,6 +108,27 @@ struct Dev {
     int *plane_off;    // [nplane] first tile of each plane in tiles
     int *tent;         // [8 * tiles] (tile in plane << 3 | octant) entries of a split sweep: plane p's
                        // entries start at 8 plane_off[p], those without solid cells first
+    // unstructured spatial mesh (null otherwise).  Cell i's faces are entries
+    // ucf_off[i] .. ucf_off[i + 1] of: ucf_nb the cell on the other side, or
+    // -1 - b for boundary face b; ucf_meta = k | s << 5 | slot << 6 with n_k
+    // the face's orientation, s = 1 when the normal out of cell i is -n_k, and
+    // the boundary slot; ucf_c* = S / V_i.  Orientations uori* [UMAXORI][4];
+    // classes ucls[c] = (sign mask: bit k set when xi . n_k >= 0, first
+    // position in a VDF row, node count, 0); ulev the sweep entries
+    // (cell << 8 | class) level after level; boundary face b: its cell, slot,
+    // unit normal out of the cell ([4] per face) and incoming density scale.
+    double *uvol;      // [ncell] cell volumes (residual weights)
+    int *ucf_off, *ucf_nb, *ucf_meta;
+    double *ucf_c64;
+    float *ucf_c32;
+    double *uori64;
+    float *uori32;
+    int4 *ucls;
+    int *ulev;
+    int *ubf_cell, *ubf_slot;
+    double *ubf_n;
+    double *ubf_s64;
+    float *ubf_s32;
     double *corr;      // [ncell][NCORR]
     double *snap;      // [ncell][NSNAP]
     // macroscopic solve, all structures of arrays [field][ncell] ([field][nface]

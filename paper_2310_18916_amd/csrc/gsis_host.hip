@@ -6,6 +6,7 @@
 #include "gsis_resid_host.h"
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -24,6 +25,10 @@ struct gsis_ctx {
     std::vector<int> cflag, nbr, face_cell, face_dir, face_bc, perm;
     std::vector<double> xi[3], w[3];
     std::vector<double> vlist;   // node list [nv][4] in the caller's order (list mode)
+    // unstructured spatial mesh (g.umesh): what the sweep needs, built when the
+    // mesh is set (see Dev for the meaning of each array)
+    std::vector<double> uvol, ucf_c, uori, ubf_n;
+    std::vector<int> ucf_off, ucf_nb, ucf_meta, ulev, ulev_off, ubf_cell, ubf_slot, uperm, ucls;
     int tx = 0, ty = 0, tz = 0, bs = 0;
     std::vector<int> tiles, plane_off, plane_cnt, npblk;
     std::vector<int> tent, nclean;   // split sweep entries (cases with solid cells)
@@ -184,6 +189,22 @@ void build_meta(gsis_ctx *c)
 {
     Geo &g = c->g;
     int nx = g.nx, ny = g.ny, nz = g.nz, n = g.ncell;
+    if (g.umesh) {
+        // every cell of the mesh is a fluid cell; the box's neighbour table,
+        // face list and sweep tiles stay empty
+        c->mask.assign(n, 0);
+        c->cflag.assign(n, 1);
+        c->nbr.assign((size_t)n * 6, -1);
+        c->face_cell.clear(); c->face_dir.clear(); c->face_bc.clear();
+        g.nface = 0;
+        g.nfluid = n;
+        c->perm = c->uperm;
+        c->vw = 1;
+        c->tiles.clear(); c->plane_off.clear(); c->plane_cnt.clear(); c->npblk.clear();
+        c->tent.clear(); c->nclean.clear();
+        c->meta_ready = true;
+        return;
+    }
     if (c->mask.empty()) c->mask.assign(n, 0);
     c->cflag.assign(n, 0);
     c->nbr.assign((size_t)n * 6, 0);
@@ -308,6 +329,27 @@ size_t layout(gsis_ctx *c, char *base)
     Case *dc = nullptr;
     carve(off, dc, 1, base);
     if (base) c->dcase = dc;
+    d.uvol = nullptr; d.ucf_off = d.ucf_nb = d.ucf_meta = nullptr; d.ucf_c64 = nullptr; d.ucf_c32 = nullptr;
+    d.uori64 = nullptr; d.uori32 = nullptr; d.ucls = nullptr; d.ulev = nullptr;
+    d.ubf_cell = d.ubf_slot = nullptr; d.ubf_n = nullptr; d.ubf_s64 = nullptr; d.ubf_s32 = nullptr;
+    if (g.umesh) {
+        const size_t ne = c->ucf_nb.size(), nb = std::max(g.unbf, 1);
+        carve(off, d.uvol, n, base);
+        carve(off, d.ucf_off, n + 1, base);
+        carve(off, d.ucf_nb, ne, base);
+        carve(off, d.ucf_meta, ne, base);
+        carve(off, d.ucf_c64, ne, base);
+        carve(off, d.ucf_c32, ne, base);
+        carve(off, d.uori64, (size_t)UMAXORI * 4, base);
+        carve(off, d.uori32, (size_t)UMAXORI * 4, base);
+        carve(off, d.ucls, (size_t)g.ucls, base);
+        carve(off, d.ulev, c->ulev.size(), base);
+        carve(off, d.ubf_cell, nb, base);
+        carve(off, d.ubf_slot, nb, base);
+        carve(off, d.ubf_n, nb * 4, base);
+        carve(off, d.ubf_s64, nb, base);
+        carve(off, d.ubf_s32, nb, base);
+    }
     carve(off, d.corr, n * NCORR, base);
     carve(off, d.snap, n * NSNAP, base);
     carve(off, d.W, n * 6, base);
@@ -651,6 +693,7 @@ gsis_status gsis_set_velocity_list(gsis_ctx *ctx, const double *nodes, int n)
 {
     if (!ctx) return GSIS_EINVAL;
     if (ctx->bound || ctx->meta_ready) return fail(ctx, GSIS_ESTATE, "set_velocity_list must precede workspace_size/bind");
+    if (ctx->g.umesh) return fail(ctx, GSIS_ESTATE, "set_velocity_list must precede set_spatial_mesh");
     if (!nodes) return fail(ctx, GSIS_EINVAL, "nodes is NULL");
     if (n < 2 || n > (1 << 24)) return fail(ctx, GSIS_EINVAL, "the node count must be in [2, 2^24]");
     for (int k = 0; k < n; ++k) {
@@ -668,10 +711,209 @@ gsis_status gsis_set_velocity_list(gsis_ctx *ctx, const double *nodes, int n)
     return GSIS_OK;
 }
 
+gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume, int nface, const int *face_cell,
+                                  const double *face_geom)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (ctx->bound || ctx->meta_ready) return fail(ctx, GSIS_ESTATE, "set_spatial_mesh must precede workspace_size/bind");
+    if (ctx->g.umesh) return fail(ctx, GSIS_ESTATE, "the spatial mesh is already set");
+    if (!ctx->g.vlist) return fail(ctx, GSIS_ESTATE, "set_velocity_list must precede set_spatial_mesh");
+    if (ctx->g.order != 1) return fail(ctx, GSIS_ESTATE, "an unstructured mesh runs the first-order update (order 1)");
+    if (!ctx->mask.empty()) return fail(ctx, GSIS_ESTATE, "an unstructured mesh takes no solid mask");
+    if (!volume || !face_cell || !face_geom) return fail(ctx, GSIS_EINVAL, "mesh array is NULL");
+    if (ncell < 1 || nface < 1) return fail(ctx, GSIS_EINVAL, "the mesh needs cells and faces");
+    if (ncell >= (1 << 23)) return fail(ctx, GSIS_EINVAL, "at most 2^23 - 1 cells");
+    if ((long long)ncell * ctx->g.nv > (1ll << 40)) return fail(ctx, GSIS_EINVAL, "cells x nodes too large");
+    for (int i = 0; i < ncell; ++i)
+        if (!(volume[i] > 0) || !std::isfinite(volume[i])) return fail(ctx, GSIS_EINVAL, "cell volumes must be positive");
+    std::vector<int> nfc(ncell, 0);
+    std::vector<double> clos((size_t)ncell * 3, 0.0), area((size_t)ncell, 0.0);
+    for (int f = 0; f < nface; ++f) {
+        const int o = face_cell[2 * f], nb = face_cell[2 * f + 1];
+        const double *gg = face_geom + (size_t)f * 4;
+        if (o < 0 || o >= ncell || nb >= ncell || nb == o || nb < -NBC)
+            return fail(ctx, GSIS_EINVAL, "face " + std::to_string(f) + ": bad owner or neighbour");
+        if (!(gg[0] >= 0) || !std::isfinite(gg[0])) return fail(ctx, GSIS_EINVAL, "face areas must be >= 0");
+        const double nn = gg[1] * gg[1] + gg[2] * gg[2] + gg[3] * gg[3];
+        if (!(std::fabs(nn - 1.0) <= 1e-9)) return fail(ctx, GSIS_EINVAL, "face normals must be unit vectors");
+        for (int side = 0; side < (nb >= 0 ? 2 : 1); ++side) {
+            const int c = side ? nb : o;
+            const double sg = side ? -1.0 : 1.0;
+            if (++nfc[c] > UMAXF) return fail(ctx, GSIS_EINVAL, "a cell has more than 16 faces");
+            for (int a = 0; a < 3; ++a) clos[(size_t)c * 3 + a] += sg * gg[0] * gg[1 + a];
+            area[c] += gg[0];
+        }
+    }
+    for (int i = 0; i < ncell; ++i) {
+        const double *v = &clos[(size_t)i * 3];
+        if (!(std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) <= 1e-9 * area[i]))
+            return fail(ctx, GSIS_EINVAL, "cell " + std::to_string(i) + " is not closed (its area-weighted normals do not sum to zero)");
+    }
+    // face orientations up to sign, the three axes first (so that the classes
+    // below refine the octants); a normal's canonical sign makes its first
+    // component of magnitude above 1e-9 positive
+    std::vector<double> ori = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
+    std::vector<int> fk(nface), fflip(nface);
+    for (int f = 0; f < nface; ++f) {
+        const double *gg = face_geom + (size_t)f * 4 + 1;
+        int a0 = 0;
+        while (a0 < 2 && !(std::fabs(gg[a0]) > 1e-9)) ++a0;
+        const double sg = gg[a0] < 0 ? -1.0 : 1.0;
+        const double cn[3] = {sg * gg[0], sg * gg[1], sg * gg[2]};
+        int k = 0;
+        const int nk = (int)ori.size() / 4;
+        for (; k < nk; ++k)
+            if (std::fabs(ori[4 * k] - cn[0]) <= 1e-9 && std::fabs(ori[4 * k + 1] - cn[1]) <= 1e-9 &&
+                std::fabs(ori[4 * k + 2] - cn[2]) <= 1e-9)
+                break;
+        if (k == nk) {
+            if (nk == UMAXORI) return fail(ctx, GSIS_EINVAL, "the mesh has more than 32 distinct face orientations");
+            ori.insert(ori.end(), {cn[0], cn[1], cn[2], 0.0});
+        }
+        fk[f] = k;
+        fflip[f] = sg < 0 ? 1 : 0;
+    }
+    const int nori = (int)ori.size() / 4;
+    // velocity classes: nodes with the same signs of xi . n_k for every k,
+    // ordered by octant, then by mask; each class contiguous in a VDF row
+    const int nv = ctx->g.nv;
+    std::vector<unsigned> nmask(nv);
+    for (int v = 0; v < nv; ++v) {
+        const double *t = &ctx->vlist[(size_t)v * 4];
+        unsigned m = 0;
+        for (int k = 0; k < nori; ++k)
+            if (t[0] * ori[4 * k] + t[1] * ori[4 * k + 1] + t[2] * ori[4 * k + 2] >= 0.0) m |= 1u << k;
+        nmask[v] = m;
+    }
+    auto octant_of = [](unsigned m) { return (int)((~m) & 7u); };   // bit a of the mask: xi_a >= 0
+    std::vector<unsigned> masks(nmask);
+    std::sort(masks.begin(), masks.end(), [&](unsigned x, unsigned y) {
+        return octant_of(x) != octant_of(y) ? octant_of(x) < octant_of(y) : x < y;
+    });
+    masks.erase(std::unique(masks.begin(), masks.end()), masks.end());
+    const int ncls = (int)masks.size();
+    if (ncls > 256) return fail(ctx, GSIS_EINVAL, "more than 256 velocity classes");
+    std::map<unsigned, int> cls_of;
+    for (int c = 0; c < ncls; ++c) cls_of[masks[c]] = c;
+    std::vector<int> cnt(ncls, 0);
+    for (int v = 0; v < nv; ++v) ++cnt[cls_of[nmask[v]]];
+    std::vector<int> cpos(ncls + 1, 0);
+    for (int c = 0; c < ncls; ++c) cpos[c + 1] = cpos[c] + cnt[c];
+    std::vector<int> perm(nv), at(cpos.begin(), cpos.end() - 1);
+    for (int v = 0; v < nv; ++v) perm[at[cls_of[nmask[v]]]++] = v;
+    // faces of every cell in input order (the owner's entry, then the neighbour's)
+    std::vector<int> off(ncell + 1, 0);
+    for (int i = 0; i < ncell; ++i) off[i + 1] = off[i] + nfc[i];
+    std::vector<int> cnb(off[ncell]), cmeta(off[ncell]), pos(off.begin(), off.end() - 1);
+    std::vector<double> ccoef(off[ncell]);
+    std::vector<int> bcell, bslot;
+    std::vector<double> bn;
+    for (int f = 0; f < nface; ++f) {
+        const int o = face_cell[2 * f], nb = face_cell[2 * f + 1];
+        const double *gg = face_geom + (size_t)f * 4;
+        int other = nb;
+        int slot = 0;
+        if (nb < 0) {
+            slot = -1 - nb;
+            other = -1 - (int)bcell.size();
+            bcell.push_back(o);
+            bslot.push_back(slot);
+            bn.insert(bn.end(), {gg[1], gg[2], gg[3], 0.0});
+        }
+        int e = pos[o]++;
+        cnb[e] = other;
+        cmeta[e] = fk[f] | fflip[f] << 5 | slot << 6;
+        ccoef[e] = gg[0] / volume[o];
+        if (nb >= 0) {
+            e = pos[nb]++;
+            cnb[e] = o;
+            cmeta[e] = fk[f] | (fflip[f] ^ 1) << 5;
+            ccoef[e] = gg[0] / volume[nb];
+        }
+    }
+    // per class: the levels of its upwind graph (Kahn); then the sweep
+    // entries level by level, classes in order, cells ascending
+    std::vector<std::vector<int>> lev(ncls);
+    int nlev = 0;
+    std::vector<int> indeg(ncell), level(ncell);
+    for (int c = 0; c < ncls; ++c) {
+        const unsigned m = masks[c];
+        auto leaves = [&](int i, int e) {   // the class's nodes leave cell i through entry e
+            return (((m >> (cmeta[e] & 31)) & 1u) != 0) != (((cmeta[e] >> 5) & 1) != 0);
+        };
+        std::fill(indeg.begin(), indeg.end(), 0);
+        for (int i = 0; i < ncell; ++i)
+            for (int e = off[i]; e < off[i + 1]; ++e)
+                if (cnb[e] >= 0 && !leaves(i, e)) ++indeg[i];
+        std::vector<int> front, next;
+        for (int i = 0; i < ncell; ++i)
+            if (indeg[i] == 0) front.push_back(i);
+        int done = 0, L = 0;
+        while (!front.empty()) {
+            std::sort(front.begin(), front.end());
+            for (int i : front) level[i] = L;
+            done += (int)front.size();
+            next.clear();
+            for (int i : front)
+                for (int e = off[i]; e < off[i + 1]; ++e)
+                    if (cnb[e] >= 0 && leaves(i, e) && --indeg[cnb[e]] == 0) next.push_back(cnb[e]);
+            front.swap(next);
+            ++L;
+        }
+        if (done < ncell)
+            return fail(ctx, GSIS_EINVAL, "the upwind graph of velocity class " + std::to_string(c) +
+                                              " has a cycle: no sweep order solves this mesh exactly");
+        lev[c].assign(level.begin(), level.end());
+        nlev = std::max(nlev, L);
+    }
+    std::vector<int> lcount(nlev + 1, 0);
+    for (int c = 0; c < ncls; ++c)
+        for (int i = 0; i < ncell; ++i) ++lcount[lev[c][i] + 1];
+    for (int L = 0; L < nlev; ++L) lcount[L + 1] += lcount[L];
+    std::vector<int> ent(lcount[nlev]), lat(lcount.begin(), lcount.end() - 1);
+    for (int c = 0; c < ncls; ++c)
+        for (int i = 0; i < ncell; ++i) ent[lat[lev[c][i]]++] = i << 8 | c;
+    for (int L = 0; L < nlev; ++L)   // within a level: class by class, cells ascending
+        std::sort(ent.begin() + lcount[L], ent.begin() + lcount[L + 1], [](int x, int y) {
+            return (x & 255) != (y & 255) ? (x & 255) < (y & 255) : x < y;
+        });
+    // commit
+    Geo &g = ctx->g;
+    ctx->uvol.assign(volume, volume + ncell);
+    ctx->ucf_off = off;
+    ctx->ucf_nb = cnb;
+    ctx->ucf_meta = cmeta;
+    ctx->ucf_c = ccoef;
+    ctx->uori.assign((size_t)UMAXORI * 4, 0.0);
+    std::copy(ori.begin(), ori.end(), ctx->uori.begin());
+    ctx->ucls.assign((size_t)ncls * 4, 0);
+    for (int c = 0; c < ncls; ++c) {
+        ctx->ucls[4 * c] = (int)masks[c];
+        ctx->ucls[4 * c + 1] = cpos[c];
+        ctx->ucls[4 * c + 2] = cnt[c];
+    }
+    ctx->ulev = ent;
+    ctx->ulev_off = lcount;
+    ctx->ubf_cell = bcell;
+    ctx->ubf_slot = bslot;
+    ctx->ubf_n = bn;
+    ctx->uperm = perm;
+    g.umesh = 1;
+    g.ucls = ncls;
+    g.unbf = (int)bcell.size();
+    g.nori = nori;
+    g.nx = ncell;
+    g.ny = g.nz = 1;
+    g.ncell = ncell;
+    ctx->mask.clear();
+    return GSIS_OK;
+}
+
 gsis_status gsis_set_solid_mask(gsis_ctx *ctx, const uint8_t *mask, size_t n)
 {
     if (!ctx) return GSIS_EINVAL;
     if (ctx->bound || ctx->meta_ready) return fail(ctx, GSIS_ESTATE, "set_solid_mask must precede workspace_size/bind");
+    if (ctx->g.umesh) return fail(ctx, GSIS_ESTATE, "an unstructured mesh takes no solid mask (leave solid cells out of it)");
     if (!mask) return fail(ctx, GSIS_EINVAL, "mask is NULL");
     if (n != (size_t)ctx->g.ncell) return fail(ctx, GSIS_EINVAL, "mask size must be nx*ny*nz");
     size_t fluid = 0;
@@ -781,6 +1023,24 @@ gsis_status gsis_bind_workspace(gsis_ctx *ctx, void *device_ptr, size_t bytes)
         HIPCHK(ctx, up(d.nt32, nt32.data(), nt32.size() * sizeof(float)));
     }
     HIPCHK(ctx, up(d.perm, ctx->perm.data(), ctx->perm.size() * sizeof(int)));
+    if (g.umesh) {
+        std::vector<float> c32(ctx->ucf_c.begin(), ctx->ucf_c.end()), o32(ctx->uori.begin(), ctx->uori.end());
+        HIPCHK(ctx, up(d.uvol, ctx->uvol.data(), ctx->uvol.size() * sizeof(double)));
+        HIPCHK(ctx, up(d.ucf_off, ctx->ucf_off.data(), ctx->ucf_off.size() * sizeof(int)));
+        HIPCHK(ctx, up(d.ucf_nb, ctx->ucf_nb.data(), ctx->ucf_nb.size() * sizeof(int)));
+        HIPCHK(ctx, up(d.ucf_meta, ctx->ucf_meta.data(), ctx->ucf_meta.size() * sizeof(int)));
+        HIPCHK(ctx, up(d.ucf_c64, ctx->ucf_c.data(), ctx->ucf_c.size() * sizeof(double)));
+        HIPCHK(ctx, up(d.ucf_c32, c32.data(), c32.size() * sizeof(float)));
+        HIPCHK(ctx, up(d.uori64, ctx->uori.data(), ctx->uori.size() * sizeof(double)));
+        HIPCHK(ctx, up(d.uori32, o32.data(), o32.size() * sizeof(float)));
+        HIPCHK(ctx, up(d.ucls, ctx->ucls.data(), ctx->ucls.size() * sizeof(int)));
+        HIPCHK(ctx, up(d.ulev, ctx->ulev.data(), ctx->ulev.size() * sizeof(int)));
+        if (g.unbf > 0) {
+            HIPCHK(ctx, up(d.ubf_cell, ctx->ubf_cell.data(), ctx->ubf_cell.size() * sizeof(int)));
+            HIPCHK(ctx, up(d.ubf_slot, ctx->ubf_slot.data(), ctx->ubf_slot.size() * sizeof(int)));
+            HIPCHK(ctx, up(d.ubf_n, ctx->ubf_n.data(), ctx->ubf_n.size() * sizeof(double)));
+        }
+    }
     HIPCHK(ctx, upload_tiles(ctx));
     HIPCHK(ctx, hipMemset(d.errflag, 0, 4 * sizeof(int)));
     HIPCHK(ctx, hipMemset(d.dmax, 0, (size_t)2 * DSLOT * DSTRIDE * sizeof(unsigned long long)));
@@ -831,6 +1091,22 @@ gsis_status gsis_kinetic_step(gsis_ctx *ctx, int npasses)
             if (st) return st;
         }
         PhaseTimer t0, t1, t2, t3;
+        if (g.umesh) {
+            HIPCHK(ctx, t0.start(ctx, GSIS_PHASE_PREP));
+            HIPCHK(ctx, launch_params(t, ctx->stream));
+            HIPCHK(ctx, launch_uface_scale(t, ctx->stream));
+            HIPCHK(ctx, t0.stop());
+            HIPCHK(ctx, t1.start(ctx, GSIS_PHASE_SWEEP));
+            HIPCHK(ctx, launch_usweep(t, ctx->ulev_off.data(), (int)ctx->ulev_off.size() - 1, ctx->stream));
+            HIPCHK(ctx, t1.stop());
+            HIPCHK(ctx, t2.start(ctx, GSIS_PHASE_MOMENTS));
+            gsis_status st = reduce_vdf(ctx);
+            if (st) return st;
+            HIPCHK(ctx, t2.stop());
+            ctx->passes++;
+            ctx->stepped = true;
+            continue;
+        }
         HIPCHK(ctx, t0.start(ctx, GSIS_PHASE_PREP));
         HIPCHK(ctx, launch_params(t, ctx->stream));
         HIPCHK(ctx, launch_face_scale(t, ctx->stream));
@@ -870,6 +1146,7 @@ gsis_status gsis_moments(gsis_ctx *ctx, double *out, int out_is_device)
 gsis_status gsis_gsis_correct(gsis_ctx *ctx, int inner_iters)
 {
     if (!ctx) return GSIS_EINVAL;
+    if (ctx->g.umesh) return fail(ctx, GSIS_ESTATE, "the macroscopic correction is built for the box of hex cells; an unstructured mesh runs kinetic passes");
     if (!ctx->inited || !ctx->stepped) return fail(ctx, GSIS_ESTATE, "gsis_correct needs a kinetic step since init");
     if (inner_iters < 0) return fail(ctx, GSIS_EINVAL, "inner_iters must be >= 0");
     gsis_status st = materialize(ctx);
@@ -888,6 +1165,7 @@ gsis_status gsis_gsis_correct(gsis_ctx *ctx, int inner_iters)
 gsis_status gsis_precondition(gsis_ctx *ctx, int macro_steps, int kinetic_steps)
 {
     if (!ctx) return GSIS_EINVAL;
+    if (ctx->g.umesh) return fail(ctx, GSIS_ESTATE, "the macroscopic correction is built for the box of hex cells; an unstructured mesh runs kinetic passes");
     if (!ctx->inited) return fail(ctx, GSIS_ESTATE, "initialise the VDF first");
     if (macro_steps < 0 || kinetic_steps < 0) return fail(ctx, GSIS_EINVAL, "steps must be >= 0");
     gsis_status st = materialize(ctx);
@@ -1045,6 +1323,7 @@ gsis_status gsis_set_state(gsis_ctx *ctx, const void *src_device)
 gsis_status gsis_set_tile(gsis_ctx *ctx, int tx, int ty, int tz, int block)
 {
     if (!ctx) return GSIS_EINVAL;
+    if (ctx->g.umesh) return fail(ctx, GSIS_ESTATE, "an unstructured mesh has no sweep tiles");
     if (tx == 0 && ty == 0 && tz == 0 && block == 0) {
         default_tile(ctx);
     } else {
@@ -1066,6 +1345,7 @@ gsis_status gsis_set_tile(gsis_ctx *ctx, int tx, int ty, int tz, int block)
 gsis_status gsis_autotune(gsis_ctx *ctx, int reps, int *cfg_out, double *ms_out, int max, int *count)
 {
     if (!ctx) return GSIS_EINVAL;
+    if (ctx->g.umesh) return fail(ctx, GSIS_ESTATE, "an unstructured mesh has no sweep tiles to tune");
     if (!ctx->inited) return fail(ctx, GSIS_ESTATE, "initialise the VDF first");
     if (reps < 1 || max < 0) return fail(ctx, GSIS_EINVAL, "reps must be >= 1");
     if (ctx->g.inv_dt != 0.0 || ctx->g.order != 1)
@@ -1462,7 +1742,7 @@ gsis_status gsis_batch_create(gsis_batch **out, gsis_ctx *const *cases, int ncas
         for (int j = 0; j < i; ++j)
             if (cases[j] == c) return GSIS_EINVAL;
         if (c->fp32 != cases[0]->fp32 || c->g.species != cases[0]->g.species) return GSIS_EINVAL;
-        if (c->g.inv_dt != 0.0 || c->g.order != 1 || c->g.vlist) return GSIS_EINVAL;
+        if (c->g.inv_dt != 0.0 || c->g.order != 1 || c->g.vlist || c->g.umesh) return GSIS_EINVAL;
     }
     gsis_batch *b = new (std::nothrow) gsis_batch();
     if (!b) return GSIS_ENOMEM;

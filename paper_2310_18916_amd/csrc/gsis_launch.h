@@ -57,6 +57,10 @@ bool sweep_shape_supported(bool fp32, bool dia, int tx, int ty);
 int sweep_shape_waves(bool fp32, int tx, int ty);
 int sweep_shapes(bool fp32, int *out, int max);
 hipError_t launch_sweep(const Target &t, hipStream_t s);
+// unstructured mesh: boundary-face density scales, then the sweep level by level
+// (lev_off[L] .. lev_off[L + 1] are the entries of level L)
+hipError_t launch_uface_scale(const Target &t, hipStream_t s);
+hipError_t launch_usweep(const Target &t, const int *lev_off, int nlev, hipStream_t s);
 
 // euler != 0: the Euler constitutive relations (no stress, heat flux, HoT or
 // diffusive pseudo-time terms) and the iterate's own boundary flux

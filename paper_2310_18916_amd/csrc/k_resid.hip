@@ -1,6 +1,7 @@
 // Convergence criterion of Sec. 5, Eq. (convergence_critertion): volume-weighted relative L2 change of
-// rho, u (as a vector) and Tt between two states; uniform cells, so the
-// weights cancel.  Two-stage fixed-order reduction (deterministic).
+// rho, u (as a vector) and Tt between two states; uniform hex cells weigh 1
+// (the weights cancel), cells of an unstructured mesh their volume.
+// Two-stage fixed-order reduction (deterministic).
 #include "gsis_common.h"
 #include "gsis_launch.h"
 
@@ -35,6 +36,10 @@ __global__ __launch_bounds__(256) void k_resid_partial(GSIS_SPAN_ARGS, double *r
         }
         v[2] = dT * dT;
         v[5] = p[4] * p[4];
+        if (d.uvol) {
+            const double V = d.uvol[cell];
+            for (int k = 0; k < 6; ++k) v[k] *= V;
+        }
     }
     __shared__ double sh[6][256];
     for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = v[k];

@@ -24,6 +24,8 @@ class GsisError(RuntimeError):
 def make_config(case: Case, dtype: str = "fp64") -> _lib.Config:
     c = _lib.Config()
     c.nx, c.ny, c.nz = case.nx, case.ny, case.nz
+    if case.mesh is not None:      # the box is replaced by gsis_set_spatial_mesh
+        c.nx = c.ny = c.nz = 1
     c.lx, c.ly, c.lz = case.lx, case.ly, case.lz
     c.nvx, c.nvy, c.nvz = case.nv
     for a in range(3):
@@ -86,6 +88,14 @@ class Context:
             self._vlist = t
             self._check(self.L.gsis_set_velocity_list(self.h, t.ctypes.data_as(C.c_void_p), t.shape[0]),
                         "gsis_set_velocity_list")
+        if case.mesh is not None:
+            m = case.mesh
+            vol = np.ascontiguousarray(m.volume, dtype=np.float64)
+            fc = np.ascontiguousarray(m.face_cell, dtype=np.int32)
+            fg = np.ascontiguousarray(m.face_geom, dtype=np.float64)
+            self._check(self.L.gsis_set_spatial_mesh(self.h, vol.size, vol.ctypes.data_as(C.c_void_p), fc.shape[0],
+                                                     fc.ctypes.data_as(C.c_void_p), fg.ctypes.data_as(C.c_void_p)),
+                        "gsis_set_spatial_mesh")
 
     def _check(self, st: int, where: str):
         if st:
