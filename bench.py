@@ -32,10 +32,12 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c3r", "c4", "c5"],
+    p.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c3r", "c3t", "c4", "c5"],
                    help="headline workload (c5 runs only the 64-cavity batch)")
     p.add_argument("--no-gsis-extras", action="store_true",
                    help="skip the c2 GSIS step, convergence and second-order runs beside a c3/c4 headline")
+    p.add_argument("--no-umesh", action="store_true",
+                   help="skip the block flow on the tetrahedral spatial mesh beside a c3 headline")
     p.add_argument("--no-refined", action="store_true",
                    help="skip the passes of the block flow on the refined velocity mesh beside a c3 headline")
     p.add_argument("--dtype", default=None, choices=["fp64", "fp32"])
@@ -87,7 +89,7 @@ def sweep_traffic(dtype, tile, workload_name):
 
 def workload(name):
     from paper_2310_18916_amd import inputs as I
-    return {"c1": I.c1, "c2": I.c2, "c3": I.c3, "c3r": I.c3r, "c4": I.c4}[name]()
+    return {"c1": I.c1, "c2": I.c2, "c3": I.c3, "c3r": I.c3r, "c3t": I.c3t, "c4": I.c4}[name]()
 
 
 def run_gpu(case, dtype, steps, warmup, macro_iters, tile):
@@ -96,7 +98,7 @@ def run_gpu(case, dtype, steps, warmup, macro_iters, tile):
     s = Solver(case, dtype, tile=tile)
     s.init_maxwellian()
     tune = None
-    if tile is None and case.inv_dt == 0.0:
+    if tile is None and case.inv_dt == 0.0 and case.mesh is None:
         tune = sorted(s.autotune(reps=2), key=lambda r: r[1])   # untimed set-up: one pass
 
     def step():
@@ -415,6 +417,31 @@ def refined_mesh(steps, warmup):
     return res
 
 
+def unstructured_mesh(steps, warmup):
+    """Kinetic passes of the block flow on an unstructured spatial mesh (291,840
+    tetrahedra, the refined velocity mesh of c3r): the level-by-level sweep
+    over velocity classes, FP64 and FP32, with the phase times and the
+    sweep's and moments' HBM rates (algorithmic bytes: every point written
+    once by the sweep and read once by the moment kernel)."""
+    import torch
+    case = workload("c3t")
+    pts = case.nfluid * case.nvel
+    res = {"workload": case.name, "cells": case.mesh.ncell, "faces": case.mesh.nface, "nodes": case.nvel}
+    for dtype in ("fp64", "fp32"):
+        r = run_gpu(case, dtype, steps, warmup, 0, None)
+        esz = 8 if dtype == "fp64" else 4
+        prof = r["prof"]
+        sweep_ms, n = prof["sweep"]
+        mom_ms, _ = prof["moments"]
+        res[dtype] = {"value": pts * steps / r["seconds"], "ms_per_pass": r["seconds"] / steps * 1e3,
+                      "phases_ms_per_pass": {k: v[0] / steps for k, v in prof.items() if v[1]},
+                      "sweep_gbs": pts * esz / (sweep_ms / n * 1e-3) / 1e9,
+                      "moments_gbs": pts * esz / (mom_ms / n * 1e-3) / 1e9}
+        del r
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -518,6 +545,8 @@ def main():
         out["gsis_c2"] = gsis_extras(a, steps, a.warmup)
     if a.workload == "c3" and not a.no_refined:
         out["refined_velocity_mesh"] = refined_mesh(max(3, steps // 4), 2)
+    if a.workload == "c3" and not a.no_umesh:
+        out["unstructured_mesh"] = unstructured_mesh(max(3, steps // 4), 2)
     if not a.no_batch:
         out["batched"] = batched(a.batch_iters)
     if a.copy_calib_mib > 0:

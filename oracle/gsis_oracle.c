@@ -685,16 +685,15 @@ static void uface_of(const orc_state *s, int i, int e, double n[3], double *sv, 
 }
 
 /* Density scale of the incoming half of boundary face f (unit normal n out
- * of its cell): diffuse wall rho_w = sum_{xi.n>0} w xi.n f0 /
+ * of its cell) from the f0 row of its cell: diffuse wall rho_w = sum_{xi.n>0} w xi.n f0 /
  * sum_{xi.n<0} w |xi.n| M(1,u_w,T_w) (zero discrete mass flux through the
  * wall), inflow the fixed density. */
-static double uface_scale(const orc_state *s, int f)
+static double uface_scale_row(const orc_state *s, int f, const double *f0)
 {
     const orc_cfg *c = &s->c;
-    int cell = s->ufc[2 * f], bc = -1 - s->ufc[2 * f + 1];
+    int bc = -1 - s->ufc[2 * f + 1];
     if (c->bc_kind[bc] == ORC_INFLOW) return c->bc_rho[bc];
     const double *g = s->ufg + (size_t)f * 4;
-    const double *f0 = s->f0 + (size_t)cell * s->nv;
     nsum out = {0, 0}, in = {0, 0};
     for (int v = 0; v < s->nv; ++v) {
         double xi[3], w;
@@ -704,6 +703,11 @@ static double uface_scale(const orc_state *s, int f)
         else if (xn < 0) nadd(&in, w * (-xn) * s->mbw[(size_t)bc * s->nv + v]);
     }
     return nval(&out) / nval(&in);
+}
+
+static double uface_scale(const orc_state *s, int f)
+{
+    return uface_scale_row(s, f, s->f0 + (size_t)s->ufc[2 * f] * s->nv);
 }
 
 /* The kinetic update of node v on an unstructured mesh: Eq.
@@ -1053,6 +1057,53 @@ static int one_pass(orc_state *s)
     return s->status;
 }
 
+/* orc_first_pass_nodes on an unstructured mesh: every cell holds the same
+ * f^n, so one cell's parameters serve all cells and each boundary face's wall
+ * density comes from that one row; nodes swept as in one_pass_umesh. */
+static int first_pass_nodes_umesh(const orc_cfg *cfg, double rho, const double u[3], double T, double Tr,
+                                  const int *nodes, int nn, double *out0, double *out1)
+{
+    orc_cfg one = *cfg;
+    one.ucells = one.ufaces = 0;
+    one.uvol = NULL; one.uface_cell = NULL; one.uface_geom = NULL;
+    one.nx = one.ny = one.nz = 1;
+    one.lx = one.ly = one.lz = 1.0;
+    orc_state *s1 = create_state(&one, NULL, 1);
+    orc_state *s = create_state(cfg, NULL, 0);
+    if (!s1 || !s) { orc_free(s1); orc_free(s); return -3; }
+    orc_init_maxwellian(s1, rho, u, T, Tr);
+    cellpar p1;
+    cell_params(s1, 0, &p1);
+    int status = (!isfinite(p1.invtau) || !(p1.m.rho > 0) || !(p1.m.Tt > 0)) ? -5 : 0;
+    int ncell = s->ncell, dia = cfg->species == 1;
+    cellpar *P = malloc(sizeof(cellpar) * (size_t)ncell);
+    double *bscale = calloc((size_t)s->nface, sizeof(double));
+    for (int cell = 0; cell < ncell; ++cell) P[cell] = p1;
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int f = 0; f < s->nface; ++f)
+        if (s->ufc[2 * f + 1] < 0) bscale[f] = uface_scale_row(s, f, s1->f0);
+    #pragma omp parallel
+    {
+        int *indeg = malloc(sizeof(int) * (size_t)ncell), *queue = malloc(sizeof(int) * (size_t)ncell);
+        #pragma omp for schedule(dynamic, 1)
+        for (int k = 0; k < nn; ++k) {
+            double *col0 = out0 + (size_t)k * ncell;
+            double *col1 = dia ? out1 + (size_t)k * ncell : NULL;
+            for (int cell = 0; cell < ncell; ++cell) {
+                col0[cell] = s1->f0[nodes[k]];
+                if (dia) col1[cell] = s1->f1[nodes[k]];
+            }
+            usweep_node(s, nodes[k], P, bscale, col0, col1, indeg, queue);
+        }
+        free(indeg); free(queue);
+    }
+    if (s->status) status = s->status;
+    free(P); free(bscale);
+    orc_free(s1);
+    orc_free(s);
+    return status;
+}
+
 /* The first pass from a uniform Maxwellian at selected nodes only, for
  * problems too large to hold the VDF: every fluid cell then has the same
  * f^n, so one cell's parameters and its wall densities (per face direction
@@ -1062,7 +1113,7 @@ static int one_pass(orc_state *s)
 int orc_first_pass_nodes(const orc_cfg *cfg, const unsigned char *solid, double rho, const double u[3], double T,
                          double Tr, const int *nodes, int nn, double *out0, double *out1)
 {
-    if (cfg->ucells > 0) return -2;
+    if (cfg->ucells > 0) return first_pass_nodes_umesh(cfg, rho, u, T, Tr, nodes, nn, out0, out1);
     orc_cfg one = *cfg;
     one.nx = one.ny = one.nz = 1;
     orc_state *s1 = create_state(&one, NULL, 1);

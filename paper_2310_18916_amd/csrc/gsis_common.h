@@ -59,6 +59,8 @@ struct Geo {
     // orientation n_k of the mesh, so that they share one upwind order), unbf
     // boundary faces, nori orientations
     int umesh, ucls, unbf, nori;
+    int umaxcnt;   // nodes of the largest class
+    int umaxf;     // faces of the cell with the most
 };
 
 struct BcInfo {
@@ -108,23 +110,22 @@ struct Dev {
     int *plane_off;    // [nplane] first tile of each plane in tiles
     int *tent;         // [8 * tiles] (tile in plane << 3 | octant) entries of a split sweep: plane p's
                        // entries start at 8 plane_off[p], those without solid cells first
-    // unstructured spatial mesh (null otherwise).  Cell i's faces are entries
-    // ucf_off[i] .. ucf_off[i + 1] of: ucf_nb the cell on the other side, or
-    // -1 - b for boundary face b; ucf_meta = k | s << 5 | slot << 6 with n_k
-    // the face's orientation, s = 1 when the normal out of cell i is -n_k, and
-    // the boundary slot; ucf_c* = S / V_i.  Orientations uori* [UMAXORI][4];
-    // classes ucls[c] = (sign mask: bit k set when xi . n_k >= 0, first
-    // position in a VDF row, node count, 0); ulev the sweep entries
-    // (cell << 8 | class) level after level; boundary face b: its cell, slot,
-    // unit normal out of the cell ([4] per face) and incoming density scale.
+    // unstructured spatial mesh (null otherwise).  Face entries of every cell,
+    // cell i's from the first face entry given with its sweep entries: ucf_nb
+    // the cell on the other side, or -1 - b for boundary face b; ucf_meta = k |
+    // s << 5 | slot << 6 with n_k the face's orientation, s = 1 when the
+    // normal out of the cell is -n_k, and the boundary slot; ucf_g* [4] =
+    // (S / V_i, unit normal out of the cell).  Classes ucls[c] = (sign mask:
+    // bit k set when xi . n_k >= 0, first position in a VDF row, node count,
+    // 0); ulev the sweep entries level after level, (cell << 8 | class, first
+    // face entry << 5 | face count); boundary face b: its cell, slot, unit
+    // normal out of the cell ([4] per face) and incoming density scale.
     double *uvol;      // [ncell] cell volumes (residual weights)
-    int *ucf_off, *ucf_nb, *ucf_meta;
-    double *ucf_c64;
-    float *ucf_c32;
-    double *uori64;
-    float *uori32;
+    int *ucf_nb, *ucf_meta;
+    double *ucf_g64;
+    float *ucf_g32;
     int4 *ucls;
-    int *ulev;
+    int2 *ulev;
     int *ubf_cell, *ubf_slot;
     double *ubf_n;
     double *ubf_s64;

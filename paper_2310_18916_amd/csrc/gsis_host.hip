@@ -27,8 +27,8 @@ struct gsis_ctx {
     std::vector<double> vlist;   // node list [nv][4] in the caller's order (list mode)
     // unstructured spatial mesh (g.umesh): what the sweep needs, built when the
     // mesh is set (see Dev for the meaning of each array)
-    std::vector<double> uvol, ucf_c, uori, ubf_n;
-    std::vector<int> ucf_off, ucf_nb, ucf_meta, ulev, ulev_off, ubf_cell, ubf_slot, uperm, ucls;
+    std::vector<double> uvol, ucf_g, ubf_n;
+    std::vector<int> ucf_nb, ucf_meta, ulev, ulev_off, ubf_cell, ubf_slot, uperm, ucls;   // ulev: 2 ints per entry
     int tx = 0, ty = 0, tz = 0, bs = 0;
     std::vector<int> tiles, plane_off, plane_cnt, npblk;
     std::vector<int> tent, nclean;   // split sweep entries (cases with solid cells)
@@ -329,21 +329,18 @@ size_t layout(gsis_ctx *c, char *base)
     Case *dc = nullptr;
     carve(off, dc, 1, base);
     if (base) c->dcase = dc;
-    d.uvol = nullptr; d.ucf_off = d.ucf_nb = d.ucf_meta = nullptr; d.ucf_c64 = nullptr; d.ucf_c32 = nullptr;
-    d.uori64 = nullptr; d.uori32 = nullptr; d.ucls = nullptr; d.ulev = nullptr;
+    d.uvol = nullptr; d.ucf_nb = d.ucf_meta = nullptr; d.ucf_g64 = nullptr; d.ucf_g32 = nullptr;
+    d.ucls = nullptr; d.ulev = nullptr;
     d.ubf_cell = d.ubf_slot = nullptr; d.ubf_n = nullptr; d.ubf_s64 = nullptr; d.ubf_s32 = nullptr;
     if (g.umesh) {
         const size_t ne = c->ucf_nb.size(), nb = std::max(g.unbf, 1);
         carve(off, d.uvol, n, base);
-        carve(off, d.ucf_off, n + 1, base);
         carve(off, d.ucf_nb, ne, base);
         carve(off, d.ucf_meta, ne, base);
-        carve(off, d.ucf_c64, ne, base);
-        carve(off, d.ucf_c32, ne, base);
-        carve(off, d.uori64, (size_t)UMAXORI * 4, base);
-        carve(off, d.uori32, (size_t)UMAXORI * 4, base);
+        carve(off, d.ucf_g64, ne * 4, base);
+        carve(off, d.ucf_g32, ne * 4, base);
         carve(off, d.ucls, (size_t)g.ucls, base);
-        carve(off, d.ulev, c->ulev.size(), base);
+        carve(off, d.ulev, c->ulev.size() / 2, base);
         carve(off, d.ubf_cell, nb, base);
         carve(off, d.ubf_slot, nb, base);
         carve(off, d.ubf_n, nb * 4, base);
@@ -797,6 +794,8 @@ gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume
     for (int c = 0; c < ncls; ++c) cls_of[masks[c]] = c;
     std::vector<int> cnt(ncls, 0);
     for (int v = 0; v < nv; ++v) ++cnt[cls_of[nmask[v]]];
+    if (*std::max_element(cnt.begin(), cnt.end()) > 65535 * 256)
+        return fail(ctx, GSIS_EINVAL, "more than 65535 x 256 nodes in one velocity class");
     std::vector<int> cpos(ncls + 1, 0);
     for (int c = 0; c < ncls; ++c) cpos[c + 1] = cpos[c] + cnt[c];
     std::vector<int> perm(nv), at(cpos.begin(), cpos.end() - 1);
@@ -804,8 +803,9 @@ gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume
     // faces of every cell in input order (the owner's entry, then the neighbour's)
     std::vector<int> off(ncell + 1, 0);
     for (int i = 0; i < ncell; ++i) off[i + 1] = off[i] + nfc[i];
+    if (off[ncell] >= (1 << 26)) return fail(ctx, GSIS_EINVAL, "at most 2^26 - 1 face entries (two per interior face)");
     std::vector<int> cnb(off[ncell]), cmeta(off[ncell]), pos(off.begin(), off.end() - 1);
-    std::vector<double> ccoef(off[ncell]);
+    std::vector<double> cgeo((size_t)off[ncell] * 4);
     std::vector<int> bcell, bslot;
     std::vector<double> bn;
     for (int f = 0; f < nface; ++f) {
@@ -823,12 +823,14 @@ gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume
         int e = pos[o]++;
         cnb[e] = other;
         cmeta[e] = fk[f] | fflip[f] << 5 | slot << 6;
-        ccoef[e] = gg[0] / volume[o];
+        cgeo[4 * (size_t)e] = gg[0] / volume[o];
+        for (int a = 0; a < 3; ++a) cgeo[4 * (size_t)e + 1 + a] = gg[1 + a];
         if (nb >= 0) {
             e = pos[nb]++;
             cnb[e] = o;
             cmeta[e] = fk[f] | (fflip[f] ^ 1) << 5;
-            ccoef[e] = gg[0] / volume[nb];
+            cgeo[4 * (size_t)e] = gg[0] / volume[nb];
+            for (int a = 0; a < 3; ++a) cgeo[4 * (size_t)e + 1 + a] = -gg[1 + a];
         }
     }
     // per class: the levels of its upwind graph (Kahn); then the sweep
@@ -870,22 +872,25 @@ gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume
     for (int c = 0; c < ncls; ++c)
         for (int i = 0; i < ncell; ++i) ++lcount[lev[c][i] + 1];
     for (int L = 0; L < nlev; ++L) lcount[L + 1] += lcount[L];
-    std::vector<int> ent(lcount[nlev]), lat(lcount.begin(), lcount.end() - 1);
+    std::vector<int> key(lcount[nlev]), lat(lcount.begin(), lcount.end() - 1);
     for (int c = 0; c < ncls; ++c)
-        for (int i = 0; i < ncell; ++i) ent[lat[lev[c][i]]++] = i << 8 | c;
+        for (int i = 0; i < ncell; ++i) key[lat[lev[c][i]]++] = i << 8 | c;
     for (int L = 0; L < nlev; ++L)   // within a level: class by class, cells ascending
-        std::sort(ent.begin() + lcount[L], ent.begin() + lcount[L + 1], [](int x, int y) {
+        std::sort(key.begin() + lcount[L], key.begin() + lcount[L + 1], [](int x, int y) {
             return (x & 255) != (y & 255) ? (x & 255) < (y & 255) : x < y;
         });
+    std::vector<int> ent((size_t)lcount[nlev] * 2);
+    for (size_t k = 0; k < key.size(); ++k) {
+        const int i = key[k] >> 8;
+        ent[2 * k] = key[k];
+        ent[2 * k + 1] = off[i] << 5 | nfc[i];
+    }
     // commit
     Geo &g = ctx->g;
     ctx->uvol.assign(volume, volume + ncell);
-    ctx->ucf_off = off;
     ctx->ucf_nb = cnb;
     ctx->ucf_meta = cmeta;
-    ctx->ucf_c = ccoef;
-    ctx->uori.assign((size_t)UMAXORI * 4, 0.0);
-    std::copy(ori.begin(), ori.end(), ctx->uori.begin());
+    ctx->ucf_g = cgeo;
     ctx->ucls.assign((size_t)ncls * 4, 0);
     for (int c = 0; c < ncls; ++c) {
         ctx->ucls[4 * c] = (int)masks[c];
@@ -902,6 +907,8 @@ gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume
     g.ucls = ncls;
     g.unbf = (int)bcell.size();
     g.nori = nori;
+    g.umaxcnt = *std::max_element(cnt.begin(), cnt.end());
+    g.umaxf = *std::max_element(nfc.begin(), nfc.end());
     g.nx = ncell;
     g.ny = g.nz = 1;
     g.ncell = ncell;
@@ -1024,15 +1031,12 @@ gsis_status gsis_bind_workspace(gsis_ctx *ctx, void *device_ptr, size_t bytes)
     }
     HIPCHK(ctx, up(d.perm, ctx->perm.data(), ctx->perm.size() * sizeof(int)));
     if (g.umesh) {
-        std::vector<float> c32(ctx->ucf_c.begin(), ctx->ucf_c.end()), o32(ctx->uori.begin(), ctx->uori.end());
+        std::vector<float> g32(ctx->ucf_g.begin(), ctx->ucf_g.end());
         HIPCHK(ctx, up(d.uvol, ctx->uvol.data(), ctx->uvol.size() * sizeof(double)));
-        HIPCHK(ctx, up(d.ucf_off, ctx->ucf_off.data(), ctx->ucf_off.size() * sizeof(int)));
         HIPCHK(ctx, up(d.ucf_nb, ctx->ucf_nb.data(), ctx->ucf_nb.size() * sizeof(int)));
         HIPCHK(ctx, up(d.ucf_meta, ctx->ucf_meta.data(), ctx->ucf_meta.size() * sizeof(int)));
-        HIPCHK(ctx, up(d.ucf_c64, ctx->ucf_c.data(), ctx->ucf_c.size() * sizeof(double)));
-        HIPCHK(ctx, up(d.ucf_c32, c32.data(), c32.size() * sizeof(float)));
-        HIPCHK(ctx, up(d.uori64, ctx->uori.data(), ctx->uori.size() * sizeof(double)));
-        HIPCHK(ctx, up(d.uori32, o32.data(), o32.size() * sizeof(float)));
+        HIPCHK(ctx, up(d.ucf_g64, ctx->ucf_g.data(), ctx->ucf_g.size() * sizeof(double)));
+        HIPCHK(ctx, up(d.ucf_g32, g32.data(), g32.size() * sizeof(float)));
         HIPCHK(ctx, up(d.ucls, ctx->ucls.data(), ctx->ucls.size() * sizeof(int)));
         HIPCHK(ctx, up(d.ulev, ctx->ulev.data(), ctx->ulev.size() * sizeof(int)));
         if (g.unbf > 0) {

@@ -63,8 +63,12 @@ __global__ __launch_bounds__(256) void k_uface_scale(GSIS_SPAN_ARGS)
     }
 }
 
-// Sweep entries [e0, e1) of one level: entry (cell << 8 | class), one wave each.
-template <typename T, bool DIA>
+// Sweep entries [e0, e1) of one level, one wave each: entry (cell << 8 |
+// class, first face entry << 5 | face count).  The wave walks the class's
+// nodes 64 at a time; the loads of the next 64 (inflow values and node
+// velocities) are issued before the current 64 are computed, so a wave keeps
+// two rounds of memory traffic in flight.  MAXF bounds the faces of a cell.
+template <typename T, bool DIA, int MAXF>
 __global__ __launch_bounds__(256) void k_usweep(GSIS_SPAN_ARGS, int e0, int e1)
 {
 #pragma clang fp contract(off)
@@ -76,8 +80,9 @@ __global__ __launch_bounds__(256) void k_usweep(GSIS_SPAN_ARGS, int e0, int e1)
     const int e = __builtin_amdgcn_readfirstlane(e0 + b * 4 + (int)(threadIdx.x >> 6));
     if (e >= e1) return;   // uniform over the wave
     const int lane = threadIdx.x & 63;
-    const int ent = ((cptr<int>)C.d.ulev)[e];
-    const int cell = ent >> 8, cls = ent & 255;
+    const cptr<int> ent = (cptr<int>)(C.d.ulev + e);
+    const int cell = ent[0] >> 8, cls = ent[0] & 255;
+    const int fb = ent[1] >> 5, nf = ent[1] & 31;
     const cptr<int> cl = (cptr<int>)(C.d.ucls + cls);
     const unsigned mask = (unsigned)cl[0];
     const int pos0 = cl[1], cnt = cl[2];
@@ -85,12 +90,9 @@ __global__ __launch_bounds__(256) void k_usweep(GSIS_SPAN_ARGS, int e0, int e1)
     T p[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) p[k] = par[k];
-    const cptr<int> coff = (cptr<int>)C.d.ucf_off;
-    const int fb = coff[cell], nf = coff[cell + 1] - fb;
     const cptr<int> cnb = (cptr<int>)C.d.ucf_nb + fb;
     const cptr<int> cmeta = (cptr<int>)C.d.ucf_meta + fb;
-    const cptr<T> ccoef = (F32 ? (cptr<T>)C.d.ucf_c32 : (cptr<T>)C.d.ucf_c64) + fb;
-    const cptr<T> ori = F32 ? (cptr<T>)C.d.uori32 : (cptr<T>)C.d.uori64;
+    const cptr<T> cgeo = (F32 ? (cptr<T>)C.d.ucf_g32 : (cptr<T>)C.d.ucf_g64) + 4 * (size_t)fb;
     const cptr<T> bsc = F32 ? (cptr<T>)C.d.ubf_s32 : (cptr<T>)C.d.ubf_s64;
     const gptr<const T> nt = F32 ? (gptr<const T>)C.d.nt32 : (gptr<const T>)C.d.nt64;
     const gptr<const T> mb = F32 ? (gptr<const T>)C.d.mb32 : (gptr<const T>)C.d.mb64;
@@ -98,81 +100,92 @@ __global__ __launch_bounds__(256) void k_usweep(GSIS_SPAN_ARGS, int e0, int e1)
     const size_t nv = (size_t)g.nv;
     const gptr<T> f0 = (gptr<T>)C.d.f0, f1 = (gptr<T>)C.d.f1;
     const T idt = (T)g.inv_dt;
+    const bool fdt = g.inv_dt != 0.0;
     const T invtau = DIA ? p[33] : p[13];
 
-    // the faces of the cell: which bring the class's nodes in, and from where
-    int src[UMAXF];      // cell row of an interior inflow face, or -1 - boundary face
-    bool in[UMAXF];
-    T on[UMAXF][3], cf[UMAXF];
+    // the faces of the cell: which bring the class's nodes in, from where, and
+    // their (S / V, unit normal out of the cell)
+    int src[MAXF];       // cell row of an interior inflow face, or -1 - boundary face
+    int slot[MAXF];
+    bool in[MAXF];
+    T geo[MAXF][4];
 #pragma unroll
-    for (int j = 0; j < UMAXF; ++j) {
+    for (int j = 0; j < MAXF; ++j) {
         if (j < nf) {
-            const int meta = cmeta[j], k = meta & 31;
+            const int meta = cmeta[j];
             const bool flip = (meta >> 5) & 1;
-            in[j] = (((mask >> k) & 1u) != 0) == flip;   // xi . n out of the cell < 0 for the class
+            in[j] = (((mask >> (meta & 31)) & 1u) != 0) == flip;   // xi . n out of the cell < 0 for the class
             src[j] = cnb[j];
-            on[j][0] = ori[4 * k];
-            on[j][1] = ori[4 * k + 1];
-            on[j][2] = ori[4 * k + 2];
-            cf[j] = ccoef[j];
+            slot[j] = (meta >> 6) & 7;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) geo[j][q] = cgeo[4 * j + q];
         } else {
             in[j] = false;
             src[j] = 0;
-            on[j][0] = on[j][1] = on[j][2] = cf[j] = T(0);
+            slot[j] = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) geo[j][q] = T(0);
         }
     }
-    for (int l0 = 0; l0 < cnt; l0 += 64) {
-        const int l = l0 + lane;
-        const bool active = l < cnt;
-        const size_t pos = (size_t)pos0 + (active ? l : 0);
-        const T xix = nt[4 * pos], xiy = nt[4 * pos + 1], xiz = nt[4 * pos + 2];
-        // the inflow values first (independent loads), then the arithmetic
-        T F0[UMAXF], F1[UMAXF];
+    // the loads of one run of 64 nodes: velocities, inflow values, f^n of the cell (finite dt)
+    struct Run { T x, y, z, o0, o1, F0[MAXF], F1[MAXF]; };
+    auto load = [&](int l0, Run &r) {
+        const int l = min(l0 + lane, cnt - 1);
+        const size_t pos = (size_t)pos0 + l;
+        r.x = nt[4 * pos];
+        r.y = nt[4 * pos + 1];
+        r.z = nt[4 * pos + 2];
 #pragma unroll
-        for (int j = 0; j < UMAXF; ++j) {
-            F0[j] = F1[j] = T(0);
+        for (int j = 0; j < MAXF; ++j) {
+            r.F0[j] = r.F1[j] = T(0);
             if (j < nf && in[j]) {
                 if (src[j] >= 0) {
-                    F0[j] = f0[(size_t)src[j] * nv + pos];
-                    if (DIA) F1[j] = f1[(size_t)src[j] * nv + pos];
+                    r.F0[j] = f0[(size_t)src[j] * nv + pos];
+                    if (DIA) r.F1[j] = f1[(size_t)src[j] * nv + pos];
                 } else {
-                    const int bfi = -1 - src[j];
-                    const int slot = (cmeta[j] >> 6) & 7;
-                    const T sc = bsc[bfi];
-                    F0[j] = sc * mb[(size_t)slot * nv + pos];
-                    if (DIA) F1[j] = sc * mb1[(size_t)slot * nv + pos];
+                    const T sc = bsc[-1 - src[j]];
+                    r.F0[j] = sc * mb[(size_t)slot[j] * nv + pos];
+                    if (DIA) r.F1[j] = sc * mb1[(size_t)slot[j] * nv + pos];
                 }
             }
         }
-        T own0 = T(0), own1 = T(0);
-        if (g.inv_dt != 0.0) {
-            own0 = f0[(size_t)cell * nv + pos];
-            if (DIA) own1 = f1[(size_t)cell * nv + pos];
+        r.o0 = r.o1 = T(0);
+        if (fdt) {
+            r.o0 = f0[(size_t)cell * nv + pos];
+            if (DIA) r.o1 = f1[(size_t)cell * nv + pos];
         }
-        const T cx = xix - p[0], cy = xiy - p[1], cz = xiz - p[2];
+    };
+    Run cur, nxt;
+    load(0, cur);
+    for (int l0 = 0; l0 < cnt; l0 += 64) {
+        if (l0 + 64 < cnt) load(l0 + 64, nxt);   // uniform
+        const T cx = cur.x - p[0], cy = cur.y - p[1], cz = cur.z - p[2];
         T num0, num1 = T(0);
         if (DIA) ref_dia<T>(p, cx, cy, cz, p[3], p[4], num0, num1);
         else num0 = ref_mono<T>(p, cx, cy, cz, p[3]);
-        num0 = fma(idt, own0, num0);
-        if (DIA) num1 = fma(idt, own1, num1);
+        num0 = fma(idt, cur.o0, num0);
+        if (DIA) num1 = fma(idt, cur.o1, num1);
         T den = idt + invtau;
 #pragma unroll
-        for (int j = 0; j < UMAXF; ++j) {
+        for (int j = 0; j < MAXF; ++j) {
             if (j < nf) {
-                const T xn = fma(xiz, on[j][2], fma(xiy, on[j][1], xix * on[j][0]));
-                const T a = fabs(xn) * cf[j];
+                const T xn = fma(cur.z, geo[j][3], fma(cur.y, geo[j][2], cur.x * geo[j][1]));
+                const T a = fabs(xn) * geo[j][0];
                 if (in[j]) {
-                    num0 = fma(a, F0[j], num0);
-                    if (DIA) num1 = fma(a, F1[j], num1);
+                    num0 = fma(a, cur.F0[j], num0);
+                    if (DIA) num1 = fma(a, cur.F1[j], num1);
                 } else {
                     den += a;
                 }
             }
         }
-        if (active) {
+        const int l = l0 + lane;
+        if (l < cnt) {
+            const size_t pos = (size_t)pos0 + l;
             f0[(size_t)cell * nv + pos] = Arith<T>::div(num0, den);
             if (DIA) f1[(size_t)cell * nv + pos] = Arith<T>::div(num1, den);
         }
+        cur = nxt;
     }
 }
 
@@ -188,13 +201,22 @@ hipError_t launch_uface_scale(const Target &t, hipStream_t s)
 
 hipError_t launch_usweep(const Target &t, const int *lev_off, int nlev, hipStream_t s)
 {
+    const int mf = t.host->g.umaxf;
     for (int L = 0; L < nlev; ++L) {
         const int e0 = lev_off[L], e1 = lev_off[L + 1];
         if (e1 <= e0) continue;
         const dim3 grid((e1 - e0 + 3) / 4);
-#define GSIS_USWEEP(T, D) hipLaunchKernelGGL((k_usweep<T, D>), grid, dim3(256), 0, s, t.cases, nullptr, e0, e1)
-        if (t.fp32) { if (t.dia) GSIS_USWEEP(float, true); else GSIS_USWEEP(float, false); }
-        else { if (t.dia) GSIS_USWEEP(double, true); else GSIS_USWEEP(double, false); }
+#define GSIS_USWEEP(T, D, M) hipLaunchKernelGGL((k_usweep<T, D, M>), grid, dim3(256), 0, s, t.cases, nullptr, e0, e1)
+#define GSIS_USWEEP_F(T, D) \
+    do { \
+        if (mf <= 4) GSIS_USWEEP(T, D, 4); \
+        else if (mf <= 6) GSIS_USWEEP(T, D, 6); \
+        else if (mf <= 8) GSIS_USWEEP(T, D, 8); \
+        else GSIS_USWEEP(T, D, UMAXF); \
+    } while (0)
+        if (t.fp32) { if (t.dia) GSIS_USWEEP_F(float, true); else GSIS_USWEEP_F(float, false); }
+        else { if (t.dia) GSIS_USWEEP_F(double, true); else GSIS_USWEEP_F(double, false); }
+#undef GSIS_USWEEP_F
 #undef GSIS_USWEEP
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;

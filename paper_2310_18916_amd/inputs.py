@@ -525,3 +525,16 @@ def on_mesh(case: Case, mesh: SpatialMesh, name: Optional[str] = None) -> Case:
     if name:
         c.name = name
     return c
+
+
+def c3t() -> Case:
+    """The Ma = 5 block flow of c3r (Kn = 0.05, the refined velocity mesh of
+    Sec. 3.1, 7788 nodes) on an unstructured spatial mesh: the 48x32x32 lattice
+    of the same box (cubes of twice the c3 cell side), every cube cut into six
+    tetrahedra, the block's 8^3 cubes left out (291,840 tetrahedra; the
+    block's surface is slot 6)."""
+    base = c3r()
+    solid = np.zeros((32, 32, 48), dtype=np.uint8)
+    solid[12:20, 12:20, 20:28] = 1
+    mesh = lattice_mesh(48, 32, 32, base.lx, base.ly, base.lz, split=TET, solid=solid)
+    return on_mesh(base, mesh, name="c3t_block48x32x32_tet_refined7788")

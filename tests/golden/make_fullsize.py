@@ -1,17 +1,19 @@
 """Writes the full-size oracle fields that tests/test_gpu_fullsize_oracle.py
 compares the GPU with: the 48^3 x 32^3 cavity (three GSIS iterations), the
-Mach-5 block flow at 96x64x64 x 40^3 (two source-iteration passes) and the
-nitrogen block flow at 64x48x48 x 32^3 (a GSIS iteration and a pass), each
-from its uniform initial Maxwellian, FP64.
+Mach-5 block flow at 96x64x64 x 40^3 (two source-iteration passes), the
+nitrogen block flow at 64x48x48 x 32^3 (a GSIS iteration and a pass) and the
+Mach-5 block flow on 291,840 tetrahedra with the 7788-node refined velocity
+mesh (two passes), each from its uniform initial Maxwellian, FP64.
 
-Calls only the CPU oracle (its streaming mode, which holds no VDF) and the
-seeded workload definitions.  The files keep, per recorded stage, the moments
+Calls only the CPU oracle (its streaming mode, which holds no VDF; the
+tetrahedral mesh, which the streaming mode does not take, through the
+stored-VDF mode: 18 GB of host memory) and the seeded workload definitions.  The files keep, per recorded stage, the moments
 of a fixed sample of fluid cells (half of them next to a wall, solid or
 inflow face), the largest |value| of every moment over all fluid cells (the
 denominators of the parity norm) and the residual against the previous
 record (the first against the initial state).
 
-    python tests/golden/make_fullsize.py c2 c3 c4     (about an hour on 8 cores)
+    python tests/golden/make_fullsize.py c2 c3 c4 c3t     (about an hour on 8 cores)
 """
 import os
 import sys
@@ -24,7 +26,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-from oracle.oracle import StreamOracle  # noqa: E402
+from oracle.oracle import Oracle, StreamOracle  # noqa: E402
 from paper_2310_18916_amd import inputs as I  # noqa: E402
 
 MACRO_ITERS = 300
@@ -34,16 +36,24 @@ PLANS = {
     "c2": ["pass", "correct", "record", "pass", "correct", "pass", "correct", "record"],
     "c3": ["pass", "record", "pass", "record"],
     "c4": ["pass", "correct", "record", "pass", "record"],
+    "c3t": ["pass", "record", "pass", "record"],
 }
 
 
 def workload(name):
-    return {"c2": I.c2, "c3": I.c3, "c4": I.c4}[name]()
+    return {"c2": I.c2, "c3": I.c3, "c4": I.c4, "c3t": I.c3t}[name]()
 
 
 def sample_cells(case, seed):
     """Fluid cells: NSAMPLE uniform draws and NSAMPLE among cells with a
     boundary (wall, solid or inflow) face, without repeats, sorted."""
+    rng = np.random.default_rng(seed)
+    if case.mesh is not None:
+        fc = case.mesh.face_cell
+        ed = np.unique(fc[fc[:, 1] < 0, 0])
+        a = rng.choice(case.mesh.ncell, size=min(NSAMPLE, case.mesh.ncell), replace=False)
+        b = rng.choice(ed, size=min(NSAMPLE, ed.size), replace=False)
+        return np.unique(np.concatenate([a, b])).astype(np.int64)
     n = (case.nx, case.ny, case.nz)
     solid = case.solid_mask().reshape(n[2], n[1], n[0]).astype(bool)
     fluid = ~solid
@@ -53,7 +63,6 @@ def sample_cells(case, seed):
         for sh in (-1, 1):
             edge |= np.roll(pad, sh, axis=ax)[1:-1, 1:-1, 1:-1]
     edge &= fluid
-    rng = np.random.default_rng(seed)
     fl = np.flatnonzero(fluid.reshape(-1))
     ed = np.flatnonzero(edge.reshape(-1))
     a = rng.choice(fl, size=min(NSAMPLE, fl.size), replace=False)
@@ -65,7 +74,7 @@ def run(name):
     case = workload(name)
     cells = sample_cells(case, seed=2310_18916 + sum(map(ord, name)))
     fluid = ~case.solid_mask().astype(bool)
-    o = StreamOracle(case)
+    o = Oracle(case) if case.mesh is not None else StreamOracle(case)
     o.init_maxwellian()
     o.residual()
     mom, fmax, eps, tags = [], [], [], []

@@ -10,7 +10,9 @@ cells, and the residual (tests/golden/make_fullsize.py):
   (kinetic pass + GSIS-II correction with 300 inner iterations);
 * c3, the Mach-5 block flow at 96x64x64 x 40^3: after one and two passes;
 * c4, the nitrogen block flow at 64x48x48 x 32^3: after a GSIS iteration and
-  after the pass that follows it.
+  after the pass that follows it;
+* c3t, the Mach-5 block flow on 291,840 tetrahedra with the 7788-node refined
+  velocity mesh: after one and two passes (the stored-VDF oracle).
 
 The GPU runs the same plan at full size, its first pass being the
 autotuner's (the launch configuration bench.py uses), in FP64 and FP32.
@@ -57,9 +59,11 @@ def groups(nm):
 
 
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
-@pytest.mark.parametrize("workload", ["c2", "c3", "c4"])
+@pytest.mark.parametrize("workload", ["c2", "c3", "c4", "c3t"])
 def test_full_size_matches_streaming_oracle(workload, dtype):
     path = os.path.join(GOLDEN, f"fullsize_{workload}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not written yet (tests/golden/make_fullsize.py)")
     gold = np.load(path, allow_pickle=False)
     case = getattr(I, workload)()
     assert str(gold["workload"]) == case.name
@@ -75,9 +79,12 @@ def test_full_size_matches_streaming_oracle(workload, dtype):
     try:
         for k, op in enumerate(plan):
             if op == "pass":
-                if first:
+                if first and case.mesh is None:
                     s.autotune(reps=1)          # the first pass, in bench.py's configuration
                     say(f"  tile {s.get_tile()}")
+                    first = False
+                elif first:
+                    s.kinetic_step(1)           # an unstructured mesh has no tiles to tune
                     first = False
                 else:
                     s.kinetic_step(1)
