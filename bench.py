@@ -62,6 +62,11 @@ def parse():
     return p.parse_args()
 
 
+# the sources the box sweep kernel is built from: its counter summary holds while they hash the same
+SWEEP_SOURCES = ("paper_2310_18916_amd/csrc/k_sweep.hip", "paper_2310_18916_amd/csrc/gsis_common.h",
+                 "paper_2310_18916_amd/csrc/gsis_sweep_math.h")
+
+
 def sweep_traffic(dtype, tile, workload_name):
     """HBM bytes per sweep pass from the committed rocprofv3 counter summary, or
     None when that summary was taken on other kernel sources or has no entry
@@ -79,7 +84,7 @@ def sweep_traffic(dtype, tile, workload_name):
             k, v = line.strip().split(":", 1)
             kv[k.strip()] = v.strip()
     h = hashlib.sha256()
-    for f in ("paper_2310_18916_amd/csrc/k_sweep.hip", "paper_2310_18916_amd/csrc/gsis_common.h"):
+    for f in SWEEP_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     key = "tile " + ",".join(map(str, tile))
     if kv.get("source_sha256") != h.hexdigest() or f"{key} fetch_bytes_per_pass" not in kv:
