@@ -98,6 +98,10 @@ typedef struct {
     const double *uvol;
     const int *uface_cell;
     const double *uface_geom;
+    /* cell centroids [ucells][3] and face centroids [ufaces][3] of the
+     * unstructured mesh (the macroscopic correction's gradients and face
+     * distances); NULL: kinetic passes only. */
+    const double *ucenter, *ufcenter;
 } orc_cfg;
 
 typedef struct {
@@ -117,7 +121,7 @@ typedef struct {
      * the faces of every cell, cf[cf_off[i] .. cf_off[i + 1]) = 2 f + side
      * (side 0: the cell owns face f, 1: it is the neighbour) */
     int umesh, nface;
-    double *uvol, *ufg;
+    double *uvol, *ufg, *ucen, *ufcen;
     int *ufc, *cf_off, *cf;
     int status;
 } orc_state;
@@ -175,7 +179,7 @@ void orc_free(orc_state *s)
     free(s->solid);
     for (int a = 0; a < 3; ++a) { free(s->xi[a]); free(s->w1[a]); }
     free(s->f0); free(s->f1); free(s->prev); free(s->lastW); free(s->mbw); free(s->ntab);
-    free(s->uvol); free(s->ufg); free(s->ufc); free(s->cf_off); free(s->cf);
+    free(s->uvol); free(s->ufg); free(s->ufc); free(s->cf_off); free(s->cf); free(s->ucen); free(s->ufcen);
     free(s);
 }
 
@@ -251,7 +255,14 @@ static orc_state *create_state(const orc_cfg *cfg, const unsigned char *solid, i
             if (s->ufc[2 * f + 1] >= 0) s->cf[at[s->ufc[2 * f + 1]]++] = 2 * f + 1;
         }
         free(at);
+        if (cfg->ucenter && cfg->ufcenter) {
+            s->ucen = malloc(sizeof(double) * 3 * (size_t)nc);
+            s->ufcen = malloc(sizeof(double) * 3 * (size_t)nf);
+            memcpy(s->ucen, cfg->ucenter, sizeof(double) * 3 * (size_t)nc);
+            memcpy(s->ufcen, cfg->ufcenter, sizeof(double) * 3 * (size_t)nf);
+        }
         s->c.uvol = NULL; s->c.uface_cell = NULL; s->c.uface_geom = NULL;   /* copied */
+        s->c.ucenter = NULL; s->c.ufcenter = NULL;
     }
     for (int a = 0; a < 3 && !list; ++a) {
         int n = cfg->nv[a];
@@ -1804,6 +1815,370 @@ static int macro_solve(orc_state *s, const moms *K, const double *Fkin, const do
     return s->status;
 }
 
+/* ------------------------------------- unstructured macroscopic solve -- */
+/* The GSIS-II correction on an unstructured mesh: the same equations and
+ * iteration as macro_solve, written for faces of any normal n (out of the
+ * owner), area S and cells of volume V, with
+ *  - the velocity gradient of a cell by least squares over its face
+ *    neighbours, G minimising sum_j |u_j - u_i - G (x_j - x_i)|^2: G = B A^+,
+ *    A = sum_j d_j d_j^T, B = sum_j (u_j - u_i) d_j^T, A^+ the inverse on the
+ *    range of A (Jacobi eigen-decomposition; eigenvalues below 1e-12 of the
+ *    largest dropped), so a direction without neighbours gets no gradient
+ *    (on whole hexahedra: the central, next to a boundary one-sided,
+ *    difference of macro_solve);
+ *  - at a face between L and R (d = x_R - x_L): the face gradient is the mean
+ *    of the two cells' plus the correction that makes its component along d
+ *    the two-cell difference, G_f = Gm + [(u_R - u_L)/|d| - Gm d/|d|] d^T/|d|,
+ *    the normal heat fluxes -k mu (T_R - T_L) / h and h = d . n (on
+ *    hexahedra: the normal difference and mean tangential gradients of
+ *    macro_solve);
+ *  - Gamma = s + C_d Tt^omega / (delta rho h), h = d . n inside and twice the
+ *    distance along n from the cell centroid to the face centroid on a
+ *    boundary face; h_min of the pseudo time step the smallest of these;
+ *  - face fluxes per unit area times S / V in the residual and the diagonal,
+ *    D_i = 1/dtau_i + (1/2) sum_faces Gamma S / V;
+ *  - the high-order terms of reading "face-consistent HoT": at every face the
+ *    kinetic scheme's flux of f^{n+1/2} (first-order upwind values across
+ *    the face's own normal) minus the macroscopic flux of W^{n+1/2}. */
+static void sym3_pinv(const double A[9], double Pi[9])
+{
+    double a[3][3], v[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) a[i][j] = A[i * 3 + j];
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]);
+        if (off == 0.0) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                if (a[p][q] == 0.0) continue;
+                double th = 0.5 * (a[q][q] - a[p][p]) / a[p][q];
+                double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < 3; ++k) {   /* A <- A J */
+                    double x = a[k][p], y = a[k][q];
+                    a[k][p] = cs * x - sn * y;
+                    a[k][q] = sn * x + cs * y;
+                }
+                for (int k = 0; k < 3; ++k) {   /* A <- J^T A */
+                    double x = a[p][k], y = a[q][k];
+                    a[p][k] = cs * x - sn * y;
+                    a[q][k] = sn * x + cs * y;
+                }
+                for (int k = 0; k < 3; ++k) {   /* V <- V J */
+                    double x = v[k][p], y = v[k][q];
+                    v[k][p] = cs * x - sn * y;
+                    v[k][q] = sn * x + cs * y;
+                }
+            }
+    }
+    double emax = fmax(fabs(a[0][0]), fmax(fabs(a[1][1]), fabs(a[2][2])));
+    double inv[3];
+    for (int k = 0; k < 3; ++k) inv[k] = (emax > 0 && a[k][k] > 1e-12 * emax) ? 1.0 / a[k][k] : 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += v[i][k] * inv[k] * v[j][k];
+            Pi[i * 3 + j] = acc;
+        }
+}
+
+static void ucell_grad(const orc_state *s, const prim_t *P, int i, double G[9])
+{
+    double A[9] = {0}, B[9] = {0}, Ai[9];
+    const double *xi = s->ucen + (size_t)i * 3;
+    for (int e = s->cf_off[i]; e < s->cf_off[i + 1]; ++e) {
+        double n[3], sv;
+        int j;
+        uface_of(s, i, s->cf[e], n, &sv, &j);
+        if (j < 0) continue;
+        const double *xj = s->ucen + (size_t)j * 3;
+        double d[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
+        for (int b = 0; b < 3; ++b)
+            for (int c = 0; c < 3; ++c) {
+                A[b * 3 + c] += d[b] * d[c];
+                B[b * 3 + c] += (P[j].u[b] - P[i].u[b]) * d[c];
+            }
+    }
+    sym3_pinv(A, Ai);
+    for (int b = 0; b < 3; ++b)
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += B[b * 3 + k] * Ai[k * 3 + c];
+            G[b * 3 + c] = acc;
+        }
+}
+
+/* Flux from L to R across a face of unit normal n (out of L), d = x_R - x_L,
+ * hot = HoT of the six flux components added as given. */
+static void uface_flux(const macpar *mp, const prim_t *L, const prim_t *R, const double *gL, const double *gR,
+                       const double n[3], const double d[3], const double hot[6], double F[6], double *Gam)
+{
+    double h = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
+    double sN[3] = {0, 0, 0}, qN = 0, qrN = 0;
+    double TF = 0.5 * (L->Tt + R->Tt);
+    if (!mp->euler) {
+        double mu = pow(TF, mp->omega) / mp->delta;
+        double dl = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double e[3] = {d[0] / dl, d[1] / dl, d[2] / dl};
+        double G[9];
+        for (int b = 0; b < 3; ++b) {
+            double gm[3], gd = 0;
+            for (int c = 0; c < 3; ++c) { gm[c] = 0.5 * (gL[b * 3 + c] + gR[b * 3 + c]); gd += gm[c] * e[c]; }
+            double corr = (R->u[b] - L->u[b]) / dl - gd;
+            for (int c = 0; c < 3; ++c) G[b * 3 + c] = gm[c] + corr * e[c];
+        }
+        double div = G[0] + G[4] + G[8];
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0;
+            for (int c = 0; c < 3; ++c) acc += (G[b * 3 + c] + G[c * 3 + b]) * n[c];
+            sN[b] = -mu * (acc - (2.0 / 3.0) * div * n[b]);
+        }
+        qN = -mp->kt * mu * (R->Tt - L->Tt) / h;
+        qrN = mp->dia ? -mp->kr * mu * (R->Tr - L->Tr) / h : 0.0;
+    }
+    const prim_t *S[2] = {L, R};
+    double Phi[2][6], Wv[2][6], un[2];
+    for (int k = 0; k < 2; ++k) {
+        const prim_t *Pk = S[k];
+        un[k] = Pk->u[0] * n[0] + Pk->u[1] * n[1] + Pk->u[2] * n[2];
+        Phi[k][0] = Pk->rho * un[k];
+        for (int b = 0; b < 3; ++b) Phi[k][1 + b] = Pk->rho * Pk->u[b] * un[k] + 0.5 * Pk->p * n[b];
+        Phi[k][4] = (Pk->E + Pk->p) * un[k];
+        Phi[k][5] = Pk->Er * un[k];
+        Wv[k][0] = Pk->rho;
+        for (int b = 0; b < 3; ++b) Wv[k][1 + b] = Pk->rho * Pk->u[b];
+        Wv[k][4] = Pk->E;
+        Wv[k][5] = Pk->Er;
+    }
+    double sL = fabs(un[0]) + L->cs, sR = fabs(un[1]) + R->cs;
+    double smax = sL > sR ? sL : sR;
+    for (int k = 0; k < 6; ++k) F[k] = 0.5 * (Phi[0][k] + Phi[1][k]) - 0.5 * smax * (Wv[1][k] - Wv[0][k]);
+    double uF[3];
+    for (int b = 0; b < 3; ++b) uF[b] = 0.5 * (L->u[b] + R->u[b]);
+    for (int b = 0; b < 3; ++b) F[1 + b] += 0.5 * sN[b];
+    F[4] += sN[0] * uF[0] + sN[1] * uF[1] + sN[2] * uF[2] + qN + qrN;
+    F[5] += qrN;
+    for (int k = 0; k < 6; ++k) F[k] += hot[k];
+    double rF = 0.5 * (L->rho + R->rho);
+    *Gam = mp->euler ? smax : smax + mp->Cd * pow(TF, mp->omega) / (mp->delta * rF * h);
+}
+
+/* The kinetic flux of face f out of its owner: sum w (xi.n) psi f_face with
+ * psi = (1, xi, |xi|^2 f0 + f1, f1), f_face the upwind cell's value inside;
+ * on a boundary face the owner's value going out and the boundary value
+ * coming in (wall density from this f, zero mass flux). */
+static void ukinetic_face_flux(const orc_state *s, int f, double F[6])
+{
+    const orc_cfg *c = &s->c;
+    int L = s->ufc[2 * f], R = s->ufc[2 * f + 1];
+    const double *g = s->ufg + (size_t)f * 4;
+    const double *f0L = s->f0 + (size_t)L * s->nv, *f1L = s->f1 ? s->f1 + (size_t)L * s->nv : NULL;
+    const double *f0R = R >= 0 ? s->f0 + (size_t)R * s->nv : NULL;
+    const double *f1R = (R >= 0 && s->f1) ? s->f1 + (size_t)R * s->nv : NULL;
+    int bc = R < 0 ? -1 - R : 0;
+    double sc = R < 0 ? uface_scale(s, f) : 0.0;
+    nsum acc[6];
+    memset(acc, 0, sizeof acc);
+    for (int v = 0; v < s->nv; ++v) {
+        double xi[3], w;
+        node_xi(s, v, xi, &w);
+        double xn = xi[0] * g[1] + xi[1] * g[2] + xi[2] * g[3];
+        if (xn == 0.0) continue;
+        double a0, a1;
+        if (xn > 0) {
+            a0 = f0L[v];
+            a1 = f1L ? f1L[v] : 0.0;
+        } else if (R >= 0) {
+            a0 = f0R[v];
+            a1 = f1R ? f1R[v] : 0.0;
+        } else {
+            boundary_value(c, bc, sc, xi, &a0, &a1);
+            if (!s->f1) a1 = 0.0;
+        }
+        double x2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+        double ww = w * xn;
+        nadd(&acc[0], ww * a0);
+        for (int b = 0; b < 3; ++b) nadd(&acc[1 + b], ww * xi[b] * a0);
+        nadd(&acc[4], ww * (x2 * a0 + a1));
+        nadd(&acc[5], ww * a1);
+    }
+    for (int k = 0; k < 6; ++k) F[k] = nval(&acc[k]);
+}
+
+/* F_eq of boundary face f: its flux when the owner holds the Maxwellian of P
+ * (f1 = (dr/2) Tr M), with the boundary rule of the face. */
+static void uequilibrium_face_flux(const orc_state *s, const prim_t *P, int f, double F[6])
+{
+    const orc_cfg *c = &s->c;
+    const double *g = s->ufg + (size_t)f * 4;
+    int bc = -1 - s->ufc[2 * f + 1], dia = c->species == 1;
+    const double pc = pow(M_PI * P->Tt, -1.5);
+    const double *Mb = s->mbw + (size_t)bc * s->nv;
+    double sc = c->bc_rho[bc];
+    if (c->bc_kind[bc] == ORC_WALL) {
+        nsum out = {0, 0}, in = {0, 0};
+        for (int v = 0; v < s->nv; ++v) {
+            double xi[3], w;
+            node_xi(s, v, xi, &w);
+            double xn = xi[0] * g[1] + xi[1] * g[2] + xi[2] * g[3];
+            if (xn > 0) nadd(&out, w * xn * maxwellian_pre(P->rho, pc, P->u, P->Tt, xi));
+            else if (xn < 0) nadd(&in, w * (-xn) * Mb[v]);
+        }
+        sc = nval(&out) / nval(&in);
+    }
+    nsum acc[6];
+    memset(acc, 0, sizeof acc);
+    for (int v = 0; v < s->nv; ++v) {
+        double xi[3], w;
+        node_xi(s, v, xi, &w);
+        double xn = xi[0] * g[1] + xi[1] * g[2] + xi[2] * g[3];
+        if (xn == 0.0) continue;
+        double a0, a1;
+        if (xn > 0) {
+            a0 = maxwellian_pre(P->rho, pc, P->u, P->Tt, xi);
+            a1 = dia ? 0.5 * c->dr * P->Tr * a0 : 0.0;
+        } else {
+            a0 = sc * Mb[v];
+            a1 = dia ? 0.5 * c->dr * c->bc_T[bc] * a0 : 0.0;
+        }
+        double x2 = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+        double ww = w * xn;
+        nadd(&acc[0], ww * a0);
+        for (int b = 0; b < 3; ++b) nadd(&acc[1 + b], ww * xi[b] * a0);
+        nadd(&acc[4], ww * (x2 * a0 + a1));
+        nadd(&acc[5], ww * a1);
+    }
+    for (int k = 0; k < 6; ++k) F[k] = nval(&acc[k]);
+}
+
+/* h of face f: d . n between the two centroids inside, twice the distance
+ * along n from the owner's centroid to the face centroid on the boundary. */
+static double uface_h(const orc_state *s, int f, double d[3])
+{
+    const double *g = s->ufg + (size_t)f * 4;
+    int L = s->ufc[2 * f], R = s->ufc[2 * f + 1];
+    const double *xL = s->ucen + (size_t)L * 3;
+    const double *xR = R >= 0 ? s->ucen + (size_t)R * 3 : s->ufcen + (size_t)f * 3;
+    double k = R >= 0 ? 1.0 : 2.0;
+    for (int a = 0; a < 3; ++a) d[a] = k * (xR[a] - xL[a]);
+    return d[0] * g[1] + d[1] * g[2] + d[2] * g[3];
+}
+
+static int umacro_solve(orc_state *s, const moms *K, int iters, prim_t *P)
+{
+    const orc_cfg *c = &s->c;
+    macpar mp;
+    macro_params(s, &mp);
+    mp.euler = 0;
+    int ncell = s->ncell, nw = mp.nw, nf = s->nface;
+    static const double nohot[6] = {0, 0, 0, 0, 0, 0};
+    double *W = calloc((size_t)ncell * 6, sizeof(double));
+    double *fix = calloc((size_t)nf * 6, sizeof(double));   /* HoT of interior faces, fixed part of boundary faces */
+    double *grad = calloc((size_t)ncell * 9, sizeof(double));
+    double *R = calloc((size_t)ncell * 6, sizeof(double));
+    double *Dc = calloc((size_t)ncell, sizeof(double));
+    double *Src = calloc((size_t)ncell, sizeof(double));
+    double hmin = INFINITY;
+    for (int f = 0; f < nf; ++f) {
+        double d[3], h = uface_h(s, f, d);
+        if (h < hmin) hmin = h;
+    }
+    for (int cell = 0; cell < ncell; ++cell) {
+        const moms *m = &K[cell];
+        double u2 = m->u[0] * m->u[0] + m->u[1] * m->u[1] + m->u[2] * m->u[2];
+        double *w = W + (size_t)cell * 6;
+        w[0] = m->rho;
+        for (int a = 0; a < 3; ++a) w[1 + a] = m->rho * m->u[a];
+        double Er = mp.dia ? 0.5 * c->dr * m->rho * m->Tr : 0.0;
+        w[4] = m->rho * u2 + 1.5 * m->rho * m->Tt + Er;
+        w[5] = Er;
+        prim_of(&mp, w, &P[cell]);
+    }
+    for (int cell = 0; cell < ncell; ++cell) ucell_grad(s, P, cell, grad + (size_t)cell * 9);
+    /* fixed parts: F_kin(f^{n+1/2}) - F(W^{n+1/2}) at every face */
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int f = 0; f < nf; ++f) {
+        int L = s->ufc[2 * f], Rr = s->ufc[2 * f + 1];
+        double Fk[6], Fm[6], Gam, d[3];
+        ukinetic_face_flux(s, f, Fk);
+        if (Rr >= 0) {
+            uface_h(s, f, d);
+            uface_flux(&mp, &P[L], &P[Rr], grad + (size_t)L * 9, grad + (size_t)Rr * 9, s->ufg + (size_t)f * 4 + 1, d,
+                       nohot, Fm, &Gam);
+        } else {
+            uequilibrium_face_flux(s, &P[L], f, Fm);
+        }
+        for (int k = 0; k < 6; ++k) fix[(size_t)f * 6 + k] = Fk[k] - Fm[k];
+        if (!mp.dia && Rr >= 0) fix[(size_t)f * 6 + 5] = 0.0;
+    }
+    double *Ff = calloc((size_t)nf * 7, sizeof(double));   /* face flux (owner -> other) and Gamma of an iterate */
+    for (int it = 0; it < iters; ++it) {
+        for (int cell = 0; cell < ncell; ++cell) prim_of(&mp, W + (size_t)cell * 6, &P[cell]);
+        for (int cell = 0; cell < ncell; ++cell) ucell_grad(s, P, cell, grad + (size_t)cell * 9);
+        #pragma omp parallel for schedule(dynamic, 16)
+        for (int f = 0; f < nf; ++f) {
+            int L = s->ufc[2 * f], Rr = s->ufc[2 * f + 1];
+            double *o = Ff + (size_t)f * 7, d[3];
+            double h = uface_h(s, f, d);
+            if (Rr >= 0) {
+                uface_flux(&mp, &P[L], &P[Rr], grad + (size_t)L * 9, grad + (size_t)Rr * 9, s->ufg + (size_t)f * 4 + 1,
+                           d, fix + (size_t)f * 6, o, &o[6]);
+            } else {
+                double Fe[6];
+                uequilibrium_face_flux(s, &P[L], f, Fe);
+                for (int k = 0; k < 6; ++k) o[k] = fix[(size_t)f * 6 + k] + Fe[k];
+                const double *g = s->ufg + (size_t)f * 4;
+                const prim_t *Pi = &P[L];
+                double un = Pi->u[0] * g[1] + Pi->u[1] * g[2] + Pi->u[2] * g[3];
+                o[6] = fabs(un) + Pi->cs + mp.Cd * pow(Pi->Tt, mp.omega) / (mp.delta * Pi->rho * h);
+            }
+        }
+        #pragma omp parallel for schedule(dynamic, 16)
+        for (int cell = 0; cell < ncell; ++cell) {
+            const prim_t *Pi = &P[cell];
+            double res[6] = {0, 0, 0, 0, 0, 0}, sumG = 0;
+            for (int e = s->cf_off[cell]; e < s->cf_off[cell + 1]; ++e) {
+                int f = s->cf[e] >> 1, side = s->cf[e] & 1;
+                const double *o = Ff + (size_t)f * 7;
+                double sv = s->ufg[(size_t)f * 4] / s->uvol[cell];
+                for (int k = 0; k < nw; ++k) res[k] -= (side ? -o[k] : o[k]) * sv;
+                sumG += o[6] * sv;
+            }
+            double invtau = mp.delta * Pi->rho * pow(Pi->Tt, 1.0 - mp.omega);
+            if (mp.dia) {
+                double T = (3.0 * Pi->Tt + mp.dr * Pi->Tr) / (3.0 + mp.dr);
+                res[5] += 0.5 * mp.dr * Pi->rho * (T - Pi->Tr) * invtau / mp.Z;
+            }
+            double umag = sqrt(Pi->u[0] * Pi->u[0] + Pi->u[1] * Pi->u[1] + Pi->u[2] * Pi->u[2]);
+            double vis = mp.Cd * pow(Pi->Tt, mp.omega) / (mp.delta * Pi->rho * hmin);
+            double idt = (umag + Pi->cs + vis) / (mp.cfl * hmin);
+            double *r = R + (size_t)cell * 6;
+            for (int k = 0; k < 6; ++k) r[k] = res[k];
+            Dc[cell] = idt + 0.5 * sumG;
+            Src[cell] = mp.dia ? invtau / mp.Z : 0.0;
+        }
+        double Dmax = 0.0;
+        for (int cell = 0; cell < ncell; ++cell)
+            if (Dc[cell] > Dmax) Dmax = Dc[cell];
+        for (int cell = 0; cell < ncell; ++cell) {
+            double *w = W + (size_t)cell * 6;
+            const double *r = R + (size_t)cell * 6;
+            for (int k = 0; k < 5; ++k) w[k] += r[k] / Dmax;
+            if (mp.dia) w[5] += r[5] / (Dmax + Src[cell]);
+        }
+    }
+    int bad = 0;
+    for (int cell = 0; cell < ncell; ++cell) {
+        prim_of(&mp, W + (size_t)cell * 6, &P[cell]);
+        if (!(P[cell].rho > 0) || !(P[cell].Tt > 0) || !isfinite(P[cell].E)) bad = 1;
+    }
+    if (bad) s->status = -5;
+    if (!s->lastW) s->lastW = malloc(sizeof(double) * (size_t)ncell * 6);
+    memcpy(s->lastW, W, sizeof(double) * (size_t)ncell * 6);
+    free(W); free(fix); free(grad); free(R); free(Dc); free(Src); free(Ff);
+    return s->status;
+}
+
 /* gsis_correct on the stored VDF: kinetic moments and boundary fluxes of
  * f^{n+1/2}, the macroscopic solve, then Eq. (updatef):
  * f0 += M(W^{n+1}) - M(W^{n+1/2}), f1 += (dr/2)[Tr' M(W^{n+1}) - Tr M(W^{n+1/2})],
@@ -1811,24 +2186,26 @@ static int macro_solve(orc_state *s, const moms *K, const double *Fkin, const do
  * Chapman-Enskog expansion). */
 static int gsis_correct_mode(orc_state *s, int iters, int euler)
 {
-    if (s->umesh) return -2;   /* the macroscopic solve is built for the box of hex cells */
+    /* unstructured mesh: the correction needs the centroids; no Euler form */
+    if (s->umesh && (euler || !s->ucen)) return -2;
     const orc_cfg *c = &s->c;
     int ncell = s->ncell, dia = c->species == 1;
     moms *K = calloc((size_t)ncell, sizeof(moms));
-    double *Fkin = calloc((size_t)ncell * 36, sizeof(double));
-    double *Fint = calloc((size_t)ncell * 18, sizeof(double));
+    double *Fkin = s->umesh ? NULL : calloc((size_t)ncell * 36, sizeof(double));
+    double *Fint = s->umesh ? NULL : calloc((size_t)ncell * 18, sizeof(double));
     prim_t *P = calloc((size_t)ncell, sizeof(prim_t));
     #pragma omp parallel for schedule(dynamic, 16)
     for (int cell = 0; cell < ncell; ++cell) {
         if (s->solid[cell]) continue;
         cell_moments(s, cell, &K[cell]);
-        for (int d = 0; d < 6; ++d) {
+        for (int d = 0; d < 6 && !s->umesh; ++d) {
             int n = neighbour(s, cell, d);
             if (n < 0 && !euler) kinetic_face_flux(s, cell, d, -1 - n, Fkin + (size_t)cell * 36 + d * 6);
             if (n >= 0 && (d & 1) && !euler) kinetic_interior_flux(s, cell, n, d / 2, Fint + (size_t)cell * 18 + (d / 2) * 6);
         }
     }
-    macro_solve(s, K, Fkin, Fint, iters, euler, P);
+    if (s->umesh) umacro_solve(s, K, iters, P);
+    else macro_solve(s, K, Fkin, Fint, iters, euler, P);
     #pragma omp parallel for schedule(static)
     for (int cell = 0; cell < ncell; ++cell) {
         if (s->solid[cell]) continue;
@@ -1900,6 +2277,21 @@ int orc_nsf_face(const orc_state *s, const double *W, int cell, int a, double ou
 }
 
 /* Total mass sum rho V of the current VDF (closed-cavity drift diagnostic). */
+/* The least-squares velocity gradients of the unstructured macroscopic solve
+ * for a field W[ncell][6]: G[ncell][9], G[b*3+c] = d u_b / d x_c; -2 without
+ * an unstructured mesh with centroids. */
+int orc_umesh_grad(const orc_state *s, const double *W, double *G)
+{
+    if (!s->umesh || !s->ucen) return -2;
+    macpar mp;
+    macro_params(s, &mp);
+    prim_t *P = calloc((size_t)s->ncell, sizeof(prim_t));
+    for (int i = 0; i < s->ncell; ++i) prim_of(&mp, W + (size_t)i * 6, &P[i]);
+    for (int i = 0; i < s->ncell; ++i) ucell_grad(s, P, i, G + (size_t)i * 9);
+    free(P);
+    return 0;
+}
+
 double orc_total_mass(const orc_state *s)
 {
     nsum m = {0, 0};

@@ -40,6 +40,7 @@ class _Cfg(C.Structure):
         ("nlist", C.c_int), ("node_list", C.POINTER(C.c_double)),
         ("ucells", C.c_int), ("ufaces", C.c_int), ("uvol", C.POINTER(C.c_double)),
         ("uface_cell", C.POINTER(C.c_int)), ("uface_geom", C.POINTER(C.c_double)),
+        ("ucenter", C.POINTER(C.c_double)), ("ufcenter", C.POINTER(C.c_double)),
     ]
 
 
@@ -75,6 +76,7 @@ def lib():
         L.orc_boundary_values.argtypes = [P, C.c_int, C.c_int, D, D]
         L.orc_face_values.argtypes = [P, C.c_int, C.c_int, C.c_int, D]
         L.orc_flux_divergence.argtypes = [P, C.c_int, C.c_int, C.c_int, D]
+        L.orc_umesh_grad.argtypes = [P, D, D]
         L.orc_total_mass.argtypes = [P]
         L.orc_total_mass.restype = C.c_double
         L.orc_ref_components.argtypes = [C.POINTER(_Cfg), C.c_double, D, C.c_double, C.c_double, D, D,
@@ -140,6 +142,12 @@ def make_cfg(case) -> _Cfg:
         c.uvol = vol.ctypes.data_as(C.POINTER(C.c_double))
         c.uface_cell = fc.ctypes.data_as(C.POINTER(C.c_int))
         c.uface_geom = fg.ctypes.data_as(C.POINTER(C.c_double))
+        if mesh.face_center is not None:
+            cc = np.ascontiguousarray(mesh.centroid, dtype=np.float64)
+            fcc = np.ascontiguousarray(mesh.face_center, dtype=np.float64)
+            c._keep += [cc, fcc]
+            c.ucenter = cc.ctypes.data_as(C.POINTER(C.c_double))
+            c.ufcenter = fcc.ctypes.data_as(C.POINTER(C.c_double))
     if getattr(case, "velocity_list", None) is not None:
         t = np.ascontiguousarray(case.velocity_list, dtype=np.float64)
         c._keep.append(t)
@@ -253,6 +261,15 @@ class Oracle:
         if lib().orc_nsf_face(self.h, _dp(W), cell, a, _dp(out)) != 0:
             raise ValueError("not an interior fluid face")
         return out
+
+    def umesh_grad(self, W: np.ndarray) -> np.ndarray:
+        """[cell][3][3] least-squares velocity gradients (d u_b / d x_c) of the
+        unstructured macroscopic solve for the field W[cell][6]."""
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        G = np.empty((self.ncell, 9))
+        if lib().orc_umesh_grad(self.h, _dp(W), _dp(G)) != 0:
+            raise ValueError("no unstructured mesh with centroids")
+        return G.reshape(-1, 3, 3)
 
     def total_mass(self) -> float:
         return lib().orc_total_mass(self.h)

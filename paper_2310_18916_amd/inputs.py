@@ -343,12 +343,15 @@ class SpatialMesh:
     ``-1 - slot`` for a boundary face of boundary slot 0..6 (the box faces
     -x, +x, -y, +y, -z, +z, then the surface of a solid body);
     ``face_geom[f] = (area, n_x, n_y, n_z)`` with n the unit normal pointing
-    out of the owner.  ``centroid`` and ``kind`` serve sampling and reports."""
+    out of the owner; ``centroid`` the cell centroids and ``face_center`` the
+    face centroids (the macroscopic correction's gradients and distances);
+    ``kind`` the cell kind (reports)."""
     volume: np.ndarray
     face_cell: np.ndarray
     face_geom: np.ndarray
     centroid: np.ndarray
     kind: np.ndarray
+    face_center: Optional[np.ndarray] = None
 
     @property
     def ncell(self) -> int:
@@ -448,19 +451,25 @@ def lattice_mesh(nx: int, ny: int, nz: int, lx: float, ly: float, lz: float, spl
         sel = np.flatnonzero(kc == k)
         for lc in range(ncell_of[k]):
             kind[first[sel] + lc] = k
-    # cell centroid (mean of its triangles' vertices: inside a convex cell), triangle geometry
+    # a point inside every cell (the mean of its triangles' vertices: inside a
+    # convex cell), triangle geometry, then volume and centroid from the
+    # pyramids the triangles span with that point
     tp = pts[tri_v]
-    cen = np.zeros((ncell, 3))
-    np.add.at(cen, tri_cell, tp.sum(axis=1))
-    cen /= np.bincount(tri_cell, minlength=ncell)[:, None] * 3
+    ref = np.zeros((ncell, 3))
+    np.add.at(ref, tri_cell, tp.sum(axis=1))
+    ref /= np.bincount(tri_cell, minlength=ncell)[:, None] * 3
     cr = np.cross(tp[:, 1] - tp[:, 0], tp[:, 2] - tp[:, 0])
     area = 0.5 * np.linalg.norm(cr, axis=1)
     nrm = cr / (2.0 * area[:, None])
     tc = tp.mean(axis=1)
-    flip = np.einsum("ij,ij->i", nrm, tc - cen[tri_cell]) < 0
+    flip = np.einsum("ij,ij->i", nrm, tc - ref[tri_cell]) < 0
     nrm[flip] *= -1.0                                   # out of the triangle's own cell
+    pv = area * np.einsum("ij,ij->i", nrm, tc - ref[tri_cell]) / 3.0
     vol = np.zeros(ncell)
-    np.add.at(vol, tri_cell, area * np.einsum("ij,ij->i", nrm, tc) / 3.0)
+    np.add.at(vol, tri_cell, pv)
+    cen = np.zeros((ncell, 3))
+    np.add.at(cen, tri_cell, pv[:, None] * (0.75 * tc + 0.25 * ref[tri_cell]))
+    cen /= vol[:, None]
     # pair the triangles: equal vertex sets are the two sides of one interface
     key = np.sort(tri_v, axis=1)
     order = np.lexsort((key[:, 2], key[:, 1], key[:, 0]))
@@ -486,6 +495,10 @@ def lattice_mesh(nx: int, ny: int, nz: int, lx: float, ly: float, lz: float, spl
     inv = inv.reshape(-1)
     fa = np.zeros(uq.shape[0])
     np.add.at(fa, inv, geom[:, 0])
+    tcs = np.concatenate([tc[a_idx], tc[lone]])
+    fcen = np.zeros((uq.shape[0], 3))
+    np.add.at(fcen, inv, geom[:, :1] * tcs)
+    fcen /= fa[:, None]
     rep = np.zeros(uq.shape[0], dtype=np.int64)
     rep[inv[::-1]] = np.arange(inv.size)[::-1]          # first triangle of every face
     fn = geom[rep, 1:]
@@ -493,7 +506,7 @@ def lattice_mesh(nx: int, ny: int, nz: int, lx: float, ly: float, lz: float, spl
     fo = np.lexsort((fc[:, 1], fc[:, 0]))
     return SpatialMesh(volume=vol, face_cell=np.ascontiguousarray(fc[fo]),
                        face_geom=np.ascontiguousarray(np.column_stack([fa, fn])[fo]),
-                       centroid=cen, kind=kind)
+                       centroid=cen, kind=kind, face_center=np.ascontiguousarray(fcen[fo]))
 
 
 def tensor_velocity_list(nv, vmin, vmax) -> np.ndarray:
