@@ -142,25 +142,32 @@ gsis_status gsis_set_velocity_list(gsis_ctx *ctx, const double *nodes, int n);
  * volume[ncell] > 0; face_cell[nface][2] = (owner cell, neighbour cell or
  * -1 - slot for a boundary face of boundary slot 0..6, whose condition
  * gsis_set_boundary gives); face_geom[nface][4] = (area >= 0, unit normal
- * out of the owner).  Replaces the box of hex cells of the configuration
- * (its nx, ny, nz, lx, ly, lz are then unused; cells are numbered as given,
- * gsis_moments has ncell rows) and runs the first-order update, solved
- * exactly: the library groups the velocity nodes into classes that agree on
- * the sign of xi . n for every face orientation of the mesh and sorts each
- * class's upwind graph into levels, swept one after another.  Requires
- * gsis_set_velocity_list first, order 1 and no solid mask (a body is a hole
- * in the mesh, its surface boundary slot 6); must precede
- * gsis_workspace_size.  Kinetic passes, moments, residual (volume-weighted)
- * and state calls work as on the box; gsis_gsis_correct, gsis_precondition,
- * gsis_set_tile, gsis_autotune and gsis_batch_create return GSIS_ESTATE
- * (GSIS_EINVAL for the batch).  EINVAL when an index, area, normal or volume
- * is invalid, a cell has more than 16 faces or is not closed (its area times
+ * out of the owner); cell_center[ncell][3] and face_center[nface][3] the
+ * centroids (both NULL: kinetic passes only, no macroscopic correction).
+ * Replaces the box of hex cells of the configuration (its nx, ny, nz, lx,
+ * ly, lz are then unused; cells are numbered as given, gsis_moments has
+ * ncell rows) and runs the first-order update, solved exactly: the library
+ * groups the velocity nodes into classes that agree on the sign of xi . n
+ * for every face orientation of the mesh and sorts each class's upwind graph
+ * into levels, swept one after another.  gsis_gsis_correct solves the GSIS-II
+ * equations of Sec. 3.3 on the same cells (least-squares velocity gradients
+ * over the face neighbours, face gradients corrected along the line of the
+ * two centroids, fluxes per unit area times S/V, the high-order terms of each
+ * face from the kinetic face flux).  Requires gsis_set_velocity_list first,
+ * order 1 and no solid mask (a body is a hole in the mesh, its surface
+ * boundary slot 6); must precede gsis_workspace_size.  Kinetic passes,
+ * moments, residual (volume-weighted) and state calls work as on the box;
+ * gsis_precondition, gsis_set_tile and gsis_autotune return GSIS_ESTATE (as
+ * does gsis_gsis_correct without centroids) and gsis_batch_create
+ * GSIS_EINVAL.  EINVAL when an index, area, normal, volume or centroid is
+ * invalid (a face whose centroid distance along its normal is not
+ * positive), a cell has more than 16 faces or is not closed (its area times
  * outward normals do not sum to zero within 1e-9 of its area), the faces
  * have more than 32 distinct orientations up to sign, the nodes fall into
  * more than 256 classes, or a class's upwind graph has a cycle (a mesh no
  * sweep orders exactly); ESTATE out of order. */
 gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume, int nface, const int *face_cell,
-                                  const double *face_geom);
+                                  const double *face_geom, const double *cell_center, const double *face_center);
 
 /* Boundary condition of slot face (GSIS_FACE_*): kind GSIS_DIFFUSE_WALL with
  * wall velocity u and temperature T (rho ignored; the wall density is set so

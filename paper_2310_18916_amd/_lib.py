@@ -36,7 +36,7 @@ SIGNATURES = {
     "gsis_set_solid_mask": (_I, [_P, _P, _SZ]),
     "gsis_set_velocity_nodes": (_I, [_P, C.c_int, _P, C.c_int]),
     "gsis_set_velocity_list": (_I, [_P, _P, C.c_int]),
-    "gsis_set_spatial_mesh": (_I, [_P, C.c_int, _P, C.c_int, _P, _P]),
+    "gsis_set_spatial_mesh": (_I, [_P, C.c_int, _P, C.c_int, _P, _P, _P, _P]),
     "gsis_precondition": (_I, [_P, C.c_int, C.c_int]),
     "gsis_set_boundary": (_I, [_P, _I, _I, _DP, _D, _D]),
     "gsis_workspace_size": (_I, [_P, C.POINTER(_SZ)]),

@@ -61,6 +61,9 @@ struct Geo {
     int umesh, ucls, unbf, nori;
     int umaxcnt;   // nodes of the largest class
     int umaxf;     // faces of the cell with the most
+    int unface;    // faces of the mesh
+    int ucen;      // 1: centroids given (the macroscopic correction runs)
+    double uhmin;  // smallest face distance h of the macroscopic pseudo time step
 };
 
 struct BcInfo {
@@ -130,6 +133,19 @@ struct Dev {
     double *ubf_n;
     double *ubf_s64;
     float *ubf_s32;
+    // macroscopic correction on the mesh (centroids given): per face entry the
+    // least-squares weights [3] of the neighbour across (0 on the boundary) and
+    // the face (f << 1 | 1 when the cell is the face's neighbour); per face
+    // (owner, neighbour or -1 - boundary face) and (S, n, h, |d|, d/|d|) [9];
+    // the kinetic flux [6], its fixed part [6] and the iterate's flux and Gamma
+    // [7]; per boundary face the incoming half-range psi-moments of its
+    // boundary Maxwellian [6]
+    double *ucf_lsq;
+    int *ucf_face;
+    int *ucf_first;    // [ncell + 1] first face entry of every cell
+    int *ubf_face;     // [unbf] the face of every boundary face
+    int *uf_cell;
+    double *uf_geo, *uFk, *ufix, *uFf, *ubin;
     double *corr;      // [ncell][NCORR]
     double *snap;      // [ncell][NSNAP]
     // macroscopic solve, all structures of arrays [field][ncell] ([field][nface]

@@ -27,8 +27,9 @@ struct gsis_ctx {
     std::vector<double> vlist;   // node list [nv][4] in the caller's order (list mode)
     // unstructured spatial mesh (g.umesh): what the sweep needs, built when the
     // mesh is set (see Dev for the meaning of each array)
-    std::vector<double> uvol, ucf_g, ubf_n;
+    std::vector<double> uvol, ucf_g, ubf_n, ucf_lsq, uf_geo;
     std::vector<int> ucf_nb, ucf_meta, ulev, ulev_off, ubf_cell, ubf_slot, uperm, ucls;   // ulev: 2 ints per entry
+    std::vector<int> ucf_face, uf_cell, ucf_first, ubf_face;
     int tx = 0, ty = 0, tz = 0, bs = 0;
     std::vector<int> tiles, plane_off, plane_cnt, npblk;
     std::vector<int> tent, nclean;   // split sweep entries (cases with solid cells)
@@ -331,6 +332,8 @@ size_t layout(gsis_ctx *c, char *base)
     if (base) c->dcase = dc;
     d.uvol = nullptr; d.ucf_nb = d.ucf_meta = nullptr; d.ucf_g64 = nullptr; d.ucf_g32 = nullptr;
     d.ucls = nullptr; d.ulev = nullptr;
+    d.ucf_lsq = nullptr; d.ucf_face = nullptr; d.uf_cell = nullptr; d.ucf_first = nullptr; d.ubf_face = nullptr;
+    d.uf_geo = d.uFk = d.ufix = d.uFf = d.ubin = nullptr;
     d.ubf_cell = d.ubf_slot = nullptr; d.ubf_n = nullptr; d.ubf_s64 = nullptr; d.ubf_s32 = nullptr;
     if (g.umesh) {
         const size_t ne = c->ucf_nb.size(), nb = std::max(g.unbf, 1);
@@ -346,6 +349,19 @@ size_t layout(gsis_ctx *c, char *base)
         carve(off, d.ubf_n, nb * 4, base);
         carve(off, d.ubf_s64, nb, base);
         carve(off, d.ubf_s32, nb, base);
+        if (g.ucen) {
+            const size_t nfc = (size_t)g.unface;
+            carve(off, d.ucf_lsq, ne * 3, base);
+            carve(off, d.ucf_face, ne, base);
+            carve(off, d.ucf_first, n + 1, base);
+            carve(off, d.ubf_face, nb, base);
+            carve(off, d.uf_cell, nfc * 2, base);
+            carve(off, d.uf_geo, nfc * 9, base);
+            carve(off, d.uFk, nfc * 6, base);
+            carve(off, d.ufix, nfc * 6, base);
+            carve(off, d.uFf, nfc * 7, base);
+            carve(off, d.ubin, nb * 6, base);
+        }
     }
     carve(off, d.corr, n * NCORR, base);
     carve(off, d.snap, n * NSNAP, base);
@@ -708,8 +724,47 @@ gsis_status gsis_set_velocity_list(gsis_ctx *ctx, const double *nodes, int n)
     return GSIS_OK;
 }
 
+// Symmetric 3x3 matrix: its inverse on its range (Jacobi eigen-decomposition,
+// eigenvalues below 1e-12 of the largest dropped).
+static void sym3_pinv(const double A[9], double Pi[9])
+{
+    double a[3][3], v[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) a[i][j] = A[i * 3 + j];
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        if (std::fabs(a[0][1]) + std::fabs(a[0][2]) + std::fabs(a[1][2]) == 0.0) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                if (a[p][q] == 0.0) continue;
+                const double th = 0.5 * (a[q][q] - a[p][p]) / a[p][q];
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < 3; ++k) {
+                    const double x = a[k][p], y = a[k][q];
+                    a[k][p] = cs * x - sn * y;
+                    a[k][q] = sn * x + cs * y;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    const double x = a[p][k], y = a[q][k];
+                    a[p][k] = cs * x - sn * y;
+                    a[q][k] = sn * x + cs * y;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    const double x = v[k][p], y = v[k][q];
+                    v[k][p] = cs * x - sn * y;
+                    v[k][q] = sn * x + cs * y;
+                }
+            }
+    }
+    const double emax = std::max(std::fabs(a[0][0]), std::max(std::fabs(a[1][1]), std::fabs(a[2][2])));
+    double inv[3];
+    for (int k = 0; k < 3; ++k) inv[k] = (emax > 0 && a[k][k] > 1e-12 * emax) ? 1.0 / a[k][k] : 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Pi[i * 3 + j] = v[i][0] * inv[0] * v[j][0] + v[i][1] * inv[1] * v[j][1] + v[i][2] * inv[2] * v[j][2];
+}
+
 gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume, int nface, const int *face_cell,
-                                  const double *face_geom)
+                                  const double *face_geom, const double *cell_center, const double *face_center)
 {
     if (!ctx) return GSIS_EINVAL;
     if (ctx->bound || ctx->meta_ready) return fail(ctx, GSIS_ESTATE, "set_spatial_mesh must precede workspace_size/bind");
@@ -718,6 +773,8 @@ gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume
     if (ctx->g.order != 1) return fail(ctx, GSIS_ESTATE, "an unstructured mesh runs the first-order update (order 1)");
     if (!ctx->mask.empty()) return fail(ctx, GSIS_ESTATE, "an unstructured mesh takes no solid mask");
     if (!volume || !face_cell || !face_geom) return fail(ctx, GSIS_EINVAL, "mesh array is NULL");
+    if ((cell_center == nullptr) != (face_center == nullptr))
+        return fail(ctx, GSIS_EINVAL, "give both cell and face centroids, or neither");
     if (ncell < 1 || nface < 1) return fail(ctx, GSIS_EINVAL, "the mesh needs cells and faces");
     if (ncell >= (1 << 23)) return fail(ctx, GSIS_EINVAL, "at most 2^23 - 1 cells");
     if ((long long)ncell * ctx->g.nv > (1ll << 40)) return fail(ctx, GSIS_EINVAL, "cells x nodes too large");
@@ -806,7 +863,7 @@ gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume
     if (off[ncell] >= (1 << 26)) return fail(ctx, GSIS_EINVAL, "at most 2^26 - 1 face entries (two per interior face)");
     std::vector<int> cnb(off[ncell]), cmeta(off[ncell]), pos(off.begin(), off.end() - 1);
     std::vector<double> cgeo((size_t)off[ncell] * 4);
-    std::vector<int> bcell, bslot;
+    std::vector<int> bcell, bslot, bface, fcell((size_t)nface * 2), cface(off[ncell]);
     std::vector<double> bn;
     for (int f = 0; f < nface; ++f) {
         const int o = face_cell[2 * f], nb = face_cell[2 * f + 1];
@@ -818,8 +875,13 @@ gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume
             other = -1 - (int)bcell.size();
             bcell.push_back(o);
             bslot.push_back(slot);
+            bface.push_back(f);
             bn.insert(bn.end(), {gg[1], gg[2], gg[3], 0.0});
         }
+        fcell[2 * (size_t)f] = o;
+        fcell[2 * (size_t)f + 1] = other;
+        cface[pos[o]] = f << 1;
+        if (nb >= 0) cface[pos[nb]] = f << 1 | 1;
         int e = pos[o]++;
         cnb[e] = other;
         cmeta[e] = fk[f] | fflip[f] << 5 | slot << 6;
@@ -885,6 +947,57 @@ gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume
         ent[2 * k] = key[k];
         ent[2 * k + 1] = off[i] << 5 | nfc[i];
     }
+    // the macroscopic correction's geometry: least-squares weights of every
+    // interior face entry, per face (S, n, h, |d|, d/|d|), the smallest h
+    std::vector<double> lsq, fgeo;
+    double hmin = 0.0;
+    if (cell_center) {
+        lsq.assign((size_t)off[ncell] * 3, 0.0);
+        fgeo.assign((size_t)nface * 9, 0.0);
+        hmin = INFINITY;
+        for (int f = 0; f < nface; ++f) {
+            const int o = face_cell[2 * f], nb = face_cell[2 * f + 1];
+            const double *gg = face_geom + (size_t)f * 4, *xo = cell_center + (size_t)o * 3;
+            const double *xr = nb >= 0 ? cell_center + (size_t)nb * 3 : face_center + (size_t)f * 3;
+            const double k = nb >= 0 ? 1.0 : 2.0;
+            double dv[3], dl = 0.0, h = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                dv[a] = k * (xr[a] - xo[a]);
+                dl += dv[a] * dv[a];
+                h += dv[a] * gg[1 + a];
+            }
+            dl = std::sqrt(dl);
+            if (!(h > 0.0) || !std::isfinite(h))
+                return fail(ctx, GSIS_EINVAL, "face " + std::to_string(f) + ": its centroid distance along the normal is not positive");
+            double *fg = &fgeo[(size_t)f * 9];
+            fg[0] = gg[0];
+            fg[1] = gg[1]; fg[2] = gg[2]; fg[3] = gg[3];
+            fg[4] = h;
+            fg[5] = dl;
+            for (int a = 0; a < 3; ++a) fg[6 + a] = dv[a] / dl;
+            hmin = std::min(hmin, h);
+        }
+        for (int i = 0; i < ncell; ++i) {
+            double A[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Ai[9];
+            const double *xi = cell_center + (size_t)i * 3;
+            for (int e = off[i]; e < off[i + 1]; ++e) {
+                if (cnb[e] < 0) continue;
+                const double *xj = cell_center + (size_t)cnb[e] * 3;
+                for (int b = 0; b < 3; ++b)
+                    for (int c = 0; c < 3; ++c) A[b * 3 + c] += (xj[b] - xi[b]) * (xj[c] - xi[c]);
+            }
+            sym3_pinv(A, Ai);
+            for (int e = off[i]; e < off[i + 1]; ++e) {
+                if (cnb[e] < 0) continue;
+                const double *xj = cell_center + (size_t)cnb[e] * 3;
+                for (int c = 0; c < 3; ++c) {
+                    double acc = 0.0;
+                    for (int k = 0; k < 3; ++k) acc += Ai[c * 3 + k] * (xj[k] - xi[k]);
+                    lsq[(size_t)e * 3 + c] = acc;
+                }
+            }
+        }
+    }
     // commit
     Geo &g = ctx->g;
     ctx->uvol.assign(volume, volume + ncell);
@@ -903,6 +1016,15 @@ gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume
     ctx->ubf_slot = bslot;
     ctx->ubf_n = bn;
     ctx->uperm = perm;
+    ctx->ucf_lsq = lsq;
+    ctx->ucf_face = cface;
+    ctx->ucf_first = off;
+    ctx->ubf_face = bface;
+    ctx->uf_cell = fcell;
+    ctx->uf_geo = fgeo;
+    g.ucen = cell_center ? 1 : 0;
+    g.unface = nface;
+    g.uhmin = hmin;
     g.umesh = 1;
     g.ucls = ncls;
     g.unbf = (int)bcell.size();
@@ -1039,6 +1161,14 @@ gsis_status gsis_bind_workspace(gsis_ctx *ctx, void *device_ptr, size_t bytes)
         HIPCHK(ctx, up(d.ucf_g32, g32.data(), g32.size() * sizeof(float)));
         HIPCHK(ctx, up(d.ucls, ctx->ucls.data(), ctx->ucls.size() * sizeof(int)));
         HIPCHK(ctx, up(d.ulev, ctx->ulev.data(), ctx->ulev.size() * sizeof(int)));
+        if (g.ucen) {
+            HIPCHK(ctx, up(d.ucf_lsq, ctx->ucf_lsq.data(), ctx->ucf_lsq.size() * sizeof(double)));
+            HIPCHK(ctx, up(d.ucf_face, ctx->ucf_face.data(), ctx->ucf_face.size() * sizeof(int)));
+            HIPCHK(ctx, up(d.ucf_first, ctx->ucf_first.data(), ctx->ucf_first.size() * sizeof(int)));
+            if (g.unbf > 0) HIPCHK(ctx, up(d.ubf_face, ctx->ubf_face.data(), ctx->ubf_face.size() * sizeof(int)));
+            HIPCHK(ctx, up(d.uf_cell, ctx->uf_cell.data(), ctx->uf_cell.size() * sizeof(int)));
+            HIPCHK(ctx, up(d.uf_geo, ctx->uf_geo.data(), ctx->uf_geo.size() * sizeof(double)));
+        }
         if (g.unbf > 0) {
             HIPCHK(ctx, up(d.ubf_cell, ctx->ubf_cell.data(), ctx->ubf_cell.size() * sizeof(int)));
             HIPCHK(ctx, up(d.ubf_slot, ctx->ubf_slot.data(), ctx->ubf_slot.size() * sizeof(int)));
@@ -1098,11 +1228,12 @@ gsis_status gsis_kinetic_step(gsis_ctx *ctx, int npasses)
         if (g.umesh) {
             HIPCHK(ctx, t0.start(ctx, GSIS_PHASE_PREP));
             HIPCHK(ctx, launch_params(t, ctx->stream));
-            HIPCHK(ctx, launch_uface_scale(t, ctx->stream));
+            HIPCHK(ctx, launch_uface_scale(t, ctx->pending ? 1 : 0, ctx->stream));
             HIPCHK(ctx, t0.stop());
             HIPCHK(ctx, t1.start(ctx, GSIS_PHASE_SWEEP));
             HIPCHK(ctx, launch_usweep(t, ctx->ulev_off.data(), (int)ctx->ulev_off.size() - 1, ctx->stream));
             HIPCHK(ctx, t1.stop());
+            ctx->pending = false;   // every point was rewritten
             HIPCHK(ctx, t2.start(ctx, GSIS_PHASE_MOMENTS));
             gsis_status st = reduce_vdf(ctx);
             if (st) return st;
@@ -1150,7 +1281,8 @@ gsis_status gsis_moments(gsis_ctx *ctx, double *out, int out_is_device)
 gsis_status gsis_gsis_correct(gsis_ctx *ctx, int inner_iters)
 {
     if (!ctx) return GSIS_EINVAL;
-    if (ctx->g.umesh) return fail(ctx, GSIS_ESTATE, "the macroscopic correction is built for the box of hex cells; an unstructured mesh runs kinetic passes");
+    if (ctx->g.umesh && !ctx->g.ucen)
+        return fail(ctx, GSIS_ESTATE, "the macroscopic correction on an unstructured mesh needs its centroids");
     if (!ctx->inited || !ctx->stepped) return fail(ctx, GSIS_ESTATE, "gsis_correct needs a kinetic step since init");
     if (inner_iters < 0) return fail(ctx, GSIS_EINVAL, "inner_iters must be >= 0");
     gsis_status st = materialize(ctx);
@@ -1158,7 +1290,8 @@ gsis_status gsis_gsis_correct(gsis_ctx *ctx, int inner_iters)
     PhaseTimer t;
     HIPCHK(ctx, t.start(ctx, GSIS_PHASE_MACRO));
     const Target tg = target_of(ctx);
-    HIPCHK(ctx, launch_gsis_macro(tg, inner_iters, ctx->stream));
+    if (ctx->g.umesh) HIPCHK(ctx, launch_umacro(tg, inner_iters, ctx->stream));
+    else HIPCHK(ctx, launch_gsis_macro(tg, inner_iters, ctx->stream));
     HIPCHK(ctx, launch_commit_correction(tg, ctx->stream));
     HIPCHK(ctx, launch_derive(tg, ctx->stream));
     HIPCHK(ctx, t.stop());
@@ -1169,7 +1302,7 @@ gsis_status gsis_gsis_correct(gsis_ctx *ctx, int inner_iters)
 gsis_status gsis_precondition(gsis_ctx *ctx, int macro_steps, int kinetic_steps)
 {
     if (!ctx) return GSIS_EINVAL;
-    if (ctx->g.umesh) return fail(ctx, GSIS_ESTATE, "the macroscopic correction is built for the box of hex cells; an unstructured mesh runs kinetic passes");
+    if (ctx->g.umesh) return fail(ctx, GSIS_ESTATE, "the initial field of Alg. 1 (Euler steps) is built for the box of hex cells");
     if (!ctx->inited) return fail(ctx, GSIS_ESTATE, "initialise the VDF first");
     if (macro_steps < 0 || kinetic_steps < 0) return fail(ctx, GSIS_EINVAL, "steps must be >= 0");
     gsis_status st = materialize(ctx);

@@ -59,12 +59,14 @@ int sweep_shapes(bool fp32, int *out, int max);
 hipError_t launch_sweep(const Target &t, hipStream_t s);
 // unstructured mesh: boundary-face density scales, then the sweep level by level
 // (lev_off[L] .. lev_off[L + 1] are the entries of level L)
-hipError_t launch_uface_scale(const Target &t, hipStream_t s);
+hipError_t launch_uface_scale(const Target &t, int pending, hipStream_t s);
 hipError_t launch_usweep(const Target &t, const int *lev_off, int nlev, hipStream_t s);
 
 // euler != 0: the Euler constitutive relations (no stress, heat flux, HoT or
 // diffusive pseudo-time terms) and the iterate's own boundary flux
 hipError_t launch_gsis_macro(const Target &t, int iters, hipStream_t s, int euler = 0);
+// the same solve on an unstructured mesh (one case, centroids given)
+hipError_t launch_umacro(const Target &t, int iters, hipStream_t s);
 
 int resid_blocks(const Geo &g);
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);

@@ -23,6 +23,8 @@
 #include "gsis_common.h"
 #include "gsis_launch.h"
 
+#include <algorithm>
+
 namespace gsis {
 
 // prims per cell: rho, ux, uy, uz, Tt, Tr, E, Er, c_s, Tt^omega / delta, 1/tau, (unused)
@@ -669,6 +671,386 @@ hipError_t launch_gsis_macro(const Target &t, int iters, hipStream_t s, int eule
                            it == iters - 1 ? 1 : 0, euler);
     }
     hipLaunchKernelGGL(k_mac_final, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(t.span(K_CELL128)));
+    return hipGetLastError();
+}
+
+// ------------------------------------------------ unstructured mesh solve
+// The same solve on an unstructured mesh (one case): faces of any normal n
+// (out of the owner), area S, cells of volume V.  Velocity gradient of a cell
+// by least squares over its face neighbours (weights from the host: the
+// inverse of sum_j d_j d_j^T on its range applied to d_j), face gradient the
+// mean of the two cells' corrected along d = x_R - x_L to the two-cell
+// difference, normal heat fluxes -k mu (T_R - T_L) / h with h = d . n (twice
+// the centroid-to-face distance along n on a boundary), Rusanov; fluxes per
+// unit area times S / V in the residual and the diagonal; the high-order
+// terms at every face the kinetic flux of f^{n+1/2} minus the macroscopic
+// flux of W^{n+1/2}; on a boundary face F_kin + F_eq(W^m) - F_eq(W^{n+1/2}).
+
+// Rusanov + NSF flux across face f from L to R (no high-order terms).
+template <class PV, class GV>
+__device__ __forceinline__ void uface_flux(const Geo &g, const PV &L, const PV &R, const GV &gL, const GV &gR,
+                                           const double fg[9], double F[6], double *Gam)
+{
+    const double n[3] = {fg[1], fg[2], fg[3]}, h = fg[4], dl = fg[5], e[3] = {fg[6], fg[7], fg[8]};
+    const double TF = 0.5 * (L[4] + R[4]), rF = 0.5 * (L[0] + R[0]);
+    const double mu = pow_pos(TF, g.omega) / g.delta;
+    double G[9];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        double gm[3], gd = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            gm[c] = 0.5 * (gL[b * 3 + c] + gR[b * 3 + c]);
+            gd += gm[c] * e[c];
+        }
+        const double corr = (R[1 + b] - L[1 + b]) / dl - gd;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) G[b * 3 + c] = gm[c] + corr * e[c];
+    }
+    const double div = G[0] + G[4] + G[8];
+    double sN[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc += (G[b * 3 + c] + G[c * 3 + b]) * n[c];
+        sN[b] = -mu * (acc - (2.0 / 3.0) * div * n[b]);
+    }
+    const double qN = -g.kt * mu * (R[4] - L[4]) / h;
+    const double qrN = g.species == 1 ? -g.kr * mu * (R[5] - L[5]) / h : 0.0;
+    double Phi[2][6], Wv[2][6], un[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const PV &P = k ? R : L;
+        const double rho = P[0], p = P[0] * P[4];
+        un[k] = P[1] * n[0] + P[2] * n[1] + P[3] * n[2];
+        Phi[k][0] = rho * un[k];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Phi[k][1 + b] = rho * P[1 + b] * un[k] + 0.5 * p * n[b];
+        Phi[k][4] = (P[6] + p) * un[k];
+        Phi[k][5] = P[7] * un[k];
+        Wv[k][0] = rho;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Wv[k][1 + b] = rho * P[1 + b];
+        Wv[k][4] = P[6];
+        Wv[k][5] = P[7];
+    }
+    const double sL = fabs(un[0]) + L[8], sR = fabs(un[1]) + R[8];
+    const double smax = sL > sR ? sL : sR;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) F[k] = 0.5 * (Phi[0][k] + Phi[1][k]) - 0.5 * smax * (Wv[1][k] - Wv[0][k]);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) F[1 + b] += 0.5 * sN[b];
+    F[4] += sN[0] * 0.5 * (L[1] + R[1]) + sN[1] * 0.5 * (L[2] + R[2]) + sN[2] * 0.5 * (L[3] + R[3]) + qN + qrN;
+    F[5] += qrN;
+    *Gam = smax + g.Cd * mu / (rF * h);
+}
+
+// Velocity gradient of every cell: G[b][c] = sum over its interior face
+// entries of (u_j - u_i)_b w_c.
+__global__ __launch_bounds__(256) void k_umac_grad(GSIS_SPAN_ARGS)
+{
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    const int cell = blk * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell) return;
+    const size_t n = g.ncell;
+    const Soa<double> P = soa(d.P, n, cell);
+    const double ui[3] = {P[1], P[2], P[3]};
+    double Gc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int first = G(d.ucf_first)[cell], cnt = G(d.ucf_first)[cell + 1] - first;
+    for (int k = 0; k < cnt; ++k) {
+        const int e = first + k;
+        const int j = G(d.ucf_nb)[e];
+        if (j < 0) continue;
+        const Soa<double> Pj = soa(d.P, n, j);
+        const double w0 = G(d.ucf_lsq)[3 * (size_t)e], w1 = G(d.ucf_lsq)[3 * (size_t)e + 1], w2 = G(d.ucf_lsq)[3 * (size_t)e + 2];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double du = Pj[1 + b] - ui[b];
+            Gc[b * 3] += du * w0;
+            Gc[b * 3 + 1] += du * w1;
+            Gc[b * 3 + 2] += du * w2;
+        }
+    }
+    const Soa<double> Gd = soa(d.grad, n, cell);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Gd[k] = Gc[k];
+}
+
+// Kinetic flux of every face out of its owner, one wave per face: sum over
+// the nodes of w (xi.n) psi f_face, psi = (1, xi, |xi|^2 f0 + f1, f1), f_face
+// the upwind cell's value inside; on a boundary face the owner's value going
+// out and the boundary value coming in, the wall density from this f (zero
+// mass flux).  A boundary face also keeps the incoming half-range
+// psi-moments of its boundary Maxwellian, w (xi.n) psi M_b over xi.n < 0.
+template <typename T, bool DIA>
+__global__ __launch_bounds__(256) void k_umac_kin(GSIS_SPAN_ARGS)
+{
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    const int f = __builtin_amdgcn_readfirstlane(blk * 4 + (int)(threadIdx.x >> 6));
+    if (f >= g.unface) return;
+    const int lane = threadIdx.x & 63;
+    const int L = G(d.uf_cell)[2 * (size_t)f], R = G(d.uf_cell)[2 * (size_t)f + 1];
+    const gptr<const double> fg = G((const double *)d.uf_geo) + 9 * (size_t)f;
+    const double n0 = fg[1], n1 = fg[2], n2 = fg[3];
+    const size_t nv = (size_t)g.nv;
+    const gptr<const T> f0L = (gptr<const T>)d.f0 + (size_t)L * nv;
+    const gptr<const T> f1L = DIA ? (gptr<const T>)d.f1 + (size_t)L * nv : f0L;
+    const int Rr = R >= 0 ? R : L;
+    const gptr<const T> f0R = (gptr<const T>)d.f0 + (size_t)Rr * nv;
+    const gptr<const T> f1R = DIA ? (gptr<const T>)d.f1 + (size_t)Rr * nv : f0R;
+    const gptr<const double> nt = G((const double *)d.nt64);
+    const int bf = R >= 0 ? 0 : -1 - R;
+    const int slot = R >= 0 ? 0 : G(d.ubf_slot)[bf];
+    const gptr<const double> mb = G((const double *)d.mb64) + (size_t)slot * nv;
+    const gptr<const double> mb1 = G((const double *)d.mb1_64) + (size_t)slot * nv;
+    double acc[6] = {0, 0, 0, 0, 0, 0}, bin[6] = {0, 0, 0, 0, 0, 0}, out = 0.0, in = 0.0;
+    for (int pos = lane; pos < g.nv; pos += 64) {
+        const double x0 = nt[4 * (size_t)pos], x1 = nt[4 * (size_t)pos + 1], x2 = nt[4 * (size_t)pos + 2];
+        const double w = nt[4 * (size_t)pos + 3];
+        const double xn = x0 * n0 + x1 * n1 + x2 * n2;
+        if (xn == 0.0) continue;
+        double a0, a1;
+        bool add = true;
+        if (xn > 0.0) {
+            a0 = (double)f0L[pos];
+            a1 = DIA ? (double)f1L[pos] : 0.0;
+            if (R < 0) out += w * xn * a0;
+        } else if (R >= 0) {
+            a0 = (double)f0R[pos];
+            a1 = DIA ? (double)f1R[pos] : 0.0;
+        } else {
+            a0 = mb[pos];
+            a1 = DIA ? mb1[pos] : 0.0;
+            in += w * (-xn) * a0;
+            add = false;   // into bin: scaled by the wall density once it is known
+        }
+        const double ww = w * xn, xx = x0 * x0 + x1 * x1 + x2 * x2;
+        double *t = add ? acc : bin;
+        t[0] += ww * a0;
+        t[1] += ww * x0 * a0;
+        t[2] += ww * x1 * a0;
+        t[3] += ww * x2 * a0;
+        t[4] += ww * (xx * a0 + a1);
+        t[5] += ww * a1;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[k] = wave_sum(acc[k]);
+    if (R < 0) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) bin[k] = wave_sum(bin[k]);
+        out = wave_sum(out);
+        in = wave_sum(in);
+        const double sc = C.bc.kind[slot] == 1 ? C.bc.rho[slot] : out / in;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[k] += sc * bin[k];
+        if (lane < 6) G(d.ubin)[6 * (size_t)bf + lane] = bin[lane];
+    }
+    if (lane < 6) G(d.uFk)[6 * (size_t)f + lane] = acc[lane];
+}
+
+// Interior faces, one thread each: the macroscopic flux of the current W;
+// mode 0 keeps F_kin - F as the face's high-order terms, mode 1 stores
+// F + HoT and Gamma for the residual.
+__global__ __launch_bounds__(256) void k_umac_iflux(GSIS_SPAN_ARGS, int mode)
+{
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    const int f = blk * blockDim.x + threadIdx.x;
+    if (f >= g.unface) return;
+    const int L = G(d.uf_cell)[2 * (size_t)f], R = G(d.uf_cell)[2 * (size_t)f + 1];
+    if (R < 0) return;
+    const size_t n = g.ncell;
+    double fg[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) fg[k] = G(d.uf_geo)[9 * (size_t)f + k];
+    double F[6], Gam;
+    uface_flux(g, soa(d.P, n, L), soa(d.P, n, R), soa(d.grad, n, L), soa(d.grad, n, R), fg, F, &Gam);
+    if (mode == 0) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) G(d.ufix)[6 * (size_t)f + k] = G(d.uFk)[6 * (size_t)f + k] - F[k];
+        if (g.species != 1) G(d.ufix)[6 * (size_t)f + 5] = 0.0;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) G(d.uFf)[7 * (size_t)f + k] = F[k] + G(d.ufix)[6 * (size_t)f + k];
+        G(d.uFf)[7 * (size_t)f + 6] = Gam;
+    }
+}
+
+// Boundary faces, one wave each: F_eq of the owner's Maxwellian (outgoing
+// half-range sums over the nodes, incoming part the boundary Maxwellian at
+// the face's density rule); mode 0 keeps F_kin - F_eq(W^{n+1/2}), mode 1
+// stores fixed part + F_eq(W^m) and Gamma.
+__global__ __launch_bounds__(256) void k_umac_bflux(GSIS_SPAN_ARGS, int mode)
+{
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    const int bf = __builtin_amdgcn_readfirstlane(blk * 4 + (int)(threadIdx.x >> 6));
+    if (bf >= g.unbf) return;
+    const int lane = threadIdx.x & 63;
+    const int f = G(d.ubf_face)[bf], cell = G(d.ubf_cell)[bf], slot = G(d.ubf_slot)[bf];
+    const gptr<const double> fg = G((const double *)d.uf_geo) + 9 * (size_t)f;
+    const double n0 = fg[1], n1 = fg[2], n2 = fg[3], h = fg[4];
+    const Soa<double> P = soa(d.P, (size_t)g.ncell, cell);
+    const double rho = P[0], u0 = P[1], u1 = P[2], u2 = P[3], T = P[4], iT = 1.0 / T;
+    const double piT = PI * T, K = rho / (piT * sqrt(piT));
+    const double h1 = g.species == 1 ? 0.5 * g.dr * P[5] : 0.0;
+    const gptr<const double> nt = G((const double *)d.nt64);
+    double s0 = 0.0, s1[3] = {0.0, 0.0, 0.0}, s4 = 0.0;
+    for (int pos = lane; pos < g.nv; pos += 64) {
+        const double x0 = nt[4 * (size_t)pos], x1 = nt[4 * (size_t)pos + 1], x2 = nt[4 * (size_t)pos + 2];
+        const double xn = x0 * n0 + x1 * n1 + x2 * n2;
+        if (!(xn > 0.0)) continue;
+        const double cx = x0 - u0, cy = x1 - u1, cz = x2 - u2;
+        const double ex = nt[4 * (size_t)pos + 3] * exp_core(fmax(-(cx * cx + cy * cy + cz * cz) * iT, -745.0)) * xn;
+        s0 += ex;
+        s1[0] += ex * x0;
+        s1[1] += ex * x1;
+        s1[2] += ex * x2;
+        s4 += ex * (x0 * x0 + x1 * x1 + x2 * x2);
+    }
+    s0 = wave_sum(s0);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) s1[q] = wave_sum(s1[q]);
+    s4 = wave_sum(s4);
+    if (lane != 0) return;
+    double out[6];
+    out[0] = K * s0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) out[1 + q] = K * s1[q];
+    out[4] = K * s4 + h1 * out[0];
+    out[5] = h1 * out[0];
+    const gptr<const double> bin = G((const double *)d.ubin) + 6 * (size_t)bf;
+    const double sc = C.bc.kind[slot] == 1 ? C.bc.rho[slot] : out[0] / (-bin[0]);
+    double Fe[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Fe[k] = out[k] + sc * bin[k];
+    if (mode == 0) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) G(d.ufix)[6 * (size_t)f + k] = G(d.uFk)[6 * (size_t)f + k] - Fe[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) G(d.uFf)[7 * (size_t)f + k] = G(d.ufix)[6 * (size_t)f + k] + Fe[k];
+        const double un = u0 * n0 + u1 * n1 + u2 * n2;
+        G(d.uFf)[7 * (size_t)f + 6] = fabs(un) + P[8] + g.Cd * P[9] / (rho * h);
+    }
+}
+
+// Residual and diagonal of every cell from the face fluxes (S / V per face,
+// the sign of the owner's side), the rotational relaxation on the Er row; one
+// atomic max of D per wave into the slot's partials.
+__global__ __launch_bounds__(256) void k_umac_res(GSIS_SPAN_ARGS, int slot)
+{
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    const int cell = blk * blockDim.x + threadIdx.x;
+    double D = 0.0;
+    if (cell < g.ncell) {
+        const size_t n = g.ncell;
+        const Soa<double> P = soa(d.P, n, cell);
+        double res[6] = {0, 0, 0, 0, 0, 0}, sumG = 0.0;
+        const double iV = 1.0 / G(d.uvol)[cell];
+        const int first = G(d.ucf_first)[cell], cnt = G(d.ucf_first)[cell + 1] - first;
+        for (int k = 0; k < cnt; ++k) {
+            const int fs = G(d.ucf_face)[first + k], f = fs >> 1;
+            const double sv = G(d.uf_geo)[9 * (size_t)f] * iV, sg = (fs & 1) ? -1.0 : 1.0;
+            const gptr<const double> o = G((const double *)d.uFf) + 7 * (size_t)f;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) res[q] -= sg * o[q] * sv;
+            sumG += o[6] * sv;
+        }
+        if (g.species != 1) res[5] = 0.0;
+        const double invtau = P[10];
+        if (g.species == 1) {
+            const double T = (3.0 * P[4] + g.dr * P[5]) / (3.0 + g.dr);
+            res[5] += 0.5 * g.dr * P[0] * (T - P[5]) * invtau / g.Zr;
+        }
+        const double umag = sqrt(P[1] * P[1] + P[2] * P[2] + P[3] * P[3]);
+        const double idt = (umag + P[8] + g.Cd * P[9] / (P[0] * g.uhmin)) / (g.macro_cfl * g.uhmin);
+        D = idt + 0.5 * sumG;
+        const Soa<double> r = soa(d.R, n, cell);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) r[q] = res[q];
+        G(d.Src)[cell] = g.species == 1 ? invtau / g.Zr : 0.0;
+        if (!(D > 0.0 && isfinite(D))) {
+            atomicOr(d.errflag, 2);
+            D = 0.0;
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) D = fmax(D, __shfl_xor(D, m, 64));
+    if ((threadIdx.x & 63) == 0 && D > 0.0)
+        atomicMax(&d.dmax[(size_t)(slot * DSLOT + ((blk * 4 + (int)(threadIdx.x >> 6)) & (DSLOT - 1))) * DSTRIDE],
+                  (unsigned long long)__double_as_longlong(D));
+}
+
+// W += R / D* (the Er row with its relaxation on the diagonal) and the new
+// prims; block 0 clears the partials of the other slot (the previous
+// iteration's).
+__global__ __launch_bounds__(256) void k_umac_advance(GSIS_SPAN_ARGS, int slot)
+{
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    double Dm = __longlong_as_double((long long)G(d.dmax)[(size_t)(slot * DSLOT + (threadIdx.x & (DSLOT - 1))) * DSTRIDE]);
+#pragma unroll
+    for (int m = 1; m < DSLOT; m <<= 1) Dm = fmax(Dm, __shfl_xor(Dm, m, 64));
+    if (blk == 0 && (int)threadIdx.x < DSLOT) G(d.dmax)[(size_t)((slot ^ 1) * DSLOT + threadIdx.x) * DSTRIDE] = 0ull;
+    const int cell = blk * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell) return;
+    const size_t n = g.ncell;
+    const double iDm = 1.0 / Dm;
+    const Soa<double> W = soa(d.W, n, cell);
+    const Soa<double> r = soa(d.R, n, cell);
+    double Wn[6];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Wn[k] = W[k] + r[k] * iDm;
+    Wn[5] = g.species == 1 ? W[5] + r[5] / (Dm + G(d.Src)[cell]) : W[5];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) W[k] = Wn[k];
+    prim_from_W(g, Wn, soa(d.P, n, cell));
+}
+
+hipError_t launch_umacro(const Target &t, int iters, hipStream_t s)
+{
+    const Geo &g = t.host->g;
+    const Span sp{t.cases, nullptr};
+    const dim3 cells((g.ncell + 255) / 256), faces((g.unface + 255) / 256);
+    const dim3 fwaves((g.unface + 3) / 4), bwaves((std::max(g.unbf, 1) + 3) / 4);
+    hipLaunchKernelGGL(k_mac_reset, dim3(1), dim3(64), 0, s, GSIS_SPAN(sp));
+    hipLaunchKernelGGL(k_mac_init, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(sp));
+    hipLaunchKernelGGL(k_umac_grad, cells, dim3(256), 0, s, GSIS_SPAN(sp));
+    if (t.fp32) {
+        if (t.dia) hipLaunchKernelGGL((k_umac_kin<float, true>), fwaves, dim3(256), 0, s, GSIS_SPAN(sp));
+        else hipLaunchKernelGGL((k_umac_kin<float, false>), fwaves, dim3(256), 0, s, GSIS_SPAN(sp));
+    } else {
+        if (t.dia) hipLaunchKernelGGL((k_umac_kin<double, true>), fwaves, dim3(256), 0, s, GSIS_SPAN(sp));
+        else hipLaunchKernelGGL((k_umac_kin<double, false>), fwaves, dim3(256), 0, s, GSIS_SPAN(sp));
+    }
+    hipLaunchKernelGGL(k_umac_iflux, faces, dim3(256), 0, s, GSIS_SPAN(sp), 0);
+    if (g.unbf > 0) hipLaunchKernelGGL(k_umac_bflux, bwaves, dim3(256), 0, s, GSIS_SPAN(sp), 0);
+    for (int it = 0; it < iters; ++it) {
+        const int slot = it & 1;
+        if (it > 0) hipLaunchKernelGGL(k_umac_grad, cells, dim3(256), 0, s, GSIS_SPAN(sp));
+        hipLaunchKernelGGL(k_umac_iflux, faces, dim3(256), 0, s, GSIS_SPAN(sp), 1);
+        if (g.unbf > 0) hipLaunchKernelGGL(k_umac_bflux, bwaves, dim3(256), 0, s, GSIS_SPAN(sp), 1);
+        hipLaunchKernelGGL(k_umac_res, cells, dim3(256), 0, s, GSIS_SPAN(sp), slot);
+        hipLaunchKernelGGL(k_umac_advance, cells, dim3(256), 0, s, GSIS_SPAN(sp), slot);
+    }
+    hipLaunchKernelGGL(k_mac_final, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(sp));
     return hipGetLastError();
 }
 

@@ -30,10 +30,13 @@ namespace gsis {
 // Incoming density scale of every boundary face, from f^n of its cell: a
 // diffuse wall gets rho_w = sum_{xi.n>0} w xi.n f0 / sum_{xi.n<0} w |xi.n| M_w
 // (zero discrete mass flux through the wall), an inflow face its fixed
-// density.  One wave per face, FP64 sums, lane partials combined by a fixed
-// butterfly.
+// density.  With a GSIS correction pending (committed to the moments, not yet
+// to the stored VDF: a source-iteration pass never reads f^n otherwise) f^n
+// is the stored row plus M(W^{n+1}) - M(W^{n+1/2}) of Eq. (updatef), formed
+// here per node.  One wave per face, FP64 sums, lane partials combined by a
+// fixed butterfly.
 template <typename T>
-__global__ __launch_bounds__(256) void k_uface_scale(GSIS_SPAN_ARGS)
+__global__ __launch_bounds__(256) void k_uface_scale(GSIS_SPAN_ARGS, int pend)
 {
     int b;
     const Case &C = case_of(span_cases, span_map, b);
@@ -48,12 +51,26 @@ __global__ __launch_bounds__(256) void k_uface_scale(GSIS_SPAN_ARGS)
         const size_t nv = (size_t)g.nv;
         const T *f = (const T *)C.d.f0 + (size_t)cell * nv;
         const double *mb = C.d.mb64 + (size_t)slot * nv;
+        const double *c = C.d.corr + (size_t)cell * NCORR;
+        const double pn = PI * c[4], po = PI * c[10];
+        const double an = c[0] / (pn * sqrt(pn)), ao = c[6] / (po * sqrt(po));
+        const double itn = 1.0 / c[4], ito = 1.0 / c[10];
         double out = 0.0, in = 0.0;
         for (int pos = lane; pos < g.nv; pos += 64) {
             const double *t = C.d.nt64 + 4 * (size_t)pos;
             const double xn = t[0] * nx + t[1] * ny + t[2] * nz;
-            if (xn > 0.0) out += t[3] * xn * (double)f[pos];
-            else if (xn < 0.0) in += t[3] * (-xn) * mb[pos];
+            if (xn > 0.0) {
+                double fv = (double)f[pos];
+                if (pend) {
+                    const double ex = t[0] - c[1], ey = t[1] - c[2], ez = t[2] - c[3];
+                    const double ox = t[0] - c[7], oy = t[1] - c[8], oz = t[2] - c[9];
+                    fv += an * exp_core(fmax(-(ex * ex + ey * ey + ez * ez) * itn, -745.0)) -
+                          ao * exp_core(fmax(-(ox * ox + oy * oy + oz * oz) * ito, -745.0));
+                }
+                out += t[3] * xn * fv;
+            } else if (xn < 0.0) {
+                in += t[3] * (-xn) * mb[pos];
+            }
         }
         scale = wave_sum(out) / wave_sum(in);
     }
@@ -192,13 +209,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) 
     }
 }
 
-hipError_t launch_uface_scale(const Target &t, hipStream_t s)
+hipError_t launch_uface_scale(const Target &t, int pending, hipStream_t s)
 {
     const Geo &g = t.host->g;
     if (g.unbf == 0) return hipSuccess;
     const dim3 grid((g.unbf + 3) / 4);
-    if (t.fp32) hipLaunchKernelGGL(k_uface_scale<float>, grid, dim3(256), 0, s, t.cases, nullptr);
-    else hipLaunchKernelGGL(k_uface_scale<double>, grid, dim3(256), 0, s, t.cases, nullptr);
+    if (t.fp32) hipLaunchKernelGGL(k_uface_scale<float>, grid, dim3(256), 0, s, t.cases, nullptr, pending);
+    else hipLaunchKernelGGL(k_uface_scale<double>, grid, dim3(256), 0, s, t.cases, nullptr, pending);
     return hipGetLastError();
 }
 

@@ -93,8 +93,13 @@ class Context:
             vol = np.ascontiguousarray(m.volume, dtype=np.float64)
             fc = np.ascontiguousarray(m.face_cell, dtype=np.int32)
             fg = np.ascontiguousarray(m.face_geom, dtype=np.float64)
-            self._check(self.L.gsis_set_spatial_mesh(self.h, vol.size, vol.ctypes.data_as(C.c_void_p), fc.shape[0],
-                                                     fc.ctypes.data_as(C.c_void_p), fg.ctypes.data_as(C.c_void_p)),
+            cc = fcc = None
+            if m.face_center is not None:
+                cc = np.ascontiguousarray(m.centroid, dtype=np.float64)
+                fcc = np.ascontiguousarray(m.face_center, dtype=np.float64)
+            ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
+            self._check(self.L.gsis_set_spatial_mesh(self.h, vol.size, ptr(vol), fc.shape[0], ptr(fc), ptr(fg),
+                                                     ptr(cc), ptr(fcc)),
                         "gsis_set_spatial_mesh")
 
     def _check(self, st: int, where: str):

@@ -24,12 +24,16 @@ def raw_ctx(case, with_list=True):
     return L, h
 
 
-def set_mesh(L, h, vol, fc, fg):
+def set_mesh(L, h, vol, fc, fg, cc=None, fcc=None):
     vol = np.ascontiguousarray(vol, dtype=np.float64)
     fc = np.ascontiguousarray(fc, dtype=np.int32)
     fg = np.ascontiguousarray(fg, dtype=np.float64)
+    ptr = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(C.c_void_p)
+    keep = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (cc, fcc)]
     return L.gsis_set_spatial_mesh(h, vol.size, vol.ctypes.data_as(C.c_void_p), fc.shape[0],
-                                   fc.ctypes.data_as(C.c_void_p), fg.ctypes.data_as(C.c_void_p))
+                                   fc.ctypes.data_as(C.c_void_p), fg.ctypes.data_as(C.c_void_p),
+                                   None if keep[0] is None else keep[0].ctypes.data_as(C.c_void_p),
+                                   None if keep[1] is None else keep[1].ctypes.data_as(C.c_void_p))
 
 
 def test_lattice_meshes_are_accepted():
@@ -57,6 +61,24 @@ def test_bad_meshes_are_rejected():
         L, h = raw_ctx(base)
         assert set_mesh(L, h, vol, fc, fg) == EINVAL
         L.gsis_destroy(h)
+
+
+def test_bad_centroids_are_rejected():
+    """Centroids come in pairs, and a face's centroid distance along its normal
+    must be positive (a cell centroid on the wrong side of a face)."""
+    base = I.cavity(2, 4, 0.5)
+    m = I.lattice_mesh(2, 2, 2, 1.0, 1.0, 1.0, split=I.TET)
+    L, h = raw_ctx(base)
+    assert set_mesh(L, h, m.volume, m.face_cell, m.face_geom, m.centroid, None) == EINVAL
+    L.gsis_destroy(h)
+    bad = m.centroid.copy()
+    bad[0] = m.centroid[m.face_cell[0, 1]] if m.face_cell[0, 1] >= 0 else bad[0] + 10.0
+    L, h = raw_ctx(base)
+    assert set_mesh(L, h, m.volume, m.face_cell, m.face_geom, bad, m.face_center) == EINVAL
+    L.gsis_destroy(h)
+    L, h = raw_ctx(base)
+    assert set_mesh(L, h, m.volume, m.face_cell, m.face_geom, m.centroid, m.face_center) == 0
+    L.gsis_destroy(h)
 
 
 def test_cyclic_mesh_is_rejected():

@@ -9,9 +9,12 @@ solid body as a hole with diffuse walls), the diatomic block flow, a block
 flow on a refined velocity mesh and a finite time step.  Bars: one pass from
 a seeded random VDF, FP64 1e-12 and FP32 3e-6 relative per point; several
 passes from the initial Maxwellian, FP64 1e-12 and FP32 1e-5 on rho, u, T,
-and the volume-weighted residual; a mesh of whole hexahedra against the
-box path on the GPU; repeated runs bit for bit.
+and the volume-weighted residual; GSIS iterations (kinetic pass and the
+GSIS-II correction on the mesh) against the oracle, FP64 1e-12 and FP32 1e-5;
+a mesh of whole hexahedra against the box path on the GPU, kinetic passes and
+GSIS; repeated runs bit for bit.
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -147,13 +150,67 @@ def test_unstructured_runs_repeat_bit_for_bit(dtype):
     assert np.array_equal(out[0], out[1])
 
 
-def test_unstructured_refuses_the_macroscopic_correction():
-    case = CASES["tet_cavity"]
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["tet_cavity", "mixed_block", "n2_mixed_block", "tet_block_refined"])
+def test_unstructured_gsis(name, dtype):
+    case = CASES[name]
+    say(f"[umesh gsis] {name} {dtype}")
+    s = Solver(case, dtype)
+    o = Oracle(case)
+    s.init_maxwellian()
+    o.init_maxwellian()
+    for _ in range(2):
+        s.kinetic_step(1)
+        assert o.step(1) == 0
+        s.gsis_correct(25)
+        assert o.gsis_correct(25) == 0
+    s.kinetic_step(1)
+    assert o.step(1) == 0
+    eg, eo = s.residual(), o.residual()
+    e = field_errors(s.moments(), o.moments())
+    say(f"  errors {e}; residual {eg} oracle {eo}")
+    tol = 1e-12 if dtype == "fp64" else 1e-5
+    assert max(e.values()) <= tol
+    assert np.abs(eg - eo).max() <= (1e-9 if dtype == "fp64" else 1e-3) * np.abs(eo).max()
+
+
+def test_hex_mesh_gsis_matches_the_box_path():
+    """GSIS on whole hexahedra given as an unstructured mesh and on the box:
+    the two GPU solves agree to rounding."""
+    say("[umesh hex gsis vs box]")
+    base = I.small_block(n=(8, 6, 6), blk=((3, 5), (2, 4), (2, 4)), m=8)
+    box = I.with_velocity_list(base, I.tensor_velocity_list(base.nv, base.vmin, base.vmax))
+    hexc = I.on_mesh(box, block_mesh(box, (8, 6, 6), I.HEX))
+    a, b = Solver(box, "fp64"), Solver(hexc, "fp64")
+    a.init_maxwellian()
+    b.init_maxwellian()
+    for _ in range(2):
+        a.kinetic_step(1)
+        b.kinetic_step(1)
+        a.gsis_correct(30)
+        b.gsis_correct(30)
+    a.kinetic_step(1)
+    b.kinetic_step(1)
+    fluid = ~box.solid_mask().astype(bool)
+    e = field_errors(b.moments(), a.moments()[fluid])
+    say(f"  errors {e}")
+    assert max(e.values()) <= 1e-12
+
+
+def test_unstructured_refusals():
     say("[umesh refusals]")
+    case = CASES["tet_cavity"]
     s = Solver(case, "fp64")
     s.init_maxwellian()
     s.kinetic_step(1)
-    for call in (lambda: s.gsis_correct(10), lambda: s.autotune(1), lambda: s.set_tile(4, 4, 4, 128)):
+    for call in (lambda: s.precondition(10, 1), lambda: s.autotune(1), lambda: s.set_tile(4, 4, 4, 128)):
         with pytest.raises(GsisError) as ei:
             call()
         assert ei.value.status == -2
+    bare = dataclasses.replace(case, mesh=dataclasses.replace(case.mesh, face_center=None))
+    t = Solver(bare, "fp64")
+    t.init_maxwellian()
+    t.kinetic_step(1)
+    with pytest.raises(GsisError) as ei:
+        t.gsis_correct(5)
+    assert ei.value.status == -2
