@@ -427,7 +427,8 @@ def unstructured_mesh(steps, warmup):
     tetrahedra, the refined velocity mesh of c3r): the level-by-level sweep
     over velocity classes, FP64 and FP32, with the phase times and the
     sweep's and moments' HBM rates (algorithmic bytes: every point written
-    once by the sweep and read once by the moment kernel)."""
+    once by the sweep and read once by the moment kernel); then the GSIS step
+    on the same mesh."""
     import torch
     case = workload("c3t")
     pts = case.nfluid * case.nvel
@@ -442,6 +443,19 @@ def unstructured_mesh(steps, warmup):
                       "phases_ms_per_pass": {k: v[0] / steps for k, v in prof.items() if v[1]},
                       "sweep_gbs": pts * esz / (sweep_ms / n * 1e-3) / 1e9,
                       "moments_gbs": pts * esz / (mom_ms / n * 1e-3) / 1e9}
+        del r
+        torch.cuda.empty_cache()
+    # the GSIS step on the same mesh: kinetic pass + GSIS-II correction (300 inner
+    # iterations on the tetrahedra) + residual
+    import dataclasses
+    gcase = dataclasses.replace(case, gsis=True, macro_iters=300)
+    res["gsis"] = {"macro_iters": 300, "step": "kinetic pass + gsis_correct + residual"}
+    for dtype in ("fp64", "fp32"):
+        r = run_gpu(gcase, dtype, max(2, steps // 2), 1, 300, None)
+        ns = max(2, steps // 2)
+        res["gsis"][dtype] = {"value": pts * ns / r["seconds"], "ms_per_step": r["seconds"] / ns * 1e3,
+                              "phases_ms_per_step": {k: v[0] / ns for k, v in r["prof"].items() if v[1]},
+                              "eps": r["eps"]}
         del r
         torch.cuda.empty_cache()
     return res
