@@ -41,7 +41,9 @@
  *   gsis_correct       Sec. 3.3, GSIS-II macroscopic equations with the
  *                      high-order terms of Eq. (full_constitutive), Rusanov
  *                      convective flux, the diagonal of Eq. (res_macro) in a
- *                      point-Jacobi iteration, then Eq. (updatef).
+ *                      point-Jacobi iteration, then Eq. (updatef); on an
+ *                      unstructured mesh the same solve over faces of any
+ *                      normal (least-squares cell gradients).
  *   residual           Eq. (convergence_critertion), Sec. 5.
  */
 #define _GNU_SOURCE
