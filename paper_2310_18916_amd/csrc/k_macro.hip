@@ -832,13 +832,14 @@ __global__ __launch_bounds__(256) void k_umac_kin(GSIS_SPAN_ARGS)
             add = false;   // into bin: scaled by the wall density once it is known
         }
         const double ww = w * xn, xx = x0 * x0 + x1 * x1 + x2 * x2;
-        double *t = add ? acc : bin;
-        t[0] += ww * a0;
-        t[1] += ww * x0 * a0;
-        t[2] += ww * x1 * a0;
-        t[3] += ww * x2 * a0;
-        t[4] += ww * (xx * a0 + a1);
-        t[5] += ww * a1;
+        const double c[6] = {ww * a0, ww * x0 * a0, ww * x1 * a0, ww * x2 * a0, ww * (xx * a0 + a1), ww * a1};
+        if (add) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc[k] += c[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) bin[k] += c[k];
+        }
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k) acc[k] = wave_sum(acc[k]);
@@ -885,64 +886,96 @@ __global__ __launch_bounds__(256) void k_umac_iflux(GSIS_SPAN_ARGS, int mode)
     }
 }
 
-// Boundary faces, one wave each: F_eq of the owner's Maxwellian (outgoing
+// Boundary faces, UBF to a wave: F_eq of the owner's Maxwellian (outgoing
 // half-range sums over the nodes, incoming part the boundary Maxwellian at
-// the face's density rule); mode 0 keeps F_kin - F_eq(W^{n+1/2}), mode 1
-// stores fixed part + F_eq(W^m) and Gamma.
+// the face's density rule); the wave reads every node's velocity once for
+// its UBF faces.  Mode 0 keeps F_kin - F_eq(W^{n+1/2}), mode 1 stores fixed
+// part + F_eq(W^m) and Gamma.
+constexpr int UBF = 8;
+
 __global__ __launch_bounds__(256) void k_umac_bflux(GSIS_SPAN_ARGS, int mode)
 {
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
     const Geo &g = C.g;
     const Dev &d = C.d;
-    const int bf = __builtin_amdgcn_readfirstlane(blk * 4 + (int)(threadIdx.x >> 6));
-    if (bf >= g.unbf) return;
+    const int bf0 = __builtin_amdgcn_readfirstlane((blk * 4 + (int)(threadIdx.x >> 6)) * UBF);
+    if (bf0 >= g.unbf) return;
     const int lane = threadIdx.x & 63;
-    const int f = G(d.ubf_face)[bf], cell = G(d.ubf_cell)[bf], slot = G(d.ubf_slot)[bf];
-    const gptr<const double> fg = G((const double *)d.uf_geo) + 9 * (size_t)f;
-    const double n0 = fg[1], n1 = fg[2], n2 = fg[3], h = fg[4];
-    const Soa<double> P = soa(d.P, (size_t)g.ncell, cell);
-    const double rho = P[0], u0 = P[1], u1 = P[2], u2 = P[3], T = P[4], iT = 1.0 / T;
-    const double piT = PI * T, K = rho / (piT * sqrt(piT));
-    const double h1 = g.species == 1 ? 0.5 * g.dr * P[5] : 0.0;
+    int f[UBF], cell[UBF], slot[UBF];
+    double n[UBF][3], u[UBF][3], iT[UBF], s0[UBF], s1[UBF][3], s4[UBF];
+#pragma unroll
+    for (int q = 0; q < UBF; ++q) {
+        const int bf = min(bf0 + q, g.unbf - 1);
+        f[q] = G(d.ubf_face)[bf];
+        cell[q] = G(d.ubf_cell)[bf];
+        slot[q] = G(d.ubf_slot)[bf];
+        const gptr<const double> fg = G((const double *)d.uf_geo) + 9 * (size_t)f[q];
+        n[q][0] = fg[1];
+        n[q][1] = fg[2];
+        n[q][2] = fg[3];
+        const Soa<double> P = soa(d.P, (size_t)g.ncell, cell[q]);
+        u[q][0] = P[1];
+        u[q][1] = P[2];
+        u[q][2] = P[3];
+        iT[q] = 1.0 / P[4];
+        s0[q] = s4[q] = 0.0;
+        s1[q][0] = s1[q][1] = s1[q][2] = 0.0;
+    }
     const gptr<const double> nt = G((const double *)d.nt64);
-    double s0 = 0.0, s1[3] = {0.0, 0.0, 0.0}, s4 = 0.0;
     for (int pos = lane; pos < g.nv; pos += 64) {
         const double x0 = nt[4 * (size_t)pos], x1 = nt[4 * (size_t)pos + 1], x2 = nt[4 * (size_t)pos + 2];
-        const double xn = x0 * n0 + x1 * n1 + x2 * n2;
-        if (!(xn > 0.0)) continue;
-        const double cx = x0 - u0, cy = x1 - u1, cz = x2 - u2;
-        const double ex = nt[4 * (size_t)pos + 3] * exp_core(fmax(-(cx * cx + cy * cy + cz * cz) * iT, -745.0)) * xn;
-        s0 += ex;
-        s1[0] += ex * x0;
-        s1[1] += ex * x1;
-        s1[2] += ex * x2;
-        s4 += ex * (x0 * x0 + x1 * x1 + x2 * x2);
+        const double w = nt[4 * (size_t)pos + 3], xx = x0 * x0 + x1 * x1 + x2 * x2;
+#pragma unroll
+        for (int q = 0; q < UBF; ++q) {
+            const double xn = x0 * n[q][0] + x1 * n[q][1] + x2 * n[q][2];
+            if (!(xn > 0.0)) continue;
+            const double cx = x0 - u[q][0], cy = x1 - u[q][1], cz = x2 - u[q][2];
+            const double ex = w * exp_core(fmax(-(cx * cx + cy * cy + cz * cz) * iT[q], -745.0)) * xn;
+            s0[q] += ex;
+            s1[q][0] += ex * x0;
+            s1[q][1] += ex * x1;
+            s1[q][2] += ex * x2;
+            s4[q] += ex * xx;
+        }
     }
-    s0 = wave_sum(s0);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) s1[q] = wave_sum(s1[q]);
-    s4 = wave_sum(s4);
-    if (lane != 0) return;
-    double out[6];
-    out[0] = K * s0;
+    for (int q = 0; q < UBF; ++q) {
+        s0[q] = wave_sum(s0[q]);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) out[1 + q] = K * s1[q];
-    out[4] = K * s4 + h1 * out[0];
-    out[5] = h1 * out[0];
-    const gptr<const double> bin = G((const double *)d.ubin) + 6 * (size_t)bf;
-    const double sc = C.bc.kind[slot] == 1 ? C.bc.rho[slot] : out[0] / (-bin[0]);
-    double Fe[6];
+        for (int k = 0; k < 3; ++k) s1[q][k] = wave_sum(s1[q][k]);
+        s4[q] = wave_sum(s4[q]);
+    }
+    // lane q finishes face q
 #pragma unroll
-    for (int k = 0; k < 6; ++k) Fe[k] = out[k] + sc * bin[k];
-    if (mode == 0) {
+    for (int q = 0; q < UBF; ++q) {
+        if (lane != q || bf0 + q >= g.unbf) continue;
+        const Soa<double> P = soa(d.P, (size_t)g.ncell, cell[q]);
+        const double rho = P[0], T = P[4];
+        const double piT = PI * T, K = rho / (piT * sqrt(piT));
+        const double h1 = g.species == 1 ? 0.5 * g.dr * P[5] : 0.0;
+        double out[6];
+        out[0] = K * s0[q];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) G(d.ufix)[6 * (size_t)f + k] = G(d.uFk)[6 * (size_t)f + k] - Fe[k];
-    } else {
+        for (int k = 0; k < 3; ++k) out[1 + k] = K * s1[q][k];
+        out[4] = K * s4[q] + h1 * out[0];
+        out[5] = h1 * out[0];
+        const int bf = bf0 + q;
+        const gptr<const double> bin = G((const double *)d.ubin) + 6 * (size_t)bf;
+        const double sc = C.bc.kind[slot[q]] == 1 ? C.bc.rho[slot[q]] : out[0] / (-bin[0]);
+        double Fe[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) G(d.uFf)[7 * (size_t)f + k] = G(d.ufix)[6 * (size_t)f + k] + Fe[k];
-        const double un = u0 * n0 + u1 * n1 + u2 * n2;
-        G(d.uFf)[7 * (size_t)f + 6] = fabs(un) + P[8] + g.Cd * P[9] / (rho * h);
+        for (int k = 0; k < 6; ++k) Fe[k] = out[k] + sc * bin[k];
+        const size_t ff = f[q];
+        if (mode == 0) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) G(d.ufix)[6 * ff + k] = G(d.uFk)[6 * ff + k] - Fe[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) G(d.uFf)[7 * ff + k] = G(d.ufix)[6 * ff + k] + Fe[k];
+            const double un = u[q][0] * n[q][0] + u[q][1] * n[q][1] + u[q][2] * n[q][2];
+            G(d.uFf)[7 * ff + 6] = fabs(un) + P[8] + g.Cd * P[9] / (rho * G(d.uf_geo)[9 * ff + 4]);
+        }
     }
 }
 
@@ -1029,7 +1062,7 @@ hipError_t launch_umacro(const Target &t, int iters, hipStream_t s)
     const Geo &g = t.host->g;
     const Span sp{t.cases, nullptr};
     const dim3 cells((g.ncell + 255) / 256), faces((g.unface + 255) / 256);
-    const dim3 fwaves((g.unface + 3) / 4), bwaves((std::max(g.unbf, 1) + 3) / 4);
+    const dim3 fwaves((g.unface + 3) / 4), bwaves(((std::max(g.unbf, 1) + UBF - 1) / UBF + 3) / 4);
     hipLaunchKernelGGL(k_mac_reset, dim3(1), dim3(64), 0, s, GSIS_SPAN(sp));
     hipLaunchKernelGGL(k_mac_init, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(sp));
     hipLaunchKernelGGL(k_umac_grad, cells, dim3(256), 0, s, GSIS_SPAN(sp));
