@@ -12,7 +12,9 @@ cells, and the residual (tests/golden/make_fullsize.py):
 * c4, the nitrogen block flow at 64x48x48 x 32^3: after a GSIS iteration and
   after the pass that follows it;
 * c3t, the Mach-5 block flow on 291,840 tetrahedra with the 7788-node refined
-  velocity mesh: after one and two passes (the stored-VDF oracle).
+  velocity mesh: after one and two passes, and after a GSIS iteration (the
+  correction on the tetrahedra) and the pass that follows it (the stored-VDF
+  oracle).
 
 The GPU runs the same plan at full size, its first pass being the
 autotuner's (the launch configuration bench.py uses), in FP64 and FP32.
@@ -59,13 +61,16 @@ def groups(nm):
 
 
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
-@pytest.mark.parametrize("workload", ["c2", "c3", "c4", "c3t"])
+WORKLOADS = {"c2": I.c2, "c3": I.c3, "c4": I.c4, "c3t": I.c3t, "c3t_gsis": I.c3t}
+
+
+@pytest.mark.parametrize("workload", ["c2", "c3", "c4", "c3t", "c3t_gsis"])
 def test_full_size_matches_streaming_oracle(workload, dtype):
     path = os.path.join(GOLDEN, f"fullsize_{workload}.npz")
     if not os.path.exists(path):
         pytest.skip(f"{path} not written yet (tests/golden/make_fullsize.py)")
     gold = np.load(path, allow_pickle=False)
-    case = getattr(I, workload)()
+    case = WORKLOADS[workload]()
     assert str(gold["workload"]) == case.name
     plan = [str(x) for x in gold["plan"]]
     cells = gold["cells"]
