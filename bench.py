@@ -36,6 +36,8 @@ def parse():
                    help="headline workload (c5 runs only the 64-cavity batch)")
     p.add_argument("--no-gsis-extras", action="store_true",
                    help="skip the c2 GSIS step, convergence and second-order runs beside a c3/c4 headline")
+    p.add_argument("--gsis", action="store_true",
+                   help="GSIS steps (kinetic pass + correction + residual) on the headline workload")
     p.add_argument("--no-umesh", action="store_true",
                    help="skip the block flow on the tetrahedral spatial mesh beside a c3 headline")
     p.add_argument("--no-refined", action="store_true",
@@ -471,6 +473,9 @@ def main():
         print(json.dumps({"batched": batched(a.batch_iters)}), flush=True)
         return
     case = workload(a.workload)
+    if a.gsis:
+        import dataclasses
+        case = dataclasses.replace(case, gsis=True)
     if a.stretch > 0:
         from paper_2310_18916_amd import inputs as I
         case = I.with_nodes(case, [I.stretched_nodes(case.nv[k], max(-case.vmin[k], case.vmax[k]), a.stretch)
