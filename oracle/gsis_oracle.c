@@ -2066,12 +2066,12 @@ static double uface_h(const orc_state *s, int f, double d[3])
     return d[0] * g[1] + d[1] * g[2] + d[2] * g[3];
 }
 
-static int umacro_solve(orc_state *s, const moms *K, int iters, prim_t *P)
+static int umacro_solve(orc_state *s, const moms *K, int iters, int euler, prim_t *P)
 {
     const orc_cfg *c = &s->c;
     macpar mp;
     macro_params(s, &mp);
-    mp.euler = 0;
+    mp.euler = euler;
     int ncell = s->ncell, nw = mp.nw, nf = s->nface;
     static const double nohot[6] = {0, 0, 0, 0, 0, 0};
     double *W = calloc((size_t)ncell * 6, sizeof(double));
@@ -2097,9 +2097,11 @@ static int umacro_solve(orc_state *s, const moms *K, int iters, prim_t *P)
         prim_of(&mp, w, &P[cell]);
     }
     for (int cell = 0; cell < ncell; ++cell) ucell_grad(s, P, cell, grad + (size_t)cell * 9);
-    /* fixed parts: F_kin(f^{n+1/2}) - F(W^{n+1/2}) at every face */
+    /* fixed parts: F_kin(f^{n+1/2}) - F(W^{n+1/2}) at every face (zero for
+     * Euler: no high-order terms, the boundary flux of the iterate's own
+     * Maxwellian) */
     #pragma omp parallel for schedule(dynamic, 16)
-    for (int f = 0; f < nf; ++f) {
+    for (int f = 0; f < nf * !euler; ++f) {
         int L = s->ufc[2 * f], Rr = s->ufc[2 * f + 1];
         double Fk[6], Fm[6], Gam, d[3];
         ukinetic_face_flux(s, f, Fk);
@@ -2132,7 +2134,7 @@ static int umacro_solve(orc_state *s, const moms *K, int iters, prim_t *P)
                 const double *g = s->ufg + (size_t)f * 4;
                 const prim_t *Pi = &P[L];
                 double un = Pi->u[0] * g[1] + Pi->u[1] * g[2] + Pi->u[2] * g[3];
-                o[6] = fabs(un) + Pi->cs + mp.Cd * pow(Pi->Tt, mp.omega) / (mp.delta * Pi->rho * h);
+                o[6] = fabs(un) + Pi->cs + (euler ? 0.0 : mp.Cd * pow(Pi->Tt, mp.omega) / (mp.delta * Pi->rho * h));
             }
         }
         #pragma omp parallel for schedule(dynamic, 16)
@@ -2152,7 +2154,7 @@ static int umacro_solve(orc_state *s, const moms *K, int iters, prim_t *P)
                 res[5] += 0.5 * mp.dr * Pi->rho * (T - Pi->Tr) * invtau / mp.Z;
             }
             double umag = sqrt(Pi->u[0] * Pi->u[0] + Pi->u[1] * Pi->u[1] + Pi->u[2] * Pi->u[2]);
-            double vis = mp.Cd * pow(Pi->Tt, mp.omega) / (mp.delta * Pi->rho * hmin);
+            double vis = euler ? 0.0 : mp.Cd * pow(Pi->Tt, mp.omega) / (mp.delta * Pi->rho * hmin);
             double idt = (umag + Pi->cs + vis) / (mp.cfl * hmin);
             double *r = R + (size_t)cell * 6;
             for (int k = 0; k < 6; ++k) r[k] = res[k];
@@ -2188,8 +2190,8 @@ static int umacro_solve(orc_state *s, const moms *K, int iters, prim_t *P)
  * Chapman-Enskog expansion). */
 static int gsis_correct_mode(orc_state *s, int iters, int euler)
 {
-    /* unstructured mesh: the correction needs the centroids; no Euler form */
-    if (s->umesh && (euler || !s->ucen)) return -2;
+    /* unstructured mesh: the correction needs the centroids */
+    if (s->umesh && !s->ucen) return -2;
     const orc_cfg *c = &s->c;
     int ncell = s->ncell, dia = c->species == 1;
     moms *K = calloc((size_t)ncell, sizeof(moms));
@@ -2206,7 +2208,7 @@ static int gsis_correct_mode(orc_state *s, int iters, int euler)
             if (n >= 0 && (d & 1) && !euler) kinetic_interior_flux(s, cell, n, d / 2, Fint + (size_t)cell * 18 + (d / 2) * 6);
         }
     }
-    if (s->umesh) umacro_solve(s, K, iters, P);
+    if (s->umesh) umacro_solve(s, K, iters, euler, P);
     else macro_solve(s, K, Fkin, Fint, iters, euler, P);
     #pragma omp parallel for schedule(static)
     for (int cell = 0; cell < ncell; ++cell) {

@@ -1302,7 +1302,8 @@ gsis_status gsis_gsis_correct(gsis_ctx *ctx, int inner_iters)
 gsis_status gsis_precondition(gsis_ctx *ctx, int macro_steps, int kinetic_steps)
 {
     if (!ctx) return GSIS_EINVAL;
-    if (ctx->g.umesh) return fail(ctx, GSIS_ESTATE, "the initial field of Alg. 1 (Euler steps) is built for the box of hex cells");
+    if (ctx->g.umesh && !ctx->g.ucen)
+        return fail(ctx, GSIS_ESTATE, "the Euler steps on an unstructured mesh need its centroids");
     if (!ctx->inited) return fail(ctx, GSIS_ESTATE, "initialise the VDF first");
     if (macro_steps < 0 || kinetic_steps < 0) return fail(ctx, GSIS_EINVAL, "steps must be >= 0");
     gsis_status st = materialize(ctx);
@@ -1311,7 +1312,8 @@ gsis_status gsis_precondition(gsis_ctx *ctx, int macro_steps, int kinetic_steps)
         PhaseTimer t;
         HIPCHK(ctx, t.start(ctx, GSIS_PHASE_MACRO));
         const Target tg = target_of(ctx);
-        HIPCHK(ctx, launch_gsis_macro(tg, macro_steps, ctx->stream, 1));
+        if (ctx->g.umesh) HIPCHK(ctx, launch_umacro(tg, macro_steps, ctx->stream, 1));
+        else HIPCHK(ctx, launch_gsis_macro(tg, macro_steps, ctx->stream, 1));
         HIPCHK(ctx, launch_commit_correction(tg, ctx->stream));
         HIPCHK(ctx, launch_derive(tg, ctx->stream));
         HIPCHK(ctx, t.stop());

@@ -66,7 +66,7 @@ hipError_t launch_usweep(const Target &t, const int *lev_off, int nlev, hipStrea
 // diffusive pseudo-time terms) and the iterate's own boundary flux
 hipError_t launch_gsis_macro(const Target &t, int iters, hipStream_t s, int euler = 0);
 // the same solve on an unstructured mesh (one case, centroids given)
-hipError_t launch_umacro(const Target &t, int iters, hipStream_t s);
+hipError_t launch_umacro(const Target &t, int iters, hipStream_t s, int euler = 0);
 
 int resid_blocks(const Geo &g);
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);

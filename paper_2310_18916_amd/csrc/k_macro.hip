@@ -689,11 +689,12 @@ hipError_t launch_gsis_macro(const Target &t, int iters, hipStream_t s, int eule
 // Rusanov + NSF flux across face f from L to R (no high-order terms).
 template <class PV, class GV>
 __device__ __forceinline__ void uface_flux(const Geo &g, const PV &L, const PV &R, const GV &gL, const GV &gR,
-                                           const double fg[9], double F[6], double *Gam)
+                                           const double fg[9], bool euler, double F[6], double *Gam)
 {
     const double n[3] = {fg[1], fg[2], fg[3]}, h = fg[4], dl = fg[5], e[3] = {fg[6], fg[7], fg[8]};
     const double TF = 0.5 * (L[4] + R[4]), rF = 0.5 * (L[0] + R[0]);
-    const double mu = pow_pos(TF, g.omega) / g.delta;
+    // Euler constitutive relations: no stress or heat flux, no diffusive part in Gamma
+    const double mu = euler ? 0.0 : pow_pos(TF, g.omega) / g.delta;
     double G[9];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
@@ -743,7 +744,7 @@ __device__ __forceinline__ void uface_flux(const Geo &g, const PV &L, const PV &
     for (int b = 0; b < 3; ++b) F[1 + b] += 0.5 * sN[b];
     F[4] += sN[0] * 0.5 * (L[1] + R[1]) + sN[1] * 0.5 * (L[2] + R[2]) + sN[2] * 0.5 * (L[3] + R[3]) + qN + qrN;
     F[5] += qrN;
-    *Gam = smax + g.Cd * mu / (rF * h);
+    *Gam = euler ? smax : smax + g.Cd * mu / (rF * h);
 }
 
 // Velocity gradient of every cell: G[b][c] = sum over its interior face
@@ -859,7 +860,7 @@ __global__ __launch_bounds__(256) void k_umac_kin(GSIS_SPAN_ARGS)
 // Interior faces, one thread each: the macroscopic flux of the current W;
 // mode 0 keeps F_kin - F as the face's high-order terms, mode 1 stores
 // F + HoT and Gamma for the residual.
-__global__ __launch_bounds__(256) void k_umac_iflux(GSIS_SPAN_ARGS, int mode)
+__global__ __launch_bounds__(256) void k_umac_iflux(GSIS_SPAN_ARGS, int mode, int euler)
 {
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
@@ -874,7 +875,7 @@ __global__ __launch_bounds__(256) void k_umac_iflux(GSIS_SPAN_ARGS, int mode)
 #pragma unroll
     for (int k = 0; k < 9; ++k) fg[k] = G(d.uf_geo)[9 * (size_t)f + k];
     double F[6], Gam;
-    uface_flux(g, soa(d.P, n, L), soa(d.P, n, R), soa(d.grad, n, L), soa(d.grad, n, R), fg, F, &Gam);
+    uface_flux(g, soa(d.P, n, L), soa(d.P, n, R), soa(d.grad, n, L), soa(d.grad, n, R), fg, euler != 0, F, &Gam);
     if (mode == 0) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) G(d.ufix)[6 * (size_t)f + k] = G(d.uFk)[6 * (size_t)f + k] - F[k];
@@ -893,7 +894,7 @@ __global__ __launch_bounds__(256) void k_umac_iflux(GSIS_SPAN_ARGS, int mode)
 // part + F_eq(W^m) and Gamma.
 constexpr int UBF = 8;
 
-__global__ __launch_bounds__(256) void k_umac_bflux(GSIS_SPAN_ARGS, int mode)
+__global__ __launch_bounds__(256) void k_umac_bflux(GSIS_SPAN_ARGS, int mode, int euler)
 {
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
@@ -974,7 +975,7 @@ __global__ __launch_bounds__(256) void k_umac_bflux(GSIS_SPAN_ARGS, int mode)
 #pragma unroll
             for (int k = 0; k < 6; ++k) G(d.uFf)[7 * ff + k] = G(d.ufix)[6 * ff + k] + Fe[k];
             const double un = u[q][0] * n[q][0] + u[q][1] * n[q][1] + u[q][2] * n[q][2];
-            G(d.uFf)[7 * ff + 6] = fabs(un) + P[8] + g.Cd * P[9] / (rho * G(d.uf_geo)[9 * ff + 4]);
+            G(d.uFf)[7 * ff + 6] = fabs(un) + P[8] + (euler ? 0.0 : g.Cd * P[9] / (rho * G(d.uf_geo)[9 * ff + 4]));
         }
     }
 }
@@ -982,7 +983,7 @@ __global__ __launch_bounds__(256) void k_umac_bflux(GSIS_SPAN_ARGS, int mode)
 // Residual and diagonal of every cell from the face fluxes (S / V per face,
 // the sign of the owner's side), the rotational relaxation on the Er row; one
 // atomic max of D per wave into the slot's partials.
-__global__ __launch_bounds__(256) void k_umac_res(GSIS_SPAN_ARGS, int slot)
+__global__ __launch_bounds__(256) void k_umac_res(GSIS_SPAN_ARGS, int slot, int euler)
 {
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
@@ -1011,7 +1012,8 @@ __global__ __launch_bounds__(256) void k_umac_res(GSIS_SPAN_ARGS, int slot)
             res[5] += 0.5 * g.dr * P[0] * (T - P[5]) * invtau / g.Zr;
         }
         const double umag = sqrt(P[1] * P[1] + P[2] * P[2] + P[3] * P[3]);
-        const double idt = (umag + P[8] + g.Cd * P[9] / (P[0] * g.uhmin)) / (g.macro_cfl * g.uhmin);
+        const double vis = euler ? 0.0 : g.Cd * P[9] / (P[0] * g.uhmin);
+        const double idt = (umag + P[8] + vis) / (g.macro_cfl * g.uhmin);
         D = idt + 0.5 * sumG;
         const Soa<double> r = soa(d.R, n, cell);
 #pragma unroll
@@ -1057,7 +1059,17 @@ __global__ __launch_bounds__(256) void k_umac_advance(GSIS_SPAN_ARGS, int slot)
     prim_from_W(g, Wn, soa(d.P, n, cell));
 }
 
-hipError_t launch_umacro(const Target &t, int iters, hipStream_t s)
+// Euler steps: no high-order terms, the boundary flux of the iterate's own
+// Maxwellian -- every fixed part zero.
+__global__ __launch_bounds__(256) void k_umac_nofix(GSIS_SPAN_ARGS)
+{
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const int i = blk * blockDim.x + threadIdx.x;
+    if (i < 6 * C.g.unface) G(C.d.ufix)[i] = 0.0;
+}
+
+hipError_t launch_umacro(const Target &t, int iters, hipStream_t s, int euler)
 {
     const Geo &g = t.host->g;
     const Span sp{t.cases, nullptr};
@@ -1066,6 +1078,7 @@ hipError_t launch_umacro(const Target &t, int iters, hipStream_t s)
     hipLaunchKernelGGL(k_mac_reset, dim3(1), dim3(64), 0, s, GSIS_SPAN(sp));
     hipLaunchKernelGGL(k_mac_init, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(sp));
     hipLaunchKernelGGL(k_umac_grad, cells, dim3(256), 0, s, GSIS_SPAN(sp));
+    // the kinetic face fluxes, and the boundary Maxwellians' incoming moments the boundary fluxes need
     if (t.fp32) {
         if (t.dia) hipLaunchKernelGGL((k_umac_kin<float, true>), fwaves, dim3(256), 0, s, GSIS_SPAN(sp));
         else hipLaunchKernelGGL((k_umac_kin<float, false>), fwaves, dim3(256), 0, s, GSIS_SPAN(sp));
@@ -1073,14 +1086,18 @@ hipError_t launch_umacro(const Target &t, int iters, hipStream_t s)
         if (t.dia) hipLaunchKernelGGL((k_umac_kin<double, true>), fwaves, dim3(256), 0, s, GSIS_SPAN(sp));
         else hipLaunchKernelGGL((k_umac_kin<double, false>), fwaves, dim3(256), 0, s, GSIS_SPAN(sp));
     }
-    hipLaunchKernelGGL(k_umac_iflux, faces, dim3(256), 0, s, GSIS_SPAN(sp), 0);
-    if (g.unbf > 0) hipLaunchKernelGGL(k_umac_bflux, bwaves, dim3(256), 0, s, GSIS_SPAN(sp), 0);
+    if (euler) {
+        hipLaunchKernelGGL(k_umac_nofix, dim3((6 * g.unface + 255) / 256), dim3(256), 0, s, GSIS_SPAN(sp));
+    } else {
+        hipLaunchKernelGGL(k_umac_iflux, faces, dim3(256), 0, s, GSIS_SPAN(sp), 0, 0);
+        if (g.unbf > 0) hipLaunchKernelGGL(k_umac_bflux, bwaves, dim3(256), 0, s, GSIS_SPAN(sp), 0, 0);
+    }
     for (int it = 0; it < iters; ++it) {
         const int slot = it & 1;
         if (it > 0) hipLaunchKernelGGL(k_umac_grad, cells, dim3(256), 0, s, GSIS_SPAN(sp));
-        hipLaunchKernelGGL(k_umac_iflux, faces, dim3(256), 0, s, GSIS_SPAN(sp), 1);
-        if (g.unbf > 0) hipLaunchKernelGGL(k_umac_bflux, bwaves, dim3(256), 0, s, GSIS_SPAN(sp), 1);
-        hipLaunchKernelGGL(k_umac_res, cells, dim3(256), 0, s, GSIS_SPAN(sp), slot);
+        hipLaunchKernelGGL(k_umac_iflux, faces, dim3(256), 0, s, GSIS_SPAN(sp), 1, euler);
+        if (g.unbf > 0) hipLaunchKernelGGL(k_umac_bflux, bwaves, dim3(256), 0, s, GSIS_SPAN(sp), 1, euler);
+        hipLaunchKernelGGL(k_umac_res, cells, dim3(256), 0, s, GSIS_SPAN(sp), slot, euler);
         hipLaunchKernelGGL(k_umac_advance, cells, dim3(256), 0, s, GSIS_SPAN(sp), slot);
     }
     hipLaunchKernelGGL(k_mac_final, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(sp));
