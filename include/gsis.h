@@ -156,10 +156,10 @@ gsis_status gsis_set_velocity_list(gsis_ctx *ctx, const double *nodes, int n);
  * face from the kinetic face flux).  Requires gsis_set_velocity_list first,
  * order 1 and no solid mask (a body is a hole in the mesh, its surface
  * boundary slot 6); must precede gsis_workspace_size.  Kinetic passes,
- * moments, residual (volume-weighted) and state calls work as on the box;
- * gsis_precondition, gsis_set_tile and gsis_autotune return GSIS_ESTATE (as
- * does gsis_gsis_correct without centroids) and gsis_batch_create
- * GSIS_EINVAL.  EINVAL when an index, area, normal, volume or centroid is
+ * moments, residual (volume-weighted), gsis_precondition (the Euler form of
+ * the same solve) and state calls work as on the box; gsis_set_tile and
+ * gsis_autotune return GSIS_ESTATE (as do gsis_gsis_correct and
+ * gsis_precondition without centroids) and gsis_batch_create GSIS_EINVAL.  EINVAL when an index, area, normal, volume or centroid is
  * invalid (a face whose centroid distance along its normal is not
  * positive), a cell has more than 16 faces or is not closed (its area times
  * outward normals do not sum to zero within 1e-9 of its area), the faces
