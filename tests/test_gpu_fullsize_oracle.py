@@ -60,10 +60,10 @@ def groups(nm):
     return g
 
 
-@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
 WORKLOADS = {"c2": I.c2, "c3": I.c3, "c4": I.c4, "c3t": I.c3t, "c3t_gsis": I.c3t}
 
 
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
 @pytest.mark.parametrize("workload", ["c2", "c3", "c4", "c3t", "c3t_gsis"])
 def test_full_size_matches_streaming_oracle(workload, dtype):
     path = os.path.join(GOLDEN, f"fullsize_{workload}.npz")
