@@ -104,6 +104,12 @@ typedef struct {
      * unstructured mesh (the macroscopic correction's gradients and face
      * distances); NULL: kinetic passes only. */
     const double *ucenter, *ufcenter;
+    /* macroscopic boundary flux of the correction (Sec. 3.3): 0 the cell's
+     * Maxwellian (F_eq), 1 the Grad-13 reconstruction of Eq. (G13_VDF) from
+     * the iterate and Eq. (full_constitutive) (F_G13); both enter as the
+     * kinetic flux plus the change of the model flux from W^{n+1/2} to W^m.
+     * Box meshes only. */
+    int wall_flux;
 } orc_cfg;
 
 typedef struct {
@@ -207,6 +213,8 @@ static orc_state *create_state(const orc_cfg *cfg, const unsigned char *solid, i
     if (um && !check_mesh(cfg)) return NULL;
     if (!um && (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1)) return NULL;
     if (cfg->order != 1 && cfg->order != 2) return NULL;
+    if (cfg->wall_flux != 0 && cfg->wall_flux != 1) return NULL;
+    if (um && cfg->wall_flux != 0) return NULL;
     if (!isfinite(cfg->limiter_k)) return NULL;
     const int list = cfg->nlist > 0;
     if (cfg->nlist < 0 || (list && !cfg->node_list)) return NULL;
@@ -1430,6 +1438,15 @@ void orc_ref_components(const orc_cfg *c, double rho, const double u[3], double 
  * (outgoing half of M(W), incoming wall Maxwellian with zero mass flux, or the
  * fixed inflow).  A frozen F_kin alone leaves momentum and energy fluxes that
  * need not balance, and the closed-box problem then has no steady state.
+ * With wall_flux = 1 the model flux is that of the Grad-13 distributions of
+ * Eq. (G13_VDF) (g13_vdf) in place of M(W):  F_b(W^m) = F_kin +
+ * F_G13(W^m) - F_G13(W^{n+1/2}), the distributions built from the iterate's
+ * rho, u, Tt, Tr and the stress and heat fluxes of Eq. (full_constitutive) at
+ * the cell, NSF_c(W^m) + HoT_c with HoT_c the kinetic values of f^{n+1/2}
+ * minus NSF_c(W^{n+1/2}) (NSF_c from the cell's central gradients), so the
+ * wall flux answers the iterate's gradients next to the wall as well as its
+ * state; at W^{n+1/2} the stress and heat fluxes are the kinetic ones and
+ * F_b = F_kin, so a kinetic fixed point stays a fixed point.
  * Iteration: point-Jacobi on the diagonal D of Eq. (res_macro),
  *   D_i = 1/dtau_i + (1/2) sum_faces Gamma / h,  Gamma = s + C_d Tt^omega / (delta rho h),
  *   1/dtau_i = (|u| + c_s + C_d Tt^omega/(delta rho h_min)) / (CFL h_min),
@@ -1506,6 +1523,62 @@ static void cell_grad(const orc_state *s, const prim_t *P, int cell, double G[9]
             G[b * 3 + c] = g;
         }
     }
+}
+
+/* Central (one-sided next to non-fluid neighbours) gradients of Tt and Tr of a cell. */
+static void cell_tgrad(const orc_state *s, const prim_t *P, int cell, double gt[3], double gr[3])
+{
+    for (int c = 0; c < 3; ++c) {
+        int nm = neighbour(s, cell, 2 * c), np = neighbour(s, cell, 2 * c + 1);
+        double h = s->h[c];
+        const prim_t *A = &P[np >= 0 ? np : cell], *B = &P[nm >= 0 ? nm : cell];
+        double den = (nm >= 0 && np >= 0) ? 2.0 * h : h;
+        int none = nm < 0 && np < 0;
+        gt[c] = none ? 0.0 : (A->Tt - B->Tt) / den;
+        gr[c] = none ? 0.0 : (A->Tr - B->Tr) / den;
+    }
+}
+
+/* Stress and heat fluxes of a cell by Eq. (NSF_constitutive) from its central
+ * gradients, sq = (sigma xx yy zz xy xz yz, q, qr), mu = Tt^omega / delta. */
+static void cell_nsf(const orc_state *s, const macpar *mp, const prim_t *P, int cell, double sq[12])
+{
+    double G[9], gt[3], gr[3];
+    cell_grad(s, P, cell, G);
+    cell_tgrad(s, P, cell, gt, gr);
+    double mu = pow(P[cell].Tt, mp->omega) / mp->delta;
+    double div = G[0] + G[4] + G[8];
+    static const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
+    for (int k = 0; k < 6; ++k) {
+        int a = pa[k], b = pb[k];
+        sq[k] = -mu * (G[a * 3 + b] + G[b * 3 + a] - (a == b ? (2.0 / 3.0) * div : 0.0));
+    }
+    for (int a = 0; a < 3; ++a) {
+        sq[6 + a] = -mp->kt * mu * gt[a];
+        sq[9 + a] = mp->dia ? -mp->kr * mu * gr[a] : 0.0;
+    }
+}
+
+/* High-order terms of a cell for the Grad-13 wall flux: the kinetic stress and
+ * heat fluxes of f^{n+1/2} (moments K) minus the cell's NSF values at
+ * W^{n+1/2} (prims P), hot[12] in the order of sq. */
+static void g13_cell_hot(const orc_state *s, const macpar *mp, const moms *K, const prim_t *P, int cell, double hot[12])
+{
+    cell_nsf(s, mp, P, cell, hot);
+    for (int k = 0; k < 6; ++k) hot[k] = K->sig[k] - hot[k];
+    for (int a = 0; a < 3; ++a) {
+        hot[6 + a] = K->q[a] - hot[6 + a];
+        hot[9 + a] = mp->dia ? K->qr[a] - hot[9 + a] : 0.0;
+    }
+}
+
+/* Stress and heat fluxes of Eq. (full_constitutive) at a cell for the iterate
+ * (prims P): NSF_c(W^m) + HoT_c. */
+static void g13_cell_stress(const orc_state *s, const macpar *mp, const prim_t *P, int cell, const double hot[12],
+                            double sq[12])
+{
+    cell_nsf(s, mp, P, cell, sq);
+    for (int k = 0; k < 12; ++k) sq[k] += hot[k];
 }
 
 /* NSF stress column sigma_{b a} (b = x,y,z), q_a, qr_a at the face between L and
@@ -1620,9 +1693,49 @@ static void kinetic_interior_flux(const orc_state *s, int L, int R, int a, doubl
     for (int k = 0; k < 6; ++k) F[k] = nval(&acc[k]);
 }
 
-/* F_eq of a boundary face: the flux of the face when the cell holds the
- * Maxwellian of W (f1 = (dr/2) Tr M), with the same boundary rule. */
-static void equilibrium_face_flux(const orc_state *s, const prim_t *P, int d, int bc, double F[6])
+/* Grad-13 reconstruction of a cell's distributions from its macroscopic state
+ * and its stress and heat fluxes (Eq. G13_VDF), in the units above
+ * (velocities in sqrt(2 R T0), sigma = 2 int (cc - |c|^2 I/3) f0,
+ * q = int c |c|^2 f0, qr = int c f1).  With c = xi - u and M the Maxwellian
+ * of (rho, u, Tt) (pre = (pi Tt)^{-3/2}):
+ *   f0 = M [1 + sigma:cc / (rho Tt^2) + 2 (q.c) / (rho Tt^2) (2 |c|^2 / (5 Tt) - 1)],
+ *   f1 = (dr/2) Tr f0 + 2 M (qr.c) / (rho Tt).
+ * The printed coefficients (1/(2 rho T^2), (c^2/(5T) - 1)/(rho T^2) and
+ * 1/(rho Tt)) are those of velocities in sqrt(R T0) with sigma = int (cc -
+ * ..) f and q = (1/2) int c c^2 f; in the units here the forms above give
+ * back rho, u, Tt, sigma, q, Tr and qr as the moments of Eq. (getmoment).
+ * sq = (sigma xx yy zz xy xz yz, q, qr); sq == NULL: the Maxwellian itself. */
+static void g13_vdf(const orc_cfg *c, const prim_t *P, double pre, const double *sq, const double xi[3],
+                    double *f0, double *f1)
+{
+    double M = maxwellian_pre(P->rho, pre, P->u, P->Tt, xi);
+    if (!sq) {
+        *f0 = M;
+        *f1 = c->species == 1 ? 0.5 * c->dr * P->Tr * M : 0.0;
+        return;
+    }
+    double cx = xi[0] - P->u[0], cy = xi[1] - P->u[1], cz = xi[2] - P->u[2];
+    double c2 = cx * cx + cy * cy + cz * cz;
+    double rT2 = P->rho * P->Tt * P->Tt;
+    double scc = sq[0] * cx * cx + sq[1] * cy * cy + sq[2] * cz * cz
+               + 2.0 * (sq[3] * cx * cy + sq[4] * cx * cz + sq[5] * cy * cz);
+    double qc = sq[6] * cx + sq[7] * cy + sq[8] * cz;
+    double b = 1.0 + scc / rT2 + 2.0 * qc / rT2 * (2.0 * c2 / (5.0 * P->Tt) - 1.0);
+    *f0 = M * b;
+    if (c->species == 1) {
+        double qrc = sq[9] * cx + sq[10] * cy + sq[11] * cz;
+        *f1 = 0.5 * c->dr * P->Tr * (*f0) + 2.0 * M * qrc / (P->rho * P->Tt);
+    } else {
+        *f1 = 0.0;
+    }
+}
+
+/* The flux of a boundary face when the cell holds the Maxwellian of W
+ * (f1 = (dr/2) Tr M) -- F_eq -- or, given sq, the Grad-13 distributions of
+ * g13_vdf -- F_G13, Eq. (GSIS-DVM-flux) -- with the same boundary rule: the
+ * cell's distributions at the outgoing nodes, the boundary value at the
+ * incoming ones (a wall's density from zero net mass flux). */
+static void model_face_flux(const orc_state *s, const prim_t *P, const double *sq, int d, int bc, double F[6])
 {
     const orc_cfg *c = &s->c;
     int a = d / 2;
@@ -1631,12 +1744,14 @@ static void equilibrium_face_flux(const orc_state *s, const prim_t *P, int d, in
     double sc = c->bc_rho[bc];
     const double pc = pow(M_PI * P->Tt, -1.5);
     const double *Mb = s->mbw + (size_t)bc * s->nv;
-    /* the cell's Maxwellian at the outgoing nodes, evaluated once */
+    /* the cell's distributions at the outgoing nodes, evaluated once */
     double *Mc = malloc(sizeof(double) * (size_t)s->nv);
+    double *Mc1 = malloc(sizeof(double) * (size_t)s->nv);
     for (int v = 0; v < s->nv; ++v) {
         double xi[3], w;
         node_xi(s, v, xi, &w);
-        Mc[v] = sg * xi[a] > 0 ? maxwellian_pre(P->rho, pc, P->u, P->Tt, xi) : 0.0;
+        Mc[v] = Mc1[v] = 0.0;
+        if (sg * xi[a] > 0) g13_vdf(c, P, pc, sq, xi, &Mc[v], &Mc1[v]);
     }
     if (c->bc_kind[bc] == ORC_WALL) {
         nsum out = {0, 0};
@@ -1658,7 +1773,7 @@ static void equilibrium_face_flux(const orc_state *s, const prim_t *P, int d, in
         double a0, a1;
         if (xn > 0) {
             a0 = Mc[v];
-            a1 = dia ? 0.5 * c->dr * P->Tr * a0 : 0.0;
+            a1 = Mc1[v];
         } else {
             /* the boundary value sc M(1, u_b, T_b) (f1: (dr/2) T_b times it) */
             a0 = sc * Mb[v];
@@ -1673,7 +1788,9 @@ static void equilibrium_face_flux(const orc_state *s, const prim_t *P, int d, in
     }
     for (int k = 0; k < 6; ++k) F[k] = nval(&acc[k]);
     free(Mc);
+    free(Mc1);
 }
+
 
 /* The macroscopic solve from the kinetic moments K[cell] of f^{n+1/2}, the
  * kinetic boundary fluxes Fkin[cell][6][6] (out of the cell through each
@@ -1705,6 +1822,12 @@ static int macro_solve(orc_state *s, const moms *K, const double *Fkin, const do
     double *R = calloc((size_t)ncell * 6, sizeof(double));
     double *Dc = calloc((size_t)ncell, sizeof(double));
     double *Src = calloc((size_t)ncell, sizeof(double));
+    /* Grad-13 boundary flux: the high-order terms of each cell with a boundary
+     * face, HoT_c = (sigma, q, qr)(f^{n+1/2}) - NSF_c(W^{n+1/2}), so that the
+     * stress and heat fluxes of the iterate, NSF_c(W^m) + HoT_c (Eq.
+     * full_constitutive at the cell), are the kinetic ones at W^{n+1/2} */
+    const int g13 = c->wall_flux == 1 && !euler;
+    double *hotc = g13 ? calloc((size_t)ncell * 12, sizeof(double)) : NULL;
 
     /* the starting W from the kinetic moments, and the fixed boundary fluxes */
     for (int cell = 0; cell < ncell; ++cell) {
@@ -1722,15 +1845,26 @@ static int macro_solve(orc_state *s, const moms *K, const double *Fkin, const do
     /* HoT at interior faces (cell, cell + e_a), from W^{n+1/2} */
     for (int cell = 0; cell < ncell; ++cell)
         if (!s->solid[cell]) prim_of(&mp, W + (size_t)cell * 6, &P[cell]);
-    /* fixed part of the boundary fluxes: F_kin - F_eq(W^{n+1/2}) (zero for Euler) */
+    if (g13) {
+        for (int cell = 0; cell < ncell; ++cell) {
+            if (s->solid[cell]) continue;
+            int nbnd = 0;
+            for (int d = 0; d < 6; ++d) nbnd += neighbour(s, cell, d) < 0;
+            if (!nbnd) continue;
+            g13_cell_hot(s, &mp, &K[cell], P, cell, hotc + (size_t)cell * 12);
+        }
+    }
+    /* fixed part of the boundary fluxes: F_kin - F_model(W^{n+1/2}) (zero for Euler) */
     #pragma omp parallel for schedule(dynamic, 16)
     for (int cell = 0; cell < ncell; ++cell) {
         if (s->solid[cell] || euler) continue;
+        double sq[12];
+        if (g13) g13_cell_stress(s, &mp, P, cell, hotc + (size_t)cell * 12, sq);
         for (int d = 0; d < 6; ++d) {
             int n = neighbour(s, cell, d);
             if (n >= 0) continue;
             double Fe[6];
-            equilibrium_face_flux(s, &P[cell], d, -1 - n, Fe);
+            model_face_flux(s, &P[cell], g13 ? sq : NULL, d, -1 - n, Fe);
             for (int k = 0; k < 6; ++k) Fb[(size_t)cell * 36 + d * 6 + k] -= Fe[k];
         }
     }
@@ -1771,8 +1905,9 @@ static int macro_solve(orc_state *s, const moms *K, const double *Fkin, const do
                     const double *fx = fix + (size_t)L * 18 + a * 6;
                     for (int k = 0; k < 6; ++k) out[k] = (d & 1) ? F[k] + fx[k] : -(F[k] + fx[k]);
                 } else {
-                    double Fe[6];
-                    equilibrium_face_flux(s, Pi, d, -1 - n, Fe);
+                    double Fe[6], sq[12];
+                    if (g13) g13_cell_stress(s, &mp, P, cell, hotc + (size_t)cell * 12, sq);
+                    model_face_flux(s, Pi, g13 ? sq : NULL, d, -1 - n, Fe);
                     for (int k = 0; k < 6; ++k) out[k] = Fb[(size_t)cell * 36 + d * 6 + k] + Fe[k];
                     Gam = fabs(Pi->u[a]) + Pi->cs;
                     if (!euler) Gam += mp.Cd * pow(Pi->Tt, mp.omega) / (mp.delta * Pi->rho * h);
@@ -1813,7 +1948,7 @@ static int macro_solve(orc_state *s, const moms *K, const double *Fkin, const do
     if (bad) s->status = -5;
     if (!s->lastW) s->lastW = malloc(sizeof(double) * (size_t)ncell * 6);
     memcpy(s->lastW, W, sizeof(double) * (size_t)ncell * 6);
-    free(W); free(Fb); free(fix); free(grad); free(R); free(Dc); free(Src);
+    free(W); free(Fb); free(fix); free(grad); free(R); free(Dc); free(Src); free(hotc);
     return s->status;
 }
 
@@ -2276,6 +2411,77 @@ int orc_nsf_face(const orc_state *s, const double *W, int cell, int a, double ou
     for (int b = 0; b < 3; ++b) out[b] = sig[b];
     out[3] = q;
     out[4] = qr;
+    free(P);
+    return 0;
+}
+
+/* The Grad-13 distributions of Eq. (G13_VDF) (g13_vdf) of the state (rho, u,
+ * Tt, Tr) with sq = (sigma xx yy zz xy xz yz, q, qr), at n velocities
+ * xi[n][3]: f0[n], f1[n] (f1 zero for the monatomic gas of c). */
+void orc_g13_vdf(const orc_cfg *c, double rho, const double u[3], double Tt, double Tr, const double sq[12], int n,
+                 const double *xi, double *f0, double *f1)
+{
+    prim_t P;
+    memset(&P, 0, sizeof P);
+    P.rho = rho;
+    for (int a = 0; a < 3; ++a) P.u[a] = u[a];
+    P.Tt = Tt;
+    P.Tr = Tr;
+    double pre = pow(M_PI * Tt, -1.5);
+    for (int i = 0; i < n; ++i) g13_vdf(c, &P, pre, sq, xi + 3 * i, &f0[i], &f1[i]);
+}
+
+/* The model flux out of boundary face d (0..5 = -x, +x, -y, +y, -z, +z) of a
+ * fluid cell whose W = (rho, rho u, E, Er) is W6, with the boundary rule of
+ * that face (model_face_flux): the Maxwellian's with sq == NULL, else the
+ * Grad-13 distributions' of sq (as orc_g13_vdf).  Returns -1 if the face is
+ * not a boundary face of a fluid cell. */
+int orc_model_face_flux(const orc_state *s, const double W6[6], const double *sq, int cell, int d, double F[6])
+{
+    if (s->umesh || cell < 0 || cell >= s->ncell || d < 0 || d > 5 || s->solid[cell]) return -1;
+    int n = neighbour(s, cell, d);
+    if (n >= 0) return -1;
+    macpar mp;
+    macro_params(s, &mp);
+    prim_t P;
+    prim_of(&mp, W6, &P);
+    model_face_flux(s, &P, sq, d, -1 - n, F);
+    return 0;
+}
+
+/* The stress and heat fluxes the Grad-13 wall flux takes at fluid cell `cell`
+ * for the iterate Wm[ncell][6] (rho, rho u, E, Er), the current VDF standing
+ * for f^{n+1/2}: NSF_c(W^m) + HoT_c with HoT_c = kinetic - NSF_c(W^{n+1/2}),
+ * W^{n+1/2} from the moments of the VDF (g13_cell_hot, g13_cell_stress).
+ * sq[12] as orc_g13_vdf.  Returns -1 for a solid or out-of-range cell. */
+int orc_g13_wall_stress(const orc_state *s, const double *Wm, int cell, double sq[12])
+{
+    if (s->umesh || cell < 0 || cell >= s->ncell || s->solid[cell]) return -1;
+    const orc_cfg *c = &s->c;
+    macpar mp;
+    macro_params(s, &mp);
+    int ncell = s->ncell;
+    moms K;
+    prim_t *P = calloc((size_t)ncell, sizeof(prim_t));
+    double W[6];
+    for (int i = 0; i < ncell; ++i) {
+        if (s->solid[i]) continue;
+        moms m;
+        cell_moments(s, i, &m);
+        if (i == cell) K = m;
+        double u2 = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+        double Er = mp.dia ? 0.5 * c->dr * m.rho * m.Tr : 0.0;
+        W[0] = m.rho;
+        for (int a = 0; a < 3; ++a) W[1 + a] = m.rho * m.u[a];
+        W[4] = m.rho * u2 + 1.5 * m.rho * m.Tt + Er;
+        W[5] = Er;
+        prim_of(&mp, W, &P[i]);
+    }
+    double hot[12];
+    g13_cell_hot(s, &mp, &K, P, cell, hot);
+    for (int i = 0; i < ncell; ++i)
+        if (!s->solid[i]) prim_of(&mp, Wm + (size_t)i * 6, &P[i]);
+    g13_cell_stress(s, &mp, P, cell, hot, sq);
     free(P);
     return 0;
 }

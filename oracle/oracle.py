@@ -41,6 +41,7 @@ class _Cfg(C.Structure):
         ("ucells", C.c_int), ("ufaces", C.c_int), ("uvol", C.POINTER(C.c_double)),
         ("uface_cell", C.POINTER(C.c_int)), ("uface_geom", C.POINTER(C.c_double)),
         ("ucenter", C.POINTER(C.c_double)), ("ufcenter", C.POINTER(C.c_double)),
+        ("wall_flux", C.c_int),
     ]
 
 
@@ -93,6 +94,9 @@ def lib():
         L.orc_stream_residual.argtypes = [P, D]
         L.orc_stream_status.argtypes = [P]
         L.orc_nsf_face.argtypes = [P, D, C.c_int, C.c_int, D]
+        L.orc_g13_vdf.argtypes = [C.POINTER(_Cfg), C.c_double, D, C.c_double, C.c_double, D, C.c_int, D, D, D]
+        L.orc_model_face_flux.argtypes = [P, D, D, C.c_int, C.c_int, D]
+        L.orc_g13_wall_stress.argtypes = [P, D, C.c_int, D]
         L.orc_first_pass_nodes.argtypes = [C.POINTER(_Cfg), C.c_void_p, C.c_double, D, C.c_double, C.c_double,
                                            C.POINTER(C.c_int), C.c_int, D, D]
         _lib = L
@@ -103,6 +107,19 @@ def _dp(a: Optional[np.ndarray]):
     if a is None:
         return None
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def g13_vdf(case, rho, u, Tt, Tr, sq, xi):
+    """Grad-13 distributions (f0, f1) of Eq. (G13_VDF) of the state (rho, u,
+    Tt, Tr) with sq = (sigma xx yy zz xy xz yz, q, qr) at velocities xi[n][3]."""
+    cfg = make_cfg(case)
+    xi = np.ascontiguousarray(xi, dtype=np.float64).reshape(-1, 3)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    sq = np.ascontiguousarray(sq, dtype=np.float64)
+    f0 = np.empty(xi.shape[0])
+    f1 = np.empty(xi.shape[0])
+    lib().orc_g13_vdf(C.byref(cfg), rho, _dp(u), Tt, Tr, _dp(sq), xi.shape[0], _dp(xi), _dp(f0), _dp(f1))
+    return f0, f1
 
 
 def make_cfg(case) -> _Cfg:
@@ -123,6 +140,7 @@ def make_cfg(case) -> _Cfg:
     c.macro_cfl = case.macro_cfl
     c.order = case.order
     c.limiter_k = case.limiter_k
+    c.wall_flux = getattr(case, "wall_flux", 0)
     for b, bc in enumerate(case.bcs):
         c.bc_kind[b] = bc.kind
         for a in range(3):
@@ -273,6 +291,27 @@ class Oracle:
 
     def total_mass(self) -> float:
         return lib().orc_total_mass(self.h)
+
+    def g13_wall_stress(self, Wm, cell: int) -> np.ndarray:
+        """(sigma xx yy zz xy xz yz, q, qr) the Grad-13 wall flux takes at
+        `cell` for the iterate Wm[ncell][6], the current VDF being f^{n+1/2}."""
+        Wm = np.ascontiguousarray(Wm, dtype=np.float64)
+        out = np.empty(12)
+        if lib().orc_g13_wall_stress(self.h, _dp(Wm), cell, _dp(out)) != 0:
+            raise ValueError("not a fluid cell")
+        return out
+
+    def model_face_flux(self, W6, cell: int, d: int, sq=None) -> np.ndarray:
+        """Flux (mass, momentum, energy, Er) out of boundary face d of `cell`
+        whose conservative state is W6, with that face's boundary rule: of the
+        cell's Maxwellian (sq None) or of its Grad-13 distributions with
+        sq = (sigma xx yy zz xy xz yz, q, qr)."""
+        W6 = np.ascontiguousarray(W6, dtype=np.float64)
+        sqa = None if sq is None else np.ascontiguousarray(sq, dtype=np.float64)
+        out = np.empty(6)
+        if lib().orc_model_face_flux(self.h, _dp(W6), _dp(sqa), cell, d, _dp(out)) != 0:
+            raise ValueError("not a boundary face of a fluid cell")
+        return out
 
     def face_values(self, v: int, which: int = 0, order: int = 2) -> np.ndarray:
         """[cell][6] value of canonical node v at each face of each cell

@@ -77,6 +77,10 @@ class Case:
     # order
     order: int = 1
     limiter_k: float = 1.0
+    # macroscopic boundary flux of the GSIS correction: 0 the kinetic flux plus
+    # the change of the cell Maxwellian's flux, 1 the same with the Grad-13
+    # distributions of the iterate's state, stress and heat fluxes (Sec. 3.3)
+    wall_flux: int = 0
     bcs: List[Boundary] = dataclasses.field(default_factory=lambda: [Boundary() for _ in range(7)])
     solid: Optional[np.ndarray] = None
     init: Tuple[float, Tuple[float, float, float], float, float] = (1.0, (0.0, 0.0, 0.0), 1.0, 1.0)
