@@ -60,6 +60,8 @@ typedef enum {
 enum { GSIS_MONATOMIC = 0, GSIS_DIATOMIC = 1 };
 enum { GSIS_FP64 = 0, GSIS_FP32 = 1 };
 enum { GSIS_DIFFUSE_WALL = 0, GSIS_MAXWELL_INFLOW = 1 };
+/* macroscopic boundary flux of gsis_gsis_correct (gsis_set_wall_flux) */
+enum { GSIS_WALLFLUX_MAXWELL = 0, GSIS_WALLFLUX_G13 = 1 };
 /* boundary slots for gsis_set_boundary: box faces, then the solid surface */
 enum { GSIS_FACE_XM = 0, GSIS_FACE_XP = 1, GSIS_FACE_YM = 2, GSIS_FACE_YP = 3,
        GSIS_FACE_ZM = 4, GSIS_FACE_ZP = 5, GSIS_FACE_SOLID = 6 };
@@ -175,6 +177,26 @@ gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume
  * (rho, u, T) entering through the face (Tr = T for the diatomic VDF).  Must
  * precede gsis_bind_workspace. */
 gsis_status gsis_set_boundary(gsis_ctx *ctx, int face, int kind, const double u[3], double T, double rho);
+
+/* Boundary flux of the macroscopic correction (Sec. 3.3, Eq. G13_VDF and
+ * Eq. GSIS-DVM-flux).  At every boundary face the correction's flux is the
+ * kinetic flux of f^{n+1/2} plus the change, from W^{n+1/2} to the iterate
+ * W^m, of a model flux: the half-range flux of the cell's distributions with
+ * the face's boundary rule (incoming wall Maxwellian at zero net mass flux,
+ * or the inflow).  GSIS_WALLFLUX_MAXWELL (the default): the cell's Maxwellian
+ * (f1 = (dr/2) Tr M).  GSIS_WALLFLUX_G13: its Grad-13 distributions, in
+ * velocities of sqrt(2 R T0)
+ *   f0 = M [1 + sigma:cc / (rho Tt^2) + 2 (q.c) / (rho Tt^2) (2 |c|^2 / (5 Tt) - 1)],
+ *   f1 = (dr/2) Tr f0 + 2 M (qr.c) / (rho Tt),
+ * c = xi - u, M the Maxwellian of (rho, u, Tt), built from the iterate's
+ * rho, u, Tt, Tr and the stress and heat fluxes of Eq. (full_constitutive) at
+ * the cell: the NSF values of the iterate's central gradients (one-sided next
+ * to a non-fluid neighbour) plus the cell's high-order terms, the kinetic
+ * values of f^{n+1/2} minus the NSF values at W^{n+1/2}.  Either way the flux
+ * at W^{n+1/2} is the kinetic one, so a kinetic fixed point stays a fixed
+ * point.  Box meshes only.  Must precede gsis_bind_workspace; EINVAL on an
+ * unknown model or G13 on an unstructured mesh, ESTATE once bound. */
+gsis_status gsis_set_wall_flux(gsis_ctx *ctx, int model);
 
 /* Bytes of device workspace the context needs (after the mask is set). */
 gsis_status gsis_workspace_size(const gsis_ctx *ctx, size_t *bytes);

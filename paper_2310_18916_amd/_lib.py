@@ -39,6 +39,7 @@ SIGNATURES = {
     "gsis_set_spatial_mesh": (_I, [_P, C.c_int, _P, C.c_int, _P, _P, _P, _P]),
     "gsis_precondition": (_I, [_P, C.c_int, C.c_int]),
     "gsis_set_boundary": (_I, [_P, _I, _I, _DP, _D, _D]),
+    "gsis_set_wall_flux": (_I, [_P, _I]),
     "gsis_workspace_size": (_I, [_P, C.POINTER(_SZ)]),
     "gsis_bind_workspace": (_I, [_P, _P, _SZ]),
     "gsis_set_stream": (_I, [_P, _P]),

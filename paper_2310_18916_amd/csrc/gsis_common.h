@@ -64,6 +64,9 @@ struct Geo {
     int unface;    // faces of the mesh
     int ucen;      // 1: centroids given (the macroscopic correction runs)
     double uhmin;  // smallest face distance h of the macroscopic pseudo time step
+    // macroscopic boundary flux of the correction: 0 the Maxwellian's change,
+    // 1 the Grad-13 distributions' change (box meshes)
+    int wall_flux;
 };
 
 struct BcInfo {
@@ -153,6 +156,7 @@ struct Dev {
     // high-order terms of the three + faces (six flux components each),
     // residual R
     double *W, *W2, *P, *grad, *hot, *R, *Dc, *Src, *fbfix, *Fb, *Gb;
+    double *ghot;      // [12][nface] Grad-13 wall flux: the face cell's HoT_c (sigma 6, q 3, qr 3)
     double *red;       // reduction scratch
     unsigned long long *dmax;   // [2][DSLOT] partial maxima, one per 128-byte line (DSTRIDE words apart),
                                 // bit patterns of positive doubles

@@ -376,6 +376,7 @@ size_t layout(gsis_ctx *c, char *base)
     carve(off, d.fbfix, nf * 6, base);
     carve(off, d.Fb, nf * 6, base);
     carve(off, d.Gb, nf, base);
+    carve(off, d.ghot, nf * 12, base);
     carve(off, d.red, (size_t)(resid_blocks(g) + 1) * 6, base);
     carve(off, d.dmax, (size_t)2 * DSLOT * DSTRIDE, base);
     carve(off, d.errflag, 4, base);
@@ -400,6 +401,7 @@ Target target_of(const gsis_ctx *c)
     t.rfn = c->g.inv_dt != 0.0 || c->g.order == 2;
     t.mom_nblk[vw_class(c->vw)] = c->g.ncell;
     t.vlist = c->g.vlist != 0;
+    t.g13 = c->g.wall_flux == GSIS_WALLFLUX_G13;
     if (!c->nclean.empty()) {
         t.nclean = c->nclean.data();
         t.pcnt = c->plane_cnt.data();
@@ -769,6 +771,8 @@ gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume
     if (!ctx) return GSIS_EINVAL;
     if (ctx->bound || ctx->meta_ready) return fail(ctx, GSIS_ESTATE, "set_spatial_mesh must precede workspace_size/bind");
     if (ctx->g.umesh) return fail(ctx, GSIS_ESTATE, "the spatial mesh is already set");
+    if (ctx->g.wall_flux != GSIS_WALLFLUX_MAXWELL)
+        return fail(ctx, GSIS_ESTATE, "the Grad-13 wall flux runs on box meshes only");
     if (!ctx->g.vlist) return fail(ctx, GSIS_ESTATE, "set_velocity_list must precede set_spatial_mesh");
     if (ctx->g.order != 1) return fail(ctx, GSIS_ESTATE, "an unstructured mesh runs the first-order update (order 1)");
     if (!ctx->mask.empty()) return fail(ctx, GSIS_ESTATE, "an unstructured mesh takes no solid mask");
@@ -1069,6 +1073,17 @@ gsis_status gsis_set_boundary(gsis_ctx *ctx, int face, int kind, const double u[
     for (int a = 0; a < 3; ++a) ctx->bc.u[face][a] = u[a];
     ctx->bc.T[face] = T;
     ctx->bc.rho[face] = kind == GSIS_MAXWELL_INFLOW ? rho : 1.0;
+    return GSIS_OK;
+}
+
+gsis_status gsis_set_wall_flux(gsis_ctx *ctx, int model)
+{
+    if (!ctx) return GSIS_EINVAL;
+    if (ctx->bound) return fail(ctx, GSIS_ESTATE, "set_wall_flux must precede bind_workspace");
+    if (model != GSIS_WALLFLUX_MAXWELL && model != GSIS_WALLFLUX_G13) return fail(ctx, GSIS_EINVAL, "unknown wall flux model");
+    if (ctx->g.umesh && model != GSIS_WALLFLUX_MAXWELL)
+        return fail(ctx, GSIS_EINVAL, "the Grad-13 wall flux runs on box meshes only");
+    ctx->g.wall_flux = model;
     return GSIS_OK;
 }
 
@@ -1814,6 +1829,7 @@ hipError_t batch_build_maps(gsis_batch *b)
     t.dia = b->dia;
     t.mask = false;
     for (const gsis_ctx *c : b->cs) t.mask = t.mask || c->g.nfluid != c->g.ncell;
+    for (const gsis_ctx *c : b->cs) t.g13 = t.g13 || c->g.wall_flux == GSIS_WALLFLUX_G13;
     t.rfn = false;
     t.tx = b->tx;
     t.ty = b->ty;

@@ -28,6 +28,7 @@ struct Target {
     int nvb = 0;
     bool fp32 = false, dia = false, mask = false, rfn = false;
     bool vlist = false;               // the node-list kernels (a refined or unstructured velocity mesh)
+    bool g13 = false;                 // some case takes the Grad-13 wall flux in its correction
     // the moment kernel runs once per vector width (1, 2, 4) over the cases of that width
     const int2 *mom_map[3] = {};
     int mom_nblk[3] = {};

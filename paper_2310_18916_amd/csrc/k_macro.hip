@@ -16,7 +16,11 @@
 // (one-sided at non-fluid neighbours) gradients.  Convective flux: Rusanov.
 // Boundary faces: F_kin + F_eq(W^m) - F_eq(W^{n+1/2}) -- the kinetic flux of
 // f^{n+1/2} keeps its non-equilibrium part while the equilibrium part
-// follows the iterate.  Pseudo time: the diagonal of Eq. (res_macro),
+// follows the iterate -- or, with the Grad-13 wall flux, the same with the
+// flux of the Grad-13 distributions of Eq. (G13_VDF) in place of F_eq, built
+// from the iterate and the stress and heat fluxes of Eq. (full_constitutive)
+// at the cell (NSF from its central gradients plus HoT_c, the kinetic values
+// of f^{n+1/2} minus the NSF values at W^{n+1/2}).  Pseudo time: the diagonal of Eq. (res_macro),
 // D_i = 1/dtau_i + (1/2) sum_faces Gamma / h, Gamma = s + C_d Tt^omega/(delta rho h),
 // with one global step D* = max_i D_i per iteration so the update is exactly
 // conservative, and the rotational relaxation 1/(Z tau) on the Er row.
@@ -232,6 +236,207 @@ __device__ void group_equilibrium_flux(const Geo &g, const BcInfo &bc, const Dev
     for (int k = 0; k < 6; ++k) F[k] = out[k] + sc * in[k];
 }
 
+// Stress and heat fluxes of Eq. (NSF_constitutive) at the face group's cell
+// from its central gradients (one-sided next to a non-fluid neighbour, zero
+// with none): lane sub of the group holds v = (ux, uy, uz, Tt, Tr) of the
+// cell's neighbour across direction sub (0..5; the cell's own state, with
+// has = false, where that is not a fluid cell), lanes 6 and 7 the cell's own;
+// mu = Tt^omega / delta of the cell.  sq = (sigma xx yy zz xy xz yz, q, qr),
+// the same in every lane of the group.
+__device__ __forceinline__ void group_cell_nsf(const Geo &g, const double v[5], bool has, double mu, double sq[12])
+{
+    const int base = (int)(threadIdx.x & 63) & ~(FG - 1);
+    double Gu[9], gt[3], gr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int hm = __shfl((int)has, base + 2 * a, 64), hp = __shfl((int)has, base + 2 * a + 1, 64);
+        const double iden = (hm && hp) ? 0.5 * g.invh[a] : g.invh[a];
+        const bool none = !hm && !hp;
+        double dv[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) dv[k] = __shfl(v[k], base + 2 * a + 1, 64) - __shfl(v[k], base + 2 * a, 64);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Gu[b * 3 + a] = none ? 0.0 : dv[b] * iden;
+        gt[a] = none ? 0.0 : dv[3] * iden;
+        gr[a] = none ? 0.0 : dv[4] * iden;
+    }
+    const double div = Gu[0] + Gu[4] + Gu[8];
+    sq[0] = -mu * (2.0 * Gu[0] - (2.0 / 3.0) * div);
+    sq[1] = -mu * (2.0 * Gu[4] - (2.0 / 3.0) * div);
+    sq[2] = -mu * (2.0 * Gu[8] - (2.0 / 3.0) * div);
+    sq[3] = -mu * (Gu[1] + Gu[3]);
+    sq[4] = -mu * (Gu[2] + Gu[6]);
+    sq[5] = -mu * (Gu[5] + Gu[7]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        sq[6 + a] = -g.kt * mu * gt[a];
+        sq[9 + a] = g.species == 1 ? -g.kr * mu * gr[a] : 0.0;
+    }
+}
+
+// sum over the outgoing half of w xi_n c^e B(c) M(c) / (rho (pi T)^{-3/2}) on
+// the tensor grid, c in the face's axes (normal, t1, t2), B the Grad-13
+// bracket 1 + cs sigma:cc + cq (q.c)(c5 |c|^2 - 1): products of the 1-D sums
+// N[i] = sum_{out} w e xi_n c_n^i and S1[j], S2[k] = sum w e c_t^j over the
+// tangential axes (e the 1-D Gaussian factor).
+template <int EN, int E1, int E2>
+__device__ __forceinline__ double g13_bsum(const double N[6], const double S1[6], const double S2[6],
+                                           const double sl[3][3], const double ql[3], double cs, double cq, double c5)
+{
+#define GSIS_A3(i, j, k) (N[(i) + EN] * S1[(j) + E1] * S2[(k) + E2])
+    double r = GSIS_A3(0, 0, 0);
+    r += cs * (sl[0][0] * GSIS_A3(2, 0, 0) + sl[1][1] * GSIS_A3(0, 2, 0) + sl[2][2] * GSIS_A3(0, 0, 2)
+               + 2.0 * (sl[0][1] * GSIS_A3(1, 1, 0) + sl[0][2] * GSIS_A3(1, 0, 1) + sl[1][2] * GSIS_A3(0, 1, 1)));
+    const double t = ql[0] * (c5 * (GSIS_A3(3, 0, 0) + GSIS_A3(1, 2, 0) + GSIS_A3(1, 0, 2)) - GSIS_A3(1, 0, 0))
+                   + ql[1] * (c5 * (GSIS_A3(2, 1, 0) + GSIS_A3(0, 3, 0) + GSIS_A3(0, 1, 2)) - GSIS_A3(0, 1, 0))
+                   + ql[2] * (c5 * (GSIS_A3(2, 0, 1) + GSIS_A3(0, 2, 1) + GSIS_A3(0, 0, 3)) - GSIS_A3(0, 0, 1));
+#undef GSIS_A3
+    return r + cq * t;
+}
+
+// The Grad-13 half-range sums of group_g13_flux on the tensor grid for a face
+// normal to axis A (a compile-time constant, so that every stress and heat-flux
+// component is picked by a constant index): out[6] before the boundary rule.
+template <int A>
+__device__ __forceinline__ void g13_tensor_flux(const Geo &g, const Dev &d, const double u[3], const double sq[12],
+                                                double sg, double iT, double K, double cs, double cq, double c5,
+                                                double cr, double h1, bool dia, int sub, double out[6])
+{
+    constexpr int T1 = (A + 1) % 3, T2 = (A + 2) % 3;
+    constexpr int ax[3] = {A, T1, T2};
+    // sq slot of sigma_{pq} in the face's axes: the diagonal 0..2, xy 3, xz 4, yz 5
+    auto sslot = [](int x, int y) constexpr { return x == y ? x : 2 + x + y; };
+    double N[6] = {0, 0, 0, 0, 0, 0}, S1[6] = {0, 0, 0, 0, 0, 0}, S2[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = sub; k < g.n1[A]; k += FG) {
+        const double x = G(d.xi64[A])[k];
+        if (!(sg * x > 0.0)) continue;
+        const double c = x - u[A];
+        double e = G(d.w64[A])[k] * exp_core(fmax(-c * c * iT, -745.0)) * x;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            N[p] += e;
+            e *= c;
+        }
+    }
+    for (int k = sub; k < g.n1[T1]; k += FG) {
+        const double c = G(d.xi64[T1])[k] - u[T1];
+        double e = G(d.w64[T1])[k] * exp_core(fmax(-c * c * iT, -745.0));
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            S1[p] += e;
+            e *= c;
+        }
+    }
+    for (int k = sub; k < g.n1[T2]; k += FG) {
+        const double c = G(d.xi64[T2])[k] - u[T2];
+        double e = G(d.w64[T2])[k] * exp_core(fmax(-c * c * iT, -745.0));
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            S2[p] += e;
+            e *= c;
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        N[p] = group_sum(N[p]);
+        S1[p] = group_sum(S1[p]);
+        S2[p] = group_sum(S2[p]);
+    }
+    double sl[3][3], ql[3], rl[3], ul[3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) sl[p][q] = sq[sslot(ax[p], ax[q])];
+        ql[p] = sq[6 + ax[p]];
+        rl[p] = sq[9 + ax[p]];
+        ul[p] = u[ax[p]];
+    }
+    const double b0 = g13_bsum<0, 0, 0>(N, S1, S2, sl, ql, cs, cq, c5);
+    const double bn = g13_bsum<1, 0, 0>(N, S1, S2, sl, ql, cs, cq, c5);
+    const double b1 = g13_bsum<0, 1, 0>(N, S1, S2, sl, ql, cs, cq, c5);
+    const double b2 = g13_bsum<0, 0, 1>(N, S1, S2, sl, ql, cs, cq, c5);
+    const double bnn = g13_bsum<2, 0, 0>(N, S1, S2, sl, ql, cs, cq, c5);
+    const double b11 = g13_bsum<0, 2, 0>(N, S1, S2, sl, ql, cs, cq, c5);
+    const double b22 = g13_bsum<0, 0, 2>(N, S1, S2, sl, ql, cs, cq, c5);
+    out[0] = K * b0;
+    out[1 + A] = K * (bn + ul[0] * b0);
+    out[1 + T1] = K * (b1 + ul[1] * b0);
+    out[1 + T2] = K * (b2 + ul[2] * b0);
+    const double uu = ul[0] * ul[0] + ul[1] * ul[1] + ul[2] * ul[2];
+    const double e0 = bnn + b11 + b22 + 2.0 * (ul[0] * bn + ul[1] * b1 + ul[2] * b2) + uu * b0;
+    const double sr = rl[0] * N[1] * S1[0] * S2[0] + rl[1] * N[0] * S1[1] * S2[0] + rl[2] * N[0] * S1[0] * S2[1];
+    const double f1 = dia ? K * (h1 * b0 + cr * sr) : 0.0;
+    out[4] = K * e0 + f1;
+    out[5] = f1;
+}
+
+// The flux of boundary face dir when the cell holds the Grad-13 distributions
+// of Eq. (G13_VDF) of its state P and sq = (sigma, q, qr) (Eq. GSIS-DVM-flux),
+// with the face's boundary rule (a wall's density from zero net mass flux):
+//   f0 = M [1 + sigma:cc / (rho Tt^2) + 2 (q.c) / (rho Tt^2) (2 |c|^2 / (5 Tt) - 1)],
+//   f1 = (dr/2) Tr f0 + 2 M (qr.c) / (rho Tt),
+// velocities in sqrt(2 R T0) (these forms give back rho, u, Tt, sigma, q, Tr
+// and qr as the moments of Eq. getmoment).  A group of FG lanes per face, as
+// group_equilibrium_flux.
+template <class PV>
+__device__ __forceinline__ void group_g13_flux(const Geo &g, const BcInfo &bc, const Dev &d, const PV &P, const double sq[12], int dir,
+                               int b, int sub, double F[6])
+{
+    const int a = dir / 2;
+    const double sg = (dir & 1) ? 1.0 : -1.0;
+    const double T = P[4], iT = 1.0 / T;
+    const double piT = PI * T;
+    const double K = P[0] / (piT * sqrt(piT)) * sg;
+    const double u[3] = {P[1], P[2], P[3]};
+    const double irT2 = 1.0 / (P[0] * T * T);
+    const double cs = irT2, cq = 2.0 * irT2, c5 = 2.0 / (5.0 * T);
+    const double cr = 2.0 / (P[0] * T);
+    const bool dia = g.species == 1;
+    const double h1 = dia ? 0.5 * g.dr * P[5] : 0.0;
+    const gptr<const double> in = G((const double *)d.inpsi) + (b * 6 + dir) * 6;
+    double out[6];
+    if (g.vlist) {
+        double s0 = 0.0, s1[3] = {0.0, 0.0, 0.0}, s4 = 0.0, sr = 0.0;
+        const gptr<const double> nt = G((const double *)d.nt64);
+        for (int k = sub; k < g.nv; k += FG) {
+            const double x = nt[4 * (size_t)k + a];
+            if (!(sg * x > 0.0)) continue;
+            const double v0 = nt[4 * (size_t)k], v1 = nt[4 * (size_t)k + 1], v2 = nt[4 * (size_t)k + 2];
+            const double cx = v0 - u[0], cy = v1 - u[1], cz = v2 - u[2];
+            const double cc = cx * cx + cy * cy + cz * cz;
+            const double e = nt[4 * (size_t)k + 3] * exp_core(fmax(-cc * iT, -745.0)) * x;
+            const double scc = sq[0] * cx * cx + sq[1] * cy * cy + sq[2] * cz * cz
+                             + 2.0 * (sq[3] * cx * cy + sq[4] * cx * cz + sq[5] * cy * cz);
+            const double qc = sq[6] * cx + sq[7] * cy + sq[8] * cz;
+            const double eb = e * (1.0 + cs * scc + cq * qc * (c5 * cc - 1.0));
+            s0 += eb;
+            s1[0] += eb * v0;
+            s1[1] += eb * v1;
+            s1[2] += eb * v2;
+            s4 += eb * (v0 * v0 + v1 * v1 + v2 * v2);
+            if (dia) sr += e * (sq[9] * cx + sq[10] * cy + sq[11] * cz);
+        }
+        s0 = group_sum(s0);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) s1[q] = group_sum(s1[q]);
+        s4 = group_sum(s4);
+        sr = group_sum(sr);
+        out[0] = K * s0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) out[1 + q] = K * s1[q];
+        const double f1 = dia ? K * (h1 * s0 + cr * sr) : 0.0;
+        out[4] = K * s4 + f1;
+        out[5] = f1;
+    } else {
+        if (a == 0) g13_tensor_flux<0>(g, d, u, sq, sg, iT, K, cs, cq, c5, cr, h1, dia, sub, out);
+        else if (a == 1) g13_tensor_flux<1>(g, d, u, sq, sg, iT, K, cs, cq, c5, cr, h1, dia, sub, out);
+        else g13_tensor_flux<2>(g, d, u, sq, sg, iT, K, cs, cq, c5, cr, h1, dia, sub, out);
+    }
+    const double sc = bc.kind[b] == 1 ? bc.rho[b] : out[0] / (-in[0]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) F[k] = out[k] + sc * in[k];
+}
+
 // Gamma of a boundary face: outward speed plus the diffusive term of the cell
 template <class PV>
 __device__ __forceinline__ double boundary_gamma(const Geo &g, const PV &P, int a, bool euler)
@@ -353,6 +558,9 @@ __global__ __launch_bounds__(128) void k_mac_hot(GSIS_SPAN_ARGS, int euler)
 // Fixed part of each boundary face flux, F_kin(f^{n+1/2}) - F_eq(W^{n+1/2}), and
 // the face flux of the first inner iteration, fixed part + F_eq(W^{n+1/2}).
 // One group of FG lanes per face.
+// G13: compiled with the Grad-13 wall flux for the cases that take it (the
+// plain instantiation keeps its registers for the common path).
+template <bool G13>
 __global__ __launch_bounds__(256) void k_mac_fbfix(GSIS_SPAN_ARGS, int euler)
 {
     int blk;
@@ -382,7 +590,34 @@ __global__ __launch_bounds__(256) void k_mac_fbfix(GSIS_SPAN_ARGS, int euler)
     const double sc = bc.kind[b] == 1 ? bc.rho[b] : out[0] / (-in[0]);
     const Soa<double> P = soa(d.P, g.ncell, cell);
     double Fe[6];
-    group_equilibrium_flux(g, bc, d, P, dir, b, sub, Fe);
+    if (G13 && g.wall_flux == 1 && !euler) {
+        // Grad-13 wall flux: the cell's high-order terms, HoT_c = kinetic stress
+        // and heat fluxes of f^{n+1/2} - NSF_c(W^{n+1/2}), kept per face, and the
+        // flux of the distributions of NSF_c + HoT_c
+        int who = cell;
+        bool has = false;
+        if (sub < 6) {
+            const int nb = G(d.nbr)[(size_t)sub * g.ncell + cell];
+            if (nb >= 0) { who = nb; has = true; }
+        }
+        const Soa<double> Pw = soa(d.P, g.ncell, who);
+        const double v[5] = {Pw[1], Pw[2], Pw[3], Pw[4], Pw[5]};
+        double sq[12];
+        group_cell_nsf(g, v, has, P[9], sq);
+        const gptr<const double> m = G((const double *)d.cm) + (size_t)cell * NMOM;
+        const bool dia = g.species == 1;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            // cm: sigma at 5..10, q at 11..13, qr at 15..17
+            const double kin = k < 9 ? m[5 + k] : (dia ? m[6 + k] : 0.0);
+            const double hot = kin - sq[k];
+            if ((k & (FG - 1)) == sub) G(d.ghot)[(size_t)k * g.nface + f] = hot;
+            sq[k] += hot;
+        }
+        group_g13_flux(g, bc, d, P, sq, dir, b, sub, Fe);
+    } else {
+        group_equilibrium_flux(g, bc, d, P, dir, b, sub, Fe);
+    }
     if (sub < 6) {
         // Euler: the boundary flux is the iterate's own F_eq, no fixed kinetic part
         const double fix = euler ? 0.0 : out[sub] + sc * in[sub] - Fe[sub];
@@ -557,6 +792,7 @@ __device__ __forceinline__ void stepped_mass_momentum(const Geo &g, const Dev &d
 // boundary face, then (cell, axis) threads (the axis-0 blocks also write W'
 // and the prims).  Neighbours' new velocities and the face cells' new prims are
 // formed from W and R directly, so W is double buffered (read src, write dst).
+template <bool G13>
 __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, int parity, int last, int euler)
 {
     int blk;
@@ -617,7 +853,27 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
     stepped_W(g, d, Ws, cell, Dm, iDm, Wn);
     prim_from_W(g, Wn, P);
     double Fe[6];
-    group_equilibrium_flux(g, bc, d, P, dir, G(d.face_bc)[f], sub, Fe);
+    if (G13 && g.wall_flux == 1 && !euler) {
+        // Grad-13 wall flux of the new state: NSF_c from the new states of the
+        // cell and its neighbours (one per lane) plus the cell's HoT_c
+        int who = cell;
+        bool has = false;
+        if (sub < 6) {
+            const int nb = G(d.nbr)[(size_t)sub * g.ncell + cell];
+            if (nb >= 0) { who = nb; has = true; }
+        }
+        double Ww[6], Pw[NP];
+        stepped_W(g, d, Ws, who, Dm, iDm, Ww);
+        prim_from_W(g, Ww, Pw);
+        const double v[5] = {Pw[1], Pw[2], Pw[3], Pw[4], Pw[5]};
+        double sq[12];
+        group_cell_nsf(g, v, has, P[9], sq);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) sq[k] += G(d.ghot)[(size_t)k * g.nface + f];
+        group_g13_flux(g, bc, d, P, sq, dir, G(d.face_bc)[f], sub, Fe);
+    } else {
+        group_equilibrium_flux(g, bc, d, P, dir, G(d.face_bc)[f], sub, Fe);
+    }
     if (sub < 6) G(d.Fb)[(size_t)sub * g.nface + f] = G(d.fbfix)[(size_t)sub * g.nface + f] + Fe[sub];
     if (sub == 7) G(d.Gb)[f] = boundary_gamma(g, P, dir / 2, euler);
 }
@@ -652,8 +908,10 @@ hipError_t launch_gsis_macro(const Target &t, int iters, hipStream_t s, int eule
     hipLaunchKernelGGL(k_mac_init, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(t.span(K_CELL128)));
     hipLaunchKernelGGL(k_mac_grad, dim3(t.nblk[K_GRAD]), dim3(256), 0, s, GSIS_SPAN(t.span(K_GRAD)), 0, euler);
     hipLaunchKernelGGL(k_mac_hot, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(t.span(K_CELL128)), euler);
-    if (t.nblk[K_FACE8] > 0)
-        hipLaunchKernelGGL(k_mac_fbfix, dim3(t.nblk[K_FACE8]), dim3(256), 0, s, GSIS_SPAN(t.span(K_FACE8)), euler);
+    if (t.nblk[K_FACE8] > 0) {
+        if (t.g13) hipLaunchKernelGGL(k_mac_fbfix<true>, dim3(t.nblk[K_FACE8]), dim3(256), 0, s, GSIS_SPAN(t.span(K_FACE8)), euler);
+        else hipLaunchKernelGGL(k_mac_fbfix<false>, dim3(t.nblk[K_FACE8]), dim3(256), 0, s, GSIS_SPAN(t.span(K_FACE8)), euler);
+    }
     for (int it = 0; it < iters; ++it) {
         const int slot = it & 1;
         // the Euler form is its own instantiation: a run-time flag costs the
@@ -667,8 +925,12 @@ hipError_t launch_gsis_macro(const Target &t, int iters, hipStream_t s, int eule
             if (euler) hipLaunchKernelGGL((k_mac_res<false, true>), gr, bl, 0, s, GSIS_SPAN(sp), slot);
             else hipLaunchKernelGGL((k_mac_res<false, false>), gr, bl, 0, s, GSIS_SPAN(sp), slot);
         }
-        hipLaunchKernelGGL(k_mac_advance, dim3(t.nblk[K_GRAD]), dim3(256), 0, s, GSIS_SPAN(t.span(K_GRAD)), slot, it & 1,
-                           it == iters - 1 ? 1 : 0, euler);
+        if (t.g13)
+            hipLaunchKernelGGL(k_mac_advance<true>, dim3(t.nblk[K_GRAD]), dim3(256), 0, s, GSIS_SPAN(t.span(K_GRAD)), slot,
+                               it & 1, it == iters - 1 ? 1 : 0, euler);
+        else
+            hipLaunchKernelGGL(k_mac_advance<false>, dim3(t.nblk[K_GRAD]), dim3(256), 0, s, GSIS_SPAN(t.span(K_GRAD)), slot,
+                               it & 1, it == iters - 1 ? 1 : 0, euler);
     }
     hipLaunchKernelGGL(k_mac_final, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(t.span(K_CELL128)));
     return hipGetLastError();

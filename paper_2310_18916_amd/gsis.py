@@ -76,6 +76,8 @@ class Context:
         for face, bc in enumerate(case.bcs):
             u = (C.c_double * 3)(*bc.u)
             self._check(self.L.gsis_set_boundary(self.h, face, bc.kind, u, bc.T, bc.rho), "gsis_set_boundary")
+        if case.wall_flux:
+            self._check(self.L.gsis_set_wall_flux(self.h, case.wall_flux), "gsis_set_wall_flux")
         if case.nodes is not None:
             for a, x in enumerate(case.nodes):
                 if x is None:
