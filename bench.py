@@ -15,6 +15,7 @@ reported as extra keys.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -381,12 +382,21 @@ def gsis_extras(a, steps, warmup):
                                                                  + r["prof"]["moments"][0]) * 1e-3)}
         del r
     out["speedup_fp32_vs_fp64"] = out["fp32"]["value"] / out["fp64"]["value"]
+    # the Grad-13 wall flux of the correction (gsis_set_wall_flux): its step
+    g13 = dataclasses.replace(case, wall_flux=1)
+    r = run_gpu(g13, "fp64", steps, warmup, macro, out["fp64"]["sweep_tile"])
+    out["fp64_g13_wall_flux"] = {"value": pts * steps / r["seconds"], "ms_per_step": r["seconds"] / steps * 1e3,
+                                 "phases_ms_per_step": {k: v[0] / steps for k, v in r["prof"].items()}}
+    del r
     if not a.no_converge:
         c64, m64 = converge(case, "fp64", out["fp64"]["sweep_tile"], max_iters=100)
         c32, m32 = converge(case, "fp32", out["fp32"]["sweep_tile"], max_iters=100)
         out["converged"] = {"tol": 1e-6, "fp64": c64, "fp32": c32,
                             "fp32_vs_fp64_max_rel_diff": field_diff(m32, m64),
                             "speedup_fp32_vs_fp64_time_to_converge": c64["seconds"] / c32["seconds"]}
+        cg, mg = converge(g13, "fp64", out["fp64"]["sweep_tile"], max_iters=100)
+        out["converged"]["fp64_g13_wall_flux"] = cg
+        out["converged"]["g13_vs_maxwell_wall_flux_max_rel_diff"] = field_diff(mg, m64)
         if a.precondition != "none":
             pre = tuple(int(x) for x in a.precondition.split(","))
             cp, mp = converge(case, "fp64", out["fp64"]["sweep_tile"], pre=pre, max_iters=100)
@@ -565,6 +575,9 @@ def main():
             out["converged"] = {"tol": 1e-6, "fp64": c64, "fp32": c32,
                                 "fp32_vs_fp64_max_rel_diff": field_diff(m32, m64),
                                 "speedup_fp32_vs_fp64_time_to_converge": c64["seconds"] / c32["seconds"]}
+        cg, mg = converge(g13, "fp64", out["fp64"]["sweep_tile"], max_iters=100)
+        out["converged"]["fp64_g13_wall_flux"] = cg
+        out["converged"]["g13_vs_maxwell_wall_flux_max_rel_diff"] = field_diff(mg, m64)
     elif not a.no_gsis_extras:
         out["gsis_c2"] = gsis_extras(a, steps, a.warmup)
     if a.workload == "c3" and not a.no_refined:
