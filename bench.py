@@ -575,9 +575,6 @@ def main():
             out["converged"] = {"tol": 1e-6, "fp64": c64, "fp32": c32,
                                 "fp32_vs_fp64_max_rel_diff": field_diff(m32, m64),
                                 "speedup_fp32_vs_fp64_time_to_converge": c64["seconds"] / c32["seconds"]}
-        cg, mg = converge(g13, "fp64", out["fp64"]["sweep_tile"], max_iters=100)
-        out["converged"]["fp64_g13_wall_flux"] = cg
-        out["converged"]["g13_vs_maxwell_wall_flux_max_rel_diff"] = field_diff(mg, m64)
     elif not a.no_gsis_extras:
         out["gsis_c2"] = gsis_extras(a, steps, a.warmup)
     if a.workload == "c3" and not a.no_refined:

@@ -30,7 +30,11 @@ constexpr int RB = 256;      // nodes per block: one run of an octant
 // which the blocks of those columns read at about the same time.  Logical
 // block = run * (nx ny) + column; blocks are dealt to the 8 XCDs round
 // robin, so logical block (b mod 8) (nblk / 8) + b / 8 gives every XCD one
-// contiguous range of columns.
+// contiguous range of columns.  Within a run the columns go in patches of
+// RPX x RPY (where nx and ny divide), so that the y neighbours of a column
+// are read by blocks RPX apart instead of nx apart and find their lines in
+// the XCD's L2 (48^3 x 32^3 cavity, FP64: 65.0 -> 59.3 ms per pass).
+constexpr int RPX = 8, RPY = 8;
 struct ReconBlock { int o, l, col, i, j; };
 
 __device__ __forceinline__ ReconBlock recon_block(const Geo &g, int nvb)
@@ -41,9 +45,18 @@ __device__ __forceinline__ ReconBlock recon_block(const Geo &g, int nvb)
     const int ncol = g.nx * g.ny;
     const int chunk = b / ncol;
     ReconBlock r;
-    r.col = b - chunk * ncol;
-    r.i = r.col % g.nx;
-    r.j = r.col / g.nx;
+    const int rem = b - chunk * ncol;
+    if (g.nx % RPX == 0 && g.ny % RPY == 0) {
+        const int p = rem / (RPX * RPY), w = rem - p * (RPX * RPY);
+        const int ppr = g.nx / RPX;
+        r.i = (p % ppr) * RPX + w % RPX;
+        r.j = (p / ppr) * RPY + w / RPX;
+        r.col = r.i + g.nx * r.j;
+    } else {
+        r.col = rem;
+        r.i = r.col % g.nx;
+        r.j = r.col / g.nx;
+    }
     r.o = chunk / nvb;
     r.l = (chunk - r.o * nvb) * RB + (int)threadIdx.x;
     return r;
