@@ -107,8 +107,7 @@ typedef struct {
     /* macroscopic boundary flux of the correction (Sec. 3.3): 0 the cell's
      * Maxwellian (F_eq), 1 the Grad-13 reconstruction of Eq. (G13_VDF) from
      * the iterate and Eq. (full_constitutive) (F_G13); both enter as the
-     * kinetic flux plus the change of the model flux from W^{n+1/2} to W^m.
-     * Box meshes only. */
+     * kinetic flux plus the change of the model flux from W^{n+1/2} to W^m. */
     int wall_flux;
 } orc_cfg;
 
@@ -214,7 +213,6 @@ static orc_state *create_state(const orc_cfg *cfg, const unsigned char *solid, i
     if (!um && (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1)) return NULL;
     if (cfg->order != 1 && cfg->order != 2) return NULL;
     if (cfg->wall_flux != 0 && cfg->wall_flux != 1) return NULL;
-    if (um && cfg->wall_flux != 0) return NULL;
     if (!isfinite(cfg->limiter_k)) return NULL;
     const int list = cfg->nlist > 0;
     if (cfg->nlist < 0 || (list && !cfg->node_list)) return NULL;
@@ -1539,13 +1537,22 @@ static void cell_tgrad(const orc_state *s, const prim_t *P, int cell, double gt[
     }
 }
 
+static void ucell_grad(const orc_state *s, const prim_t *P, int i, double G[9]);
+static void ucell_tgrad(const orc_state *s, const prim_t *P, int i, double gt[3], double gr[3]);
+
 /* Stress and heat fluxes of a cell by Eq. (NSF_constitutive) from its central
- * gradients, sq = (sigma xx yy zz xy xz yz, q, qr), mu = Tt^omega / delta. */
+ * gradients (on an unstructured mesh its least-squares gradients), sq =
+ * (sigma xx yy zz xy xz yz, q, qr), mu = Tt^omega / delta. */
 static void cell_nsf(const orc_state *s, const macpar *mp, const prim_t *P, int cell, double sq[12])
 {
     double G[9], gt[3], gr[3];
-    cell_grad(s, P, cell, G);
-    cell_tgrad(s, P, cell, gt, gr);
+    if (s->umesh) {
+        ucell_grad(s, P, cell, G);
+        ucell_tgrad(s, P, cell, gt, gr);
+    } else {
+        cell_grad(s, P, cell, G);
+        cell_tgrad(s, P, cell, gt, gr);
+    }
     double mu = pow(P[cell].Tt, mp->omega) / mp->delta;
     double div = G[0] + G[4] + G[8];
     static const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
@@ -2045,6 +2052,37 @@ static void ucell_grad(const orc_state *s, const prim_t *P, int i, double G[9])
         }
 }
 
+/* Least-squares gradients of Tt and Tr of cell i, with the weights of
+ * ucell_grad. */
+static void ucell_tgrad(const orc_state *s, const prim_t *P, int i, double gt[3], double gr[3])
+{
+    double A[9] = {0}, bt[3] = {0}, br[3] = {0}, Ai[9];
+    const double *xi = s->ucen + (size_t)i * 3;
+    for (int e = s->cf_off[i]; e < s->cf_off[i + 1]; ++e) {
+        double n[3], sv;
+        int j;
+        uface_of(s, i, s->cf[e], n, &sv, &j);
+        if (j < 0) continue;
+        const double *xj = s->ucen + (size_t)j * 3;
+        double d[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
+        for (int b = 0; b < 3; ++b) {
+            for (int c = 0; c < 3; ++c) A[b * 3 + c] += d[b] * d[c];
+            bt[b] += (P[j].Tt - P[i].Tt) * d[b];
+            br[b] += (P[j].Tr - P[i].Tr) * d[b];
+        }
+    }
+    sym3_pinv(A, Ai);
+    for (int c = 0; c < 3; ++c) {
+        double at = 0, ar = 0;
+        for (int k = 0; k < 3; ++k) {
+            at += bt[k] * Ai[k * 3 + c];
+            ar += br[k] * Ai[k * 3 + c];
+        }
+        gt[c] = at;
+        gr[c] = ar;
+    }
+}
+
 /* Flux from L to R across a face of unit normal n (out of L), d = x_R - x_L,
  * hot = HoT of the six flux components added as given. */
 static void uface_flux(const macpar *mp, const prim_t *L, const prim_t *R, const double *gL, const double *gR,
@@ -2144,7 +2182,7 @@ static void ukinetic_face_flux(const orc_state *s, int f, double F[6])
 
 /* F_eq of boundary face f: its flux when the owner holds the Maxwellian of P
  * (f1 = (dr/2) Tr M), with the boundary rule of the face. */
-static void uequilibrium_face_flux(const orc_state *s, const prim_t *P, int f, double F[6])
+static void umodel_face_flux(const orc_state *s, const prim_t *P, const double *sq, int f, double F[6])
 {
     const orc_cfg *c = &s->c;
     const double *g = s->ufg + (size_t)f * 4;
@@ -2155,11 +2193,15 @@ static void uequilibrium_face_flux(const orc_state *s, const prim_t *P, int f, d
     if (c->bc_kind[bc] == ORC_WALL) {
         nsum out = {0, 0}, in = {0, 0};
         for (int v = 0; v < s->nv; ++v) {
-            double xi[3], w;
+            double xi[3], w, o0, o1;
             node_xi(s, v, xi, &w);
             double xn = xi[0] * g[1] + xi[1] * g[2] + xi[2] * g[3];
-            if (xn > 0) nadd(&out, w * xn * maxwellian_pre(P->rho, pc, P->u, P->Tt, xi));
-            else if (xn < 0) nadd(&in, w * (-xn) * Mb[v]);
+            if (xn > 0) {
+                g13_vdf(c, P, pc, sq, xi, &o0, &o1);
+                nadd(&out, w * xn * o0);
+            } else if (xn < 0) {
+                nadd(&in, w * (-xn) * Mb[v]);
+            }
         }
         sc = nval(&out) / nval(&in);
     }
@@ -2172,8 +2214,7 @@ static void uequilibrium_face_flux(const orc_state *s, const prim_t *P, int f, d
         if (xn == 0.0) continue;
         double a0, a1;
         if (xn > 0) {
-            a0 = maxwellian_pre(P->rho, pc, P->u, P->Tt, xi);
-            a1 = dia ? 0.5 * c->dr * P->Tr * a0 : 0.0;
+            g13_vdf(c, P, pc, sq, xi, &a0, &a1);
         } else {
             a0 = sc * Mb[v];
             a1 = dia ? 0.5 * c->dr * c->bc_T[bc] * a0 : 0.0;
@@ -2215,6 +2256,10 @@ static int umacro_solve(orc_state *s, const moms *K, int iters, int euler, prim_
     double *R = calloc((size_t)ncell * 6, sizeof(double));
     double *Dc = calloc((size_t)ncell, sizeof(double));
     double *Src = calloc((size_t)ncell, sizeof(double));
+    /* Grad-13 wall flux: the high-order terms of the cells with a boundary
+     * face, as in macro_solve */
+    const int g13 = c->wall_flux == 1 && !euler;
+    double *hotc = g13 ? calloc((size_t)ncell * 12, sizeof(double)) : NULL;
     double hmin = INFINITY;
     for (int f = 0; f < nf; ++f) {
         double d[3], h = uface_h(s, f, d);
@@ -2232,6 +2277,11 @@ static int umacro_solve(orc_state *s, const moms *K, int iters, int euler, prim_
         prim_of(&mp, w, &P[cell]);
     }
     for (int cell = 0; cell < ncell; ++cell) ucell_grad(s, P, cell, grad + (size_t)cell * 9);
+    for (int f = 0; g13 && f < nf; ++f)
+        if (s->ufc[2 * f + 1] < 0) {
+            int L = s->ufc[2 * f];
+            g13_cell_hot(s, &mp, &K[L], P, L, hotc + (size_t)L * 12);
+        }
     /* fixed parts: F_kin(f^{n+1/2}) - F(W^{n+1/2}) at every face (zero for
      * Euler: no high-order terms, the boundary flux of the iterate's own
      * Maxwellian) */
@@ -2245,7 +2295,9 @@ static int umacro_solve(orc_state *s, const moms *K, int iters, int euler, prim_
             uface_flux(&mp, &P[L], &P[Rr], grad + (size_t)L * 9, grad + (size_t)Rr * 9, s->ufg + (size_t)f * 4 + 1, d,
                        nohot, Fm, &Gam);
         } else {
-            uequilibrium_face_flux(s, &P[L], f, Fm);
+            double sq[12];
+            if (g13) g13_cell_stress(s, &mp, P, L, hotc + (size_t)L * 12, sq);
+            umodel_face_flux(s, &P[L], g13 ? sq : NULL, f, Fm);
         }
         for (int k = 0; k < 6; ++k) fix[(size_t)f * 6 + k] = Fk[k] - Fm[k];
         if (!mp.dia && Rr >= 0) fix[(size_t)f * 6 + 5] = 0.0;
@@ -2263,8 +2315,9 @@ static int umacro_solve(orc_state *s, const moms *K, int iters, int euler, prim_
                 uface_flux(&mp, &P[L], &P[Rr], grad + (size_t)L * 9, grad + (size_t)Rr * 9, s->ufg + (size_t)f * 4 + 1,
                            d, fix + (size_t)f * 6, o, &o[6]);
             } else {
-                double Fe[6];
-                uequilibrium_face_flux(s, &P[L], f, Fe);
+                double Fe[6], sq[12];
+                if (g13) g13_cell_stress(s, &mp, P, L, hotc + (size_t)L * 12, sq);
+                umodel_face_flux(s, &P[L], g13 ? sq : NULL, f, Fe);
                 for (int k = 0; k < 6; ++k) o[k] = fix[(size_t)f * 6 + k] + Fe[k];
                 const double *g = s->ufg + (size_t)f * 4;
                 const prim_t *Pi = &P[L];
@@ -2314,7 +2367,7 @@ static int umacro_solve(orc_state *s, const moms *K, int iters, int euler, prim_
     if (bad) s->status = -5;
     if (!s->lastW) s->lastW = malloc(sizeof(double) * (size_t)ncell * 6);
     memcpy(s->lastW, W, sizeof(double) * (size_t)ncell * 6);
-    free(W); free(fix); free(grad); free(R); free(Dc); free(Src); free(Ff);
+    free(W); free(fix); free(grad); free(R); free(Dc); free(Src); free(Ff); free(hotc);
     return s->status;
 }
 
@@ -2456,7 +2509,7 @@ int orc_model_face_flux(const orc_state *s, const double W6[6], const double *sq
  * sq[12] as orc_g13_vdf.  Returns -1 for a solid or out-of-range cell. */
 int orc_g13_wall_stress(const orc_state *s, const double *Wm, int cell, double sq[12])
 {
-    if (s->umesh || cell < 0 || cell >= s->ncell || s->solid[cell]) return -1;
+    if ((s->umesh && !s->ucen) || cell < 0 || cell >= s->ncell || s->solid[cell]) return -1;
     const orc_cfg *c = &s->c;
     macpar mp;
     macro_params(s, &mp);

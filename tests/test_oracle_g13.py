@@ -17,6 +17,9 @@ Eq. G13_VDF and Eq. GSIS-DVM-flux).
 (e) The correction with this wall flux keeps a kinetic fixed point fixed and
     GSIS reaches the kinetic fixed point of a closed cavity, its mass constant
     once converged.
+(f) Unstructured meshes: whole hexahedra reproduce the box, kinetic fixed
+    points on tetrahedra and a mixed-element mesh stay fixed, and the
+    least-squares wall stress follows the NSF law on tetrahedra.
 """
 import dataclasses
 
@@ -221,11 +224,98 @@ def test_g13_gsis_reaches_the_kinetic_fixed_point_in_a_closed_box():
     assert abs(o.total_mass() - m1) <= 1e-12 * m1
 
 
-def test_g13_refused_on_unstructured_meshes():
-    mesh = I.lattice_mesh(2, 2, 2, 1.0, 1.0, 1.0, split=I.TET)
-    case = dataclasses.replace(I.on_mesh(I.cavity(2, 6, 0.3), mesh), wall_flux=1)
-    with pytest.raises(ValueError):
-        O.Oracle(case)
+def _list_case(case):
+    return I.with_velocity_list(case, I.tensor_velocity_list(case.nv, case.vmin, case.vmax))
+
+
+def _mixed_split(n, seed):
+    return np.random.default_rng(seed).integers(0, 4, size=(n[2], n[1], n[0]))
+
+
+@pytest.mark.parametrize("kind", ["cavity", "block", "n2_block"])
+def test_g13_hex_mesh_reproduces_the_box(kind):
+    """On whole hexahedra given as an unstructured mesh, the Grad-13 wall flux
+    (least-squares gradients of u, Tt and Tr, faces of any normal) gives the
+    box's GSIS iterations."""
+    if kind == "cavity":
+        box = _list_case(I.cavity(5, 6, 0.3, lid=0.2))
+        mesh = I.lattice_mesh(5, 5, 5, 1.0, 1.0, 1.0, split=I.HEX)
+    else:
+        sp = I.DIATOMIC if kind == "n2_block" else I.MONATOMIC
+        n, blk = ((6, 5, 5), ((2, 4), (2, 3), (2, 3))) if sp == I.DIATOMIC else ((7, 5, 6), ((2, 4), (1, 3), (2, 4)))
+        box = _list_case(I.small_block(species=sp, n=n, blk=blk, m=6))
+        mesh = I.lattice_mesh(box.nx, box.ny, box.nz, box.lx, box.ly, box.lz, split=I.HEX, solid=box.solid)
+    box = dataclasses.replace(box, wall_flux=1)
+    a, b = O.Oracle(box), O.Oracle(I.on_mesh(box, mesh))
+    a.init_maxwellian()
+    b.init_maxwellian()
+    for _ in range(2):
+        assert a.step(1) == 0 and b.step(1) == 0
+        assert a.gsis_correct(30) == 0 and b.gsis_correct(30) == 0
+    fluid = ~box.solid_mask().astype(bool)
+    ma, mb = a.moments()[fluid], b.moments()
+    assert np.abs(ma - mb).max() <= 1e-13 * np.abs(ma).max()
+
+
+def _mesh_fp_cases():
+    cav = I.cavity(3, 6, 0.3, lid=0.2)
+    dia = I.small_block(species=I.DIATOMIC, n=(5, 4, 4), blk=((2, 3), (1, 3), (1, 3)), m=8)
+    return {
+        "tet_cavity": I.on_mesh(cav, I.lattice_mesh(3, 3, 3, 1.0, 1.0, 1.0, split=I.TET)),
+        "n2_mixed_block": I.on_mesh(dia, I.lattice_mesh(5, 4, 4, dia.lx, dia.ly, dia.lz,
+                                                        split=_mixed_split((5, 4, 4), 7), solid=dia.solid)),
+    }
+
+
+@pytest.mark.parametrize("name", ["tet_cavity", "n2_mixed_block"])
+def test_g13_unstructured_kinetic_fixed_point_is_a_gsis_fixed_point(name):
+    case = dataclasses.replace(_mesh_fp_cases()[name], wall_flux=1)
+    o = O.Oracle(case)
+    o.init_maxwellian()
+    converge_kinetic(o)
+    f0, f1 = o.get_vdf()
+    assert o.gsis_correct(60) == 0
+    g0, g1 = o.get_vdf()
+    assert np.abs(g0 - f0).max() <= 1e-12 * np.abs(f0).max()
+    if f1 is not None:
+        assert np.abs(g1 - f1).max() <= 1e-12 * np.abs(f1).max()
+
+
+@pytest.mark.parametrize("species", [I.MONATOMIC, I.DIATOMIC])
+def test_g13_wall_stress_on_tetrahedra_follows_the_nsf_law(species):
+    """On Kuhn tetrahedra the least-squares gradients are exact for linear
+    fields, so the wall cell's stress and heat fluxes move by the NSF law
+    under a linear shear and linear temperatures, as on the box."""
+    case = I.cavity(3, 6, 0.3, lid=0.2)
+    if species == I.DIATOMIC:
+        case = n2(case)
+    mesh = I.lattice_mesh(3, 3, 3, 1.0, 1.0, 1.0, split=I.TET)
+    case = dataclasses.replace(I.on_mesh(case, mesh), wall_flux=1)
+    o = O.Oracle(case)
+    o.init_maxwellian()
+    assert o.step(2) == 0
+    m = o.moments()
+    rho, u, Tt = m[:, 0], m[:, 1:4], m[:, 4]
+    Tr = m[:, 14] if species == I.DIATOMIC else Tt
+    W0 = prims_to_W(case, rho, u, Tt, Tr)
+    X = np.asarray(mesh.centroid)
+    kt, kr = O.conductivities(case)
+    for cell in (0, mesh.ncell // 2, mesh.ncell - 1):
+        kin = np.concatenate([m[cell, 5:14], m[cell, 15:18] if species == I.DIATOMIC else np.zeros(3)])
+        assert np.abs(o.g13_wall_stress(W0, cell) - kin).max() <= 1e-12 * np.abs(kin).max()
+        mu = Tt[cell] ** case.omega / (np.sqrt(np.pi) / (2.0 * case.Kn))
+        a, b, br = 0.07, -0.05, 0.04
+        u1 = u.copy()
+        u1[:, 0] += a * (X[:, 1] - X[cell, 1])
+        T1 = Tt + b * (X[:, 0] - X[cell, 0])
+        Tr1 = Tr + br * (X[:, 2] - X[cell, 2]) if species == I.DIATOMIC else T1
+        sq = o.g13_wall_stress(prims_to_W(case, rho, u1, T1, Tr1), cell)
+        expect = kin.copy()
+        expect[3] -= mu * a
+        expect[6] -= kt * mu * b
+        if species == I.DIATOMIC:
+            expect[11] -= kr * mu * br
+        assert np.abs(sq - expect).max() <= 1e-11 * np.abs(expect).max() + 1e-15, (cell, sq - expect)
 
 
 def cell_centres(case):
