@@ -191,11 +191,12 @@ gsis_status gsis_set_boundary(gsis_ctx *ctx, int face, int kind, const double u[
  * c = xi - u, M the Maxwellian of (rho, u, Tt), built from the iterate's
  * rho, u, Tt, Tr and the stress and heat fluxes of Eq. (full_constitutive) at
  * the cell: the NSF values of the iterate's central gradients (one-sided next
- * to a non-fluid neighbour) plus the cell's high-order terms, the kinetic
+ * to a non-fluid neighbour; on an unstructured mesh the least-squares
+ * gradients of u, Tt and Tr) plus the cell's high-order terms, the kinetic
  * values of f^{n+1/2} minus the NSF values at W^{n+1/2}.  Either way the flux
  * at W^{n+1/2} is the kinetic one, so a kinetic fixed point stays a fixed
- * point.  Box meshes only.  Must precede gsis_bind_workspace; EINVAL on an
- * unknown model or G13 on an unstructured mesh, ESTATE once bound. */
+ * point.  Must precede gsis_bind_workspace; EINVAL on an unknown model,
+ * ESTATE once bound. */
 gsis_status gsis_set_wall_flux(gsis_ctx *ctx, int model);
 
 /* Bytes of device workspace the context needs (after the mask is set). */

@@ -65,7 +65,7 @@ struct Geo {
     int ucen;      // 1: centroids given (the macroscopic correction runs)
     double uhmin;  // smallest face distance h of the macroscopic pseudo time step
     // macroscopic boundary flux of the correction: 0 the Maxwellian's change,
-    // 1 the Grad-13 distributions' change (box meshes)
+    // 1 the Grad-13 distributions' change
     int wall_flux;
 };
 
@@ -149,6 +149,7 @@ struct Dev {
     int *ubf_face;     // [unbf] the face of every boundary face
     int *uf_cell;
     double *uf_geo, *uFk, *ufix, *uFf, *ubin;
+    double *ubsq, *ubhot;   // Grad-13 wall flux: per boundary face [12][unbf] the stress of the iterate, HoT_c
     double *corr;      // [ncell][NCORR]
     double *snap;      // [ncell][NSNAP]
     // macroscopic solve, all structures of arrays [field][ncell] ([field][nface]

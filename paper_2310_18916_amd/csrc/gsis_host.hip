@@ -334,6 +334,7 @@ size_t layout(gsis_ctx *c, char *base)
     d.ucls = nullptr; d.ulev = nullptr;
     d.ucf_lsq = nullptr; d.ucf_face = nullptr; d.uf_cell = nullptr; d.ucf_first = nullptr; d.ubf_face = nullptr;
     d.uf_geo = d.uFk = d.ufix = d.uFf = d.ubin = nullptr;
+    d.ubsq = d.ubhot = nullptr;
     d.ubf_cell = d.ubf_slot = nullptr; d.ubf_n = nullptr; d.ubf_s64 = nullptr; d.ubf_s32 = nullptr;
     if (g.umesh) {
         const size_t ne = c->ucf_nb.size(), nb = std::max(g.unbf, 1);
@@ -361,6 +362,8 @@ size_t layout(gsis_ctx *c, char *base)
             carve(off, d.ufix, nfc * 6, base);
             carve(off, d.uFf, nfc * 7, base);
             carve(off, d.ubin, nb * 6, base);
+            carve(off, d.ubsq, nb * 12, base);
+            carve(off, d.ubhot, nb * 12, base);
         }
     }
     carve(off, d.corr, n * NCORR, base);
@@ -771,8 +774,6 @@ gsis_status gsis_set_spatial_mesh(gsis_ctx *ctx, int ncell, const double *volume
     if (!ctx) return GSIS_EINVAL;
     if (ctx->bound || ctx->meta_ready) return fail(ctx, GSIS_ESTATE, "set_spatial_mesh must precede workspace_size/bind");
     if (ctx->g.umesh) return fail(ctx, GSIS_ESTATE, "the spatial mesh is already set");
-    if (ctx->g.wall_flux != GSIS_WALLFLUX_MAXWELL)
-        return fail(ctx, GSIS_ESTATE, "the Grad-13 wall flux runs on box meshes only");
     if (!ctx->g.vlist) return fail(ctx, GSIS_ESTATE, "set_velocity_list must precede set_spatial_mesh");
     if (ctx->g.order != 1) return fail(ctx, GSIS_ESTATE, "an unstructured mesh runs the first-order update (order 1)");
     if (!ctx->mask.empty()) return fail(ctx, GSIS_ESTATE, "an unstructured mesh takes no solid mask");
@@ -1081,8 +1082,6 @@ gsis_status gsis_set_wall_flux(gsis_ctx *ctx, int model)
     if (!ctx) return GSIS_EINVAL;
     if (ctx->bound) return fail(ctx, GSIS_ESTATE, "set_wall_flux must precede bind_workspace");
     if (model != GSIS_WALLFLUX_MAXWELL && model != GSIS_WALLFLUX_G13) return fail(ctx, GSIS_EINVAL, "unknown wall flux model");
-    if (ctx->g.umesh && model != GSIS_WALLFLUX_MAXWELL)
-        return fail(ctx, GSIS_EINVAL, "the Grad-13 wall flux runs on box meshes only");
     ctx->g.wall_flux = model;
     return GSIS_OK;
 }

@@ -1149,24 +1149,103 @@ __global__ __launch_bounds__(256) void k_umac_iflux(GSIS_SPAN_ARGS, int mode, in
     }
 }
 
-// Boundary faces, UBF to a wave: F_eq of the owner's Maxwellian (outgoing
+// Stress and heat fluxes of the Grad-13 wall flux at every boundary face's
+// cell, one thread per boundary face: the NSF values of the current iterate
+// (its least-squares velocity gradient and the gradients of Tt and Tr with the
+// same weights) plus the cell's high-order terms.  Mode 0 (at W^{n+1/2})
+// forms and keeps those terms, the kinetic stress and heat fluxes of
+// f^{n+1/2} minus the NSF values; mode 1 adds the kept terms.  ubsq[12][unbf]
+// = (sigma xx yy zz xy xz yz, q, qr).
+__global__ __launch_bounds__(256) void k_umac_g13s(GSIS_SPAN_ARGS, int mode)
+{
+    int blk;
+    const Case &C = case_of(span_cases, span_map, blk);
+    const Geo &g = C.g;
+    const Dev &d = C.d;
+    const int bf = blk * blockDim.x + threadIdx.x;
+    if (bf >= g.unbf) return;
+    const size_t n = g.ncell, nb = g.unbf;
+    const int cell = G(d.ubf_cell)[bf];
+    const Soa<double> P = soa(d.P, n, cell);
+    const Soa<double> Gu = soa(d.grad, n, cell);
+    double gt[3] = {0, 0, 0}, gr[3] = {0, 0, 0};
+    const int first = G(d.ucf_first)[cell], cnt = G(d.ucf_first)[cell + 1] - first;
+    for (int k = 0; k < cnt; ++k) {
+        const int e = first + k;
+        const int j = G(d.ucf_nb)[e];
+        if (j < 0) continue;
+        const Soa<double> Pj = soa(d.P, n, j);
+        const double dt = Pj[4] - P[4], dr = Pj[5] - P[5];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double w = G(d.ucf_lsq)[3 * (size_t)e + c];
+            gt[c] += dt * w;
+            gr[c] += dr * w;
+        }
+    }
+    const double mu = P[9];
+    double G9[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) G9[k] = Gu[k];
+    const double div = G9[0] + G9[4] + G9[8];
+    double sq[12];
+    sq[0] = -mu * (2.0 * G9[0] - (2.0 / 3.0) * div);
+    sq[1] = -mu * (2.0 * G9[4] - (2.0 / 3.0) * div);
+    sq[2] = -mu * (2.0 * G9[8] - (2.0 / 3.0) * div);
+    sq[3] = -mu * (G9[1] + G9[3]);
+    sq[4] = -mu * (G9[2] + G9[6]);
+    sq[5] = -mu * (G9[5] + G9[7]);
+    const bool dia = g.species == 1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        sq[6 + c] = -g.kt * mu * gt[c];
+        sq[9 + c] = dia ? -g.kr * mu * gr[c] : 0.0;
+    }
+    const gptr<double> hot = G(d.ubhot);
+    if (mode == 0) {
+        // cm: sigma at 5..10, q at 11..13, qr at 15..17
+        const gptr<const double> m = G((const double *)d.cm) + (size_t)cell * NMOM;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const double kin = k < 9 ? m[5 + k] : (dia ? m[6 + k] : 0.0);
+            const double h = kin - sq[k];
+            hot[(size_t)k * nb + bf] = h;
+            sq[k] += h;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) sq[k] += hot[(size_t)k * nb + bf];
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) G(d.ubsq)[(size_t)k * nb + bf] = sq[k];
+}
+
+// Boundary faces, NF to a wave: F_eq of the owner's Maxwellian (outgoing
 // half-range sums over the nodes, incoming part the boundary Maxwellian at
 // the face's density rule); the wave reads every node's velocity once for
-// its UBF faces.  Mode 0 keeps F_kin - F_eq(W^{n+1/2}), mode 1 stores fixed
-// part + F_eq(W^m) and Gamma.
-constexpr int UBF = 8;
+// its NF faces.  Mode 0 keeps F_kin - F_eq(W^{n+1/2}), mode 1 stores fixed
+// part + F_eq(W^m) and Gamma.  G13: the same with the outgoing half of the
+// owner's Grad-13 distributions of Eq. (G13_VDF) (stress and heat fluxes
+// from k_umac_g13s), f0 = M B(c), f1 = (dr/2) Tr f0 + 2 M (qr.c) / (rho Tt).
+constexpr int UBF = 8, UBF_G13 = 4;
 
+template <int NF, bool G13>
 __global__ __launch_bounds__(256) void k_umac_bflux(GSIS_SPAN_ARGS, int mode, int euler)
 {
     int blk;
     const Case &C = case_of(span_cases, span_map, blk);
     const Geo &g = C.g;
     const Dev &d = C.d;
+    constexpr int UBF = NF;
     const int bf0 = __builtin_amdgcn_readfirstlane((blk * 4 + (int)(threadIdx.x >> 6)) * UBF);
     if (bf0 >= g.unbf) return;
     const int lane = threadIdx.x & 63;
+    const bool dia = g.species == 1;
     int f[UBF], cell[UBF], slot[UBF];
     double n[UBF][3], u[UBF][3], iT[UBF], s0[UBF], s1[UBF][3], s4[UBF];
+    // Grad-13: the bracket's coefficients per face, sigma / (rho Tt^2),
+    // 2 q / (rho Tt^2), 2 / (5 Tt), 2 qr / (rho Tt), and the q_r sum
+    double sg[G13 ? UBF : 1][6], qv[G13 ? UBF : 1][3], c5[G13 ? UBF : 1], qr[G13 ? UBF : 1][3], sr[G13 ? UBF : 1];
 #pragma unroll
     for (int q = 0; q < UBF; ++q) {
         const int bf = min(bf0 + q, g.unbf - 1);
@@ -1184,6 +1263,22 @@ __global__ __launch_bounds__(256) void k_umac_bflux(GSIS_SPAN_ARGS, int mode, in
         iT[q] = 1.0 / P[4];
         s0[q] = s4[q] = 0.0;
         s1[q][0] = s1[q][1] = s1[q][2] = 0.0;
+        if constexpr (G13) {
+            const int bf = min(bf0 + q, g.unbf - 1);
+            const size_t nb = g.unbf;
+            const gptr<const double> b = G((const double *)d.ubsq) + bf;
+            const double irT2 = 1.0 / (P[0] * P[4] * P[4]);
+            const double cr = 2.0 / (P[0] * P[4]);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sg[q][k] = b[(size_t)k * nb] * irT2;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                qv[q][k] = 2.0 * irT2 * b[(size_t)(6 + k) * nb];
+                qr[q][k] = dia ? cr * b[(size_t)(9 + k) * nb] : 0.0;
+            }
+            c5[q] = 2.0 / (5.0 * P[4]);
+            sr[q] = 0.0;
+        }
     }
     const gptr<const double> nt = G((const double *)d.nt64);
     for (int pos = lane; pos < g.nv; pos += 64) {
@@ -1194,12 +1289,27 @@ __global__ __launch_bounds__(256) void k_umac_bflux(GSIS_SPAN_ARGS, int mode, in
             const double xn = x0 * n[q][0] + x1 * n[q][1] + x2 * n[q][2];
             if (!(xn > 0.0)) continue;
             const double cx = x0 - u[q][0], cy = x1 - u[q][1], cz = x2 - u[q][2];
-            const double ex = w * exp_core(fmax(-(cx * cx + cy * cy + cz * cz) * iT[q], -745.0)) * xn;
-            s0[q] += ex;
-            s1[q][0] += ex * x0;
-            s1[q][1] += ex * x1;
-            s1[q][2] += ex * x2;
-            s4[q] += ex * xx;
+            if constexpr (G13) {
+                const double cc = cx * cx + cy * cy + cz * cz;
+                const double e = w * exp_core(fmax(-cc * iT[q], -745.0)) * xn;
+                const double scc = sg[q][0] * cx * cx + sg[q][1] * cy * cy + sg[q][2] * cz * cz
+                                 + 2.0 * (sg[q][3] * cx * cy + sg[q][4] * cx * cz + sg[q][5] * cy * cz);
+                const double qc = qv[q][0] * cx + qv[q][1] * cy + qv[q][2] * cz;
+                const double ex = e * (1.0 + scc + qc * (c5[q] * cc - 1.0));
+                s0[q] += ex;
+                s1[q][0] += ex * x0;
+                s1[q][1] += ex * x1;
+                s1[q][2] += ex * x2;
+                s4[q] += ex * xx;
+                sr[q] += e * (qr[q][0] * cx + qr[q][1] * cy + qr[q][2] * cz);
+            } else {
+                const double ex = w * exp_core(fmax(-(cx * cx + cy * cy + cz * cz) * iT[q], -745.0)) * xn;
+                s0[q] += ex;
+                s1[q][0] += ex * x0;
+                s1[q][1] += ex * x1;
+                s1[q][2] += ex * x2;
+                s4[q] += ex * xx;
+            }
         }
     }
 #pragma unroll
@@ -1208,6 +1318,7 @@ __global__ __launch_bounds__(256) void k_umac_bflux(GSIS_SPAN_ARGS, int mode, in
 #pragma unroll
         for (int k = 0; k < 3; ++k) s1[q][k] = wave_sum(s1[q][k]);
         s4[q] = wave_sum(s4[q]);
+        if constexpr (G13) sr[q] = wave_sum(sr[q]);
     }
     // lane q finishes face q
 #pragma unroll
@@ -1221,8 +1332,14 @@ __global__ __launch_bounds__(256) void k_umac_bflux(GSIS_SPAN_ARGS, int mode, in
         out[0] = K * s0[q];
 #pragma unroll
         for (int k = 0; k < 3; ++k) out[1 + k] = K * s1[q][k];
-        out[4] = K * s4[q] + h1 * out[0];
-        out[5] = h1 * out[0];
+        if constexpr (G13) {
+            const double f1 = dia ? K * (h1 * s0[q] + sr[q]) : 0.0;
+            out[4] = K * s4[q] + f1;
+            out[5] = f1;
+        } else {
+            out[4] = K * s4[q] + h1 * out[0];
+            out[5] = h1 * out[0];
+        }
         const int bf = bf0 + q;
         const gptr<const double> bin = G((const double *)d.ubin) + 6 * (size_t)bf;
         const double sc = C.bc.kind[slot[q]] == 1 ? C.bc.rho[slot[q]] : out[0] / (-bin[0]);
@@ -1337,6 +1454,17 @@ hipError_t launch_umacro(const Target &t, int iters, hipStream_t s, int euler)
     const Span sp{t.cases, nullptr};
     const dim3 cells((g.ncell + 255) / 256), faces((g.unface + 255) / 256);
     const dim3 fwaves((g.unface + 3) / 4), bwaves(((std::max(g.unbf, 1) + UBF - 1) / UBF + 3) / 4);
+    const dim3 gwaves(((std::max(g.unbf, 1) + UBF_G13 - 1) / UBF_G13 + 3) / 4), bthreads((std::max(g.unbf, 1) + 255) / 256);
+    // the Grad-13 wall flux: its stress and heat fluxes first, then its flux
+    const bool g13 = t.g13 && !euler;
+    auto bflux = [&](int mode) {
+        if (g13) {
+            hipLaunchKernelGGL(k_umac_g13s, bthreads, dim3(256), 0, s, GSIS_SPAN(sp), mode);
+            hipLaunchKernelGGL((k_umac_bflux<UBF_G13, true>), gwaves, dim3(256), 0, s, GSIS_SPAN(sp), mode, euler);
+        } else {
+            hipLaunchKernelGGL((k_umac_bflux<UBF, false>), bwaves, dim3(256), 0, s, GSIS_SPAN(sp), mode, euler);
+        }
+    };
     hipLaunchKernelGGL(k_mac_reset, dim3(1), dim3(64), 0, s, GSIS_SPAN(sp));
     hipLaunchKernelGGL(k_mac_init, dim3(t.nblk[K_CELL128]), dim3(128), 0, s, GSIS_SPAN(sp));
     hipLaunchKernelGGL(k_umac_grad, cells, dim3(256), 0, s, GSIS_SPAN(sp));
@@ -1352,13 +1480,13 @@ hipError_t launch_umacro(const Target &t, int iters, hipStream_t s, int euler)
         hipLaunchKernelGGL(k_umac_nofix, dim3((6 * g.unface + 255) / 256), dim3(256), 0, s, GSIS_SPAN(sp));
     } else {
         hipLaunchKernelGGL(k_umac_iflux, faces, dim3(256), 0, s, GSIS_SPAN(sp), 0, 0);
-        if (g.unbf > 0) hipLaunchKernelGGL(k_umac_bflux, bwaves, dim3(256), 0, s, GSIS_SPAN(sp), 0, 0);
+        if (g.unbf > 0) bflux(0);
     }
     for (int it = 0; it < iters; ++it) {
         const int slot = it & 1;
         if (it > 0) hipLaunchKernelGGL(k_umac_grad, cells, dim3(256), 0, s, GSIS_SPAN(sp));
         hipLaunchKernelGGL(k_umac_iflux, faces, dim3(256), 0, s, GSIS_SPAN(sp), 1, euler);
-        if (g.unbf > 0) hipLaunchKernelGGL(k_umac_bflux, bwaves, dim3(256), 0, s, GSIS_SPAN(sp), 1, euler);
+        if (g.unbf > 0) bflux(1);
         hipLaunchKernelGGL(k_umac_res, cells, dim3(256), 0, s, GSIS_SPAN(sp), slot, euler);
         hipLaunchKernelGGL(k_umac_advance, cells, dim3(256), 0, s, GSIS_SPAN(sp), slot);
     }

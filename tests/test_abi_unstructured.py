@@ -125,8 +125,8 @@ def test_workspace_holds_the_sweep_schedule():
 
 
 def test_wall_flux_model_validation():
-    """gsis_set_wall_flux: unknown models are EINVAL; the Grad-13 wall flux
-    is refused on an unstructured mesh in either order of the calls."""
+    """gsis_set_wall_flux: unknown models are EINVAL; both models are accepted
+    on a box and, in either order of the calls, on an unstructured mesh."""
     base = I.small_block(n=(6, 5, 5), blk=((2, 4), (2, 3), (2, 3)), m=6)
     L = _lib.lib()
     cfg = make_config(base)
@@ -138,14 +138,12 @@ def test_wall_flux_model_validation():
     assert L.gsis_set_wall_flux(h, 0) == 0
     L.gsis_destroy(h)
     mesh = I.lattice_mesh(2, 2, 2, 1.0, 1.0, 1.0, split=I.TET)
-    # mesh first, then the model
     L, h = raw_ctx(base)
     assert set_mesh(L, h, mesh.volume, mesh.face_cell, mesh.face_geom, mesh.centroid, mesh.face_center) == 0
-    assert L.gsis_set_wall_flux(h, 1) == EINVAL
-    assert L.gsis_set_wall_flux(h, 0) == 0
+    assert L.gsis_set_wall_flux(h, 1) == 0
+    assert L.gsis_set_wall_flux(h, 3) == EINVAL
     L.gsis_destroy(h)
-    # the model first, then the mesh
     L, h = raw_ctx(base)
     assert L.gsis_set_wall_flux(h, 1) == 0
-    assert set_mesh(L, h, mesh.volume, mesh.face_cell, mesh.face_geom, mesh.centroid, mesh.face_center) == ESTATE
+    assert set_mesh(L, h, mesh.volume, mesh.face_cell, mesh.face_geom, mesh.centroid, mesh.face_center) == 0
     L.gsis_destroy(h)

@@ -3,7 +3,8 @@
 FP64 oracle: GSIS iterations on a moving-lid cavity (walls), the nitrogen
 block flow (inflow faces and the walls of a solid block), a non-uniform
 tensor grid, and a node list (the summed form of the half-range fluxes), in
-FP64 (1e-12 on rho, u, T) and FP32 (1e-5); the correction differs from the
+FP64 (1e-12 on rho, u, T) and FP32 (1e-5), and on unstructured meshes (tetrahedra; a mixed-element
+mesh of the nitrogen block flow); the correction differs from the
 Maxwellian wall flux's away from the fixed point.
 """
 import dataclasses
@@ -38,7 +39,14 @@ def g13_cases():
     x = np.sinh(np.linspace(-2.0, 2.0, 8)) * (4.0 / np.sinh(2.0))
     stretched = dataclasses.replace(stretched, nodes=(x, None, x))
     lst = I.with_velocity_list(I.cavity(5, 6, 0.1, lid=0.3), I.tensor_velocity_list((6, 6, 6), (-4.0,) * 3, (4.0,) * 3))
-    cases = {"cavity": cav, "n2_block": blk, "stretched": stretched, "list_cavity": lst}
+    # unstructured meshes: Kuhn tetrahedra of a cavity, and the nitrogen block
+    # flow on a mixed-element mesh (inflow faces, walls of the body)
+    tet = I.on_mesh(I.cavity(4, 6, 0.1, lid=0.3), I.lattice_mesh(4, 4, 4, 1.0, 1.0, 1.0, split=I.TET))
+    nb = I.small_block(species=I.DIATOMIC, n=(6, 5, 5), blk=((2, 4), (2, 3), (2, 3)), m=6)
+    split = np.random.default_rng(5).integers(0, 4, size=(5, 5, 6))
+    mixed = I.on_mesh(nb, I.lattice_mesh(6, 5, 5, nb.lx, nb.ly, nb.lz, split=split, solid=nb.solid))
+    cases = {"cavity": cav, "n2_block": blk, "stretched": stretched, "list_cavity": lst,
+             "tet_cavity": tet, "n2_mixed_mesh": mixed}
     return {k: dataclasses.replace(v, wall_flux=1) for k, v in cases.items()}
 
 
@@ -65,7 +73,7 @@ def test_g13_gsis_parity(name, dtype):
     o = Oracle(case)
     s.init_maxwellian()
     o.init_maxwellian()
-    solid = case.solid_mask() if case.solid is not None else None
+    solid = case.solid_mask() if (case.solid is not None and case.mesh is None) else None
     for it in range(2):
         s.kinetic_step(1)
         o.step(1)
