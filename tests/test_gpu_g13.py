@@ -104,3 +104,28 @@ def test_g13_correction_differs_from_the_maxwellian_wall_flux():
     d = np.abs(out[1][:, :5] - out[0][:, :5]).max()
     say(f"  max moment difference {d:.3e}")
     assert d > 1e-6
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_g13_in_a_batch_equals_single_contexts(graph):
+    """A batch mixing Grad-13 and Maxwellian wall fluxes (the G13 kernels run
+    for the whole batch, each case taking its own model): every case bitwise
+    the case run alone, eager and captured in a graph."""
+    from paper_2310_18916_amd.gsis import Batch
+    say(f"[g13 batch] graph={graph}")
+    cases = [dataclasses.replace(I.cavity(6, 8, 0.2, lid=0.2), wall_flux=1), I.cavity(5, 9, 0.5, lid=0.3),
+             dataclasses.replace(I.cavity(7, 10, 0.05, lid=0.15), wall_flux=1)]
+    iters, inner = 2, 20
+    b = Batch(cases, "fp64")
+    tile = b.get_tile()
+    b.init_maxwellian()
+    b.run(iters, inner, graph=graph)
+    for i, case in enumerate(cases):
+        s = Solver(case, "fp64", tile=tile)
+        s.init_maxwellian()
+        for _ in range(iters):
+            s.kinetic_step(1)
+            s.gsis_correct(inner)
+            s.residual()
+        assert np.array_equal(b[i].moments(), s.moments()), i
+    b.close()
