@@ -14,7 +14,9 @@ cells, and the residual (tests/golden/make_fullsize.py):
 * c3t, the Mach-5 block flow on 291,840 tetrahedra with the 7788-node refined
   velocity mesh: after one and two passes, and after a GSIS iteration (the
   correction on the tetrahedra) and the pass that follows it (the stored-VDF
-  oracle).
+  oracle);
+* c2_g13, the cavity with the Grad-13 wall flux of the correction: after one
+  and after three GSIS iterations.
 
 The GPU runs the same plan at full size, its first pass being the
 autotuner's (the launch configuration bench.py uses), in FP64 and FP32.
@@ -28,6 +30,7 @@ FP64 1e-12 and FP32 1e-5 on rho, u, T (and T_r); sigma and q are held to
 1e-10 (FP64) and 1e-4 (FP32), which bounds the cancellation of the raw-moment
 reduction at Mach 5.
 """
+import dataclasses
 import os
 import sys
 
@@ -60,11 +63,12 @@ def groups(nm):
     return g
 
 
-WORKLOADS = {"c2": I.c2, "c3": I.c3, "c4": I.c4, "c3t": I.c3t, "c3t_gsis": I.c3t}
+WORKLOADS = {"c2": I.c2, "c3": I.c3, "c4": I.c4, "c3t": I.c3t, "c3t_gsis": I.c3t,
+             "c2_g13": lambda: dataclasses.replace(I.c2(), wall_flux=1)}
 
 
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
-@pytest.mark.parametrize("workload", ["c2", "c3", "c4", "c3t", "c3t_gsis"])
+@pytest.mark.parametrize("workload", ["c2", "c3", "c4", "c3t", "c3t_gsis", "c2_g13"])
 def test_full_size_matches_streaming_oracle(workload, dtype):
     path = os.path.join(GOLDEN, f"fullsize_{workload}.npz")
     if not os.path.exists(path):
