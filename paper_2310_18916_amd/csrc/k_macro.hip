@@ -1227,7 +1227,10 @@ __global__ __launch_bounds__(256) void k_umac_g13s(GSIS_SPAN_ARGS, int mode)
 // part + F_eq(W^m) and Gamma.  G13: the same with the outgoing half of the
 // owner's Grad-13 distributions of Eq. (G13_VDF) (stress and heat fluxes
 // from k_umac_g13s), f0 = M B(c), f1 = (dr/2) Tr f0 + 2 M (qr.c) / (rho Tt).
-constexpr int UBF = 8, UBF_G13 = 4;
+// Two faces to a wave (tetrahedral block flow, 17k boundary faces x 7788
+// nodes, 300 inner iterations: 8 faces 120.3 ms per correction, 4: 106.3,
+// 2: 103.7, 1: 116.1; Grad-13 form 4: 140.2, 2: 129.1).
+constexpr int UBF = 2, UBF_G13 = 2;
 
 template <int NF, bool G13>
 __global__ __launch_bounds__(256) void k_umac_bflux(GSIS_SPAN_ARGS, int mode, int euler)
