@@ -6,6 +6,7 @@ touches three box faces.  Each: one pass from a seeded random VDF (FP64 1e-13,
 FP32 3e-6 relative, as the small-case parity tests), and two GSIS iterations
 from the Maxwellian followed by a pass (FP64 1e-12).
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -70,10 +71,14 @@ def test_degenerate_one_pass(name, dtype):
     assert e <= (1e-13 if dtype == "fp64" else 3e-6)
 
 
+@pytest.mark.parametrize("wall_flux", [0, 1])
 @pytest.mark.parametrize("name", list(CASES))
-def test_degenerate_gsis(name):
-    say(f"[degenerate gsis] {name}")
-    case = CASES[name]
+def test_degenerate_gsis(name, wall_flux):
+    """Two GSIS iterations and a pass against the oracle, with the Maxwellian
+    and with the Grad-13 wall flux (whose wall-cell gradients fall back to
+    one-sided differences, or none, on these shapes)."""
+    say(f"[degenerate gsis] {name} wall_flux={wall_flux}")
+    case = dataclasses.replace(CASES[name], wall_flux=wall_flux)
     s = Solver(case, "fp64")
     o = Oracle(case)
     s.init_maxwellian()
