@@ -45,8 +45,10 @@ def g13_cases():
     nb = I.small_block(species=I.DIATOMIC, n=(6, 5, 5), blk=((2, 4), (2, 3), (2, 3)), m=6)
     split = np.random.default_rng(5).integers(0, 4, size=(5, 5, 6))
     mixed = I.on_mesh(nb, I.lattice_mesh(6, 5, 5, nb.lx, nb.ly, nb.lz, split=split, solid=nb.solid))
+    # the second-order right-hand side of the kinetic passes
+    cav2 = dataclasses.replace(I.cavity(6, 8, 0.1, lid=0.2), order=2, limiter_k=1.0)
     cases = {"cavity": cav, "n2_block": blk, "stretched": stretched, "list_cavity": lst,
-             "tet_cavity": tet, "n2_mixed_mesh": mixed}
+             "tet_cavity": tet, "n2_mixed_mesh": mixed, "cavity_order2": cav2}
     return {k: dataclasses.replace(v, wall_flux=1) for k, v in cases.items()}
 
 
