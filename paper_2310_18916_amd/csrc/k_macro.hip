@@ -862,10 +862,14 @@ __global__ __launch_bounds__(256) void k_mac_advance(GSIS_SPAN_ARGS, int slot, i
             const int nb = G(d.nbr)[(size_t)sub * g.ncell + cell];
             if (nb >= 0) { who = nb; has = true; }
         }
-        double Ww[6], Pw[NP];
+        double Ww[6];
         stepped_W(g, d, Ws, who, Dm, iDm, Ww);
-        prim_from_W(g, Ww, Pw);
-        const double v[5] = {Pw[1], Pw[2], Pw[3], Pw[4], Pw[5]};
+        // u, Tt, Tr of the new state, as prim_from_W forms them
+        const double irho = 1.0 / Ww[0];
+        const double w0 = Ww[1] * irho, w1 = Ww[2] * irho, w2 = Ww[3] * irho;
+        const double wEr = g.species == 1 ? Ww[5] : 0.0;
+        const double wTt = (2.0 / 3.0) * (Ww[4] - wEr - Ww[0] * (w0 * w0 + w1 * w1 + w2 * w2)) * irho;
+        const double v[5] = {w0, w1, w2, wTt, g.species == 1 ? 2.0 * wEr / (g.dr * Ww[0]) : wTt};
         double sq[12];
         group_cell_nsf(g, v, has, P[9], sq);
 #pragma unroll
