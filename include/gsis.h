@@ -224,15 +224,18 @@ gsis_status gsis_moments(gsis_ctx *ctx, double *out, int out_is_device);
 
 /* GSIS-II macroscopic correction (Algorithm 2, Sec. 3.3): inner_iters >= 0
  * point-Jacobi iterations of the synthetic equations with the high-order
- * terms of Eq. (full_constitutive), then the update of Eq. (updatef), whose
- * moments are applied at once and whose pointwise part is deferred until the
- * VDF is next read.  Needs a kinetic step since init.  Asynchronous. */
+ * terms of Eq. (full_constitutive) and the boundary flux of gsis_set_wall_flux,
+ * then the update of Eq. (updatef), whose moments are applied at once and
+ * whose pointwise part is deferred until the VDF is next read.  Needs a
+ * kinetic step since init.  Asynchronous. */
 gsis_status gsis_gsis_correct(gsis_ctx *ctx, int inner_iters);
 
 /* Initial field of Alg. 1, line 1: macro_steps iterations of the macroscopic
  * solver of gsis_gsis_correct with the Euler constitutive relations (no
  * stress, heat flux or HoT; no diffusive term in the pseudo-time diagonal; the
- * boundary faces take the flux of the iterate's own Maxwellian), started from
+ * boundary faces take the flux of the iterate's own Maxwellian, whichever
+ * gsis_set_wall_flux model is set, since without stress and heat flux the
+ * Grad-13 distributions are that Maxwellian), started from
  * the current moments; the VDF is corrected to the result as in Eq. (updatef);
  * then kinetic_steps kinetic passes.  Typically after gsis_init_maxwellian,
  * with 1000 and 10.  Asynchronous; EINVAL for negative counts, ESTATE before
