@@ -3,6 +3,8 @@ the cell's velocity and per-face outgoing fluxes) against its stored-VDF
 mode: the same iteration of Sec. 3.2 / Sec. 3.3 in another loop order, so
 every moment agrees to rounding after passes and GSIS-II corrections, on a
 cavity, a masked Mach-5 block and the diatomic gas."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -15,11 +17,15 @@ def _norm_err(ma, mb, cols, fluid):
     return np.abs(a - b).max() / max(np.abs(a).max(), 1e-300)
 
 
+@pytest.mark.parametrize("wall_flux", [0, 1])
 @pytest.mark.parametrize("name", ["cavity", "block", "n2_block"])
-def test_streaming_equals_stored_vdf(name):
+def test_streaming_equals_stored_vdf(name, wall_flux):
+    """With either wall flux of the correction (the Grad-13 one takes the
+    stress and heat fluxes of the streamed moments)."""
     case = {"cavity": I.cavity(6, 9, 0.05, lid=0.2),
             "block": I.small_block(m=8),
             "n2_block": I.small_block(species=I.DIATOMIC, m=8)}[name]
+    case = dataclasses.replace(case, wall_flux=wall_flux)
     full, stream = O.Oracle(case), O.StreamOracle(case)
     full.init_maxwellian()
     stream.init_maxwellian()
