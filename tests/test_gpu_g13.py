@@ -131,3 +131,12 @@ def test_g13_in_a_batch_equals_single_contexts(graph):
             s.residual()
         assert np.array_equal(b[i].moments(), s.moments()), i
     b.close()
+
+
+def test_g13_set_after_bind_is_refused():
+    """The wall-flux model is part of the set-up: once the workspace is bound,
+    gsis_set_wall_flux returns GSIS_ESTATE and the model stays as it was."""
+    say("[g13 after bind]")
+    s = Solver(I.cavity(4, 6, 0.1, lid=0.2), "fp64")
+    assert s.L.gsis_set_wall_flux(s.h, 1) == -2
+    assert s.L.gsis_set_wall_flux(s.h, 7) in (-1, -2)
